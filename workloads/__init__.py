@@ -1,0 +1,158 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle checks.
+
+This module only describes problems and draws random inputs: lattice sizes,
+direction-grid parameters, boundary kinds, phase-function parameters, per-cell
+optical depth / albedo / emission fields, boundary radiances and initial
+states.  It contains none of the solver's arithmetic (no directions, phase
+matrices, coefficients or streaming); the oracle and the HIP library each build
+those themselves from the description.
+
+Every random field is rounded to float32 and returned as float64, so that the
+float32 device path and the float64 oracle see bit-identical inputs.
+
+Workloads (the paper's method at the sizes it is benchmarked on here):
+  plain32      32x32 periodic, n = 8 (2 zenith x 4 azimuth, D2Q9 shifts),
+               tau_ext = 1 per step, albedo 0.9, Rayleigh, unpolarised unit
+               point source at the centre, 100 steps
+  beam512      512x512 vertical plane, n = 32 (4 x 8), lognormal extinction,
+               albedo U[0.8, 1], HG(g = 0.7) weights with Rayleigh-shaped
+               polarisation, unpolarised beam at solar zenith 30 deg entering
+               the top, vacuum sides and bottom, 2000 steps
+  prec1024     1024x1024, n = 128 (8 x 16), the beam512 generator, 200 steps
+  adjoint256   256x256, n = 32, beam512 generator plus emission U[0, 0.05],
+               top-edge (I + DoLP) loss after 500 steps
+  spectral64   64 channels 400-900 nm, Rayleigh optical depth ~ lambda^-4 plus
+               aerosol HG(0.6), per-channel lattice and direction count drawn
+               from {128,256,384,512}^2 x {16,32,64}, 200 steps
+"""
+import copy
+import numpy as np
+
+BC_PERIODIC, BC_ABSORBING, BC_INFLOW = 0, 1, 2
+
+_BASE = {
+    "plain32": dict(nx=32, ny=32, n_zen=2, n_az=4, zen_rule="equal_area", az_offset_deg=0.0,
+                    plane="xy_d2q9", courant=1.0, bc=(0, 0, 0, 0),
+                    phase={"kind": "rayleigh"}, dt=1.0, steps=100, seed=1,
+                    medium="uniform", tau0=1.0, albedo0=0.9, source="point"),
+    "beam512": dict(nx=512, ny=512, n_zen=4, n_az=8, zen_rule="equal_area", az_offset_deg=0.0,
+                    plane="xz", courant=1.0, bc=(1, 1, 1, 2),
+                    phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=2000, seed=2,
+                    medium="lognormal", tau_ref_n=512, beam_dir=3 * 8 + 0, source="none"),
+    "prec1024": dict(nx=1024, ny=1024, n_zen=8, n_az=16, zen_rule="equal_area",
+                     az_offset_deg=0.0, plane="xz", courant=1.0, bc=(1, 1, 1, 2),
+                     phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=200, seed=3,
+                     medium="lognormal", tau_ref_n=1024, beam_dir=6 * 16 + 0,
+                     source="none"),
+    "adjoint256": dict(nx=256, ny=256, n_zen=4, n_az=8, zen_rule="equal_area",
+                       az_offset_deg=0.0, plane="xz", courant=1.0, bc=(1, 1, 1, 2),
+                       phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=4,
+                       medium="lognormal", tau_ref_n=256, beam_dir=3 * 8 + 0,
+                       source="uniform_emis",
+                       emis_max=0.05, loss_edge=3),
+}
+# beam_dir: index d = i_zen * n_az + j_az of the downward direction nearest to
+# propagation zenith 150 deg (solar zenith 30 deg) at azimuth 0.  Equal-area
+# zeniths for n_zen = 4 are 41.4/75.5/104.5/138.6 deg (i = 3 is nearest), for
+# n_zen = 8 the nearest is i = 6 (144.3 deg), for n_zen = 2 it is i = 1 (120 deg).
+BEAM_ZEN_INDEX = {2: 1, 4: 3, 8: 6}
+
+
+def spec(name, **over):
+    """A workload description (dict) with optional overrides."""
+    s = copy.deepcopy(_BASE[name])
+    s["name"] = name
+    s.update(over)
+    if "beam_dir" in s and ("n_zen" in over or "n_az" in over):
+        s["beam_dir"] = BEAM_ZEN_INDEX[s["n_zen"]] * s["n_az"]
+    return s
+
+
+def ndir(s):
+    return int(s["n_zen"]) * int(s["n_az"])
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def medium(s, seed=None):
+    """Per-cell tau_ext (per-step optical depth), albedo, emission; jprof; inflow.
+
+    Arrays are [ny, nx]; jprof [n, 4]; inflow [4 edges, n, 4].
+    lognormal: tau = tau_scale * exp(N(0,1)) / N with N the full-size lattice
+    side tau_ref_n (unit domain, dt = 1/N as in Sec. 3.2.2), so a reduced test
+    lattice keeps the per-step optical-depth distribution; albedo ~ U[0.8, 1].
+    """
+    rng = np.random.default_rng(s["seed"] if seed is None else seed)
+    nx, ny, n = s["nx"], s["ny"], ndir(s)
+    if s["medium"] == "uniform":
+        tau = np.full((ny, nx), s["tau0"])
+        alb = np.full((ny, nx), s["albedo0"])
+    elif s["medium"] == "lognormal":
+        tau = (np.exp(rng.normal(0.0, 1.0, size=(ny, nx))) * s.get("tau_scale", 1.0)
+               / s.get("tau_ref_n", ny))
+        alb = rng.uniform(0.8, 1.0, size=(ny, nx))
+    else:
+        raise ValueError(s["medium"])
+    emis = np.zeros((ny, nx))
+    jprof = np.zeros((n, 4))
+    src = s.get("source", "none")
+    if src == "point":
+        y, x = s.get("source_cell") or (ny // 2, nx // 2)
+        emis[y, x] = 1.0
+        jprof[:, 0] = 1.0 / n
+        if s.get("source_pol") == "linear":
+            jprof[:, 1] = 1.0 / n
+    elif src == "uniform_emis":
+        emis = rng.uniform(0.0, s["emis_max"], size=(ny, nx))
+        jprof[:, 0] = 1.0
+    inflow = np.zeros((4, n, 4))
+    if "beam_dir" in s and s["bc"][3] == BC_INFLOW:
+        inflow[3, s["beam_dir"], 0] = 1.0
+    return {"tau": _f32(tau), "albedo": _f32(alb), "emis": _f32(emis),
+            "jprof": _f32(jprof), "inflow": _f32(inflow)}
+
+
+def initial_state(s, kind="zero", seed=None):
+    """S0[d, s, y, x]: zeros, or random physical Stokes vectors (I >= |(Q,U,V)|)."""
+    nx, ny, n = s["nx"], s["ny"], ndir(s)
+    if kind == "zero":
+        return np.zeros((n, 4, ny, nx))
+    rng = np.random.default_rng(1000 + (s["seed"] if seed is None else seed))
+    I = rng.uniform(0.1, 1.0, size=(n, ny, nx))
+    v = rng.normal(size=(n, 3, ny, nx))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    p = rng.uniform(0.0, 0.99, size=(n, ny, nx))
+    S = np.empty((n, 4, ny, nx))
+    S[:, 0] = I
+    S[:, 1:] = v * (p * I)[:, None]
+    return _f32(S)
+
+
+def spectral_channels(nchan=64, seed=5):
+    """Per-channel descriptions for the spectral batch.
+
+    lambda_k = 400 + 500 k / (nchan - 1) nm.  Rayleigh column optical depth
+    0.1 (lambda / 550)^-4, aerosol 0.2 with HG(0.6); the phase function of a
+    channel is the optical-depth-weighted mixture.  Lattice side and
+    (n_zen, n_az) are drawn per channel.
+    """
+    rng = np.random.default_rng(seed)
+    sides = [128, 256, 384, 512]
+    grids = [(2, 8), (4, 8), (4, 16)]
+    out = []
+    for k in range(nchan):
+        lam = 400.0 + 500.0 * k / (nchan - 1)
+        t_r = 0.1 * (lam / 550.0) ** -4
+        t_a = 0.2
+        side = sides[rng.integers(len(sides))]
+        nz, na = grids[rng.integers(len(grids))]
+        s = dict(nx=side, ny=side, n_zen=nz, n_az=na, zen_rule="equal_area",
+                 az_offset_deg=0.0, plane="xz", courant=1.0, bc=(1, 1, 1, 2),
+                 phase={"kind": "mix", "g": 0.6, "mix_ray": t_r / (t_r + t_a)},
+                 dt=1.0, steps=200, seed=5000 + k, medium="lognormal",
+                 tau_scale=(t_r + t_a), tau_ref_n=side, beam_dir=BEAM_ZEN_INDEX[nz] * na,
+                 source="none", name="spectral64[%d]" % k, wavelength_nm=lam)
+        out.append(s)
+    return out

@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the polarized LBM radiative-transfer solver on one MI355X.
+
+One timed step is one pass of the whole hot path over the beam512 workload
+(512x512 lattice, n = 32 directions = 4 zenith x 8 azimuth, lognormal
+extinction, albedo U[0.8,1], HG(0.7) weights with Rayleigh polarisation,
+solar beam entering the top, 2000 time steps):
+  forward run of T steps with sqrt(T) checkpoints (fused stream + collide
+  kernel), top-edge readout, readout adjoint, and the checkpointed adjoint
+  over T steps (segment recompute + fused adjoint kernel + gradient chain).
+value = (C n T forward + C n T adjoint) Stokes cell-direction updates per
+second of that step.  All inputs are resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_23057_amd", "csrc", "rt_kernels.hip")
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_key)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def loss_grad(out):
+    """d/d(readout) of sum(I + DoLP), DoLP = sqrt(Q^2+U^2+(1e-6 I)^2)/I (torch ops on the readout)."""
+    import torch
+    I, Q, U = out[..., 0], out[..., 1], out[..., 2]
+    Ic = torch.clamp(I, min=1e-30)
+    r = torch.sqrt(Q * Q + U * U + (1e-6 * Ic) ** 2)
+    g = torch.zeros_like(out)
+    g[..., 0] = 1.0 + 1e-12 / r - r / (Ic * Ic)
+    g[..., 1] = Q / (r * Ic)
+    g[..., 2] = U / (r * Ic)
+    return g
+
+
+def make_solver(spec, precision):
+    import numpy as np
+    import torch
+    import paper_2609_23057_amd as P
+    import workloads as W
+    s = dict(spec)
+    s["precision"] = precision
+    solver = P.Solver(P.make_problem(**s))
+    med = W.medium(spec)
+    dev = solver.device
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    solver._med = (t(med["tau"]), t(med["albedo"]), t(med["emis"]))
+    solver.set_medium(*solver._med, med["jprof"], med["inflow"])
+    return solver
+
+
+def cpu_baseline(spec, nsteps=3):
+    """The FP64 oracle on the host cores: nsteps forward steps of the full
+    512x512 lattice plus the adjoint over them (the oracle's adjoint re-runs
+    the forward and stores every state)."""
+    import numpy as np
+    import workloads as W
+    from oracle import adjoint as OA
+    from oracle import lbm as OL
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    med = W.medium(spec)
+    prob = OL.make_problem(spec, med)
+    S0 = np.zeros(prob.shape)
+    t0 = time.perf_counter()
+    ST = OL.run(S0, prob, nsteps)
+    _, g = OL.edge_loss(ST, prob, 3)
+    OA.adjoint(S0, prob, nsteps, OL.readout_transpose(g, prob, 3))
+    dt = time.perf_counter() - t0
+    C, n = spec["nx"] * spec["ny"], W.ndir(spec)
+    return {"value": 2.0 * C * n * nsteps / dt, "unit": "Stokes cell-direction updates/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": "float64 NumPy oracle, %d forward steps + adjoint over them on the full "
+                      "512x512 n=32 lattice (%.1f s); host has %d logical CPUs"
+                      % (nsteps, dt, os.cpu_count() or 0)}
+
+
+def precision_extras(T=20, warm=3):
+    """Forward throughput of the fused step at 1024x1024, n = 128 per contraction precision."""
+    import torch
+    import workloads as W
+    spec = W.spec("prec1024")
+    C, n = spec["nx"] * spec["ny"], W.ndir(spec)
+    res = {}
+    for prec in ("fp32", "bf16", "bf16x3", "fp16"):
+        _log("bench: prec1024 %s" % prec)
+        solver = make_solver(spec, prec)
+        S = solver.empty_state()
+        solver.run(S, warm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        solver.run(S, T)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[prec] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+        del solver, S
+        torch.cuda.empty_cache()
+    base = res["fp32"]["cell_dir_updates_per_s"]
+    for k in res:
+        res[k]["speedup_vs_fp32"] = res[k]["cell_dir_updates_per_s"] / base
+    return {"workload": "prec1024: 1024x1024, n=128 (8x16), forward steps", "steps": T, "rates": res}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tsteps", type=int, default=None, help="time steps per pass (default 2000)")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver build runs on a single GPU; multi-GPU runs (--gpus %d) are "
+              "not part of it" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    spec = W.spec("beam512")
+    T = args.tsteps or spec["steps"]
+    C, n = spec["nx"] * spec["ny"], W.ndir(spec)
+    K = max(1, int(math.ceil(math.sqrt(T))))
+    _log("bench: building solver (beam512, %s)" % args.precision)
+    solver = make_solver(spec, args.precision)
+    S0 = solver.empty_state()
+    S = solver.empty_state()
+    ck = solver.checkpoint_buffer(T, K)
+    seg = solver.segment_buffer(K)
+    edge = 3
+
+    def one_step():
+        S.copy_(S0)
+        solver.run(S, T, ck, K)
+        out = solver.readout(S, edge)
+        lam = solver.readout_adjoint(edge, loss_grad(out))
+        return solver.adjoint(T, ck, K, lam, seg)
+
+    for i in range(args.warmup):
+        _log("bench: warmup %d" % i)
+        one_step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        one_step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    _log("bench: timed %d steps, %.1f ms/step (wall %.2f s)" % (args.steps, ms_per_step, wall))
+
+    # phase split (outside the timed region): forward run alone, adjoint alone
+    fa, fb, fc = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    S.copy_(S0)
+    torch.cuda.synchronize()
+    fa.record()
+    solver.run(S, T, ck, K)
+    fb.record()
+    lam = solver.readout_adjoint(edge, loss_grad(solver.readout(S, edge)))
+    fc0 = torch.cuda.Event(enable_timing=True)
+    fc0.record()
+    solver.adjoint(T, ck, K, lam, seg)
+    fc.record()
+    torch.cuda.synchronize()
+    ms_fwd = fa.elapsed_time(fb)
+    ms_adj = fc0.elapsed_time(fc)
+    # the forward run is T + 1 launches of one-read-one-write steps (T - 1 fused,
+    # one collide-only, one stream); its mean launch time is the fused kernel's
+    avg_fused_us = ms_fwd * 1e3 / (T + 1)
+    bytes_per_launch = C * (32.0 * n + 12.0)
+    achieved = bytes_per_launch / (avg_fused_us * 1e-6) / 1e9
+
+    line = {
+        "metric": "Stokes cell-direction updates/s (forward + adjoint hot path)",
+        "value": 2.0 * C * n * T / (ms_per_step / 1e3),
+        "unit": "Stokes cell-direction updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": "beam512: 512x512 lattice, n=32 (4 zenith x 8 azimuth), T=%d time "
+                               "steps; forward with sqrt(T) checkpoints + readout + adjoint" % T,
+                   "nx": 512, "ny": 512, "ndir": n, "time_steps": T, "ckpt_every": K,
+                   "contraction_precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": "fused_kernel (forward step)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("fused_fwd_beam512_%s" % args.precision),
+                     "avg_launch_us": avg_fused_us,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "phases": {"forward_ms": ms_fwd, "adjoint_ms": ms_adj, "adjoint_fwd_ratio": ms_adj / ms_fwd,
+                   "forward_cell_dir_updates_per_s": C * n * T / (ms_fwd / 1e3)},
+    }
+    if not args.no_extras:
+        del ck, seg
+        torch.cuda.empty_cache()
+        line["precision_speedup"] = precision_extras()
+    if not args.no_cpu:
+        _log("bench: cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * rt_lbm.h -- C ABI of the MI355X polarized lattice-Boltzmann radiative-transfer solver.
+ *
+ * The solver advances Stokes populations S[d][s][y][x] (direction d, Stokes
+ * component s in I,Q,U,V, lattice row y, column x) one time step at a time:
+ * emission, Beer-Lambert absorption, scattering through the rotated 4x4
+ * phase matrix and bilinear streaming along the lattice displacement of each
+ * direction (paper: Sec. 2.1.1 Eq. 2; operator chain Eq. 5 with states Eq. 8,
+ * 10, 32, 39; emission Eq. 6; absorption Sec. 2.1.4; scattering Eq. 11-17 and
+ * 21-30; streaming Eq. 33-39; boundaries Sec. 2.1.7).  The library also
+ * provides the edge readout, diagnostic maps and the adjoint of a time-stepped
+ * run with respect to per-cell extinction, albedo and emission.
+ *
+ * Conventions shared by every call
+ *  - Memory: every d_* pointer is device memory owned by the caller (for
+ *    example a torch tensor's data_ptr()), float32 unless stated.  It must stay
+ *    valid until the work queued on the context's stream has finished.  h_*
+ *    pointers are host memory read (or written) during the call only.  The
+ *    library allocates no device memory: all persistent device data lives in
+ *    the caller's workspace, whose size rt_workspace_bytes() returns.
+ *  - State layout: S[d][s][y][x], d = i_zen * n_az + j_az, s = 0..3 (I,Q,U,V),
+ *    x fastest; 4 * n * nx * ny floats, where n = n_zen * n_az.
+ *  - Stokes vectors of direction d are referred to its meridian frame
+ *    (e_theta, e_phi), polar axis +z.
+ *  - Asynchrony: all calls that take a context enqueue on the context's
+ *    stream and return without waiting, except where an h_* output is
+ *    written (those synchronise the stream).
+ *  - Errors: every call returns an rt_status; a message is available from
+ *    rt_last_error(ctx) (or rt_last_error(NULL) for calls without a context).
+ *    No call throws.  A context is used by one host thread at a time.
+ */
+#ifndef RT_LBM_H
+#define RT_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_ctx rt_ctx;
+
+typedef enum {
+  RT_OK = 0,
+  RT_EINVAL = 1,        /* null pointer, bad size or enum, NaN/Inf, albedo outside [0,1], tau < 0 */
+  RT_ERANGE = 2,        /* survival 1 - tau_sca < 0 (Eq. 31), |l| > 1, non-finite totals */
+  RT_ESTATE = 3,        /* call order misuse, e.g. stepping before rt_set_medium */
+  RT_ENOMEM = 4,        /* workspace or scratch buffer smaller than required */
+  RT_EDEVICE = 5,       /* a HIP runtime error */
+  RT_EUNSUPPORTED = 6   /* device is not gfx950, or an unsupported option combination */
+} rt_status;
+
+/* Arithmetic of the direction-pair contraction (the collision).  The state is
+ * always float32; streaming, emission, absorption and the survival term are
+ * always float32.  RT_FP32 uses float32 matrix cores, RT_BF16 / RT_FP16
+ * round the contraction operands to bf16 / fp16 (fp16 with a per-cell
+ * power-of-two scale of the state and a global one of the matrix) with
+ * float32 accumulation, RT_BF16X3 splits both operands into bf16 high and low
+ * parts and sums the three leading products. */
+typedef enum { RT_FP32 = 0, RT_BF16 = 1, RT_FP16 = 2, RT_BF16X3 = 3 } rt_precision;
+
+/* Zenith nodes: equal-area cos(theta) midpoints arccos(1 - (2i+1)/n_zen)
+ * (the reading of "uniformly distributed" pinned at n_zen = 2 by the DOP
+ * table of Sec. 3.2.2), uniform theta (i+1) pi/(n_zen+1), or explicit degrees. */
+typedef enum { RT_ZEN_EQUAL_AREA = 0, RT_ZEN_UNIFORM_THETA = 1, RT_ZEN_EXPLICIT = 2 } rt_zen_rule;
+
+/* Lattice plane and displacement per step l(d) (Eq. 33):
+ *   RT_PLANE_XY       l = courant * (k_x, k_y)   (horizontal plane)
+ *   RT_PLANE_XZ       l = courant * (k_x, k_z)   (vertical plane, lattice y = altitude)
+ *   RT_PLANE_XY_D2Q9  each component of (cos phi, sin phi) rounded to -1, 0 or 1
+ *                     (the D2Q9 velocities of Sec. 2.1); components within 1e-6
+ *                     of +-1/2 are refused as ambiguous. */
+typedef enum { RT_PLANE_XY = 0, RT_PLANE_XZ = 1, RT_PLANE_XY_D2Q9 = 2 } rt_plane;
+
+/* Edges are numbered 0 = x-, 1 = x+, 2 = y-, 3 = y+.  Periodic is the
+ * recycling boundary of Eq. 39 (both edges of an axis must be periodic or
+ * neither); absorbing discards what leaves (Sec. 2.1.7); inflow supplies a
+ * prescribed radiance per edge and direction to what enters. */
+typedef enum { RT_BC_PERIODIC = 0, RT_BC_ABSORBING = 1, RT_BC_INFLOW = 2 } rt_bc;
+
+/* Scalar phase function used in the Eq. 17 weights.  The polarisation part
+ * is always the Rayleigh reduced matrix rotated into the meridian frames
+ * (Eq. 13, 16), so HG and the mixture carry Rayleigh-shaped P12/P33/P44
+ * ratios.  HG(g) = (1-g^2)/(4 pi (1+g^2-2g cos)^1.5); the mixture is
+ * mix_ray * Rayleigh + (1 - mix_ray) * HG(g). */
+typedef enum { RT_PHASE_RAYLEIGH = 0, RT_PHASE_HG = 1, RT_PHASE_MIX = 2 } rt_phase;
+
+/* Option flags. */
+enum {
+  RT_ABS_TAYLOR = 1u << 0,    /* absorption factor 1 - tau_abs instead of exp(-tau_abs) (Sec. 2.1.4) */
+  RT_SCAT_EXP = 1u << 1,      /* survival exp(-tau_sca) instead of 1 - tau_sca (extension, not in the paper) */
+  RT_FUSED_TAYLOR = 1u << 2,  /* literal Eq. 2: Y = (1-tau_ext) S + tau_sca M S + dt J */
+  RT_RENORM_IROW = 1u << 3,   /* make sum_out of the Q,U -> I elements zero (exact conservation) */
+  RT_SCALAR = 1u << 4,        /* intensity-only transport: keep the I -> I elements only */
+  RT_PLAIN = 1u << 5          /* unfused reference path: separate stream and vector-ALU collision (RT_FP32 only) */
+};
+
+typedef struct {
+  int32_t nx, ny;             /* lattice size, >= 1 each */
+  int32_t n_zen, n_az;        /* direction grid, n = n_zen * n_az, 1 <= n <= 256 */
+  int32_t zen_rule;           /* rt_zen_rule */
+  const double *zen_deg;      /* host [n_zen] zenith angles in degrees for RT_ZEN_EXPLICIT, else NULL */
+  double az_offset_deg;       /* azimuths phi_j = offset + 360 j / n_az (Table 1 uses 0 and 22.5) */
+  int32_t plane;              /* rt_plane */
+  double courant;             /* c dt / dx for RT_PLANE_XY / RT_PLANE_XZ */
+  int32_t bc[4];              /* rt_bc per edge */
+  int32_t phase;              /* rt_phase */
+  double g;                   /* HG asymmetry for RT_PHASE_HG / RT_PHASE_MIX, |g| < 1 */
+  double mix_ray;             /* Rayleigh fraction for RT_PHASE_MIX, in [0, 1] */
+  double dt;                  /* time step multiplying the source J (Eq. 2, Eq. 8) */
+  uint32_t flags;             /* RT_* option flags */
+  int32_t precision;          /* rt_precision */
+} rt_problem;
+
+/* ---- host-only helpers (no device needed) ------------------------------ */
+
+/* Checks a problem description; RT_OK or the error code with a message. */
+rt_status rt_validate(const rt_problem *p);
+
+/* Bytes of device workspace rt_init needs for p (0 if p is invalid).  About
+ * 2 state buffers plus 2 adjoint buffers plus O(n^2 + cells) of tables. */
+size_t rt_workspace_bytes(const rt_problem *p);
+
+/* Bytes of one state S (4 * n * nx * ny floats). */
+size_t rt_state_bytes(const rt_problem *p);
+
+/* Direction set and operators in float64, as the library builds them.
+ *   h_dirs  [n][6] or NULL: theta, phi (radians), dOmega, l_x, l_y, outgoing
+ *           edge mask (bit e set when direction d leaves through edge e)
+ *   h_M     [4n][4n] or NULL: collision matrix, row 4*d_out+s_out, column
+ *           4*d_in+s_in: the Eq. 17 weight times the Rayleigh Mueller matrix
+ *           of the pair normalised to its I->I element (Eq. 13, 16, 25/30),
+ *           built from the dipole field projection in the meridian frames. */
+rt_status rt_describe(const rt_problem *p, double *h_dirs, double *h_M);
+
+/* Number of directions leaving through `edge` (the readout width). */
+int32_t rt_num_outgoing(const rt_problem *p, int32_t edge);
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Builds the direction set and operators (host, float64), uploads the
+ * tables into d_ws (ws_bytes >= rt_workspace_bytes(p)) on `stream` (a
+ * hipStream_t, NULL = default stream) and returns a context in *out.
+ * RT_EUNSUPPORTED if the current device is not gfx950. */
+rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream, rt_ctx **out);
+
+/* Per-cell medium, [ny][nx] each: d_tau = per-step extinction optical depth
+ * k_ext * dt (>= 0), d_albedo = k_scat / k_ext in [0, 1], d_emis = emission
+ * amplitude eps.  The source of direction d is J = eps * h_jprof[d][0..3]
+ * (host [n][4]).  h_inflow (host [4][n][4] or NULL = zero) is the radiance
+ * entering through each inflow edge per direction.  The values are copied
+ * into the workspace and the per-cell coefficients alpha = a s,
+ * beta = a (1 - s) (a = absorption factor, s = survival, Eq. 11) are formed.
+ * Validation needs the values on the host, so this call synchronises the
+ * stream; RT_ERANGE if some cell has 1 - tau_sca < 0 (Eq. 31). */
+rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, const float *d_emis,
+                        const float *h_jprof, const float *h_inflow);
+
+/* One step S_out = Stream(Collide(S_in)); S_in and S_out must not overlap. */
+rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out);
+
+/* nsteps steps in place on d_S (S_0 in, S_nsteps out).  If d_ckpt is not NULL
+ * it receives S_{k*ckpt_every} in slot k = 0 .. ceil(nsteps/ckpt_every)-1
+ * (slots of rt_state_bytes each), as rt_adjoint expects. */
+rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t ckpt_every);
+
+/* Stokes vectors of the outgoing directions on one edge row/column:
+ * d_out[e][k][4], e along the edge (x for edges 2,3; y for edges 0,1), k over
+ * the directions leaving through the edge in increasing d.  If h_sums is not
+ * NULL it receives the float64 sums of I, Q, U, V over the whole field
+ * (synchronises). */
+rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, double *h_sums);
+
+/* Direction-mean intensity and direction-mean degree of polarisation
+ * sqrt(Q^2+U^2+V^2)/I (Sec. 3.2.1) per cell, [ny][nx] each. */
+rt_status rt_maps(rt_ctx *c, const float *d_S, float *d_I_mean, float *d_dop_mean);
+
+/* Transpose of rt_readout: d_lambdaT (a full state) is set to zero except the
+ * edge entries, which receive d_gout[e][k][4]. */
+rt_status rt_readout_adjoint(rt_ctx *c, int32_t edge, const float *d_gout, float *d_lambdaT);
+
+/* Bytes of the segment buffer rt_adjoint needs for ckpt_every. */
+size_t rt_adjoint_segment_bytes(const rt_problem *p, int32_t ckpt_every);
+
+/* Gradients of a loss L(S_nsteps) with respect to the per-cell medium, given
+ * d_lambdaT = dL/dS_nsteps, by reverse time stepping with checkpoints written
+ * by rt_run (same nsteps and ckpt_every; recomputes each segment into d_seg).
+ * Outputs [ny][nx]: d_g_tau = dL/dtau, d_g_albedo = dL/dalbedo, d_g_emis =
+ * dL/deps; d_lambda0 (state, or NULL) = dL/dS_0.  Inflow radiances and the
+ * emission profile are treated as constants. */
+rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckpt_every, float *d_seg,
+                     const float *d_lambdaT, float *d_g_tau, float *d_g_albedo, float *d_g_emis,
+                     float *d_lambda0);
+
+/* Waits for the context's stream. */
+rt_status rt_synchronize(rt_ctx *c);
+
+/* Releases the context (not the caller's memory). */
+rt_status rt_destroy(rt_ctx *c);
+
+const char *rt_status_str(rt_status s);
+const char *rt_last_error(const rt_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT_LBM_H */

@@ -1,0 +1,166 @@
+"""ctypes binding of librtlbm.so: the C ABI of include/rt_lbm.h under the same names.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device pointers are passed as integers (for example tensor.data_ptr()).  A
+non-RT_OK status raises RTError carrying rt_last_error().  If the library has
+not been built, importing this module raises ImportError: there is no fallback.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_size_t, c_uint32, c_void_p
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtlbm.so")
+
+RT_OK, RT_EINVAL, RT_ERANGE, RT_ESTATE, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED = range(7)
+RT_FP32, RT_BF16, RT_FP16, RT_BF16X3 = range(4)
+RT_ZEN_EQUAL_AREA, RT_ZEN_UNIFORM_THETA, RT_ZEN_EXPLICIT = range(3)
+RT_PLANE_XY, RT_PLANE_XZ, RT_PLANE_XY_D2Q9 = range(3)
+RT_BC_PERIODIC, RT_BC_ABSORBING, RT_BC_INFLOW = range(3)
+RT_PHASE_RAYLEIGH, RT_PHASE_HG, RT_PHASE_MIX = range(3)
+RT_ABS_TAYLOR, RT_SCAT_EXP, RT_FUSED_TAYLOR, RT_RENORM_IROW, RT_SCALAR, RT_PLAIN = (
+    1, 2, 4, 8, 16, 32)
+
+PRECISIONS = {"fp32": RT_FP32, "bf16": RT_BF16, "fp16": RT_FP16, "bf16x3": RT_BF16X3}
+
+
+class RtProblem(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("n_zen", c_int32), ("n_az", c_int32),
+                ("zen_rule", c_int32), ("zen_deg", POINTER(c_double)),
+                ("az_offset_deg", c_double), ("plane", c_int32), ("courant", c_double),
+                ("bc", c_int32 * 4), ("phase", c_int32), ("g", c_double), ("mix_ray", c_double),
+                ("dt", c_double), ("flags", c_uint32), ("precision", c_int32)]
+
+
+class RTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+_STATUS = {RT_OK: "RT_OK", RT_EINVAL: "RT_EINVAL", RT_ERANGE: "RT_ERANGE",
+           RT_ESTATE: "RT_ESTATE", RT_ENOMEM: "RT_ENOMEM", RT_EDEVICE: "RT_EDEVICE",
+           RT_EUNSUPPORTED: "RT_EUNSUPPORTED"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librtlbm.so is not built; run python -m paper_2609_23057_amd.build")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = POINTER(RtProblem)
+_SIGS = {
+    "rt_validate": (c_int32, [_P]),
+    "rt_workspace_bytes": (c_size_t, [_P]),
+    "rt_state_bytes": (c_size_t, [_P]),
+    "rt_describe": (c_int32, [_P, c_void_p, c_void_p]),
+    "rt_num_outgoing": (c_int32, [_P, c_int32]),
+    "rt_init": (c_int32, [_P, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "rt_set_medium": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "rt_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rt_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
+    "rt_readout": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "rt_maps": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "rt_readout_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "rt_adjoint_segment_bytes": (c_size_t, [_P, c_int32]),
+    "rt_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_void_p, c_void_p]),
+    "rt_synchronize": (c_int32, [c_void_p]),
+    "rt_destroy": (c_int32, [c_void_p]),
+    "rt_status_str": (c_char_p, [c_int32]),
+    "rt_last_error": (c_char_p, [c_void_p]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(status, ctx=None):
+    if status != RT_OK:
+        msg = _lib.rt_last_error(ctx)
+        raise RTError(status, msg.decode() if msg else "")
+
+
+def rt_status_str(status):
+    return _lib.rt_status_str(status).decode()
+
+
+def rt_last_error(ctx=None):
+    m = _lib.rt_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def rt_validate(p):
+    _check(_lib.rt_validate(ctypes.byref(p)))
+
+
+def rt_workspace_bytes(p):
+    return int(_lib.rt_workspace_bytes(ctypes.byref(p)))
+
+
+def rt_state_bytes(p):
+    return int(_lib.rt_state_bytes(ctypes.byref(p)))
+
+
+def rt_describe(p, h_dirs=None, h_M=None):
+    """h_dirs / h_M: numpy float64 arrays ([n,6], [4n,4n]) or None."""
+    _check(_lib.rt_describe(ctypes.byref(p),
+                            None if h_dirs is None else h_dirs.ctypes.data,
+                            None if h_M is None else h_M.ctypes.data))
+
+
+def rt_num_outgoing(p, edge):
+    return int(_lib.rt_num_outgoing(ctypes.byref(p), edge))
+
+
+def rt_init(p, d_ws, ws_bytes, stream):
+    out = c_void_p()
+    _check(_lib.rt_init(ctypes.byref(p), d_ws, ws_bytes, stream, ctypes.byref(out)))
+    return out.value
+
+
+def rt_set_medium(ctx, d_tau, d_albedo, d_emis, h_jprof, h_inflow=None):
+    """h_jprof / h_inflow: numpy float32 arrays ([n,4], [4,n,4]) or None."""
+    _check(_lib.rt_set_medium(ctx, d_tau, d_albedo, d_emis, h_jprof.ctypes.data,
+                              None if h_inflow is None else h_inflow.ctypes.data), ctx)
+
+
+def rt_step(ctx, d_S_in, d_S_out):
+    _check(_lib.rt_step(ctx, d_S_in, d_S_out), ctx)
+
+
+def rt_run(ctx, d_S, nsteps, d_ckpt=None, ckpt_every=0):
+    _check(_lib.rt_run(ctx, d_S, nsteps, d_ckpt, ckpt_every), ctx)
+
+
+def rt_readout(ctx, d_S, edge, d_out=None, h_sums=None):
+    """h_sums: numpy float64 array of 4 or None."""
+    _check(_lib.rt_readout(ctx, d_S, edge, d_out,
+                           None if h_sums is None else h_sums.ctypes.data), ctx)
+
+
+def rt_maps(ctx, d_S, d_I_mean, d_dop_mean):
+    _check(_lib.rt_maps(ctx, d_S, d_I_mean, d_dop_mean), ctx)
+
+
+def rt_readout_adjoint(ctx, edge, d_gout, d_lambdaT):
+    _check(_lib.rt_readout_adjoint(ctx, edge, d_gout, d_lambdaT), ctx)
+
+
+def rt_adjoint_segment_bytes(p, ckpt_every):
+    return int(_lib.rt_adjoint_segment_bytes(ctypes.byref(p), ckpt_every))
+
+
+def rt_adjoint(ctx, nsteps, d_ckpt, ckpt_every, d_seg, d_lambdaT, d_g_tau, d_g_albedo, d_g_emis,
+               d_lambda0=None):
+    _check(_lib.rt_adjoint(ctx, nsteps, d_ckpt, ckpt_every, d_seg, d_lambdaT, d_g_tau,
+                           d_g_albedo, d_g_emis, d_lambda0), ctx)
+
+
+def rt_synchronize(ctx):
+    _check(_lib.rt_synchronize(ctx), ctx)
+
+
+def rt_destroy(ctx):
+    _check(_lib.rt_destroy(ctx))

@@ -1,0 +1,577 @@
+// C ABI of the polarized LBM solver: contexts, workspace layout, time loops.
+//
+// The forward time loop keeps the post-collision field Y_t in two workspace
+// buffers and streams it inside the next step's load (fused kernel), so one
+// step reads and writes the state once:
+//   Y_0 = collide(S_0);  Y_t = collide(L(Y_{t-1}));  S_T = L(Y_{T-1}).
+// The adjoint replays the run backwards with square-root checkpointing:
+// rt_run stores S_{kK}; for each segment in reverse the forward is recomputed
+// into the caller's segment buffer and the fused adjoint kernel walks it back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+#include "rt_kernels.h"
+
+using namespace rtl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+  // byte offsets into the workspace
+  size_t tables, tables_bytes;   // uploaded host tables (rows, taps, tiles, fragments, M)
+  size_t rows, taps, outdirs, M_abi;
+  size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
+  size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
+  size_t jrow, ghost;             // set by rt_set_medium
+  size_t tau, alb, emis, alpha, beta;
+  size_t gacc, partial, sums, bad;
+  size_t Ya, Yb, La, Lb;
+  size_t total;
+  int npart;
+};
+
+struct Packed {
+  std::vector<TileRange> t_fwd32, t_adj32, t_fwd, t_adj;
+  std::vector<uint8_t> f_fwd32, f_adj32, f_fwd, f_fwd_lo, f_adj, f_adj_lo;
+  double a_scale = 1.0;
+};
+
+void pack_all(const HostPlan &hp, int prec, Packed *pk) {
+  std::vector<TileRange> dummy;
+  pack_fragments(hp, false, FRAG_F32, 1.0, false, &pk->t_fwd32, &pk->f_fwd32);
+  pack_fragments(hp, true, FRAG_F32, 1.0, false, &pk->t_adj32, &pk->f_adj32);
+  if (prec == RT_FP32) {
+    pk->t_fwd = pk->t_fwd32;
+    pk->t_adj = pk->t_adj32;
+    return;
+  }
+  FragKind kind = prec == RT_FP16 ? FRAG_F16 : FRAG_BF16;
+  double scale = 1.0;
+  if (prec == RT_FP16) {
+    double mx = 0.0;
+    for (double v : hp.M) mx = std::max(mx, std::fabs(v));
+    int e = 0;
+    if (mx > 0) std::frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+    scale = std::ldexp(1.0, 13 - e);  // max |M| scale in [2^12, 2^13)
+  }
+  pk->a_scale = scale;
+  pack_fragments(hp, false, kind, scale, false, &pk->t_fwd, &pk->f_fwd);
+  pack_fragments(hp, true, kind, scale, false, &pk->t_adj, &pk->f_adj);
+  if (prec == RT_BF16X3) {
+    pack_fragments(hp, false, FRAG_BF16, 1.0, true, &dummy, &pk->f_fwd_lo);
+    pack_fragments(hp, true, FRAG_BF16, 1.0, true, &dummy, &pk->f_adj_lo);
+  }
+}
+
+Layout make_layout(const HostPlan &hp, const Packed &pk) {
+  Layout L{};
+  const size_t C = (size_t)hp.nx * hp.ny;
+  const size_t state = C * 4 * hp.n * sizeof(float);
+  const int ntile = hp.Rpad / kTileRows;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.tables = off;
+  L.rows = take(hp.Rpad * sizeof(RowInfo));
+  L.taps = take(hp.n * sizeof(DirTaps));
+  L.outdirs = take(4 * hp.n * sizeof(int32_t));
+  L.M_abi = take((size_t)hp.R * hp.R * sizeof(float));
+  L.tiles_fwd32 = take(ntile * sizeof(TileRange));
+  L.tiles_adj32 = take(ntile * sizeof(TileRange));
+  L.tiles_fwd = take(ntile * sizeof(TileRange));
+  L.tiles_adj = take(ntile * sizeof(TileRange));
+  L.frag_fwd32 = take(pk.f_fwd32.size());
+  L.frag_adj32 = take(pk.f_adj32.size());
+  L.frag_fwd = take(pk.f_fwd.size());
+  L.frag_fwd_lo = take(pk.f_fwd_lo.size());
+  L.frag_adj = take(pk.f_adj.size());
+  L.frag_adj_lo = take(pk.f_adj_lo.size());
+  L.tables_bytes = off - L.tables;
+  L.jrow = take(hp.Rpad * sizeof(float));
+  L.ghost = take(4 * hp.Rpad * sizeof(float));
+  L.tau = take(C * sizeof(float));
+  L.alb = take(C * sizeof(float));
+  L.emis = take(C * sizeof(float));
+  L.alpha = take(C * sizeof(float));
+  L.beta = take(C * sizeof(float));
+  L.gacc = take(3 * C * sizeof(double));
+  Geometry g{(int64_t)C, hp.nx, hp.ny, 0, 0, hp.n, hp.R, hp.Rpad};
+  L.npart = sums_partials(g);
+  L.partial = take((size_t)L.npart * 4 * sizeof(double));
+  L.sums = take(4 * sizeof(double));
+  L.bad = take(sizeof(int));
+  L.Ya = take(state);
+  L.Yb = take(state);
+  L.La = take(state);
+  L.Lb = take(state);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct rt_ctx {
+  rt_problem prob{};
+  std::vector<double> zen;
+  HostPlan hp;
+  Packed pk;
+  Layout L{};
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  Geometry geo{};
+  std::vector<uint8_t> host_tables;
+  std::vector<float> host_medium;  // jrow + ghost staging
+  int nout[4] = {0, 0, 0, 0};
+  bool medium_set = false;
+  int prec = 0;
+  int cb_fwd = 2, cb_adj = 2;
+  int grid_limit = 1024;
+  std::string err;
+
+  template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+  rt_status fail(rt_status s, const std::string &m) {
+    err = m;
+    g_last_error = m;
+    return s;
+  }
+  rt_status hip(hipError_t e, const char *where) {
+    if (e == hipSuccess) return RT_OK;
+    return fail(RT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  }
+  StepArgs args(bool adjoint) const;
+};
+
+StepArgs rt_ctx::args(bool adjoint) const {
+  StepArgs a{};
+  a.geo = geo;
+  a.rows = at<RowInfo>(L.rows);
+  a.taps = at<DirTaps>(L.taps);
+  a.jrow = at<float>(L.jrow);
+  a.ghost = at<float>(L.ghost);
+  a.alpha = at<float>(L.alpha);
+  a.beta = at<float>(L.beta);
+  a.emis = at<float>(L.emis);
+  const bool fused_taylor = (prob.flags & RT_FUSED_TAYLOR) != 0;
+  a.dt_pre = fused_taylor ? 0.0f : (float)prob.dt;
+  a.dt_post = fused_taylor ? (float)prob.dt : 0.0f;
+  const bool f32 = prec == P_F32;
+  a.frag = at<uint4>(adjoint ? (f32 ? L.frag_adj32 : L.frag_adj) : (f32 ? L.frag_fwd32 : L.frag_fwd));
+  a.frag_lo = at<uint4>(adjoint ? L.frag_adj_lo : L.frag_fwd_lo);
+  a.tiles = at<TileRange>(adjoint ? (f32 ? L.tiles_adj32 : L.tiles_adj)
+                                  : (f32 ? L.tiles_fwd32 : L.tiles_fwd));
+  a.a_scale_inv = (float)(1.0 / pk.a_scale);
+  a.gacc = at<double>(L.gacc);
+  return a;
+}
+
+namespace {
+
+rt_status set_err(rt_status s, const std::string &m) {
+  g_last_error = m;
+  return s;
+}
+
+rt_status plan_for(const rt_problem *p, HostPlan *hp, Packed *pk, Layout *L, std::string *msg) {
+  rt_status st = build_plan(p, hp, msg);
+  if (st != RT_OK) return st;
+  pack_all(*hp, p->precision, pk);
+  *L = make_layout(*hp, *pk);
+  return RT_OK;
+}
+
+size_t state_elems(const rt_ctx *c) { return (size_t)c->geo.C * 4 * c->geo.n; }
+
+}  // namespace
+
+extern "C" {
+
+const char *rt_status_str(rt_status s) {
+  switch (s) {
+    case RT_OK: return "RT_OK";
+    case RT_EINVAL: return "RT_EINVAL";
+    case RT_ERANGE: return "RT_ERANGE";
+    case RT_ESTATE: return "RT_ESTATE";
+    case RT_ENOMEM: return "RT_ENOMEM";
+    case RT_EDEVICE: return "RT_EDEVICE";
+    case RT_EUNSUPPORTED: return "RT_EUNSUPPORTED";
+  }
+  return "RT_UNKNOWN";
+}
+
+const char *rt_last_error(const rt_ctx *c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+rt_status rt_validate(const rt_problem *p) {
+  HostPlan hp;
+  std::string msg;
+  rt_status st = build_plan(p, &hp, &msg);
+  if (st != RT_OK) return set_err(st, msg);
+  if (!(p->flags & RT_PLAIN) && hp.Rpad > 512)
+    return set_err(RT_EUNSUPPORTED, "the fused matrix-core path supports n <= 128 (use RT_PLAIN)");
+  g_last_error.clear();
+  return RT_OK;
+}
+
+size_t rt_workspace_bytes(const rt_problem *p) {
+  if (rt_validate(p) != RT_OK) return 0;
+  HostPlan hp;
+  Packed pk;
+  Layout L;
+  std::string msg;
+  if (plan_for(p, &hp, &pk, &L, &msg) != RT_OK) return 0;
+  return L.total;
+}
+
+size_t rt_state_bytes(const rt_problem *p) {
+  if (!p || p->nx < 1 || p->ny < 1 || p->n_zen < 1 || p->n_az < 1) return 0;
+  return (size_t)p->nx * p->ny * p->n_zen * p->n_az * 4 * sizeof(float);
+}
+
+size_t rt_adjoint_segment_bytes(const rt_problem *p, int32_t ckpt_every) {
+  if (ckpt_every < 1) return 0;
+  const size_t k = ckpt_every > 1 ? (size_t)(ckpt_every - 1) : 1;
+  return k * rt_state_bytes(p);
+}
+
+rt_status rt_describe(const rt_problem *p, double *h_dirs, double *h_M) {
+  HostPlan hp;
+  std::string msg;
+  rt_status st = build_plan(p, &hp, &msg);
+  if (st != RT_OK) return set_err(st, msg);
+  if (h_dirs) {
+    for (int d = 0; d < hp.n; ++d) {
+      h_dirs[6 * d + 0] = hp.theta[d];
+      h_dirs[6 * d + 1] = hp.phi[d];
+      h_dirs[6 * d + 2] = hp.domega[d];
+      h_dirs[6 * d + 3] = hp.lx[d];
+      h_dirs[6 * d + 4] = hp.ly[d];
+      h_dirs[6 * d + 5] = hp.outmask[d];
+    }
+  }
+  if (h_M) std::memcpy(h_M, hp.M.data(), hp.M.size() * sizeof(double));
+  return RT_OK;
+}
+
+int32_t rt_num_outgoing(const rt_problem *p, int32_t edge) {
+  HostPlan hp;
+  std::string msg;
+  if (edge < 0 || edge > 3 || build_plan(p, &hp, &msg) != RT_OK) return -1;
+  int k = 0;
+  for (int d = 0; d < hp.n; ++d) k += (hp.outmask[d] >> edge) & 1;
+  return k;
+}
+
+rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream, rt_ctx **out) {
+  if (!out) return set_err(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  rt_status st = rt_validate(p);
+  if (st != RT_OK) return st;
+  if (!d_ws) return set_err(RT_EINVAL, "workspace is NULL");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return set_err(RT_EDEVICE, "no HIP device");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_err(RT_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+
+  rt_ctx *c = new rt_ctx();
+  c->prob = *p;
+  if (p->zen_rule == RT_ZEN_EXPLICIT) {
+    c->zen.assign(p->zen_deg, p->zen_deg + p->n_zen);
+    c->prob.zen_deg = c->zen.data();
+  } else {
+    c->prob.zen_deg = nullptr;
+  }
+  std::string msg;
+  st = plan_for(&c->prob, &c->hp, &c->pk, &c->L, &msg);
+  if (st != RT_OK) {
+    delete c;
+    return set_err(st, msg);
+  }
+  if (ws_bytes < c->L.total) {
+    delete c;
+    return set_err(RT_ENOMEM, "workspace smaller than rt_workspace_bytes()");
+  }
+  c->ws = static_cast<char *>(d_ws);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->prec = p->precision;
+  const HostPlan &hp = c->hp;
+  c->geo = Geometry{(int64_t)hp.nx * hp.ny, hp.nx, hp.ny, p->bc[0] == RT_BC_PERIODIC,
+                    p->bc[2] == RT_BC_PERIODIC, hp.n, hp.R, hp.Rpad};
+
+  // launch shapes: two cell blocks per tile when the LDS budget allows
+  const size_t lds_max = 160 * 1024;
+  c->cb_fwd = step_lds_bytes(c->geo, c->prec, 2, false) <= lds_max ? 2 : 1;
+  c->cb_adj = step_lds_bytes(c->geo, c->prec, 2, true) <= lds_max ? 2 : 1;
+  if (!(p->flags & RT_PLAIN) && (step_lds_bytes(c->geo, c->prec, c->cb_fwd, false) > lds_max ||
+                                 step_lds_bytes(c->geo, c->prec, c->cb_adj, true) > lds_max)) {
+    delete c;
+    return set_err(RT_EUNSUPPORTED, "problem does not fit the fused kernel's LDS budget");
+  }
+  const int W = hp.Rpad / 32;
+  const int per_cu = std::max(1, std::min(8, 16 / W));
+  c->grid_limit = prop.multiProcessorCount * per_cu;
+
+  // host tables
+  std::vector<uint8_t> &tb = c->host_tables;
+  tb.assign(c->L.tables_bytes, 0);
+  auto put = [&](size_t off, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(tb.data() + (off - c->L.tables), src, bytes);
+  };
+  std::vector<RowInfo> rows(hp.Rpad, RowInfo{-1, 0});
+  for (int d = 0; d < hp.n; ++d)
+    for (int s = 0; s < 4; ++s) rows[gemm_row(hp.n, d, s)] = RowInfo{(int16_t)(4 * d + s), (int16_t)d};
+  put(c->L.rows, rows.data(), rows.size() * sizeof(RowInfo));
+  std::vector<DirTaps> taps(hp.n);
+  for (int d = 0; d < hp.n; ++d) {
+    const double fx0 = std::floor(hp.lx[d]), fy0 = std::floor(hp.ly[d]);
+    const double fx = hp.lx[d] - fx0, fy = hp.ly[d] - fy0;
+    taps[d] = DirTaps{(int32_t)fx0, (int32_t)fy0, (float)(1.0 - fx), (float)fx, (float)(1.0 - fy), (float)fy};
+  }
+  put(c->L.taps, taps.data(), taps.size() * sizeof(DirTaps));
+  std::vector<int32_t> od(4 * hp.n, 0);
+  for (int e = 0; e < 4; ++e) {
+    int k = 0;
+    for (int d = 0; d < hp.n; ++d)
+      if ((hp.outmask[d] >> e) & 1) od[e * hp.n + k++] = d;
+    c->nout[e] = k;
+  }
+  put(c->L.outdirs, od.data(), od.size() * sizeof(int32_t));
+  std::vector<float> M32(hp.M.size());
+  for (size_t i = 0; i < M32.size(); ++i) M32[i] = (float)hp.M[i];
+  put(c->L.M_abi, M32.data(), M32.size() * sizeof(float));
+  put(c->L.tiles_fwd32, c->pk.t_fwd32.data(), c->pk.t_fwd32.size() * sizeof(TileRange));
+  put(c->L.tiles_adj32, c->pk.t_adj32.data(), c->pk.t_adj32.size() * sizeof(TileRange));
+  put(c->L.tiles_fwd, c->pk.t_fwd.data(), c->pk.t_fwd.size() * sizeof(TileRange));
+  put(c->L.tiles_adj, c->pk.t_adj.data(), c->pk.t_adj.size() * sizeof(TileRange));
+  put(c->L.frag_fwd32, c->pk.f_fwd32.data(), c->pk.f_fwd32.size());
+  put(c->L.frag_adj32, c->pk.f_adj32.data(), c->pk.f_adj32.size());
+  put(c->L.frag_fwd, c->pk.f_fwd.data(), c->pk.f_fwd.size());
+  put(c->L.frag_fwd_lo, c->pk.f_fwd_lo.data(), c->pk.f_fwd_lo.size());
+  put(c->L.frag_adj, c->pk.f_adj.data(), c->pk.f_adj.size());
+  put(c->L.frag_adj_lo, c->pk.f_adj_lo.data(), c->pk.f_adj_lo.size());
+  st = c->hip(hipMemcpyAsync(c->ws + c->L.tables, tb.data(), tb.size(), hipMemcpyHostToDevice, c->stream),
+              "upload tables");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "upload tables");
+  if (st != RT_OK) {
+    std::string m = c->err;
+    delete c;
+    return set_err(st, m);
+  }
+  *out = c;
+  return RT_OK;
+}
+
+rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, const float *d_emis,
+                        const float *h_jprof, const float *h_inflow) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_tau || !d_albedo || !d_emis || !h_jprof) return c->fail(RT_EINVAL, "NULL medium pointer");
+  const HostPlan &hp = c->hp;
+  const int n = hp.n, Rp = hp.Rpad;
+  std::vector<float> &hm = c->host_medium;
+  hm.assign(Rp + 4 * Rp, 0.0f);
+  for (int d = 0; d < n; ++d)
+    for (int s = 0; s < 4; ++s) {
+      const float v = h_jprof[4 * d + s];
+      if (!std::isfinite(v)) return c->fail(RT_EINVAL, "emission profile not finite");
+      hm[gemm_row(n, d, s)] = v;
+    }
+  for (int e = 0; e < 4; ++e)
+    for (int d = 0; d < n; ++d)
+      for (int s = 0; s < 4; ++s) {
+        const float v = h_inflow ? h_inflow[(e * n + d) * 4 + s] : 0.0f;
+        if (!std::isfinite(v)) return c->fail(RT_EINVAL, "inflow radiance not finite");
+        hm[Rp + e * Rp + gemm_row(n, d, s)] = (c->prob.bc[e] == RT_BC_INFLOW) ? v : 0.0f;
+      }
+  static_assert(sizeof(float) == 4, "float");
+  rt_status st = c->hip(hipMemcpyAsync(c->ws + c->L.jrow, hm.data(), Rp * sizeof(float),
+                                       hipMemcpyHostToDevice, c->stream), "upload jprof");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data() + Rp, 4 * Rp * sizeof(float),
+                               hipMemcpyHostToDevice, c->stream), "upload inflow");
+  int *bad = c->at<int>(c->L.bad);
+  if (st == RT_OK) st = c->hip(hipMemsetAsync(bad, 0, sizeof(int), c->stream), "clear counter");
+  if (st == RT_OK)
+    st = c->hip(launch_coef(c->geo.C, d_tau, d_albedo, d_emis, c->at<float>(c->L.tau), c->at<float>(c->L.alb),
+                            c->at<float>(c->L.emis), c->at<float>(c->L.alpha), c->at<float>(c->L.beta),
+                            c->prob.flags, bad, c->stream), "coef");
+  int hbad = 0;
+  if (st == RT_OK) st = c->hip(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream), "read counter");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "set_medium");
+  if (st != RT_OK) return st;
+  if (hbad) {
+    c->medium_set = false;
+    return c->fail(RT_ERANGE, std::to_string(hbad) +
+                                  " cells have invalid tau/albedo/emission or a negative survival "
+                                  "1 - tau_sca (or absorption factor)");
+  }
+  c->medium_set = true;
+  return RT_OK;
+}
+
+static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, float *s_out) {
+  StepArgs a = c->args(false);
+  a.in = in;
+  a.out = out;
+  a.s_out = s_out;
+  return c->hip(launch_step_mfma(a, c->prec, gather, c->cb_fwd, c->stream, c->grid_limit), "step");
+}
+
+static rt_status plain_step(rt_ctx *c, const float *S_in, float *S_out) {
+  StepArgs a = c->args(false);
+  float *Y = c->at<float>(c->L.Ya);
+  rt_status st = c->hip(launch_collide_valu(a, c->at<float>(c->L.M_abi), S_in, Y, c->stream), "collide");
+  if (st == RT_OK) st = c->hip(launch_stream(a, Y, S_out, c->stream), "stream");
+  return st;
+}
+
+rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_S_in || !d_S_out) return c->fail(RT_EINVAL, "NULL state pointer");
+  if (d_S_in == d_S_out) return c->fail(RT_EINVAL, "S_in and S_out must differ");
+  if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  if (c->prob.flags & RT_PLAIN) return plain_step(c, d_S_in, d_S_out);
+  float *Y = c->at<float>(c->L.Ya);
+  rt_status st = fwd_step(c, d_S_in, false, Y, nullptr);
+  if (st == RT_OK) st = c->hip(launch_stream(c->args(false), Y, d_S_out, c->stream), "stream");
+  return st;
+}
+
+rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t ckpt_every) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_S) return c->fail(RT_EINVAL, "NULL state pointer");
+  if (nsteps < 0) return c->fail(RT_EINVAL, "nsteps < 0");
+  if (d_ckpt && ckpt_every < 1) return c->fail(RT_EINVAL, "ckpt_every < 1");
+  if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  if (nsteps == 0) return RT_OK;
+  const size_t sb = state_elems(c) * sizeof(float);
+  auto slot = [&](int k) { return reinterpret_cast<float *>(reinterpret_cast<char *>(d_ckpt) + (size_t)k * sb); };
+  rt_status st = RT_OK;
+  if (c->prob.flags & RT_PLAIN) {
+    for (int t = 0; t < nsteps && st == RT_OK; ++t) {
+      if (d_ckpt && t % ckpt_every == 0)
+        st = c->hip(hipMemcpyAsync(slot(t / ckpt_every), d_S, sb, hipMemcpyDeviceToDevice, c->stream), "ckpt");
+      if (st == RT_OK) st = plain_step(c, d_S, d_S);
+    }
+    return st;
+  }
+  float *Y[2] = {c->at<float>(c->L.Ya), c->at<float>(c->L.Yb)};
+  if (d_ckpt) st = c->hip(hipMemcpyAsync(slot(0), d_S, sb, hipMemcpyDeviceToDevice, c->stream), "ckpt");
+  if (st == RT_OK) st = fwd_step(c, d_S, false, Y[0], nullptr);
+  for (int t = 1; t < nsteps && st == RT_OK; ++t) {
+    float *s_out = (d_ckpt && t % ckpt_every == 0) ? slot(t / ckpt_every) : nullptr;
+    st = fwd_step(c, Y[(t - 1) & 1], true, Y[t & 1], s_out);
+  }
+  if (st == RT_OK) st = c->hip(launch_stream(c->args(false), Y[(nsteps - 1) & 1], d_S, c->stream), "stream");
+  return st;
+}
+
+rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, double *h_sums) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_S) return c->fail(RT_EINVAL, "NULL state pointer");
+  if (edge < 0 || edge > 3) return c->fail(RT_EINVAL, "edge must be 0..3");
+  rt_status st = RT_OK;
+  if (d_out)
+    st = c->hip(launch_readout(c->geo, d_S, edge, c->at<int32_t>(c->L.outdirs) + edge * c->geo.n,
+                               c->nout[edge], d_out, c->stream), "readout");
+  if (st == RT_OK && h_sums) {
+    double *res = c->at<double>(c->L.sums);
+    st = c->hip(launch_sums(c->geo, d_S, c->at<double>(c->L.partial), c->L.npart, res, c->stream), "sums");
+    if (st == RT_OK) st = c->hip(hipMemcpyAsync(h_sums, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "sums");
+    if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "sums");
+    if (st == RT_OK)
+      for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(h_sums[k])) return c->fail(RT_ERANGE, "non-finite Stokes totals");
+  }
+  return st;
+}
+
+rt_status rt_maps(rt_ctx *c, const float *d_S, float *d_I_mean, float *d_dop_mean) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_S || !d_I_mean || !d_dop_mean) return c->fail(RT_EINVAL, "NULL pointer");
+  return c->hip(launch_maps(c->geo, d_S, d_I_mean, d_dop_mean, c->stream), "maps");
+}
+
+rt_status rt_readout_adjoint(rt_ctx *c, int32_t edge, const float *d_gout, float *d_lambdaT) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_gout || !d_lambdaT) return c->fail(RT_EINVAL, "NULL pointer");
+  if (edge < 0 || edge > 3) return c->fail(RT_EINVAL, "edge must be 0..3");
+  rt_status st = c->hip(launch_fill_f32(d_lambdaT, (int64_t)state_elems(c), 0.0f, c->stream), "fill");
+  if (st == RT_OK)
+    st = c->hip(launch_readout_adjoint(c->geo, edge, c->at<int32_t>(c->L.outdirs) + edge * c->geo.n,
+                                       c->nout[edge], d_gout, d_lambdaT, c->stream), "readout adjoint");
+  return st;
+}
+
+rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckpt_every, float *d_seg,
+                     const float *d_lambdaT, float *d_g_tau, float *d_g_albedo, float *d_g_emis,
+                     float *d_lambda0) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_ckpt || !d_lambdaT) return c->fail(RT_EINVAL, "NULL checkpoint or lambda_T");
+  if (nsteps < 1 || ckpt_every < 1) return c->fail(RT_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
+  if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  const int prec_save = c->prec;
+  if (c->prob.flags & RT_PLAIN) c->prec = P_F32;  // the plain path replays on the fused float32 kernels
+  const size_t sb = state_elems(c) * sizeof(float);
+  auto ck = [&](int k) {
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(d_ckpt) + (size_t)k * sb);
+  };
+  auto seg = [&](int k) { return reinterpret_cast<float *>(reinterpret_cast<char *>(d_seg) + (size_t)k * sb); };
+  rt_status st = c->hip(launch_fill_f64(c->at<double>(c->L.gacc), 3 * c->geo.C, 0.0, c->stream), "fill");
+  float *Lb[2] = {c->at<float>(c->L.La), c->at<float>(c->L.Lb)};
+  const float *lam_next = d_lambdaT;
+  int flip = 0;
+  const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+  for (int k = nseg - 1; k >= 0 && st == RT_OK; --k) {
+    const int t0 = k * ckpt_every;
+    const int t1 = std::min(nsteps, t0 + ckpt_every);
+    // recompute Y_{t0} .. Y_{t1-2}
+    if (t1 - t0 >= 2) {
+      st = fwd_step(c, ck(k), false, seg(0), nullptr);
+      for (int t = t0 + 1; t <= t1 - 2 && st == RT_OK; ++t)
+        st = fwd_step(c, seg(t - 1 - t0), true, seg(t - t0), nullptr);
+    }
+    for (int t = t1 - 1; t >= t0 && st == RT_OK; --t) {
+      StepArgs a = c->args(true);
+      const bool gather = t > t0;
+      a.in = gather ? seg(t - 1 - t0) : ck(k);
+      a.lam_next = lam_next;
+      a.out = Lb[flip];
+      st = c->hip(launch_adjoint_mfma(a, c->prec, gather, c->cb_adj, c->stream, c->grid_limit), "adjoint");
+      lam_next = Lb[flip];
+      flip ^= 1;
+    }
+  }
+  if (st == RT_OK)
+    st = c->hip(launch_gradchain(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb), c->prob.flags,
+                                 c->at<double>(c->L.gacc), d_g_tau, d_g_albedo, d_g_emis, c->stream), "gradchain");
+  if (st == RT_OK && d_lambda0)
+    st = c->hip(hipMemcpyAsync(d_lambda0, lam_next, sb, hipMemcpyDeviceToDevice, c->stream), "lambda0");
+  c->prec = prec_save;
+  return st;
+}
+
+rt_status rt_synchronize(rt_ctx *c) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  return c->hip(hipStreamSynchronize(c->stream), "synchronize");
+}
+
+rt_status rt_destroy(rt_ctx *c) {
+  delete c;
+  return RT_OK;
+}
+
+}  // extern "C"

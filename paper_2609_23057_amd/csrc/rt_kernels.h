@@ -1,0 +1,91 @@
+// Device kernel launchers of the polarized LBM solver (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rt_internal.h"
+
+namespace rtl {
+
+// Per-row and per-direction tables the kernels read (built on the host, then
+// copied into the workspace).  Rows are in GEMM order r = s * n + d.
+struct RowInfo {
+  int16_t plane;   // state plane 4*d + s, or -1 for padding rows
+  int16_t dir;     // d
+};
+
+struct Geometry {
+  int64_t C;       // cells nx * ny
+  int32_t nx, ny;
+  int32_t per_x, per_y;   // periodic axes
+  int32_t n, R, Rpad;
+};
+
+// Everything a fused forward or adjoint launch needs.
+struct StepArgs {
+  Geometry geo;
+  const RowInfo *rows;     // [Rpad]
+  const DirTaps *taps;     // [n]
+  const float *jrow;       // [Rpad] emission profile per row
+  const float *ghost;      // [4][Rpad] ghost radiance per edge and row (0 if not inflow)
+  const float *alpha, *beta, *emis;   // [C]
+  float dt_pre;            // dt * e: emission added before the collision
+  float dt_post;           // dt * (1 - e): emission added after it (fused Taylor)
+  const uint4 *frag;       // A fragments (M for forward, M^T for adjoint)
+  const uint4 *frag_lo;    // low bf16 parts for BF16X3
+  const TileRange *tiles;  // [Rpad / 32]
+  float a_scale_inv;       // 1 / global scale of A (FP16)
+  // forward
+  const float *in;         // gather source (Y_{t-1}) or direct state S_t
+  float *out;              // Y_t (forward) / lambda_t (adjoint)
+  float *s_out;            // optional streamed state S_t (forward)
+  // adjoint
+  const float *lam_next;   // lambda_{t+1}
+  double *gacc;            // [3][C]: g_alpha, g_beta, g_emis accumulators
+};
+
+enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };
+
+// Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +
+// dt_pre J; otherwise X = in + dt_pre J.  out = alpha X + beta M X + dt_post J.
+hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s,
+                            int grid_limit);
+
+// Fused adjoint step: mu = L^T lam_next, X as in the forward, nu = M^T mu,
+// out = alpha mu + beta nu, gacc += per-cell (<mu,X>, <nu,X>, dt<.,j>).
+hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s,
+                               int grid_limit);
+
+// Plain float32 path: separate streaming and vector-ALU collision.
+hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s);
+hipError_t launch_collide_valu(const StepArgs &a, const float *M_abi, const float *in, float *out,
+                               hipStream_t s);
+
+// Per-cell coefficients from tau/albedo; counts invalid cells into *bad.
+hipError_t launch_coef(int64_t C, const float *tau, const float *alb, const float *emis,
+                       float *tau_c, float *alb_c, float *emis_c, float *alpha, float *beta,
+                       uint32_t flags, int *bad, hipStream_t s);
+hipError_t launch_gradchain(int64_t C, const float *tau, const float *alb, uint32_t flags,
+                            const double *gacc, float *g_tau, float *g_alb, float *g_emis,
+                            hipStream_t s);
+
+hipError_t launch_fill_f32(float *p, int64_t count, float v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
+
+hipError_t launch_readout(const Geometry &g, const float *S, int edge, const int32_t *dirs,
+                          int nout, float *out, hipStream_t s);
+hipError_t launch_readout_adjoint(const Geometry &g, int edge, const int32_t *dirs, int nout,
+                                  const float *gout, float *lam, hipStream_t s);
+hipError_t launch_sums(const Geometry &g, const float *S, double *partial, int npart,
+                       double *result, hipStream_t s);
+hipError_t launch_maps(const Geometry &g, const float *S, float *I_mean, float *dop_mean,
+                       hipStream_t s);
+
+int sums_partials(const Geometry &g);
+
+// LDS bytes of a fused launch (0 if the configuration does not fit).
+size_t step_lds_bytes(const Geometry &g, int prec, int cb, bool adjoint);
+
+}  // namespace rtl

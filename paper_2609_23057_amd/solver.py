@@ -1,0 +1,186 @@
+"""Torch-facing wrapper of the C ABI: owns a context and its workspace tensor.
+
+PyTorch supplies device memory and the stream; every computation is a call
+into librtlbm.so.  Tensors must be contiguous float32 on the current CUDA/HIP
+device.  State tensors have shape [n, 4, ny, nx] (the ABI layout S[d][s][y][x]).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+_ZEN = {"equal_area": A.RT_ZEN_EQUAL_AREA, "uniform_theta": A.RT_ZEN_UNIFORM_THETA,
+        "explicit": A.RT_ZEN_EXPLICIT}
+_PLANE = {"xy": A.RT_PLANE_XY, "xz": A.RT_PLANE_XZ, "xy_d2q9": A.RT_PLANE_XY_D2Q9}
+_PHASE = {"rayleigh": A.RT_PHASE_RAYLEIGH, "hg": A.RT_PHASE_HG, "mix": A.RT_PHASE_MIX}
+
+
+def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=None,
+                 az_offset_deg=0.0, plane="xy", courant=1.0, bc=(0, 0, 0, 0), phase=None,
+                 dt=1.0, precision="fp32", abs_taylor=False, scat_exp=False, fused_taylor=False,
+                 renorm_irow=False, scalar=False, plain=False, **_ignored):
+    """An RtProblem from keyword arguments (names follow the ABI struct)."""
+    phase = phase or {"kind": "rayleigh"}
+    p = A.RtProblem()
+    p.nx, p.ny, p.n_zen, p.n_az = int(nx), int(ny), int(n_zen), int(n_az)
+    p.zen_rule = _ZEN[zen_rule]
+    if zen_rule == "explicit":
+        arr = (ctypes.c_double * int(n_zen))(*[float(z) for z in zen_explicit_deg])
+        p._zen_keepalive = arr
+        p.zen_deg = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    p.az_offset_deg = float(az_offset_deg)
+    p.plane = _PLANE[plane]
+    p.courant = float(courant)
+    for e in range(4):
+        p.bc[e] = int(bc[e])
+    p.phase = _PHASE[phase.get("kind", "rayleigh")]
+    p.g = float(phase.get("g", 0.0))
+    p.mix_ray = float(phase.get("mix_ray", 1.0))
+    p.dt = float(dt)
+    flags = 0
+    flags |= A.RT_ABS_TAYLOR if abs_taylor else 0
+    flags |= A.RT_SCAT_EXP if scat_exp else 0
+    flags |= A.RT_FUSED_TAYLOR if fused_taylor else 0
+    flags |= A.RT_RENORM_IROW if renorm_irow else 0
+    flags |= A.RT_SCALAR if scalar else 0
+    flags |= A.RT_PLAIN if plain else 0
+    p.flags = flags
+    p.precision = A.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return p
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+class Solver:
+    """One context: problem, workspace and stream (torch's current stream)."""
+
+    def __init__(self, problem, device=None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the solver needs a HIP device")
+        self.problem = problem
+        A.rt_validate(problem)
+        self.device = torch.device(device or "cuda")
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.n = problem.n_zen * problem.n_az
+        self.nx, self.ny = problem.nx, problem.ny
+        self.shape = (self.n, 4, self.ny, self.nx)
+        nbytes = A.rt_workspace_bytes(problem)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = A.rt_init(problem, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        self.nout = [A.rt_num_outgoing(problem, e) for e in range(4)]
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            A.rt_destroy(ctx)
+            self.ctx = None
+
+    # -- helpers ---------------------------------------------------------------
+    def empty_state(self):
+        return torch.zeros(self.shape, dtype=torch.float32, device=self.device)
+
+    def state_bytes(self):
+        return A.rt_state_bytes(self.problem)
+
+    def describe(self):
+        dirs = np.zeros((self.n, 6))
+        M = np.zeros((4 * self.n, 4 * self.n))
+        A.rt_describe(self.problem, dirs, M)
+        return dirs, M
+
+    # -- ABI calls -----------------------------------------------------------------
+    def set_medium(self, tau, albedo, emis, jprof, inflow=None):
+        jp = np.ascontiguousarray(jprof, dtype=np.float32).reshape(self.n, 4)
+        inf = None if inflow is None else np.ascontiguousarray(inflow, dtype=np.float32).reshape(4, self.n, 4)
+        self._medium = (tau, albedo, emis)
+        A.rt_set_medium(self.ctx, _ptr(tau), _ptr(albedo), _ptr(emis), jp, inf)
+
+    def step(self, S_in, S_out):
+        A.rt_step(self.ctx, _ptr(S_in), _ptr(S_out))
+
+    def run(self, S, nsteps, ckpt=None, ckpt_every=0):
+        A.rt_run(self.ctx, _ptr(S), int(nsteps), _ptr(ckpt), int(ckpt_every))
+
+    def readout(self, S, edge, sums=False):
+        out = torch.empty((self.ny if edge < 2 else self.nx, self.nout[edge], 4),
+                          dtype=torch.float32, device=self.device)
+        h = np.zeros(4) if sums else None
+        A.rt_readout(self.ctx, _ptr(S), int(edge), _ptr(out) if out.numel() else None, h)
+        return (out, h) if sums else out
+
+    def sums(self, S):
+        h = np.zeros(4)
+        A.rt_readout(self.ctx, _ptr(S), 0, None, h)
+        return h
+
+    def maps(self, S):
+        I = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        D = torch.empty_like(I)
+        A.rt_maps(self.ctx, _ptr(S), _ptr(I), _ptr(D))
+        return I, D
+
+    def readout_adjoint(self, edge, gout):
+        lam = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        A.rt_readout_adjoint(self.ctx, int(edge), _ptr(gout.contiguous()), _ptr(lam))
+        return lam
+
+    def checkpoint_buffer(self, nsteps, ckpt_every):
+        nck = (nsteps + ckpt_every - 1) // ckpt_every
+        return torch.empty((nck,) + self.shape, dtype=torch.float32, device=self.device)
+
+    def segment_buffer(self, ckpt_every):
+        k = max(ckpt_every - 1, 1)
+        return torch.empty((k,) + self.shape, dtype=torch.float32, device=self.device)
+
+    def adjoint(self, nsteps, ckpt, ckpt_every, lamT, seg=None, want_lambda0=False):
+        seg = self.segment_buffer(ckpt_every) if seg is None else seg
+        g = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        lam0 = torch.empty(self.shape, dtype=torch.float32, device=self.device) if want_lambda0 else None
+        A.rt_adjoint(self.ctx, int(nsteps), _ptr(ckpt), int(ckpt_every), _ptr(seg), _ptr(lamT),
+                     _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(lam0))
+        return (g[0], g[1], g[2], lam0) if want_lambda0 else (g[0], g[1], g[2])
+
+    def synchronize(self):
+        A.rt_synchronize(self.ctx)
+
+
+def sqrt_checkpoint_interval(nsteps):
+    """K = ceil(sqrt(T)) steps between checkpoints."""
+    return max(1, int(np.ceil(np.sqrt(nsteps))))
+
+
+class RTSolve(torch.autograd.Function):
+    """Edge readout after nsteps as a differentiable function of the medium.
+
+    forward(tau, albedo, emis, solver, S0, nsteps, edge, jprof, inflow) ->
+    readout [edge length, outgoing directions, 4]; backward returns
+    (dL/dtau, dL/dalbedo, dL/demis).  The forward stores sqrt(T) checkpoints;
+    the backward replays each segment and runs the fused adjoint kernels.
+    """
+
+    @staticmethod
+    def forward(ctx, tau, albedo, emis, solver, S0, nsteps, edge, jprof, inflow=None):
+        solver.set_medium(tau.contiguous(), albedo.contiguous(), emis.contiguous(), jprof, inflow)
+        K = sqrt_checkpoint_interval(nsteps)
+        ck = solver.checkpoint_buffer(nsteps, K)
+        S = S0.clone()
+        solver.run(S, nsteps, ck, K)
+        out = solver.readout(S, edge)
+        ctx.solver, ctx.nsteps, ctx.edge, ctx.K = solver, nsteps, edge, K
+        ctx.ck = ck
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        s = ctx.solver
+        lam = s.readout_adjoint(ctx.edge, gout.contiguous().float())
+        g_tau, g_alb, g_em = s.adjoint(ctx.nsteps, ctx.ck, ctx.K, lam)
+        return g_tau, g_alb, g_em, None, None, None, None, None, None

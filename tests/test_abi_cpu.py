@@ -1,0 +1,139 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/rt_lbm.h declares, validates problems with the documented status
+codes, and its float64 host setup (directions, displacements, collision matrix
+built from the dipole field projection) agrees with the oracle's independent
+construction (directions + rotation-phase-rotation sequence of Eq. 13).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import directions as ODir
+from oracle import phase as OP
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt_lbm.h")
+
+P = pytest.importorskip("paper_2609_23057_amd")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(rt_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(P._abi.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(P._abi.EXPORTED)
+
+
+def _spec_problem(name, **kw):
+    s = W.spec(name, **kw)
+    return s, P.make_problem(**s)
+
+
+@pytest.mark.parametrize("name,over", [("plain32", {}), ("beam512", {}),
+                                       ("beam512", dict(n_zen=8, n_az=16)),
+                                       ("plain32", dict(n_az=8, plane="xy", az_offset_deg=22.5))])
+def test_host_plan_matches_oracle(name, over):
+    """Directions, displacements and the 4n x 4n collision matrix agree with
+    the oracle to 1e-13 (Tables 1-2 accept 1e-13 between independent solvers)."""
+    s, p = _spec_problem(name, **over)
+    n = W.ndir(s)
+    dirs = np.zeros((n, 6))
+    M = np.zeros((4 * n, 4 * n))
+    P.rt_describe(p, dirs, M)
+    od = ODir.make_directions(s["n_zen"], s["n_az"], s.get("zen_rule", "equal_area"),
+                              s.get("az_offset_deg", 0.0))
+    assert np.allclose(dirs[:, 0], od.theta, atol=1e-14)
+    assert np.allclose(np.mod(dirs[:, 1], 2 * np.pi), np.mod(od.phi, 2 * np.pi), atol=1e-14)
+    sh = ODir.displacements(od, s["plane"], s.get("courant", 1.0))
+    assert np.allclose(dirs[:, 3:5], sh, atol=1e-14)
+    ph = s["phase"]
+    Mo = OP.collision_matrix(od, ph["kind"], ph.get("g", 0.0), ph.get("mix_ray", 1.0))
+    assert np.abs(M - Mo).max() < 1e-13
+
+
+@pytest.mark.parametrize("flags", [dict(renorm_irow=True), dict(scalar=True)])
+def test_host_plan_options_match_oracle(flags):
+    s, p = _spec_problem("beam512", **flags)
+    n = W.ndir(s)
+    M = np.zeros((4 * n, 4 * n))
+    P.rt_describe(p, None, M)
+    od = ODir.make_directions(s["n_zen"], s["n_az"])
+    Mo = OP.collision_matrix(od, "hg", 0.7, 1.0, flags.get("renorm_irow", False),
+                             flags.get("scalar", False))
+    assert np.abs(M - Mo).max() < 1e-13
+
+
+def test_explicit_zeniths_and_outgoing_counts():
+    p = P.make_problem(16, 16, 4, 2, zen_rule="explicit", zen_explicit_deg=[30, 45, 60, 75],
+                       plane="xz")
+    dirs = np.zeros((8, 6))
+    P.rt_describe(p, dirs, None)
+    assert np.allclose(np.degrees(dirs[::2, 0]), [30, 45, 60, 75])
+    assert P.rt_num_outgoing(p, 3) == 8          # all upward
+    assert P.rt_num_outgoing(p, 2) == 0
+    assert P.rt_num_outgoing(p, 1) == 4 and P.rt_num_outgoing(p, 0) == 4
+
+
+def _expect(status, **kw):
+    base = dict(nx=8, ny=8, n_zen=2, n_az=4, plane="xy")
+    base.update(kw)
+    p = P.make_problem(**base)
+    with pytest.raises(P.RTError) as ei:
+        P.rt_validate(p)
+    assert ei.value.status == status
+    assert P.rt_last_error()
+    assert P.rt_workspace_bytes(p) == 0
+
+
+def test_validation_status_codes():
+    _expect(P.RT_EINVAL, nx=0)
+    _expect(P.RT_EINVAL, n_az=0)
+    _expect(P.RT_EINVAL, bc=(0, 1, 0, 0))          # half-periodic axis
+    _expect(P.RT_EINVAL, bc=(0, 0, 7, 7))
+    _expect(P.RT_EINVAL, courant=float("nan"))
+    _expect(P.RT_ERANGE, courant=1.5)              # |l| > 1 cell per step
+    _expect(P.RT_EINVAL, phase={"kind": "hg", "g": 1.0})
+    _expect(P.RT_EINVAL, phase={"kind": "mix", "g": 0.5, "mix_ray": 1.5})
+    _expect(P.RT_EINVAL, dt=-1.0)
+    _expect(P.RT_EINVAL, fused_taylor=True, abs_taylor=True)
+    _expect(P.RT_EUNSUPPORTED, plain=True, precision="bf16")
+    _expect(P.RT_EINVAL, plane="xy_d2q9", n_az=3)  # cos 120 deg = -1/2 is ambiguous
+    _expect(P.RT_EINVAL, zen_rule="explicit", zen_explicit_deg=[30.0, 190.0])
+    _expect(P.RT_EUNSUPPORTED, n_zen=8, n_az=32)   # fused path limited to n <= 128
+    p = P.make_problem(8, 8, 8, 32, plain=True)
+    P.rt_validate(p)                               # ... but the plain path takes it
+
+
+def test_valid_problem_sizes():
+    s, p = _spec_problem("prec1024")
+    P.rt_validate(p)
+    n = W.ndir(s)
+    state = 4 * n * s["nx"] * s["ny"] * 4
+    assert P.rt_state_bytes(p) == state
+    ws = P.rt_workspace_bytes(p)
+    assert 4 * state <= ws < 4 * state + 64 * 2 ** 20
+    assert P.rt_adjoint_segment_bytes(p, 15) == 14 * state
+    assert P.rt_status_str(P.RT_ERANGE) == "RT_ERANGE"
+
+
+def test_init_without_device_reports_error():
+    """rt_init on a machine without a gfx950 device fails with a status, not a crash."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    p = P.make_problem(8, 8, 2, 4)
+    with pytest.raises(P.RTError) as ei:
+        P.rt_init(p, 1 << 20, 1 << 30, None)
+    assert ei.value.status in (P.RT_EDEVICE, P.RT_EUNSUPPORTED)

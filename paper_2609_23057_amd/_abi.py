@@ -44,6 +44,10 @@ _STATUS = {RT_OK: "RT_OK", RT_EINVAL: "RT_EINVAL", RT_ERANGE: "RT_ERANGE",
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("librtlbm.so is not built; run python -m paper_2609_23057_amd.build")
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7); it
+# must be the one loaded, so that the library and torch share one runtime (and
+# one view of the device, streams and memory).  Import torch before the CDLL.
+import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 _P = POINTER(RtProblem)

@@ -79,7 +79,7 @@ class Solver:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
+        if ctx and A is not None and getattr(A, "rt_destroy", None) is not None:
             A.rt_destroy(ctx)
             self.ctx = None
 

@@ -12,9 +12,9 @@ from oracle import lbm as OL
 # (beta <= 0.2, the regime of the optically thin per-step media); for
 # scattering-dominated media (beta up to 0.8) the contraction's operand
 # rounding (2^-9 for bf16) enters every step at full weight and the bound is
-# 1e-2.
+# 1e-2; bf16x3 keeps about 16 mantissa bits and is held to 5e-5 there.
 TOL = {"fp32": 1e-5, "plain": 1e-5, "bf16x3": 1e-5, "bf16": 2e-3, "fp16": 2e-3}
-TOL_THICK = {"fp32": 1e-5, "plain": 1e-5, "bf16x3": 1e-5, "bf16": 1e-2, "fp16": 1e-2}
+TOL_THICK = {"fp32": 1e-5, "plain": 1e-5, "bf16x3": 5e-5, "bf16": 1e-2, "fp16": 1e-2}
 # gradients: float32 paths 1e-4; the bf16 adjoint 1e-2
 GTOL = {"fp32": 1e-4, "plain": 1e-4, "bf16x3": 1e-4, "bf16": 1e-2, "fp16": 1e-2}
 # a polarised component smaller than this fraction of the intensity norm is

@@ -29,7 +29,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   // byte offsets into the workspace
   size_t tables, tables_bytes;   // uploaded host tables (rows, taps, tiles, fragments, M)
-  size_t rows, taps, outdirs, M_abi;
+  size_t taps, outdirs, M_abi;
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
@@ -85,7 +85,6 @@ Layout make_layout(const HostPlan &hp, const Packed &pk) {
     return o;
   };
   L.tables = off;
-  L.rows = take(hp.Rpad * sizeof(RowInfo));
   L.taps = take(hp.n * sizeof(DirTaps));
   L.outdirs = take(4 * hp.n * sizeof(int32_t));
   L.M_abi = take((size_t)hp.R * hp.R * sizeof(float));
@@ -137,7 +136,6 @@ struct rt_ctx {
   int nout[4] = {0, 0, 0, 0};
   bool medium_set = false;
   int prec = 0;
-  int cb_fwd = 2, cb_adj = 2;
   int grid_limit = 1024;
   std::string err;
 
@@ -157,7 +155,6 @@ struct rt_ctx {
 StepArgs rt_ctx::args(bool adjoint) const {
   StepArgs a{};
   a.geo = geo;
-  a.rows = at<RowInfo>(L.rows);
   a.taps = at<DirTaps>(L.taps);
   a.jrow = at<float>(L.jrow);
   a.ghost = at<float>(L.ghost);
@@ -313,10 +310,8 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
 
   // launch shapes: two cell blocks per tile when the LDS budget allows
   const size_t lds_max = 160 * 1024;
-  c->cb_fwd = step_lds_bytes(c->geo, c->prec, 2, false) <= lds_max ? 2 : 1;
-  c->cb_adj = step_lds_bytes(c->geo, c->prec, 2, true) <= lds_max ? 2 : 1;
-  if (!(p->flags & RT_PLAIN) && (step_lds_bytes(c->geo, c->prec, c->cb_fwd, false) > lds_max ||
-                                 step_lds_bytes(c->geo, c->prec, c->cb_adj, true) > lds_max)) {
+  if (!(p->flags & RT_PLAIN) && (step_lds_bytes(c->geo, c->prec, false) > lds_max ||
+                                 step_lds_bytes(c->geo, c->prec, true) > lds_max)) {
     delete c;
     return set_err(RT_EUNSUPPORTED, "problem does not fit the fused kernel's LDS budget");
   }
@@ -330,15 +325,13 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
   auto put = [&](size_t off, const void *src, size_t bytes) {
     if (bytes) std::memcpy(tb.data() + (off - c->L.tables), src, bytes);
   };
-  std::vector<RowInfo> rows(hp.Rpad, RowInfo{-1, 0});
-  for (int d = 0; d < hp.n; ++d)
-    for (int s = 0; s < 4; ++s) rows[gemm_row(hp.n, d, s)] = RowInfo{(int16_t)(4 * d + s), (int16_t)d};
-  put(c->L.rows, rows.data(), rows.size() * sizeof(RowInfo));
   std::vector<DirTaps> taps(hp.n);
   for (int d = 0; d < hp.n; ++d) {
     const double fx0 = std::floor(hp.lx[d]), fy0 = std::floor(hp.ly[d]);
     const double fx = hp.lx[d] - fx0, fy = hp.ly[d] - fy0;
-    taps[d] = DirTaps{(int32_t)fx0, (int32_t)fy0, (float)(1.0 - fx), (float)fx, (float)(1.0 - fy), (float)fy};
+    const double wx0 = 1.0 - fx, wx1 = fx, wy0 = 1.0 - fy, wy1 = fy;
+    taps[d] = DirTaps{(int32_t)fx0, (int32_t)fy0, (float)wx0, (float)wx1, (float)wy0, (float)wy1,
+                      (float)(wx0 * wy0), (float)(wx1 * wy0), (float)(wx0 * wy1), (float)(wx1 * wy1)};
   }
   put(c->L.taps, taps.data(), taps.size() * sizeof(DirTaps));
   std::vector<int32_t> od(4 * hp.n, 0);
@@ -426,7 +419,7 @@ static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, f
   a.in = in;
   a.out = out;
   a.s_out = s_out;
-  return c->hip(launch_step_mfma(a, c->prec, gather, c->cb_fwd, c->stream, c->grid_limit), "step");
+  return c->hip(launch_step_mfma(a, c->prec, gather, c->stream, c->grid_limit), "step");
 }
 
 static rt_status plain_step(rt_ctx *c, const float *S_in, float *S_out) {
@@ -550,7 +543,7 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
       a.in = gather ? seg(t - 1 - t0) : ck(k);
       a.lam_next = lam_next;
       a.out = Lb[flip];
-      st = c->hip(launch_adjoint_mfma(a, c->prec, gather, c->cb_adj, c->stream, c->grid_limit), "adjoint");
+      st = c->hip(launch_adjoint_mfma(a, c->prec, gather, c->stream, c->grid_limit), "adjoint");
       lam_next = Lb[flip];
       flip ^= 1;
     }

@@ -36,12 +36,13 @@ struct DirTaps {
   int32_t ox0, oy0;   // base offsets floor(l_x), floor(l_y)
   float wx0, wx1;     // weights of offsets ox0 and ox0 + 1
   float wy0, wy1;
+  float w00, w10, w01, w11;   // products wx_b * wy_b' (tap (bx, by) -> w_{bx by})
 };
 
 // Contraction tables in the row order used by the kernels: GEMM row
-// r = s * n + d (Stokes-major, so the IQU and V blocks are contiguous), padded
-// to Rpad.  For every 32-row tile t, columns [klo[t], khi[t]) cover all its
-// non-zero entries (rounded to the fragment K step).
+// r = 4 d + s (the state's own plane order), padded to Rpad.  For every
+// 32-row tile t, columns [klo[t], khi[t]) cover all its non-zero entries
+// (rounded to the fragment K step).
 struct TileRange {
   int32_t klo, khi;   // K range
   int32_t frag_off;   // offset (in 16-byte lane records) of the tile's fragments

@@ -9,13 +9,6 @@
 
 namespace rtl {
 
-// Per-row and per-direction tables the kernels read (built on the host, then
-// copied into the workspace).  Rows are in GEMM order r = s * n + d.
-struct RowInfo {
-  int16_t plane;   // state plane 4*d + s, or -1 for padding rows
-  int16_t dir;     // d
-};
-
 struct Geometry {
   int64_t C;       // cells nx * ny
   int32_t nx, ny;
@@ -26,10 +19,9 @@ struct Geometry {
 // Everything a fused forward or adjoint launch needs.
 struct StepArgs {
   Geometry geo;
-  const RowInfo *rows;     // [Rpad]
   const DirTaps *taps;     // [n]
-  const float *jrow;       // [Rpad] emission profile per row
-  const float *ghost;      // [4][Rpad] ghost radiance per edge and row (0 if not inflow)
+  const float *jrow;       // [Rpad] emission profile j[d][s] at row 4 d + s (zero padded)
+  const float *ghost;      // [4][Rpad] ghost radiance per edge and row 4 d + s (0 if not inflow)
   const float *alpha, *beta, *emis;   // [C]
   float dt_pre;            // dt * e: emission added before the collision
   float dt_post;           // dt * (1 - e): emission added after it (fused Taylor)
@@ -50,12 +42,11 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };
 
 // Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +
 // dt_pre J; otherwise X = in + dt_pre J.  out = alpha X + beta M X + dt_post J.
-hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s,
-                            int grid_limit);
+hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit);
 
 // Fused adjoint step: mu = L^T lam_next, X as in the forward, nu = M^T mu,
 // out = alpha mu + beta nu, gacc += per-cell (<mu,X>, <nu,X>, dt<.,j>).
-hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s,
+hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s,
                                int grid_limit);
 
 // Plain float32 path: separate streaming and vector-ALU collision.
@@ -86,6 +77,6 @@ hipError_t launch_maps(const Geometry &g, const float *S, float *I_mean, float *
 int sums_partials(const Geometry &g);
 
 // LDS bytes of a fused launch (0 if the configuration does not fit).
-size_t step_lds_bytes(const Geometry &g, int prec, int cb, bool adjoint);
+size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint);
 
 }  // namespace rtl

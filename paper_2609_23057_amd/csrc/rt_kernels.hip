@@ -1,25 +1,28 @@
 // Device kernels of the polarized lattice-Boltzmann radiative-transfer solver, gfx950.
 //
 // State layout: planes p = 4 d + s (direction d, Stokes s), each a row-major
-// ny x nx float32 array; plane p starts at p * C, C = nx * ny.
+// ny x nx float32 array; plane p starts at p * C, C = nx * ny.  The four
+// Stokes planes of a direction are adjacent.
 //
-// The hot kernel is `fused_kernel`: one time step for a tile of 32*CB
+// The hot kernel is `fused_kernel`: one time step for a tile of 32
 // consecutive cells and all 4n rows (direction x Stokes) of those cells.
-//  1. Every wave owns one 32-row tile of the contraction and gathers, for its
-//     rows and the tile's cells, the streamed state (bilinear pull of Eq. 34
-//     from the previous post-collision field, with periodic / absorbing /
-//     inflow edges) plus the emission (Eq. 6/8).  The lane mapping of this
-//     load is the accumulator layout of a 32x32 MFMA tile, so the values stay
-//     in registers for the epilogue.
+// Contraction rows are in the state's own order r = 4 d + s.
+//  1. Every wave owns one 32-row tile of the contraction (8 directions x 4
+//     Stokes).  The accumulator layout of a 32x32 MFMA tile gives each lane
+//     one cell and 16 rows: 4 directions (one per group of 4 accumulator
+//     elements) x their 4 Stokes components.  The lane keeps the streaming
+//     taps and weights of its 4 directions in registers for the whole
+//     kernel, and gathers for them the streamed state (bilinear pull of
+//     Eq. 34 from the previous post-collision field, with periodic /
+//     absorbing / inflow edges) plus the emission (Eq. 6/8): one tap address
+//     per direction serves its 4 Stokes planes.
 //  2. The waves write their rows into one LDS tile B[cell][row] in the
 //     contraction precision; after a barrier every wave multiplies its 32
-//     rows of the collision matrix (read as pre-swizzled lane fragments from
-//     L2-resident global memory, only the K range that holds non-zeros) by
-//     the whole B tile on the matrix cores (Eq. 25/30).
+//     rows of the collision matrix (pre-swizzled lane fragments read from
+//     L2-resident global memory) by the whole B tile on the matrix cores
+//     (Eq. 25/30).
 //  3. Epilogue in float32: Y = alpha X + beta (M X) (absorption and survival,
 //     Sec. 2.1.4-2.1.5, Eq. 11), stored as the next post-collision field.
-// Contraction rows are ordered r = s * n + d, so the Rayleigh structure (no
-// coupling between I,Q,U and V) leaves whole tiles of zeros that are skipped.
 //
 // The adjoint kernel is the same skeleton run backwards: the B tile holds the
 // reverse-pulled adjoint field mu = L^T lambda, the matrix-core product uses
@@ -44,66 +47,226 @@ namespace {
 
 constexpr int kEdgeXm = 0, kEdgeXp = 1, kEdgeYm = 2, kEdgeYp = 3;
 
+static_assert(sizeof(DirTaps) == 40, "direction tap entry layout");
+
+// Periodic wrap of a source index that lies at most two cells outside [0, n);
+// identity on a non-periodic axis.  Branch-free.
 __device__ __forceinline__ int wrap_axis(int v, int n, int per) {
-  if (per) {
-    if (v < 0) v += n;
-    if (v < 0) v += n;
-    if (v >= n) v -= n;
-  }
+  const int m = per ? n : 0;
+  v += v < 0 ? m : 0;
+  v += v < 0 ? m : 0;
+  v -= (per && v >= n) ? m : 0;
+  v -= (per && v >= n) ? m : 0;
   return v;
 }
 
-// Forward pull of Eq. 34: sum over taps of w * Y(x - ox, y - oy); a source
-// outside the lattice on a non-periodic axis reads the ghost radiance of the
-// edge it lies beyond (y edges first), which is zero for absorbing edges.
-__device__ __forceinline__ float pull_forward(const float *__restrict__ plane, const Geometry &g,
-                                              const DirTaps &tp, int x, int y,
-                                              const float *__restrict__ ghost, int r) {
-  float v = 0.0f;
-#pragma unroll
-  for (int bx = 0; bx < 2; ++bx) {
-    const float wx = bx ? tp.wx1 : tp.wx0;
-    if (wx == 0.0f) continue;
-    const int xs = wrap_axis(x - tp.ox0 - bx, g.nx, g.per_x);
-#pragma unroll
-    for (int by = 0; by < 2; ++by) {
-      const float wy = by ? tp.wy1 : tp.wy0;
-      if (wy == 0.0f) continue;
-      const int ys = wrap_axis(y - tp.oy0 - by, g.ny, g.per_y);
-      float f;
-      if (ys < 0) f = ghost[kEdgeYm * g.Rpad + r];
-      else if (ys >= g.ny) f = ghost[kEdgeYp * g.Rpad + r];
-      else if (xs < 0) f = ghost[kEdgeXm * g.Rpad + r];
-      else if (xs >= g.nx) f = ghost[kEdgeXp * g.Rpad + r];
-      else f = plane[(int64_t)ys * g.nx + xs];
-      v += (wx * wy) * f;
-    }
+// Streaming data of one direction, held by a lane for the whole kernel.
+struct LaneDir {
+  int64_t off;   // element offset of plane (d, s = 0); Stokes s adds s * C
+  int td;        // oy0 * nx + ox0
+  int ox0, oy0;  // floor of the displacement (Eq. 34)
+  float w00, w10, w01, w11;   // bilinear weights of taps (bx, by)
+  int d;         // direction index (rows of padding directions d >= n give zero)
+};
+
+__device__ __forceinline__ LaneDir lane_dir(const StepArgs &a, int d) {
+  LaneDir L;
+  L.d = d;
+  if (d < a.geo.n) {
+    const DirTaps tp = a.taps[d];
+    L.off = (int64_t)(4 * d) * a.geo.C;
+    L.ox0 = tp.ox0;
+    L.oy0 = tp.oy0;
+    L.td = tp.oy0 * a.geo.nx + tp.ox0;
+    L.w00 = tp.w00;
+    L.w10 = tp.w10;
+    L.w01 = tp.w01;
+    L.w11 = tp.w11;
+  } else {
+    L.off = 0;
+    L.ox0 = L.oy0 = L.td = 0;
+    L.w00 = L.w10 = L.w01 = L.w11 = 0.0f;
   }
-  return v;
+  return L;
 }
 
-// Transpose of the linear part of pull_forward: the target cell (x, y) reads
-// lambda at (x + ox, y + oy) with the same weights; targets that fall outside
-// a non-periodic lattice contribute nothing.
-__device__ __forceinline__ float pull_adjoint(const float *__restrict__ plane, const Geometry &g,
-                                              const DirTaps &tp, int x, int y) {
-  float v = 0.0f;
-#pragma unroll
-  for (int bx = 0; bx < 2; ++bx) {
-    const float wx = bx ? tp.wx1 : tp.wx0;
-    if (wx == 0.0f) continue;
-    const int xs = wrap_axis(x + tp.ox0 + bx, g.nx, g.per_x);
-    if (xs < 0 || xs >= g.nx) continue;
-#pragma unroll
-    for (int by = 0; by < 2; ++by) {
-      const float wy = by ? tp.wy1 : tp.wy0;
-      if (wy == 0.0f) continue;
-      const int ys = wrap_axis(y + tp.oy0 + by, g.ny, g.per_y);
-      if (ys < 0 || ys >= g.ny) continue;
-      v += (wx * wy) * plane[(int64_t)ys * g.nx + xs];
+// Cell of a lane.  Cell indices fit in 32 bits (nx * ny < 2^31 is validated
+// on the host).  Lanes past the end of the lattice take the tile's first cell
+// (valid, and interior when the tile is) and are masked to zero.
+struct LaneCell {
+  int c, x, y;
+  bool valid;
+};
+
+__device__ __forceinline__ LaneCell lane_cell(const Geometry &g, int c0, int x0, int y0, int col) {
+  LaneCell lc;
+  lc.valid = (int64_t)c0 + col < g.C;
+  int x = x0 + (lc.valid ? col : 0), y = y0;
+  while (x >= g.nx) {  // at most ceil(32 / nx) iterations
+    x -= g.nx;
+    ++y;
+  }
+  lc.x = x;
+  lc.y = y;
+  lc.c = y * g.nx + x;
+  return lc;
+}
+
+// Four-tap pull of Eq. 34 for one plane.  The forward (REV = false) reads the
+// previous post-collision field at (x - ox - bx, y - oy - by); the adjoint
+// (REV = true) reads lambda at (x + ox + bx, y + oy + by).  INTERIOR tiles
+// (every tap of every cell inside the lattice, decided once per tile) address
+// the taps from one base; otherwise periodic axes wrap, addresses are clamped
+// into the lattice so every load is valid, and tap_combine replaces taps that
+// lie outside by the edge's ghost radiance (forward) or zero (adjoint).
+// Zero-weight taps still load a valid address.  Tap order in v[]:
+// (bx, by) = (0,0), (1,0), (0,1), (1,1).
+struct TapIdx {
+  int xs0, xs1, ys0, ys1;
+};
+
+template <bool REV>
+__device__ __forceinline__ TapIdx tap_index(const Geometry &g, const LaneDir &ld, int x, int y) {
+  TapIdx t;
+  t.xs0 = wrap_axis(REV ? x + ld.ox0 : x - ld.ox0, g.nx, g.per_x);
+  t.xs1 = wrap_axis(REV ? x + ld.ox0 + 1 : x - ld.ox0 - 1, g.nx, g.per_x);
+  t.ys0 = wrap_axis(REV ? y + ld.oy0 : y - ld.oy0, g.ny, g.per_y);
+  t.ys1 = wrap_axis(REV ? y + ld.oy0 + 1 : y - ld.oy0 - 1, g.ny, g.per_y);
+  return t;
+}
+
+template <bool REV, bool INTERIOR>
+__device__ __forceinline__ void tap_load(const float *__restrict__ plane, const Geometry &g,
+                                         const LaneDir &ld, const TapIdx &t, int c, float (&v)[4]) {
+  if (INTERIOR) {
+    const int step = REV ? 1 : -1;
+    const float *p0 = plane + c + (REV ? ld.td : -ld.td);
+    const float *p1 = p0 + step * g.nx;
+    v[0] = p0[0];
+    v[1] = p0[step];
+    v[2] = p1[0];
+    v[3] = p1[step];
+  } else {
+    const int xc0 = min(max(t.xs0, 0), g.nx - 1), xc1 = min(max(t.xs1, 0), g.nx - 1);
+    const int yc0 = min(max(t.ys0, 0), g.ny - 1), yc1 = min(max(t.ys1, 0), g.ny - 1);
+    const float *p0 = plane + yc0 * g.nx;
+    const float *p1 = plane + yc1 * g.nx;
+    v[0] = p0[xc0];
+    v[1] = p0[xc1];
+    v[2] = p1[xc0];
+    v[3] = p1[xc1];
+  }
+}
+
+// gh: ghost radiance of the row per edge (x-, x+, y-, y+), used for REV = false.
+template <bool REV, bool INTERIOR>
+__device__ __forceinline__ float tap_combine(const Geometry &g, const LaneDir &ld, const TapIdx &t,
+                                             const float (&vin)[4], const float (&gh)[4]) {
+  float v00 = vin[0], v10 = vin[1], v01 = vin[2], v11 = vin[3];
+  if (!INTERIOR) {
+    const bool ix0 = (unsigned)t.xs0 < (unsigned)g.nx, ix1 = (unsigned)t.xs1 < (unsigned)g.nx;
+    const bool iy0 = (unsigned)t.ys0 < (unsigned)g.ny, iy1 = (unsigned)t.ys1 < (unsigned)g.ny;
+    if (REV) {
+      v00 = (ix0 && iy0) ? v00 : 0.0f;
+      v10 = (ix1 && iy0) ? v10 : 0.0f;
+      v01 = (ix0 && iy1) ? v01 : 0.0f;
+      v11 = (ix1 && iy1) ? v11 : 0.0f;
+    } else {
+      // ghost of a source beyond the lattice: the y edge it crossed, else the x edge
+      const float gy0 = t.ys0 < 0 ? gh[kEdgeYm] : gh[kEdgeYp];
+      const float gy1 = t.ys1 < 0 ? gh[kEdgeYm] : gh[kEdgeYp];
+      const float gx0 = t.xs0 < 0 ? gh[kEdgeXm] : gh[kEdgeXp];
+      const float gx1 = t.xs1 < 0 ? gh[kEdgeXm] : gh[kEdgeXp];
+      v00 = (ix0 && iy0) ? v00 : (iy0 ? gx0 : gy0);
+      v10 = (ix1 && iy0) ? v10 : (iy0 ? gx1 : gy0);
+      v01 = (ix0 && iy1) ? v01 : (iy1 ? gx0 : gy1);
+      v11 = (ix1 && iy1) ? v11 : (iy1 ? gx1 : gy1);
     }
   }
-  return v;
+  return (ld.w00 * v00 + ld.w10 * v10) + (ld.w01 * v01 + ld.w11 * v11);
+}
+
+// One group = the 4 Stokes rows of one of the lane's directions: their 16
+// tap loads (or 4 direct loads) are issued together.
+template <bool REV, bool GATHER, bool INTERIOR>
+__device__ __forceinline__ void dir_issue(const float *__restrict__ src, const Geometry &g,
+                                          const LaneDir &ld, const LaneCell &lc, float (&v)[4][4]) {
+  const TapIdx t = tap_index<REV>(g, ld, lc.x, lc.y);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float *plane = src + ld.off + (int64_t)s * g.C;
+    if (GATHER) {
+      tap_load<REV, INTERIOR>(plane, g, ld, t, lc.c, v[s]);
+    } else {
+      v[s][0] = plane[lc.c];
+      v[s][1] = v[s][2] = v[s][3] = 0.0f;
+    }
+    if (!INTERIOR) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Combines a group into dst[0..3] (the 4 Stokes of the direction): the pulled
+// (or direct) value, plus dt_pre * eps * j[d][s] for the state field (EMIT);
+// for CKPT the streamed value before emission is also stored into s_out.
+template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT>
+__device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g, const LaneDir &ld,
+                                            const LaneCell &lc, float emis_dt, const float (&v)[4][4],
+                                            float *dst) {
+  const bool live = lc.valid && ld.d < g.n;
+  const TapIdx t = tap_index<REV>(g, ld, lc.x, lc.y);
+  f32x4 jp = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (EMIT) jp = *reinterpret_cast<const f32x4 *>(a.jrow + 4 * ld.d);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    float sv;
+    if (GATHER) {
+      float gh[4] = {0.f, 0.f, 0.f, 0.f};
+      if (!INTERIOR && !REV)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gh[e] = a.ghost[e * g.Rpad + 4 * ld.d + s];
+      sv = tap_combine<REV, INTERIOR>(g, ld, t, v[s], gh);
+    } else {
+      sv = v[s][0];
+    }
+    if (CKPT && live) a.s_out[ld.off + (int64_t)s * g.C + lc.c] = sv;
+    if (EMIT) sv += emis_dt * jp[s];
+    dst[s] = live ? sv : 0.0f;
+  }
+}
+
+// Gathers the 16 values a lane owns: the streamed (GATHER) or direct state
+// with emission, or with REV the reverse-pulled adjoint field.  Two-stage
+// pipeline over the 4 direction groups: the loads of group k are issued
+// before group k-1 is combined, keeping two groups (32 loads) in flight.
+template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT>
+__device__ __forceinline__ void gather_field(const StepArgs &a, const float *__restrict__ src,
+                                             const Geometry &g, const LaneDir (&ld)[4],
+                                             const LaneCell &lc, float emis_dt, float (&dst)[16]) {
+  if (!INTERIOR) {
+    // edge tiles (a small share): one group at a time, which keeps the wrap,
+    // clamp and ghost bookkeeping of only one direction live
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float v[4][4];
+      dir_issue<REV, GATHER, INTERIOR>(src, g, ld[k], lc, v);
+      dir_combine<REV, GATHER, INTERIOR, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, &dst[4 * k]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return;
+  }
+  float va[4][4], vb[4][4];
+  dir_issue<REV, GATHER, INTERIOR>(src, g, ld[0], lc, va);
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+    if (k < 4) dir_issue<REV, GATHER, INTERIOR>(src, g, ld[k], lc, vb);
+    __builtin_amdgcn_sched_barrier(0);
+    dir_combine<REV, GATHER, INTERIOR, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, &dst[4 * (k - 1)]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) va[j][m] = vb[j][m];
+  }
 }
 
 // Row r of the 32x32 accumulator held by element i of a lane in half-wave h.
@@ -117,29 +280,25 @@ template <> struct PrecTraits<P_F16> { static constexpr int esize = 2, ntile = 1
 template <> struct PrecTraits<P_BF16X3> { static constexpr int esize = 2, ntile = 2; };
 
 struct LdsLayout {
-  int rows_off, taps_off, jrow_off, b_off, red_off, total;
+  int b_off, red_off, total;
   int strideB;   // bytes per cell row of the B tile
   int tileB;     // bytes of one B tile
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int n, int Rpad, int esize, int ntile, int cb, int W,
-                                               bool adjoint, bool f16) {
+// LDS of a fused launch: the B tile(s) [32 cells][Rpad rows] (row stride
+// padded by 16 bytes against bank conflicts of the 16-byte fragment reads) and
+// the cross-wave reduction scratch (fp16 scales, adjoint per-cell sums).
+__host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
+                                               bool f16) {
   LdsLayout L;
   int off = 0;
-  L.rows_off = off;
-  off += Rpad * 4;
-  L.taps_off = off;
-  off += n * (int)sizeof(DirTaps);
-  L.jrow_off = off;
-  off += Rpad * 4;
-  off = (off + 15) & ~15;
   L.b_off = off;
   L.strideB = Rpad * esize + 16;
-  L.tileB = 32 * cb * L.strideB;
+  L.tileB = 32 * L.strideB;
   off += ntile * L.tileB;
   L.red_off = off;
-  int nred = adjoint ? 3 : (f16 ? 1 : 0);
-  off += nred * W * 32 * cb * 4;
+  const int nred = adjoint ? 3 : (f16 ? 1 : 0);
+  off += nred * W * 32 * 4;
   L.total = off;
   return L;
 }
@@ -148,7 +307,7 @@ __device__ __forceinline__ f32x16 mfma_step_f32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-template <int PREC, bool GATHER, int CB, bool ADJ, int MAXW>
+template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT>
 __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
   extern __shared__ __align__(16) char smem[];
@@ -158,23 +317,16 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   const int w = threadIdx.x >> 6;
   const int col = lane & 31;
   const int h = lane >> 5;
-  const LdsLayout L = lds_layout(g.n, g.Rpad, T::esize, T::ntile, CB, W, ADJ, PREC == P_F16);
-  RowInfo *s_rows = reinterpret_cast<RowInfo *>(smem + L.rows_off);
-  DirTaps *s_taps = reinterpret_cast<DirTaps *>(smem + L.taps_off);
-  float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
+  const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
   char *s_b = smem + L.b_off;
   float *s_red = reinterpret_cast<float *>(smem + L.red_off);
 
-  for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) {
-    s_rows[i] = a.rows[i];
-    s_jrow[i] = a.jrow[i];
-  }
-  for (int i = threadIdx.x; i < g.n; i += blockDim.x) s_taps[i] = a.taps[i];
-  __syncthreads();
-
-  const int t = w;  // the 32-row tile this wave owns
+  const int t = __builtin_amdgcn_readfirstlane(w);  // the 32-row tile this wave owns
   const TileRange tr = a.tiles[t];
-  constexpr int NC = 32 * CB;
+  // the lane's 4 directions: element group q holds direction 8 t + 2 q + h
+  LaneDir ldk[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ldk[q] = lane_dir(a, 8 * t + 2 * q + h);
 
   // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
   // so block b serves a contiguous eighth of the lattice and the halo rows it
@@ -187,90 +339,80 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   const int64_t last = ntiles * (kq + 1) / chunks;
 
   for (int64_t tile = first; tile < last; tile += per) {
-    const int64_t c0 = tile * NC;
-    float xv[CB][16];
-    float mv[ADJ ? CB : 1][16];
-    float cscale[CB];
+    const int c0 = (int)(tile * 32);
+    // The plane offsets do not change between tiles; opaque per-tile copies
+    // keep the compiler from hoisting all 16 (direction, Stokes) plane
+    // pointers of every buffer out of the loop, which would not fit in VGPRs.
+    LaneDir ld[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ld[q] = ldk[q];
+      asm volatile("" : "+v"(ld[q].off), "+v"(ld[q].td));
+    }
+    float xv[16];
+    float mv[ADJ ? 16 : 1];
+    float cscale = 1.0f;
     (void)mv;
 
     // ---- 1. gather own rows ------------------------------------------------
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int64_t c = c0 + cb * 32 + col;
-      const bool valid = c < g.C;
-      const int y = valid ? (int)(c / g.nx) : 0;
-      const int x = valid ? (int)(c - (int64_t)y * g.nx) : 0;
-      const float em = valid ? a.emis[c] : 0.0f;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int r = t * 32 + acc_row(i, h);
-        const RowInfo ri = s_rows[r];
-        float xval = 0.0f, mval = 0.0f;
-        if (valid && ri.plane >= 0) {
-          const DirTaps tp = s_taps[ri.dir];
-          const float *pl = a.in + (int64_t)ri.plane * g.C;
-          float sv;
-          if (GATHER) sv = pull_forward(pl, g, tp, x, y, a.ghost, r);
-          else sv = pl[c];
-          if (!ADJ && a.s_out) a.s_out[(int64_t)ri.plane * g.C + c] = sv;
-          xval = sv + a.dt_pre * em * s_jrow[r];
-          if (ADJ) mval = pull_adjoint(a.lam_next + (int64_t)ri.plane * g.C, g, tp, x, y);
-        }
-        xv[cb][i] = xval;
-        if (ADJ) mv[cb][i] = mval;
-      }
+    // First cell of the tile (one 32-bit division per tile) and the lane's cell.
+    const int y0 = c0 / g.nx, x0 = c0 - y0 * g.nx;
+    const LaneCell lc = lane_cell(g, c0, x0, y0, col);
+    const float emis_dt = a.dt_pre * a.emis[lc.c];
+    // A tile is interior when every tap of every cell lies inside the lattice
+    // (taps reach at most two cells either way); then no wrap or ghost is needed.
+    const int c_last = (int)((c0 + 32 < g.C ? (int64_t)c0 + 32 : g.C) - 1);
+    const int ty1 = c_last / g.nx, tx1 = c_last - ty1 * g.nx;
+    const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
+    if (interior) {
+      gather_field<false, GATHER, true, true, CKPT>(a, a.in, g, ld, lc, emis_dt, xv);
+      if constexpr (ADJ) gather_field<true, true, true, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv);
+    } else {
+      gather_field<false, GATHER, false, true, CKPT>(a, a.in, g, ld, lc, emis_dt, xv);
+      if constexpr (ADJ) gather_field<true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv);
     }
 
     // ---- 1b. per-cell power-of-two scale for fp16 operands -------------------
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) cscale[cb] = 1.0f;
     if (PREC == P_F16) {
+      float m = 0.0f;
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        float m = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(ADJ ? mv[cb][i] : xv[cb][i]));
-        m = fmaxf(m, __shfl_xor(m, 32));
-        if (h == 0) s_red[w * NC + cb * 32 + col] = m;
-      }
+      for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(ADJ ? mv[i] : xv[i]));
+      m = fmaxf(m, __shfl_xor(m, 32));
+      if (h == 0) s_red[w * 32 + col] = m;
       __syncthreads();
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        float m = 0.0f;
-        for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * NC + cb * 32 + col]);
-        int e = 0;
-        if (m > 0.0f) (void)frexpf(m, &e);
-        cscale[cb] = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
-      }
+      m = 0.0f;
+      for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * 32 + col]);
+      int e = 0;
+      if (m > 0.0f) (void)frexpf(m, &e);
+      cscale = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
     }
 
     // ---- 2. rows -> LDS B tile -------------------------------------------------
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      char *brow = s_b + (cb * 32 + col) * L.strideB;
+    {
+      char *brow = s_b + col * L.strideB;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r0 = t * 32 + q * 8 + h * 4;
         float v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = ADJ ? mv[cb][4 * q + j] : xv[cb][4 * q + j];
+        for (int j = 0; j < 4; ++j) v[j] = ADJ ? mv[4 * q + j] : xv[4 * q + j];
         if (PREC == P_F32) {
           *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[0], v[1], v[2], v[3]};
         } else if (PREC == P_BF16 || PREC == P_BF16X3) {
-          bf16x4 hi;
+          bf16x4 hv;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) hi[j] = static_cast<__bf16>(v[j]);
-          *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hi;
+          for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[j]);
+          *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hv;
           if (PREC == P_BF16X3) {
             bf16x4 lo;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[j] - static_cast<float>(hi[j]));
+            for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[j] - static_cast<float>(hv[j]));
             *reinterpret_cast<bf16x4 *>(brow + L.tileB + r0 * 2) = lo;
           }
         } else {
           f16x4 hv;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[j] * cscale[cb]);
+          for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[j] * cscale);
           *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
         }
       }
@@ -278,76 +420,77 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     __syncthreads();
 
     // ---- 3. matrix-core contraction over the tile's K range ------------------
-    f32x16 acc[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) acc[cb] = f32x16{0};
+    f32x16 acc = f32x16{0};
     if (PREC == P_F32) {
-      int rec = tr.frag_off;
-      for (int kb = tr.klo; kb < tr.khi; kb += 8, rec += 64) {
-        const f32x4 av = *reinterpret_cast<const f32x4 *>(a.frag + rec + lane);
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + (cb * 32 + col) * L.strideB +
-                                                            (kb + 4 * h) * 4);
-          acc[cb] = mfma_step_f32(av[0], bv[0], acc[cb]);
-          acc[cb] = mfma_step_f32(av[1], bv[1], acc[cb]);
-          acc[cb] = mfma_step_f32(av[2], bv[2], acc[cb]);
-          acc[cb] = mfma_step_f32(av[3], bv[3], acc[cb]);
-        }
+      const int nk = (tr.khi - tr.klo) >> 3;
+      const f32x4 *A = reinterpret_cast<const f32x4 *>(a.frag) + tr.frag_off + lane;
+      f32x4 an = nk > 0 ? A[0] : f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int s = 0; s < nk; ++s) {
+        const f32x4 av = an;
+        if (s + 1 < nk) an = A[(s + 1) * 64];
+        const int kb = tr.klo + 8 * s;
+        const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + col * L.strideB + (kb + 4 * h) * 4);
+        acc = mfma_step_f32(av[0], bv[0], acc);
+        acc = mfma_step_f32(av[1], bv[1], acc);
+        acc = mfma_step_f32(av[2], bv[2], acc);
+        acc = mfma_step_f32(av[3], bv[3], acc);
       }
     } else {
-      int rec = tr.frag_off;
-      for (int kb = tr.klo; kb < tr.khi; kb += 16, rec += 64) {
-        const uint4 araw = a.frag[rec + lane];
-        uint4 araw_lo;
-        if (PREC == P_BF16X3) araw_lo = a.frag_lo[rec + lane];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          const char *bp = s_b + (cb * 32 + col) * L.strideB + (kb + 8 * h) * 2;
-          if (PREC == P_F16) {
-            const f16x8 av = __builtin_bit_cast(f16x8, araw);
-            const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[cb], 0, 0, 0);
-          } else {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
-            if (PREC == P_BF16X3) {
-              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
-              const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
-              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc[cb], 0, 0, 0);
-              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc[cb], 0, 0, 0);
-            }
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[cb], 0, 0, 0);
+      const int nk = (tr.khi - tr.klo) >> 4;
+      const uint4 *A = a.frag + tr.frag_off + lane;
+      const uint4 *Alo = a.frag_lo + tr.frag_off + lane;
+      uint4 an = nk > 0 ? A[0] : uint4{0, 0, 0, 0};
+      uint4 an_lo = (PREC == P_BF16X3 && nk > 0) ? Alo[0] : uint4{0, 0, 0, 0};
+      for (int s = 0; s < nk; ++s) {
+        const uint4 araw = an, araw_lo = an_lo;
+        if (s + 1 < nk) {
+          an = A[(s + 1) * 64];
+          if (PREC == P_BF16X3) an_lo = Alo[(s + 1) * 64];
+        }
+        const int kb = tr.klo + 16 * s;
+        const char *bp = s_b + col * L.strideB + (kb + 8 * h) * 2;
+        if (PREC == P_F16) {
+          const f16x8 av = __builtin_bit_cast(f16x8, araw);
+          const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+        } else {
+          const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
+          if (PREC == P_BF16X3) {
+            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+            const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc, 0, 0, 0);
           }
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
         }
       }
     }
 
     // ---- 4. epilogue -------------------------------------------------------------
-    float part[3][CB];
+    float part[3] = {0.0f, 0.0f, 0.0f};
+    if (lc.valid) {
+      const int c = lc.c;
+      const float al = a.alpha[c], be = a.beta[c];
+      const float em = a.emis[c];
+      const float unscale = a.a_scale_inv / cscale;
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      part[0][cb] = part[1][cb] = part[2][cb] = 0.0f;
-      const int64_t c = c0 + cb * 32 + col;
-      if (c < g.C) {
-        const float al = a.alpha[c], be = a.beta[c];
-        const float em = a.emis[c];
-        const float unscale = a.a_scale_inv / cscale[cb];
+      for (int q = 0; q < 4; ++q) {
+        if (ld[q].d >= g.n) continue;
+        const f32x4 jp = *reinterpret_cast<const f32x4 *>(a.jrow + 4 * ld[q].d);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = t * 32 + acc_row(i, h);
-          const RowInfo ri = s_rows[r];
-          if (ri.plane < 0) continue;
-          const float prod = acc[cb][i] * unscale;
+        for (int s = 0; s < 4; ++s) {
+          const int i = 4 * q + s;
+          const float prod = acc[i] * unscale;
+          float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
           if (!ADJ) {
-            const float yv = al * xv[cb][i] + be * prod + a.dt_post * em * s_jrow[r];
-            a.out[(int64_t)ri.plane * g.C + c] = yv;
+            *o = al * xv[i] + be * prod + a.dt_post * em * jp[s];
           } else {
-            const float lam = al * mv[cb][i] + be * prod;
-            a.out[(int64_t)ri.plane * g.C + c] = lam;
-            part[0][cb] += mv[cb][i] * xv[cb][i];
-            part[1][cb] += prod * xv[cb][i];
-            part[2][cb] += (a.dt_pre * lam + a.dt_post * mv[cb][i]) * s_jrow[r];
+            const float lam = al * mv[i] + be * prod;
+            *o = lam;
+            part[0] += mv[i] * xv[i];
+            part[1] += prod * xv[i];
+            part[2] += (a.dt_pre * lam + a.dt_post * mv[i]) * jp[s];
           }
         }
       }
@@ -355,21 +498,18 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     if (ADJ) {
       // per-cell sums over all rows: half-waves, then waves via LDS
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          float v = part[k][cb];
-          v += __shfl_xor(v, 32);
-          if (h == 0) s_red[(k * W + w) * NC + cb * 32 + col] = v;
-        }
+      for (int k = 0; k < 3; ++k) {
+        float v = part[k];
+        v += __shfl_xor(v, 32);
+        if (h == 0) s_red[(k * W + w) * 32 + col] = v;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < 3 * NC; e += blockDim.x) {
-        const int k = e / NC, cc = e - k * NC;
-        const int64_t c = c0 + cc;
+      for (int e = threadIdx.x; e < 3 * 32; e += blockDim.x) {
+        const int k = e / 32, cc = e - k * 32;
+        const int64_t c = (int64_t)c0 + cc;
         if (c < g.C) {
           double s = 0.0;
-          for (int ww = 0; ww < W; ++ww) s += (double)s_red[(k * W + ww) * NC + cc];
+          for (int ww = 0; ww < W; ++ww) s += (double)s_red[(k * W + ww) * 32 + cc];
           a.gacc[(int64_t)k * g.C + c] += s;
         }
       }
@@ -378,22 +518,22 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   }
 }
 
-template <int PREC, bool GATHER, int CB, bool ADJ>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int grid_limit) {
   using T = PrecTraits<PREC>;
-  const LdsLayout L = lds_layout(a.geo.n, a.geo.Rpad, T::esize, T::ntile, CB, W, ADJ, PREC == P_F16);
-  const int64_t ntiles = (a.geo.C + 32 * CB - 1) / (32 * CB);
+  const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
+  const int64_t ntiles = (a.geo.C + 31) / 32;
   int64_t grid = ntiles;
   if (grid > grid_limit) grid = grid_limit;
   if (grid >= 8) grid &= ~7LL;
   if (grid < 1) grid = 1;
   if (W <= 4) {
-    auto k = fused_kernel<PREC, GATHER, CB, ADJ, 4>;
+    auto k = fused_kernel<PREC, GATHER, ADJ, 4, CKPT>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
   } else {
-    auto k = fused_kernel<PREC, GATHER, CB, ADJ, 16>;
+    auto k = fused_kernel<PREC, GATHER, ADJ, 16, CKPT>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
@@ -401,16 +541,19 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int grid_limi
   return hipGetLastError();
 }
 
+// The checkpointing variant only exists for the forward gather (the step that
+// produces S_t).
 template <bool ADJ>
-hipError_t launch_fused(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s, int grid_limit) {
+hipError_t launch_fused(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit) {
   const int W = a.geo.Rpad / 32;
   if (W < 1 || W > 16) return hipErrorInvalidValue;
+  const bool ckpt = !ADJ && a.s_out != nullptr;
+  if (ckpt && !gather) return hipErrorInvalidValue;
 #define RT_DISPATCH(P)                                                                       \
   if (prec == P) {                                                                           \
-    if (gather) return cb == 2 ? launch_fused_t<P, true, 2, ADJ>(a, W, s, grid_limit)        \
-                               : launch_fused_t<P, true, 1, ADJ>(a, W, s, grid_limit);       \
-    return cb == 2 ? launch_fused_t<P, false, 2, ADJ>(a, W, s, grid_limit)                   \
-                   : launch_fused_t<P, false, 1, ADJ>(a, W, s, grid_limit);                  \
+    if (ckpt) return launch_fused_t<P, true, ADJ, !ADJ>(a, W, s, grid_limit);                \
+    if (gather) return launch_fused_t<P, true, ADJ, false>(a, W, s, grid_limit);             \
+    return launch_fused_t<P, false, ADJ, false>(a, W, s, grid_limit);                        \
   }
   RT_DISPATCH(P_F32)
   RT_DISPATCH(P_BF16)
@@ -422,20 +565,35 @@ hipError_t launch_fused(const StepArgs &a, int prec, bool gather, int cb, hipStr
 
 // ---------------------------------------------------------------- plain path --
 
-// S_out[p](x, y) = pull_forward(S_in[p]) for every plane p = blockIdx.y.
+// S_out[p](x, y) = pull of S_in[p] (Eq. 34) for every plane p = blockIdx.y;
+// cells on the grid-stride loop, branch-free taps, the edge path only for
+// cells within two cells of the lattice border.
 __global__ void __launch_bounds__(256) stream_kernel(StepArgs a, const float *__restrict__ in,
                                                      float *__restrict__ out) {
   const Geometry g = a.geo;
   const int p = blockIdx.y;
   const int d = p >> 2, s = p & 3;
-  const int r = s * g.n + d;
-  const DirTaps tp = a.taps[d];
-  const float *pl = in + (int64_t)p * g.C;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.C;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(c / g.nx);
-    const int x = (int)(c - (int64_t)y * g.nx);
-    out[(int64_t)p * g.C + c] = pull_forward(pl, g, tp, x, y, a.ghost, r);
+  LaneDir ld = lane_dir(a, d);
+  ld.off += (int64_t)s * g.C;
+  float gh[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) gh[e] = a.ghost[e * g.Rpad + p];
+  const float *plane = in + ld.off;
+  const int C = (int)g.C;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+    const int y = c / g.nx;
+    const int x = c - y * g.nx;
+    const TapIdx ti = tap_index<false>(g, ld, x, y);
+    float v[4];
+    float res;
+    if (x >= 2 && x <= g.nx - 3 && y >= 2 && y <= g.ny - 3) {
+      tap_load<false, true>(plane, g, ld, ti, c, v);
+      res = tap_combine<false, true>(g, ld, ti, v, gh);
+    } else {
+      tap_load<false, false>(plane, g, ld, ti, c, v);
+      res = tap_combine<false, false>(g, ld, ti, v, gh);
+    }
+    out[ld.off + c] = res;
   }
 }
 
@@ -456,7 +614,7 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
         float xs[4];
 #pragma unroll
         for (int si = 0; si < 4; ++si)
-          xs[si] = in[(int64_t)(4 * di + si) * g.C + c] + a.dt_pre * em * a.jrow[si * n + di];
+          xs[si] = in[(int64_t)(4 * di + si) * g.C + c] + a.dt_pre * em * a.jrow[4 * di + si];
         const float *mrow = M + (int64_t)(4 * dout) * R + 4 * di;
 #pragma unroll
         for (int so = 0; so < 4; ++so)
@@ -466,7 +624,7 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
 #pragma unroll
       for (int so = 0; so < 4; ++so) {
         const int64_t off = (int64_t)(4 * dout + so) * g.C + c;
-        const float jr = a.jrow[so * n + dout];
+        const float jr = a.jrow[4 * dout + so];
         const float xo = in[off] + a.dt_pre * em * jr;
         out[off] = al * xo + be * acc[so] + a.dt_post * em * jr;
       }
@@ -635,21 +793,19 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 4096) {
 
 }  // namespace
 
-size_t step_lds_bytes(const Geometry &g, int prec, int cb, bool adjoint) {
+size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint) {
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
-  const LdsLayout L = lds_layout(g.n, g.Rpad, esize, ntile, cb, g.Rpad / 32, adjoint, prec == P_F16);
+  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, g.Rpad / 32, adjoint, prec == P_F16);
   return (size_t)L.total;
 }
 
-hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s,
-                            int grid_limit) {
-  return launch_fused<false>(a, prec, gather, cb, s, grid_limit);
+hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit) {
+  return launch_fused<false>(a, prec, gather, s, grid_limit);
 }
 
-hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, int cb, hipStream_t s,
-                               int grid_limit) {
-  return launch_fused<true>(a, prec, gather, cb, s, grid_limit);
+hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit) {
+  return launch_fused<true>(a, prec, gather, s, grid_limit);
 }
 
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s) {

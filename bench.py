@@ -50,6 +50,27 @@ def measured_traffic(kernel_key):
     return rec.get("bytes_per_launch")
 
 
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0}
+
+
+def roofline(nbytes, flops, launch_us, precision):
+    """Roofline of one fused step launch: the bound is whichever of HBM
+    traffic (8 TB/s) and the dense contraction on the matrix cores (peak of
+    the contraction dtype) takes longer at peak."""
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = flops / (MFMA_PEAK_TFLOPS[precision] * 1e12)
+    sec = launch_us * 1e-6
+    hbm = {"achieved": nbytes / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    mfma = {"achieved": flops / sec / 1e12, "peak": MFMA_PEAK_TFLOPS[precision], "unit": "TFLOP/s"}
+    for r in (hbm, mfma):
+        r["frac"] = r["achieved"] / r["peak"]
+    main, other = (hbm, mfma) if t_hbm >= t_mfma else (mfma, hbm)
+    out = dict(main)
+    out["bound"] = "hbm" if main is hbm else "mfma"
+    out["secondary"] = dict(other)
+    return out
+
+
 def loss_grad(out):
     """d/d(readout) of sum(I + DoLP), DoLP = sqrt(Q^2+U^2+(1e-6 I)^2)/I (torch ops on the readout)."""
     import torch
@@ -64,12 +85,15 @@ def loss_grad(out):
 
 
 def make_solver(spec, precision):
+    """precision: fp32 / bf16 / fp16 / bf16x3 (fused matrix-core step) or
+    plain (float32 streaming kernel + vector-ALU collision)."""
     import numpy as np
     import torch
     import paper_2609_23057_amd as P
     import workloads as W
     s = dict(spec)
-    s["precision"] = precision
+    s["precision"] = "fp32" if precision == "plain" else precision
+    s["plain"] = precision == "plain"
     solver = P.Solver(P.make_problem(**s))
     med = W.medium(spec)
     dev = solver.device
@@ -115,7 +139,7 @@ def precision_extras(T=20, warm=3):
     spec = W.spec("prec1024")
     C, n = spec["nx"] * spec["ny"], W.ndir(spec)
     res = {}
-    for prec in ("fp32", "bf16", "bf16x3", "fp16"):
+    for prec in ("plain", "fp32", "bf16", "bf16x3", "fp16"):
         _log("bench: prec1024 %s" % prec)
         solver = make_solver(spec, prec)
         S = solver.empty_state()
@@ -130,9 +154,11 @@ def precision_extras(T=20, warm=3):
         res[prec] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
         del solver, S
         torch.cuda.empty_cache()
-    base = res["fp32"]["cell_dir_updates_per_s"]
     for k in res:
-        res[k]["speedup_vs_fp32"] = res[k]["cell_dir_updates_per_s"] / base
+        res[k]["speedup_vs_fused_fp32"] = (res[k]["cell_dir_updates_per_s"]
+                                           / res["fp32"]["cell_dir_updates_per_s"])
+        res[k]["speedup_vs_plain_fp32"] = (res[k]["cell_dir_updates_per_s"]
+                                           / res["plain"]["cell_dir_updates_per_s"])
     return {"workload": "prec1024: 1024x1024, n=128 (8x16), forward steps", "steps": T, "rates": res}
 
 
@@ -142,7 +168,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tsteps", type=int, default=None, help="time steps per pass (default 2000)")
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16", "fp16", "bf16x3"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
@@ -168,9 +194,17 @@ def main():
     seg = solver.segment_buffer(K)
     edge = 3
 
-    def one_step():
+    fwd_events = []
+
+    def one_step(timed=False):
         S.copy_(S0)
+        if timed:
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            fwd_events.append(ev)
+            ev[0].record()
         solver.run(S, T, ck, K)
+        if timed:
+            ev[1].record()
         out = solver.readout(S, edge)
         lam = solver.readout_adjoint(edge, loss_grad(out))
         return solver.adjoint(T, ck, K, lam, seg)
@@ -183,7 +217,7 @@ def main():
     t0 = time.perf_counter()
     e0.record()
     for i in range(args.steps):
-        one_step()
+        one_step(timed=True)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -191,26 +225,16 @@ def main():
     ms_per_step = ms_total / args.steps
     _log("bench: timed %d steps, %.1f ms/step (wall %.2f s)" % (args.steps, ms_per_step, wall))
 
-    # phase split (outside the timed region): forward run alone, adjoint alone
-    fa, fb, fc = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    S.copy_(S0)
-    torch.cuda.synchronize()
-    fa.record()
-    solver.run(S, T, ck, K)
-    fb.record()
-    lam = solver.readout_adjoint(edge, loss_grad(solver.readout(S, edge)))
-    fc0 = torch.cuda.Event(enable_timing=True)
-    fc0.record()
-    solver.adjoint(T, ck, K, lam, seg)
-    fc.record()
-    torch.cuda.synchronize()
-    ms_fwd = fa.elapsed_time(fb)
-    ms_adj = fc0.elapsed_time(fc)
-    # the forward run is T + 1 launches of one-read-one-write steps (T - 1 fused,
-    # one collide-only, one stream); its mean launch time is the fused kernel's
+    # Forward run inside the timed region (events on the solver's stream, which
+    # is torch's current stream): T + 1 launches of one-read-one-write steps
+    # (T - 1 fused, one collide-only, one stream); their mean is the fused
+    # kernel's launch time.
+    ms_fwd = sum(a.elapsed_time(b) for a, b in fwd_events) / len(fwd_events)
+    ms_adj_est = ms_per_step - ms_fwd
     avg_fused_us = ms_fwd * 1e3 / (T + 1)
     bytes_per_launch = C * (32.0 * n + 12.0)
-    achieved = bytes_per_launch / (avg_fused_us * 1e-6) / 1e9
+    flops_per_launch = 2.0 * (4.0 * n) ** 2 * C
+    roof = roofline(bytes_per_launch, flops_per_launch, avg_fused_us, args.precision)
 
     line = {
         "metric": "Stokes cell-direction updates/s (forward + adjoint hot path)",
@@ -224,13 +248,13 @@ def main():
                                "steps; forward with sqrt(T) checkpoints + readout + adjoint" % T,
                    "nx": 512, "ny": 512, "ndir": n, "time_steps": T, "ckpt_every": K,
                    "contraction_precision": args.precision},
-        "roofline": {"bound": "hbm", "kernel": "fused_kernel (forward step)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("fused_fwd_beam512_%s" % args.precision),
-                     "avg_launch_us": avg_fused_us,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
-        "phases": {"forward_ms": ms_fwd, "adjoint_ms": ms_adj, "adjoint_fwd_ratio": ms_adj / ms_fwd,
+        "roofline": dict(roof, kernel="fused_kernel (forward step)",
+                         traffic=measured_traffic("fused_fwd_beam512_%s" % args.precision),
+                         avg_launch_us=avg_fused_us,
+                         algorithmic_bytes_per_launch=bytes_per_launch,
+                         algorithmic_flops_per_launch=flops_per_launch),
+        "phases": {"forward_ms": ms_fwd, "adjoint_ms": ms_adj_est,
+                   "adjoint_fwd_ratio": ms_adj_est / ms_fwd,
                    "forward_cell_dir_updates_per_s": C * n * T / (ms_fwd / 1e3)},
     }
     if not args.no_extras:

@@ -100,7 +100,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk) {
   L.frag_adj_lo = take(pk.f_adj_lo.size());
   L.tables_bytes = off - L.tables;
   L.jrow = take(hp.Rpad * sizeof(float));
-  L.ghost = take(4 * hp.Rpad * sizeof(float));
+  L.ghost = take(5 * hp.Rpad * sizeof(float));   // 4 edges + a zero row
   L.tau = take(C * sizeof(float));
   L.alb = take(C * sizeof(float));
   L.emis = take(C * sizeof(float));
@@ -374,7 +374,7 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
   const HostPlan &hp = c->hp;
   const int n = hp.n, Rp = hp.Rpad;
   std::vector<float> &hm = c->host_medium;
-  hm.assign(Rp + 4 * Rp, 0.0f);
+  hm.assign(Rp + 5 * Rp, 0.0f);
   for (int d = 0; d < n; ++d)
     for (int s = 0; s < 4; ++s) {
       const float v = h_jprof[4 * d + s];
@@ -392,7 +392,7 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
   rt_status st = c->hip(hipMemcpyAsync(c->ws + c->L.jrow, hm.data(), Rp * sizeof(float),
                                        hipMemcpyHostToDevice, c->stream), "upload jprof");
   if (st == RT_OK)
-    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data() + Rp, 4 * Rp * sizeof(float),
+    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data() + Rp, 5 * Rp * sizeof(float),
                                hipMemcpyHostToDevice, c->stream), "upload inflow");
   int *bad = c->at<int>(c->L.bad);
   if (st == RT_OK) st = c->hip(hipMemsetAsync(bad, 0, sizeof(int), c->stream), "clear counter");

@@ -21,7 +21,8 @@ struct StepArgs {
   Geometry geo;
   const DirTaps *taps;     // [n]
   const float *jrow;       // [Rpad] emission profile j[d][s] at row 4 d + s (zero padded)
-  const float *ghost;      // [4][Rpad] ghost radiance per edge and row 4 d + s (0 if not inflow)
+  const float *ghost;      // [5][Rpad] ghost radiance per edge and row 4 d + s (0 if not inflow),
+                           // then a row of zeros
   const float *alpha, *beta, *emis;   // [C]
   float dt_pre;            // dt * e: emission added before the collision
   float dt_post;           // dt * (1 - e): emission added after it (fused Taylor)

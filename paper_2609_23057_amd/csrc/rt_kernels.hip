@@ -112,15 +112,17 @@ __device__ __forceinline__ LaneCell lane_cell(const Geometry &g, int c0, int x0,
   return lc;
 }
 
-// Four-tap pull of Eq. 34 for one plane.  The forward (REV = false) reads the
-// previous post-collision field at (x - ox - bx, y - oy - by); the adjoint
-// (REV = true) reads lambda at (x + ox + bx, y + oy + by).  INTERIOR tiles
-// (every tap of every cell inside the lattice, decided once per tile) address
-// the taps from one base; otherwise periodic axes wrap, addresses are clamped
-// into the lattice so every load is valid, and tap_combine replaces taps that
-// lie outside by the edge's ghost radiance (forward) or zero (adjoint).
-// Zero-weight taps still load a valid address.  Tap order in v[]:
-// (bx, by) = (0,0), (1,0), (0,1), (1,1).
+// Four-tap pull of Eq. 34.  The forward (REV = false) reads the previous
+// post-collision field at (x - ox - bx, y - oy - by); the adjoint (REV = true)
+// reads lambda at (x + ox + bx, y + oy + by).  Tap order (bx, by) = (0,0),
+// (1,0), (0,1), (1,1).  INTERIOR tiles (every tap of every cell inside the
+// lattice, decided once per tile) address the taps from one base.  Elsewhere
+// periodic axes wrap, and a tap outside the lattice on a non-periodic axis
+// is given its own address in the ghost table instead of the field: the
+// ghost radiance of the edge it crossed (forward; a y edge takes precedence
+// over an x edge) or the table's zero row (adjoint).  The table is [5][Rpad]
+// in row order 4 d + s, so the 4 Stokes values of a direction are adjacent
+// there (stride 1) while in the field they are C apart.
 struct TapIdx {
   int xs0, xs1, ys0, ys1;
 };
@@ -135,99 +137,76 @@ __device__ __forceinline__ TapIdx tap_index(const Geometry &g, const LaneDir &ld
   return t;
 }
 
-template <bool REV, bool INTERIOR>
-__device__ __forceinline__ void tap_load(const float *__restrict__ plane, const Geometry &g,
-                                         const LaneDir &ld, const TapIdx &t, int c, float (&v)[4]) {
-  if (INTERIOR) {
-    const int step = REV ? 1 : -1;
-    const float *p0 = plane + c + (REV ? ld.td : -ld.td);
-    const float *p1 = p0 + step * g.nx;
-    v[0] = p0[0];
-    v[1] = p0[step];
-    v[2] = p1[0];
-    v[3] = p1[step];
-  } else {
-    const int xc0 = min(max(t.xs0, 0), g.nx - 1), xc1 = min(max(t.xs1, 0), g.nx - 1);
-    const int yc0 = min(max(t.ys0, 0), g.ny - 1), yc1 = min(max(t.ys1, 0), g.ny - 1);
-    const float *p0 = plane + yc0 * g.nx;
-    const float *p1 = plane + yc1 * g.nx;
-    v[0] = p0[xc0];
-    v[1] = p0[xc1];
-    v[2] = p1[xc0];
-    v[3] = p1[xc1];
-  }
-}
+constexpr int kZeroRow = 4;   // ghost-table row of zeros
 
-// gh: ghost radiance of the row per edge (x-, x+, y-, y+), used for REV = false.
-template <bool REV, bool INTERIOR>
-__device__ __forceinline__ float tap_combine(const Geometry &g, const LaneDir &ld, const TapIdx &t,
-                                             const float (&vin)[4], const float (&gh)[4]) {
-  float v00 = vin[0], v10 = vin[1], v01 = vin[2], v11 = vin[3];
-  if (!INTERIOR) {
-    const bool ix0 = (unsigned)t.xs0 < (unsigned)g.nx, ix1 = (unsigned)t.xs1 < (unsigned)g.nx;
-    const bool iy0 = (unsigned)t.ys0 < (unsigned)g.ny, iy1 = (unsigned)t.ys1 < (unsigned)g.ny;
-    if (REV) {
-      v00 = (ix0 && iy0) ? v00 : 0.0f;
-      v10 = (ix1 && iy0) ? v10 : 0.0f;
-      v01 = (ix0 && iy1) ? v01 : 0.0f;
-      v11 = (ix1 && iy1) ? v11 : 0.0f;
-    } else {
-      // ghost of a source beyond the lattice: the y edge it crossed, else the x edge
-      const float gy0 = t.ys0 < 0 ? gh[kEdgeYm] : gh[kEdgeYp];
-      const float gy1 = t.ys1 < 0 ? gh[kEdgeYm] : gh[kEdgeYp];
-      const float gx0 = t.xs0 < 0 ? gh[kEdgeXm] : gh[kEdgeXp];
-      const float gx1 = t.xs1 < 0 ? gh[kEdgeXm] : gh[kEdgeXp];
-      v00 = (ix0 && iy0) ? v00 : (iy0 ? gx0 : gy0);
-      v10 = (ix1 && iy0) ? v10 : (iy0 ? gx1 : gy0);
-      v01 = (ix0 && iy1) ? v01 : (iy1 ? gx0 : gy1);
-      v11 = (ix1 && iy1) ? v11 : (iy1 ? gx1 : gy1);
-    }
+template <bool REV>
+__device__ __forceinline__ void edge_taps(const StepArgs &a, const float *__restrict__ src,
+                                          const Geometry &g, const LaneDir &ld, const LaneCell &lc,
+                                          const float *(&p)[4], int (&stride)[4]) {
+  const TapIdx t = tap_index<REV>(g, ld, lc.x, lc.y);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int xs = (k & 1) ? t.xs1 : t.xs0;
+    const int ys = (k & 2) ? t.ys1 : t.ys0;
+    const bool inx = (unsigned)xs < (unsigned)g.nx, iny = (unsigned)ys < (unsigned)g.ny;
+    const bool inside = inx && iny;
+    const int e = REV ? kZeroRow : (!iny ? (ys < 0 ? kEdgeYm : kEdgeYp) : (xs < 0 ? kEdgeXm : kEdgeXp));
+    // branch-free: one base pointer select and one offset select
+    const float *base = inside ? src : a.ghost;
+    const int64_t eoff = inside ? ld.off + (ys * g.nx + xs) : (int64_t)(e * g.Rpad + 4 * ld.d);
+    p[k] = base + eoff;
+    stride[k] = inside ? (int)g.C : 1;
   }
-  return (ld.w00 * v00 + ld.w10 * v10) + (ld.w01 * v01 + ld.w11 * v11);
 }
 
 // One group = the 4 Stokes rows of one of the lane's directions: their 16
 // tap loads (or 4 direct loads) are issued together.
 template <bool REV, bool GATHER, bool INTERIOR>
-__device__ __forceinline__ void dir_issue(const float *__restrict__ src, const Geometry &g,
-                                          const LaneDir &ld, const LaneCell &lc, float (&v)[4][4]) {
-  const TapIdx t = tap_index<REV>(g, ld, lc.x, lc.y);
+__device__ __forceinline__ void dir_issue(const StepArgs &a, const float *__restrict__ src,
+                                          const Geometry &g, const LaneDir &ld, const LaneCell &lc,
+                                          float (&v)[4][4]) {
+  if (!GATHER) {
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const float *plane = src + ld.off + (int64_t)s * g.C;
-    if (GATHER) {
-      tap_load<REV, INTERIOR>(plane, g, ld, t, lc.c, v[s]);
-    } else {
-      v[s][0] = plane[lc.c];
+    for (int s = 0; s < 4; ++s) {
+      v[s][0] = src[ld.off + (int64_t)s * g.C + lc.c];
       v[s][1] = v[s][2] = v[s][3] = 0.0f;
     }
-    if (!INTERIOR) __builtin_amdgcn_sched_barrier(0);
+  } else if (INTERIOR) {
+    const int step = REV ? 1 : -1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float *p0 = src + ld.off + (int64_t)s * g.C + lc.c + (REV ? ld.td : -ld.td);
+      const float *p1 = p0 + step * g.nx;
+      v[s][0] = p0[0];
+      v[s][1] = p0[step];
+      v[s][2] = p1[0];
+      v[s][3] = p1[step];
+    }
+  } else {
+    const float *p[4];
+    int stride[4];
+    edge_taps<REV>(a, src, g, ld, lc, p, stride);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[s][k] = p[k][(int64_t)s * stride[k]];
   }
 }
 
 // Combines a group into dst[0..3] (the 4 Stokes of the direction): the pulled
 // (or direct) value, plus dt_pre * eps * j[d][s] for the state field (EMIT);
 // for CKPT the streamed value before emission is also stored into s_out.
-template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT>
+template <bool GATHER, bool EMIT, bool CKPT>
 __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g, const LaneDir &ld,
                                             const LaneCell &lc, float emis_dt, const float (&v)[4][4],
                                             float *dst) {
   const bool live = lc.valid && ld.d < g.n;
-  const TapIdx t = tap_index<REV>(g, ld, lc.x, lc.y);
   f32x4 jp = f32x4{0.f, 0.f, 0.f, 0.f};
   if (EMIT) jp = *reinterpret_cast<const f32x4 *>(a.jrow + 4 * ld.d);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    float sv;
-    if (GATHER) {
-      float gh[4] = {0.f, 0.f, 0.f, 0.f};
-      if (!INTERIOR && !REV)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) gh[e] = a.ghost[e * g.Rpad + 4 * ld.d + s];
-      sv = tap_combine<REV, INTERIOR>(g, ld, t, v[s], gh);
-    } else {
-      sv = v[s][0];
-    }
+    float sv = v[s][0];
+    if (GATHER) sv = (ld.w00 * v[s][0] + ld.w10 * v[s][1]) + (ld.w01 * v[s][2] + ld.w11 * v[s][3]);
     if (CKPT && live) a.s_out[ld.off + (int64_t)s * g.C + lc.c] = sv;
     if (EMIT) sv += emis_dt * jp[s];
     dst[s] = live ? sv : 0.0f;
@@ -235,32 +214,48 @@ __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g
 }
 
 // Gathers the 16 values a lane owns: the streamed (GATHER) or direct state
-// with emission, or with REV the reverse-pulled adjoint field.  Two-stage
-// pipeline over the 4 direction groups: the loads of group k are issued
-// before group k-1 is combined, keeping two groups (32 loads) in flight.
-template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT>
+// with emission, or with REV the reverse-pulled adjoint field.  Group k (the
+// 4 Stokes rows of direction 8 t + 2 k + h) goes to dst[4k..4k+3], or with
+// TO_LDS straight to the lane's float32 LDS row at lds + 32 k bytes (rows
+// 8 k apart), so that it holds no registers afterwards.  Interior tiles run a
+// two-stage pipeline over the groups (the loads of group k are issued before
+// group k-1 is combined: two groups, 32 loads, in flight).
+template <bool TO_LDS>
+__device__ __forceinline__ void put_group(const float (&o)[4], float *dst, char *lds, int k) {
+  if (TO_LDS)
+    *reinterpret_cast<f32x4 *>(lds + 32 * k) = f32x4{o[0], o[1], o[2], o[3]};
+  else
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dst[4 * k + s] = o[s];
+}
+
+template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, bool TO_LDS>
 __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__restrict__ src,
                                              const Geometry &g, const LaneDir (&ld)[4],
-                                             const LaneCell &lc, float emis_dt, float (&dst)[16]) {
+                                             const LaneCell &lc, float emis_dt, float *dst,
+                                             char *lds) {
   if (!INTERIOR) {
-    // edge tiles (a small share): one group at a time, which keeps the wrap,
-    // clamp and ghost bookkeeping of only one direction live
+    // edge tiles (a small share): one group at a time, which keeps the wrap
+    // and ghost bookkeeping of only one direction live
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      float v[4][4];
-      dir_issue<REV, GATHER, INTERIOR>(src, g, ld[k], lc, v);
-      dir_combine<REV, GATHER, INTERIOR, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, &dst[4 * k]);
+      float v[4][4], o[4];
+      dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, v);
+      dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, o);
+      put_group<TO_LDS>(o, dst, lds, k);
       __builtin_amdgcn_sched_barrier(0);
     }
     return;
   }
   float va[4][4], vb[4][4];
-  dir_issue<REV, GATHER, INTERIOR>(src, g, ld[0], lc, va);
+  dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[0], lc, va);
 #pragma unroll
   for (int k = 1; k <= 4; ++k) {
-    if (k < 4) dir_issue<REV, GATHER, INTERIOR>(src, g, ld[k], lc, vb);
+    if (k < 4) dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, vb);
     __builtin_amdgcn_sched_barrier(0);
-    dir_combine<REV, GATHER, INTERIOR, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, &dst[4 * (k - 1)]);
+    float o[4];
+    dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, o);
+    put_group<TO_LDS>(o, dst, lds, k - 1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -280,14 +275,18 @@ template <> struct PrecTraits<P_F16> { static constexpr int esize = 2, ntile = 1
 template <> struct PrecTraits<P_BF16X3> { static constexpr int esize = 2, ntile = 2; };
 
 struct LdsLayout {
-  int b_off, red_off, total;
+  int b_off, x_off, red_off, total;
   int strideB;   // bytes per cell row of the B tile
   int tileB;     // bytes of one B tile
+  int strideX;   // bytes per cell row of the adjoint's float32 X tile
 };
 
 // LDS of a fused launch: the B tile(s) [32 cells][Rpad rows] (row stride
-// padded by 16 bytes against bank conflicts of the 16-byte fragment reads) and
-// the cross-wave reduction scratch (fp16 scales, adjoint per-cell sums).
+// padded by 16 bytes against bank conflicts of the 16-byte fragment reads),
+// a float32 tile of the forward operand X [32 cells][Rpad rows] that the
+// gather writes and the epilogue reads back (the B tile itself for the
+// forward float32 contraction), and the cross-wave reduction scratch (fp16
+// scales, adjoint per-cell sums).
 __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
                                                bool f16) {
   LdsLayout L;
@@ -296,6 +295,14 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
   L.strideB = Rpad * esize + 16;
   L.tileB = 32 * L.strideB;
   off += ntile * L.tileB;
+  // the forward float32 contraction reads X itself: the X tile is the B tile
+  L.strideX = Rpad * 4 + 16;
+  if (adjoint || esize != 4) {
+    L.x_off = off;
+    off += 32 * L.strideX;
+  } else {
+    L.x_off = L.b_off;
+  }
   L.red_off = off;
   const int nred = adjoint ? 3 : (f16 ? 1 : 0);
   off += nred * W * 32 * 4;
@@ -319,6 +326,8 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   const int h = lane >> 5;
   const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
   char *s_b = smem + L.b_off;
+  char *s_x = smem + L.x_off;
+  (void)s_x;
   float *s_red = reinterpret_cast<float *>(smem + L.red_off);
 
   const int t = __builtin_amdgcn_readfirstlane(w);  // the 32-row tile this wave owns
@@ -340,19 +349,19 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
 
   for (int64_t tile = first; tile < last; tile += per) {
     const int c0 = (int)(tile * 32);
-    // The plane offsets do not change between tiles; opaque per-tile copies
-    // keep the compiler from hoisting all 16 (direction, Stokes) plane
-    // pointers of every buffer out of the loop, which would not fit in VGPRs.
-    LaneDir ld[4];
+    // The direction data does not change between tiles.  Making it opaque in
+    // place at every tile keeps the compiler from hoisting what derives from
+    // it (16 plane pointers per buffer, the emission rows) out of the loop,
+    // which would not fit in VGPRs, without holding a second copy.
+    LaneDir(&ld)[4] = ldk;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ld[q] = ldk[q];
-      asm volatile("" : "+v"(ld[q].off), "+v"(ld[q].td));
-    }
-    float xv[16];
+    for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
     float mv[ADJ ? 16 : 1];
     float cscale = 1.0f;
     (void)mv;
+    // this lane's rows in the LDS tiles: cell col, rows rbase + 8 q + (0..3)
+    const int rbase = t * 32 + h * 4;
+    char *xrow = s_x + col * L.strideX + rbase * 4;
 
     // ---- 1. gather own rows ------------------------------------------------
     // First cell of the tile (one 32-bit division per tile) and the lane's cell.
@@ -364,55 +373,68 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     const int c_last = (int)((c0 + 32 < g.C ? (int64_t)c0 + 32 : g.C) - 1);
     const int ty1 = c_last / g.nx, tx1 = c_last - ty1 * g.nx;
     const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
-    if (interior) {
-      gather_field<false, GATHER, true, true, CKPT>(a, a.in, g, ld, lc, emis_dt, xv);
-      if constexpr (ADJ) gather_field<true, true, true, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv);
-    } else {
-      gather_field<false, GATHER, false, true, CKPT>(a, a.in, g, ld, lc, emis_dt, xv);
-      if constexpr (ADJ) gather_field<true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv);
+    // X (float32) goes to the X tile; the epilogue reads it back from there.
+    if (interior)
+      gather_field<false, GATHER, true, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow);
+    else
+      gather_field<false, GATHER, false, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow);
+    if constexpr (ADJ) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (interior)
+        gather_field<true, true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr);
+      else
+        gather_field<true, true, false, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr);
     }
 
-    // ---- 1b. per-cell power-of-two scale for fp16 operands -------------------
-    if (PREC == P_F16) {
-      float m = 0.0f;
+    // ---- 2. B operand: the contraction input in its precision ------------------
+    // forward: X (already in place for float32); adjoint: mu.
+    if (ADJ || PREC != P_F32) {
+      float v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(ADJ ? mv[i] : xv[i]));
-      m = fmaxf(m, __shfl_xor(m, 32));
-      if (h == 0) s_red[w * 32 + col] = m;
-      __syncthreads();
-      m = 0.0f;
-      for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * 32 + col]);
-      int e = 0;
-      if (m > 0.0f) (void)frexpf(m, &e);
-      cscale = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
-    }
-
-    // ---- 2. rows -> LDS B tile -------------------------------------------------
-    {
+      for (int q = 0; q < 4; ++q) {
+        f32x4 x4;
+        if (ADJ)
+          x4 = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
+        else
+          x4 = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * q + j] = x4[j];
+      }
+      // per-cell power-of-two scale for fp16 operands (max over all rows)
+      if (PREC == P_F16) {
+        float m = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(v[i]));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        if (h == 0) s_red[w * 32 + col] = m;
+        __syncthreads();
+        m = 0.0f;
+        for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * 32 + col]);
+        int e = 0;
+        if (m > 0.0f) (void)frexpf(m, &e);
+        cscale = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
+      }
       char *brow = s_b + col * L.strideB;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r0 = t * 32 + q * 8 + h * 4;
-        float v[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = ADJ ? mv[4 * q + j] : xv[4 * q + j];
+        const int r0 = rbase + q * 8;
         if (PREC == P_F32) {
-          *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[0], v[1], v[2], v[3]};
+          *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
         } else if (PREC == P_BF16 || PREC == P_BF16X3) {
           bf16x4 hv;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[j]);
+          for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[4 * q + j]);
           *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hv;
           if (PREC == P_BF16X3) {
             bf16x4 lo;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[j] - static_cast<float>(hv[j]));
+            for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[4 * q + j] - static_cast<float>(hv[j]));
             *reinterpret_cast<bf16x4 *>(brow + L.tileB + r0 * 2) = lo;
           }
         } else {
           f16x4 hv;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[j] * cscale);
+          for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[4 * q + j] * cscale);
           *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
         }
       }
@@ -478,18 +500,19 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
       for (int q = 0; q < 4; ++q) {
         if (ld[q].d >= g.n) continue;
         const f32x4 jp = *reinterpret_cast<const f32x4 *>(a.jrow + 4 * ld[q].d);
+        const f32x4 xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int i = 4 * q + s;
           const float prod = acc[i] * unscale;
           float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
           if (!ADJ) {
-            *o = al * xv[i] + be * prod + a.dt_post * em * jp[s];
+            *o = al * xq[s] + be * prod + a.dt_post * em * jp[s];
           } else {
             const float lam = al * mv[i] + be * prod;
             *o = lam;
-            part[0] += mv[i] * xv[i];
-            part[1] += prod * xv[i];
+            part[0] += mv[i] * xq[s];
+            part[1] += prod * xq[s];
             part[2] += (a.dt_pre * lam + a.dt_post * mv[i]) * jp[s];
           }
         }
@@ -573,27 +596,29 @@ __global__ void __launch_bounds__(256) stream_kernel(StepArgs a, const float *__
   const Geometry g = a.geo;
   const int p = blockIdx.y;
   const int d = p >> 2, s = p & 3;
-  LaneDir ld = lane_dir(a, d);
-  ld.off += (int64_t)s * g.C;
-  float gh[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) gh[e] = a.ghost[e * g.Rpad + p];
-  const float *plane = in + ld.off;
+  const LaneDir ld = lane_dir(a, d);
+  const int64_t plane = ld.off + (int64_t)s * g.C;
   const int C = (int)g.C;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
     const int y = c / g.nx;
     const int x = c - y * g.nx;
-    const TapIdx ti = tap_index<false>(g, ld, x, y);
     float v[4];
-    float res;
     if (x >= 2 && x <= g.nx - 3 && y >= 2 && y <= g.ny - 3) {
-      tap_load<false, true>(plane, g, ld, ti, c, v);
-      res = tap_combine<false, true>(g, ld, ti, v, gh);
+      const float *p0 = in + plane + c - ld.td;
+      const float *p1 = p0 - g.nx;
+      v[0] = p0[0];
+      v[1] = p0[-1];
+      v[2] = p1[0];
+      v[3] = p1[-1];
     } else {
-      tap_load<false, false>(plane, g, ld, ti, c, v);
-      res = tap_combine<false, false>(g, ld, ti, v, gh);
+      const LaneCell lc{c, x, y, true};
+      const float *tp[4];
+      int stride[4];
+      edge_taps<false>(a, in, g, ld, lc, tp, stride);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = tp[k][(int64_t)s * stride[k]];
     }
-    out[ld.off + c] = res;
+    out[plane + c] = (ld.w00 * v[0] + ld.w10 * v[1]) + (ld.w01 * v[2] + ld.w11 * v[3]);
   }
 }
 

@@ -136,7 +136,7 @@ struct rt_ctx {
   int nout[4] = {0, 0, 0, 0};
   bool medium_set = false;
   int prec = 0;
-  int grid_limit = 1024;
+  int cu_count = 256;
   std::string err;
 
   template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -308,16 +308,14 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
   c->geo = Geometry{(int64_t)hp.nx * hp.ny, hp.nx, hp.ny, p->bc[0] == RT_BC_PERIODIC,
                     p->bc[2] == RT_BC_PERIODIC, hp.n, hp.R, hp.Rpad};
 
-  // launch shapes: two cell blocks per tile when the LDS budget allows
+  // the fused kernels must fit the LDS budget
   const size_t lds_max = 160 * 1024;
   if (!(p->flags & RT_PLAIN) && (step_lds_bytes(c->geo, c->prec, false) > lds_max ||
                                  step_lds_bytes(c->geo, c->prec, true) > lds_max)) {
     delete c;
     return set_err(RT_EUNSUPPORTED, "problem does not fit the fused kernel's LDS budget");
   }
-  const int W = hp.Rpad / 32;
-  const int per_cu = std::max(1, std::min(8, 16 / W));
-  c->grid_limit = prop.multiProcessorCount * per_cu;
+  c->cu_count = prop.multiProcessorCount;
 
   // host tables
   std::vector<uint8_t> &tb = c->host_tables;
@@ -419,7 +417,7 @@ static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, f
   a.in = in;
   a.out = out;
   a.s_out = s_out;
-  return c->hip(launch_step_mfma(a, c->prec, gather, c->stream, c->grid_limit), "step");
+  return c->hip(launch_step_mfma(a, c->prec, gather, c->stream, c->cu_count), "step");
 }
 
 static rt_status plain_step(rt_ctx *c, const float *S_in, float *S_out) {
@@ -543,7 +541,7 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
       a.in = gather ? seg(t - 1 - t0) : ck(k);
       a.lam_next = lam_next;
       a.out = Lb[flip];
-      st = c->hip(launch_adjoint_mfma(a, c->prec, gather, c->stream, c->grid_limit), "adjoint");
+      st = c->hip(launch_adjoint_mfma(a, c->prec, gather, c->stream, c->cu_count), "adjoint");
       lam_next = Lb[flip];
       flip ^= 1;
     }

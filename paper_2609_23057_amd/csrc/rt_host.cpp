@@ -326,6 +326,8 @@ void pack_fragments(const HostPlan &hp, bool transpose, FragKind kind, double sc
     }
     (*tiles)[t] = tr;
   }
+  bytes->insert(bytes->end(), 64 * 16, uint8_t(0));
+  for (TileRange &tr : *tiles) tr.zero_off = rec;
 }
 
 }  // namespace rtl

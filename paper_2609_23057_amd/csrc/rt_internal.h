@@ -42,17 +42,20 @@ struct DirTaps {
 // Contraction tables in the row order used by the kernels: GEMM row
 // r = 4 d + s (the state's own plane order), padded to Rpad.  For every
 // 32-row tile t, columns [klo[t], khi[t]) cover all its non-zero entries
-// (rounded to the fragment K step).
+// (rounded to the fragment K step).  Every fragment table ends with one
+// K step of zeros (64 lane records) at zero_off, which kernels read for
+// steps past a tile's range.
 struct TileRange {
   int32_t klo, khi;   // K range
   int32_t frag_off;   // offset (in 16-byte lane records) of the tile's fragments
-  int32_t pad;
+  int32_t zero_off;   // offset of the table's zero block
 };
 
 enum FragKind { FRAG_F32 = 0, FRAG_BF16 = 1, FRAG_F16 = 2 };
 
 // Packs A = (transpose ? G^T : G) of the GEMM-ordered matrix G into MFMA lane
-// fragments: for each tile, each K step, 64 lanes x 16 bytes.  For FRAG_F32
+// fragments: for each tile, each K step, 64 lanes x 16 bytes, then one zero
+// K step.  For FRAG_F32
 // one record feeds four 32x32x2 steps (K step 8); for bf16/f16 one record is
 // one 32x32x16 step (K step 16).  `scale` multiplies every entry; `lo` selects
 // the low part of a bf16 hi/lo split.

@@ -43,12 +43,13 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };
 
 // Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +
 // dt_pre J; otherwise X = in + dt_pre J.  out = alpha X + beta M X + dt_post J.
-hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit);
+// cu_count: compute units of the device (sets the persistent grid).
+hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int cu_count);
 
 // Fused adjoint step: mu = L^T lam_next, X as in the forward, nu = M^T mu,
 // out = alpha mu + beta nu, gacc += per-cell (<mu,X>, <nu,X>, dt<.,j>).
 hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s,
-                               int grid_limit);
+                               int cu_count);
 
 // Plain float32 path: separate streaming and vector-ALU collision.
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s);
@@ -77,7 +78,7 @@ hipError_t launch_maps(const Geometry &g, const float *S, float *I_mean, float *
 
 int sums_partials(const Geometry &g);
 
-// LDS bytes of a fused launch (0 if the configuration does not fit).
+// LDS bytes of the fused launch the library will use (SIZE_MAX if none fits).
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint);
 
 }  // namespace rtl

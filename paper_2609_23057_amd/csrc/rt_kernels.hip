@@ -30,6 +30,7 @@
 // the per-cell gradient contributions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "rt_kernels.h"
@@ -194,15 +195,17 @@ __device__ __forceinline__ void dir_issue(const StepArgs &a, const float *__rest
 }
 
 // Combines a group into dst[0..3] (the 4 Stokes of the direction): the pulled
-// (or direct) value, plus dt_pre * eps * j[d][s] for the state field (EMIT);
-// for CKPT the streamed value before emission is also stored into s_out.
+// (or direct) value, plus dt_pre * eps * j[d][s] for the state field (EMIT;
+// jrow is the block's LDS copy of the emission rows, so that reading it never
+// waits on the wave's outstanding global loads); for CKPT the streamed value
+// before emission is also stored into s_out.
 template <bool GATHER, bool EMIT, bool CKPT>
 __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g, const LaneDir &ld,
                                             const LaneCell &lc, float emis_dt, const float (&v)[4][4],
-                                            float *dst) {
+                                            float *dst, const float *jrow) {
   const bool live = lc.valid && ld.d < g.n;
   f32x4 jp = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (EMIT) jp = *reinterpret_cast<const f32x4 *>(a.jrow + 4 * ld.d);
+  if (EMIT) jp = *reinterpret_cast<const f32x4 *>(jrow + 4 * ld.d);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     float sv = v[s][0];
@@ -218,8 +221,9 @@ __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g
 // 4 Stokes rows of direction 8 t + 2 k + h) goes to dst[4k..4k+3], or with
 // TO_LDS straight to the lane's float32 LDS row at lds + 32 k bytes (rows
 // 8 k apart), so that it holds no registers afterwards.  Interior tiles run a
-// two-stage pipeline over the groups (the loads of group k are issued before
-// group k-1 is combined: two groups, 32 loads, in flight).
+// two-stage pipeline (group k's loads are issued before group k-1 is
+// combined: two groups, 32 loads, in flight); edge tiles take one group at a
+// time.
 template <bool TO_LDS>
 __device__ __forceinline__ void put_group(const float (&o)[4], float *dst, char *lds, int k) {
   if (TO_LDS)
@@ -233,7 +237,7 @@ template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, bool TO_LD
 __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__restrict__ src,
                                              const Geometry &g, const LaneDir (&ld)[4],
                                              const LaneCell &lc, float emis_dt, float *dst,
-                                             char *lds) {
+                                             char *lds, const float *jrow) {
   if (!INTERIOR) {
     // edge tiles (a small share): one group at a time, which keeps the wrap
     // and ghost bookkeeping of only one direction live
@@ -241,7 +245,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
     for (int k = 0; k < 4; ++k) {
       float v[4][4], o[4];
       dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, v);
-      dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, o);
+      dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, o, jrow);
       put_group<TO_LDS>(o, dst, lds, k);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -254,7 +258,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
     if (k < 4) dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, vb);
     __builtin_amdgcn_sched_barrier(0);
     float o[4];
-    dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, o);
+    dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, o, jrow);
     put_group<TO_LDS>(o, dst, lds, k - 1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -275,7 +279,7 @@ template <> struct PrecTraits<P_F16> { static constexpr int esize = 2, ntile = 1
 template <> struct PrecTraits<P_BF16X3> { static constexpr int esize = 2, ntile = 2; };
 
 struct LdsLayout {
-  int b_off, x_off, red_off, total;
+  int b_off, x_off, red_off, jrow_off, total;
   int strideB;   // bytes per cell row of the B tile
   int tileB;     // bytes of one B tile
   int strideX;   // bytes per cell row of the adjoint's float32 X tile
@@ -306,8 +310,16 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
   L.red_off = off;
   const int nred = adjoint ? 3 : (f16 ? 1 : 0);
   off += nred * W * 32 * 4;
+  L.jrow_off = off;
+  off += Rpad * 4;
   L.total = off;
   return L;
+}
+
+// Lane-record offset (before adding the lane) of the A fragments of K step s
+// of a tile: the table's zero block for steps past the tile's range.
+__device__ __forceinline__ int frag_rec(const TileRange &tr, int s, int nk) {
+  return s < nk ? tr.frag_off + s * 64 : tr.zero_off;
 }
 
 __device__ __forceinline__ f32x16 mfma_step_f32(float a, float b, f32x16 c) {
@@ -328,6 +340,9 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   char *s_b = smem + L.b_off;
   char *s_x = smem + L.x_off;
   (void)s_x;
+  float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
+  for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
+  __syncthreads();
   float *s_red = reinterpret_cast<float *>(smem + L.red_off);
 
   const int t = __builtin_amdgcn_readfirstlane(w);  // the 32-row tile this wave owns
@@ -367,7 +382,10 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     // First cell of the tile (one 32-bit division per tile) and the lane's cell.
     const int y0 = c0 / g.nx, x0 = c0 - y0 * g.nx;
     const LaneCell lc = lane_cell(g, c0, x0, y0, col);
-    const float emis_dt = a.dt_pre * a.emis[lc.c];
+    // per-cell coefficients, loaded now so that their latency is off the
+    // epilogue's path (invalid lanes read the tile's first cell)
+    const float al = a.alpha[lc.c], be = a.beta[lc.c], em = a.emis[lc.c];
+    const float emis_dt = a.dt_pre * em;
     // A tile is interior when every tap of every cell lies inside the lattice
     // (taps reach at most two cells either way); then no wrap or ghost is needed.
     const int c_last = (int)((c0 + 32 < g.C ? (int64_t)c0 + 32 : g.C) - 1);
@@ -375,15 +393,31 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
     // X (float32) goes to the X tile; the epilogue reads it back from there.
     if (interior)
-      gather_field<false, GATHER, true, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow);
+      gather_field<false, GATHER, true, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
     else
-      gather_field<false, GATHER, false, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow);
+      gather_field<false, GATHER, false, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
     if constexpr (ADJ) {
       __builtin_amdgcn_sched_barrier(0);
       if (interior)
-        gather_field<true, true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr);
+        gather_field<true, true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
       else
-        gather_field<true, true, false, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr);
+        gather_field<true, true, false, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
+    }
+
+    // ---- 3a. first A fragments in flight ---------------------------------------
+    // A is the same for every tile; an L2 round trip for one K step is several
+    // times longer than that step's MFMAs, so a ring of kRing steps is kept in
+    // flight, started here to overlap the B conversion and the barrier.
+    constexpr int kRing = MAXW > 4 ? 1 : 4;
+    constexpr int kStep = PREC == P_F32 ? 8 : 16;
+    const int nk = (tr.khi - tr.klo) / kStep;
+    const uint4 *A = a.frag + lane;
+    const uint4 *Alo = a.frag_lo + lane;
+    uint4 ring[kRing], ring_lo[PREC == P_BF16X3 ? kRing : 1];
+#pragma unroll
+    for (int j = 0; j < kRing; ++j) {
+      ring[j] = A[frag_rec(tr, j, nk)];
+      if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, j, nk)];
     }
 
     // ---- 2. B operand: the contraction input in its precision ------------------
@@ -442,49 +476,42 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     __syncthreads();
 
     // ---- 3. matrix-core contraction over the tile's K range ------------------
+    // Steps are taken in groups of kRing; steps past nk multiply the zero block
+    // with the last valid B row (finite), adding nothing.
     f32x16 acc = f32x16{0};
-    if (PREC == P_F32) {
-      const int nk = (tr.khi - tr.klo) >> 3;
-      const f32x4 *A = reinterpret_cast<const f32x4 *>(a.frag) + tr.frag_off + lane;
-      f32x4 an = nk > 0 ? A[0] : f32x4{0.f, 0.f, 0.f, 0.f};
-      for (int s = 0; s < nk; ++s) {
-        const f32x4 av = an;
-        if (s + 1 < nk) an = A[(s + 1) * 64];
-        const int kb = tr.klo + 8 * s;
-        const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + col * L.strideB + (kb + 4 * h) * 4);
-        acc = mfma_step_f32(av[0], bv[0], acc);
-        acc = mfma_step_f32(av[1], bv[1], acc);
-        acc = mfma_step_f32(av[2], bv[2], acc);
-        acc = mfma_step_f32(av[3], bv[3], acc);
-      }
-    } else {
-      const int nk = (tr.khi - tr.klo) >> 4;
-      const uint4 *A = a.frag + tr.frag_off + lane;
-      const uint4 *Alo = a.frag_lo + tr.frag_off + lane;
-      uint4 an = nk > 0 ? A[0] : uint4{0, 0, 0, 0};
-      uint4 an_lo = (PREC == P_BF16X3 && nk > 0) ? Alo[0] : uint4{0, 0, 0, 0};
-      for (int s = 0; s < nk; ++s) {
-        const uint4 araw = an, araw_lo = an_lo;
-        if (s + 1 < nk) {
-          an = A[(s + 1) * 64];
-          if (PREC == P_BF16X3) an_lo = Alo[(s + 1) * 64];
-        }
-        const int kb = tr.klo + 16 * s;
-        const char *bp = s_b + col * L.strideB + (kb + 8 * h) * 2;
-        if (PREC == P_F16) {
-          const f16x8 av = __builtin_bit_cast(f16x8, araw);
-          const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+    const int nsteps = (nk + kRing - 1) / kRing * kRing;
+    for (int s0 = 0; s0 < nsteps; s0 += kRing) {
+#pragma unroll
+      for (int j = 0; j < kRing; ++j) {
+        const int s = s0 + j;
+        const uint4 araw = ring[j], araw_lo = ring_lo[PREC == P_BF16X3 ? j : 0];
+        ring[j] = A[frag_rec(tr, s + kRing, nk)];
+        if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
+        const int kb = tr.klo + kStep * min(s, nk - 1);
+        if (PREC == P_F32) {
+          const f32x4 av = __builtin_bit_cast(f32x4, araw);
+          const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + col * L.strideB + (kb + 4 * h) * 4);
+          acc = mfma_step_f32(av[0], bv[0], acc);
+          acc = mfma_step_f32(av[1], bv[1], acc);
+          acc = mfma_step_f32(av[2], bv[2], acc);
+          acc = mfma_step_f32(av[3], bv[3], acc);
         } else {
-          const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-          const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
-          if (PREC == P_BF16X3) {
-            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
-            const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc, 0, 0, 0);
+          const char *bp = s_b + col * L.strideB + (kb + 8 * h) * 2;
+          if (PREC == P_F16) {
+            const f16x8 av = __builtin_bit_cast(f16x8, araw);
+            const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+          } else {
+            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
+            if (PREC == P_BF16X3) {
+              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+              const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
+              acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc, 0, 0, 0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
           }
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
         }
       }
     }
@@ -493,13 +520,11 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     float part[3] = {0.0f, 0.0f, 0.0f};
     if (lc.valid) {
       const int c = lc.c;
-      const float al = a.alpha[c], be = a.beta[c];
-      const float em = a.emis[c];
       const float unscale = a.a_scale_inv / cscale;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (ld[q].d >= g.n) continue;
-        const f32x4 jp = *reinterpret_cast<const f32x4 *>(a.jrow + 4 * ld[q].d);
+        const f32x4 jp = *reinterpret_cast<const f32x4 *>(s_jrow + 4 * ld[q].d);
         const f32x4 xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -542,11 +567,12 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
 }
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
-hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int grid_limit) {
+hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
   const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
   const int64_t ntiles = (a.geo.C + 31) / 32;
   int64_t grid = ntiles;
+  const int64_t grid_limit = (int64_t)cu_count * std::max(1, std::min(8, 16 / W));
   if (grid > grid_limit) grid = grid_limit;
   if (grid >= 8) grid &= ~7LL;
   if (grid < 1) grid = 1;
@@ -567,16 +593,16 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int grid_limi
 // The checkpointing variant only exists for the forward gather (the step that
 // produces S_t).
 template <bool ADJ>
-hipError_t launch_fused(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit) {
+hipError_t launch_fused(const StepArgs &a, int prec, bool gather, hipStream_t s, int cu_count) {
   const int W = a.geo.Rpad / 32;
   if (W < 1 || W > 16) return hipErrorInvalidValue;
   const bool ckpt = !ADJ && a.s_out != nullptr;
   if (ckpt && !gather) return hipErrorInvalidValue;
 #define RT_DISPATCH(P)                                                                       \
   if (prec == P) {                                                                           \
-    if (ckpt) return launch_fused_t<P, true, ADJ, !ADJ>(a, W, s, grid_limit);                \
-    if (gather) return launch_fused_t<P, true, ADJ, false>(a, W, s, grid_limit);             \
-    return launch_fused_t<P, false, ADJ, false>(a, W, s, grid_limit);                        \
+    if (ckpt) return launch_fused_t<P, true, ADJ, !ADJ>(a, W, s, cu_count);                  \
+    if (gather) return launch_fused_t<P, true, ADJ, false>(a, W, s, cu_count);               \
+    return launch_fused_t<P, false, ADJ, false>(a, W, s, cu_count);                          \
   }
   RT_DISPATCH(P_F32)
   RT_DISPATCH(P_BF16)
@@ -819,18 +845,19 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 4096) {
 }  // namespace
 
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint) {
+  if (g.Rpad / 32 > 16) return (size_t)-1;
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
   const LdsLayout L = lds_layout(g.Rpad, esize, ntile, g.Rpad / 32, adjoint, prec == P_F16);
   return (size_t)L.total;
 }
 
-hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit) {
-  return launch_fused<false>(a, prec, gather, s, grid_limit);
+hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int cu_count) {
+  return launch_fused<false>(a, prec, gather, s, cu_count);
 }
 
-hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int grid_limit) {
-  return launch_fused<true>(a, prec, gather, s, grid_limit);
+hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int cu_count) {
+  return launch_fused<true>(a, prec, gather, s, cu_count);
 }
 
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s) {

@@ -193,6 +193,61 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
                      const float *d_lambdaT, float *d_g_tau, float *d_g_albedo, float *d_g_emis,
                      float *d_lambda0);
 
+/* ---- Spectral batch ------------------------------------------------------
+ * Independent problems -- spectral channels, each with its own lattice,
+ * direction grid, phase function and medium -- advanced together on one
+ * stream.  A time step of all channels is one persistent kernel launch over
+ * a work queue of (channel, tile) items: the fused step of Sec. 2.1 (Eq. 5)
+ * and its adjoint, per channel exactly as rt_run / rt_adjoint compute it.
+ * With graph mode on, a run or adjoint is recorded into a HIP graph once and
+ * replayed.  Requirements: every channel has the same precision and flags
+ * (RT_PLAIN excluded) and 4n rounded up to a multiple of 32 is 32, 64, 128 or
+ * 256 (n <= 64).  Per-channel arrays of device pointers are passed as host
+ * arrays of nchan entries. */
+typedef struct rt_batch rt_batch;
+
+/* Workspace bytes of a batch: the channels' workspaces plus the work-queue
+ * descriptors.  0 if some problem is invalid. */
+size_t rt_batch_workspace_bytes(const rt_problem *probs, int32_t nchan);
+
+/* Creates a batch of nchan channels, probs[i] describing channel i, on the
+ * given stream; d_ws must hold rt_batch_workspace_bytes(probs, nchan) bytes
+ * (256-byte aligned).  Sets up every channel as rt_init does (synchronises). */
+rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size_t ws_bytes, void *stream,
+                        rt_batch **out);
+
+/* Context of channel ch, owned by the batch (do not destroy it): for
+ * rt_set_medium, rt_readout, rt_maps, rt_readout_adjoint of that channel. */
+rt_status rt_batch_channel(rt_batch *b, int32_t ch, rt_ctx **out);
+
+/* rt_run for every channel: h_states[i] is channel i's state (updated in
+ * place); h_ckpt is NULL or gives each channel's checkpoint buffer as in
+ * rt_run. */
+rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, float *const *h_ckpt,
+                       int32_t ckpt_every);
+
+/* rt_adjoint for every channel (checkpoints from rt_batch_run with the same
+ * nsteps and ckpt_every; h_seg[i] holds rt_adjoint_segment_bytes of channel
+ * i).  Outputs as rt_adjoint, without lambda_0. */
+rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, int32_t ckpt_every,
+                           float *const *h_seg, float *const *h_lambdaT, float *const *h_g_tau,
+                           float *const *h_g_albedo, float *const *h_g_emis);
+
+/* Graph mode (0 off, 1 on).  On: rt_batch_run and rt_batch_adjoint record
+ * their launches into a HIP graph the first time they see a set of arguments
+ * and replay it while the arguments stay the same (one graph per entry
+ * point; new arguments record anew).  The device memory named by the
+ * arguments must then stay allocated until the batch is destroyed or the
+ * mode is switched off. */
+rt_status rt_batch_set_graph(rt_batch *b, int32_t enabled);
+
+/* Waits for the batch's stream. */
+rt_status rt_batch_synchronize(rt_batch *b);
+
+/* Releases the batch, its channel contexts and graphs (not the caller's
+ * memory). */
+rt_status rt_batch_destroy(rt_batch *b);
+
 /* Waits for the context's stream. */
 rt_status rt_synchronize(rt_ctx *c);
 
@@ -201,6 +256,9 @@ rt_status rt_destroy(rt_ctx *c);
 
 const char *rt_status_str(rt_status s);
 const char *rt_last_error(const rt_ctx *c);
+
+/* Message of the last failed batch call (NULL batch: the last failure of any call). */
+const char *rt_batch_last_error(const rt_batch *b);
 
 #ifdef __cplusplus
 }

@@ -43,7 +43,7 @@ _STATUS = {RT_OK: "RT_OK", RT_EINVAL: "RT_EINVAL", RT_ERANGE: "RT_ERANGE",
            RT_EUNSUPPORTED: "RT_EUNSUPPORTED"}
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("librtlbm.so is not built; run python -m paper_2609_23057_amd.build")
+    raise ImportError("librtlbm.so is not built; run python paper_2609_23057_amd/build.py")
 # torch ships its own HIP runtime under the same soname (libamdhip64.so.7); it
 # must be the one loaded, so that the library and torch share one runtime (and
 # one view of the device, streams and memory).  Import torch before the CDLL.
@@ -67,6 +67,17 @@ _SIGS = {
     "rt_adjoint_segment_bytes": (c_size_t, [_P, c_int32]),
     "rt_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_void_p]),
+    "rt_batch_workspace_bytes": (c_size_t, [_P, c_int32]),
+    "rt_batch_init": (c_int32, [_P, c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "rt_batch_channel": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
+    "rt_batch_run": (c_int32, [c_void_p, POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32]),
+    "rt_batch_adjoint": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), c_int32, POINTER(c_void_p),
+                                   POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                   POINTER(c_void_p)]),
+    "rt_batch_set_graph": (c_int32, [c_void_p, c_int32]),
+    "rt_batch_synchronize": (c_int32, [c_void_p]),
+    "rt_batch_destroy": (c_int32, [c_void_p]),
+    "rt_batch_last_error": (c_char_p, [c_void_p]),
     "rt_synchronize": (c_int32, [c_void_p]),
     "rt_destroy": (c_int32, [c_void_p]),
     "rt_status_str": (c_char_p, [c_int32]),
@@ -160,6 +171,69 @@ def rt_adjoint(ctx, nsteps, d_ckpt, ckpt_every, d_seg, d_lambdaT, d_g_tau, d_g_a
                d_lambda0=None):
     _check(_lib.rt_adjoint(ctx, nsteps, d_ckpt, ckpt_every, d_seg, d_lambdaT, d_g_tau,
                            d_g_albedo, d_g_emis, d_lambda0), ctx)
+
+
+def _bcheck(status, b=None):
+    if status != RT_OK:
+        msg = _lib.rt_batch_last_error(b)
+        raise RTError(status, msg.decode() if msg else "")
+
+
+def _ptrs(seq):
+    """Host array of device pointers (None -> NULL array)."""
+    if seq is None:
+        return None
+    return (c_void_p * len(seq))(*[int(x) if x else None for x in seq])
+
+
+def _probs(probs):
+    arr = (RtProblem * len(probs))()
+    for i, p in enumerate(probs):
+        arr[i] = p
+    return arr
+
+
+def rt_batch_workspace_bytes(probs):
+    return int(_lib.rt_batch_workspace_bytes(_probs(probs), len(probs)))
+
+
+def rt_batch_init(probs, d_ws, ws_bytes, stream):
+    out = c_void_p()
+    _bcheck(_lib.rt_batch_init(_probs(probs), len(probs), d_ws, ws_bytes, stream, ctypes.byref(out)))
+    return out.value
+
+
+def rt_batch_channel(b, ch):
+    out = c_void_p()
+    _bcheck(_lib.rt_batch_channel(b, ch, ctypes.byref(out)), b)
+    return out.value
+
+
+def rt_batch_run(b, d_states, nsteps, d_ckpts=None, ckpt_every=0):
+    """d_states / d_ckpts: sequences of per-channel device pointers (ints)."""
+    _bcheck(_lib.rt_batch_run(b, _ptrs(d_states), nsteps, _ptrs(d_ckpts), ckpt_every), b)
+
+
+def rt_batch_adjoint(b, nsteps, d_ckpts, ckpt_every, d_segs, d_lambdaT, d_g_tau, d_g_albedo, d_g_emis):
+    _bcheck(_lib.rt_batch_adjoint(b, nsteps, _ptrs(d_ckpts), ckpt_every, _ptrs(d_segs), _ptrs(d_lambdaT),
+                                  _ptrs(d_g_tau), _ptrs(d_g_albedo), _ptrs(d_g_emis)), b)
+
+
+def rt_batch_set_graph(b, enabled):
+    _bcheck(_lib.rt_batch_set_graph(b, int(enabled)), b)
+
+
+def rt_batch_synchronize(b):
+    _bcheck(_lib.rt_batch_synchronize(b), b)
+
+
+def rt_batch_destroy(b):
+    _bcheck(_lib.rt_batch_destroy(b))
+
+
+def rt_batch_last_error(b=None):
+    m = _lib.rt_batch_last_error(b)
+    return m.decode() if m else ""
 
 
 def rt_synchronize(ctx):

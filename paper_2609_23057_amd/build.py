@@ -1,6 +1,6 @@
 """Builds librtlbm.so (the HIP/C++ solver library) in-tree for gfx950.
 
-    python -m paper_2609_23057_amd.build
+    python paper_2609_23057_amd/build.py
 
 Compiles the host setup and ABI layer as host C++ and the kernels as HIP for
 gfx950, then links one shared library next to this file.  Packed-FP32
@@ -20,7 +20,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]
-DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# No automatic multiply-add contraction: the kernels write their fused
+# multiply-adds explicitly, so every instantiation of a step rounds the same.
+DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-ffp-contract=off"]
 
 SOURCES = [("rt_host.cpp", False), ("rt_abi.cpp", False), ("rt_kernels.hip", True)]
 

@@ -555,6 +555,404 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   return st;
 }
 
+// ---------------------------------------------------------------- spectral batch
+
+}  // extern "C"
+
+struct rt_batch {
+  int nchan = 0;
+  std::vector<rt_ctx *> ch;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  // device descriptor tables: forward run, forward recompute in the adjoint, adjoint
+  BatchChan *d_run = nullptr, *d_rec = nullptr, *d_adj = nullptr;
+  std::vector<BatchChan> h_run, h_rec, h_adj;
+  int64_t nitems = 0;
+  int prec = 0;
+  int lds = 0;
+  int grid = 0;
+  bool graph_mode = false;
+  hipStream_t cap = nullptr;   // private stream graphs are recorded on (the caller's may be the null stream)
+  struct Graph {
+    std::vector<uintptr_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  } g_run, g_adj;
+  std::string err;
+
+  rt_status fail(rt_status s, const std::string &m) {
+    err = m;
+    g_last_error = m;
+    return s;
+  }
+  rt_status hip(hipError_t e, const char *where) {
+    if (e == hipSuccess) return RT_OK;
+    return fail(RT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  }
+  static void drop(Graph &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = Graph{};
+  }
+  ~rt_batch() {
+    drop(g_run);
+    drop(g_adj);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (rt_ctx *c : ch) delete c;
+  }
+  rt_status upload(BatchChan *d, const std::vector<BatchChan> &h) {
+    return hip(hipMemcpyAsync(d, h.data(), h.size() * sizeof(BatchChan), hipMemcpyHostToDevice, stream),
+               "batch descriptors");
+  }
+  rt_status step(const BatchChan *d, bool adjoint, bool gather, bool ckpt, const BatchSel &sel) {
+    return hip(launch_batch_step(d, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds, grid, stream),
+               "batch step");
+  }
+  // Records body() into a graph unless the cached one has the same key, then
+  // launches it on the caller's stream.  Recording happens on a private
+  // stream (body() enqueues on `stream`, which points there meanwhile).
+  template <typename F>
+  rt_status graphed(Graph &g, const std::vector<uintptr_t> &key, F body) {
+    if (!(g.exec && g.key == key)) {
+      drop(g);
+      if (!cap) {
+        rt_status sc = hip(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+        if (sc != RT_OK) return sc;
+      }
+      rt_status st = hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+      if (st != RT_OK) return st;
+      hipStream_t user = stream;
+      stream = cap;
+      rt_status sb = body();
+      stream = user;
+      hipGraph_t graph = nullptr;
+      st = hip(hipStreamEndCapture(cap, &graph), "end capture");
+      if (sb != RT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return sb;
+      }
+      if (st != RT_OK) return st;
+      hipGraphExec_t exec = nullptr;
+      st = hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate graph");
+      if (st != RT_OK) {
+        (void)hipGraphDestroy(graph);
+        return st;
+      }
+      g.graph = graph;
+      g.exec = exec;
+      g.key = key;
+    }
+    return hip(hipGraphLaunch(g.exec, stream), "launch graph");
+  }
+};
+
+namespace {
+
+BatchSel sel_of(int in, int in_slot, int out, int out_slot, int sout = kBufNone, int sout_slot = 0,
+                int lam = kBufNone, int lam_slot = 0) {
+  BatchSel b;
+  b.in = in;
+  b.in_slot = in_slot;
+  b.out = out;
+  b.out_slot = out_slot;
+  b.sout = sout;
+  b.sout_slot = sout_slot;
+  b.lam = lam;
+  b.lam_slot = lam_slot;
+  return b;
+}
+
+// Work-queue offsets of the channels inside the workspace.
+struct BatchPlan {
+  std::vector<size_t> off, bytes;
+  size_t table_off = 0, table_bytes = 0, total = 0;
+};
+
+rt_status batch_plan(const rt_problem *probs, int32_t nchan, BatchPlan *bp, std::string *msg) {
+  if (!probs || nchan < 1) {
+    *msg = "need at least one channel";
+    return RT_EINVAL;
+  }
+  bp->table_off = 0;
+  bp->table_bytes = align256(3 * (size_t)nchan * sizeof(BatchChan));
+  size_t off = bp->table_bytes;
+  for (int i = 0; i < nchan; ++i) {
+    const rt_problem &p = probs[i];
+    rt_status st = rt_validate(&p);
+    if (st != RT_OK) {
+      *msg = "channel " + std::to_string(i) + ": " + g_last_error;
+      return st;
+    }
+    if (p.flags & RT_PLAIN) {
+      *msg = "RT_PLAIN channels cannot be batched";
+      return RT_EUNSUPPORTED;
+    }
+    if (p.precision != probs[0].precision || p.flags != probs[0].flags) {
+      *msg = "channel " + std::to_string(i) + ": precision and flags must match channel 0";
+      return RT_EINVAL;
+    }
+    const int n = p.n_zen * p.n_az;
+    const int Rpad = (4 * n + 31) / 32 * 32;
+    if (batch_lds_bytes(Rpad, p.precision, false) == (size_t)-1) {
+      *msg = "channel " + std::to_string(i) + ": batching needs 4n padded to 32, 64, 128 or 256";
+      return RT_EUNSUPPORTED;
+    }
+    const size_t b = align256(rt_workspace_bytes(&p));
+    bp->off.push_back(off);
+    bp->bytes.push_back(b);
+    off += b;
+  }
+  bp->total = off;
+  return RT_OK;
+}
+
+rt_status batch_set_err(rt_batch *b, rt_status s, const std::string &m) {
+  if (b) return b->fail(s, m);
+  g_last_error = m;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rt_batch_last_error(const rt_batch *b) { return b ? b->err.c_str() : g_last_error.c_str(); }
+
+size_t rt_batch_workspace_bytes(const rt_problem *probs, int32_t nchan) {
+  BatchPlan bp;
+  std::string msg;
+  if (batch_plan(probs, nchan, &bp, &msg) != RT_OK) return 0;
+  return bp.total;
+}
+
+rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size_t ws_bytes, void *stream,
+                        rt_batch **out) {
+  if (!out) return set_err(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d_ws) return set_err(RT_EINVAL, "workspace is NULL");
+  BatchPlan bp;
+  std::string msg;
+  rt_status st = batch_plan(probs, nchan, &bp, &msg);
+  if (st != RT_OK) return set_err(st, msg);
+  if (ws_bytes < bp.total) return set_err(RT_ENOMEM, "workspace smaller than rt_batch_workspace_bytes()");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return set_err(RT_EINVAL, "workspace not 256-byte aligned");
+  rt_batch *b = new rt_batch;
+  b->nchan = nchan;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->ws = static_cast<char *>(d_ws);
+  b->prec = probs[0].precision;
+  for (int i = 0; i < nchan; ++i) {
+    rt_ctx *c = nullptr;
+    st = rt_init(&probs[i], b->ws + bp.off[i], bp.bytes[i], stream, &c);
+    if (st != RT_OK) {
+      const std::string m = "channel " + std::to_string(i) + ": " + g_last_error;
+      delete b;
+      return set_err(st, m);
+    }
+    b->ch.push_back(c);
+  }
+  b->d_run = reinterpret_cast<BatchChan *>(b->ws + bp.table_off);
+  b->d_rec = b->d_run + nchan;
+  b->d_adj = b->d_rec + nchan;
+  int64_t item = 0;
+  size_t lds = 0;
+  for (int i = 0; i < nchan; ++i) {
+    rt_ctx *c = b->ch[i];
+    BatchChan f{};
+    f.a = c->args(false);
+    f.buf[kBufYa] = c->at<float>(c->L.Ya);
+    f.buf[kBufYb] = c->at<float>(c->L.Yb);
+    f.buf[kBufLa] = c->at<float>(c->L.La);
+    f.buf[kBufLb] = c->at<float>(c->L.Lb);
+    f.state_elems = (int64_t)state_elems(c);
+    const int W = c->geo.Rpad / 32;
+    f.groups = kBatchWaves / W;
+    f.ntiles = (c->geo.C + 31) / 32;
+    f.item0 = item;
+    item += (f.ntiles + f.groups - 1) / f.groups;
+    BatchChan a = f;
+    a.a = c->args(true);
+    b->h_run.push_back(f);
+    b->h_rec.push_back(f);
+    b->h_adj.push_back(a);
+    lds = std::max(lds, std::max(batch_lds_bytes(c->geo.Rpad, b->prec, false),
+                                 batch_lds_bytes(c->geo.Rpad, b->prec, true)));
+  }
+  b->nitems = item;
+  if (lds > 160 * 1024) {
+    delete b;
+    return set_err(RT_EUNSUPPORTED, "batch does not fit the fused kernel's LDS budget");
+  }
+  b->lds = (int)lds;
+  int per_cu = 0;
+  st = b->hip(prepare_batch(b->prec, b->lds, &per_cu), "prepare batch kernels");
+  if (st == RT_OK) {
+    b->grid = (int)std::min<int64_t>(b->nitems, (int64_t)b->ch[0]->cu_count * per_cu);
+    st = b->upload(b->d_run, b->h_run);
+  }
+  if (st == RT_OK) st = b->upload(b->d_rec, b->h_rec);
+  if (st == RT_OK) st = b->upload(b->d_adj, b->h_adj);
+  if (st == RT_OK) st = b->hip(hipStreamSynchronize(b->stream), "batch init");
+  if (st != RT_OK) {
+    const std::string m = b->err;
+    delete b;
+    return set_err(st, m);
+  }
+  *out = b;
+  return RT_OK;
+}
+
+rt_status rt_batch_channel(rt_batch *b, int32_t ch, rt_ctx **out) {
+  if (!b || !out) return batch_set_err(b, RT_EINVAL, "NULL batch or out");
+  if (ch < 0 || ch >= b->nchan) return b->fail(RT_EINVAL, "channel index out of range");
+  *out = b->ch[ch];
+  return RT_OK;
+}
+
+rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, float *const *h_ckpt,
+                       int32_t ckpt_every) {
+  if (!b) return set_err(RT_EINVAL, "batch is NULL");
+  if (!h_states) return b->fail(RT_EINVAL, "NULL state array");
+  if (nsteps < 0) return b->fail(RT_EINVAL, "nsteps < 0");
+  if (h_ckpt && ckpt_every < 1) return b->fail(RT_EINVAL, "ckpt_every < 1");
+  for (int i = 0; i < b->nchan; ++i) {
+    if (!h_states[i] || (h_ckpt && !h_ckpt[i])) return b->fail(RT_EINVAL, "NULL state or checkpoint pointer");
+    if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
+  }
+  if (nsteps == 0) return RT_OK;
+  auto body = [&]() -> rt_status {
+    rt_status st = RT_OK;
+    if (h_ckpt)
+      for (int i = 0; i < b->nchan && st == RT_OK; ++i)
+        st = b->hip(hipMemcpyAsync(h_ckpt[i], h_states[i], state_elems(b->ch[i]) * sizeof(float),
+                                   hipMemcpyDeviceToDevice, b->stream), "ckpt");
+    if (st == RT_OK) st = b->step(b->d_run, false, false, false, sel_of(kBufS, 0, kBufYa, 0));
+    for (int t = 1; t < nsteps && st == RT_OK; ++t) {
+      const int yin = (t - 1) & 1 ? kBufYb : kBufYa, yout = t & 1 ? kBufYb : kBufYa;
+      const bool ck = h_ckpt && t % ckpt_every == 0;
+      st = b->step(b->d_run, false, true, ck, sel_of(yin, 0, yout, 0, ck ? kBufCkpt : kBufNone, ck ? t / ckpt_every : 0));
+    }
+    const int ylast = (nsteps - 1) & 1 ? kBufYb : kBufYa;
+    for (int i = 0; i < b->nchan && st == RT_OK; ++i)
+      st = b->hip(launch_stream(b->ch[i]->args(false), b->h_run[i].buf[ylast], h_states[i], b->stream), "stream");
+    return st;
+  };
+  for (int i = 0; i < b->nchan; ++i) {
+    b->h_run[i].buf[kBufS] = h_states[i];
+    b->h_run[i].buf[kBufCkpt] = h_ckpt ? h_ckpt[i] : nullptr;
+  }
+  if (!b->graph_mode) {
+    rt_status st = b->upload(b->d_run, b->h_run);
+    return st == RT_OK ? body() : st;
+  }
+  std::vector<uintptr_t> key = {1, (uintptr_t)nsteps, (uintptr_t)ckpt_every, (uintptr_t)(h_ckpt != nullptr)};
+  for (int i = 0; i < b->nchan; ++i) {
+    key.push_back(reinterpret_cast<uintptr_t>(h_states[i]));
+    key.push_back(reinterpret_cast<uintptr_t>(h_ckpt ? h_ckpt[i] : nullptr));
+  }
+  if (!(b->g_run.exec && b->g_run.key == key)) {
+    rt_status st = b->upload(b->d_run, b->h_run);
+    if (st != RT_OK) return st;
+  }
+  return b->graphed(b->g_run, key, body);
+}
+
+rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, int32_t ckpt_every,
+                           float *const *h_seg, float *const *h_lambdaT, float *const *h_g_tau,
+                           float *const *h_g_albedo, float *const *h_g_emis) {
+  if (!b) return set_err(RT_EINVAL, "batch is NULL");
+  if (!h_ckpt || !h_lambdaT || !h_g_tau || !h_g_albedo || !h_g_emis)
+    return b->fail(RT_EINVAL, "NULL pointer array");
+  if (nsteps < 1 || ckpt_every < 1) return b->fail(RT_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if (ckpt_every > 1 && !h_seg) return b->fail(RT_EINVAL, "segment buffers are NULL");
+  for (int i = 0; i < b->nchan; ++i) {
+    if (!h_ckpt[i] || !h_lambdaT[i] || !h_g_tau[i] || !h_g_albedo[i] || !h_g_emis[i] ||
+        (ckpt_every > 1 && !h_seg[i]))
+      return b->fail(RT_EINVAL, "NULL per-channel pointer");
+    if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
+  }
+  auto body = [&]() -> rt_status {
+    rt_status st = RT_OK;
+    for (int i = 0; i < b->nchan && st == RT_OK; ++i) {
+      rt_ctx *c = b->ch[i];
+      st = b->hip(launch_fill_f64(c->at<double>(c->L.gacc), 3 * c->geo.C, 0.0, b->stream), "fill");
+    }
+    int lam = kBufLamT;
+    int flip = 0;
+    const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    for (int k = nseg - 1; k >= 0 && st == RT_OK; --k) {
+      const int t0 = k * ckpt_every;
+      const int t1 = std::min(nsteps, t0 + ckpt_every);
+      if (t1 - t0 >= 2) {
+        st = b->step(b->d_rec, false, false, false, sel_of(kBufCkpt, k, kBufSeg, 0));
+        for (int t = t0 + 1; t <= t1 - 2 && st == RT_OK; ++t)
+          st = b->step(b->d_rec, false, true, false, sel_of(kBufSeg, t - 1 - t0, kBufSeg, t - t0));
+      }
+      for (int t = t1 - 1; t >= t0 && st == RT_OK; --t) {
+        const bool gather = t > t0;
+        const int out = flip ? kBufLb : kBufLa;
+        st = b->step(b->d_adj, true, gather, false,
+                     sel_of(gather ? kBufSeg : kBufCkpt, gather ? t - 1 - t0 : k, out, 0, kBufNone, 0, lam, 0));
+        lam = out;
+        flip ^= 1;
+      }
+    }
+    for (int i = 0; i < b->nchan && st == RT_OK; ++i) {
+      rt_ctx *c = b->ch[i];
+      st = b->hip(launch_gradchain(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb), c->prob.flags,
+                                   c->at<double>(c->L.gacc), h_g_tau[i], h_g_albedo[i], h_g_emis[i], b->stream),
+                  "gradchain");
+    }
+    return st;
+  };
+  for (int i = 0; i < b->nchan; ++i)
+    for (std::vector<BatchChan> *tb : {&b->h_rec, &b->h_adj}) {
+      (*tb)[i].buf[kBufCkpt] = h_ckpt[i];
+      (*tb)[i].buf[kBufSeg] = h_seg ? h_seg[i] : nullptr;
+      (*tb)[i].buf[kBufLamT] = h_lambdaT[i];
+    }
+  auto upload_both = [&]() -> rt_status {
+    rt_status st = b->upload(b->d_rec, b->h_rec);
+    return st == RT_OK ? b->upload(b->d_adj, b->h_adj) : st;
+  };
+  if (!b->graph_mode) {
+    rt_status st = upload_both();
+    return st == RT_OK ? body() : st;
+  }
+  std::vector<uintptr_t> key = {2, (uintptr_t)nsteps, (uintptr_t)ckpt_every};
+  for (int i = 0; i < b->nchan; ++i)
+    for (const void *ptr : {(const void *)h_ckpt[i], (const void *)(h_seg ? h_seg[i] : nullptr),
+                            (const void *)h_lambdaT[i], (const void *)h_g_tau[i], (const void *)h_g_albedo[i],
+                            (const void *)h_g_emis[i]})
+      key.push_back(reinterpret_cast<uintptr_t>(ptr));
+  if (!(b->g_adj.exec && b->g_adj.key == key)) {
+    rt_status st = upload_both();
+    if (st != RT_OK) return st;
+  }
+  return b->graphed(b->g_adj, key, body);
+}
+
+rt_status rt_batch_set_graph(rt_batch *b, int32_t enabled) {
+  if (!b) return set_err(RT_EINVAL, "batch is NULL");
+  if (enabled != 0 && enabled != 1) return b->fail(RT_EINVAL, "enabled must be 0 or 1");
+  b->graph_mode = enabled == 1;
+  if (!b->graph_mode) {
+    rt_batch::drop(b->g_run);
+    rt_batch::drop(b->g_adj);
+  }
+  return RT_OK;
+}
+
+rt_status rt_batch_synchronize(rt_batch *b) {
+  if (!b) return set_err(RT_EINVAL, "batch is NULL");
+  return b->hip(hipStreamSynchronize(b->stream), "synchronize");
+}
+
+rt_status rt_batch_destroy(rt_batch *b) {
+  delete b;
+  return RT_OK;
+}
+
 rt_status rt_synchronize(rt_ctx *c) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   return c->hip(hipStreamSynchronize(c->stream), "synchronize");

@@ -41,6 +41,54 @@ struct StepArgs {
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };
 
+// ---- spectral batch ----------------------------------------------------------
+// Buffers of a channel by id; a batched launch names, for every role (input,
+// output, checkpoint store, adjoint lambda), one id and a slot, the same for
+// all channels.  Slotted buffers hold consecutive states of the channel.
+enum BatchBuf {
+  kBufNone = -1,
+  kBufS = 0,     // caller's state
+  kBufYa = 1,    // post-collision ping-pong buffers (workspace)
+  kBufYb = 2,
+  kBufCkpt = 3,  // caller's checkpoints (slotted)
+  kBufSeg = 4,   // caller's segment buffer (slotted)
+  kBufLamT = 5,  // caller's lambda_T
+  kBufLa = 6,    // adjoint ping-pong buffers (workspace)
+  kBufLb = 7,
+  kBufCount = 8
+};
+
+struct BatchChan {
+  StepArgs a;            // operators and per-cell tables of the channel (role pointers unused)
+  float *buf[kBufCount]; // buffers by id
+  int64_t state_elems;   // floats of one state (stride of slotted buffers)
+  int64_t item0;         // first work item of the channel
+  int64_t ntiles;        // 32-cell tiles
+  int32_t groups;        // tile groups per work item (8 waves / waves per tile)
+  int32_t pad;
+};
+
+struct BatchSel {
+  int in, out, sout, lam;
+  int in_slot, out_slot, sout_slot, lam_slot;
+};
+
+// Waves per block of the batched kernel; a channel needs Rpad / 32 waves per
+// tile and runs 8 / (Rpad / 32) tiles side by side in one block.
+constexpr int kBatchWaves = 8;
+
+// LDS bytes the batched kernel needs for a channel of this padded size.
+size_t batch_lds_bytes(int Rpad, int prec, bool adjoint);
+
+// Sets the kernel attributes and returns the blocks per CU of the batched
+// kernels for the given LDS size (called once, before any stream capture).
+hipError_t prepare_batch(int prec, int lds_bytes, int *blocks_per_cu);
+
+// One batched fused step (forward or adjoint) over every channel's tiles.
+hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
+                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int grid,
+                             hipStream_t s);
+
 // Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +
 // dt_pre J; otherwise X = in + dt_pre J.  out = alpha X + beta M X + dt_post J.
 // cu_count: compute units of the device (sets the persistent grid).

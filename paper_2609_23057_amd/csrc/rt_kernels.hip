@@ -160,6 +160,13 @@ __device__ __forceinline__ void edge_taps(const StepArgs &a, const float *__rest
   }
 }
 
+// Bilinear combination of the 4 taps of one plane.  Device code is built
+// without automatic multiply-add contraction; the fused multiply-adds are
+// written out so that every kernel instantiation rounds identically.
+__device__ __forceinline__ float tap_sum(const LaneDir &ld, const float (&v)[4]) {
+  return fmaf(ld.w10, v[1], ld.w00 * v[0]) + fmaf(ld.w11, v[3], ld.w01 * v[2]);
+}
+
 // One group = the 4 Stokes rows of one of the lane's directions: their 16
 // tap loads (or 4 direct loads) are issued together.
 template <bool REV, bool GATHER, bool INTERIOR>
@@ -209,9 +216,9 @@ __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     float sv = v[s][0];
-    if (GATHER) sv = (ld.w00 * v[s][0] + ld.w10 * v[s][1]) + (ld.w01 * v[s][2] + ld.w11 * v[s][3]);
+    if (GATHER) sv = tap_sum(ld, v[s]);
     if (CKPT && live) a.s_out[ld.off + (int64_t)s * g.C + lc.c] = sv;
-    if (EMIT) sv += emis_dt * jp[s];
+    if (EMIT) sv = fmaf(emis_dt, jp[s], sv);
     dst[s] = live ? sv : 0.0f;
   }
 }
@@ -279,20 +286,23 @@ template <> struct PrecTraits<P_F16> { static constexpr int esize = 2, ntile = 1
 template <> struct PrecTraits<P_BF16X3> { static constexpr int esize = 2, ntile = 2; };
 
 struct LdsLayout {
-  int b_off, x_off, red_off, jrow_off, total;
+  int b_off, x_off, red_off;   // within a tile group
+  int group;                   // bytes of one tile group; group g starts at g * group
+  int jrow_off, total;         // block-wide
   int strideB;   // bytes per cell row of the B tile
   int tileB;     // bytes of one B tile
-  int strideX;   // bytes per cell row of the adjoint's float32 X tile
+  int strideX;   // bytes per cell row of the float32 X tile
 };
 
-// LDS of a fused launch: the B tile(s) [32 cells][Rpad rows] (row stride
-// padded by 16 bytes against bank conflicts of the 16-byte fragment reads),
-// a float32 tile of the forward operand X [32 cells][Rpad rows] that the
-// gather writes and the epilogue reads back (the B tile itself for the
-// forward float32 contraction), and the cross-wave reduction scratch (fp16
-// scales, adjoint per-cell sums).
+// LDS of a fused launch, per tile group (the W waves that share one 32-cell
+// tile): the B tile(s) [32 cells][Rpad rows] (row stride padded by 16 bytes
+// against bank conflicts of the 16-byte fragment reads), a float32 tile of
+// the forward operand X [32 cells][Rpad rows] that the gather writes and the
+// epilogue reads back (the B tile itself for the forward float32
+// contraction), and the cross-wave reduction scratch (fp16 scales, adjoint
+// per-cell sums).  After the groups, one copy of the emission rows.
 __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
-                                               bool f16) {
+                                               bool f16, int ngroups = 1) {
   LdsLayout L;
   int off = 0;
   L.b_off = off;
@@ -310,9 +320,9 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
   L.red_off = off;
   const int nred = adjoint ? 3 : (f16 ? 1 : 0);
   off += nred * W * 32 * 4;
-  L.jrow_off = off;
-  off += Rpad * 4;
-  L.total = off;
+  L.group = off;
+  L.jrow_off = ngroups * off;
+  L.total = L.jrow_off + Rpad * 4;
   return L;
 }
 
@@ -326,6 +336,222 @@ __device__ __forceinline__ f32x16 mfma_step_f32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// One 32-cell tile of the fused step, executed by the W waves of one tile
+// group (this wave: row tile t = wg).  An inactive group (no tile left in a
+// ragged batch) still takes part in every barrier; its lanes count as
+// invalid, read the lattice's first cells and store nothing.
+struct TileLds {
+  char *s_b, *s_x;
+  float *s_red;
+  const float *s_jrow;
+};
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing>
+__device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
+                                           const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
+                                           int64_t tile, bool active, int t, int wg, int W, int lane) {
+  const int col = lane & 31;
+  const int h = lane >> 5;
+  char *s_b = ts.s_b;
+  char *s_x = ts.s_x;
+  float *s_red = ts.s_red;
+  const float *s_jrow = ts.s_jrow;
+  (void)s_red;
+  const int c0 = active ? (int)(tile * 32) : 0;
+  float mv[ADJ ? 16 : 1];
+  float cscale = 1.0f;
+  (void)mv;
+  // this lane's rows in the LDS tiles: cell col, rows rbase + 8 q + (0..3)
+  const int rbase = t * 32 + h * 4;
+  char *xrow = s_x + col * L.strideX + rbase * 4;
+
+  // ---- 1. gather own rows ------------------------------------------------
+  // First cell of the tile (one 32-bit division per tile) and the lane's cell.
+  const int y0 = c0 / g.nx, x0 = c0 - y0 * g.nx;
+  LaneCell lc = lane_cell(g, c0, x0, y0, col);
+  lc.valid = lc.valid && active;
+  // per-cell coefficients, loaded now so that their latency is off the
+  // epilogue's path (invalid lanes read the tile's first cell)
+  const float al = a.alpha[lc.c], be = a.beta[lc.c], em = a.emis[lc.c];
+  const float emis_dt = a.dt_pre * em;
+  // A tile is interior when every tap of every cell lies inside the lattice
+  // (taps reach at most two cells either way); then no wrap or ghost is needed.
+  const int c_last = (int)((c0 + 32 < g.C ? (int64_t)c0 + 32 : g.C) - 1);
+  const int ty1 = c_last / g.nx, tx1 = c_last - ty1 * g.nx;
+  const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
+  // X (float32) goes to the X tile; the epilogue reads it back from there.
+  if (interior)
+    gather_field<false, GATHER, true, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
+  else
+    gather_field<false, GATHER, false, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
+  if constexpr (ADJ) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (interior)
+      gather_field<true, true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
+    else
+      gather_field<true, true, false, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
+  }
+
+  // ---- 3a. first A fragments in flight ---------------------------------------
+  // A is the same for every tile; an L2 round trip for one K step is several
+  // times longer than that step's MFMAs, so a ring of kRing steps is kept in
+  // flight, started here to overlap the B conversion and the barrier.
+    constexpr int kStep = PREC == P_F32 ? 8 : 16;
+  const int nk = (tr.khi - tr.klo) / kStep;
+  const uint4 *A = a.frag + lane;
+  const uint4 *Alo = a.frag_lo + lane;
+  uint4 ring[kRing], ring_lo[PREC == P_BF16X3 ? kRing : 1];
+#pragma unroll
+  for (int j = 0; j < kRing; ++j) {
+    ring[j] = A[frag_rec(tr, j, nk)];
+    if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, j, nk)];
+  }
+
+  // ---- 2. B operand: the contraction input in its precision ------------------
+  // forward: X (already in place for float32); adjoint: mu.
+  if (ADJ || PREC != P_F32) {
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      f32x4 x4;
+      if (ADJ)
+        x4 = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
+      else
+        x4 = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[4 * q + j] = x4[j];
+    }
+    // per-cell power-of-two scale for fp16 operands (max over all rows)
+    if (PREC == P_F16) {
+      float m = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(v[i]));
+      m = fmaxf(m, __shfl_xor(m, 32));
+      if (h == 0) s_red[wg * 32 + col] = m;
+      __syncthreads();
+      m = 0.0f;
+      for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * 32 + col]);
+      int e = 0;
+      if (m > 0.0f) (void)frexpf(m, &e);
+      cscale = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
+    }
+    char *brow = s_b + col * L.strideB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r0 = rbase + q * 8;
+      if (PREC == P_F32) {
+        *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+      } else if (PREC == P_BF16 || PREC == P_BF16X3) {
+        bf16x4 hv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[4 * q + j]);
+        *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hv;
+        if (PREC == P_BF16X3) {
+          bf16x4 lo;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[4 * q + j] - static_cast<float>(hv[j]));
+          *reinterpret_cast<bf16x4 *>(brow + L.tileB + r0 * 2) = lo;
+        }
+      } else {
+        f16x4 hv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[4 * q + j] * cscale);
+        *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. matrix-core contraction over the tile's K range ------------------
+  // Steps are taken in groups of kRing; steps past nk multiply the zero block
+  // with the last valid B row (finite), adding nothing.
+  f32x16 acc = f32x16{0};
+  const int nsteps = (nk + kRing - 1) / kRing * kRing;
+  for (int s0 = 0; s0 < nsteps; s0 += kRing) {
+#pragma unroll
+    for (int j = 0; j < kRing; ++j) {
+      const int s = s0 + j;
+      const uint4 araw = ring[j], araw_lo = ring_lo[PREC == P_BF16X3 ? j : 0];
+      ring[j] = A[frag_rec(tr, s + kRing, nk)];
+      if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
+      const int kb = tr.klo + kStep * min(s, nk - 1);
+      if (PREC == P_F32) {
+        const f32x4 av = __builtin_bit_cast(f32x4, araw);
+        const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + col * L.strideB + (kb + 4 * h) * 4);
+        acc = mfma_step_f32(av[0], bv[0], acc);
+        acc = mfma_step_f32(av[1], bv[1], acc);
+        acc = mfma_step_f32(av[2], bv[2], acc);
+        acc = mfma_step_f32(av[3], bv[3], acc);
+      } else {
+        const char *bp = s_b + col * L.strideB + (kb + 8 * h) * 2;
+        if (PREC == P_F16) {
+          const f16x8 av = __builtin_bit_cast(f16x8, araw);
+          const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+        } else {
+          const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
+          if (PREC == P_BF16X3) {
+            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+            const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc, 0, 0, 0);
+          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // ---- 4. epilogue -------------------------------------------------------------
+  float part[3] = {0.0f, 0.0f, 0.0f};
+  if (lc.valid) {
+    const int c = lc.c;
+    const float unscale = a.a_scale_inv / cscale;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (ld[q].d >= g.n) continue;
+      const f32x4 jp = *reinterpret_cast<const f32x4 *>(s_jrow + 4 * ld[q].d);
+      const f32x4 xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int i = 4 * q + s;
+        const float prod = acc[i] * unscale;
+        float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
+        if (!ADJ) {
+          *o = fmaf(be, prod, fmaf(al, xq[s], a.dt_post * em * jp[s]));
+        } else {
+          const float lam = fmaf(be, prod, al * mv[i]);
+          *o = lam;
+          part[0] = fmaf(mv[i], xq[s], part[0]);
+          part[1] = fmaf(prod, xq[s], part[1]);
+          part[2] = fmaf(fmaf(a.dt_pre, lam, a.dt_post * mv[i]), jp[s], part[2]);
+        }
+      }
+    }
+  }
+  if (ADJ) {
+    // per-cell sums over all rows: half-waves, then waves via LDS
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float v = part[k];
+      v += __shfl_xor(v, 32);
+      if (h == 0) s_red[(k * W + wg) * 32 + col] = v;
+    }
+    __syncthreads();
+    for (int e = wg * 64 + lane; e < 3 * 32; e += W * 64) {
+      const int k = e / 32, cc = e - k * 32;
+      const int64_t c = (int64_t)c0 + cc;
+      if (active && c < g.C) {
+        double s = 0.0;
+        for (int ww = 0; ww < W; ++ww) s += (double)s_red[(k * W + ww) * 32 + cc];
+        a.gacc[(int64_t)k * g.C + c] += s;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT>
 __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
@@ -334,16 +560,12 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   const int W = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int col = lane & 31;
   const int h = lane >> 5;
   const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
-  char *s_b = smem + L.b_off;
-  char *s_x = smem + L.x_off;
-  (void)s_x;
   float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
   for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
   __syncthreads();
-  float *s_red = reinterpret_cast<float *>(smem + L.red_off);
+  const TileLds ts{smem + L.b_off, smem + L.x_off, reinterpret_cast<float *>(smem + L.red_off), s_jrow};
 
   const int t = __builtin_amdgcn_readfirstlane(w);  // the 32-row tile this wave owns
   const TileRange tr = a.tiles[t];
@@ -363,207 +585,159 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   const int64_t last = ntiles * (kq + 1) / chunks;
 
   for (int64_t tile = first; tile < last; tile += per) {
-    const int c0 = (int)(tile * 32);
     // The direction data does not change between tiles.  Making it opaque in
     // place at every tile keeps the compiler from hoisting what derives from
     // it (16 plane pointers per buffer, the emission rows) out of the loop,
     // which would not fit in VGPRs, without holding a second copy.
-    LaneDir(&ld)[4] = ldk;
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    float mv[ADJ ? 16 : 1];
-    float cscale = 1.0f;
-    (void)mv;
-    // this lane's rows in the LDS tiles: cell col, rows rbase + 8 q + (0..3)
-    const int rbase = t * 32 + h * 4;
-    char *xrow = s_x + col * L.strideX + rbase * 4;
-
-    // ---- 1. gather own rows ------------------------------------------------
-    // First cell of the tile (one 32-bit division per tile) and the lane's cell.
-    const int y0 = c0 / g.nx, x0 = c0 - y0 * g.nx;
-    const LaneCell lc = lane_cell(g, c0, x0, y0, col);
-    // per-cell coefficients, loaded now so that their latency is off the
-    // epilogue's path (invalid lanes read the tile's first cell)
-    const float al = a.alpha[lc.c], be = a.beta[lc.c], em = a.emis[lc.c];
-    const float emis_dt = a.dt_pre * em;
-    // A tile is interior when every tap of every cell lies inside the lattice
-    // (taps reach at most two cells either way); then no wrap or ghost is needed.
-    const int c_last = (int)((c0 + 32 < g.C ? (int64_t)c0 + 32 : g.C) - 1);
-    const int ty1 = c_last / g.nx, tx1 = c_last - ty1 * g.nx;
-    const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
-    // X (float32) goes to the X tile; the epilogue reads it back from there.
-    if (interior)
-      gather_field<false, GATHER, true, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
-    else
-      gather_field<false, GATHER, false, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
-    if constexpr (ADJ) {
-      __builtin_amdgcn_sched_barrier(0);
-      if (interior)
-        gather_field<true, true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
-      else
-        gather_field<true, true, false, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
-    }
-
-    // ---- 3a. first A fragments in flight ---------------------------------------
-    // A is the same for every tile; an L2 round trip for one K step is several
-    // times longer than that step's MFMAs, so a ring of kRing steps is kept in
-    // flight, started here to overlap the B conversion and the barrier.
-    constexpr int kRing = MAXW > 4 ? 1 : 4;
-    constexpr int kStep = PREC == P_F32 ? 8 : 16;
-    const int nk = (tr.khi - tr.klo) / kStep;
-    const uint4 *A = a.frag + lane;
-    const uint4 *Alo = a.frag_lo + lane;
-    uint4 ring[kRing], ring_lo[PREC == P_BF16X3 ? kRing : 1];
-#pragma unroll
-    for (int j = 0; j < kRing; ++j) {
-      ring[j] = A[frag_rec(tr, j, nk)];
-      if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, j, nk)];
-    }
-
-    // ---- 2. B operand: the contraction input in its precision ------------------
-    // forward: X (already in place for float32); adjoint: mu.
-    if (ADJ || PREC != P_F32) {
-      float v[16];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        f32x4 x4;
-        if (ADJ)
-          x4 = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
-        else
-          x4 = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[4 * q + j] = x4[j];
-      }
-      // per-cell power-of-two scale for fp16 operands (max over all rows)
-      if (PREC == P_F16) {
-        float m = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(v[i]));
-        m = fmaxf(m, __shfl_xor(m, 32));
-        if (h == 0) s_red[w * 32 + col] = m;
-        __syncthreads();
-        m = 0.0f;
-        for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * 32 + col]);
-        int e = 0;
-        if (m > 0.0f) (void)frexpf(m, &e);
-        cscale = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
-      }
-      char *brow = s_b + col * L.strideB;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r0 = rbase + q * 8;
-        if (PREC == P_F32) {
-          *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
-        } else if (PREC == P_BF16 || PREC == P_BF16X3) {
-          bf16x4 hv;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[4 * q + j]);
-          *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hv;
-          if (PREC == P_BF16X3) {
-            bf16x4 lo;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[4 * q + j] - static_cast<float>(hv[j]));
-            *reinterpret_cast<bf16x4 *>(brow + L.tileB + r0 * 2) = lo;
-          }
-        } else {
-          f16x4 hv;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[4 * q + j] * cscale);
-          *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- 3. matrix-core contraction over the tile's K range ------------------
-    // Steps are taken in groups of kRing; steps past nk multiply the zero block
-    // with the last valid B row (finite), adding nothing.
-    f32x16 acc = f32x16{0};
-    const int nsteps = (nk + kRing - 1) / kRing * kRing;
-    for (int s0 = 0; s0 < nsteps; s0 += kRing) {
-#pragma unroll
-      for (int j = 0; j < kRing; ++j) {
-        const int s = s0 + j;
-        const uint4 araw = ring[j], araw_lo = ring_lo[PREC == P_BF16X3 ? j : 0];
-        ring[j] = A[frag_rec(tr, s + kRing, nk)];
-        if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
-        const int kb = tr.klo + kStep * min(s, nk - 1);
-        if (PREC == P_F32) {
-          const f32x4 av = __builtin_bit_cast(f32x4, araw);
-          const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + col * L.strideB + (kb + 4 * h) * 4);
-          acc = mfma_step_f32(av[0], bv[0], acc);
-          acc = mfma_step_f32(av[1], bv[1], acc);
-          acc = mfma_step_f32(av[2], bv[2], acc);
-          acc = mfma_step_f32(av[3], bv[3], acc);
-        } else {
-          const char *bp = s_b + col * L.strideB + (kb + 8 * h) * 2;
-          if (PREC == P_F16) {
-            const f16x8 av = __builtin_bit_cast(f16x8, araw);
-            const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
-          } else {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
-            if (PREC == P_BF16X3) {
-              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
-              const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
-              acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc, 0, 0, 0);
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-          }
-        }
-      }
-    }
-
-    // ---- 4. epilogue -------------------------------------------------------------
-    float part[3] = {0.0f, 0.0f, 0.0f};
-    if (lc.valid) {
-      const int c = lc.c;
-      const float unscale = a.a_scale_inv / cscale;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (ld[q].d >= g.n) continue;
-        const f32x4 jp = *reinterpret_cast<const f32x4 *>(s_jrow + 4 * ld[q].d);
-        const f32x4 xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int i = 4 * q + s;
-          const float prod = acc[i] * unscale;
-          float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
-          if (!ADJ) {
-            *o = al * xq[s] + be * prod + a.dt_post * em * jp[s];
-          } else {
-            const float lam = al * mv[i] + be * prod;
-            *o = lam;
-            part[0] += mv[i] * xq[s];
-            part[1] += prod * xq[s];
-            part[2] += (a.dt_pre * lam + a.dt_post * mv[i]) * jp[s];
-          }
-        }
-      }
-    }
-    if (ADJ) {
-      // per-cell sums over all rows: half-waves, then waves via LDS
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        float v = part[k];
-        v += __shfl_xor(v, 32);
-        if (h == 0) s_red[(k * W + w) * 32 + col] = v;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < 3 * 32; e += blockDim.x) {
-        const int k = e / 32, cc = e - k * 32;
-        const int64_t c = (int64_t)c0 + cc;
-        if (c < g.C) {
-          double s = 0.0;
-          for (int ww = 0; ww < W; ++ww) s += (double)s_red[(k * W + ww) * 32 + cc];
-          a.gacc[(int64_t)k * g.C + c] += s;
-        }
-      }
-    }
-    __syncthreads();
+    fused_tile<PREC, GATHER, ADJ, CKPT, (MAXW > 4 ? 1 : 4)>(a, g, L, ts, tr, ldk, tile, true, t, t, W, lane);
   }
+}
+
+// ------------------------------------------------------------- spectral batch --
+//
+// One launch advances every channel of the batch by one step.  The work
+// queue is the channels' tiles in channel order, a work item being one tile
+// per tile group of the block; each block takes a contiguous run of items,
+// so it changes channel rarely.  On a change the block reloads the channel's
+// descriptor (scalar loads), its emission rows into LDS and each lane's
+// direction data.
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+__global__ void __launch_bounds__(64 * kBatchWaves) batch_kernel(const BatchChan *__restrict__ chans, int nchan,
+                                                                 int64_t nitems, BatchSel sel) {
+  using T = PrecTraits<PREC>;
+  extern __shared__ __align__(16) char smem[];
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i0 = nitems * blockIdx.x / gridDim.x;
+  const int64_t i1 = nitems * (blockIdx.x + 1) / gridDim.x;
+
+  int ch = -1;
+  int64_t next0 = 0;   // first item of the next channel
+  int64_t item0 = 0, ntiles = 0;
+  int W = 1, grp = 0, t = 0;
+  StepArgs a{};
+  Geometry g{};
+  LdsLayout L{};
+  TileLds ts{};
+  TileRange tr{};
+  LaneDir ld[4];
+  for (int64_t it = i0; it < i1; ++it) {
+    if (ch < 0 || it >= next0) {
+      int c = ch < 0 ? 0 : ch;
+      while (c + 1 < nchan && chans[c + 1].item0 <= it) ++c;
+      ch = c;
+      const BatchChan &bc = chans[c];
+      next0 = c + 1 < nchan ? chans[c + 1].item0 : nitems;
+      item0 = bc.item0;
+      ntiles = bc.ntiles;
+      a = bc.a;
+      auto bufp = [&](int id, int slot) -> float * {
+        return id < 0 ? nullptr : bc.buf[id] + (int64_t)slot * bc.state_elems;
+      };
+      a.in = bufp(sel.in, sel.in_slot);
+      a.out = bufp(sel.out, sel.out_slot);
+      a.s_out = bufp(sel.sout, sel.sout_slot);
+      a.lam_next = bufp(sel.lam, sel.lam_slot);
+      g = a.geo;
+      W = g.Rpad / 32;
+      grp = w / W;
+      t = w - grp * W;
+      L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, bc.groups);
+      char *gb = smem + grp * L.group;
+      float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
+      ts = TileLds{gb + L.b_off, gb + L.x_off, reinterpret_cast<float *>(gb + L.red_off), s_jrow};
+      tr = a.tiles[t];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ld[q] = lane_dir(a, 8 * t + 2 * q + h);
+      __syncthreads();   // the previous channel's last tile is done with the LDS
+      for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ld[q].off), "+v"(ld[q].td), "+v"(ld[q].d));
+    const int64_t tile = (it - item0) * (kBatchWaves / W) + grp;
+    fused_tile<PREC, GATHER, ADJ, CKPT, 4>(a, g, L, ts, tr, ld, tile, tile < ntiles, t, t, W, lane);
+  }
+}
+
+size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint) {
+  const int W = Rpad / 32;
+  if (W < 1 || W > kBatchWaves || kBatchWaves % W != 0) return (size_t)-1;
+  const int esize = prec == P_F32 ? 4 : 2;
+  const int ntile = prec == P_BF16X3 ? 2 : 1;
+  return (size_t)lds_layout(Rpad, esize, ntile, W, adjoint, prec == P_F16, kBatchWaves / W).total;
+}
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+hipError_t prepare_batch_k(int lds_bytes, int *occ) {
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  int o = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)k, 64 * kBatchWaves, lds_bytes);
+  if (e != hipSuccess) return e;
+  *occ = std::min(*occ, o);
+  return hipSuccess;
+}
+
+template <int PREC>
+hipError_t prepare_batch_p(int lds_bytes, int *occ) {
+  hipError_t e;
+  if ((e = prepare_batch_k<PREC, false, false, false>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, false>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, true>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, false, true, false>(lds_bytes, occ)) != hipSuccess) return e;
+  return prepare_batch_k<PREC, true, true, false>(lds_bytes, occ);
+}
+
+hipError_t prepare_batch_impl(int prec, int lds_bytes, int *blocks_per_cu) {
+  int occ = 1 << 20;
+  hipError_t e = hipErrorInvalidValue;
+  if (prec == P_F32) e = prepare_batch_p<P_F32>(lds_bytes, &occ);
+  if (prec == P_BF16) e = prepare_batch_p<P_BF16>(lds_bytes, &occ);
+  if (prec == P_F16) e = prepare_batch_p<P_F16>(lds_bytes, &occ);
+  if (prec == P_BF16X3) e = prepare_batch_p<P_BF16X3>(lds_bytes, &occ);
+  if (e != hipSuccess) return e;
+  if (occ < 1) return hipErrorInvalidConfiguration;
+  *blocks_per_cu = occ;
+  return hipSuccess;
+}
+
+template <int PREC>
+hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
+                          const BatchSel &sel, int lds_bytes, int grid, hipStream_t s) {
+  const dim3 gd((unsigned)grid), bd(64 * kBatchWaves);
+  if (adjoint) {
+    if (gather)
+      hipLaunchKernelGGL((batch_kernel<PREC, true, true, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
+    else
+      hipLaunchKernelGGL((batch_kernel<PREC, false, true, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
+  } else if (ckpt) {
+    hipLaunchKernelGGL((batch_kernel<PREC, true, false, true>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
+  } else if (gather) {
+    hipLaunchKernelGGL((batch_kernel<PREC, true, false, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
+  } else {
+    hipLaunchKernelGGL((batch_kernel<PREC, false, false, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
+                                  bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int grid,
+                                  hipStream_t s) {
+  if (ckpt && (adjoint || !gather)) return hipErrorInvalidValue;
+  if (grid < 1 || nitems < 1) return hipErrorInvalidValue;
+  switch (prec) {
+    case P_F32: return launch_batch_p<P_F32>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+    case P_BF16: return launch_batch_p<P_BF16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+    case P_F16: return launch_batch_p<P_F16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+    case P_BF16X3: return launch_batch_p<P_BF16X3>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
@@ -644,7 +818,7 @@ __global__ void __launch_bounds__(256) stream_kernel(StepArgs a, const float *__
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] = tp[k][(int64_t)s * stride[k]];
     }
-    out[plane + c] = (ld.w00 * v[0] + ld.w10 * v[1]) + (ld.w01 * v[2] + ld.w11 * v[3]);
+    out[plane + c] = tap_sum(ld, v);
   }
 }
 
@@ -665,19 +839,19 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
         float xs[4];
 #pragma unroll
         for (int si = 0; si < 4; ++si)
-          xs[si] = in[(int64_t)(4 * di + si) * g.C + c] + a.dt_pre * em * a.jrow[4 * di + si];
+          xs[si] = fmaf(a.dt_pre * em, a.jrow[4 * di + si], in[(int64_t)(4 * di + si) * g.C + c]);
         const float *mrow = M + (int64_t)(4 * dout) * R + 4 * di;
 #pragma unroll
         for (int so = 0; so < 4; ++so)
 #pragma unroll
-          for (int si = 0; si < 4; ++si) acc[so] += mrow[so * R + si] * xs[si];
+          for (int si = 0; si < 4; ++si) acc[so] = fmaf(mrow[so * R + si], xs[si], acc[so]);
       }
 #pragma unroll
       for (int so = 0; so < 4; ++so) {
         const int64_t off = (int64_t)(4 * dout + so) * g.C + c;
         const float jr = a.jrow[4 * dout + so];
-        const float xo = in[off] + a.dt_pre * em * jr;
-        out[off] = al * xo + be * acc[so] + a.dt_post * em * jr;
+        const float xo = fmaf(a.dt_pre * em, jr, in[off]);
+        out[off] = fmaf(be, acc[so], fmaf(al, xo, a.dt_post * em * jr));
       }
     }
   }
@@ -843,6 +1017,18 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 4096) {
 }
 
 }  // namespace
+
+size_t batch_lds_bytes(int Rpad, int prec, bool adjoint) { return batch_lds_bytes_impl(Rpad, prec, adjoint); }
+
+hipError_t prepare_batch(int prec, int lds_bytes, int *blocks_per_cu) {
+  return prepare_batch_impl(prec, lds_bytes, blocks_per_cu);
+}
+
+hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
+                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int grid,
+                             hipStream_t s) {
+  return launch_batch_step_impl(d_chans, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+}
 
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint) {
   if (g.Rpad / 32 > 16) return (size_t)-1;

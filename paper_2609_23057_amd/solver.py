@@ -60,9 +60,12 @@ def _ptr(t):
 
 
 class Solver:
-    """One context: problem, workspace and stream (torch's current stream)."""
+    """One context: problem, workspace and stream (torch's current stream).
 
-    def __init__(self, problem, device=None, stream=None):
+    A Solver made by Batch.channel() views a channel of a batch: it shares the
+    batch's context, workspace and stream and does not own them."""
+
+    def __init__(self, problem, device=None, stream=None, _ctx=None, _owner=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the solver needs a HIP device")
         self.problem = problem
@@ -72,14 +75,19 @@ class Solver:
         self.n = problem.n_zen * problem.n_az
         self.nx, self.ny = problem.nx, problem.ny
         self.shape = (self.n, 4, self.ny, self.nx)
-        nbytes = A.rt_workspace_bytes(problem)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.ctx = A.rt_init(problem, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if _ctx is None:
+            nbytes = A.rt_workspace_bytes(problem)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.ctx = A.rt_init(problem, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+            self._owned = True
+        else:
+            self.ctx, self._owner, self._owned = _ctx, _owner, False
         self.nout = [A.rt_num_outgoing(problem, e) for e in range(4)]
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx and A is not None and getattr(A, "rt_destroy", None) is not None:
+        if ctx and getattr(self, "_owned", False) and A is not None and \
+                getattr(A, "rt_destroy", None) is not None:
             A.rt_destroy(ctx)
             self.ctx = None
 
@@ -184,3 +192,62 @@ class RTSolve(torch.autograd.Function):
         lam = s.readout_adjoint(ctx.edge, gout.contiguous().float())
         g_tau, g_alb, g_em = s.adjoint(ctx.nsteps, ctx.ck, ctx.K, lam)
         return g_tau, g_alb, g_em, None, None, None, None, None, None
+
+
+class Batch:
+    """Spectral batch: independent channels advanced together, one launch per
+    time step over all channels' tiles.  Per-channel medium, readout and
+    readout adjoint go through the channel views (Solver objects)."""
+
+    def __init__(self, problems, device=None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the batch needs a HIP device")
+        self.problems = list(problems)
+        self.device = torch.device(device or "cuda")
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        nbytes = A.rt_batch_workspace_bytes(self.problems)
+        if nbytes == 0:
+            raise A.RTError(A.RT_EINVAL, A.rt_batch_last_error())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.handle = A.rt_batch_init(self.problems, aligned, nbytes, self.stream.cuda_stream)
+        self.channels = [Solver(p, self.device, self.stream, _ctx=A.rt_batch_channel(self.handle, i), _owner=self)
+                         for i, p in enumerate(self.problems)]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and A is not None and getattr(A, "rt_batch_destroy", None) is not None:
+            self.channels = []
+            A.rt_batch_destroy(h)
+            self.handle = None
+
+    def __len__(self):
+        return len(self.problems)
+
+    def empty_states(self):
+        return [c.empty_state() for c in self.channels]
+
+    def set_graph(self, enabled):
+        A.rt_batch_set_graph(self.handle, enabled)
+
+    def run(self, states, nsteps, ckpts=None, ckpt_every=0):
+        A.rt_batch_run(self.handle, [_ptr(s) for s in states], int(nsteps),
+                       None if ckpts is None else [_ptr(c) for c in ckpts], int(ckpt_every))
+
+    def checkpoint_buffers(self, nsteps, ckpt_every):
+        return [c.checkpoint_buffer(nsteps, ckpt_every) for c in self.channels]
+
+    def segment_buffers(self, ckpt_every):
+        return [c.segment_buffer(ckpt_every) for c in self.channels]
+
+    def adjoint(self, nsteps, ckpts, ckpt_every, lamTs, segs=None):
+        segs = self.segment_buffers(ckpt_every) if segs is None else segs
+        grads = [torch.empty((3, c.ny, c.nx), dtype=torch.float32, device=self.device) for c in self.channels]
+        A.rt_batch_adjoint(self.handle, int(nsteps), [_ptr(c) for c in ckpts], int(ckpt_every),
+                           [_ptr(s) for s in segs], [_ptr(l) for l in lamTs],
+                           [_ptr(g[0]) for g in grads], [_ptr(g[1]) for g in grads], [_ptr(g[2]) for g in grads])
+        return [(g[0], g[1], g[2]) for g in grads]
+
+    def synchronize(self):
+        A.rt_batch_synchronize(self.handle)

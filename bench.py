@@ -11,6 +11,10 @@ solar beam entering the top, 2000 time steps):
 value = (C n T forward + C n T adjoint) Stokes cell-direction updates per
 second of that step.  All inputs are resident in HBM before timing starts.
 
+Extras (skipped with --no-extras): forward rates at 1024x1024, n = 128 per
+contraction precision, and the 64-channel spectral batch (one launch per step
+for all channels, eager and as a replayed HIP graph).
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 import argparse
@@ -162,6 +166,72 @@ def precision_extras(T=20, warm=3):
     return {"workload": "prec1024: 1024x1024, n=128 (8x16), forward steps", "steps": T, "rates": res}
 
 
+def spectral_extras(T=200):
+    """The 64-channel spectral batch (per-channel lattice 128^2..512^2 and
+    n = 16..64, bf16 contraction): forward run of T steps with sqrt(T)
+    checkpoints, top-edge readout adjoint and the batched adjoint, each step
+    of all channels one launch; timed eagerly and as a replayed HIP graph."""
+    import numpy as np
+    import torch
+    import paper_2609_23057_amd as P
+    import paper_2609_23057_amd._abi as A
+    import workloads as W
+    specs = W.spectral_channels(64)
+    batch = P.Batch([P.make_problem(**dict(s, precision="bf16")) for s in specs])
+    keep = []
+    for ch, s in zip(batch.channels, specs):
+        med = W.medium(s)
+        t = [torch.tensor(np.ascontiguousarray(med[k]), dtype=torch.float32, device=ch.device)
+             for k in ("tau", "albedo", "emis")]
+        ch.set_medium(*t, med["jprof"], med["inflow"])
+        keep.append(t)
+    K = max(1, int(math.ceil(math.sqrt(T))))
+    states = [torch.zeros(ch.shape, device=ch.device) for ch in batch.channels]
+    ck = batch.checkpoint_buffers(T, K)
+    segs = batch.segment_buffers(K)
+    lams = [torch.empty(ch.shape, device=ch.device) for ch in batch.channels]
+    grads = [torch.empty((3, ch.ny, ch.nx), device=ch.device) for ch in batch.channels]
+    ptrs = lambda xs: [x.data_ptr() for x in xs]  # noqa: E731
+
+    def forward():
+        for x in states:
+            x.zero_()
+        batch.run(states, T, ck, K)
+
+    def adjoint():
+        for ch, x, lam in zip(batch.channels, states, lams):
+            A.rt_readout_adjoint(ch.ctx, 3, loss_grad(ch.readout(x, 3)).data_ptr(), lam.data_ptr())
+        A.rt_batch_adjoint(batch.handle, T, ptrs(ck), K, ptrs(segs), ptrs(lams), [g[0].data_ptr() for g in grads],
+                           [g[1].data_ptr() for g in grads], [g[2].data_ptr() for g in grads])
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    res = {}
+    for mode in ("eager", "graph"):
+        batch.set_graph(mode == "graph")
+        _log("bench: spectral64 %s" % mode)
+        forward()
+        adjoint()
+        torch.cuda.synchronize()
+        res[mode] = {"forward_ms": timed(forward), "adjoint_ms": timed(adjoint)}
+    batch.set_graph(False)
+    upd = float(sum(ch.nx * ch.ny * ch.n for ch in batch.channels))
+    g = res["graph"]
+    return {"workload": "spectral64: 64 channels, 400-900 nm, lattices 128^2..512^2, n in {16, 32, 64}, "
+                        "bf16 contraction, T=%d, checkpoints every %d steps" % (T, K),
+            "cell_dir_per_step": upd, "time_steps": T, "ms": res,
+            "forward_cell_dir_updates_per_s": upd * T / (g["forward_ms"] / 1e3),
+            "forward_adjoint_cell_dir_updates_per_s": 2 * upd * T / ((g["forward_ms"] + g["adjoint_ms"]) / 1e3),
+            "adjoint_fwd_ratio": g["adjoint_ms"] / g["forward_ms"],
+            "graph_speedup_forward": res["eager"]["forward_ms"] / g["forward_ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +331,9 @@ def main():
         del ck, seg
         torch.cuda.empty_cache()
         line["precision_speedup"] = precision_extras()
+        torch.cuda.empty_cache()
+        line["spectral_batch"] = spectral_extras()
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         _log("bench: cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(spec)

@@ -12,8 +12,9 @@ value = (C n T forward + C n T adjoint) Stokes cell-direction updates per
 second of that step.  All inputs are resident in HBM before timing starts.
 
 Extras (skipped with --no-extras): forward rates at 1024x1024, n = 128 per
-contraction precision, and the 64-channel spectral batch (one launch per step
-for all channels, eager and as a replayed HIP graph).
+contraction precision, the stand-alone streaming kernel's HBM rate at beam512
+and prec1024, and the 64-channel spectral batch (one launch per step for all
+channels, eager and as a replayed HIP graph).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
@@ -164,6 +165,40 @@ def precision_extras(T=20, warm=3):
         res[k]["speedup_vs_plain_fp32"] = (res[k]["cell_dir_updates_per_s"]
                                            / res["plain"]["cell_dir_updates_per_s"])
     return {"workload": "prec1024: 1024x1024, n=128 (8x16), forward steps", "steps": T, "rates": res}
+
+
+def streaming_extras(reps=50):
+    """The stand-alone streaming kernel (rt_stream, Eq. 34 pull with the
+    workload's edges) at beam512 and prec1024: average launch time over
+    `reps` launches (HIP events on the solver's stream) and algorithmic HBM
+    traffic 32 B per cell-direction (16 B read, 16 B written) against the
+    8 TB/s peak."""
+    import torch
+    import workloads as W
+    res = {}
+    for name in ("beam512", "prec1024"):
+        spec = W.spec(name)
+        C, n = spec["nx"] * spec["ny"], W.ndir(spec)
+        solver = make_solver(spec, "fp32")
+        a = torch.rand(solver.shape, device=solver.device)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            solver.stream_field(a, b)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            solver.stream_field(a, b) if i % 2 == 0 else solver.stream_field(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        nbytes = 32.0 * C * n
+        gbs = nbytes / (us * 1e-6) / 1e9
+        res[name] = {"avg_launch_us": us, "algorithmic_bytes_per_launch": nbytes, "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "bound": "hbm"}
+        del solver, a, b
+        torch.cuda.empty_cache()
+    return res
 
 
 def spectral_extras(T=200):
@@ -331,6 +366,8 @@ def main():
         del ck, seg
         torch.cuda.empty_cache()
         line["precision_speedup"] = precision_extras()
+        torch.cuda.empty_cache()
+        line["streaming"] = streaming_extras()
         torch.cuda.empty_cache()
         line["spectral_batch"] = spectral_extras()
         torch.cuda.empty_cache()

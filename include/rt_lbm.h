@@ -160,6 +160,16 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
 /* One step S_out = Stream(Collide(S_in)); S_in and S_out must not overlap. */
 rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out);
 
+/* Streaming alone (Sec. 2.1.6, Eq. 33-34): d_out[p] = bilinear pull of
+ * d_in[p] by the displacement of plane p's direction, with the context's
+ * edges (periodic wrap, Eq. 39; absorbing edges give zero; inflow edges give
+ * the radiance set by rt_set_medium).  Both fields are device [4n][ny][nx]
+ * float32 (rt_state_bytes), caller-owned, and must not overlap.  Fields that
+ * are 16-byte aligned with nx a multiple of 4 take the vectorised kernel;
+ * the result is the same either way.  RT_ESTATE before rt_set_medium (the
+ * inflow radiance lives there).  Asynchronous on the context's stream. */
+rt_status rt_stream(rt_ctx *c, const float *d_in, float *d_out);
+
 /* nsteps steps in place on d_S (S_0 in, S_nsteps out).  If d_ckpt is not NULL
  * it receives S_{k*ckpt_every} in slot k = 0 .. ceil(nsteps/ckpt_every)-1
  * (slots of rt_state_bytes each), as rt_adjoint expects. */

@@ -60,6 +60,7 @@ _SIGS = {
     "rt_init": (c_int32, [_P, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "rt_set_medium": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rt_stream": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
     "rt_readout": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_maps": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -143,6 +144,10 @@ def rt_set_medium(ctx, d_tau, d_albedo, d_emis, h_jprof, h_inflow=None):
 
 def rt_step(ctx, d_S_in, d_S_out):
     _check(_lib.rt_step(ctx, d_S_in, d_S_out), ctx)
+
+
+def rt_stream(ctx, d_in, d_out):
+    _check(_lib.rt_stream(ctx, d_in, d_out), ctx)
 
 
 def rt_run(ctx, d_S, nsteps, d_ckpt=None, ckpt_every=0):

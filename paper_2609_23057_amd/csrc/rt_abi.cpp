@@ -440,6 +440,16 @@ rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out) {
   return st;
 }
 
+rt_status rt_stream(rt_ctx *c, const float *d_in, float *d_out) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_in || !d_out) return c->fail(RT_EINVAL, "NULL field pointer");
+  const size_t bytes = rt_state_bytes(&c->prob);
+  const char *i0 = reinterpret_cast<const char *>(d_in), *o0 = reinterpret_cast<const char *>(d_out);
+  if (i0 < o0 + bytes && o0 < i0 + bytes) return c->fail(RT_EINVAL, "d_in and d_out overlap");
+  if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  return c->hip(launch_stream(c->args(false), d_in, d_out, c->stream), "stream");
+}
+
 rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t ckpt_every) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_S) return c->fail(RT_EINVAL, "NULL state pointer");

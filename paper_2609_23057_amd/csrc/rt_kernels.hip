@@ -822,6 +822,94 @@ __global__ void __launch_bounds__(256) stream_kernel(StepArgs a, const float *__
   }
 }
 
+// The same pull for nx a multiple of 4 and 16-byte aligned fields.  Each
+// plane is split into interior quads (4 consecutive cells of a row, rows
+// [2, ny - 3], cells [4, nx - 5], every tap inside the lattice) and the
+// border ring (the remaining 4 nx + 8 (ny - 4) cells); a block takes one
+// kind only, so no wave mixes the two paths.  An interior quad reads each of
+// its two source rows as two aligned 16-byte vectors: with nx = 0 mod 4 the
+// misalignment of the first tap, SH = (-ox0 - 1) mod 4, is the same for
+// every cell of a plane, so it is a template argument chosen per block.
+// Blocks are dispatched round-robin over the 8 XCDs; the block index is
+// remapped so that each XCD takes one contiguous run of rows, and the two
+// output rows that read a source row mostly share an L2.  Same arithmetic
+// as stream_kernel (tap_sum), hence the same bits.
+struct QuadSplit {
+  int nqi, nri;     // interior quads per row, interior rows (both 0 if none)
+  int int_blocks;   // blocks per plane taking interior quads
+  int nbord;        // border cells per plane
+  int bpp;          // blocks per plane
+};
+
+template <int SH>
+__device__ __forceinline__ void stream_interior_quad(const Geometry &g, const LaneDir &ld, int64_t plane,
+                                                     int qi, int nqi, const float *__restrict__ in,
+                                                     float *__restrict__ out) {
+  const int r = qi / nqi;
+  const int c = (2 + r) * g.nx + 4 + 4 * (qi - r * nqi);
+  // b points SH + 1 floats before the first cell's (0,0) tap; 16-byte aligned
+  const float *b = in + plane + c - ld.td - 1 - SH;
+  const f32x4 e0 = *reinterpret_cast<const f32x4 *>(b);
+  const f32x4 e1 = *reinterpret_cast<const f32x4 *>(b + 4);
+  const f32x4 f0 = *reinterpret_cast<const f32x4 *>(b - g.nx);
+  const f32x4 f1 = *reinterpret_cast<const f32x4 *>(b - g.nx + 4);
+  const float e[8] = {e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3]};
+  const float f[8] = {f0[0], f0[1], f0[2], f0[3], f1[0], f1[1], f1[2], f1[3]};
+  float r4[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float v[4] = {e[SH + k + 1], e[SH + k], f[SH + k + 1], f[SH + k]};
+    r4[k] = tap_sum(ld, v);
+  }
+  *reinterpret_cast<f32x4 *>(out + plane + c) = f32x4{r4[0], r4[1], r4[2], r4[3]};
+}
+
+__global__ void __launch_bounds__(256) stream4_kernel(StepArgs a, QuadSplit qs, const float *__restrict__ in,
+                                                      float *__restrict__ out) {
+  const Geometry g = a.geo;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = b & 7;
+  const int lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + (b >> 3);
+  const int p = lb / qs.bpp, bx = lb - p * qs.bpp;
+  const LaneDir ld = lane_dir(a, p >> 2);
+  const int s = p & 3;
+  const int64_t plane = ld.off + (int64_t)s * g.C;
+  if (bx < qs.int_blocks) {
+    const int qi = bx * 256 + (int)threadIdx.x;
+    if (qi >= qs.nqi * qs.nri) return;
+    switch ((-ld.ox0 - 1) & 3) {
+      case 0: stream_interior_quad<0>(g, ld, plane, qi, qs.nqi, in, out); break;
+      case 1: stream_interior_quad<1>(g, ld, plane, qi, qs.nqi, in, out); break;
+      case 2: stream_interior_quad<2>(g, ld, plane, qi, qs.nqi, in, out); break;
+      default: stream_interior_quad<3>(g, ld, plane, qi, qs.nqi, in, out); break;
+    }
+    return;
+  }
+  const int k = (bx - qs.int_blocks) * 256 + (int)threadIdx.x;
+  if (k >= qs.nbord) return;
+  int x, y;
+  if (qs.nqi == 0) {           // no interior: the ring is the whole plane
+    y = k / g.nx;
+    x = k - y * g.nx;
+  } else if (k < 4 * g.nx) {   // rows 0, 1, ny - 2, ny - 1
+    const int r = k / g.nx;
+    x = k - r * g.nx;
+    y = r < 2 ? r : g.ny - 4 + r;
+  } else {                     // rows 2 .. ny - 3: cells 0..3 and nx - 4 .. nx - 1
+    const int m = k - 4 * g.nx, i = m & 7;
+    y = 2 + (m >> 3);
+    x = i < 4 ? i : g.nx - 8 + i;
+  }
+  const LaneCell lc{y * g.nx + x, x, y, true};
+  const float *tp[4];
+  int stride[4];
+  edge_taps<false>(a, in, g, ld, lc, tp, stride);
+  float v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = tp[t][(int64_t)s * stride[t]];
+  out[plane + lc.c] = tap_sum(ld, v);
+}
+
 // Y(c) = alpha X(c) + beta M X(c) + dt_post J(c), X = S + dt_pre J, one
 // thread per cell, M in ABI order (row 4 d_out + s_out) read with uniform
 // (scalar) loads.
@@ -1047,8 +1135,23 @@ hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStre
 }
 
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s) {
-  dim3 grid(grid_for(a.geo.C, 256, 1024), 4 * a.geo.n);
-  hipLaunchKernelGGL(stream_kernel, grid, dim3(256), 0, s, a, in, out);
+  const bool quads = a.geo.nx % 4 == 0 && ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  if (quads) {
+    QuadSplit qs;
+    qs.nqi = std::max(0, a.geo.nx / 4 - 2);
+    qs.nri = std::max(0, a.geo.ny - 4);
+    if (qs.nqi == 0 || qs.nri == 0) qs.nqi = qs.nri = 0;
+    const int64_t nint = (int64_t)qs.nqi * qs.nri;
+    qs.nbord = (int)(a.geo.C - 4 * nint);
+    qs.int_blocks = (int)((nint + 255) / 256);
+    qs.bpp = qs.int_blocks + (qs.nbord + 255) / 256;
+    const int64_t blocks = (int64_t)qs.bpp * 4 * a.geo.n;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream4_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, qs, in, out);
+  } else {
+    dim3 grid(grid_for(a.geo.C, 256, 1024), 4 * a.geo.n);
+    hipLaunchKernelGGL(stream_kernel, grid, dim3(256), 0, s, a, in, out);
+  }
   return hipGetLastError();
 }
 

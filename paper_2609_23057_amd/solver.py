@@ -114,6 +114,9 @@ class Solver:
     def step(self, S_in, S_out):
         A.rt_step(self.ctx, _ptr(S_in), _ptr(S_out))
 
+    def stream_field(self, S_in, S_out):
+        A.rt_stream(self.ctx, _ptr(S_in), _ptr(S_out))
+
     def run(self, S, nsteps, ckpt=None, ckpt_every=0):
         A.rt_run(self.ctx, _ptr(S), int(nsteps), _ptr(ckpt), int(ckpt_every))
 

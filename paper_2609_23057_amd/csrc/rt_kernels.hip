@@ -830,6 +830,7 @@ __global__ void __launch_bounds__(256) stream_kernel(StepArgs a, const float *__
 // its two source rows as two aligned 16-byte vectors: with nx = 0 mod 4 the
 // misalignment of the first tap, SH = (-ox0 - 1) mod 4, is the same for
 // every cell of a plane, so it is a template argument chosen per block.
+// A thread takes one quad column in two consecutive interior rows.
 // Blocks are dispatched round-robin over the 8 XCDs; the block index is
 // remapped so that each XCD takes one contiguous run of rows, and the two
 // output rows that read a source row mostly share an L2.  Same arithmetic
@@ -841,18 +842,12 @@ struct QuadSplit {
   int bpp;          // blocks per plane
 };
 
+// One output quad from its two source rows (e: row y - oy0, f: the row
+// below it), each given as the 8 aligned floats that start SH + 1 floats
+// before the first cell's (0,0) tap.
 template <int SH>
-__device__ __forceinline__ void stream_interior_quad(const Geometry &g, const LaneDir &ld, int64_t plane,
-                                                     int qi, int nqi, const float *__restrict__ in,
-                                                     float *__restrict__ out) {
-  const int r = qi / nqi;
-  const int c = (2 + r) * g.nx + 4 + 4 * (qi - r * nqi);
-  // b points SH + 1 floats before the first cell's (0,0) tap; 16-byte aligned
-  const float *b = in + plane + c - ld.td - 1 - SH;
-  const f32x4 e0 = *reinterpret_cast<const f32x4 *>(b);
-  const f32x4 e1 = *reinterpret_cast<const f32x4 *>(b + 4);
-  const f32x4 f0 = *reinterpret_cast<const f32x4 *>(b - g.nx);
-  const f32x4 f1 = *reinterpret_cast<const f32x4 *>(b - g.nx + 4);
+__device__ __forceinline__ void quad_out(const LaneDir &ld, const f32x4 &e0, const f32x4 &e1, const f32x4 &f0,
+                                         const f32x4 &f1, float *dst) {
   const float e[8] = {e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3]};
   const float f[8] = {f0[0], f0[1], f0[2], f0[3], f1[0], f1[1], f1[2], f1[3]};
   float r4[4];
@@ -861,7 +856,31 @@ __device__ __forceinline__ void stream_interior_quad(const Geometry &g, const La
     const float v[4] = {e[SH + k + 1], e[SH + k], f[SH + k + 1], f[SH + k]};
     r4[k] = tap_sum(ld, v);
   }
-  *reinterpret_cast<f32x4 *>(out + plane + c) = f32x4{r4[0], r4[1], r4[2], r4[3]};
+  *reinterpret_cast<f32x4 *>(dst) = f32x4{r4[0], r4[1], r4[2], r4[3]};
+}
+
+// Interior quad qi covers the same 4 columns of output rows y and y + 1
+// (y + 1 only while it is an interior row): three source rows serve both.
+template <int SH>
+__device__ __forceinline__ void stream_interior_quads(const Geometry &g, const LaneDir &ld, int64_t plane,
+                                                      int qi, int nqi, const float *__restrict__ in,
+                                                      float *__restrict__ out) {
+  const int r = qi / nqi;
+  const int y = 2 + 2 * r;
+  const int c = y * g.nx + 4 + 4 * (qi - r * nqi);
+  const float *b = in + plane + c - ld.td - 1 - SH;   // 16-byte aligned
+  const bool two = y + 1 <= g.ny - 3;
+  const f32x4 e0 = *reinterpret_cast<const f32x4 *>(b);
+  const f32x4 e1 = *reinterpret_cast<const f32x4 *>(b + 4);
+  const f32x4 f0 = *reinterpret_cast<const f32x4 *>(b - g.nx);
+  const f32x4 f1 = *reinterpret_cast<const f32x4 *>(b - g.nx + 4);
+  f32x4 h0 = e0, h1 = e1;
+  if (two) {
+    h0 = *reinterpret_cast<const f32x4 *>(b + g.nx);
+    h1 = *reinterpret_cast<const f32x4 *>(b + g.nx + 4);
+  }
+  quad_out<SH>(ld, e0, e1, f0, f1, out + plane + c);
+  if (two) quad_out<SH>(ld, h0, h1, e0, e1, out + plane + c + g.nx);
 }
 
 __global__ void __launch_bounds__(256) stream4_kernel(StepArgs a, QuadSplit qs, const float *__restrict__ in,
@@ -876,12 +895,12 @@ __global__ void __launch_bounds__(256) stream4_kernel(StepArgs a, QuadSplit qs, 
   const int64_t plane = ld.off + (int64_t)s * g.C;
   if (bx < qs.int_blocks) {
     const int qi = bx * 256 + (int)threadIdx.x;
-    if (qi >= qs.nqi * qs.nri) return;
+    if (qi >= qs.nqi * ((qs.nri + 1) >> 1)) return;
     switch ((-ld.ox0 - 1) & 3) {
-      case 0: stream_interior_quad<0>(g, ld, plane, qi, qs.nqi, in, out); break;
-      case 1: stream_interior_quad<1>(g, ld, plane, qi, qs.nqi, in, out); break;
-      case 2: stream_interior_quad<2>(g, ld, plane, qi, qs.nqi, in, out); break;
-      default: stream_interior_quad<3>(g, ld, plane, qi, qs.nqi, in, out); break;
+      case 0: stream_interior_quads<0>(g, ld, plane, qi, qs.nqi, in, out); break;
+      case 1: stream_interior_quads<1>(g, ld, plane, qi, qs.nqi, in, out); break;
+      case 2: stream_interior_quads<2>(g, ld, plane, qi, qs.nqi, in, out); break;
+      default: stream_interior_quads<3>(g, ld, plane, qi, qs.nqi, in, out); break;
     }
     return;
   }
@@ -1143,7 +1162,7 @@ hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStre
     if (qs.nqi == 0 || qs.nri == 0) qs.nqi = qs.nri = 0;
     const int64_t nint = (int64_t)qs.nqi * qs.nri;
     qs.nbord = (int)(a.geo.C - 4 * nint);
-    qs.int_blocks = (int)((nint + 255) / 256);
+    qs.int_blocks = (int)(((int64_t)qs.nqi * ((qs.nri + 1) / 2) + 255) / 256);   // two rows per thread
     qs.bpp = qs.int_blocks + (qs.nbord + 255) / 256;
     const int64_t blocks = (int64_t)qs.bpp * 4 * a.geo.n;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;

@@ -929,37 +929,52 @@ __global__ void __launch_bounds__(256) stream4_kernel(StepArgs a, QuadSplit qs, 
   out[plane + lc.c] = tap_sum(ld, v);
 }
 
-// Y(c) = alpha X(c) + beta M X(c) + dt_post J(c), X = S + dt_pre J, one
-// thread per cell, M in ABI order (row 4 d_out + s_out) read with uniform
-// (scalar) loads.
+// Y(c) = alpha X(c) + beta M X(c) + dt_post J(c), X = S + dt_pre J, on the
+// vector ALUs (the float32 path without matrix cores).  A wave takes 64
+// consecutive cells, one per lane, and a group of kValuRows consecutive
+// output rows (blockIdx.y): the lane accumulates its cell's rows in
+// registers while the matrix entries, the same for the whole wave, arrive
+// through scalar loads (M in ABI order, row 4 d_out + s_out, contiguous in
+// the input row).  Each input value is loaded once per row group.
+constexpr int kValuRows = 64;
+
 __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const float *__restrict__ M,
                                                            const float *__restrict__ in,
                                                            float *__restrict__ out) {
   const Geometry g = a.geo;
-  const int n = g.n, R = g.R;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.C;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const float al = a.alpha[c], be = a.beta[c], em = a.emis[c];
-    for (int dout = 0; dout < n; ++dout) {
-      float acc[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int di = 0; di < n; ++di) {
-        float xs[4];
+  const int R = g.R;   // 4 n, a multiple of 4
+  const int r0 = blockIdx.y * kValuRows;
+  const int nr = min(kValuRows, R - r0);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = c < g.C;
+  const int64_t cc = valid ? c : 0;
+  const float al = a.alpha[cc], be = a.beta[cc], em = a.emis[cc];
+  const float edt = a.dt_pre * em;
+  float acc[kValuRows];
 #pragma unroll
-        for (int si = 0; si < 4; ++si)
-          xs[si] = fmaf(a.dt_pre * em, a.jrow[4 * di + si], in[(int64_t)(4 * di + si) * g.C + c]);
-        const float *mrow = M + (int64_t)(4 * dout) * R + 4 * di;
+  for (int r = 0; r < kValuRows; ++r) acc[r] = 0.0f;
+  for (int k = 0; k < R; k += 4) {
+    float x[4];
 #pragma unroll
-        for (int so = 0; so < 4; ++so)
+    for (int i = 0; i < 4; ++i) x[i] = fmaf(edt, a.jrow[k + i], in[(int64_t)(k + i) * g.C + cc]);
+    const float *mk = M + (int64_t)r0 * R + k;
 #pragma unroll
-          for (int si = 0; si < 4; ++si) acc[so] = fmaf(mrow[so * R + si], xs[si], acc[so]);
+    for (int r = 0; r < kValuRows; ++r) {
+      if (r < nr) {
+        const f32x4 m = *reinterpret_cast<const f32x4 *>(mk + (int64_t)r * R);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[r] = fmaf(m[i], x[i], acc[r]);
       }
+    }
+  }
+  if (!valid) return;
 #pragma unroll
-      for (int so = 0; so < 4; ++so) {
-        const int64_t off = (int64_t)(4 * dout + so) * g.C + c;
-        const float jr = a.jrow[4 * dout + so];
-        const float xo = fmaf(a.dt_pre * em, jr, in[off]);
-        out[off] = fmaf(be, acc[so], fmaf(al, xo, a.dt_post * em * jr));
-      }
+  for (int r = 0; r < kValuRows; ++r) {
+    if (r < nr) {
+      const int64_t off = (int64_t)(r0 + r) * g.C + c;
+      const float jr = a.jrow[r0 + r];
+      const float xo = fmaf(edt, jr, in[off]);
+      out[off] = fmaf(be, acc[r], fmaf(al, xo, a.dt_post * em * jr));
     }
   }
 }
@@ -1176,7 +1191,8 @@ hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStre
 
 hipError_t launch_collide_valu(const StepArgs &a, const float *M_abi, const float *in, float *out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(collide_valu_kernel, dim3(grid_for(a.geo.C, 256)), dim3(256), 0, s, a, M_abi, in,
+  const dim3 grid((unsigned)((a.geo.C + 255) / 256), (unsigned)((a.geo.R + kValuRows - 1) / kValuRows));
+  hipLaunchKernelGGL(collide_valu_kernel, grid, dim3(256), 0, s, a, M_abi, in,
                      out);
   return hipGetLastError();
 }

@@ -226,25 +226,41 @@ __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g
 // Gathers the 16 values a lane owns: the streamed (GATHER) or direct state
 // with emission, or with REV the reverse-pulled adjoint field.  Group k (the
 // 4 Stokes rows of direction 8 t + 2 k + h) goes to dst[4k..4k+3], or with
-// TO_LDS straight to the lane's float32 LDS row at lds + 32 k bytes (rows
-// 8 k apart), so that it holds no registers afterwards.  Interior tiles run a
+// an LDS destination (put_group) as soon as it is combined, so that it holds
+// no registers afterwards.  Interior tiles run a
 // two-stage pipeline (group k's loads are issued before group k-1 is
 // combined: two groups, 32 loads, in flight); edge tiles take one group at a
 // time.
-template <bool TO_LDS>
-__device__ __forceinline__ void put_group(const float (&o)[4], float *dst, char *lds, int k) {
-  if (TO_LDS)
+// Where a combined group goes: registers dst[4k..4k+3], the float32 X tile
+// (lds = the lane's first row there, rows 8 k apart = 32 k bytes), or split
+// into a bf16 high part (lds = the lane's first row of the B tile, 16 k
+// bytes) and the low part v - high (lo_off bytes further: the low tile).
+enum { kPutReg = 0, kPutF32 = 1, kPutSplit = 2 };
+
+template <int PUT>
+__device__ __forceinline__ void put_group(const float (&o)[4], float *dst, char *lds, int k, int lo_off) {
+  if (PUT == kPutF32) {
     *reinterpret_cast<f32x4 *>(lds + 32 * k) = f32x4{o[0], o[1], o[2], o[3]};
-  else
+  } else if (PUT == kPutSplit) {
+    bf16x4 hv, lv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hv[j] = static_cast<__bf16>(o[j]);
+      lv[j] = static_cast<__bf16>(o[j] - static_cast<float>(hv[j]));
+    }
+    *reinterpret_cast<bf16x4 *>(lds + 16 * k) = hv;
+    *reinterpret_cast<bf16x4 *>(lds + lo_off + 16 * k) = lv;
+  } else {
 #pragma unroll
     for (int s = 0; s < 4; ++s) dst[4 * k + s] = o[s];
+  }
 }
 
-template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, bool TO_LDS>
+template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, int PUT>
 __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__restrict__ src,
                                              const Geometry &g, const LaneDir (&ld)[4],
                                              const LaneCell &lc, float emis_dt, float *dst,
-                                             char *lds, const float *jrow) {
+                                             char *lds, const float *jrow, int lo_off = 0) {
   if (!INTERIOR) {
     // edge tiles (a small share): one group at a time, which keeps the wrap
     // and ghost bookkeeping of only one direction live
@@ -253,7 +269,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
       float v[4][4], o[4];
       dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, v);
       dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, o, jrow);
-      put_group<TO_LDS>(o, dst, lds, k);
+      put_group<PUT>(o, dst, lds, k, lo_off);
       __builtin_amdgcn_sched_barrier(0);
     }
     return;
@@ -266,7 +282,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
     __builtin_amdgcn_sched_barrier(0);
     float o[4];
     dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, o, jrow);
-    put_group<TO_LDS>(o, dst, lds, k - 1);
+    put_group<PUT>(o, dst, lds, k - 1, lo_off);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -294,36 +310,48 @@ struct LdsLayout {
   int strideX;   // bytes per cell row of the float32 X tile
 };
 
-// LDS of a fused launch, per tile group (the W waves that share one 32-cell
-// tile): the B tile(s) [32 cells][Rpad rows] (row stride padded by 16 bytes
-// against bank conflicts of the 16-byte fragment reads), a float32 tile of
-// the forward operand X [32 cells][Rpad rows] that the gather writes and the
-// epilogue reads back (the B tile itself for the forward float32
-// contraction), and the cross-wave reduction scratch (fp16 scales, adjoint
-// per-cell sums).  After the groups, one copy of the emission rows.
+// LDS of a fused launch, per tile group (the W waves that share one tile of
+// 32 nb cells): the B tile(s) [32 nb cells][Rpad rows] (row stride padded by
+// 16 bytes against bank conflicts of the 16-byte fragment reads), a float32
+// tile of the forward operand X [32 nb cells][Rpad rows] that the gather
+// writes and the epilogue reads back (the B tile itself for the forward
+// float32 contraction), and the cross-wave reduction scratch (fp16 scales,
+// adjoint per-cell sums).  After the groups, one copy of the emission rows.
+// With nb = 2 and a bf16 contraction, X is not kept in float32: it is held
+// as a high part (the B tile) and a low part (a second tile of the same
+// shape) whose sum restores it to 2^-18.
 __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
-                                               bool f16, int ngroups = 1) {
+                                               bool f16, int ngroups = 1, int nb = 1) {
   LdsLayout L;
+  const bool xsplit = nb > 1 && esize == 2;
   int off = 0;
   L.b_off = off;
   L.strideB = Rpad * esize + 16;
-  L.tileB = 32 * L.strideB;
-  off += ntile * L.tileB;
+  L.tileB = 32 * nb * L.strideB;
+  off += (xsplit ? 2 : ntile) * L.tileB;
   // the forward float32 contraction reads X itself: the X tile is the B tile
   L.strideX = Rpad * 4 + 16;
-  if (adjoint || esize != 4) {
+  if (!xsplit && (adjoint || esize != 4)) {
     L.x_off = off;
-    off += 32 * L.strideX;
+    off += 32 * nb * L.strideX;
   } else {
     L.x_off = L.b_off;
   }
   L.red_off = off;
   const int nred = adjoint ? 3 : (f16 ? 1 : 0);
-  off += nred * W * 32 * 4;
+  off += nred * W * 32 * nb * 4;
   L.group = off;
   L.jrow_off = ngroups * off;
   L.total = L.jrow_off + Rpad * 4;
   return L;
+}
+
+// Cells per tile of a single-problem step: 64 (two 32-cell column blocks
+// that share every A fragment) for the float32 and bf16 forward steps with
+// more than 8 row tiles (n > 64); 32 otherwise (bf16x3 needs its float32 X
+// tile, fp16 the whole cell for its scale before it can split X).
+__host__ __device__ inline int step_nb(int W, int prec, bool adjoint) {
+  return (W > 8 && !adjoint && (prec == P_F32 || prec == P_BF16)) ? 2 : 1;
 }
 
 // Lane-record offset (before adding the lane) of the A fragments of K step s
@@ -346,10 +374,31 @@ struct TileLds {
   const float *s_jrow;
 };
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing>
+// Per-cell power-of-two scale of the fp16 operand: 2^(8 - e) for the largest
+// |value| m = f 2^e of the cell over all rows (all waves of the group, via
+// LDS scratch red[W][32]); 1 for an all-zero cell.
+__device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red, int wg, int W, int col, int h) {
+  float m = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(v[i]));
+  m = fmaxf(m, __shfl_xor(m, 32));
+  if (h == 0) red[wg * 32 + col] = m;
+  __syncthreads();
+  m = 0.0f;
+  for (int ww = 0; ww < W; ++ww) m = fmaxf(m, red[ww * 32 + col]);
+  int e = 0;
+  if (m > 0.0f) (void)frexpf(m, &e);
+  return (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
+}
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
                                            int64_t tile, bool active, int t, int wg, int W, int lane) {
+  static_assert(NB == 1 || (NB == 2 && !ADJ && (PREC == P_F32 || PREC == P_BF16)),
+                "two column blocks: forward float32 or bf16");
+  // bf16 contraction with two column blocks: X lives as high + low tiles
+  constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
   const int col = lane & 31;
   const int h = lane >> 5;
   char *s_b = ts.s_b;
@@ -357,46 +406,74 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   float *s_red = ts.s_red;
   const float *s_jrow = ts.s_jrow;
   (void)s_red;
-  const int c0 = active ? (int)(tile * 32) : 0;
+  (void)s_x;
+  const int c0 = active ? (int)(tile * (32 * NB)) : 0;
   float mv[ADJ ? 16 : 1];
-  float cscale = 1.0f;
+  float cscale[NB];
   (void)mv;
-  // this lane's rows in the LDS tiles: cell col, rows rbase + 8 q + (0..3)
+  // this lane's rows in the LDS tiles: cell 32 cb + col, rows rbase + 8 q + (0..3)
   const int rbase = t * 32 + h * 4;
-  char *xrow = s_x + col * L.strideX + rbase * 4;
 
-  // ---- 1. gather own rows ------------------------------------------------
-  // First cell of the tile (one 32-bit division per tile) and the lane's cell.
-  const int y0 = c0 / g.nx, x0 = c0 - y0 * g.nx;
-  LaneCell lc = lane_cell(g, c0, x0, y0, col);
-  lc.valid = lc.valid && active;
-  // per-cell coefficients, loaded now so that their latency is off the
-  // epilogue's path (invalid lanes read the tile's first cell)
-  const float al = a.alpha[lc.c], be = a.beta[lc.c], em = a.emis[lc.c];
-  const float emis_dt = a.dt_pre * em;
-  // A tile is interior when every tap of every cell lies inside the lattice
-  // (taps reach at most two cells either way); then no wrap or ghost is needed.
-  const int c_last = (int)((c0 + 32 < g.C ? (int64_t)c0 + 32 : g.C) - 1);
-  const int ty1 = c_last / g.nx, tx1 = c_last - ty1 * g.nx;
-  const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
-  // X (float32) goes to the X tile; the epilogue reads it back from there.
-  if (interior)
-    gather_field<false, GATHER, true, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
-  else
-    gather_field<false, GATHER, false, true, CKPT, true>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
-  if constexpr (ADJ) {
+  // ---- 1. gather own rows, per 32-cell column block --------------------------
+  LaneCell lcs[NB];
+  bool inter[NB];
+  float al[NB], be[NB], em[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    cscale[cb] = 1.0f;
+    // First cell of the block (one 32-bit division per block) and the lane's
+    // cell.  A block past the end of the lattice (in a ragged last tile)
+    // takes the tile's first cell with every lane invalid.
+    const int cbx = c0 + 32 * cb;
+    const bool inside = (int64_t)cbx < g.C;
+    const int base = inside ? cbx : c0;
+    const int y0 = base / g.nx, x0 = base - y0 * g.nx;
+    LaneCell lc = lane_cell(g, base, x0, y0, col);
+    lc.valid = lc.valid && active && inside;
+    lcs[cb] = lc;
+    // per-cell coefficients, loaded now so that their latency is off the
+    // epilogue's path (invalid lanes read the block's first cell)
+    al[cb] = a.alpha[lc.c];
+    be[cb] = a.beta[lc.c];
+    em[cb] = a.emis[lc.c];
+    const float emis_dt = a.dt_pre * em[cb];
+    // A block is interior when every tap of every cell lies inside the lattice
+    // (taps reach at most two cells either way); then no wrap or ghost is needed.
+    const int c_last = (int)((base + 32 < g.C ? (int64_t)base + 32 : g.C) - 1);
+    const int ty1 = c_last / g.nx, tx1 = c_last - ty1 * g.nx;
+    const bool interior = ty1 == y0 && y0 >= 2 && y0 <= g.ny - 3 && x0 >= 2 && tx1 <= g.nx - 3;
+    inter[cb] = interior;
+    if constexpr (XSPLIT) {
+      // each combined group goes straight to the high and low tiles
+      char *brow = s_b + (32 * cb + col) * L.strideB + rbase * 2;
+      if (interior)
+        gather_field<false, GATHER, true, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, emis_dt, nullptr, brow, s_jrow,
+                                                                   L.tileB);
+      else
+        gather_field<false, GATHER, false, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, emis_dt, nullptr, brow, s_jrow,
+                                                                    L.tileB);
+    } else {
+      // X (float32) goes to the X tile; the epilogue reads it back from there.
+      char *xrow = s_x + (32 * cb + col) * L.strideX + rbase * 4;
+      if (interior)
+        gather_field<false, GATHER, true, true, CKPT, kPutF32>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
+      else
+        gather_field<false, GATHER, false, true, CKPT, kPutF32>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
+    }
     __builtin_amdgcn_sched_barrier(0);
-    if (interior)
-      gather_field<true, true, true, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
+  }
+  if constexpr (ADJ) {
+    if (inter[0])
+      gather_field<true, true, true, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
     else
-      gather_field<true, true, false, false, false, false>(a, a.lam_next, g, ld, lc, 0.0f, mv, nullptr, s_jrow);
+      gather_field<true, true, false, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
   }
 
   // ---- 3a. first A fragments in flight ---------------------------------------
   // A is the same for every tile; an L2 round trip for one K step is several
   // times longer than that step's MFMAs, so a ring of kRing steps is kept in
   // flight, started here to overlap the B conversion and the barrier.
-    constexpr int kStep = PREC == P_F32 ? 8 : 16;
+  constexpr int kStep = PREC == P_F32 ? 8 : 16;
   const int nk = (tr.khi - tr.klo) / kStep;
   const uint4 *A = a.frag + lane;
   const uint4 *Alo = a.frag_lo + lane;
@@ -408,55 +485,46 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   }
 
   // ---- 2. B operand: the contraction input in its precision ------------------
-  // forward: X (already in place for float32); adjoint: mu.
-  if (ADJ || PREC != P_F32) {
-    float v[16];
+  // forward: X (already in place for float32 and for the split tiles); adjoint: mu.
+  if constexpr (NB == 1) {
+    if (ADJ || PREC != P_F32) {
+      char *xrow = s_x + col * L.strideX + rbase * 4;
+      float v[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      f32x4 x4;
-      if (ADJ)
-        x4 = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
-      else
-        x4 = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
+      for (int q = 0; q < 4; ++q) {
+        f32x4 x4;
+        if (ADJ)
+          x4 = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
+        else
+          x4 = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) v[4 * q + j] = x4[j];
-    }
-    // per-cell power-of-two scale for fp16 operands (max over all rows)
-    if (PREC == P_F16) {
-      float m = 0.0f;
+        for (int j = 0; j < 4; ++j) v[4 * q + j] = x4[j];
+      }
+      // per-cell power-of-two scale for fp16 operands (max over all rows)
+      if (PREC == P_F16) cscale[0] = f16_cell_scale(v, s_red, wg, W, col, h);
+      char *brow = s_b + col * L.strideB;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) m = fmaxf(m, fabsf(v[i]));
-      m = fmaxf(m, __shfl_xor(m, 32));
-      if (h == 0) s_red[wg * 32 + col] = m;
-      __syncthreads();
-      m = 0.0f;
-      for (int ww = 0; ww < W; ++ww) m = fmaxf(m, s_red[ww * 32 + col]);
-      int e = 0;
-      if (m > 0.0f) (void)frexpf(m, &e);
-      cscale = (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
-    }
-    char *brow = s_b + col * L.strideB;
+      for (int q = 0; q < 4; ++q) {
+        const int r0 = rbase + q * 8;
+        if (PREC == P_F32) {
+          *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+        } else if (PREC == P_BF16 || PREC == P_BF16X3) {
+          bf16x4 hv;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r0 = rbase + q * 8;
-      if (PREC == P_F32) {
-        *reinterpret_cast<f32x4 *>(brow + r0 * 4) = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
-      } else if (PREC == P_BF16 || PREC == P_BF16X3) {
-        bf16x4 hv;
+          for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[4 * q + j]);
+          *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hv;
+          if (PREC == P_BF16X3) {
+            bf16x4 lo;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) hv[j] = static_cast<__bf16>(v[4 * q + j]);
-        *reinterpret_cast<bf16x4 *>(brow + r0 * 2) = hv;
-        if (PREC == P_BF16X3) {
-          bf16x4 lo;
+            for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[4 * q + j] - static_cast<float>(hv[j]));
+            *reinterpret_cast<bf16x4 *>(brow + L.tileB + r0 * 2) = lo;
+          }
+        } else {
+          f16x4 hv;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) lo[j] = static_cast<__bf16>(v[4 * q + j] - static_cast<float>(hv[j]));
-          *reinterpret_cast<bf16x4 *>(brow + L.tileB + r0 * 2) = lo;
+          for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[4 * q + j] * cscale[0]);
+          *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
         }
-      } else {
-        f16x4 hv;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) hv[j] = static_cast<_Float16>(v[4 * q + j] * cscale);
-        *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
       }
     }
   }
@@ -464,8 +532,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 
   // ---- 3. matrix-core contraction over the tile's K range ------------------
   // Steps are taken in groups of kRing; steps past nk multiply the zero block
-  // with the last valid B row (finite), adding nothing.
-  f32x16 acc = f32x16{0};
+  // with the last valid B row (finite), adding nothing.  Every A fragment
+  // serves the NB column blocks.
+  f32x16 acc[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) acc[cb] = f32x16{0};
   const int nsteps = (nk + kRing - 1) / kRing * kRing;
   for (int s0 = 0; s0 < nsteps; s0 += kRing) {
 #pragma unroll
@@ -475,29 +546,33 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       ring[j] = A[frag_rec(tr, s + kRing, nk)];
       if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
       const int kb = tr.klo + kStep * min(s, nk - 1);
-      if (PREC == P_F32) {
-        const f32x4 av = __builtin_bit_cast(f32x4, araw);
-        const f32x4 bv = *reinterpret_cast<const f32x4 *>(s_b + col * L.strideB + (kb + 4 * h) * 4);
-        acc = mfma_step_f32(av[0], bv[0], acc);
-        acc = mfma_step_f32(av[1], bv[1], acc);
-        acc = mfma_step_f32(av[2], bv[2], acc);
-        acc = mfma_step_f32(av[3], bv[3], acc);
-      } else {
-        const char *bp = s_b + col * L.strideB + (kb + 8 * h) * 2;
-        if (PREC == P_F16) {
-          const f16x8 av = __builtin_bit_cast(f16x8, araw);
-          const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const char *bcell = s_b + (32 * cb + col) * L.strideB;
+        if (PREC == P_F32) {
+          const f32x4 av = __builtin_bit_cast(f32x4, araw);
+          const f32x4 bv = *reinterpret_cast<const f32x4 *>(bcell + (kb + 4 * h) * 4);
+          acc[cb] = mfma_step_f32(av[0], bv[0], acc[cb]);
+          acc[cb] = mfma_step_f32(av[1], bv[1], acc[cb]);
+          acc[cb] = mfma_step_f32(av[2], bv[2], acc[cb]);
+          acc[cb] = mfma_step_f32(av[3], bv[3], acc[cb]);
         } else {
-          const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-          const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
-          if (PREC == P_BF16X3) {
-            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
-            const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc, 0, 0, 0);
+          const char *bp = bcell + (kb + 8 * h) * 2;
+          if (PREC == P_F16) {
+            const f16x8 av = __builtin_bit_cast(f16x8, araw);
+            const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[cb], 0, 0, 0);
+          } else {
+            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
+            if (PREC == P_BF16X3) {
+              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+              const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
+              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc[cb], 0, 0, 0);
+              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc[cb], 0, 0, 0);
+            }
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[cb], 0, 0, 0);
           }
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
         }
       }
     }
@@ -505,23 +580,39 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 
   // ---- 4. epilogue -------------------------------------------------------------
   float part[3] = {0.0f, 0.0f, 0.0f};
-  if (lc.valid) {
-    const int c = lc.c;
-    const float unscale = a.a_scale_inv / cscale;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    if (!lcs[cb].valid) continue;
+    const int c = lcs[cb].c;
+    const float unscale = a.a_scale_inv / cscale[cb];
+    const char *xrow = s_x + (32 * cb + col) * L.strideX + rbase * 4;
+    const char *brow = s_b + (32 * cb + col) * L.strideB;
+    (void)xrow;
+    (void)brow;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (ld[q].d >= g.n) continue;
       const f32x4 jp = *reinterpret_cast<const f32x4 *>(s_jrow + 4 * ld[q].d);
-      const f32x4 xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
+      f32x4 xq;
+      if constexpr (XSPLIT) {
+        // X = high + low (the sum is exact in float32)
+        const int r0 = rbase + q * 8;
+        const bf16x4 hv = *reinterpret_cast<const bf16x4 *>(brow + r0 * 2);
+        const bf16x4 lv = *reinterpret_cast<const bf16x4 *>(brow + L.tileB + r0 * 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xq[j] = static_cast<float>(hv[j]) + static_cast<float>(lv[j]);
+      } else {
+        xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int i = 4 * q + s;
-        const float prod = acc[i] * unscale;
+        const float prod = acc[cb][i] * unscale;
         float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
         if (!ADJ) {
-          *o = fmaf(be, prod, fmaf(al, xq[s], a.dt_post * em * jp[s]));
+          *o = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
         } else {
-          const float lam = fmaf(be, prod, al * mv[i]);
+          const float lam = fmaf(be[cb], prod, al[cb] * mv[i]);
           *o = lam;
           part[0] = fmaf(mv[i], xq[s], part[0]);
           part[1] = fmaf(prod, xq[s], part[1]);
@@ -552,7 +643,13 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   __syncthreads();
 }
 
-template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT>
+// A-fragment ring depth: 4 steps for blocks of up to 4 waves; for the larger
+// blocks (n > 32) the register budget of 16 waves per CU leaves 2 steps for
+// the 16-bit forward contractions and 1 otherwise.
+template <int PREC, bool ADJ, int MAXW, int NB>
+constexpr int kFusedRing = MAXW <= 4 ? 4 : ((!ADJ && PREC != P_F32 && PREC != P_BF16X3) ? 2 : 1);
+
+template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB>
 __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
   extern __shared__ __align__(16) char smem[];
@@ -561,7 +658,7 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int h = lane >> 5;
-  const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
+  const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
   float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
   for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
   __syncthreads();
@@ -591,7 +688,8 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
     // which would not fit in VGPRs, without holding a second copy.
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    fused_tile<PREC, GATHER, ADJ, CKPT, (MAXW > 4 ? 1 : 4)>(a, g, L, ts, tr, ldk, tile, true, t, t, W, lane);
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB>(a, g, L, ts, tr, ldk, tile, true, t, t, W,
+                                                                           lane);
   }
 }
 
@@ -740,28 +838,30 @@ hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t n
   return hipErrorInvalidValue;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT>
-hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB>
+hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
-  const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16);
-  const int64_t ntiles = (a.geo.C + 31) / 32;
+  const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
+  const int64_t ntiles = (a.geo.C + 32 * NB - 1) / (32 * NB);
   int64_t grid = ntiles;
   const int64_t grid_limit = (int64_t)cu_count * std::max(1, std::min(8, 16 / W));
   if (grid > grid_limit) grid = grid_limit;
   if (grid >= 8) grid &= ~7LL;
   if (grid < 1) grid = 1;
-  if (W <= 4) {
-    auto k = fused_kernel<PREC, GATHER, ADJ, 4, CKPT>;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
-  } else {
-    auto k = fused_kernel<PREC, GATHER, ADJ, 16, CKPT>;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
-  }
+  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB>;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
   return hipGetLastError();
+}
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
+  if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1>(a, W, s, cu_count);
+  if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
+    if (step_nb(W, PREC, ADJ) == 2) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 2>(a, W, s, cu_count);
+  }
+  return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1>(a, W, s, cu_count);
 }
 
 // The checkpointing variant only exists for the forward gather (the step that
@@ -1156,7 +1256,8 @@ size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint) {
   if (g.Rpad / 32 > 16) return (size_t)-1;
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
-  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, g.Rpad / 32, adjoint, prec == P_F16);
+  const int W = g.Rpad / 32;
+  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, W, adjoint, prec == P_F16, 1, step_nb(W, prec, adjoint));
   return (size_t)L.total;
 }
 

@@ -42,6 +42,8 @@ FORWARD_CASES = [
     ("beam512", dict(nx=33, ny=29, n_zen=2, n_az=8), 50, "random"),  # n = 16
     ("beam512", dict(nx=21, ny=26, n_zen=4, n_az=16), 30, "random"),  # n = 64
     ("prec1024", dict(nx=19, ny=22), 25, "random"),                   # n = 128
+    ("prec1024", dict(nx=16, ny=18), 20, "random"),   # 288 cells: the last 64-cell tile's second block is empty
+    ("prec1024", dict(nx=96, ny=20), 20, "random"),   # rows of three 32-cell blocks, interior blocks
     ("adjoint256", dict(nx=40, ny=35), 40, "zero"),                   # emission everywhere
 ]
 

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "rt_kernels.h"
@@ -843,14 +844,29 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
   using T = PrecTraits<PREC>;
   const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
   const int64_t ntiles = (a.geo.C + 32 * NB - 1) / (32 * NB);
-  int64_t grid = ntiles;
-  const int64_t grid_limit = (int64_t)cu_count * std::max(1, std::min(8, 16 / W));
-  if (grid > grid_limit) grid = grid_limit;
-  if (grid >= 8) grid &= ~7LL;
-  if (grid < 1) grid = 1;
   auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
+  // persistent grid: as many blocks as are resident at once (registers and
+  // LDS of this instantiation), so that no block starts after others finish;
+  // remembered per (waves, LDS bytes)
+  static std::atomic<uint64_t> memo{0};
+  const uint64_t key = ((uint64_t)W << 32) | (uint64_t)L.total;
+  uint64_t m = memo.load(std::memory_order_relaxed);
+  int occ;
+  if (m != 0 && (m >> 8) == key) {
+    occ = (int)(m & 0xff);
+  } else {
+    occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, 64 * W, L.total);
+    if (e != hipSuccess) return e;
+    if (occ < 1) return hipErrorInvalidConfiguration;
+    occ = std::min(occ, 255);
+    memo.store((key << 8) | (uint64_t)occ, std::memory_order_relaxed);
+  }
+  int64_t grid = std::min<int64_t>(ntiles, (int64_t)cu_count * occ);
+  if (grid >= 8) grid &= ~7LL;
+  if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
   return hipGetLastError();
 }

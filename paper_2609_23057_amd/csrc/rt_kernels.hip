@@ -348,11 +348,13 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
 }
 
 // Cells per tile of a single-problem step: 64 (two 32-cell column blocks
-// that share every A fragment) for the float32 and bf16 forward steps with
-// more than 8 row tiles (n > 64); 32 otherwise (bf16x3 needs its float32 X
-// tile, fp16 the whole cell for its scale before it can split X).
+// that share every A fragment) for the float32 forward step and, with more
+// than 8 row tiles (n > 64), the bf16 forward step; 32 otherwise (bf16x3
+// needs its float32 X tile, fp16 the whole cell for its scale before it can
+// split X, and bf16 at n <= 64 keeps the spectral batch's X arithmetic).
+// The float32 64-cell tile performs the 32-cell tile's arithmetic per cell.
 __host__ __device__ inline int step_nb(int W, int prec, bool adjoint) {
-  return (W > 8 && !adjoint && (prec == P_F32 || prec == P_BF16)) ? 2 : 1;
+  return (!adjoint && ((W > 8 && prec == P_BF16) || prec == P_F32)) ? 2 : 1;
 }
 
 // Lane-record offset (before adding the lane) of the A fragments of K step s
@@ -464,10 +466,21 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     __builtin_amdgcn_sched_barrier(0);
   }
   if constexpr (ADJ) {
-    if (inter[0])
-      gather_field<true, true, true, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
-    else
-      gather_field<true, true, false, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
+    if constexpr (PREC == P_F32) {
+      // the float32 B tile is mu itself: gathered straight into it
+      char *murow = s_b + col * L.strideB + rbase * 4;
+      if (inter[0])
+        gather_field<true, true, true, false, false, kPutF32>(a, a.lam_next, g, ld, lcs[0], 0.0f, nullptr, murow,
+                                                                s_jrow);
+      else
+        gather_field<true, true, false, false, false, kPutF32>(a, a.lam_next, g, ld, lcs[0], 0.0f, nullptr, murow,
+                                                                 s_jrow);
+    } else {
+      if (inter[0])
+        gather_field<true, true, true, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
+      else
+        gather_field<true, true, false, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
+    }
   }
 
   // ---- 3a. first A fragments in flight ---------------------------------------
@@ -486,9 +499,10 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   }
 
   // ---- 2. B operand: the contraction input in its precision ------------------
-  // forward: X (already in place for float32 and for the split tiles); adjoint: mu.
+  // forward: X, adjoint: mu (both already in place for float32; X also for the
+  // split tiles).
   if constexpr (NB == 1) {
-    if (ADJ || PREC != P_F32) {
+    if (PREC != P_F32) {
       char *xrow = s_x + col * L.strideX + rbase * 4;
       float v[16];
 #pragma unroll
@@ -605,6 +619,14 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       } else {
         xq = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
       }
+      // adjoint: mu of these 4 rows (for float32 it is the B tile itself)
+      f32x4 mu = f32x4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (ADJ) {
+        if constexpr (PREC == P_F32)
+          mu = *reinterpret_cast<const f32x4 *>(brow + (rbase + q * 8) * 4);
+        else
+          mu = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int i = 4 * q + s;
@@ -613,11 +635,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
         if (!ADJ) {
           *o = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
         } else {
-          const float lam = fmaf(be[cb], prod, al[cb] * mv[i]);
+          const float lam = fmaf(be[cb], prod, al[cb] * mu[s]);
           *o = lam;
-          part[0] = fmaf(mv[i], xq[s], part[0]);
+          part[0] = fmaf(mu[s], xq[s], part[0]);
           part[1] = fmaf(prod, xq[s], part[1]);
-          part[2] = fmaf(fmaf(a.dt_pre, lam, a.dt_post * mv[i]), jp[s], part[2]);
+          part[2] = fmaf(fmaf(a.dt_pre, lam, a.dt_post * mu[s]), jp[s], part[2]);
         }
       }
     }
@@ -873,7 +895,10 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
-  if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1>(a, W, s, cu_count);
+  if (W <= 4) {
+    if constexpr (!ADJ && PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2>(a, W, s, cu_count);
+    return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1>(a, W, s, cu_count);
+  }
   if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
     if (step_nb(W, PREC, ADJ) == 2) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 2>(a, W, s, cu_count);
   }

@@ -580,7 +580,7 @@ struct rt_batch {
   int64_t nitems = 0;
   int prec = 0;
   int lds = 0;
-  int grid = 0;
+  int cu_count = 0;   // compute units of the device (each launch sizes its own grid)
   bool graph_mode = false;
   hipStream_t cap = nullptr;   // private stream graphs are recorded on (the caller's may be the null stream)
   struct Graph {
@@ -615,7 +615,7 @@ struct rt_batch {
                "batch descriptors");
   }
   rt_status step(const BatchChan *d, bool adjoint, bool gather, bool ckpt, const BatchSel &sel) {
-    return hip(launch_batch_step(d, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds, grid, stream),
+    return hip(launch_batch_step(d, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds, cu_count, stream),
                "batch step");
   }
   // Records body() into a graph unless the cached one has the same key, then
@@ -797,7 +797,7 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
   int per_cu = 0;
   st = b->hip(prepare_batch(b->prec, b->lds, &per_cu), "prepare batch kernels");
   if (st == RT_OK) {
-    b->grid = (int)std::min<int64_t>(b->nitems, (int64_t)b->ch[0]->cu_count * per_cu);
+    b->cu_count = b->ch[0]->cu_count;
     st = b->upload(b->d_run, b->h_run);
   }
   if (st == RT_OK) st = b->upload(b->d_rec, b->h_rec);

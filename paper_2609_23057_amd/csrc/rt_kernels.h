@@ -84,9 +84,10 @@ size_t batch_lds_bytes(int Rpad, int prec, bool adjoint);
 // kernels for the given LDS size (called once, before any stream capture).
 hipError_t prepare_batch(int prec, int lds_bytes, int *blocks_per_cu);
 
-// One batched fused step (forward or adjoint) over every channel's tiles.
+// One batched fused step (forward or adjoint) over every channel's tiles; the
+// persistent grid is cu_count x the resident blocks of that instantiation.
 hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
-                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int grid,
+                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s);
 
 // Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +

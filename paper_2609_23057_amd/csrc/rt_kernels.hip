@@ -666,6 +666,26 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   __syncthreads();
 }
 
+// Resident blocks per CU of kernel k at this block size and LDS (registers
+// and LDS of that instantiation), remembered in memo (one per instantiation)
+// for the last (threads, LDS) asked.
+inline hipError_t resident_blocks(const void *k, int threads, int lds, std::atomic<uint64_t> &memo, int *occ) {
+  const uint64_t key = ((uint64_t)threads << 32) | (uint64_t)(uint32_t)lds;
+  const uint64_t m = memo.load(std::memory_order_relaxed);
+  if (m != 0 && (m >> 8) == key) {
+    *occ = (int)(m & 0xff);
+    return hipSuccess;
+  }
+  int o = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, threads, lds);
+  if (e != hipSuccess) return e;
+  if (o < 1) return hipErrorInvalidConfiguration;
+  o = std::min(o, 255);
+  memo.store((key << 8) | (uint64_t)o, std::memory_order_relaxed);
+  *occ = o;
+  return hipSuccess;
+}
+
 // A-fragment ring depth: 4 steps for blocks of up to 4 waves; for the larger
 // blocks (n > 32) the register budget of 16 waves per CU leaves 2 steps for
 // the 16-bit forward contractions and 1 otherwise.
@@ -720,8 +740,9 @@ __global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t nt
 //
 // One launch advances every channel of the batch by one step.  The work
 // queue is the channels' tiles in channel order, a work item being one tile
-// per tile group of the block; each block takes a contiguous run of items,
-// so it changes channel rarely.  On a change the block reloads the channel's
+// per tile group of the block; the blocks of an XCD take every per-th item of
+// one contiguous eighth of the queue, so each block changes channel only as
+// often as its eighth does.  On a change the block reloads the channel's
 // descriptor (scalar loads), its emission rows into LDS and each lane's
 // direction data.
 
@@ -733,8 +754,16 @@ __global__ void __launch_bounds__(64 * kBatchWaves) batch_kernel(const BatchChan
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t i0 = nitems * blockIdx.x / gridDim.x;
-  const int64_t i1 = nitems * (blockIdx.x + 1) / gridDim.x;
+  // XCD-aware order, as in the single-problem kernel: blocks are dispatched
+  // round-robin over the 8 XCDs; the blocks of one XCD interleave over one
+  // contiguous eighth of the queue, so neighbouring tiles (and the halo rows
+  // they share) are processed together in that XCD's L2.
+  const int G = gridDim.x;
+  const int chunks = (G >= 8 && (G & 7) == 0) ? 8 : 1;
+  const int per = G / chunks;
+  const int64_t kq = blockIdx.x % chunks;
+  const int64_t i0 = nitems * kq / chunks + blockIdx.x / chunks;
+  const int64_t i1 = nitems * (kq + 1) / chunks;
 
   int ch = -1;
   int64_t next0 = 0;   // first item of the next channel
@@ -746,7 +775,7 @@ __global__ void __launch_bounds__(64 * kBatchWaves) batch_kernel(const BatchChan
   TileLds ts{};
   TileRange tr{};
   LaneDir ld[4];
-  for (int64_t it = i0; it < i1; ++it) {
+  for (int64_t it = i0; it < i1; it += per) {
     if (ch < 0 || it >= next0) {
       int c = ch < 0 ? 0 : ch;
       while (c + 1 < nchan && chans[c + 1].item0 <= it) ++c;
@@ -793,13 +822,21 @@ size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint) {
   return (size_t)lds_layout(Rpad, esize, ntile, W, adjoint, prec == P_F16, kBatchWaves / W).total;
 }
 
+// Occupancy of one batch instantiation; prepare_batch fills the memo before
+// any launch, so a launch under stream capture makes no runtime query.
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+hipError_t batch_blocks_per_cu(int lds_bytes, int *occ) {
+  static std::atomic<uint64_t> memo{0};
+  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT>, 64 * kBatchWaves, lds_bytes, memo, occ);
+}
+
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t prepare_batch_k(int lds_bytes, int *occ) {
   auto k = batch_kernel<PREC, GATHER, ADJ, CKPT>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return e;
   int o = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)k, 64 * kBatchWaves, lds_bytes);
+  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT>(lds_bytes, &o);
   if (e != hipSuccess) return e;
   *occ = std::min(*occ, o);
   return hipSuccess;
@@ -828,35 +865,41 @@ hipError_t prepare_batch_impl(int prec, int lds_bytes, int *blocks_per_cu) {
   return hipSuccess;
 }
 
-template <int PREC>
-hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
-                          const BatchSel &sel, int lds_bytes, int grid, hipStream_t s) {
-  const dim3 gd((unsigned)grid), bd(64 * kBatchWaves);
-  if (adjoint) {
-    if (gather)
-      hipLaunchKernelGGL((batch_kernel<PREC, true, true, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
-    else
-      hipLaunchKernelGGL((batch_kernel<PREC, false, true, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
-  } else if (ckpt) {
-    hipLaunchKernelGGL((batch_kernel<PREC, true, false, true>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
-  } else if (gather) {
-    hipLaunchKernelGGL((batch_kernel<PREC, true, false, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
-  } else {
-    hipLaunchKernelGGL((batch_kernel<PREC, false, false, false>), gd, bd, lds_bytes, s, d_chans, nchan, nitems, sel);
-  }
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+hipError_t launch_batch_k(const BatchChan *d_chans, int nchan, int64_t nitems, const BatchSel &sel, int lds_bytes,
+                          int cu_count, hipStream_t s) {
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT>;
+  // persistent grid sized by this instantiation's own occupancy
+  int occ = 0;
+  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT>(lds_bytes, &occ);
+  if (e != hipSuccess) return e;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)cu_count * occ));
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * kBatchWaves), lds_bytes, s, d_chans, nchan, nitems, sel);
   return hipGetLastError();
 }
 
+template <int PREC>
+hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
+                          const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
+  if (adjoint) {
+    if (gather) return launch_batch_k<PREC, true, true, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    return launch_batch_k<PREC, false, true, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  }
+  if (ckpt) return launch_batch_k<PREC, true, false, true>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  if (gather) return launch_batch_k<PREC, true, false, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  return launch_batch_k<PREC, false, false, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+}
+
 hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
-                                  bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int grid,
+                                  bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
                                   hipStream_t s) {
   if (ckpt && (adjoint || !gather)) return hipErrorInvalidValue;
-  if (grid < 1 || nitems < 1) return hipErrorInvalidValue;
+  if (cu_count < 1 || nitems < 1) return hipErrorInvalidValue;
   switch (prec) {
-    case P_F32: return launch_batch_p<P_F32>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
-    case P_BF16: return launch_batch_p<P_BF16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
-    case P_F16: return launch_batch_p<P_F16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
-    case P_BF16X3: return launch_batch_p<P_BF16X3>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+    case P_F32: return launch_batch_p<P_F32>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_BF16: return launch_batch_p<P_BF16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_F16: return launch_batch_p<P_F16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_BF16X3: return launch_batch_p<P_BF16X3>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
   }
   return hipErrorInvalidValue;
 }
@@ -869,23 +912,12 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
   auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
-  // persistent grid: as many blocks as are resident at once (registers and
-  // LDS of this instantiation), so that no block starts after others finish;
-  // remembered per (waves, LDS bytes)
+  // persistent grid: as many blocks as are resident at once, so that no block
+  // starts after others finish
   static std::atomic<uint64_t> memo{0};
-  const uint64_t key = ((uint64_t)W << 32) | (uint64_t)L.total;
-  uint64_t m = memo.load(std::memory_order_relaxed);
-  int occ;
-  if (m != 0 && (m >> 8) == key) {
-    occ = (int)(m & 0xff);
-  } else {
-    occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, 64 * W, L.total);
-    if (e != hipSuccess) return e;
-    if (occ < 1) return hipErrorInvalidConfiguration;
-    occ = std::min(occ, 255);
-    memo.store((key << 8) | (uint64_t)occ, std::memory_order_relaxed);
-  }
+  int occ = 0;
+  e = resident_blocks((const void *)k, 64 * W, L.total, memo, &occ);
+  if (e != hipSuccess) return e;
   int64_t grid = std::min<int64_t>(ntiles, (int64_t)cu_count * occ);
   if (grid >= 8) grid &= ~7LL;
   if (grid < 1) grid = 1;
@@ -1288,9 +1320,9 @@ hipError_t prepare_batch(int prec, int lds_bytes, int *blocks_per_cu) {
 }
 
 hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
-                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int grid,
+                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s) {
-  return launch_batch_step_impl(d_chans, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds_bytes, grid, s);
+  return launch_batch_step_impl(d_chans, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
 }
 
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint) {

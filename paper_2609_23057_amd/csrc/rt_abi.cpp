@@ -29,7 +29,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   // byte offsets into the workspace
   size_t tables, tables_bytes;   // uploaded host tables (rows, taps, tiles, fragments, M)
-  size_t taps, outdirs, M_abi;
+  size_t taps, outdirs, MT;   // MT: float32 M transposed, for the plain path
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
@@ -87,7 +87,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk) {
   L.tables = off;
   L.taps = take(hp.n * sizeof(DirTaps));
   L.outdirs = take(4 * hp.n * sizeof(int32_t));
-  L.M_abi = take((size_t)hp.R * hp.R * sizeof(float));
+  L.MT = take((size_t)hp.R * hp.R * sizeof(float));
   L.tiles_fwd32 = take(ntile * sizeof(TileRange));
   L.tiles_adj32 = take(ntile * sizeof(TileRange));
   L.tiles_fwd = take(ntile * sizeof(TileRange));
@@ -340,9 +340,11 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     c->nout[e] = k;
   }
   put(c->L.outdirs, od.data(), od.size() * sizeof(int32_t));
-  std::vector<float> M32(hp.M.size());
-  for (size_t i = 0; i < M32.size(); ++i) M32[i] = (float)hp.M[i];
-  put(c->L.M_abi, M32.data(), M32.size() * sizeof(float));
+  // plain path: M^T in float32, row k (input row) holds M[r][k] for all output rows r
+  std::vector<float> MT(hp.M.size());
+  for (int r = 0; r < hp.R; ++r)
+    for (int k = 0; k < hp.R; ++k) MT[(size_t)k * hp.R + r] = (float)hp.M[(size_t)r * hp.R + k];
+  put(c->L.MT, MT.data(), MT.size() * sizeof(float));
   put(c->L.tiles_fwd32, c->pk.t_fwd32.data(), c->pk.t_fwd32.size() * sizeof(TileRange));
   put(c->L.tiles_adj32, c->pk.t_adj32.data(), c->pk.t_adj32.size() * sizeof(TileRange));
   put(c->L.tiles_fwd, c->pk.t_fwd.data(), c->pk.t_fwd.size() * sizeof(TileRange));
@@ -423,7 +425,7 @@ static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, f
 static rt_status plain_step(rt_ctx *c, const float *S_in, float *S_out) {
   StepArgs a = c->args(false);
   float *Y = c->at<float>(c->L.Ya);
-  rt_status st = c->hip(launch_collide_valu(a, c->at<float>(c->L.M_abi), S_in, Y, c->stream), "collide");
+  rt_status st = c->hip(launch_collide_valu(a, c->at<float>(c->L.MT), S_in, Y, c->stream), "collide");
   if (st == RT_OK) st = c->hip(launch_stream(a, Y, S_out, c->stream), "stream");
   return st;
 }

@@ -102,7 +102,7 @@ hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStre
 
 // Plain float32 path: separate streaming and vector-ALU collision.
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s);
-hipError_t launch_collide_valu(const StepArgs &a, const float *M_abi, const float *in, float *out,
+hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,
                                hipStream_t s);
 
 // Per-cell coefficients from tau/albedo; counts invalid cells into *bad.

@@ -44,6 +44,8 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// 16 floats at 16-byte alignment (rows of a matrix whose stride is a multiple of 4 floats)
+typedef float f32x16u __attribute__((ext_vector_type(16), aligned(16)));
 
 namespace {
 
@@ -1107,11 +1109,12 @@ __global__ void __launch_bounds__(256) stream4_kernel(StepArgs a, QuadSplit qs, 
 // consecutive cells, one per lane, and a group of kValuRows consecutive
 // output rows (blockIdx.y): the lane accumulates its cell's rows in
 // registers while the matrix entries, the same for the whole wave, arrive
-// through scalar loads (M in ABI order, row 4 d_out + s_out, contiguous in
-// the input row).  Each input value is loaded once per row group.
-constexpr int kValuRows = 64;
+// through scalar loads from M^T (row k = input row 4 d_in + s_in, contiguous
+// over the output rows), so that one scalar load serves several rows.  Each
+// input value is loaded once per row group.
+constexpr int kValuRows = 32;
 
-__global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const float *__restrict__ M,
+__global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const float *__restrict__ MT,
                                                            const float *__restrict__ in,
                                                            float *__restrict__ out) {
   const Geometry g = a.geo;
@@ -1126,17 +1129,24 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
   float acc[kValuRows];
 #pragma unroll
   for (int r = 0; r < kValuRows; ++r) acc[r] = 0.0f;
-  for (int k = 0; k < R; k += 4) {
-    float x[4];
+  for (int k = 0; k < R; ++k) {
+    const float x = fmaf(edt, a.jrow[k], in[(int64_t)k * g.C + cc]);
+    const float *mk = MT + (int64_t)k * R + r0;   // M[r0 + r][k] = mk[r]
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = fmaf(edt, a.jrow[k + i], in[(int64_t)(k + i) * g.C + cc]);
-    const float *mk = M + (int64_t)r0 * R + k;
+    for (int r = 0; r < kValuRows; r += 16) {
+      if (r + 16 <= nr) {
+        const f32x16u m = *reinterpret_cast<const f32x16u *>(mk + r);
 #pragma unroll
-    for (int r = 0; r < kValuRows; ++r) {
-      if (r < nr) {
-        const f32x4 m = *reinterpret_cast<const f32x4 *>(mk + (int64_t)r * R);
+        for (int i = 0; i < 16; ++i) acc[r + i] = fmaf(m[i], x, acc[r + i]);
+      } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[r] = fmaf(m[i], x[i], acc[r]);
+        for (int q = r; q < r + 16; q += 4) {
+          if (q < nr) {
+            const f32x4 m = *reinterpret_cast<const f32x4 *>(mk + q);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[q + i] = fmaf(m[i], x, acc[q + i]);
+          }
+        }
       }
     }
   }
@@ -1363,10 +1373,10 @@ hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_collide_valu(const StepArgs &a, const float *M_abi, const float *in, float *out,
+hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,
                                hipStream_t s) {
   const dim3 grid((unsigned)((a.geo.C + 255) / 256), (unsigned)((a.geo.R + kValuRows - 1) / kValuRows));
-  hipLaunchKernelGGL(collide_valu_kernel, grid, dim3(256), 0, s, a, M_abi, in,
+  hipLaunchKernelGGL(collide_valu_kernel, grid, dim3(256), 0, s, a, MT, in,
                      out);
   return hipGetLastError();
 }

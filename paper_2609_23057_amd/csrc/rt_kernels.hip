@@ -560,8 +560,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     for (int j = 0; j < kRing; ++j) {
       const int s = s0 + j;
       const uint4 araw = ring[j], araw_lo = ring_lo[PREC == P_BF16X3 ? j : 0];
-      ring[j] = A[frag_rec(tr, s + kRing, nk)];
-      if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
+      if constexpr (kRing == 1) {
+        // a single slot: refill at once, so the load overlaps this step
+        ring[j] = A[frag_rec(tr, s + kRing, nk)];
+        if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
+      }
       const int kb = tr.klo + kStep * min(s, nk - 1);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
@@ -591,6 +594,17 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
             acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[cb], 0, 0, 0);
           }
         }
+      }
+      // With several slots, refill slot j only after the matrix-core steps
+      // that read it: the load can then write the slot's own registers and
+      // stay in flight across the loop's back edge until this slot is used
+      // again kRing steps later.  (Issued earlier, it needs other registers
+      // and a copy into the slot at the back edge, which waits for the load
+      // and empties the ring.)
+      if constexpr (kRing > 1) {
+        __builtin_amdgcn_sched_barrier(0);
+        ring[j] = A[frag_rec(tr, s + kRing, nk)];
+        if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
       }
     }
   }

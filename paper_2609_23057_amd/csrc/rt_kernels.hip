@@ -259,11 +259,21 @@ __device__ __forceinline__ void put_group(const float (&o)[4], float *dst, char 
   }
 }
 
+// The emission factor dt_pre * eps of the cell is formed only once the first
+// group's loads are issued: eps comes from a load issued just before, and
+// loads and stores complete in issue order, so using it earlier would make
+// the tile wait for the previous tile's stores before its first gather load.
+__device__ __forceinline__ float late_emission(const StepArgs &a, float emis) {
+  asm volatile("" : "+v"(emis));
+  return a.dt_pre * emis;
+}
+
 template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, int PUT>
 __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__restrict__ src,
                                              const Geometry &g, const LaneDir (&ld)[4],
-                                             const LaneCell &lc, float emis_dt, float *dst,
+                                             const LaneCell &lc, float emis, float *dst,
                                              char *lds, const float *jrow, int lo_off = 0) {
+  float emis_dt = 0.0f;
   if (!INTERIOR) {
     // edge tiles (a small share): one group at a time, which keeps the wrap
     // and ghost bookkeeping of only one direction live
@@ -271,6 +281,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
     for (int k = 0; k < 4; ++k) {
       float v[4][4], o[4];
       dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, v);
+      if (EMIT && k == 0) emis_dt = late_emission(a, emis);
       dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, o, jrow);
       put_group<PUT>(o, dst, lds, k, lo_off);
       __builtin_amdgcn_sched_barrier(0);
@@ -283,6 +294,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
   for (int k = 1; k <= 4; ++k) {
     if (k < 4) dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, vb);
     __builtin_amdgcn_sched_barrier(0);
+    if (EMIT && k == 1) emis_dt = late_emission(a, emis);
     float o[4];
     dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, o, jrow);
     put_group<PUT>(o, dst, lds, k - 1, lo_off);
@@ -441,7 +453,6 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     al[cb] = a.alpha[lc.c];
     be[cb] = a.beta[lc.c];
     em[cb] = a.emis[lc.c];
-    const float emis_dt = a.dt_pre * em[cb];
     // A block is interior when every tap of every cell lies inside the lattice
     // (taps reach at most two cells either way); then no wrap or ghost is needed.
     const int c_last = (int)((base + 32 < g.C ? (int64_t)base + 32 : g.C) - 1);
@@ -452,18 +463,18 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       // each combined group goes straight to the high and low tiles
       char *brow = s_b + (32 * cb + col) * L.strideB + rbase * 2;
       if (interior)
-        gather_field<false, GATHER, true, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, emis_dt, nullptr, brow, s_jrow,
+        gather_field<false, GATHER, true, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, em[cb], nullptr, brow, s_jrow,
                                                                    L.tileB);
       else
-        gather_field<false, GATHER, false, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, emis_dt, nullptr, brow, s_jrow,
+        gather_field<false, GATHER, false, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, em[cb], nullptr, brow, s_jrow,
                                                                     L.tileB);
     } else {
       // X (float32) goes to the X tile; the epilogue reads it back from there.
       char *xrow = s_x + (32 * cb + col) * L.strideX + rbase * 4;
       if (interior)
-        gather_field<false, GATHER, true, true, CKPT, kPutF32>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
+        gather_field<false, GATHER, true, true, CKPT, kPutF32>(a, a.in, g, ld, lc, em[cb], nullptr, xrow, s_jrow);
       else
-        gather_field<false, GATHER, false, true, CKPT, kPutF32>(a, a.in, g, ld, lc, emis_dt, nullptr, xrow, s_jrow);
+        gather_field<false, GATHER, false, true, CKPT, kPutF32>(a, a.in, g, ld, lc, em[cb], nullptr, xrow, s_jrow);
     }
     __builtin_amdgcn_sched_barrier(0);
   }

@@ -431,6 +431,16 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   // this lane's rows in the LDS tiles: cell 32 cb + col, rows rbase + 8 q + (0..3)
   const int rbase = t * 32 + h * 4;
 
+  // adjoint: the float64 accumulator this lane updates first at the end of
+  // the tile (entry e = wg * 64 + lane < 96 of the 3 x 32 per-cell sums),
+  // loaded now so that its latency is hidden under the tile
+  double gpre = 0.0;
+  if constexpr (ADJ) {
+    const int e = wg * 64 + lane;
+    const int k = e / 32, cc = e - k * 32;
+    if (e < 3 * 32 && active && (int64_t)c0 + cc < g.C) gpre = a.gacc[(int64_t)k * g.C + c0 + cc];
+  }
+
   // ---- 1. gather own rows, per 32-cell column block --------------------------
   LaneCell lcs[NB];
   bool inter[NB];
@@ -622,6 +632,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 
   // ---- 4. epilogue -------------------------------------------------------------
   float part[3] = {0.0f, 0.0f, 0.0f};
+  (void)gpre;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     if (!lcs[cb].valid) continue;
@@ -680,13 +691,18 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       if (h == 0) s_red[(k * W + wg) * 32 + col] = v;
     }
     __syncthreads();
-    for (int e = wg * 64 + lane; e < 3 * 32; e += W * 64) {
+    // (the lane index is made opaque so that the entry's address is formed
+    // again here rather than held in registers through the tile)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    for (int e = wg * 64 + ln, u = 0; e < 3 * 32; e += W * 64, ++u) {
       const int k = e / 32, cc = e - k * 32;
       const int64_t c = (int64_t)c0 + cc;
       if (active && c < g.C) {
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += (double)s_red[(k * W + ww) * 32 + cc];
-        a.gacc[(int64_t)k * g.C + c] += s;
+        double *p = a.gacc + (int64_t)k * g.C + c;
+        *p = (u == 0 ? gpre : *p) + s;
       }
     }
   }

@@ -339,11 +339,13 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
                                                bool f16, int ngroups = 1, int nb = 1) {
   LdsLayout L;
   const bool xsplit = nb > 1 && esize == 2;
+  // the bf16 / bf16x3 adjoint keeps mu as high (B) and low tiles
+  const bool musplit = adjoint && esize == 2 && !f16;
   int off = 0;
   L.b_off = off;
   L.strideB = Rpad * esize + 16;
   L.tileB = 32 * nb * L.strideB;
-  off += (xsplit ? 2 : ntile) * L.tileB;
+  off += ((xsplit || musplit) ? 2 : ntile) * L.tileB;
   // the forward float32 contraction reads X itself: the X tile is the B tile
   L.strideX = Rpad * 4 + 16;
   if (!xsplit && (adjoint || esize != 4)) {
@@ -425,7 +427,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   (void)s_red;
   (void)s_x;
   const int c0 = active ? (int)(tile * (32 * NB)) : 0;
-  float mv[ADJ ? 16 : 1];
+  // adjoint mu in registers: only for fp16, whose per-cell scale needs the
+  // whole cell before mu can be converted (fp32 gathers mu into its B tile,
+  // bf16 and bf16x3 into high and low 16-bit tiles)
+  constexpr bool MUSPLIT = ADJ && (PREC == P_BF16 || PREC == P_BF16X3);
+  float mv[ADJ && PREC == P_F16 ? 16 : 1];
   float cscale[NB];
   (void)mv;
   // this lane's rows in the LDS tiles: cell 32 cb + col, rows rbase + 8 q + (0..3)
@@ -498,6 +504,14 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       else
         gather_field<true, true, false, false, false, kPutF32>(a, a.lam_next, g, ld, lcs[0], 0.0f, nullptr, murow,
                                                                  s_jrow);
+    } else if constexpr (MUSPLIT) {
+      char *murow = s_b + col * L.strideB + rbase * 2;
+      if (inter[0])
+        gather_field<true, true, true, false, false, kPutSplit>(a, a.lam_next, g, ld, lcs[0], 0.0f, nullptr, murow,
+                                                                  s_jrow, L.tileB);
+      else
+        gather_field<true, true, false, false, false, kPutSplit>(a, a.lam_next, g, ld, lcs[0], 0.0f, nullptr, murow,
+                                                                   s_jrow, L.tileB);
     } else {
       if (inter[0])
         gather_field<true, true, true, false, false, kPutReg>(a, a.lam_next, g, ld, lcs[0], 0.0f, mv, nullptr, s_jrow);
@@ -523,15 +537,15 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 
   // ---- 2. B operand: the contraction input in its precision ------------------
   // forward: X, adjoint: mu (both already in place for float32; X also for the
-  // split tiles).
-  if constexpr (NB == 1) {
+  // split tiles, mu for the bf16 / bf16x3 adjoint).
+  if constexpr (NB == 1 && !MUSPLIT) {
     if (PREC != P_F32) {
       char *xrow = s_x + col * L.strideX + rbase * 4;
       float v[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         f32x4 x4;
-        if (ADJ)
+        if constexpr (ADJ)
           x4 = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
         else
           x4 = *reinterpret_cast<const f32x4 *>(xrow + 32 * q);
@@ -660,10 +674,17 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       // adjoint: mu of these 4 rows (for float32 it is the B tile itself)
       f32x4 mu = f32x4{0.f, 0.f, 0.f, 0.f};
       if constexpr (ADJ) {
-        if constexpr (PREC == P_F32)
+        if constexpr (PREC == P_F32) {
           mu = *reinterpret_cast<const f32x4 *>(brow + (rbase + q * 8) * 4);
-        else
+        } else if constexpr (MUSPLIT) {
+          // mu = high + low, exact in float32 (to 2^-18 of mu)
+          const bf16x4 hv = *reinterpret_cast<const bf16x4 *>(brow + (rbase + q * 8) * 2);
+          const bf16x4 lv = *reinterpret_cast<const bf16x4 *>(brow + L.tileB + (rbase + q * 8) * 2);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) mu[j] = static_cast<float>(hv[j]) + static_cast<float>(lv[j]);
+        } else {
           mu = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
+        }
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {

@@ -756,8 +756,15 @@ inline hipError_t resident_blocks(const void *k, int threads, int lds, std::atom
 template <int PREC, bool ADJ, int MAXW, int NB>
 constexpr int kFusedRing = MAXW <= 4 ? 4 : ((!ADJ && PREC != P_F32 && PREC != P_BF16X3) ? 2 : 1);
 
+// Waves per SIMD the register allocation must allow: 4 for the fp32 and bf16
+// adjoint in blocks of up to 4 waves (the accumulator then lives in ordinary
+// VGPRs, without spills), otherwise whatever the kernel needs.
+template <int PREC, bool ADJ, int MAXW>
+constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4 : 1;
+
 template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB>
-__global__ void __launch_bounds__(64 * MAXW) fused_kernel(StepArgs a, int64_t ntiles) {
+__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW>)))
+fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
   extern __shared__ __align__(16) char smem[];
   const Geometry g = a.geo;

@@ -590,6 +590,21 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) acc[cb] = f32x16{0};
   const int nsteps = (nk + kRing - 1) / kRing * kRing;
+  // B fragments (16 bytes per lane per column block; bf16x3 also the low
+  // part) are read from LDS one step ahead, so that their latency overlaps
+  // the previous step's matrix-core work instead of preceding this step's
+  constexpr int kLo = PREC == P_BF16X3 ? 2 : 1;
+  auto bfrag = [&](int cb, int s, int part) -> uint4 {
+    const int kb = tr.klo + kStep * min(s, nk - 1);
+    const char *bcell = s_b + (32 * cb + col) * L.strideB;
+    const char *p = PREC == P_F32 ? bcell + (kb + 4 * h) * 4 : bcell + (kb + 8 * h) * 2 + part * L.tileB;
+    return *reinterpret_cast<const uint4 *>(p);
+  };
+  uint4 bcur[NB][kLo];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+    for (int u = 0; u < kLo; ++u) bcur[cb][u] = bfrag(cb, 0, u);
   for (int s0 = 0; s0 < nsteps; s0 += kRing) {
 #pragma unroll
     for (int j = 0; j < kRing; ++j) {
@@ -600,42 +615,40 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
         ring[j] = A[frag_rec(tr, s + kRing, nk)];
         if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
       }
-      const int kb = tr.klo + kStep * min(s, nk - 1);
+      uint4 bnext[NB][kLo];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int u = 0; u < kLo; ++u) bnext[cb][u] = bfrag(cb, s + 1, u);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const char *bcell = s_b + (32 * cb + col) * L.strideB;
         if (PREC == P_F32) {
           const f32x4 av = __builtin_bit_cast(f32x4, araw);
-          const f32x4 bv = *reinterpret_cast<const f32x4 *>(bcell + (kb + 4 * h) * 4);
+          const f32x4 bv = __builtin_bit_cast(f32x4, bcur[cb][0]);
           acc[cb] = mfma_step_f32(av[0], bv[0], acc[cb]);
           acc[cb] = mfma_step_f32(av[1], bv[1], acc[cb]);
           acc[cb] = mfma_step_f32(av[2], bv[2], acc[cb]);
           acc[cb] = mfma_step_f32(av[3], bv[3], acc[cb]);
+        } else if (PREC == P_F16) {
+          const f16x8 av = __builtin_bit_cast(f16x8, araw);
+          const f16x8 bv = __builtin_bit_cast(f16x8, bcur[cb][0]);
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[cb], 0, 0, 0);
         } else {
-          const char *bp = bcell + (kb + 8 * h) * 2;
-          if (PREC == P_F16) {
-            const f16x8 av = __builtin_bit_cast(f16x8, araw);
-            const f16x8 bv = *reinterpret_cast<const f16x8 *>(bp);
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[cb], 0, 0, 0);
-          } else {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(bp);
-            if (PREC == P_BF16X3) {
-              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
-              const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(bp + L.tileB);
-              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc[cb], 0, 0, 0);
-              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc[cb], 0, 0, 0);
-            }
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[cb], 0, 0, 0);
+          const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+          const bf16x8 bv = __builtin_bit_cast(bf16x8, bcur[cb][0]);
+          if (PREC == P_BF16X3) {
+            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+            const bf16x8 blo = __builtin_bit_cast(bf16x8, bcur[cb][kLo - 1]);
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc[cb], 0, 0, 0);
           }
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[cb], 0, 0, 0);
         }
       }
-      // With several slots, refill slot j only after the matrix-core steps
-      // that read it: the load can then write the slot's own registers and
-      // stay in flight across the loop's back edge until this slot is used
-      // again kRing steps later.  (Issued earlier, it needs other registers
-      // and a copy into the slot at the back edge, which waits for the load
-      // and empties the ring.)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int u = 0; u < kLo; ++u) bcur[cb][u] = bnext[cb][u];
       if constexpr (kRing > 1) {
         __builtin_amdgcn_sched_barrier(0);
         ring[j] = A[frag_rec(tr, s + kRing, nk)];

@@ -198,7 +198,9 @@ size_t rt_adjoint_segment_bytes(const rt_problem *p, int32_t ckpt_every);
  * by rt_run (same nsteps and ckpt_every; recomputes each segment into d_seg).
  * Outputs [ny][nx]: d_g_tau = dL/dtau, d_g_albedo = dL/dalbedo, d_g_emis =
  * dL/deps; d_lambda0 (state, or NULL) = dL/dS_0.  Inflow radiances and the
- * emission profile are treated as constants. */
+ * emission profile are treated as constants.  The reverse steps run on the
+ * fused matrix-core kernels (float32 for an RT_PLAIN context), so n <= 128 is
+ * required: RT_EUNSUPPORTED otherwise. */
 rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckpt_every, float *d_seg,
                      const float *d_lambdaT, float *d_g_tau, float *d_g_albedo, float *d_g_emis,
                      float *d_lambda0);

@@ -526,6 +526,8 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (nsteps < 1 || ckpt_every < 1) return c->fail(RT_EINVAL, "nsteps and ckpt_every must be >= 1");
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  if (c->geo.Rpad > 512)
+    return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");
   const int prec_save = c->prec;
   if (c->prob.flags & RT_PLAIN) c->prec = P_F32;  // the plain path replays on the fused float32 kernels
   const size_t sb = state_elems(c) * sizeof(float);

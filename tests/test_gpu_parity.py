@@ -211,3 +211,22 @@ def test_autograd_function_matches_oracle_gradients():
     assert _rel(to_np(tau.grad), ref["g_tau"]) < 1e-4
     assert _rel(to_np(alb.grad), ref["g_albedo"]) < 1e-4
     assert _rel(to_np(em.grad), ref["g_emis"]) < 1e-4
+
+
+def test_plain_path_largest_direction_set():
+    """n = 256 (8 x 32 directions, 4n = 1024 rows) exceeds the fused kernels;
+    the plain float32 path runs it and matches the oracle, and the adjoint,
+    which runs on the fused kernels, refuses it with RT_EUNSUPPORTED."""
+    import paper_2609_23057_amd as P
+    spec = W.spec("beam512", nx=12, ny=10, n_zen=8, n_az=32)
+    solver, oprob, _ = build(spec, "plain")
+    S0 = W.initial_state(spec, "random")
+    S = to_dev(S0, solver)
+    solver.run(S, 6)
+    assert_close(to_np(S), OL.run(S0, oprob, 6), tolerance("plain", oprob), ("plain n=256",))
+    S = solver.empty_state()
+    ck = solver.checkpoint_buffer(4, 2)
+    solver.run(S, 4, ck, 2)
+    with pytest.raises(P.RTError) as ei:
+        solver.adjoint(4, ck, 2, solver.empty_state())
+    assert ei.value.status == P.RT_EUNSUPPORTED

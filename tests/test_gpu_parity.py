@@ -230,3 +230,16 @@ def test_plain_path_largest_direction_set():
     with pytest.raises(P.RTError) as ei:
         solver.adjoint(4, ck, 2, solver.empty_state())
     assert ei.value.status == P.RT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16"])
+@pytest.mark.parametrize("dims", [(1, 1, (0, 0, 0, 0)), (2, 3, (0, 0, 0, 0)), (5, 1, (1, 1, 1, 2)),
+                                  (1, 7, (1, 1, 1, 2)), (3, 2, (0, 0, 1, 2))])
+def test_degenerate_lattices(dims, precision):
+    """Lattices smaller than every tap reach: a periodic axis of length 1 or 2
+    wraps taps onto the same cells several times; absorbing and inflow edges
+    surround every cell."""
+    nx, ny, bc = dims
+    spec = W.spec("beam512", nx=nx, ny=ny, n_zen=2, n_az=8, bc=bc)
+    _, oprob, got, ref = _run_both(spec, precision, 12, "random")
+    assert_close(got, ref, tolerance(precision, oprob), ("degenerate", dims, precision))

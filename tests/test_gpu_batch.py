@@ -215,3 +215,20 @@ def test_spectral64_full_size_channels_match_single_and_oracle():
         oprob = OL.make_problem(specs[i], meds[i])
         ref = OL.run(np.zeros(oprob.shape), oprob, T)
         assert_close(to_np(states[i]), ref, tolerance("bf16", oprob), ("spectral64", i))
+
+
+def test_single_channel_batch_matches_its_context_bitwise():
+    specs = channel_specs(SMALL[2:3])
+    batch, meds = make_batch(specs, "bf16")
+    S0 = initial_states(batch, specs)
+    T, K = 7, 3
+    states = [s.clone() for s in S0]
+    ck = batch.checkpoint_buffers(T, K)
+    batch.run(states, T, ck, K)
+    single, _, _ = build(specs[0], "bf16", meds[0])
+    S = S0[0].clone()
+    ck1 = single.checkpoint_buffer(T, K)
+    single.run(S, T, ck1, K)
+    torch.cuda.synchronize()
+    assert torch.equal(S, states[0])
+    assert torch.equal(ck1, ck[0])

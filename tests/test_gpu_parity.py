@@ -243,3 +243,12 @@ def test_degenerate_lattices(dims, precision):
     spec = W.spec("beam512", nx=nx, ny=ny, n_zen=2, n_az=8, bc=bc)
     _, oprob, got, ref = _run_both(spec, precision, 12, "random")
     assert_close(got, ref, tolerance(precision, oprob), ("degenerate", dims, precision))
+
+
+@pytest.mark.parametrize("dims", [(1, 1, (0, 0, 0, 0)), (5, 1, (1, 1, 1, 2)), (3, 2, (0, 0, 1, 2))])
+def test_adjoint_degenerate_lattices(dims):
+    nx, ny, bc = dims
+    spec = W.spec("adjoint256", nx=nx, ny=ny, n_zen=2, n_az=8, bc=bc)
+    ref, got = _adjoint_case(spec, "fp32", 9, 3)
+    for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
+        assert _rel(arr, ref[key]) < GTOL["fp32"], (dims, key, _rel(arr, ref[key]))

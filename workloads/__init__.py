@@ -143,7 +143,7 @@ def spectral_channels(nchan=64, seed=5):
     grids = [(2, 8), (4, 8), (4, 16)]
     out = []
     for k in range(nchan):
-        lam = 400.0 + 500.0 * k / (nchan - 1)
+        lam = 400.0 + 500.0 * k / max(nchan - 1, 1)   # a single channel sits at 400 nm
         t_r = 0.1 * (lam / 550.0) ** -4
         t_a = 0.2
         side = sides[rng.integers(len(sides))]

@@ -24,6 +24,12 @@ albedo * tau_ext, tau_abs = (1 - albedo) * tau_ext.
 The literal Eq. 2 form (fused first-order Taylor of Igarashi et al., used by
 the paper only for the D1Q2 comparison of Sec. 3.1) is available as
 fused_taylor: Y = (1 - tau_ext) S + tau_sca M S + dt J.
+
+Phase-function mixtures (the per-cell aerosol / cloud fractions that the
+paper's conclusion names as the next step, Sec. 4): a second collision matrix
+M2 and a per-cell fraction f in [0, 1] of the scattering that follows it,
+Y = alpha X + beta ((1 - f) M X + f M2 X).  The redistribution of a cell is the
+f-weighted mixture of two phase functions, each normalised as in Eq. 17.
 """
 import math
 import numpy as np
@@ -40,7 +46,7 @@ class Problem:
 
     def __init__(self, nx, ny, dirs, shifts, M, dt, bc, tau, albedo, emis,
                  jprof, inflow=None, abs_taylor=False, scat_exp=False,
-                 fused_taylor=False):
+                 fused_taylor=False, M2=None, frac=None):
         self.nx, self.ny = int(nx), int(ny)
         self.dirs = dirs
         self.n = dirs.n
@@ -64,6 +70,14 @@ class Problem:
             raise ValueError("y edges must both be periodic or neither")
         self.alpha, self.beta = coefficients(self.tau, self.albedo, self.abs_taylor,
                                              self.scat_exp, self.fused_taylor)
+        # optional phase mixture: second collision matrix and per-cell fraction
+        self.M2 = None if M2 is None else np.asarray(M2, dtype=np.float64)
+        self.frac = None
+        if self.M2 is not None:
+            f = np.zeros((self.ny, self.nx)) if frac is None else frac
+            self.frac = np.asarray(f, dtype=np.float64).reshape(self.ny, self.nx)
+            if np.any(self.frac < 0.0) or np.any(self.frac > 1.0):
+                raise ValueError("mixture fraction outside [0, 1]")
 
     @property
     def shape(self):
@@ -224,7 +238,11 @@ def collide(S, prob):
     X = (S + e * prob.dt * J).reshape(4 * n, C)
     al = prob.alpha.reshape(1, C)
     be = prob.beta.reshape(1, C)
-    Y = al * X + be * (prob.M @ X)
+    MX = prob.M @ X
+    if prob.M2 is not None:
+        f = prob.frac.reshape(1, C)
+        MX = (1.0 - f) * MX + f * (prob.M2 @ X)
+    Y = al * X + be * MX
     Y = Y.reshape(prob.shape)
     if prob.fused_taylor:
         Y = Y + prob.dt * J
@@ -342,7 +360,14 @@ def make_problem(spec, medium):
     M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
                                 ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
                                 spec.get("scalar", False))
+    M2 = None
+    if spec.get("mixture") is not None:
+        ph2 = spec["mixture"]
+        M2 = _phase.collision_matrix(dirs, ph2.get("kind", "rayleigh"), ph2.get("g", 0.0),
+                                     ph2.get("mix_ray", 1.0), spec.get("renorm_irow", False),
+                                     spec.get("scalar", False))
     return Problem(spec["nx"], spec["ny"], dirs, shifts, M, spec.get("dt", 1.0), spec["bc"],
                    medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
                    medium.get("inflow"), spec.get("abs_taylor", False),
-                   spec.get("scat_exp", False), spec.get("fused_taylor", False))
+                   spec.get("scat_exp", False), spec.get("fused_taylor", False),
+                   M2=M2, frac=medium.get("frac"))

@@ -560,3 +560,67 @@ def test_table_grids_run_physically(g, pol):
         assert np.all(S[:, 0] ** 2 - (S[:, 1:] ** 2).sum(axis=1) >= -1e-15)
     I_map, dop_map = OL.maps(S)
     assert I_map.max() > 0 and np.all(dop_map <= 1 + 1e-12)
+
+
+# ------------------------------------------------------------- phase mixture --
+# Per-cell mixtures of two phase functions (the aerosol / cloud fractions the
+# conclusion, Sec. 4, names as the next step): Y = alpha X + beta ((1 - f) M X
+# + f M2 X).  Pinned against the single-phase problems it must reduce to, its
+# affine dependence on f, and intensity conservation.
+
+def _with_mixture(p, M2, frac):
+    return OL.Problem(p.nx, p.ny, p.dirs, p.shifts, p.M, p.dt, p.bc, p.tau, p.albedo, p.emis, p.jprof,
+                      p.inflow, p.abs_taylor, p.scat_exp, p.fused_taylor, M2=M2, frac=frac)
+
+
+def _mixture_setup(**kw):
+    nx, ny = kw.get("nx", 7), kw.get("ny", 6)
+    rng = np.random.default_rng(41)
+    base = dict(nx=nx, ny=ny, n_zen=2, n_az=8, plane="xy", tau=0.35, albedo=0.8,
+                emis=rng.uniform(0.0, 0.1, (ny, nx)), jprof=np.tile([1.0, 0.2, 0.0, 0.0], (16, 1)))
+    base.update(kw)
+    p_hg = _problem(kind="hg", g=0.6, **base)
+    p_ray = _problem(kind="rayleigh", **base)
+    S = W.initial_state(dict(nx=nx, ny=ny, n_zen=2, n_az=8, seed=9), "random")
+    return p_hg, p_ray, S, rng
+
+
+def test_mixture_fraction_zero_and_one_reduce_to_each_phase():
+    """f = 0 is the main phase function's problem, f = 1 the second's, to the
+    bit: catches swapped weights and a missing (1 - f) factor."""
+    p_hg, p_ray, S, _ = _mixture_setup()
+    zero = _with_mixture(p_hg, p_ray.M, np.zeros((p_hg.ny, p_hg.nx)))
+    one = _with_mixture(p_hg, p_ray.M, np.ones((p_hg.ny, p_hg.nx)))
+    assert np.array_equal(OL.step(S, zero), OL.step(S, p_hg))
+    assert np.array_equal(OL.step(S, one), OL.step(S, p_ray))
+    assert not np.allclose(OL.step(S, p_hg), OL.step(S, p_ray))   # the two phases differ
+
+
+def test_mixture_collision_is_affine_in_the_fraction():
+    """Per cell, the collision with fraction f equals (1 - f) times the f = 0
+    collision plus f times the f = 1 collision."""
+    p_hg, p_ray, S, rng = _mixture_setup()
+    f = rng.uniform(0.0, 1.0, (p_hg.ny, p_hg.nx))
+    Yf = OL.collide(S, _with_mixture(p_hg, p_ray.M, f))
+    Y0 = OL.collide(S, _with_mixture(p_hg, p_ray.M, np.zeros_like(f)))
+    Y1 = OL.collide(S, _with_mixture(p_hg, p_ray.M, np.ones_like(f)))
+    ref = (1.0 - f) * Y0 + f * Y1
+    assert np.abs(Yf - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+def test_mixture_conserves_total_intensity_without_absorption():
+    """Albedo 1, periodic, no source, I-row renormalised matrices: any
+    per-cell mixture of two conservative redistributions conserves total I
+    (the weights of a cell sum to one)."""
+    p_hg, p_ray, S, rng = _mixture_setup(albedo=1.0, renorm=True, emis=None, jprof=None)
+    prob = _with_mixture(p_hg, p_ray.M, rng.uniform(0.0, 1.0, (p_hg.ny, p_hg.nx)))
+    tot0 = S[:, 0].sum()
+    for _ in range(20):
+        S = OL.step(S, prob)
+    assert abs(S[:, 0].sum() - tot0) < 1e-12 * tot0
+
+
+def test_mixture_fraction_outside_unit_interval_is_refused():
+    p_hg, p_ray, _, _ = _mixture_setup()
+    with pytest.raises(ValueError):
+        _with_mixture(p_hg, p_ray.M, np.full((p_hg.ny, p_hg.nx), 1.5))

@@ -21,6 +21,8 @@ Workloads (the paper's method at the sizes it is benchmarked on here):
   prec1024     1024x1024, n = 128 (8 x 16), the beam512 generator, 200 steps
   adjoint256   256x256, n = 32, beam512 generator plus emission U[0, 0.05],
                top-edge (I + DoLP) loss after 500 steps
+  (any)        with mixture={phase}: a second phase function and a per-cell
+               fraction U[0, 1] of the scattering that follows it
   spectral64   64 channels 400-900 nm, Rayleigh optical depth ~ lambda^-4 plus
                aerosol HG(0.6), per-channel lattice and direction count drawn
                from {128,256,384,512}^2 x {16,32,64}, 200 steps
@@ -110,8 +112,14 @@ def medium(s, seed=None):
     inflow = np.zeros((4, n, 4))
     if "beam_dir" in s and s["bc"][3] == BC_INFLOW:
         inflow[3, s["beam_dir"], 0] = 1.0
+    # phase mixture: per-cell fraction of the scattering that follows the
+    # second phase function (drawn after everything else, so the other
+    # fields do not depend on whether a mixture is asked for)
+    frac = None
+    if s.get("mixture") is not None:
+        frac = _f32(rng.uniform(0.0, 1.0, size=(ny, nx)))
     return {"tau": _f32(tau), "albedo": _f32(alb), "emis": _f32(emis),
-            "jprof": _f32(jprof), "inflow": _f32(inflow)}
+            "jprof": _f32(jprof), "inflow": _f32(inflow), "frac": frac}
 
 
 def initial_state(s, kind="zero", seed=None):

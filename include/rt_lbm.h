@@ -157,6 +157,21 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
 rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, const float *d_emis,
                         const float *h_jprof, const float *h_inflow);
 
+/* Per-cell mixture of two phase functions.  With it set, the scattered part
+ * of the collision becomes beta ((1 - f) M X + f M2 X): M is the context's
+ * collision matrix, M2 the one a problem with phase2 / g2 / mix_ray2 (same
+ * meaning as rt_problem's phase / g / mix_ray) and otherwise the context's
+ * own fields would build, each normalised as Eq. 17 prescribes, and f the
+ * per-cell fraction d_frac (device [ny][nx] float32, values in [0, 1],
+ * copied into the workspace).  Every later rt_step / rt_run uses it; phase2 < 0
+ * removes it (d_frac is then ignored).  Validation reads f on the host, so
+ * the call synchronises the stream.  Errors: RT_EUNSUPPORTED for RT_PLAIN
+ * contexts and precisions other than RT_FP32 and RT_BF16; RT_EINVAL for an
+ * invalid phase function or a NULL d_frac; RT_ERANGE if some f is outside
+ * [0, 1] or not finite (the mixture is then off).  rt_adjoint, rt_batch_run
+ * and rt_batch_adjoint return RT_EUNSUPPORTED while a mixture is set. */
+rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac);
+
 /* One step S_out = Stream(Collide(S_in)); S_in and S_out must not overlap. */
 rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out);
 

@@ -33,6 +33,7 @@ struct Layout {
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
+  size_t mix_tiles, mix_frag, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
   size_t tau, alb, emis, alpha, beta;
   size_t gacc, partial, sums, bad;
   size_t Ya, Yb, La, Lb;
@@ -73,7 +74,7 @@ void pack_all(const HostPlan &hp, int prec, Packed *pk) {
   }
 }
 
-Layout make_layout(const HostPlan &hp, const Packed &pk) {
+Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_flags_plain) {
   Layout L{};
   const size_t C = (size_t)hp.nx * hp.ny;
   const size_t state = C * 4 * hp.n * sizeof(float);
@@ -101,6 +102,16 @@ Layout make_layout(const HostPlan &hp, const Packed &pk) {
   L.tables_bytes = off - L.tables;
   L.jrow = take(hp.Rpad * sizeof(float));
   L.ghost = take(5 * hp.Rpad * sizeof(float));   // 4 edges + a zero row
+  // phase mixture: tile ranges and dense A fragments of the second matrix in
+  // the contraction precision (fp32 or bf16 fused steps), per-cell fraction
+  {
+    const bool mix = !(prec_flags_plain) && (prec == RT_FP32 || prec == RT_BF16);
+    const int kstep = prec == RT_FP32 ? 8 : 16;
+    const size_t frag = mix ? ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16 : 0;
+    L.mix_tiles = take(mix ? ntile * sizeof(TileRange) : 0);
+    L.mix_frag = take(frag);
+    L.frac = take(mix ? C * sizeof(float) : 0);
+  }
   L.tau = take(C * sizeof(float));
   L.alb = take(C * sizeof(float));
   L.emis = take(C * sizeof(float));
@@ -135,6 +146,7 @@ struct rt_ctx {
   std::vector<float> host_medium;  // jrow + ghost staging
   int nout[4] = {0, 0, 0, 0};
   bool medium_set = false;
+  bool mixture = false;   // rt_set_phase_mixture succeeded
   int prec = 0;
   int cu_count = 256;
   std::string err;
@@ -171,6 +183,11 @@ StepArgs rt_ctx::args(bool adjoint) const {
                                   : (f32 ? L.tiles_fwd32 : L.tiles_fwd));
   a.a_scale_inv = (float)(1.0 / pk.a_scale);
   a.gacc = at<double>(L.gacc);
+  if (mixture && !adjoint) {
+    a.frag2 = at<uint4>(L.mix_frag);
+    a.tiles2 = at<TileRange>(L.mix_tiles);
+    a.frac = at<float>(L.frac);
+  }
   return a;
 }
 
@@ -185,7 +202,7 @@ rt_status plan_for(const rt_problem *p, HostPlan *hp, Packed *pk, Layout *L, std
   rt_status st = build_plan(p, hp, msg);
   if (st != RT_OK) return st;
   pack_all(*hp, p->precision, pk);
-  *L = make_layout(*hp, *pk);
+  *L = make_layout(*hp, *pk, p->precision, (p->flags & RT_PLAIN) != 0);
   return RT_OK;
 }
 
@@ -414,6 +431,55 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
   return RT_OK;
 }
 
+rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (phase2 < 0) {
+    c->mixture = false;
+    return RT_OK;
+  }
+  if ((c->prob.flags & RT_PLAIN) || (c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16))
+    return c->fail(RT_EUNSUPPORTED, "phase mixtures run on the fused fp32 and bf16 paths only");
+  if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
+  // the second collision matrix: the same direction set and options, another
+  // scalar phase function (Eq. 17 weights, Rayleigh polarisation part)
+  rt_problem p2 = c->prob;
+  p2.phase = phase2;
+  p2.g = g2;
+  p2.mix_ray = mix_ray2;
+  HostPlan hp2;
+  std::string msg;
+  rt_status st = build_plan(&p2, &hp2, &msg);
+  if (st != RT_OK) return c->fail(st, "second phase function: " + msg);
+  std::vector<TileRange> tiles;
+  std::vector<uint8_t> frag;
+  pack_fragments(hp2, false, c->prob.precision == RT_FP32 ? FRAG_F32 : FRAG_BF16, 1.0, false, &tiles, &frag);
+  const Layout &L = c->L;
+  if (frag.size() > L.frac - L.mix_frag || tiles.size() * sizeof(TileRange) > L.mix_frag - L.mix_tiles)
+    return c->fail(RT_EINVAL, "mixture fragments exceed their workspace region");
+  c->mixture = false;
+  const size_t C = (size_t)c->geo.C;
+  std::vector<float> hf(C);
+  st = c->hip(hipMemcpyAsync(c->ws + L.mix_tiles, tiles.data(), tiles.size() * sizeof(TileRange),
+                             hipMemcpyHostToDevice, c->stream), "upload mixture tiles");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag, frag.data(), frag.size(), hipMemcpyHostToDevice, c->stream),
+                "upload mixture fragments");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(c->ws + L.frac, d_frac, C * sizeof(float), hipMemcpyDeviceToDevice, c->stream),
+                "copy fraction");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(hf.data(), c->ws + L.frac, C * sizeof(float), hipMemcpyDeviceToHost, c->stream),
+                "read fraction");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "set_phase_mixture");
+  if (st != RT_OK) return st;
+  size_t bad = 0;
+  for (float v : hf)
+    if (!(v >= 0.0f && v <= 1.0f)) ++bad;
+  if (bad) return c->fail(RT_ERANGE, std::to_string(bad) + " cells have a mixture fraction outside [0, 1]");
+  c->mixture = true;
+  return RT_OK;
+}
+
 static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, float *s_out) {
   StepArgs a = c->args(false);
   a.in = in;
@@ -526,6 +592,7 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (nsteps < 1 || ckpt_every < 1) return c->fail(RT_EINVAL, "nsteps and ckpt_every must be >= 1");
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  if (c->mixture) return c->fail(RT_EUNSUPPORTED, "the adjoint of a phase mixture is not supported");
   if (c->geo.Rpad > 512)
     return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");
   const int prec_save = c->prec;
@@ -832,6 +899,7 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
   for (int i = 0; i < b->nchan; ++i) {
     if (!h_states[i] || (h_ckpt && !h_ckpt[i])) return b->fail(RT_EINVAL, "NULL state or checkpoint pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
+    if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
   }
   if (nsteps == 0) return RT_OK;
   auto body = [&]() -> rt_status {
@@ -884,6 +952,7 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
         (ckpt_every > 1 && !h_seg[i]))
       return b->fail(RT_EINVAL, "NULL per-channel pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
+    if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
   }
   auto body = [&]() -> rt_status {
     rt_status st = RT_OK;

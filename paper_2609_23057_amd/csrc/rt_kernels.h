@@ -37,6 +37,11 @@ struct StepArgs {
   // adjoint
   const float *lam_next;   // lambda_{t+1}
   double *gacc;            // [3][C]: g_alpha, g_beta, g_emis accumulators
+  // phase mixture (forward only; frac == nullptr: none): the scattering of
+  // cell c follows M with weight 1 - frac[c] and M2 with weight frac[c]
+  const uint4 *frag2;      // A fragments of M2, in the contraction precision
+  const TileRange *tiles2; // [Rpad / 32]
+  const float *frac;       // [C]
 };
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };

@@ -410,12 +410,14 @@ __device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red
   return (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, bool MIX = false>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
                                            int64_t tile, bool active, int t, int wg, int W, int lane) {
   static_assert(NB == 1 || (NB == 2 && !ADJ && (PREC == P_F32 || PREC == P_BF16)),
                 "two column blocks: forward float32 or bf16");
+  static_assert(!MIX || (!ADJ && NB == 1 && (PREC == P_F32 || PREC == P_BF16)),
+                "phase mixtures: forward float32 or bf16, one column block");
   // bf16 contraction with two column blocks: X lives as high + low tiles
   constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
   const int col = lane & 31;
@@ -451,6 +453,8 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   LaneCell lcs[NB];
   bool inter[NB];
   float al[NB], be[NB], em[NB];
+  float fr[MIX ? NB : 1];   // phase-mixture fraction of the second matrix
+  (void)fr;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     cscale[cb] = 1.0f;
@@ -469,6 +473,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     al[cb] = a.alpha[lc.c];
     be[cb] = a.beta[lc.c];
     em[cb] = a.emis[lc.c];
+    if constexpr (MIX) fr[cb] = a.frac[lc.c];
     // A block is interior when every tap of every cell lies inside the lattice
     // (taps reach at most two cells either way); then no wrap or ghost is needed.
     const int c_last = (int)((base + 32 < g.C ? (int64_t)base + 32 : g.C) - 1);
@@ -589,73 +594,93 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   f32x16 acc[NB];
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) acc[cb] = f32x16{0};
-  const int nsteps = (nk + kRing - 1) / kRing * kRing;
-  // B fragments (16 bytes per lane per column block; bf16x3 also the low
-  // part) are read from LDS one step ahead, so that their latency overlaps
-  // the previous step's matrix-core work instead of preceding this step's
-  constexpr int kLo = PREC == P_BF16X3 ? 2 : 1;
-  auto bfrag = [&](int cb, int s, int part) -> uint4 {
-    const int kb = tr.klo + kStep * min(s, nk - 1);
-    const char *bcell = s_b + (32 * cb + col) * L.strideB;
-    const char *p = PREC == P_F32 ? bcell + (kb + 4 * h) * 4 : bcell + (kb + 8 * h) * 2 + part * L.tileB;
-    return *reinterpret_cast<const uint4 *>(p);
-  };
-  uint4 bcur[NB][kLo];
+  // One contraction over the B tile: acc[cb] += A B for the tile's K range,
+  // A from the fragment table Ap (and Alop for bf16x3), ring rg / rgl
+  // already holding its first kRing steps.
+  auto contract = [&](const uint4 *Ap, const uint4 *Alop, const TileRange &trr, int nkk, uint4 (&rg)[kRing],
+                      uint4 (&rgl)[PREC == P_BF16X3 ? kRing : 1], f32x16 (&ac)[NB]) {
+    const int nsteps = (nkk + kRing - 1) / kRing * kRing;
+    // B fragments (16 bytes per lane per column block; bf16x3 also the low
+    // part) are read from LDS one step ahead, so that their latency overlaps
+    // the previous step's matrix-core work instead of preceding this step's
+    constexpr int kLo = PREC == P_BF16X3 ? 2 : 1;
+    auto bfrag = [&](int cb, int s, int part) -> uint4 {
+      const int kb = trr.klo + kStep * min(s, nkk - 1);
+      const char *bcell = s_b + (32 * cb + col) * L.strideB;
+      const char *p = PREC == P_F32 ? bcell + (kb + 4 * h) * 4 : bcell + (kb + 8 * h) * 2 + part * L.tileB;
+      return *reinterpret_cast<const uint4 *>(p);
+    };
+    uint4 bcur[NB][kLo];
 #pragma unroll
-  for (int cb = 0; cb < NB; ++cb)
+    for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-    for (int u = 0; u < kLo; ++u) bcur[cb][u] = bfrag(cb, 0, u);
-  for (int s0 = 0; s0 < nsteps; s0 += kRing) {
+      for (int u = 0; u < kLo; ++u) bcur[cb][u] = bfrag(cb, 0, u);
+    for (int s0 = 0; s0 < nsteps; s0 += kRing) {
 #pragma unroll
-    for (int j = 0; j < kRing; ++j) {
-      const int s = s0 + j;
-      const uint4 araw = ring[j], araw_lo = ring_lo[PREC == P_BF16X3 ? j : 0];
-      if constexpr (kRing == 1) {
-        // a single slot: refill at once, so the load overlaps this step
-        ring[j] = A[frag_rec(tr, s + kRing, nk)];
-        if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
-      }
-      uint4 bnext[NB][kLo];
+      for (int j = 0; j < kRing; ++j) {
+        const int s = s0 + j;
+        const uint4 araw = rg[j], araw_lo = rgl[PREC == P_BF16X3 ? j : 0];
+        if constexpr (kRing == 1) {
+          // a single slot: refill at once, so the load overlaps this step
+          rg[j] = Ap[frag_rec(trr, s + kRing, nkk)];
+          if (PREC == P_BF16X3) rgl[j] = Alop[frag_rec(trr, s + kRing, nkk)];
+        }
+        uint4 bnext[NB][kLo];
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
+        for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-        for (int u = 0; u < kLo; ++u) bnext[cb][u] = bfrag(cb, s + 1, u);
+          for (int u = 0; u < kLo; ++u) bnext[cb][u] = bfrag(cb, s + 1, u);
 #pragma unroll
-      for (int cb = 0; cb < NB; ++cb) {
-        if (PREC == P_F32) {
-          const f32x4 av = __builtin_bit_cast(f32x4, araw);
-          const f32x4 bv = __builtin_bit_cast(f32x4, bcur[cb][0]);
-          acc[cb] = mfma_step_f32(av[0], bv[0], acc[cb]);
-          acc[cb] = mfma_step_f32(av[1], bv[1], acc[cb]);
-          acc[cb] = mfma_step_f32(av[2], bv[2], acc[cb]);
-          acc[cb] = mfma_step_f32(av[3], bv[3], acc[cb]);
-        } else if (PREC == P_F16) {
-          const f16x8 av = __builtin_bit_cast(f16x8, araw);
-          const f16x8 bv = __builtin_bit_cast(f16x8, bcur[cb][0]);
-          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[cb], 0, 0, 0);
-        } else {
-          const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
-          const bf16x8 bv = __builtin_bit_cast(bf16x8, bcur[cb][0]);
-          if (PREC == P_BF16X3) {
-            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
-            const bf16x8 blo = __builtin_bit_cast(bf16x8, bcur[cb][kLo - 1]);
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, acc[cb], 0, 0, 0);
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, acc[cb], 0, 0, 0);
+        for (int cb = 0; cb < NB; ++cb) {
+          if (PREC == P_F32) {
+            const f32x4 av = __builtin_bit_cast(f32x4, araw);
+            const f32x4 bv = __builtin_bit_cast(f32x4, bcur[cb][0]);
+            ac[cb] = mfma_step_f32(av[0], bv[0], ac[cb]);
+            ac[cb] = mfma_step_f32(av[1], bv[1], ac[cb]);
+            ac[cb] = mfma_step_f32(av[2], bv[2], ac[cb]);
+            ac[cb] = mfma_step_f32(av[3], bv[3], ac[cb]);
+          } else if (PREC == P_F16) {
+            const f16x8 av = __builtin_bit_cast(f16x8, araw);
+            const f16x8 bv = __builtin_bit_cast(f16x8, bcur[cb][0]);
+            ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, ac[cb], 0, 0, 0);
+          } else {
+            const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
+            const bf16x8 bv = __builtin_bit_cast(bf16x8, bcur[cb][0]);
+            if (PREC == P_BF16X3) {
+              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+              const bf16x8 blo = __builtin_bit_cast(bf16x8, bcur[cb][kLo - 1]);
+              ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, ac[cb], 0, 0, 0);
+              ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, ac[cb], 0, 0, 0);
+            }
+            ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, ac[cb], 0, 0, 0);
           }
-          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[cb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int u = 0; u < kLo; ++u) bcur[cb][u] = bnext[cb][u];
+        if constexpr (kRing > 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          rg[j] = Ap[frag_rec(trr, s + kRing, nkk)];
+          if (PREC == P_BF16X3) rgl[j] = Alop[frag_rec(trr, s + kRing, nkk)];
         }
       }
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-        for (int u = 0; u < kLo; ++u) bcur[cb][u] = bnext[cb][u];
-      if constexpr (kRing > 1) {
-        __builtin_amdgcn_sched_barrier(0);
-        ring[j] = A[frag_rec(tr, s + kRing, nk)];
-        if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, s + kRing, nk)];
-      }
     }
+  };
+  contract(A, Alo, tr, nk, ring, ring_lo, acc);
+  // phase mixture: the second collision matrix's product from the same B tile
+  f32x16 acc2[MIX ? NB : 1];
+  if constexpr (MIX) {
+    const TileRange tr2 = a.tiles2[t];
+    const int nk2 = (tr2.khi - tr2.klo) / kStep;
+    const uint4 *A2 = a.frag2 + lane;
+#pragma unroll
+    for (int j = 0; j < kRing; ++j) ring[j] = A2[frag_rec(tr2, j, nk2)];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc2[cb] = f32x16{0};
+    contract(A2, Alo, tr2, nk2, ring, ring_lo, acc2);
   }
+  (void)acc2;
 
   // ---- 4. epilogue -------------------------------------------------------------
   float part[3] = {0.0f, 0.0f, 0.0f};
@@ -702,7 +727,10 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int i = 4 * q + s;
-        const float prod = acc[cb][i] * unscale;
+        float prod = acc[cb][i] * unscale;
+        // mixture: (1 - f) M X + f M2 X, formed as p0 + f (p1 - p0) (exactly
+        // p0 for f = 0)
+        if constexpr (MIX) prod = fmaf(fr[cb], acc2[cb][i] * unscale - prod, prod);
         float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
         if (!ADJ) {
           *o = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
@@ -775,7 +803,7 @@ constexpr int kFusedRing = MAXW <= 4 ? 4 : ((!ADJ && PREC != P_F32 && PREC != P_
 template <int PREC, bool ADJ, int MAXW>
 constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4 : 1;
 
-template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB>
+template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, bool MIX>
 __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW>)))
 fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
@@ -815,8 +843,8 @@ fused_kernel(StepArgs a, int64_t ntiles) {
     // which would not fit in VGPRs, without holding a second copy.
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB>(a, g, L, ts, tr, ldk, tile, true, t, t, W,
-                                                                           lane);
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, MIX>(a, g, L, ts, tr, ldk, tile, true, t,
+                                                                                t, W, lane);
   }
 }
 
@@ -988,12 +1016,12 @@ hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t n
   return hipErrorInvalidValue;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, bool MIX = false>
 hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
   const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
   const int64_t ntiles = (a.geo.C + 32 * NB - 1) / (32 * NB);
-  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB>;
+  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, MIX>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
   // persistent grid: as many blocks as are resident at once, so that no block
@@ -1011,6 +1039,14 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
+  if (a.frac != nullptr) {
+    // phase mixture: forward fp32 / bf16, 32-cell tiles
+    if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
+      if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, true>(a, W, s, cu_count);
+      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, true>(a, W, s, cu_count);
+    }
+    return hipErrorInvalidValue;
+  }
   if (W <= 4) {
     if constexpr (!ADJ && PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2>(a, W, s, cu_count);
     return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1>(a, W, s, cu_count);

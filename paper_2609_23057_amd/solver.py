@@ -111,6 +111,17 @@ class Solver:
         self._medium = (tau, albedo, emis)
         A.rt_set_medium(self.ctx, _ptr(tau), _ptr(albedo), _ptr(emis), jp, inf)
 
+    def set_phase_mixture(self, phase, frac):
+        """Per-cell mixture: a fraction frac (device [ny, nx] float32) of the
+        scattering follows `phase` ({"kind", "g", "mix_ray"}); None removes it."""
+        if phase is None:
+            A.rt_set_phase_mixture(self.ctx, -1, 0.0, 1.0, None)
+            self._frac = None
+            return
+        self._frac = frac
+        A.rt_set_phase_mixture(self.ctx, _PHASE[phase.get("kind", "rayleigh")], float(phase.get("g", 0.0)),
+                               float(phase.get("mix_ray", 1.0)), _ptr(frac))
+
     def step(self, S_in, S_out):
         A.rt_step(self.ctx, _ptr(S_in), _ptr(S_out))
 

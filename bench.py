@@ -13,7 +13,8 @@ second of that step.  All inputs are resident in HBM before timing starts.
 
 Extras (skipped with --no-extras): forward rates at 1024x1024, n = 128 per
 contraction precision, the stand-alone streaming kernel's HBM rate at beam512
-and prec1024, and the 64-channel spectral batch (one launch per step for all
+and prec1024, the forward step with a per-cell phase-function mixture at
+beam512, and the 64-channel spectral batch (one launch per step for all
 channels, eager and as a replayed HIP graph).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
@@ -165,6 +166,43 @@ def precision_extras(T=20, warm=3):
         res[k]["speedup_vs_plain_fp32"] = (res[k]["cell_dir_updates_per_s"]
                                            / res["plain"]["cell_dir_updates_per_s"])
     return {"workload": "prec1024: 1024x1024, n=128 (8x16), forward steps", "steps": T, "rates": res}
+
+
+def mixture_extras(T=20, warm=3):
+    """Forward rate of the fused step with a per-cell phase-function mixture
+    (HG(0.7) and Rayleigh, fraction U[0, 1] per cell) at beam512, beside the
+    single-phase step, per contraction precision; the mixture contracts two
+    collision matrices per cell."""
+    import numpy as np
+    import torch
+    import workloads as W
+    spec = W.spec("beam512", mixture={"kind": "rayleigh"})
+    C, n = spec["nx"] * spec["ny"], W.ndir(spec)
+    frac_host = W.medium(spec)["frac"]
+    res = {}
+    for prec in ("fp32", "bf16"):
+        solver = make_solver(spec, prec)
+        frac = torch.tensor(np.ascontiguousarray(frac_host), dtype=torch.float32, device=solver.device)
+        S = solver.empty_state()
+        out = {}
+        for mode in ("single", "mixture"):
+            _log("bench: beam512 %s %s" % (prec, mode))
+            solver.set_phase_mixture(spec["mixture"] if mode == "mixture" else None, frac)
+            solver.run(S, warm)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            solver.run(S, T)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            out[mode] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+        out["mixture_cost"] = out["mixture"]["ms_per_time_step"] / out["single"]["ms_per_time_step"]
+        res[prec] = out
+        del solver, S, frac
+        torch.cuda.empty_cache()
+    return {"workload": "beam512 with a per-cell HG(0.7) / Rayleigh mixture, forward steps", "steps": T,
+            "rates": res}
 
 
 def streaming_extras(reps=50):
@@ -368,6 +406,8 @@ def main():
         line["precision_speedup"] = precision_extras()
         torch.cuda.empty_cache()
         line["streaming"] = streaming_extras()
+        torch.cuda.empty_cache()
+        line["phase_mixture"] = mixture_extras()
         torch.cuda.empty_cache()
         line["spectral_batch"] = spectral_extras()
         torch.cuda.empty_cache()

@@ -359,13 +359,13 @@ def make_problem(spec, medium):
     ph = spec.get("phase", {"kind": "rayleigh"})
     M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
                                 ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
-                                spec.get("scalar", False))
+                                spec.get("scalar", False), ph.get("table"))
     M2 = None
     if spec.get("mixture") is not None:
         ph2 = spec["mixture"]
         M2 = _phase.collision_matrix(dirs, ph2.get("kind", "rayleigh"), ph2.get("g", 0.0),
                                      ph2.get("mix_ray", 1.0), spec.get("renorm_irow", False),
-                                     spec.get("scalar", False))
+                                     spec.get("scalar", False), ph2.get("table"))
     return Problem(spec["nx"], spec["ny"], dirs, shifts, M, spec.get("dt", 1.0), spec["bc"],
                    medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
                    medium.get("inflow"), spec.get("abs_taylor", False),

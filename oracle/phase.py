@@ -24,6 +24,17 @@ Readings (see the design notes for the full list):
     the (1+cos^2)/2 factor twice and loses energy.
   * Heyney-Greenstein and Rayleigh/HG mixtures keep the Rayleigh reduced
     matrix and change only the Eq. 17 weights (phase function p).
+  * General scattering matrices (the full-Mueller representation that the
+    conclusions name as future work, e.g. Mie particles with P34 != 0): a
+    table of the six elements of a mirror-symmetric, macroscopically
+    isotropic medium's matrix against the scattering angle,
+        F = [[a1, b1, 0, 0], [b1, a2, 0, 0], [0, 0, a3, b2], [0, 0, -b2, a4]]
+    in the scattering-plane frame (e_par, n), linearly interpolated in the
+    angle (degrees).  It takes the place of P~ in Eq. 13; a1 is the phase
+    function of the Eq. 17 weights.  For a single particle with amplitude
+    functions S1 (perpendicular) and S2 (parallel), a1 = a2 = (|S1|^2 +
+    |S2|^2)/2, b1 = (|S2|^2 - |S1|^2)/2, a3 = a4 = Re(S2 S1*) and
+    b2 = -Im(S2 S1*) when V = 2 Im(E_1 E_2*).
 """
 import numpy as np
 
@@ -75,13 +86,51 @@ def rpr_angles(dirs, d_out, d_in):
     return cos_t, sig_in, sig_out
 
 
-def pair_matrix(dirs, d_out, d_in):
-    """Z = R(sigma_out) P~(theta) R(sigma_in), Eq. 13."""
+def table_reduced(cos_t, table):
+    """F(theta) from a table of rows (theta_deg, a1, a2, a3, a4, b1, b2),
+    linear in theta between rows (rows from 0 to 180 degrees)."""
+    tab = np.asarray(table, dtype=np.float64)
+    th = np.degrees(np.arccos(np.clip(float(cos_t), -1.0, 1.0)))
+    a1, a2, a3, a4, b1, b2 = (np.interp(th, tab[:, 0], tab[:, j]) for j in range(1, 7))
+    return np.array([[a1, b1, 0.0, 0.0],
+                     [b1, a2, 0.0, 0.0],
+                     [0.0, 0.0, a3, b2],
+                     [0.0, 0.0, -b2, a4]])
+
+
+def check_table(table):
+    """Rows (theta_deg, a1, a2, a3, a4, b1, b2): at least two, angles strictly
+    increasing from 0 to 180, finite, a1 > 0, and the rows at 0 and 180
+    degrees invariant under a rotation of the scattering plane (to 1e-6 of
+    a1), where the plane n = e_phi(in) is used."""
+    tab = np.asarray(table, dtype=np.float64)
+    if tab.ndim != 2 or tab.shape[1] != 7 or tab.shape[0] < 2:
+        raise ValueError("table must have shape (>= 2, 7)")
+    if not np.all(np.isfinite(tab)):
+        raise ValueError("table not finite")
+    if tab[0, 0] != 0.0 or tab[-1, 0] != 180.0 or np.any(np.diff(tab[:, 0]) <= 0.0):
+        raise ValueError("table angles must increase strictly from 0 to 180 degrees")
+    if np.any(tab[:, 1] <= 0.0):
+        raise ValueError("table a1 must be > 0")
+    # forward and backward the scattering plane is undefined: F must not
+    # depend on it (b1 = b2 = 0, a3 = a2 forward, a3 = -a2 backward)
+    f, b = tab[0], tab[-1]
+    tol = 1e-6
+    if (abs(f[5]) > tol * f[1] or abs(f[6]) > tol * f[1] or abs(f[3] - f[2]) > tol * f[1]
+            or abs(b[5]) > tol * b[1] or abs(b[6]) > tol * b[1] or abs(b[3] + b[2]) > tol * b[1]):
+        raise ValueError("table rows at 0 and 180 degrees must not depend on the scattering plane")
+    return tab
+
+
+def pair_matrix(dirs, d_out, d_in, reduced=None):
+    """Z = R(sigma_out) F(theta) R(sigma_in), Eq. 13; F is the Rayleigh P~
+    unless `reduced` (a function of cos theta) gives another."""
     cos_t, s_in, s_out = rpr_angles(dirs, d_out, d_in)
-    return mueller_rotation(s_out) @ rayleigh_reduced(cos_t) @ mueller_rotation(s_in)
+    F = rayleigh_reduced(cos_t) if reduced is None else reduced(cos_t)
+    return mueller_rotation(s_out) @ F @ mueller_rotation(s_in)
 
 
-def phase_function(cos_t, kind="rayleigh", g=0.0, mix_ray=1.0):
+def phase_function(cos_t, kind="rayleigh", g=0.0, mix_ray=1.0, table=None):
     """Scalar phase function p(theta), normalised to 1 over 4 pi.
 
     rayleigh   3/(16 pi) (1 + cos^2)            (Eq. 16, element 11 x 2)
@@ -89,6 +138,8 @@ def phase_function(cos_t, kind="rayleigh", g=0.0, mix_ray=1.0):
     mix        mix_ray * p_rayleigh + (1-mix_ray) * p_hg
     """
     c = np.asarray(cos_t, dtype=np.float64)
+    if kind == "table":
+        return table_reduced(c, table)[0, 0]
     pr = 3.0 / (16.0 * np.pi) * (1.0 + c * c)
     if kind == "rayleigh":
         return pr
@@ -100,20 +151,20 @@ def phase_function(cos_t, kind="rayleigh", g=0.0, mix_ray=1.0):
     raise ValueError(kind)
 
 
-def weights(dirs, kind="rayleigh", g=0.0, mix_ray=1.0):
+def weights(dirs, kind="rayleigh", g=0.0, mix_ray=1.0, table=None):
     """Eq. 17: w[out, in] = p(theta) dOmega_out / sum_out p(theta) dOmega_out."""
     n = dirs.n
     w = np.zeros((n, n))
     for di in range(n):
         for do in range(n):
             ct = float(np.clip(np.dot(dirs.k[do], dirs.k[di]), -1.0, 1.0))
-            w[do, di] = phase_function(ct, kind, g, mix_ray) * dirs.domega[do]
+            w[do, di] = phase_function(ct, kind, g, mix_ray, table) * dirs.domega[do]
         w[:, di] /= w[:, di].sum()
     return w
 
 
 def collision_matrix(dirs, kind="rayleigh", g=0.0, mix_ray=1.0,
-                     renorm_irow=False, scalar=False):
+                     renorm_irow=False, scalar=False, table=None):
     """The 4n x 4n direction-pair sum of Eq. 25/30.
 
     Index convention: row/column 4*d + s, s in (I, Q, U, V).  Column block d_in
@@ -127,7 +178,11 @@ def collision_matrix(dirs, kind="rayleigh", g=0.0, mix_ray=1.0,
                  exactly for polarised fields (an option, not in the paper).
     """
     n = dirs.n
-    w = weights(dirs, kind, g, mix_ray)
+    reduced = None
+    if kind == "table":
+        table = check_table(table)
+        reduced = lambda c: table_reduced(c, table)  # noqa: E731
+    w = weights(dirs, kind, g, mix_ray, table)
     M = np.zeros((4 * n, 4 * n))
     for di in range(n):
         for do in range(n):
@@ -135,7 +190,7 @@ def collision_matrix(dirs, kind="rayleigh", g=0.0, mix_ray=1.0,
                 blk = np.zeros((4, 4))
                 blk[0, 0] = 1.0
             else:
-                Z = pair_matrix(dirs, do, di)
+                Z = pair_matrix(dirs, do, di, reduced)
                 blk = Z / Z[0, 0]
             M[4 * do:4 * do + 4, 4 * di:4 * di + 4] = w[do, di] * blk
     if renorm_irow and not scalar:

@@ -23,6 +23,9 @@ Workloads (the paper's method at the sizes it is benchmarked on here):
                top-edge (I + DoLP) loss after 500 steps
   (any)        with mixture={phase}: a second phase function and a per-cell
                fraction U[0, 1] of the scattering that follows it
+  (any)        with phase={"kind": "table", "table": scattering_table()}: a
+               tabulated scattering matrix of an aerosol-like particle
+               (forward peak, P12 < 0 at side angles, P34 != 0)
   spectral64   64 channels 400-900 nm, Rayleigh optical depth ~ lambda^-4 plus
                aerosol HG(0.6), per-channel lattice and direction count drawn
                from {128,256,384,512}^2 x {16,32,64}, 200 steps
@@ -164,3 +167,35 @@ def spectral_channels(nchan=64, seed=5):
                  source="none", name="spectral64[%d]" % k, wavelength_nm=lam)
         out.append(s)
     return out
+
+
+def scattering_table(seed=6, nang=181, g=0.6):
+    """A tabulated scattering matrix, rows (theta_deg, a1, a2, a3, a4, b1, b2)
+    at nang angles from 0 to 180 degrees, of a synthetic single particle:
+    amplitude functions S1 = sqrt(e) exp(i alpha), S2 = sqrt(e) r exp(i beta)
+    with an HG(g)-shaped envelope e plus a floor, a parallel/perpendicular
+    ratio r = 0.3 + 0.7 cos^2 (side-scattered light polarised), and smooth
+    phase lags alpha, beta drawn from the seed, with S2 = S1 forward and
+    S2 = -S1 backward (as for any particle with a symmetry plane, so the
+    matrix does not depend on the scattering plane where that plane is
+    undefined).  Then a1 = a2 = (|S1|^2 +
+    |S2|^2) / 2, b1 = (|S2|^2 - |S1|^2) / 2, a3 = a4 = Re(S2 S1*),
+    b2 = -Im(S2 S1*) (Stokes V = 2 Im(E_1 E_2*)).  This draws an input; it is
+    not the solver's arithmetic.
+    """
+    rng = np.random.default_rng(seed)
+    th = np.linspace(0.0, 180.0, nang)
+    t = np.radians(th)
+    c = np.cos(t)
+    e = (1.0 - g * g) / (1.0 + g * g - 2.0 * g * c) ** 1.5 + 0.05
+    r = 0.3 + 0.7 * c * c
+    p1, p2 = rng.uniform(0.3, 0.9, size=2)
+    alpha = p1 * np.sin(t)
+    beta = p2 * np.sin(t) + np.pi * np.sin(0.5 * t) ** 2
+    S1 = np.sqrt(e) * np.exp(1j * alpha)
+    S2 = np.sqrt(e) * r * np.exp(1j * beta)
+    a1 = 0.5 * (np.abs(S1) ** 2 + np.abs(S2) ** 2)
+    b1 = 0.5 * (np.abs(S2) ** 2 - np.abs(S1) ** 2)
+    z = S2 * np.conj(S1)
+    tab = np.stack([th, a1, a1, z.real, z.real, b1, -z.imag], axis=1)
+    return _f32(tab)

@@ -90,7 +90,10 @@ def table_reduced(cos_t, table):
     """F(theta) from a table of rows (theta_deg, a1, a2, a3, a4, b1, b2),
     linear in theta between rows (rows from 0 to 180 degrees)."""
     tab = np.asarray(table, dtype=np.float64)
-    th = np.degrees(np.arccos(np.clip(float(cos_t), -1.0, 1.0)))
+    c = float(cos_t)
+    # arccos loses half the digits next to +-1: cosines within 1e-12 of +-1
+    # are the forward / backward rows themselves
+    th = 0.0 if c >= 1.0 - 1e-12 else (180.0 if c <= -1.0 + 1e-12 else np.degrees(np.arccos(c)))
     a1, a2, a3, a4, b1, b2 = (np.interp(th, tab[:, 0], tab[:, j]) for j in range(1, 7))
     return np.array([[a1, b1, 0.0, 0.0],
                      [b1, a2, 0.0, 0.0],

@@ -79,12 +79,29 @@ typedef enum { RT_PLANE_XY = 0, RT_PLANE_XZ = 1, RT_PLANE_XY_D2Q9 = 2 } rt_plane
  * prescribed radiance per edge and direction to what enters. */
 typedef enum { RT_BC_PERIODIC = 0, RT_BC_ABSORBING = 1, RT_BC_INFLOW = 2 } rt_bc;
 
-/* Scalar phase function used in the Eq. 17 weights.  The polarisation part
- * is always the Rayleigh reduced matrix rotated into the meridian frames
- * (Eq. 13, 16), so HG and the mixture carry Rayleigh-shaped P12/P33/P44
- * ratios.  HG(g) = (1-g^2)/(4 pi (1+g^2-2g cos)^1.5); the mixture is
- * mix_ray * Rayleigh + (1 - mix_ray) * HG(g). */
-typedef enum { RT_PHASE_RAYLEIGH = 0, RT_PHASE_HG = 1, RT_PHASE_MIX = 2 } rt_phase;
+/* Scalar phase function used in the Eq. 17 weights.  For the first three
+ * kinds the polarisation part is the Rayleigh reduced matrix rotated into the
+ * meridian frames (Eq. 13, 16), so HG and the mixture carry Rayleigh-shaped
+ * P12/P33/P44 ratios.  HG(g) = (1-g^2)/(4 pi (1+g^2-2g cos)^1.5); the mixture
+ * is mix_ray * Rayleigh + (1 - mix_ray) * HG(g).
+ *
+ * RT_PHASE_TABLE: a general scattering matrix (the full-Mueller
+ * representation the paper's conclusions name as future work; Mie-type
+ * particles with P12 and P34 != 0), tabulated against the scattering angle.
+ * rt_problem.table holds n_table rows (theta_deg, a1, a2, a3, a4, b1, b2) of
+ *     F = [[a1, b1, 0, 0], [b1, a2, 0, 0], [0, 0, a3, b2], [0, 0, -b2, a4]]
+ * referred to the scattering plane (axes e_par = n x k and n = k_in x k_out
+ * normalised; Q = |E_par|^2 - |E_n|^2, U = 2 Re(E_par E_n*),
+ * V = 2 Im(E_par E_n*)), with theta strictly increasing from exactly 0 to
+ * exactly 180 and every a1 > 0.  F is linear in theta between rows; it takes
+ * the place of the Rayleigh matrix in Eq. 13 and a1 is the phase function
+ * of Eq. 17.  Forward and backward, where the scattering plane is undefined
+ * (n = e_phi of the incoming direction is used), F must not depend on it:
+ * b1 = b2 = 0 and a3 = a2 at 0 degrees, a3 = -a2 at 180 degrees, to 1e-6 of
+ * a1.  For one particle with amplitude functions S1 (perpendicular) and S2
+ * (parallel): a1 = a2 = (|S1|^2+|S2|^2)/2, b1 = (|S2|^2-|S1|^2)/2,
+ * a3 = a4 = Re(S2 S1*), b2 = -Im(S2 S1*). */
+typedef enum { RT_PHASE_RAYLEIGH = 0, RT_PHASE_HG = 1, RT_PHASE_MIX = 2, RT_PHASE_TABLE = 3 } rt_phase;
 
 /* Option flags. */
 enum {
@@ -111,6 +128,8 @@ typedef struct {
   double dt;                  /* time step multiplying the source J (Eq. 2, Eq. 8) */
   uint32_t flags;             /* RT_* option flags */
   int32_t precision;          /* rt_precision */
+  int32_t n_table;            /* rows of `table` for RT_PHASE_TABLE (2 .. 65536), else ignored */
+  const double *table;        /* host [n_table][7] for RT_PHASE_TABLE, else NULL; copied by rt_init */
 } rt_problem;
 
 /* ---- host-only helpers (no device needed) ------------------------------ */
@@ -160,7 +179,8 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
 /* Per-cell mixture of two phase functions.  With it set, the scattered part
  * of the collision becomes beta ((1 - f) M X + f M2 X): M is the context's
  * collision matrix, M2 the one a problem with phase2 / g2 / mix_ray2 (same
- * meaning as rt_problem's phase / g / mix_ray) and otherwise the context's
+ * meaning as rt_problem's phase / g / mix_ray; RT_PHASE_TABLE is not
+ * accepted here) and otherwise the context's
  * own fields would build, each normalised as Eq. 17 prescribes, and f the
  * per-cell fraction d_frac (device [ny][nx] float32, values in [0, 1],
  * copied into the workspace).  Every later rt_step / rt_run uses it; phase2 < 0

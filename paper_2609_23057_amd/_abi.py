@@ -17,7 +17,7 @@ RT_FP32, RT_BF16, RT_FP16, RT_BF16X3 = range(4)
 RT_ZEN_EQUAL_AREA, RT_ZEN_UNIFORM_THETA, RT_ZEN_EXPLICIT = range(3)
 RT_PLANE_XY, RT_PLANE_XZ, RT_PLANE_XY_D2Q9 = range(3)
 RT_BC_PERIODIC, RT_BC_ABSORBING, RT_BC_INFLOW = range(3)
-RT_PHASE_RAYLEIGH, RT_PHASE_HG, RT_PHASE_MIX = range(3)
+RT_PHASE_RAYLEIGH, RT_PHASE_HG, RT_PHASE_MIX, RT_PHASE_TABLE = range(4)
 RT_ABS_TAYLOR, RT_SCAT_EXP, RT_FUSED_TAYLOR, RT_RENORM_IROW, RT_SCALAR, RT_PLAIN = (
     1, 2, 4, 8, 16, 32)
 
@@ -29,7 +29,8 @@ class RtProblem(ctypes.Structure):
                 ("zen_rule", c_int32), ("zen_deg", POINTER(c_double)),
                 ("az_offset_deg", c_double), ("plane", c_int32), ("courant", c_double),
                 ("bc", c_int32 * 4), ("phase", c_int32), ("g", c_double), ("mix_ray", c_double),
-                ("dt", c_double), ("flags", c_uint32), ("precision", c_int32)]
+                ("dt", c_double), ("flags", c_uint32), ("precision", c_int32),
+                ("n_table", c_int32), ("table", POINTER(c_double))]
 
 
 class RTError(RuntimeError):

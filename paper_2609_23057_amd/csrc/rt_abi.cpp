@@ -136,6 +136,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
 struct rt_ctx {
   rt_problem prob{};
   std::vector<double> zen;
+  std::vector<double> table;   // copy of a tabulated scattering matrix
   HostPlan hp;
   Packed pk;
   Layout L{};
@@ -308,6 +309,13 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
   } else {
     c->prob.zen_deg = nullptr;
   }
+  if (p->phase == RT_PHASE_TABLE) {
+    c->table.assign(p->table, p->table + 7 * (size_t)p->n_table);
+    c->prob.table = c->table.data();
+  } else {
+    c->prob.table = nullptr;
+    c->prob.n_table = 0;
+  }
   std::string msg;
   st = plan_for(&c->prob, &c->hp, &c->pk, &c->L, &msg);
   if (st != RT_OK) {
@@ -440,12 +448,15 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
   if ((c->prob.flags & RT_PLAIN) || (c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16))
     return c->fail(RT_EUNSUPPORTED, "phase mixtures run on the fused fp32 and bf16 paths only");
   if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
+  if (phase2 == RT_PHASE_TABLE) return c->fail(RT_EINVAL, "the second phase function cannot be a table");
   // the second collision matrix: the same direction set and options, another
   // scalar phase function (Eq. 17 weights, Rayleigh polarisation part)
   rt_problem p2 = c->prob;
   p2.phase = phase2;
   p2.g = g2;
   p2.mix_ray = mix_ray2;
+  p2.n_table = 0;
+  p2.table = nullptr;
   HostPlan hp2;
   std::string msg;
   rt_status st = build_plan(&p2, &hp2, &msg);

@@ -36,6 +36,26 @@ double phase_fn(int kind, double c, double g, double mix) {
   return mix * pr + (1.0 - mix) * phg;
 }
 
+// The six elements (a1, a2, a3, a4, b1, b2) of a tabulated scattering matrix
+// at cos(theta) = c: linear in theta (degrees) between the rows
+// (theta_deg, a1, a2, a3, a4, b1, b2) of `tab`, whose angles rise from 0 to 180.
+void table_elements(const double *tab, int rows, double c, double *f) {
+  // acos loses half the digits next to +-1: cosines within 1e-12 of +-1 take
+  // the forward / backward rows
+  const double th = c >= 1.0 - 1e-12 ? 0.0 : (c <= -1.0 + 1e-12 ? 180.0 : std::acos(c) * (180.0 / kPi));
+  int lo = 0, hi = rows - 1;   // tab[lo][0] <= th <= tab[hi][0]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (tab[7 * mid] <= th) lo = mid; else hi = mid;
+  }
+  const double t0 = tab[7 * lo], t1 = tab[7 * hi];
+  const double u = (th - t0) / (t1 - t0);
+  for (int j = 0; j < 6; ++j) {
+    const double v0 = tab[7 * lo + 1 + j], v1 = tab[7 * hi + 1 + j];
+    f[j] = u <= 0.0 ? v0 : (u >= 1.0 ? v1 : v0 + u * (v1 - v0));
+  }
+}
+
 // Mueller matrix (row-major 4x4) of a real Jones matrix a = [[a11,a12],[a21,a22]]
 // acting on (E_theta, E_phi):  I = |E1|^2+|E2|^2, Q = |E1|^2-|E2|^2,
 // U = 2 Re(E1 E2*), V proportional to Im(E1 E2*).
@@ -57,6 +77,53 @@ void jones_to_mueller(double a11, double a12, double a21, double a22, double *Z)
   Z[13] = 0.0;
   Z[14] = 0.0;
   Z[15] = a11 * a22 - a12 * a21;
+}
+
+// Pair matrix of a tabulated scattering matrix, Eq. 13 with F in place of the
+// Rayleigh matrix: the field components in the incoming meridian axes
+// (e_theta, e_phi) are projected onto the scattering-plane axes (e_par, n),
+// F acts there, and the result is projected onto the outgoing meridian axes.
+// Both projections are real rotations; their Mueller matrices are the frame
+// rotations of Eq. 21.  n = k_in x k_out normalised (e_phi of the incoming
+// direction where k_out = +-k_in), e_par = n x k.
+void table_pair(const HostPlan &hp, const double *tab, int rows, int dout, int di, double *Z) {
+  const double *ki = &hp.kvec[3 * di], *ko = &hp.kvec[3 * dout];
+  const double *eti = &hp.eth[3 * di], *epi = &hp.eph[3 * di];
+  const double *eto = &hp.eth[3 * dout], *epo = &hp.eph[3 * dout];
+  double nv[3] = {ki[1] * ko[2] - ki[2] * ko[1], ki[2] * ko[0] - ki[0] * ko[2], ki[0] * ko[1] - ki[1] * ko[0]};
+  const double nn = std::sqrt(dot3(nv, nv));
+  if (nn < 1e-12) {
+    for (int j = 0; j < 3; ++j) nv[j] = epi[j];
+  } else {
+    for (int j = 0; j < 3; ++j) nv[j] /= nn;
+  }
+  auto cross = [](const double *a, const double *b, double *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  double pin[3], pout[3];
+  cross(nv, ki, pin);
+  cross(nv, ko, pout);
+  double Rin[16], Rout[16];
+  jones_to_mueller(dot3(pin, eti), dot3(pin, epi), dot3(nv, eti), dot3(nv, epi), Rin);
+  jones_to_mueller(dot3(eto, pout), dot3(eto, nv), dot3(epo, pout), dot3(epo, nv), Rout);
+  double f[6];
+  table_elements(tab, rows, dot3(ko, ki), f);
+  const double F[16] = {f[0], f[4], 0.0, 0.0, f[4], f[1], 0.0, 0.0, 0.0, 0.0, f[2], f[5], 0.0, 0.0, -f[5], f[3]};
+  double T[16];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double acc = 0.0;
+      for (int k = 0; k < 4; ++k) acc += F[4 * r + k] * Rin[4 * k + c];
+      T[4 * r + c] = acc;
+    }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double acc = 0.0;
+      for (int k = 0; k < 4; ++k) acc += Rout[4 * r + k] * T[4 * k + c];
+      Z[4 * r + c] = acc;
+    }
 }
 
 std::string fmt(const char *what, double v) {
@@ -94,12 +161,38 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
       (p->bc[2] == RT_BC_PERIODIC) != (p->bc[3] == RT_BC_PERIODIC)) {
     *msg = "both edges of an axis must be periodic or neither"; return RT_EINVAL;
   }
-  if (p->phase < 0 || p->phase > 2) { *msg = "phase out of range"; return RT_EINVAL; }
-  if (p->phase != RT_PHASE_RAYLEIGH && !(std::isfinite(p->g) && std::fabs(p->g) < 1.0)) {
+  if (p->phase < 0 || p->phase > 3) { *msg = "phase out of range"; return RT_EINVAL; }
+  if ((p->phase == RT_PHASE_HG || p->phase == RT_PHASE_MIX) && !(std::isfinite(p->g) && std::fabs(p->g) < 1.0)) {
     *msg = fmt("HG asymmetry must satisfy |g| < 1", p->g); return RT_EINVAL;
   }
   if (p->phase == RT_PHASE_MIX && !(p->mix_ray >= 0.0 && p->mix_ray <= 1.0)) {
     *msg = fmt("mix_ray must lie in [0, 1]", p->mix_ray); return RT_EINVAL;
+  }
+  if (p->phase == RT_PHASE_TABLE) {
+    const int rows = p->n_table;
+    const double *t = p->table;
+    if (!t) { *msg = "table is NULL for RT_PHASE_TABLE"; return RT_EINVAL; }
+    if (rows < 2 || rows > 65536) { *msg = fmt("n_table must lie in [2, 65536]", rows); return RT_EINVAL; }
+    for (int r = 0; r < rows; ++r) {
+      for (int j = 0; j < 7; ++j)
+        if (!std::isfinite(t[7 * r + j])) { *msg = fmt("table entry not finite in row", r); return RT_EINVAL; }
+      if (!(t[7 * r + 1] > 0.0)) { *msg = fmt("table a1 must be > 0; row", r); return RT_EINVAL; }
+      if (r > 0 && !(t[7 * r] > t[7 * (r - 1)])) {
+        *msg = fmt("table angles must increase strictly; row", r); return RT_EINVAL;
+      }
+    }
+    if (t[0] != 0.0 || t[7 * (rows - 1)] != 180.0) {
+      *msg = "table angles must run from exactly 0 to exactly 180 degrees"; return RT_EINVAL;
+    }
+    // forward / backward rows must not depend on the (undefined) scattering plane
+    const double *f = t, *b = t + 7 * (rows - 1);
+    const double tf = 1e-6 * f[1], tb = 1e-6 * b[1];
+    if (std::fabs(f[5]) > tf || std::fabs(f[6]) > tf || std::fabs(f[3] - f[2]) > tf || std::fabs(b[5]) > tb ||
+        std::fabs(b[6]) > tb || std::fabs(b[3] + b[2]) > tb) {
+      *msg = "table rows at 0 and 180 degrees depend on the scattering plane (need b1 = b2 = 0, "
+             "a3 = a2 forward, a3 = -a2 backward)";
+      return RT_EINVAL;
+    }
   }
   if (!(std::isfinite(p->dt) && p->dt >= 0)) { *msg = fmt("dt must be finite and >= 0", p->dt); return RT_EINVAL; }
   const uint32_t known = RT_ABS_TAYLOR | RT_SCAT_EXP | RT_FUSED_TAYLOR | RT_RENORM_IROW | RT_SCALAR | RT_PLAIN;
@@ -194,7 +287,14 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
     for (int dout = 0; dout < n; ++dout) {
       double c = dot3(&hp->kvec[3 * dout], &hp->kvec[3 * di]);
       c = std::max(-1.0, std::min(1.0, c));
-      const double v = phase_fn(p->phase, c, p->g, p->mix_ray) * hp->domega[dout];
+      double v;
+      if (p->phase == RT_PHASE_TABLE) {
+        double f[6];
+        table_elements(p->table, p->n_table, c, f);
+        v = f[0] * hp->domega[dout];
+      } else {
+        v = phase_fn(p->phase, c, p->g, p->mix_ray) * hp->domega[dout];
+      }
       w[(size_t)dout * n + di] = v;
       tot += v;
     }
@@ -210,6 +310,10 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
       if (scalar) {
         std::memset(Z, 0, sizeof(Z));
         Z[0] = 1.0;
+      } else if (p->phase == RT_PHASE_TABLE) {
+        table_pair(*hp, p->table, p->n_table, dout, di, Z);
+        const double z11 = Z[0];
+        for (int q = 0; q < 16; ++q) Z[q] /= z11;
       } else {
         const double *eto = &hp->eth[3 * dout], *epo = &hp->eph[3 * dout];
         const double *eti = &hp->eth[3 * di], *epi = &hp->eph[3 * di];

@@ -14,7 +14,7 @@ from . import _abi as A
 _ZEN = {"equal_area": A.RT_ZEN_EQUAL_AREA, "uniform_theta": A.RT_ZEN_UNIFORM_THETA,
         "explicit": A.RT_ZEN_EXPLICIT}
 _PLANE = {"xy": A.RT_PLANE_XY, "xz": A.RT_PLANE_XZ, "xy_d2q9": A.RT_PLANE_XY_D2Q9}
-_PHASE = {"rayleigh": A.RT_PHASE_RAYLEIGH, "hg": A.RT_PHASE_HG, "mix": A.RT_PHASE_MIX}
+_PHASE = {"rayleigh": A.RT_PHASE_RAYLEIGH, "hg": A.RT_PHASE_HG, "mix": A.RT_PHASE_MIX, "table": A.RT_PHASE_TABLE}
 
 
 def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=None,
@@ -38,6 +38,12 @@ def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=No
     p.phase = _PHASE[phase.get("kind", "rayleigh")]
     p.g = float(phase.get("g", 0.0))
     p.mix_ray = float(phase.get("mix_ray", 1.0))
+    if phase.get("kind") == "table":
+        # rows (theta_deg, a1, a2, a3, a4, b1, b2); the library copies them at rt_init
+        tab = np.ascontiguousarray(phase["table"], dtype=np.float64).reshape(-1, 7)
+        p._table_keepalive = tab
+        p.n_table = tab.shape[0]
+        p.table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.dt = float(dt)
     flags = 0
     flags |= A.RT_ABS_TAYLOR if abs_taylor else 0

@@ -137,3 +137,52 @@ def test_init_without_device_reports_error():
     with pytest.raises(P.RTError) as ei:
         P.rt_init(p, 1 << 20, 1 << 30, None)
     assert ei.value.status in (P.RT_EDEVICE, P.RT_EUNSUPPORTED)
+
+
+@pytest.mark.parametrize("grid,flags", [((4, 8, 0.0), {}), ((2, 4, 0.0), {}), ((3, 5, 22.5), {}),
+                                        ((8, 16, 0.0), {}), ((4, 8, 0.0), dict(renorm_irow=True)),
+                                        ((4, 8, 0.0), dict(scalar=True))])
+def test_host_table_matrix_matches_oracle(grid, flags):
+    """A tabulated scattering matrix with P12 and P34 != 0: the library builds
+    each pair by projecting onto the scattering-plane axes (Mueller matrices of
+    the two frame rotations around F), the oracle by the angles of Eq. 13-15;
+    the collision matrices agree to 1e-13."""
+    tab = W.scattering_table()
+    nz, na, off = grid
+    p = P.make_problem(16, 16, nz, na, az_offset_deg=off, plane="xz", bc=(1, 1, 1, 2),
+                       phase={"kind": "table", "table": tab}, **flags)
+    n = nz * na
+    M = np.zeros((4 * n, 4 * n))
+    P.rt_describe(p, None, M)
+    od = ODir.make_directions(nz, na, az_offset_deg=off)
+    Mo = OP.collision_matrix(od, "table", renorm_irow=flags.get("renorm_irow", False),
+                             scalar=flags.get("scalar", False), table=tab)
+    assert np.abs(M - Mo).max() < 1e-13
+    if not flags:
+        assert np.abs(M[3::4, 2::4]).max() > 1e-3     # U -> V through b2
+
+
+@pytest.mark.parametrize("bad", ["short", "order", "ends", "a1", "plane0", "plane180", "nan", "null"])
+def test_table_validation(bad):
+    tab = W.scattering_table()
+    if bad == "short":
+        tab = tab[:1]
+    elif bad == "order":
+        tab[[3, 4]] = tab[[4, 3]]
+    elif bad == "ends":
+        tab = tab[:-1]
+    elif bad == "a1":
+        tab[50, 1] = 0.0
+    elif bad == "plane0":
+        tab[0, 6] = 0.01
+    elif bad == "plane180":
+        tab[-1, 3] = -0.5 * tab[-1, 2]
+    elif bad == "nan":
+        tab[7, 4] = np.nan
+    p = P.make_problem(8, 8, 2, 4, plane="xy", phase={"kind": "table", "table": tab})
+    if bad == "null":
+        p.table = None
+    with pytest.raises(P.RTError) as ei:
+        P.rt_validate(p)
+    assert ei.value.status == P.RT_EINVAL
+    assert P.rt_workspace_bytes(p) == 0

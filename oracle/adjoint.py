@@ -23,6 +23,8 @@ from . import lbm
 
 def adjoint(S0, prob, nsteps, lam_T):
     """Returns dict(lambda0, g_alpha, g_beta, g_tau, g_albedo, g_emis)."""
+    if prob.M2 is not None or prob.eta is not None:
+        raise NotImplementedError("the adjoint covers single-phase, non-dichroic media")
     n, C = prob.n, prob.nx * prob.ny
     J = prob.emission_field()
     e = 0.0 if prob.fused_taylor else 1.0

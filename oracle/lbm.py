@@ -25,6 +25,10 @@ The literal Eq. 2 form (fused first-order Taylor of Igarashi et al., used by
 the paper only for the D1Q2 comparison of Sec. 3.1) is available as
 fused_taylor: Y = (1 - tau_ext) S + tau_sca M S + dt J.
 
+Dichroic absorption (see dichroic_absorption) multiplies the two linear
+polarisations along the meridian axes by their own absorption factors before
+the scattering.
+
 Phase-function mixtures (the per-cell aerosol / cloud fractions that the
 paper's conclusion names as the next step, Sec. 4): a second collision matrix
 M2 and a per-cell fraction f in [0, 1] of the scattering that follows it,
@@ -46,7 +50,7 @@ class Problem:
 
     def __init__(self, nx, ny, dirs, shifts, M, dt, bc, tau, albedo, emis,
                  jprof, inflow=None, abs_taylor=False, scat_exp=False,
-                 fused_taylor=False, M2=None, frac=None):
+                 fused_taylor=False, M2=None, frac=None, dichroism=None):
         self.nx, self.ny = int(nx), int(ny)
         self.dirs = dirs
         self.n = dirs.n
@@ -78,6 +82,14 @@ class Problem:
             self.frac = np.asarray(f, dtype=np.float64).reshape(self.ny, self.nx)
             if np.any(self.frac < 0.0) or np.any(self.frac > 1.0):
                 raise ValueError("mixture fraction outside [0, 1]")
+        # optional dichroic absorption: per-cell linear dichroism eta
+        self.eta = None
+        if dichroism is not None:
+            self.eta = np.asarray(dichroism, dtype=np.float64).reshape(self.ny, self.nx)
+            if np.any(~np.isfinite(self.eta)) or np.any(np.abs(self.eta) >= 1.0):
+                raise ValueError("dichroism eta must satisfy |eta| < 1")
+            if self.abs_taylor or self.fused_taylor:
+                raise ValueError("dichroic absorption is defined for Beer-Lambert absorption")
 
     @property
     def shape(self):
@@ -229,6 +241,29 @@ def stream_transpose(G, prob):
     return out
 
 
+def dichroic_absorption(X, prob):
+    """Polarisation-dependent part of the absorption (dichroic absorption,
+    named as missing in the paper's conclusions).
+
+    The absorption optical depth of direction d becomes the matrix
+    tau_abs K_d with K_d = [[1, eta w_d, 0, 0], [eta w_d, 1, 0, 0], [0, 0, 1, 0],
+    [0, 0, 0, 1]] in the meridian axes, w_d = sin^2 theta_d (aligned
+    particles with their symmetry axis along z: no dichroism along z), so the
+    absorption factor exp(-tau_abs K_d) acts on the two linear polarisations
+    along e_theta (I + Q) and e_phi (I - Q) as exp(-tau_abs (1 +- eta w_d)).
+    The scalar part exp(-tau_abs) is in alpha and beta; this returns X with
+    the remaining factors exp(-+tau_abs eta w_d) applied to I +- Q.
+    """
+    tau_abs = ((1.0 - prob.albedo) * prob.tau * prob.eta).reshape(1, -1)
+    w = np.sin(prob.dirs.theta) ** 2
+    Xd = X.reshape(prob.n, 4, -1).copy()
+    plus = (Xd[:, 0] + Xd[:, 1]) * np.exp(-tau_abs * w[:, None])
+    minus = (Xd[:, 0] - Xd[:, 1]) * np.exp(tau_abs * w[:, None])
+    Xd[:, 0] = 0.5 * (plus + minus)
+    Xd[:, 1] = 0.5 * (plus - minus)
+    return Xd.reshape(X.shape)
+
+
 def collide(S, prob):
     """Emission, absorption and scattering at every cell (steps 1-3)."""
     n = prob.n
@@ -236,6 +271,9 @@ def collide(S, prob):
     J = prob.emission_field()
     e = 0.0 if prob.fused_taylor else 1.0
     X = (S + e * prob.dt * J).reshape(4 * n, C)
+    if prob.eta is not None:
+        # absorption precedes scattering: the dichroic factor acts on X
+        X = dichroic_absorption(X, prob)
     al = prob.alpha.reshape(1, C)
     be = prob.beta.reshape(1, C)
     MX = prob.M @ X
@@ -370,4 +408,4 @@ def make_problem(spec, medium):
                    medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
                    medium.get("inflow"), spec.get("abs_taylor", False),
                    spec.get("scat_exp", False), spec.get("fused_taylor", False),
-                   M2=M2, frac=medium.get("frac"))
+                   M2=M2, frac=medium.get("frac"), dichroism=medium.get("eta"))

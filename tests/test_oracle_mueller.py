@@ -197,3 +197,88 @@ def test_check_table_refusals(bad):
         tab[7, 4] = np.nan
     with pytest.raises(ValueError):
         OP.check_table(tab)
+
+
+# ---- dichroic absorption (polarisation-dependent extinction) --------------
+
+def _dich_problem(eta, albedo=0.0, tau=0.4, n_zen=4, n_az=8, nx=5, ny=4):
+    spec = W.spec("plain32", nx=nx, ny=ny, n_zen=n_zen, n_az=n_az, plane="xy")
+    med = W.medium(spec)
+    med["tau"][:] = tau
+    med["albedo"][:] = albedo
+    med["emis"][:] = 0.0
+    med["eta"] = np.full((ny, nx), eta) if np.isscalar(eta) else eta
+    return OL.make_problem(spec, med)
+
+
+def test_dichroism_closed_form_for_the_two_linear_polarisations():
+    """A pure absorber: light polarised along e_theta (Q = I) decays as
+    exp(-tau (1 + eta sin^2 theta)), along e_phi (Q = -I) as
+    exp(-tau (1 - eta sin^2 theta)); U and V as exp(-tau); unpolarised light
+    becomes polarised with DoLP tanh(tau eta sin^2 theta)."""
+    tau, eta = 0.4, 0.6
+    prob = _dich_problem(eta, tau=tau)
+    th = prob.dirs.theta
+    w = np.sin(th) ** 2
+    for q, sign in ((1.0, 1.0), (-1.0, -1.0)):
+        S = np.zeros(prob.shape)
+        S[:, 0], S[:, 1] = 1.0, q
+        Y = OL.collide(S, prob)
+        expect = np.exp(-tau * (1 + sign * eta * w))
+        assert np.allclose(Y[:, 0], expect[:, None, None], rtol=1e-14, atol=0)
+        assert np.allclose(Y[:, 1], q * expect[:, None, None], rtol=1e-14, atol=0)
+    S = np.zeros(prob.shape)
+    S[:, 2], S[:, 3] = 0.5, -0.25
+    Y = OL.collide(S, prob)
+    assert np.allclose(Y[:, 2], 0.5 * np.exp(-tau)) and np.allclose(Y[:, 3], -0.25 * np.exp(-tau))
+    assert np.all(Y[:, :2] == 0.0)
+    S = np.zeros(prob.shape)
+    S[:, 0] = 1.0
+    Y = OL.collide(S, prob)
+    dolp = np.abs(Y[:, 1]) / Y[:, 0]
+    assert np.allclose(dolp, np.tanh(tau * eta * w)[:, None, None], rtol=1e-13, atol=1e-15)
+    assert np.all(Y[:, 1] <= 0.0)     # e_theta light is absorbed more for eta > 0
+
+
+def test_dichroism_equals_matrix_exponential_and_reduces_without_eta():
+    """exp(-tau_abs K_d) by scipy's expm, with the scattering share and a
+    random field; eta = 0 reproduces the non-dichroic collision (to the
+    rounding of forming (I + Q) and (I - Q) and halving their sum)."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(5)
+    nx, ny = 4, 3
+    eta = rng.uniform(-0.9, 0.9, size=(ny, nx))
+    prob = _dich_problem(eta, albedo=0.3, tau=0.5, nx=nx, ny=ny)
+    S = rng.standard_normal(prob.shape)
+    Y = OL.collide(S, prob)
+    plain = _dich_problem(0.0, albedo=0.3, tau=0.5, nx=nx, ny=ny)
+    plain.eta = None
+    X = S.reshape(4 * prob.n, -1)
+    tabs = 0.7 * 0.5
+    s = 1.0 - 0.3 * 0.5
+    Xa = np.empty_like(X)
+    for c in range(nx * ny):
+        for d in range(prob.n):
+            w = np.sin(prob.dirs.theta[d]) ** 2
+            K = np.eye(4)
+            K[0, 1] = K[1, 0] = eta.reshape(-1)[c] * w
+            Xa[4 * d:4 * d + 4, c] = expm(-tabs * K) @ X[4 * d:4 * d + 4, c]
+    Yref = s * Xa + (1.0 - s) * (prob.M @ Xa)
+    assert np.abs(Y.reshape(Yref.shape) - Yref).max() < 1e-13
+    zero = _dich_problem(0.0, albedo=0.3, tau=0.5, nx=nx, ny=ny)
+    assert np.abs(OL.collide(S, zero) - OL.collide(S, plain)).max() < 1e-15 * np.abs(S).max() * 4
+
+
+def test_dichroism_keeps_stokes_physical_and_refuses_bad_eta():
+    rng = np.random.default_rng(9)
+    prob = _dich_problem(rng.uniform(-0.95, 0.95, size=(6, 7)), albedo=0.5, tau=0.8, nx=7, ny=6)
+    S0 = np.zeros(prob.shape)
+    I0 = rng.uniform(0.5, 1.0, size=S0[:, 0].shape)
+    pol = rng.standard_normal(S0[:, 1:].shape)
+    pol *= 0.99 * I0[:, None] / np.linalg.norm(pol, axis=1, keepdims=True)
+    S0[:, 0], S0[:, 1:] = I0, pol
+    S = OL.run(S0, prob, 10)
+    assert np.all(np.linalg.norm(S[:, 1:], axis=1) <= S[:, 0] * (1 + 1e-12))
+    for bad in (1.0, -1.2, np.nan):
+        with pytest.raises(ValueError):
+            _dich_problem(bad)

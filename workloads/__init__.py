@@ -23,6 +23,8 @@ Workloads (the paper's method at the sizes it is benchmarked on here):
                top-edge (I + DoLP) loss after 500 steps
   (any)        with mixture={phase}: a second phase function and a per-cell
                fraction U[0, 1] of the scattering that follows it
+  (any)        with dichroism=d: a per-cell linear dichroism eta ~ U[-d, d]
+               of the absorption
   (any)        with phase={"kind": "table", "table": scattering_table()}: a
                tabulated scattering matrix of an aerosol-like particle
                (forward peak, P12 < 0 at side angles, P34 != 0)
@@ -121,8 +123,14 @@ def medium(s, seed=None):
     frac = None
     if s.get("mixture") is not None:
         frac = _f32(rng.uniform(0.0, 1.0, size=(ny, nx)))
+    # dichroic absorption: per-cell linear dichroism eta ~ U[-d, d], d < 1
+    # (drawn last for the same reason)
+    eta = None
+    if s.get("dichroism") is not None:
+        d = float(s["dichroism"])
+        eta = _f32(rng.uniform(-d, d, size=(ny, nx)))
     return {"tau": _f32(tau), "albedo": _f32(alb), "emis": _f32(emis),
-            "jprof": _f32(jprof), "inflow": _f32(inflow), "frac": frac}
+            "jprof": _f32(jprof), "inflow": _f32(inflow), "frac": frac, "eta": eta}
 
 
 def initial_state(s, kind="zero", seed=None):

@@ -188,9 +188,28 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
  * the call synchronises the stream.  Errors: RT_EUNSUPPORTED for RT_PLAIN
  * contexts and precisions other than RT_FP32 and RT_BF16; RT_EINVAL for an
  * invalid phase function or a NULL d_frac; RT_ERANGE if some f is outside
- * [0, 1] or not finite (the mixture is then off).  rt_adjoint, rt_batch_run
- * and rt_batch_adjoint return RT_EUNSUPPORTED while a mixture is set. */
+ * [0, 1] or not finite (the mixture is then off); RT_EUNSUPPORTED while
+ * dichroic absorption is set.  rt_adjoint, rt_batch_run and
+ * rt_batch_adjoint return RT_EUNSUPPORTED while a mixture is set. */
 rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac);
+
+/* Dichroic absorption (polarisation-dependent extinction, which the paper's
+ * conclusions name as missing).  The absorption optical depth of direction d
+ * in cell c becomes the matrix tau_abs K with K = [[1, eta w_d, 0, 0],
+ * [eta w_d, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1]] in the meridian axes,
+ * w_d = sin^2 theta_d (particles aligned about z: no dichroism along z),
+ * tau_abs = (1 - albedo) tau: the linear polarisations along e_theta (I + Q)
+ * and e_phi (I - Q) are absorbed by exp(-tau_abs (1 +- eta w_d)), U and V by
+ * exp(-tau_abs).  As the absorption it acts before the scattering.  d_eta is
+ * a device [ny][nx] float32 field with |eta| < 1, copied into the workspace;
+ * NULL removes it.  Later rt_step / rt_run use it, and rt_set_medium keeps it
+ * in step with a new medium.  Synchronises the stream (eta is checked).
+ * Errors: RT_EUNSUPPORTED for precisions other than RT_FP32 (fused or
+ * RT_PLAIN) and RT_BF16, with RT_ABS_TAYLOR or RT_FUSED_TAYLOR, or while a
+ * phase mixture is set; RT_ERANGE if some |eta| >= 1 or eta is not finite
+ * (dichroism is then off).  rt_adjoint, rt_batch_run and rt_batch_adjoint
+ * return RT_EUNSUPPORTED while it is set; rt_set_phase_mixture likewise. */
+rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);
 
 /* One step S_out = Stream(Collide(S_in)); S_in and S_out must not overlap. */
 rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out);

@@ -61,6 +61,7 @@ _SIGS = {
     "rt_init": (c_int32, [_P, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "rt_set_medium": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_set_phase_mixture": (c_int32, [c_void_p, c_int32, c_double, c_double, c_void_p]),
+    "rt_set_dichroism": (c_int32, [c_void_p, c_void_p]),
     "rt_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_stream": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
@@ -147,6 +148,11 @@ def rt_set_medium(ctx, d_tau, d_albedo, d_emis, h_jprof, h_inflow=None):
 def rt_set_phase_mixture(ctx, phase2, g2, mix_ray2, d_frac):
     """phase2 < 0 removes the mixture; d_frac: device [ny][nx] float32 in [0, 1]."""
     _check(_lib.rt_set_phase_mixture(ctx, phase2, g2, mix_ray2, d_frac), ctx)
+
+
+def rt_set_dichroism(ctx, d_eta):
+    """d_eta: device [ny][nx] float32 with |eta| < 1, or None to remove it."""
+    _check(_lib.rt_set_dichroism(ctx, d_eta), ctx)
 
 
 def rt_step(ctx, d_S_in, d_S_out):

@@ -34,6 +34,7 @@ struct Layout {
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
   size_t mix_tiles, mix_frag, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
+  size_t dich_eta, dich_xi, dich_w;   // dichroic absorption (rt_set_dichroism); 0 bytes if unsupported
   size_t tau, alb, emis, alpha, beta;
   size_t gacc, partial, sums, bad;
   size_t Ya, Yb, La, Lb;
@@ -111,6 +112,11 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
     L.mix_tiles = take(mix ? ntile * sizeof(TileRange) : 0);
     L.mix_frag = take(frag);
     L.frac = take(mix ? C * sizeof(float) : 0);
+    // dichroic absorption: per-cell eta and tau_abs * eta, per-direction sin^2 theta
+    const bool dich = prec == RT_FP32 || prec == RT_BF16;
+    L.dich_eta = take(dich ? C * sizeof(float) : 0);
+    L.dich_xi = take(dich ? C * sizeof(float) : 0);
+    L.dich_w = take(dich ? hp.n * sizeof(float) : 0);
   }
   L.tau = take(C * sizeof(float));
   L.alb = take(C * sizeof(float));
@@ -145,9 +151,11 @@ struct rt_ctx {
   Geometry geo{};
   std::vector<uint8_t> host_tables;
   std::vector<float> host_medium;  // jrow + ghost staging
+  std::vector<float> host_dich_w;  // sin^2 theta per direction (staging)
   int nout[4] = {0, 0, 0, 0};
   bool medium_set = false;
   bool mixture = false;   // rt_set_phase_mixture succeeded
+  bool dichroic = false;  // rt_set_dichroism succeeded
   int prec = 0;
   int cu_count = 256;
   std::string err;
@@ -188,6 +196,10 @@ StepArgs rt_ctx::args(bool adjoint) const {
     a.frag2 = at<uint4>(L.mix_frag);
     a.tiles2 = at<TileRange>(L.mix_tiles);
     a.frac = at<float>(L.frac);
+  }
+  if (dichroic && !adjoint) {
+    a.dich_xi = at<float>(L.dich_xi);
+    a.dich_w = at<float>(L.dich_w);
   }
   return a;
 }
@@ -436,6 +448,13 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
                                   "1 - tau_sca (or absorption factor)");
   }
   c->medium_set = true;
+  if (c->dichroic) {
+    // tau_abs * eta from the new medium (eta was validated when it was set)
+    st = c->hip(launch_dich_xi(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb),
+                               c->at<float>(c->L.dich_eta), c->at<float>(c->L.dich_xi), bad, c->stream),
+                "dichroism");
+    if (st != RT_OK) return st;
+  }
   return RT_OK;
 }
 
@@ -449,6 +468,7 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     return c->fail(RT_EUNSUPPORTED, "phase mixtures run on the fused fp32 and bf16 paths only");
   if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
   if (phase2 == RT_PHASE_TABLE) return c->fail(RT_EINVAL, "the second phase function cannot be a table");
+  if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");
   // the second collision matrix: the same direction set and options, another
   // scalar phase function (Eq. 17 weights, Rayleigh polarisation part)
   rt_problem p2 = c->prob;
@@ -488,6 +508,47 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     if (!(v >= 0.0f && v <= 1.0f)) ++bad;
   if (bad) return c->fail(RT_ERANGE, std::to_string(bad) + " cells have a mixture fraction outside [0, 1]");
   c->mixture = true;
+  return RT_OK;
+}
+
+rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_eta) {
+    c->dichroic = false;
+    return RT_OK;
+  }
+  if (c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16)
+    return c->fail(RT_EUNSUPPORTED, "dichroic absorption runs on the fp32 (fused or plain) and bf16 paths only");
+  if (c->prob.flags & (RT_ABS_TAYLOR | RT_FUSED_TAYLOR))
+    return c->fail(RT_EUNSUPPORTED, "dichroic absorption is defined for Beer-Lambert absorption");
+  if (c->mixture) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");
+  c->dichroic = false;
+  const Layout &L = c->L;
+  const int n = c->hp.n;
+  std::vector<float> &hw = c->host_dich_w;
+  hw.resize(n);
+  for (int d = 0; d < n; ++d) {
+    const double st = std::sin(c->hp.theta[d]);
+    hw[d] = (float)(st * st);
+  }
+  const size_t C = (size_t)c->geo.C;
+  int *bad = c->at<int>(L.bad);
+  int hbad = 0;
+  rt_status st = c->hip(hipMemcpyAsync(c->ws + L.dich_w, hw.data(), n * sizeof(float), hipMemcpyHostToDevice,
+                                       c->stream), "upload direction factors");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(c->ws + L.dich_eta, d_eta, C * sizeof(float), hipMemcpyDeviceToDevice, c->stream),
+                "copy eta");
+  if (st == RT_OK) st = c->hip(hipMemsetAsync(bad, 0, sizeof(int), c->stream), "clear counter");
+  // before rt_set_medium the coefficients are recomputed there; eta is checked either way
+  if (st == RT_OK)
+    st = c->hip(launch_dich_xi(c->geo.C, c->at<float>(L.tau), c->at<float>(L.alb), c->at<float>(L.dich_eta),
+                               c->at<float>(L.dich_xi), bad, c->stream), "dichroism");
+  if (st == RT_OK) st = c->hip(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream), "read counter");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "set_dichroism");
+  if (st != RT_OK) return st;
+  if (hbad) return c->fail(RT_ERANGE, std::to_string(hbad) + " cells have |eta| >= 1 or a non-finite eta");
+  c->dichroic = true;
   return RT_OK;
 }
 
@@ -604,6 +665,7 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
   if (c->mixture) return c->fail(RT_EUNSUPPORTED, "the adjoint of a phase mixture is not supported");
+  if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "the adjoint of dichroic absorption is not supported");
   if (c->geo.Rpad > 512)
     return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");
   const int prec_save = c->prec;
@@ -911,6 +973,7 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
     if (!h_states[i] || (h_ckpt && !h_ckpt[i])) return b->fail(RT_EINVAL, "NULL state or checkpoint pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
     if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
+    if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
   if (nsteps == 0) return RT_OK;
   auto body = [&]() -> rt_status {
@@ -964,6 +1027,7 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
       return b->fail(RT_EINVAL, "NULL per-channel pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
     if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
+    if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
   auto body = [&]() -> rt_status {
     rt_status st = RT_OK;

@@ -42,6 +42,10 @@ struct StepArgs {
   const uint4 *frag2;      // A fragments of M2, in the contraction precision
   const TileRange *tiles2; // [Rpad / 32]
   const float *frac;       // [C]
+  // dichroic absorption (forward only; dich_xi == nullptr: none): I + Q and
+  // I - Q of direction d in cell c are multiplied by exp(-+dich_xi[c] dich_w[d])
+  const float *dich_xi;    // [C] tau_abs * eta per cell
+  const float *dich_w;     // [n] sin^2 theta_d
 };
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };
@@ -114,6 +118,10 @@ hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *
 hipError_t launch_coef(int64_t C, const float *tau, const float *alb, const float *emis,
                        float *tau_c, float *alb_c, float *emis_c, float *alpha, float *beta,
                        uint32_t flags, int *bad, hipStream_t s);
+// Dichroic absorption per cell, xi = (1 - albedo) tau eta; counts |eta| >= 1
+// (or non-finite eta) into *bad.
+hipError_t launch_dich_xi(int64_t C, const float *tau, const float *alb, const float *eta, float *xi, int *bad,
+                          hipStream_t s);
 hipError_t launch_gradchain(int64_t C, const float *tau, const float *alb, uint32_t flags,
                             const double *gacc, float *g_tau, float *g_alb, float *g_emis,
                             hipStream_t s);

@@ -209,10 +209,10 @@ __device__ __forceinline__ void dir_issue(const StepArgs &a, const float *__rest
 // jrow is the block's LDS copy of the emission rows, so that reading it never
 // waits on the wave's outstanding global loads); for CKPT the streamed value
 // before emission is also stored into s_out.
-template <bool GATHER, bool EMIT, bool CKPT>
+template <bool GATHER, bool EMIT, bool CKPT, bool DICH = false>
 __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g, const LaneDir &ld,
                                             const LaneCell &lc, float emis_dt, const float (&v)[4][4],
-                                            float *dst, const float *jrow) {
+                                            float *dst, const float *jrow, float xi = 0.0f, float wd = 0.0f) {
   const bool live = lc.valid && ld.d < g.n;
   f32x4 jp = f32x4{0.f, 0.f, 0.f, 0.f};
   if (EMIT) jp = *reinterpret_cast<const f32x4 *>(jrow + 4 * ld.d);
@@ -223,6 +223,16 @@ __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g
     if (CKPT && live) a.s_out[ld.off + (int64_t)s * g.C + lc.c] = sv;
     if (EMIT) sv = fmaf(emis_dt, jp[s], sv);
     dst[s] = live ? sv : 0.0f;
+  }
+  if constexpr (DICH) {
+    // dichroic absorption: the linear polarisations along e_theta (I + Q)
+    // and e_phi (I - Q) decay at their own rates exp(-+xi w_d); the common
+    // factor exp(-tau_abs) is in alpha and beta
+    const float x = xi * wd;
+    const float pl = (dst[0] + dst[1]) * expf(-x);
+    const float mi = (dst[0] - dst[1]) * expf(x);
+    dst[0] = 0.5f * (pl + mi);
+    dst[1] = 0.5f * (pl - mi);
   }
 }
 
@@ -268,11 +278,12 @@ __device__ __forceinline__ float late_emission(const StepArgs &a, float emis) {
   return a.dt_pre * emis;
 }
 
-template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, int PUT>
+template <bool REV, bool GATHER, bool INTERIOR, bool EMIT, bool CKPT, int PUT, bool DICH = false>
 __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__restrict__ src,
                                              const Geometry &g, const LaneDir (&ld)[4],
                                              const LaneCell &lc, float emis, float *dst,
-                                             char *lds, const float *jrow, int lo_off = 0) {
+                                             char *lds, const float *jrow, int lo_off = 0, float xi = 0.0f,
+                                             const float *wd = nullptr) {
   float emis_dt = 0.0f;
   if (!INTERIOR) {
     // edge tiles (a small share): one group at a time, which keeps the wrap
@@ -282,7 +293,7 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
       float v[4][4], o[4];
       dir_issue<REV, GATHER, INTERIOR>(a, src, g, ld[k], lc, v);
       if (EMIT && k == 0) emis_dt = late_emission(a, emis);
-      dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k], lc, emis_dt, v, o, jrow);
+      dir_combine<GATHER, EMIT, CKPT, DICH>(a, g, ld[k], lc, emis_dt, v, o, jrow, xi, DICH ? wd[k] : 0.0f);
       put_group<PUT>(o, dst, lds, k, lo_off);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -296,7 +307,8 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
     __builtin_amdgcn_sched_barrier(0);
     if (EMIT && k == 1) emis_dt = late_emission(a, emis);
     float o[4];
-    dir_combine<GATHER, EMIT, CKPT>(a, g, ld[k - 1], lc, emis_dt, va, o, jrow);
+    dir_combine<GATHER, EMIT, CKPT, DICH>(a, g, ld[k - 1], lc, emis_dt, va, o, jrow, xi,
+                                          DICH ? wd[k - 1] : 0.0f);
     put_group<PUT>(o, dst, lds, k - 1, lo_off);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -410,14 +422,21 @@ __device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red
   return (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, bool MIX = false>
+// Optional extensions of the forward step: a per-cell mixture of two phase
+// functions (a second contraction) or dichroic absorption (in the gather).
+enum { kExtNone = 0, kExtMix = 1, kExtDich = 2 };
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
                                            int64_t tile, bool active, int t, int wg, int W, int lane) {
   static_assert(NB == 1 || (NB == 2 && !ADJ && (PREC == P_F32 || PREC == P_BF16)),
                 "two column blocks: forward float32 or bf16");
+  constexpr bool MIX = EXT == kExtMix;
+  constexpr bool DICH = EXT == kExtDich;
   static_assert(!MIX || (!ADJ && NB == 1 && (PREC == P_F32 || PREC == P_BF16)),
                 "phase mixtures: forward float32 or bf16, one column block");
+  static_assert(!DICH || (!ADJ && (PREC == P_F32 || PREC == P_BF16)), "dichroic absorption: forward float32 or bf16");
   // bf16 contraction with two column blocks: X lives as high + low tiles
   constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
   const int col = lane & 31;
@@ -455,6 +474,14 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   float al[NB], be[NB], em[NB];
   float fr[MIX ? NB : 1];   // phase-mixture fraction of the second matrix
   (void)fr;
+  float xi[DICH ? NB : 1];  // dichroic absorption: tau_abs * eta of the cell
+  float wdir[DICH ? 4 : 1]; // and sin^2 theta of the lane's four directions
+  (void)xi;
+  (void)wdir;
+  if constexpr (DICH) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wdir[q] = ld[q].d < g.n ? a.dich_w[ld[q].d] : 0.0f;
+  }
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     cscale[cb] = 1.0f;
@@ -474,6 +501,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     be[cb] = a.beta[lc.c];
     em[cb] = a.emis[lc.c];
     if constexpr (MIX) fr[cb] = a.frac[lc.c];
+    if constexpr (DICH) xi[cb] = a.dich_xi[lc.c];
     // A block is interior when every tap of every cell lies inside the lattice
     // (taps reach at most two cells either way); then no wrap or ghost is needed.
     const int c_last = (int)((base + 32 < g.C ? (int64_t)base + 32 : g.C) - 1);
@@ -484,18 +512,20 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       // each combined group goes straight to the high and low tiles
       char *brow = s_b + (32 * cb + col) * L.strideB + rbase * 2;
       if (interior)
-        gather_field<false, GATHER, true, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, em[cb], nullptr, brow, s_jrow,
-                                                                   L.tileB);
+        gather_field<false, GATHER, true, true, CKPT, kPutSplit, DICH>(a, a.in, g, ld, lc, em[cb], nullptr, brow,
+                                                                         s_jrow, L.tileB, xi[DICH ? cb : 0], wdir);
       else
-        gather_field<false, GATHER, false, true, CKPT, kPutSplit>(a, a.in, g, ld, lc, em[cb], nullptr, brow, s_jrow,
-                                                                    L.tileB);
+        gather_field<false, GATHER, false, true, CKPT, kPutSplit, DICH>(a, a.in, g, ld, lc, em[cb], nullptr, brow,
+                                                                          s_jrow, L.tileB, xi[DICH ? cb : 0], wdir);
     } else {
       // X (float32) goes to the X tile; the epilogue reads it back from there.
       char *xrow = s_x + (32 * cb + col) * L.strideX + rbase * 4;
       if (interior)
-        gather_field<false, GATHER, true, true, CKPT, kPutF32>(a, a.in, g, ld, lc, em[cb], nullptr, xrow, s_jrow);
+        gather_field<false, GATHER, true, true, CKPT, kPutF32, DICH>(a, a.in, g, ld, lc, em[cb], nullptr, xrow, s_jrow,
+                                                                       0, xi[DICH ? cb : 0], wdir);
       else
-        gather_field<false, GATHER, false, true, CKPT, kPutF32>(a, a.in, g, ld, lc, em[cb], nullptr, xrow, s_jrow);
+        gather_field<false, GATHER, false, true, CKPT, kPutF32, DICH>(a, a.in, g, ld, lc, em[cb], nullptr, xrow,
+                                                                        s_jrow, 0, xi[DICH ? cb : 0], wdir);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -803,7 +833,7 @@ constexpr int kFusedRing = MAXW <= 4 ? 4 : ((!ADJ && PREC != P_F32 && PREC != P_
 template <int PREC, bool ADJ, int MAXW>
 constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4 : 1;
 
-template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, bool MIX>
+template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, int EXT>
 __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW>)))
 fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
@@ -843,7 +873,7 @@ fused_kernel(StepArgs a, int64_t ntiles) {
     // which would not fit in VGPRs, without holding a second copy.
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, MIX>(a, g, L, ts, tr, ldk, tile, true, t,
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT>(a, g, L, ts, tr, ldk, tile, true, t,
                                                                                 t, W, lane);
   }
 }
@@ -1016,12 +1046,12 @@ hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t n
   return hipErrorInvalidValue;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, bool MIX = false>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, int EXT = kExtNone>
 hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
   const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
   const int64_t ntiles = (a.geo.C + 32 * NB - 1) / (32 * NB);
-  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, MIX>;
+  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, EXT>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
   // persistent grid: as many blocks as are resident at once, so that no block
@@ -1039,11 +1069,24 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
+  if (a.frac != nullptr && a.dich_xi != nullptr) return hipErrorInvalidValue;
   if (a.frac != nullptr) {
     // phase mixture: forward fp32 / bf16, 32-cell tiles
     if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
-      if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, true>(a, W, s, cu_count);
-      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, true>(a, W, s, cu_count);
+      if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtMix>(a, W, s, cu_count);
+      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtMix>(a, W, s, cu_count);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (a.dich_xi != nullptr) {
+    // dichroic absorption: forward fp32 / bf16, the tiles of the plain step
+    if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
+      if (W <= 4) {
+        if constexpr (PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2, kExtDich>(a, W, s, cu_count);
+        return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
+      }
+      if (step_nb(W, PREC, ADJ) == 2) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 2, kExtDich>(a, W, s, cu_count);
+      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtDich>(a, W, s, cu_count);
     }
     return hipErrorInvalidValue;
   }
@@ -1232,6 +1275,16 @@ __global__ void __launch_bounds__(256) stream4_kernel(StepArgs a, QuadSplit qs, 
 // input value is loaded once per row group.
 constexpr int kValuRows = 32;
 
+// Dichroic absorption of one direction's X (plain path): I + Q and I - Q
+// scaled by exp(-+x).
+__device__ __forceinline__ void dich_apply(float &xI, float &xQ, float x) {
+  const float pl = (xI + xQ) * expf(-x);
+  const float mi = (xI - xQ) * expf(x);
+  xI = 0.5f * (pl + mi);
+  xQ = 0.5f * (pl - mi);
+}
+
+template <bool DICH>
 __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const float *__restrict__ MT,
                                                            const float *__restrict__ in,
                                                            float *__restrict__ out) {
@@ -1244,12 +1297,13 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
   const int64_t cc = valid ? c : 0;
   const float al = a.alpha[cc], be = a.beta[cc], em = a.emis[cc];
   const float edt = a.dt_pre * em;
+  const float xi = DICH ? a.dich_xi[cc] : 0.0f;
   float acc[kValuRows];
 #pragma unroll
   for (int r = 0; r < kValuRows; ++r) acc[r] = 0.0f;
-  for (int k = 0; k < R; ++k) {
-    const float x = fmaf(edt, a.jrow[k], in[(int64_t)k * g.C + cc]);
-    const float *mk = MT + (int64_t)k * R + r0;   // M[r0 + r][k] = mk[r]
+  // acc[r] += M[r0 + r][k] x_k over k; mk = MT + k R + r0 holds M[r0 + r][k] at mk[r]
+  auto accumulate = [&](int k, float x) {
+    const float *mk = MT + (int64_t)k * R + r0;
 #pragma unroll
     for (int r = 0; r < kValuRows; r += 16) {
       if (r + 16 <= nr) {
@@ -1267,15 +1321,34 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
         }
       }
     }
+  };
+  if constexpr (DICH) {
+    // one direction (4 Stokes rows) at a time: its I and Q are combined
+    for (int k = 0; k < R; k += 4) {
+      float x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = fmaf(edt, a.jrow[k + j], in[(int64_t)(k + j) * g.C + cc]);
+      dich_apply(x[0], x[1], xi * a.dich_w[k / 4]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) accumulate(k + j, x[j]);
+    }
+  } else {
+    for (int k = 0; k < R; ++k) accumulate(k, fmaf(edt, a.jrow[k], in[(int64_t)k * g.C + cc]));
   }
   if (!valid) return;
 #pragma unroll
-  for (int r = 0; r < kValuRows; ++r) {
+  for (int r = 0; r < kValuRows; r += 4) {
     if (r < nr) {
-      const int64_t off = (int64_t)(r0 + r) * g.C + c;
-      const float jr = a.jrow[r0 + r];
-      const float xo = fmaf(edt, jr, in[off]);
-      out[off] = fmaf(be, acc[r], fmaf(al, xo, a.dt_post * em * jr));
+      float xo[4], jr[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        jr[j] = a.jrow[r0 + r + j];
+        xo[j] = fmaf(edt, jr[j], in[(int64_t)(r0 + r + j) * g.C + c]);
+      }
+      if constexpr (DICH) dich_apply(xo[0], xo[1], xi * a.dich_w[(r0 + r) / 4]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        out[(int64_t)(r0 + r + j) * g.C + c] = fmaf(be, acc[r + j], fmaf(al, xo[j], a.dt_post * em * jr[j]));
     }
   }
 }
@@ -1312,6 +1385,21 @@ __global__ void coef_kernel(int64_t C, const float *__restrict__ tau, const floa
     emis_c[c] = (float)e;
     alpha[c] = (float)al;
     beta[c] = (float)be;
+  }
+  if (nbad) atomicAdd(bad, nbad);
+}
+
+// Dichroic absorption per cell: xi = tau_abs * eta = (1 - albedo) tau eta
+// (float64 arithmetic, stored in float32); counts |eta| >= 1 or non-finite
+// eta into *bad.
+__global__ void dich_xi_kernel(int64_t C, const float *__restrict__ tau, const float *__restrict__ alb,
+                               const float *__restrict__ eta, float *xi, int *bad) {
+  int nbad = 0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const double e = eta[c];
+    if (!(std::fabs(e) < 1.0)) ++nbad;
+    xi[c] = (float)((1.0 - (double)alb[c]) * (double)tau[c] * e);
   }
   if (nbad) atomicAdd(bad, nbad);
 }
@@ -1494,8 +1582,10 @@ hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStre
 hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,
                                hipStream_t s) {
   const dim3 grid((unsigned)((a.geo.C + 255) / 256), (unsigned)((a.geo.R + kValuRows - 1) / kValuRows));
-  hipLaunchKernelGGL(collide_valu_kernel, grid, dim3(256), 0, s, a, MT, in,
-                     out);
+  if (a.dich_xi != nullptr)
+    hipLaunchKernelGGL(collide_valu_kernel<true>, grid, dim3(256), 0, s, a, MT, in, out);
+  else
+    hipLaunchKernelGGL(collide_valu_kernel<false>, grid, dim3(256), 0, s, a, MT, in, out);
   return hipGetLastError();
 }
 
@@ -1504,6 +1594,12 @@ hipError_t launch_coef(int64_t C, const float *tau, const float *alb, const floa
                        hipStream_t s) {
   hipLaunchKernelGGL(coef_kernel, dim3(grid_for(C, 256)), dim3(256), 0, s, C, tau, alb, emis, tau_c,
                      alb_c, emis_c, alpha, beta, flags, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dich_xi(int64_t C, const float *tau, const float *alb, const float *eta, float *xi, int *bad,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(dich_xi_kernel, dim3(grid_for(C, 256)), dim3(256), 0, s, C, tau, alb, eta, xi, bad);
   return hipGetLastError();
 }
 

@@ -128,6 +128,12 @@ class Solver:
         A.rt_set_phase_mixture(self.ctx, _PHASE[phase.get("kind", "rayleigh")], float(phase.get("g", 0.0)),
                                float(phase.get("mix_ray", 1.0)), _ptr(frac))
 
+    def set_dichroism(self, eta):
+        """Dichroic absorption with per-cell linear dichroism eta (device
+        [ny, nx] float32, |eta| < 1); None removes it."""
+        self._eta = eta
+        A.rt_set_dichroism(self.ctx, _ptr(eta))
+
     def step(self, S_in, S_out):
         A.rt_step(self.ctx, _ptr(S_in), _ptr(S_out))
 

@@ -1,0 +1,209 @@
+"""GPU parity of dichroic absorption (per-cell linear dichroism eta of the
+absorption, direction factor sin^2 theta, acting before the scattering)
+against the FP64 oracle, through the C ABI: the fused fp32 and bf16 steps
+(32- and 64-cell tiles, the bf16 split-X tiles at n = 128) and the plain
+float32 path, the order of rt_set_dichroism and rt_set_medium, and the
+refusals.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_common import assert_close, build, to_dev, to_np, tolerance
+from oracle import lbm as OL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def absorbing_medium(spec):
+    """The workload's medium with four times the optical depth (at most 1
+    per step) and 0.6 of its albedo, so that the dichroism of the absorption
+    moves Q by 6-100% of its scale over the run."""
+    med = W.medium(spec)
+    med["tau"] = np.minimum(med["tau"] * 4.0, 1.0).astype(np.float32).astype(np.float64)
+    med["albedo"] = (med["albedo"] * 0.6).astype(np.float32).astype(np.float64)
+    return med
+
+
+def _with_dichroism(spec, precision, medium=None):
+    solver, oprob, med = build(spec, precision, absorbing_medium(spec) if medium is None else medium)
+    eta = to_dev(med["eta"], solver)
+    solver.set_dichroism(eta)
+    return solver, oprob, med
+
+
+CASES = [
+    ("beam512", dict(nx=40, ny=33), 30, "zero"),                        # n = 32
+    ("beam512", dict(nx=33, ny=29, n_zen=2, n_az=8), 40, "random"),     # n = 16
+    ("beam512", dict(nx=21, ny=26, n_zen=4, n_az=16), 25, "random"),    # n = 64
+    ("prec1024", dict(nx=19, ny=22), 15, "random"),                     # n = 128
+    ("plain32", dict(nx=30, ny=21), 40, "random"),                      # n = 8
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%dx%d-n%d" % (
+    c[0], c[1]["nx"], c[1]["ny"], W.ndir(W.spec(c[0], **c[1]))))
+def test_dichroism_forward_parity(case, precision):
+    name, over, steps, init = case
+    spec = W.spec(name, dichroism=0.8, **over)
+    solver, oprob, _ = _with_dichroism(spec, precision)
+    assert oprob.eta is not None and np.abs(oprob.eta).max() > 0.5
+    S0 = W.initial_state(spec, init)
+    S = to_dev(S0, solver)
+    solver.run(S, steps)
+    ref = OL.run(S0, oprob, steps)
+    e = assert_close(to_np(S), ref, tolerance(precision, oprob), (name, precision))
+    # the dichroism matters at this tolerance: without it Q is far off
+    oprob.eta = None
+    far = OL.run(S0, oprob, steps)
+    scale = max(np.linalg.norm(ref[:, 1]), 1e-2 * np.linalg.norm(ref[:, 0]))
+    assert np.linalg.norm(far[:, 1] - ref[:, 1]) > 10 * tolerance(precision, oprob) * scale
+    print(name, precision, e)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16"])
+def test_dichroism_step_checkpoints_and_medium_order(precision):
+    """rt_set_dichroism before rt_set_medium: the medium call recomputes the
+    per-cell absorption factors; rt_step and the checkpoints of rt_run then
+    follow the oracle."""
+    spec = W.spec("beam512", nx=50, ny=44, dichroism=0.9)
+    med = absorbing_medium(spec)
+    solver, _, _ = build(spec, precision, med)
+    solver.set_dichroism(to_dev(med["eta"], solver))
+    med2 = W.medium(spec, seed=77)
+    med2["tau"] = np.minimum(med2["tau"] * 3.0, 1.0).astype(np.float32).astype(np.float64)
+    med2["eta"] = med["eta"]
+    t = [to_dev(med2[k], solver) for k in ("tau", "albedo", "emis")]
+    solver.set_medium(*t, med2["jprof"], med2["inflow"])
+    solver._tensors = t
+    oprob = OL.make_problem(spec, med2)
+    tol = tolerance(precision, oprob)
+    S0 = W.initial_state(spec, "random")
+    a, b = to_dev(S0, solver), solver.empty_state()
+    solver.step(a, b)
+    assert_close(to_np(b), OL.step(S0, oprob), tol, "step")
+    T, K = 13, 4
+    ck = solver.checkpoint_buffer(T, K)
+    S = to_dev(S0, solver)
+    solver.run(S, T, ck, K)
+    _, hist = OL.run(S0, oprob, T, keep=True)
+    for k in range(ck.shape[0]):
+        assert_close(to_np(ck[k]), hist[k * K], tol, ("ckpt", k))
+    assert_close(to_np(S), hist[T], tol, "final")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_dichroism_full_size_beam512(precision):
+    spec = W.spec("beam512", dichroism=0.8)
+    solver, oprob, _ = _with_dichroism(spec, precision)
+    rng = np.random.default_rng(51)
+    S0 = np.abs(rng.standard_normal(solver.shape)) * 0.1
+    S0[:, 1:] *= 0.2 * np.sign(rng.standard_normal(S0[:, 1:].shape))
+    T, K = 3, 2
+    S = to_dev(S0, solver)
+    ck = solver.checkpoint_buffer(T, K)
+    solver.run(S, T, ck, K)
+    torch.cuda.synchronize()
+    hist = OL.run(S0, oprob, T, keep=True)[1]
+    tol = tolerance(precision, oprob)
+    assert_close(to_np(S), hist[T], tol, ("S_T", precision))
+    assert_close(to_np(ck[1]), hist[2], tol, ("checkpoint 1", precision))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16"])
+def test_zero_dichroism_and_removal(precision):
+    """eta = 0 matches the plain absorption to rounding; removing the
+    dichroism returns to the unchanged kernels bit for bit."""
+    spec = W.spec("beam512", nx=37, ny=30, dichroism=0.5)
+    solver, _, med = build(spec, precision)
+    S0 = to_dev(W.initial_state(spec, "random"), solver)
+    ref = S0.clone()
+    solver.run(ref, 10)
+    solver.set_dichroism(torch.zeros((spec["ny"], spec["nx"]), dtype=torch.float32, device=solver.device))
+    S = S0.clone()
+    solver.run(S, 10)
+    torch.cuda.synchronize()
+    assert_close(to_np(S), to_np(ref), 2e-6, "eta = 0")
+    solver.set_dichroism(to_dev(med["eta"], solver))
+    S = S0.clone()
+    solver.run(S, 10)
+    solver.set_dichroism(None)
+    S = S0.clone()
+    solver.run(S, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(S, ref)
+
+
+def test_dichroism_refusals():
+    import paper_2609_23057_amd as P
+    spec = W.spec("beam512", nx=20, ny=18, dichroism=0.5, mixture={"kind": "rayleigh"})
+    med = W.medium(spec)
+    for precision in ("fp16", "bf16x3"):
+        solver, _, _ = build(spec, precision, med)
+        with pytest.raises(P.RTError) as ei:
+            solver.set_dichroism(to_dev(med["eta"], solver))
+        assert ei.value.status == P.RT_EUNSUPPORTED, precision
+    solver, _, _ = build(dict(spec, abs_taylor=True), "fp32", dict(med, eta=None))
+    with pytest.raises(P.RTError) as ei:
+        solver.set_dichroism(to_dev(med["eta"], solver))
+    assert ei.value.status == P.RT_EUNSUPPORTED
+    solver, _, _ = build(spec, "fp32", med)
+    S0 = to_dev(W.initial_state(spec, "random"), solver)
+    ref = S0.clone()
+    solver.run(ref, 5)
+    bad = to_dev(med["eta"], solver)
+    bad[2, 3] = 1.0
+    with pytest.raises(P.RTError) as ei:
+        solver.set_dichroism(bad)
+    assert ei.value.status == P.RT_ERANGE
+    S = S0.clone()
+    solver.run(S, 5)     # a refused eta leaves the context without dichroism
+    torch.cuda.synchronize()
+    assert torch.equal(S, ref)
+    # a mixture and dichroism exclude each other, in either order
+    frac = to_dev(med["frac"], solver)
+    solver.set_phase_mixture(spec["mixture"], frac)
+    with pytest.raises(P.RTError) as ei:
+        solver.set_dichroism(to_dev(med["eta"], solver))
+    assert ei.value.status == P.RT_EUNSUPPORTED
+    solver.set_phase_mixture(None, None)
+    solver.set_dichroism(to_dev(med["eta"], solver))
+    with pytest.raises(P.RTError) as ei:
+        solver.set_phase_mixture(spec["mixture"], frac)
+    assert ei.value.status == P.RT_EUNSUPPORTED
+    ck = solver.checkpoint_buffer(4, 2)
+    S = solver.empty_state()
+    solver.run(S, 4, ck, 2)
+    with pytest.raises(P.RTError) as ei:
+        solver.adjoint(4, ck, 2, solver.empty_state())
+    assert ei.value.status == P.RT_EUNSUPPORTED
+
+
+def test_batch_refuses_dichroic_channel():
+    import paper_2609_23057_amd as P
+    spec = W.spec("beam512", nx=24, ny=20, n_zen=2, n_az=8, dichroism=0.5)
+    prob = P.make_problem(**dict(spec, precision="bf16"))
+    batch = P.Batch([prob, prob])
+    med = W.medium(spec)
+    keep = []
+    for ch in batch.channels:
+        t = [to_dev(med[k], ch) for k in ("tau", "albedo", "emis")]
+        keep.append(t)
+        ch.set_medium(*t, med["jprof"], med["inflow"])
+    states = batch.empty_states()
+    eta = to_dev(med["eta"], batch.channels[0])
+    batch.channels[0].set_dichroism(eta)
+    with pytest.raises(P.RTError) as ei:
+        batch.run(states, 2)
+    assert ei.value.status == P.RT_EUNSUPPORTED
+    batch.channels[0].set_dichroism(None)
+    batch.run(states, 2)
+    torch.cuda.synchronize()

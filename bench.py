@@ -13,8 +13,9 @@ second of that step.  All inputs are resident in HBM before timing starts.
 
 Extras (skipped with --no-extras): forward rates at 1024x1024, n = 128 per
 contraction precision, the stand-alone streaming kernel's HBM rate at beam512
-and prec1024, the forward step with a per-cell phase-function mixture at
-beam512, and the 64-channel spectral batch (one launch per step for all
+and prec1024, the forward step at beam512 with each extension of the operator
+(tabulated scattering matrix, per-cell phase mixture, dichroic absorption),
+and the 64-channel spectral batch (one launch per step for all
 channels, eager and as a replayed HIP graph).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
@@ -168,26 +169,37 @@ def precision_extras(T=20, warm=3):
     return {"workload": "prec1024: 1024x1024, n=128 (8x16), forward steps", "steps": T, "rates": res}
 
 
-def mixture_extras(T=20, warm=3):
-    """Forward rate of the fused step with a per-cell phase-function mixture
-    (HG(0.7) and Rayleigh, fraction U[0, 1] per cell) at beam512, beside the
-    single-phase step, per contraction precision; the mixture contracts two
-    collision matrices per cell."""
+def extension_extras(T=20, warm=3):
+    """Forward rate of the fused step at beam512 with each extension of the
+    operator beside the plain workload, per contraction precision: a
+    tabulated scattering matrix (P12, P34 != 0), a per-cell phase-function
+    mixture (HG(0.7) and Rayleigh, fraction U[0, 1]; two contractions per
+    cell) and dichroic absorption (eta U[-0.8, 0.8]; applied in the gather)."""
     import numpy as np
     import torch
     import workloads as W
-    spec = W.spec("beam512", mixture={"kind": "rayleigh"})
-    C, n = spec["nx"] * spec["ny"], W.ndir(spec)
-    frac_host = W.medium(spec)["frac"]
+    base = W.spec("beam512")
+    C, n = base["nx"] * base["ny"], W.ndir(base)
+    variants = {
+        "single": (base, None),
+        "table": (W.spec("beam512", phase={"kind": "table", "table": W.scattering_table()}), None),
+        "mixture": (W.spec("beam512", mixture={"kind": "rayleigh"}), "mixture"),
+        "dichroism": (W.spec("beam512", dichroism=0.8), "dichroism"),
+    }
     res = {}
     for prec in ("fp32", "bf16"):
-        solver = make_solver(spec, prec)
-        frac = torch.tensor(np.ascontiguousarray(frac_host), dtype=torch.float32, device=solver.device)
-        S = solver.empty_state()
         out = {}
-        for mode in ("single", "mixture"):
-            _log("bench: beam512 %s %s" % (prec, mode))
-            solver.set_phase_mixture(spec["mixture"] if mode == "mixture" else None, frac)
+        for name, (spec, ext) in variants.items():
+            _log("bench: beam512 %s %s" % (prec, name))
+            solver = make_solver(spec, prec)
+            med = W.medium(spec)
+            if ext == "mixture":
+                extra = torch.tensor(np.ascontiguousarray(med["frac"]), dtype=torch.float32, device=solver.device)
+                solver.set_phase_mixture(spec["mixture"], extra)
+            elif ext == "dichroism":
+                extra = torch.tensor(np.ascontiguousarray(med["eta"]), dtype=torch.float32, device=solver.device)
+                solver.set_dichroism(extra)
+            S = solver.empty_state()
             solver.run(S, warm)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -196,13 +208,14 @@ def mixture_extras(T=20, warm=3):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
-            out[mode] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
-        out["mixture_cost"] = out["mixture"]["ms_per_time_step"] / out["single"]["ms_per_time_step"]
+            out[name] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+            del solver, S
+            torch.cuda.empty_cache()
+        for name in variants:
+            out[name]["cost_vs_single"] = out[name]["ms_per_time_step"] / out["single"]["ms_per_time_step"]
         res[prec] = out
-        del solver, S, frac
-        torch.cuda.empty_cache()
-    return {"workload": "beam512 with a per-cell HG(0.7) / Rayleigh mixture, forward steps", "steps": T,
-            "rates": res}
+    return {"workload": "beam512 (512x512, n=32), forward steps: plain workload, tabulated scattering matrix, "
+                        "per-cell HG(0.7)/Rayleigh mixture, dichroic absorption", "steps": T, "rates": res}
 
 
 def streaming_extras(reps=50):
@@ -407,7 +420,7 @@ def main():
         torch.cuda.empty_cache()
         line["streaming"] = streaming_extras()
         torch.cuda.empty_cache()
-        line["phase_mixture"] = mixture_extras()
+        line["extensions"] = extension_extras()
         torch.cuda.empty_cache()
         line["spectral_batch"] = spectral_extras()
         torch.cuda.empty_cache()

@@ -1,0 +1,140 @@
+"""Three-dimensional lattice (oracle).
+
+TEST INFRASTRUCTURE ONLY: the product path never imports this module.
+
+Paper: the conclusions state that the lattice formulation extends to three
+dimensions and name it as a priority; the paper gives no 3-D scheme, so this
+takes its 2-D steps with a third axis:
+  * collision (emission, absorption, scattering; Sec. 2.1.3-2.1.5): the
+    per-cell operator of lbm.collide, unchanged; it acts on every cell alone,
+    so it is applied to the cells of the 3-D lattice in a flattened view;
+  * streaming (Sec. 2.1.6, Eq. 33-34): the displacement is the whole
+    direction vector, l = courant * (k_x, k_y, k_z), and the pull is the
+    product of the 1-D taps of Eq. 34 along x, y and z (trilinear);
+  * faces (Sec. 2.1.7, Eq. 39): x-, x+, y-, y+, z-, z+ each periodic (both
+    faces of an axis), absorbing (ghosts are zero) or inflow (ghosts carry
+    inflow[face, d, :]); a tap outside in z takes its z face, else its
+    y face, else its x face.
+State S[d, s, z, y, x]; cell index c = (z ny + y) nx + x.
+"""
+import numpy as np
+
+from . import directions as _dirs
+from . import lbm
+from . import phase as _phase
+
+FACE_XM, FACE_XP, FACE_YM, FACE_YP, FACE_ZM, FACE_ZP = range(6)
+
+
+class Problem3D:
+    """A 3-D solve in float64: the flattened per-cell problem `flat` (its
+    nx x (ny nz) cells carry the medium; its edges are unused) plus the
+    three-axis streaming."""
+
+    def __init__(self, nx, ny, nz, dirs, courant, bc6, M, dt, tau, albedo, emis, jprof,
+                 inflow6=None, **opts):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dirs = dirs
+        self.n = dirs.n
+        self.shifts = courant * np.asarray(dirs.k, dtype=np.float64)
+        if np.any(np.abs(self.shifts) > 1.0 + 1e-12):
+            raise ValueError("|l| > 1 per step")
+        self.bc = tuple(int(b) for b in bc6)
+        for a in range(3):
+            if (self.bc[2 * a] == lbm.BC_PERIODIC) != (self.bc[2 * a + 1] == lbm.BC_PERIODIC):
+                raise ValueError("both faces of an axis must be periodic or neither")
+        if inflow6 is None:
+            inflow6 = np.zeros((6, self.n, 4))
+        self.inflow = np.asarray(inflow6, dtype=np.float64).reshape(6, self.n, 4)
+        flat = lambda a: None if a is None else np.asarray(a, dtype=np.float64).reshape(  # noqa: E731
+            self.nz * self.ny, self.nx)
+        for k in ("frac", "dichroism"):
+            if opts.get(k) is not None:
+                opts[k] = flat(opts[k])
+        self.flat = lbm.Problem(self.nx, self.ny * self.nz, dirs, self.shifts[:, :2], M, dt, (0, 0, 0, 0),
+                                flat(tau), flat(albedo), flat(emis), jprof, None, **opts)
+
+    @property
+    def shape(self):
+        return (self.n, 4, self.nz, self.ny, self.nx)
+
+
+def collide(S, prob):
+    """Emission, absorption and scattering at every cell (lbm.collide on the
+    flattened cells)."""
+    Y = lbm.collide(np.asarray(S, dtype=np.float64).reshape(prob.flat.shape), prob.flat)
+    return Y.reshape(prob.shape)
+
+
+def _fetch(vol, xs, ys, zs, d, prob):
+    """vol[4, nz, ny, nx] read at integer (xs, ys, zs) with the face rules."""
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    if prob.bc[FACE_XM] == lbm.BC_PERIODIC:
+        xs = np.mod(xs, nx)
+    if prob.bc[FACE_YM] == lbm.BC_PERIODIC:
+        ys = np.mod(ys, ny)
+    if prob.bc[FACE_ZM] == lbm.BC_PERIODIC:
+        zs = np.mod(zs, nz)
+    inz = (zs >= 0) & (zs < nz)
+    iny = (ys >= 0) & (ys < ny)
+    inx = (xs >= 0) & (xs < nx)
+    inside = inx & iny & inz
+    vals = np.zeros((4,) + xs.shape)
+    vals[:, inside] = vol[:, zs[inside], ys[inside], xs[inside]]
+    faces = ((zs >= nz, FACE_ZP), (zs < 0, FACE_ZM),
+             (inz & (ys >= ny), FACE_YP), (inz & (ys < 0), FACE_YM),
+             (inz & iny & (xs >= nx), FACE_XP), (inz & iny & (xs < 0), FACE_XM))
+    for mask, face in faces:
+        if prob.bc[face] == lbm.BC_INFLOW and np.any(mask):
+            vals[:, mask] = prob.inflow[face, d, :, None]
+    return vals
+
+
+def stream(Y, prob):
+    """S'[d](x, y, z) = sum over the taps of Eq. 34 along each axis of
+    wx wy wz Y[d](x - ox, y - oy, z - oz)."""
+    Y = np.asarray(Y, dtype=np.float64).reshape(prob.shape)
+    out = np.zeros_like(Y)
+    zz, yy, xx = np.meshgrid(np.arange(prob.nz), np.arange(prob.ny), np.arange(prob.nx), indexing="ij")
+    for d in range(prob.n):
+        lx, ly, lz = prob.shifts[d]
+        for ox, wx in lbm._taps(lx):
+            for oy, wy in lbm._taps(ly):
+                for oz, wz in lbm._taps(lz):
+                    out[d] += wx * wy * wz * _fetch(Y[d], xx - ox, yy - oy, zz - oz, d, prob)
+    return out
+
+
+def step(S, prob):
+    return stream(collide(S, prob), prob)
+
+
+def run(S0, prob, nsteps, keep=False):
+    S = np.array(S0, dtype=np.float64).reshape(prob.shape)
+    hist = [S.copy()] if keep else None
+    for _ in range(nsteps):
+        S = step(S, prob)
+        if keep:
+            hist.append(S.copy())
+    return (S, hist) if keep else S
+
+
+def make_problem(spec, medium):
+    """A Problem3D from a workload spec (plane "3d") and its medium."""
+    dirs = _dirs.make_directions(spec["n_zen"], spec["n_az"], spec.get("zen_rule", "equal_area"),
+                                 spec.get("az_offset_deg", 0.0), spec.get("zen_explicit_deg"))
+    ph = spec.get("phase", {"kind": "rayleigh"})
+    M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
+                                ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
+                                spec.get("scalar", False), ph.get("table"))
+    M2 = None
+    if spec.get("mixture") is not None:
+        ph2 = spec["mixture"]
+        M2 = _phase.collision_matrix(dirs, ph2.get("kind", "rayleigh"), ph2.get("g", 0.0),
+                                     ph2.get("mix_ray", 1.0), spec.get("renorm_irow", False),
+                                     spec.get("scalar", False), ph2.get("table"))
+    return Problem3D(spec["nx"], spec["ny"], spec["nz"], dirs, spec.get("courant", 1.0), spec["bc6"], M,
+                     spec.get("dt", 1.0), medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
+                     medium.get("inflow"), abs_taylor=spec.get("abs_taylor", False),
+                     scat_exp=spec.get("scat_exp", False), fused_taylor=spec.get("fused_taylor", False),
+                     M2=M2, frac=medium.get("frac"), dichroism=medium.get("eta"))

@@ -28,6 +28,9 @@ Workloads (the paper's method at the sizes it is benchmarked on here):
   (any)        with phase={"kind": "table", "table": scattering_table()}: a
                tabulated scattering matrix of an aerosol-like particle
                (forward peak, P12 < 0 at side angles, P34 != 0)
+  beam3d       256x256x64 three-dimensional lattice (z = altitude), n = 32,
+               the beam512 medium generator, beam entering the top face z+,
+               absorbing side and bottom faces, 500 steps
   spectral64   64 channels 400-900 nm, Rayleigh optical depth ~ lambda^-4 plus
                aerosol HG(0.6), per-channel lattice and direction count drawn
                from {128,256,384,512}^2 x {16,32,64}, 200 steps
@@ -51,6 +54,10 @@ _BASE = {
                      phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=200, seed=3,
                      medium="lognormal", tau_ref_n=1024, beam_dir=6 * 16 + 0,
                      source="none"),
+    "beam3d": dict(nx=256, ny=256, nz=64, n_zen=4, n_az=8, zen_rule="equal_area", az_offset_deg=0.0,
+                   plane="3d", courant=1.0, bc6=(1, 1, 1, 1, 1, 2),
+                   phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=7,
+                   medium="lognormal", tau_ref_n=256, beam_dir=3 * 8 + 0, source="none"),
     "adjoint256": dict(nx=256, ny=256, n_zen=4, n_az=8, zen_rule="equal_area",
                        az_offset_deg=0.0, plane="xz", courant=1.0, bc=(1, 1, 1, 2),
                        phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=4,
@@ -92,7 +99,12 @@ def medium(s, seed=None):
     lattice keeps the per-step optical-depth distribution; albedo ~ U[0.8, 1].
     """
     rng = np.random.default_rng(s["seed"] if seed is None else seed)
-    nx, ny, n = s["nx"], s["ny"], ndir(s)
+    nx, n = s["nx"], ndir(s)
+    nz = int(s.get("nz", 1))
+    three_d = s.get("plane") == "3d"
+    # a 3-D lattice draws its per-cell fields as nz * ny rows of nx cells
+    # (the draws are independent per cell) and returns them as [nz, ny, nx]
+    ny = s["ny"] * nz if three_d else s["ny"]
     if s["medium"] == "uniform":
         tau = np.full((ny, nx), s["tau0"])
         alb = np.full((ny, nx), s["albedo0"])
@@ -114,9 +126,14 @@ def medium(s, seed=None):
     elif src == "uniform_emis":
         emis = rng.uniform(0.0, s["emis_max"], size=(ny, nx))
         jprof[:, 0] = 1.0
-    inflow = np.zeros((4, n, 4))
-    if "beam_dir" in s and s["bc"][3] == BC_INFLOW:
-        inflow[3, s["beam_dir"], 0] = 1.0
+    if three_d:
+        inflow = np.zeros((6, n, 4))
+        if "beam_dir" in s and s["bc6"][5] == BC_INFLOW:
+            inflow[5, s["beam_dir"], 0] = 1.0
+    else:
+        inflow = np.zeros((4, n, 4))
+        if "beam_dir" in s and s["bc"][3] == BC_INFLOW:
+            inflow[3, s["beam_dir"], 0] = 1.0
     # phase mixture: per-cell fraction of the scattering that follows the
     # second phase function (drawn after everything else, so the other
     # fields do not depend on whether a mixture is asked for)
@@ -129,13 +146,24 @@ def medium(s, seed=None):
     if s.get("dichroism") is not None:
         d = float(s["dichroism"])
         eta = _f32(rng.uniform(-d, d, size=(ny, nx)))
-    return {"tau": _f32(tau), "albedo": _f32(alb), "emis": _f32(emis),
-            "jprof": _f32(jprof), "inflow": _f32(inflow), "frac": frac, "eta": eta}
+    out = {"tau": _f32(tau), "albedo": _f32(alb), "emis": _f32(emis),
+           "jprof": _f32(jprof), "inflow": _f32(inflow), "frac": frac, "eta": eta}
+    if three_d:
+        for k in ("tau", "albedo", "emis", "frac", "eta"):
+            if out[k] is not None:
+                out[k] = out[k].reshape(nz, s["ny"], nx)
+    return out
 
 
 def initial_state(s, kind="zero", seed=None):
-    """S0[d, s, y, x]: zeros, or random physical Stokes vectors (I >= |(Q,U,V)|)."""
-    nx, ny, n = s["nx"], s["ny"], ndir(s)
+    """S0[d, s, y, x] (S0[d, s, z, y, x] on a 3-D lattice): zeros, or random
+    physical Stokes vectors (I >= |(Q,U,V)|)."""
+    nx, n = s["nx"], ndir(s)
+    if s.get("plane") == "3d":
+        nz = int(s.get("nz", 1))
+        flat = dict(s, ny=s["ny"] * nz, plane="xz")
+        return initial_state(flat, kind, seed).reshape(n, 4, nz, s["ny"], nx)
+    ny = s["ny"]
     if kind == "zero":
         return np.zeros((n, 4, ny, nx))
     rng = np.random.default_rng(1000 + (s["seed"] if seed is None else seed))

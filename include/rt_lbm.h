@@ -70,8 +70,21 @@ typedef enum { RT_ZEN_EQUAL_AREA = 0, RT_ZEN_UNIFORM_THETA = 1, RT_ZEN_EXPLICIT 
  *   RT_PLANE_XZ       l = courant * (k_x, k_z)   (vertical plane, lattice y = altitude)
  *   RT_PLANE_XY_D2Q9  each component of (cos phi, sin phi) rounded to -1, 0 or 1
  *                     (the D2Q9 velocities of Sec. 2.1); components within 1e-6
- *                     of +-1/2 are refused as ambiguous. */
-typedef enum { RT_PLANE_XY = 0, RT_PLANE_XZ = 1, RT_PLANE_XY_D2Q9 = 2 } rt_plane;
+ *                     of +-1/2 are refused as ambiguous.
+ *   RT_PLANE_3D       a three-dimensional nx x ny x nz lattice (z = altitude),
+ *                     l = courant * (k_x, k_y, k_z): the pull of Eq. 34 along
+ *                     all three axes (trilinear), the collision per cell as in
+ *                     2-D (the paper's conclusions name the extension to three
+ *                     dimensions).  States are [4n][nz][ny][nx], cell
+ *                     c = (z ny + y) nx + x; per-cell fields are [nz][ny][nx].
+ *                     Faces x-, x+, y-, y+ take bc[0..3], z-, z+ take bc_z[0..1];
+ *                     a ghost outside in z takes its z face, else its y face,
+ *                     else its x face.  Forward only: rt_step, rt_run (with
+ *                     checkpoints), rt_stream, rt_maps, the totals of
+ *                     rt_readout, rt_set_phase_mixture and rt_set_dichroism;
+ *                     edge readouts, the adjoint and the batch return
+ *                     RT_EUNSUPPORTED. */
+typedef enum { RT_PLANE_XY = 0, RT_PLANE_XZ = 1, RT_PLANE_XY_D2Q9 = 2, RT_PLANE_3D = 3 } rt_plane;
 
 /* Edges are numbered 0 = x-, 1 = x+, 2 = y-, 3 = y+.  Periodic is the
  * recycling boundary of Eq. 39 (both edges of an axis must be periodic or
@@ -130,6 +143,8 @@ typedef struct {
   int32_t precision;          /* rt_precision */
   int32_t n_table;            /* rows of `table` for RT_PHASE_TABLE (2 .. 65536), else ignored */
   const double *table;        /* host [n_table][7] for RT_PHASE_TABLE, else NULL; copied by rt_init */
+  int32_t nz;                 /* layers of an RT_PLANE_3D lattice (>= 1); 0 or 1 for the 2-D planes */
+  int32_t bc_z[2];            /* rt_bc of the z- and z+ faces (RT_PLANE_3D) */
 } rt_problem;
 
 /* ---- host-only helpers (no device needed) ------------------------------ */
@@ -167,8 +182,9 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
 /* Per-cell medium, [ny][nx] each: d_tau = per-step extinction optical depth
  * k_ext * dt (>= 0), d_albedo = k_scat / k_ext in [0, 1], d_emis = emission
  * amplitude eps.  The source of direction d is J = eps * h_jprof[d][0..3]
- * (host [n][4]).  h_inflow (host [4][n][4] or NULL = zero) is the radiance
- * entering through each inflow edge per direction.  The values are copied
+ * (host [n][4]).  h_inflow (host [4][n][4] or NULL = zero; [6][n][4] faces
+ * x-, x+, y-, y+, z-, z+ on an RT_PLANE_3D lattice) is the radiance entering
+ * through each inflow edge per direction.  The values are copied
  * into the workspace and the per-cell coefficients alpha = a s,
  * beta = a (1 - s) (a = absorption factor, s = survival, Eq. 11) are formed.
  * Validation needs the values on the host, so this call synchronises the

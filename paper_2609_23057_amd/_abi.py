@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librtlbm.so")
 RT_OK, RT_EINVAL, RT_ERANGE, RT_ESTATE, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED = range(7)
 RT_FP32, RT_BF16, RT_FP16, RT_BF16X3 = range(4)
 RT_ZEN_EQUAL_AREA, RT_ZEN_UNIFORM_THETA, RT_ZEN_EXPLICIT = range(3)
-RT_PLANE_XY, RT_PLANE_XZ, RT_PLANE_XY_D2Q9 = range(3)
+RT_PLANE_XY, RT_PLANE_XZ, RT_PLANE_XY_D2Q9, RT_PLANE_3D = range(4)
 RT_BC_PERIODIC, RT_BC_ABSORBING, RT_BC_INFLOW = range(3)
 RT_PHASE_RAYLEIGH, RT_PHASE_HG, RT_PHASE_MIX, RT_PHASE_TABLE = range(4)
 RT_ABS_TAYLOR, RT_SCAT_EXP, RT_FUSED_TAYLOR, RT_RENORM_IROW, RT_SCALAR, RT_PLAIN = (
@@ -30,7 +30,8 @@ class RtProblem(ctypes.Structure):
                 ("az_offset_deg", c_double), ("plane", c_int32), ("courant", c_double),
                 ("bc", c_int32 * 4), ("phase", c_int32), ("g", c_double), ("mix_ray", c_double),
                 ("dt", c_double), ("flags", c_uint32), ("precision", c_int32),
-                ("n_table", c_int32), ("table", POINTER(c_double))]
+                ("n_table", c_int32), ("table", POINTER(c_double)),
+                ("nz", c_int32), ("bc_z", c_int32 * 2)]
 
 
 class RTError(RuntimeError):

@@ -29,7 +29,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   // byte offsets into the workspace
   size_t tables, tables_bytes;   // uploaded host tables (rows, taps, tiles, fragments, M)
-  size_t taps, outdirs, MT;   // MT: float32 M transposed, for the plain path
+  size_t taps, taps3, outdirs, MT;   // MT: float32 M transposed, for the plain path
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
@@ -88,6 +88,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   };
   L.tables = off;
   L.taps = take(hp.n * sizeof(DirTaps));
+  L.taps3 = take(hp.n * sizeof(DirTaps3));
   L.outdirs = take(4 * hp.n * sizeof(int32_t));
   L.MT = take((size_t)hp.R * hp.R * sizeof(float));
   L.tiles_fwd32 = take(ntile * sizeof(TileRange));
@@ -102,7 +103,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   L.frag_adj_lo = take(pk.f_adj_lo.size());
   L.tables_bytes = off - L.tables;
   L.jrow = take(hp.Rpad * sizeof(float));
-  L.ghost = take(5 * hp.Rpad * sizeof(float));   // 4 edges + a zero row
+  L.ghost = take(7 * hp.Rpad * sizeof(float));   // 4 edges (6 faces in 3-D) + zero rows
   // phase mixture: tile ranges and dense A fragments of the second matrix in
   // the contraction precision (fp32 or bf16 fused steps), per-cell fraction
   {
@@ -156,6 +157,8 @@ struct rt_ctx {
   bool medium_set = false;
   bool mixture = false;   // rt_set_phase_mixture succeeded
   bool dichroic = false;  // rt_set_dichroism succeeded
+  bool three_d = false;   // RT_PLANE_3D lattice
+  Stream3Args s3{};       // its streaming arguments
   int prec = 0;
   int cu_count = 256;
   std::string err;
@@ -263,7 +266,8 @@ size_t rt_workspace_bytes(const rt_problem *p) {
 
 size_t rt_state_bytes(const rt_problem *p) {
   if (!p || p->nx < 1 || p->ny < 1 || p->n_zen < 1 || p->n_az < 1) return 0;
-  return (size_t)p->nx * p->ny * p->n_zen * p->n_az * 4 * sizeof(float);
+  const size_t layers = (p->plane == RT_PLANE_3D && p->nz > 1) ? (size_t)p->nz : 1;
+  return (size_t)p->nx * p->ny * layers * p->n_zen * p->n_az * 4 * sizeof(float);
 }
 
 size_t rt_adjoint_segment_bytes(const rt_problem *p, int32_t ckpt_every) {
@@ -369,6 +373,27 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
                       (float)(wx0 * wy0), (float)(wx1 * wy0), (float)(wx0 * wy1), (float)(wx1 * wy1)};
   }
   put(c->L.taps, taps.data(), taps.size() * sizeof(DirTaps));
+  std::vector<DirTaps3> taps3(hp.n);
+  for (int d = 0; d < hp.n; ++d) {
+    const double l[3] = {hp.lx[d], hp.ly[d], hp.lz[d]};
+    double base[3], w[3][2];
+    for (int a = 0; a < 3; ++a) {
+      base[a] = std::floor(l[a]);
+      const double f = l[a] - base[a];
+      w[a][0] = 1.0 - f;
+      w[a][1] = f;
+    }
+    DirTaps3 t{(int32_t)base[0], (int32_t)base[1], (int32_t)base[2], 0, {}};
+    for (int b = 0; b < 8; ++b) t.w[b] = (float)(w[0][b & 1] * w[1][(b >> 1) & 1] * w[2][b >> 2]);
+    taps3[d] = t;
+  }
+  put(c->L.taps3, taps3.data(), taps3.size() * sizeof(DirTaps3));
+  if (p->plane == RT_PLANE_3D) {
+    c->three_d = true;
+    c->s3 = Stream3Args{c->geo.C, hp.nx, hp.ny_lattice, hp.nz, hp.n, hp.Rpad, p->bc[0] == RT_BC_PERIODIC,
+                        p->bc[2] == RT_BC_PERIODIC, p->bc_z[0] == RT_BC_PERIODIC,
+                        c->at<DirTaps3>(c->L.taps3), c->at<float>(c->L.ghost)};
+  }
   std::vector<int32_t> od(4 * hp.n, 0);
   for (int e = 0; e < 4; ++e) {
     int k = 0;
@@ -411,25 +436,28 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
   const HostPlan &hp = c->hp;
   const int n = hp.n, Rp = hp.Rpad;
   std::vector<float> &hm = c->host_medium;
-  hm.assign(Rp + 5 * Rp, 0.0f);
+  hm.assign(Rp + 7 * Rp, 0.0f);
   for (int d = 0; d < n; ++d)
     for (int s = 0; s < 4; ++s) {
       const float v = h_jprof[4 * d + s];
       if (!std::isfinite(v)) return c->fail(RT_EINVAL, "emission profile not finite");
       hm[gemm_row(n, d, s)] = v;
     }
-  for (int e = 0; e < 4; ++e)
+  const int nfaces = c->three_d ? 6 : 4;
+  for (int e = 0; e < nfaces; ++e) {
+    const int bc = e < 4 ? c->prob.bc[e] : c->prob.bc_z[e - 4];
     for (int d = 0; d < n; ++d)
       for (int s = 0; s < 4; ++s) {
         const float v = h_inflow ? h_inflow[(e * n + d) * 4 + s] : 0.0f;
         if (!std::isfinite(v)) return c->fail(RT_EINVAL, "inflow radiance not finite");
-        hm[Rp + e * Rp + gemm_row(n, d, s)] = (c->prob.bc[e] == RT_BC_INFLOW) ? v : 0.0f;
+        hm[Rp + e * Rp + gemm_row(n, d, s)] = (bc == RT_BC_INFLOW) ? v : 0.0f;
       }
+  }
   static_assert(sizeof(float) == 4, "float");
   rt_status st = c->hip(hipMemcpyAsync(c->ws + c->L.jrow, hm.data(), Rp * sizeof(float),
                                        hipMemcpyHostToDevice, c->stream), "upload jprof");
   if (st == RT_OK)
-    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data() + Rp, 5 * Rp * sizeof(float),
+    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data() + Rp, 7 * Rp * sizeof(float),
                                hipMemcpyHostToDevice, c->stream), "upload inflow");
   int *bad = c->at<int>(c->L.bad);
   if (st == RT_OK) st = c->hip(hipMemsetAsync(bad, 0, sizeof(int), c->stream), "clear counter");
@@ -560,6 +588,20 @@ static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, f
   return c->hip(launch_step_mfma(a, c->prec, gather, c->stream, c->cu_count), "step");
 }
 
+// One step on a 3-D lattice: the collision of every cell (the fused kernel
+// without its 2-D gather, or the plain collision), then the trilinear pull.
+static rt_status step3d(rt_ctx *c, const float *S_in, float *S_out) {
+  StepArgs a = c->args(false);
+  float *Y = c->at<float>(c->L.Ya);
+  rt_status st;
+  if (c->prob.flags & RT_PLAIN)
+    st = c->hip(launch_collide_valu(a, c->at<float>(c->L.MT), S_in, Y, c->stream), "collide");
+  else
+    st = fwd_step(c, S_in, false, Y, nullptr);
+  if (st == RT_OK) st = c->hip(launch_stream3d(c->s3, Y, S_out, c->stream), "stream3d");
+  return st;
+}
+
 static rt_status plain_step(rt_ctx *c, const float *S_in, float *S_out) {
   StepArgs a = c->args(false);
   float *Y = c->at<float>(c->L.Ya);
@@ -573,6 +615,7 @@ rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out) {
   if (!d_S_in || !d_S_out) return c->fail(RT_EINVAL, "NULL state pointer");
   if (d_S_in == d_S_out) return c->fail(RT_EINVAL, "S_in and S_out must differ");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  if (c->three_d) return step3d(c, d_S_in, d_S_out);
   if (c->prob.flags & RT_PLAIN) return plain_step(c, d_S_in, d_S_out);
   float *Y = c->at<float>(c->L.Ya);
   rt_status st = fwd_step(c, d_S_in, false, Y, nullptr);
@@ -587,6 +630,7 @@ rt_status rt_stream(rt_ctx *c, const float *d_in, float *d_out) {
   const char *i0 = reinterpret_cast<const char *>(d_in), *o0 = reinterpret_cast<const char *>(d_out);
   if (i0 < o0 + bytes && o0 < i0 + bytes) return c->fail(RT_EINVAL, "d_in and d_out overlap");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  if (c->three_d) return c->hip(launch_stream3d(c->s3, d_in, d_out, c->stream), "stream3d");
   return c->hip(launch_stream(c->args(false), d_in, d_out, c->stream), "stream");
 }
 
@@ -600,11 +644,12 @@ rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t c
   const size_t sb = state_elems(c) * sizeof(float);
   auto slot = [&](int k) { return reinterpret_cast<float *>(reinterpret_cast<char *>(d_ckpt) + (size_t)k * sb); };
   rt_status st = RT_OK;
-  if (c->prob.flags & RT_PLAIN) {
+  if ((c->prob.flags & RT_PLAIN) || c->three_d) {
+    // two passes per step (collision into the workspace, streaming back)
     for (int t = 0; t < nsteps && st == RT_OK; ++t) {
       if (d_ckpt && t % ckpt_every == 0)
         st = c->hip(hipMemcpyAsync(slot(t / ckpt_every), d_S, sb, hipMemcpyDeviceToDevice, c->stream), "ckpt");
-      if (st == RT_OK) st = plain_step(c, d_S, d_S);
+      if (st == RT_OK) st = c->three_d ? step3d(c, d_S, d_S) : plain_step(c, d_S, d_S);
     }
     return st;
   }
@@ -623,6 +668,7 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_S) return c->fail(RT_EINVAL, "NULL state pointer");
   if (edge < 0 || edge > 3) return c->fail(RT_EINVAL, "edge must be 0..3");
+  if (d_out && c->three_d) return c->fail(RT_EUNSUPPORTED, "edge readouts are 2-D only (totals are available)");
   rt_status st = RT_OK;
   if (d_out)
     st = c->hip(launch_readout(c->geo, d_S, edge, c->at<int32_t>(c->L.outdirs) + edge * c->geo.n,
@@ -649,6 +695,7 @@ rt_status rt_readout_adjoint(rt_ctx *c, int32_t edge, const float *d_gout, float
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_gout || !d_lambdaT) return c->fail(RT_EINVAL, "NULL pointer");
   if (edge < 0 || edge > 3) return c->fail(RT_EINVAL, "edge must be 0..3");
+  if (c->three_d) return c->fail(RT_EUNSUPPORTED, "edge readouts are 2-D only");
   rt_status st = c->hip(launch_fill_f32(d_lambdaT, (int64_t)state_elems(c), 0.0f, c->stream), "fill");
   if (st == RT_OK)
     st = c->hip(launch_readout_adjoint(c->geo, edge, c->at<int32_t>(c->L.outdirs) + edge * c->geo.n,
@@ -665,6 +712,7 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
   if (c->mixture) return c->fail(RT_EUNSUPPORTED, "the adjoint of a phase mixture is not supported");
+  if (c->three_d) return c->fail(RT_EUNSUPPORTED, "the adjoint runs on 2-D lattices");
   if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "the adjoint of dichroic absorption is not supported");
   if (c->geo.Rpad > 512)
     return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");
@@ -836,6 +884,10 @@ rt_status batch_plan(const rt_problem *probs, int32_t nchan, BatchPlan *bp, std:
     if (st != RT_OK) {
       *msg = "channel " + std::to_string(i) + ": " + g_last_error;
       return st;
+    }
+    if (p.plane == RT_PLANE_3D) {
+      *msg = "3-D lattices cannot be batched";
+      return RT_EUNSUPPORTED;
     }
     if (p.flags & RT_PLAIN) {
       *msg = "RT_PLAIN channels cannot be batched";

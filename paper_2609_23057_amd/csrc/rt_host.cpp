@@ -142,16 +142,27 @@ int gemm_row(int n, int d, int s) {
 rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
   if (!p) { *msg = "problem is NULL"; return RT_EINVAL; }
   if (p->nx < 1 || p->ny < 1) { *msg = "nx and ny must be >= 1"; return RT_EINVAL; }
+  if (p->plane < 0 || p->plane > 3) { *msg = "plane out of range"; return RT_EINVAL; }
+  const bool three_d = p->plane == RT_PLANE_3D;
+  if (three_d && p->nz < 1) { *msg = "nz must be >= 1 for RT_PLANE_3D"; return RT_EINVAL; }
+  if (!three_d && p->nz > 1) { *msg = "nz > 1 needs RT_PLANE_3D"; return RT_EINVAL; }
+  const int nlay = three_d ? p->nz : 1;   // layers of the lattice
   if (p->n_zen < 1 || p->n_az < 1) { *msg = "n_zen and n_az must be >= 1"; return RT_EINVAL; }
   const long long n = (long long)p->n_zen * p->n_az;
   if (n > kMaxDirs) { *msg = "n_zen * n_az must be <= 256"; return RT_EINVAL; }
-  const long long cells = (long long)p->nx * p->ny;
+  const long long cells = (long long)p->nx * p->ny * nlay;
   if (cells * 4 * n > (1LL << 40)) { *msg = "state larger than 2^40 elements"; return RT_EINVAL; }
-  if (cells >= (1LL << 31)) { *msg = "nx * ny must be < 2^31"; return RT_EINVAL; }
+  if (cells >= (1LL << 31)) { *msg = "nx * ny (* nz) must be < 2^31"; return RT_EINVAL; }
   if (p->zen_rule < 0 || p->zen_rule > 2) { *msg = "zen_rule out of range"; return RT_EINVAL; }
   if (p->zen_rule == RT_ZEN_EXPLICIT && !p->zen_deg) { *msg = "zen_deg is NULL for RT_ZEN_EXPLICIT"; return RT_EINVAL; }
   if (!std::isfinite(p->az_offset_deg)) { *msg = "az_offset_deg not finite"; return RT_EINVAL; }
-  if (p->plane < 0 || p->plane > 2) { *msg = "plane out of range"; return RT_EINVAL; }
+  if (three_d) {
+    for (int e = 0; e < 2; ++e)
+      if (p->bc_z[e] < 0 || p->bc_z[e] > 2) { *msg = "bc_z value out of range"; return RT_EINVAL; }
+    if ((p->bc_z[0] == RT_BC_PERIODIC) != (p->bc_z[1] == RT_BC_PERIODIC)) {
+      *msg = "both z faces must be periodic or neither"; return RT_EINVAL;
+    }
+  }
   if (p->plane != RT_PLANE_XY_D2Q9 && !(std::isfinite(p->courant) && p->courant > 0)) {
     *msg = fmt("courant must be finite and > 0", p->courant); return RT_EINVAL;
   }
@@ -206,7 +217,9 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
   }
 
   hp->nx = p->nx;
-  hp->ny = p->ny;
+  hp->ny = p->ny * nlay;
+  hp->nz = nlay;
+  hp->ny_lattice = p->ny;
   hp->n = (int)n;
   hp->R = 4 * hp->n;
   hp->Rpad = (hp->R + kTileRows - 1) / kTileRows * kTileRows;
@@ -235,6 +248,7 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
   hp->eph.resize(3 * n);
   hp->lx.resize(n);
   hp->ly.resize(n);
+  hp->lz.assign(n, 0.0);
   hp->outmask.assign(n, 0);
   for (int i = 0; i < nz; ++i) {
     for (int j = 0; j < na; ++j) {
@@ -249,7 +263,12 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
       et[0] = ct * cp; et[1] = ct * sp; et[2] = -st;
       ep[0] = -sp; ep[1] = cp; ep[2] = 0.0;
       double l0, l1;
-      if (p->plane == RT_PLANE_XY) {
+      if (p->plane == RT_PLANE_3D) {
+        l0 = p->courant * k[0]; l1 = p->courant * k[1];
+        const double l2 = p->courant * k[2];
+        if (std::fabs(l2) > 1.0 + 1e-12) { *msg = fmt("displacement per step exceeds one cell", l2); return RT_ERANGE; }
+        hp->lz[d] = std::max(-1.0, std::min(1.0, l2));
+      } else if (p->plane == RT_PLANE_XY) {
         l0 = p->courant * k[0]; l1 = p->courant * k[1];
       } else if (p->plane == RT_PLANE_XZ) {
         l0 = p->courant * k[0]; l1 = p->courant * k[2];

@@ -16,12 +16,13 @@ constexpr int kTileRows = 32;  // rows of one MFMA output tile (32x32 family)
 
 // Host-side description of the direction grid and the operators, float64.
 struct HostPlan {
-  int nx = 0, ny = 0, n = 0;
+  int nx = 0, ny = 0, n = 0;   // ny: rows of cells (ny_lattice * nz on a 3-D lattice)
+  int nz = 1, ny_lattice = 0;  // 3-D lattice: layers and rows per layer
   int R = 0;      // 4n: rows of the contraction
   int Rpad = 0;   // R rounded up to kTileRows
   std::vector<double> theta, phi, domega;   // [n]
   std::vector<double> kvec, eth, eph;       // [n][3]
-  std::vector<double> lx, ly;               // [n] displacement per step
+  std::vector<double> lx, ly, lz;           // [n] displacement per step (lz: 3-D only)
   std::vector<int> outmask;                 // [n] bit e: leaves through edge e
   // Collision matrix in ABI order: row 4*d_out + s_out, column 4*d_in + s_in.
   std::vector<double> M;                    // [R][R]
@@ -37,6 +38,13 @@ struct DirTaps {
   float wx0, wx1;     // weights of offsets ox0 and ox0 + 1
   float wy0, wy1;
   float w00, w10, w01, w11;   // products wx_b * wy_b' (tap (bx, by) -> w_{bx by})
+};
+
+// Per-direction trilinear taps of a 3-D lattice: base offsets floor(l) and
+// the weights w[4 bz + 2 by + bx] = wx_bx wy_by wz_bz of offsets (base + b).
+struct DirTaps3 {
+  int32_t ox0, oy0, oz0, pad;
+  float w[8];
 };
 
 // Contraction tables in the row order used by the kernels: GEMM row

@@ -109,6 +109,16 @@ hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_
 hipError_t launch_adjoint_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s,
                                int cu_count);
 
+// Streaming on a 3-D lattice (trilinear pull along x, y and z).
+struct Stream3Args {
+  int64_t C;                  // nx ny nz
+  int32_t nx, ny, nz, n, Rpad;
+  int32_t per_x, per_y, per_z;
+  const DirTaps3 *taps;       // [n]
+  const float *ghost;         // [7][Rpad]: faces x-, x+, y-, y+, z-, z+, then zeros
+};
+hipError_t launch_stream3d(const Stream3Args &a, const float *in, float *out, hipStream_t s);
+
 // Plain float32 path: separate streaming and vector-ALU collision.
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s);
 hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,

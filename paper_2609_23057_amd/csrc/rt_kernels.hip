@@ -1353,6 +1353,50 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
   }
 }
 
+// Streaming on a 3-D lattice: out[4d + s](x, y, z) = sum over the 8 taps b of
+// w_b in[4d + s](x - ox0 - bx, y - oy0 - by, z - oz0 - bz) (the pull of Eq. 34
+// along each axis).  Periodic axes wrap; a tap still outside reads the ghost
+// radiance of its face (z before y before x; zero for absorbing faces).  One
+// thread per cell of one direction (blockIdx.y), the 4 Stokes planes together.
+__global__ void __launch_bounds__(256) stream3d_kernel(Stream3Args g, const float *__restrict__ in,
+                                                       float *__restrict__ out) {
+  const int d = blockIdx.y;
+  const DirTaps3 tp = g.taps[d];
+  const int C = (int)g.C;
+  const int64_t plane0 = (int64_t)(4 * d) * C;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+    const int x = c % g.nx;
+    const int t = c / g.nx;
+    const int y = t % g.ny;
+    const int z = t / g.ny;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const float w = tp.w[b];
+      if (w == 0.0f) continue;   // the same taps vanish for the whole direction
+      const int xs = wrap_axis(x - tp.ox0 - (b & 1), g.nx, g.per_x);
+      const int ys = wrap_axis(y - tp.oy0 - ((b >> 1) & 1), g.ny, g.per_y);
+      const int zs = wrap_axis(z - tp.oz0 - (b >> 2), g.nz, g.per_z);
+      const bool inx = (unsigned)xs < (unsigned)g.nx, iny = (unsigned)ys < (unsigned)g.ny;
+      const bool inz = (unsigned)zs < (unsigned)g.nz;
+      const float *p;
+      int64_t stride;
+      if (inx && iny && inz) {
+        p = in + plane0 + ((int64_t)zs * g.ny + ys) * g.nx + xs;
+        stride = C;
+      } else {
+        const int f = !inz ? (zs < 0 ? 4 : 5) : (!iny ? (ys < 0 ? 2 : 3) : (xs < 0 ? 0 : 1));
+        p = g.ghost + f * g.Rpad + 4 * d;
+        stride = 1;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = fmaf(w, p[s * stride], acc[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) out[plane0 + (int64_t)s * C + c] = acc[s];
+  }
+}
+
 // ------------------------------------------------------------- small kernels --
 
 __global__ void coef_kernel(int64_t C, const float *__restrict__ tau, const float *__restrict__ alb,
@@ -1586,6 +1630,12 @@ hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *
     hipLaunchKernelGGL(collide_valu_kernel<true>, grid, dim3(256), 0, s, a, MT, in, out);
   else
     hipLaunchKernelGGL(collide_valu_kernel<false>, grid, dim3(256), 0, s, a, MT, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream3d(const Stream3Args &a, const float *in, float *out, hipStream_t s) {
+  if (a.n < 1 || a.n > 65535 || a.C < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream3d_kernel, dim3(grid_for(a.C, 256, 2048), a.n), dim3(256), 0, s, a, in, out);
   return hipGetLastError();
 }
 

@@ -13,14 +13,14 @@ from . import _abi as A
 
 _ZEN = {"equal_area": A.RT_ZEN_EQUAL_AREA, "uniform_theta": A.RT_ZEN_UNIFORM_THETA,
         "explicit": A.RT_ZEN_EXPLICIT}
-_PLANE = {"xy": A.RT_PLANE_XY, "xz": A.RT_PLANE_XZ, "xy_d2q9": A.RT_PLANE_XY_D2Q9}
+_PLANE = {"xy": A.RT_PLANE_XY, "xz": A.RT_PLANE_XZ, "xy_d2q9": A.RT_PLANE_XY_D2Q9, "3d": A.RT_PLANE_3D}
 _PHASE = {"rayleigh": A.RT_PHASE_RAYLEIGH, "hg": A.RT_PHASE_HG, "mix": A.RT_PHASE_MIX, "table": A.RT_PHASE_TABLE}
 
 
 def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=None,
                  az_offset_deg=0.0, plane="xy", courant=1.0, bc=(0, 0, 0, 0), phase=None,
                  dt=1.0, precision="fp32", abs_taylor=False, scat_exp=False, fused_taylor=False,
-                 renorm_irow=False, scalar=False, plain=False, **_ignored):
+                 renorm_irow=False, scalar=False, plain=False, nz=1, bc6=None, **_ignored):
     """An RtProblem from keyword arguments (names follow the ABI struct)."""
     phase = phase or {"kind": "rayleigh"}
     p = A.RtProblem()
@@ -33,8 +33,16 @@ def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=No
     p.az_offset_deg = float(az_offset_deg)
     p.plane = _PLANE[plane]
     p.courant = float(courant)
-    for e in range(4):
-        p.bc[e] = int(bc[e])
+    if plane == "3d":
+        # faces x-, x+, y-, y+, z-, z+
+        faces = bc6 if bc6 is not None else tuple(bc) + (0, 0)
+        for e in range(4):
+            p.bc[e] = int(faces[e])
+        p.bc_z[0], p.bc_z[1] = int(faces[4]), int(faces[5])
+        p.nz = int(nz)
+    else:
+        for e in range(4):
+            p.bc[e] = int(bc[e])
     p.phase = _PHASE[phase.get("kind", "rayleigh")]
     p.g = float(phase.get("g", 0.0))
     p.mix_ray = float(phase.get("mix_ray", 1.0))
@@ -80,7 +88,10 @@ class Solver:
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.n = problem.n_zen * problem.n_az
         self.nx, self.ny = problem.nx, problem.ny
-        self.shape = (self.n, 4, self.ny, self.nx)
+        self.nz = problem.nz if problem.plane == A.RT_PLANE_3D else 1
+        # per-cell fields are [ny, nx] ([nz, ny, nx] on a 3-D lattice)
+        self.cells = (self.nz, self.ny, self.nx) if problem.plane == A.RT_PLANE_3D else (self.ny, self.nx)
+        self.shape = (self.n, 4) + self.cells
         if _ctx is None:
             nbytes = A.rt_workspace_bytes(problem)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -113,7 +124,8 @@ class Solver:
     # -- ABI calls -----------------------------------------------------------------
     def set_medium(self, tau, albedo, emis, jprof, inflow=None):
         jp = np.ascontiguousarray(jprof, dtype=np.float32).reshape(self.n, 4)
-        inf = None if inflow is None else np.ascontiguousarray(inflow, dtype=np.float32).reshape(4, self.n, 4)
+        nfaces = 6 if len(self.cells) == 3 else 4   # faces of a 3-D lattice, edges of a 2-D one
+        inf = None if inflow is None else np.ascontiguousarray(inflow, dtype=np.float32).reshape(nfaces, self.n, 4)
         self._medium = (tau, albedo, emis)
         A.rt_set_medium(self.ctx, _ptr(tau), _ptr(albedo), _ptr(emis), jp, inf)
 
@@ -156,7 +168,7 @@ class Solver:
         return h
 
     def maps(self, S):
-        I = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        I = torch.empty(self.cells, dtype=torch.float32, device=self.device)
         D = torch.empty_like(I)
         A.rt_maps(self.ctx, _ptr(S), _ptr(I), _ptr(D))
         return I, D

@@ -186,3 +186,27 @@ def test_table_validation(bad):
         P.rt_validate(p)
     assert ei.value.status == P.RT_EINVAL
     assert P.rt_workspace_bytes(p) == 0
+
+
+def test_three_d_problem_validation_and_sizes():
+    s = W.spec("beam3d", nx=6, ny=5, nz=4)
+    p = P.make_problem(**s)
+    P.rt_validate(p)
+    assert P.rt_state_bytes(p) == 6 * 5 * 4 * 32 * 4 * 4
+    assert P.rt_workspace_bytes(p) > 4 * P.rt_state_bytes(p)
+    for bad in (dict(bc6=(1, 1, 1, 1, 0, 1)), dict(bc6=(1, 1, 1, 1, 3, 3)), dict(nz=0)):
+        q = P.make_problem(**dict(s, **bad))
+        with pytest.raises(P.RTError) as ei:
+            P.rt_validate(q)
+        assert ei.value.status == P.RT_EINVAL, bad
+    q = P.make_problem(**dict(W.spec("beam512", nx=8, ny=8)))
+    q.nz = 3
+    with pytest.raises(P.RTError) as ei:
+        P.rt_validate(q)
+    assert ei.value.status == P.RT_EINVAL
+    # the 3-D collision matrix is the 2-D one of the same direction set
+    n = 32
+    M3, M2 = np.zeros((4 * n, 4 * n)), np.zeros((4 * n, 4 * n))
+    P.rt_describe(p, None, M3)
+    P.rt_describe(P.make_problem(**W.spec("beam512", nx=8, ny=8)), None, M2)
+    assert np.array_equal(M3, M2)

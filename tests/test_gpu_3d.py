@@ -1,0 +1,217 @@
+"""GPU parity of the three-dimensional lattice (RT_PLANE_3D) against the FP64
+3-D oracle, through the C ABI: streaming alone for every kind of face, the
+forward step in every precision and on the plain path, checkpoints, the
+per-cell phase mixture and dichroic absorption on a 3-D lattice, direction
+maps and totals, the full 256 x 256 x 64 workload on sampled cells through
+their one-step dependence window, and the refusals (edge readouts, adjoint,
+batch)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_common import TOL, assert_close, to_dev, to_np, tolerance
+from oracle import lbm as OL
+from oracle import lbm3d as O3
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def build3(spec, precision="fp32", medium=None):
+    import paper_2609_23057_amd as P
+    plain = precision == "plain"
+    s = dict(spec, precision="fp32" if plain else precision, plain=plain)
+    solver = P.Solver(P.make_problem(**s))
+    med = W.medium(spec) if medium is None else medium
+    t = [to_dev(med[k], solver) for k in ("tau", "albedo", "emis")]
+    solver.set_medium(*t, med["jprof"], med["inflow"])
+    solver._tensors = t
+    return solver, O3.make_problem(spec, med), med
+
+
+def spec3(nx, ny, nz, bc6=(1, 1, 1, 1, 1, 2), **kw):
+    return W.spec("beam3d", nx=nx, ny=ny, nz=nz, bc6=bc6, **kw)
+
+
+@pytest.mark.parametrize("bc6", [(1, 1, 1, 1, 1, 2), (0, 0, 0, 0, 0, 0), (0, 0, 2, 1, 1, 2), (2, 2, 0, 0, 2, 1)])
+@pytest.mark.parametrize("dims", [(9, 7, 5), (3, 2, 4), (1, 1, 1), (17, 3, 2)])
+def test_stream3d_parity(dims, bc6):
+    spec = spec3(*dims, bc6=bc6, n_zen=4, n_az=8, az_offset_deg=10.0, courant=0.9)
+    med = W.medium(spec)
+    med["inflow"][:, :, 0] = 0.5
+    med["inflow"][:, :, 1] = -0.1
+    solver, p3, _ = build3(spec, "fp32", med)
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal(solver.shape)
+    out = solver.empty_state()
+    solver.stream_field(to_dev(Y, solver), out)
+    ref = O3.stream(Y, p3)
+    assert np.abs(to_np(out) - ref).max() < 1e-6 * max(np.abs(ref).max(), 1.0)
+
+
+CASES = [
+    (dict(nx=9, ny=7, nz=5), 12),                        # n = 32
+    (dict(nx=6, ny=5, nz=4, n_zen=2, n_az=8), 15),       # n = 16
+    (dict(nx=5, ny=4, nz=3, n_zen=4, n_az=16), 10),      # n = 64
+    (dict(nx=5, ny=4, nz=3, n_zen=8, n_az=16), 8),       # n = 128
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16", "bf16x3", "fp16"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%dx%dx%d-n%d" % (
+    c[0]["nx"], c[0]["ny"], c[0]["nz"], W.ndir(W.spec("beam3d", **c[0]))))
+def test_forward3d_parity(case, precision):
+    over, steps = case
+    spec = W.spec("beam3d", **over)
+    solver, p3, _ = build3(spec, precision)
+    S0 = W.initial_state(spec, "random")
+    S = to_dev(S0, solver)
+    solver.run(S, steps)
+    ref = O3.run(S0, p3, steps)
+    e = assert_close(to_np(S), ref, tolerance(precision, p3.flat), (over, precision))
+    print(over, precision, e)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_step3d_checkpoints_maps_and_totals(precision):
+    spec = spec3(11, 8, 6, bc6=(0, 0, 1, 1, 1, 2))
+    solver, p3, _ = build3(spec, precision)
+    tol = tolerance(precision, p3.flat)
+    S0 = W.initial_state(spec, "random")
+    a, b = to_dev(S0, solver), solver.empty_state()
+    solver.step(a, b)
+    assert_close(to_np(b), O3.step(S0, p3), tol, "step")
+    T, K = 9, 4
+    ck = solver.checkpoint_buffer(T, K)
+    S = to_dev(S0, solver)
+    solver.run(S, T, ck, K)
+    _, hist = O3.run(S0, p3, T, keep=True)
+    for k in range(ck.shape[0]):
+        assert_close(to_np(ck[k]), hist[k * K], tol, ("ckpt", k))
+    assert_close(to_np(S), hist[T], tol, "final")
+    I, D = solver.maps(S)
+    Io, Do = OL.maps(hist[T].reshape(p3.flat.shape))
+    assert np.abs(to_np(I) - Io.reshape(I.shape)).max() <= 10 * tol * np.abs(Io).max()
+    sums = solver.sums(S)
+    assert np.allclose(sums[0], hist[T][:, 0].sum(), rtol=10 * tol)
+
+
+def test_mixture_and_dichroism_on_a_3d_lattice():
+    spec = spec3(8, 7, 5, mixture={"kind": "rayleigh"})
+    solver, p3, med = build3(spec, "fp32")
+    solver.set_phase_mixture(spec["mixture"], to_dev(med["frac"], solver))
+    S0 = W.initial_state(spec, "random")
+    S = to_dev(S0, solver)
+    solver.run(S, 10)
+    assert_close(to_np(S), O3.run(S0, p3, 10), 1e-5, "mixture 3d")
+    spec = spec3(8, 7, 5, dichroism=0.8)
+    med = W.medium(spec)
+    med["tau"] = np.minimum(med["tau"] * 40.0, 1.0).astype(np.float32).astype(np.float64)
+    med["albedo"] = (med["albedo"] * 0.6).astype(np.float32).astype(np.float64)
+    for precision in ("fp32", "plain"):
+        solver, p3, _ = build3(spec, precision, med)
+        solver.set_dichroism(to_dev(med["eta"], solver))
+        S = to_dev(S0, solver)
+        solver.run(S, 10)
+        assert_close(to_np(S), O3.run(S0, p3, 10), 1e-5, ("dichroism 3d", precision))
+
+
+def _window_reference(spec, med, S0, cell):
+    """The oracle's one-step output at `cell` = (z, y, x) of the full lattice,
+    computed on a window that holds the cell's whole one-step dependence
+    (taps reach at most two cells along each axis): along an axis the window
+    is the lattice itself if it is short, else 5 cells around the cell, or
+    the 5 cells at a face the cell lies within 2 of (keeping that face)."""
+    dims = (spec["nz"], spec["ny"], spec["nx"])
+    sl, centre, faces = [], [], list(spec["bc6"])
+    for a, (c, n) in enumerate(zip(cell, dims)):
+        face_lo, face_hi = 2 * (2 - a), 2 * (2 - a) + 1   # axis z -> faces 4, 5; y -> 2, 3; x -> 0, 1
+        periodic = faces[face_lo] == 0
+        if n <= 5:
+            sl.append(np.arange(n))
+            centre.append(c)
+            continue
+        if periodic:
+            idx = np.arange(c - 2, c + 3) % n
+            faces[face_lo] = faces[face_hi] = 1      # the window's ends are never reached
+            sl.append(idx)
+            centre.append(2)
+        elif c < 2:
+            sl.append(np.arange(0, 5))
+            centre.append(c)
+            faces[face_hi] = 1
+        elif c > n - 3:
+            sl.append(np.arange(n - 5, n))
+            centre.append(c - (n - 5))
+            faces[face_lo] = 1
+        else:
+            sl.append(np.arange(c - 2, c + 3))
+            centre.append(2)
+            faces[face_lo] = faces[face_hi] = 1
+    ix = np.ix_(*sl)
+    wspec = dict(spec, nz=len(sl[0]), ny=len(sl[1]), nx=len(sl[2]), bc6=tuple(faces))
+    wmed = dict(med)
+    for k in ("tau", "albedo", "emis"):
+        wmed[k] = med[k][ix]
+    p = O3.make_problem(wspec, wmed)
+    S = S0[(slice(None), slice(None)) + ix]
+    out = O3.step(S, p)
+    return out[:, :, centre[0], centre[1], centre[2]]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_beam3d_full_size_sampled_cells(precision):
+    """The 256 x 256 x 64, n = 32 workload: one step of the whole lattice on
+    the GPU; sampled cells (interior, faces, edges, corners) against the
+    oracle on their dependence window; then 20 steps keep every Stokes
+    vector physical."""
+    spec = W.spec("beam3d")
+    solver, _, med = build3(spec, precision)
+    rng = np.random.default_rng(17)
+    S0 = np.abs(rng.standard_normal(solver.shape)).astype(np.float32) * 0.1
+    S0[:, 1:] *= 0.2
+    a = to_dev(S0, solver)
+    b = solver.empty_state()
+    solver.step(a, b)
+    got = b.cpu().numpy()
+    nz, ny, nx = spec["nz"], spec["ny"], spec["nx"]
+    cells = [(nz // 2, ny // 2, nx // 2), (0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz - 1, 0, nx // 3),
+             (1, ny - 2, 1), (nz // 3, 0, nx - 1)] + [tuple(int(rng.integers(0, m)) for m in (nz, ny, nx))
+                                                   for _ in range(10)]
+    S0d = S0   # windows are taken in float32 and widened by the oracle
+    tol = TOL[precision]   # the medium's scattered share per step is small (beta <= 0.2)
+    for cell in cells:
+        ref = _window_reference(spec, med, S0d, cell)
+        g = got[:, :, cell[0], cell[1], cell[2]]
+        scale = np.abs(ref).max()
+        assert np.abs(g - ref).max() <= 10 * tol * scale, (cell, np.abs(g - ref).max(), scale)
+    S = solver.empty_state()
+    solver.run(S, 20)
+    torch.cuda.synchronize()
+    I, pol = S[:, 0], S[:, 1:].pow(2).sum(1).sqrt()
+    assert bool(torch.isfinite(S).all()) and float(I.min()) >= 0.0
+    assert bool((pol <= I * (1 + 1e-4) + 1e-12).all())
+
+
+def test_3d_refusals():
+    import paper_2609_23057_amd as P
+    spec = spec3(6, 5, 4)
+    solver, _, _ = build3(spec, "fp32")
+    S = solver.empty_state()
+    with pytest.raises(P.RTError) as ei:
+        solver.readout(S, 3)
+    assert ei.value.status == P.RT_EUNSUPPORTED
+    ck = solver.checkpoint_buffer(4, 2)
+    solver.run(S, 4, ck, 2)
+    with pytest.raises(P.RTError) as ei:
+        solver.adjoint(4, ck, 2, solver.empty_state())
+    assert ei.value.status == P.RT_EUNSUPPORTED
+    prob = P.make_problem(**dict(spec, precision="bf16"))
+    with pytest.raises(P.RTError):
+        P.Batch([prob])

@@ -29,8 +29,10 @@ Workloads (the paper's method at the sizes it is benchmarked on here):
                tabulated scattering matrix of an aerosol-like particle
                (forward peak, P12 < 0 at side angles, P34 != 0)
   beam3d       256x256x64 three-dimensional lattice (z = altitude), n = 32,
-               the beam512 medium generator, beam entering the top face z+,
-               absorbing side and bottom faces, 500 steps
+               the beam512 medium generator at the per-step optical depth of
+               a 512 lattice (the 4.2M draws of a 256 one reach tau_sca > 1),
+               beam entering the top face z+, absorbing side and bottom
+               faces, 500 steps
   spectral64   64 channels 400-900 nm, Rayleigh optical depth ~ lambda^-4 plus
                aerosol HG(0.6), per-channel lattice and direction count drawn
                from {128,256,384,512}^2 x {16,32,64}, 200 steps
@@ -57,7 +59,7 @@ _BASE = {
     "beam3d": dict(nx=256, ny=256, nz=64, n_zen=4, n_az=8, zen_rule="equal_area", az_offset_deg=0.0,
                    plane="3d", courant=1.0, bc6=(1, 1, 1, 1, 1, 2),
                    phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=7,
-                   medium="lognormal", tau_ref_n=256, beam_dir=3 * 8 + 0, source="none"),
+                   medium="lognormal", tau_ref_n=512, beam_dir=3 * 8 + 0, source="none"),
     "adjoint256": dict(nx=256, ny=256, n_zen=4, n_az=8, zen_rule="equal_area",
                        az_offset_deg=0.0, plane="xz", courant=1.0, bc=(1, 1, 1, 2),
                        phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=4,

@@ -15,7 +15,7 @@ Extras (skipped with --no-extras): forward rates at 1024x1024, n = 128 per
 contraction precision, the stand-alone streaming kernel's HBM rate at beam512
 and prec1024, the forward step at beam512 with each extension of the operator
 (tabulated scattering matrix, per-cell phase mixture, dichroic absorption),
-and the 64-channel spectral batch (one launch per step for all
+the 256x256x64 three-dimensional lattice, and the 64-channel spectral batch (one launch per step for all
 channels, eager and as a replayed HIP graph).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
@@ -216,6 +216,51 @@ def extension_extras(T=20, warm=3):
         res[prec] = out
     return {"workload": "beam512 (512x512, n=32), forward steps: plain workload, tabulated scattering matrix, "
                         "per-cell HG(0.7)/Rayleigh mixture, dichroic absorption", "steps": T, "rates": res}
+
+
+def three_d_extras(T=10, warm=2, reps=20):
+    """The 3-D lattice (beam3d: 256 x 256 x 64, n = 32): forward steps per
+    contraction precision (per-cell collision, then the trilinear pull), and
+    the 3-D streaming kernel alone (HIP events around `reps` launches on the
+    solver's stream) against the HBM peak at 32 algorithmic bytes per
+    cell-direction."""
+    import torch
+    import workloads as W
+    spec = W.spec("beam3d")
+    C, n = spec["nx"] * spec["ny"] * spec["nz"], W.ndir(spec)
+    res = {}
+    for prec in ("fp32", "bf16"):
+        _log("bench: beam3d %s" % prec)
+        solver = make_solver(spec, prec)
+        S = solver.empty_state()
+        solver.run(S, warm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        solver.run(S, T)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[prec] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+        if prec == "fp32":
+            b = torch.empty_like(S)
+            solver.stream_field(S, b)
+            torch.cuda.synchronize()
+            e0.record()
+            for i in range(reps):
+                solver.stream_field(S, b) if i % 2 == 0 else solver.stream_field(b, S)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            nbytes = 32.0 * C * n
+            gbs = nbytes / (us * 1e-6) / 1e9
+            res["stream3d"] = {"avg_launch_us": us, "algorithmic_bytes_per_launch": nbytes, "achieved": gbs,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "bound": "hbm"}
+            del b
+        del solver, S
+        torch.cuda.empty_cache()
+    return {"workload": "beam3d: 256x256x64 lattice, n=32 (4x8), forward steps (collision + trilinear streaming)",
+            "steps": T, "rates": res}
 
 
 def streaming_extras(reps=50):
@@ -421,6 +466,8 @@ def main():
         line["streaming"] = streaming_extras()
         torch.cuda.empty_cache()
         line["extensions"] = extension_extras()
+        torch.cuda.empty_cache()
+        line["three_d"] = three_d_extras()
         torch.cuda.empty_cache()
         line["spectral_batch"] = spectral_extras()
         torch.cuda.empty_cache()

@@ -1356,45 +1356,130 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
 // Streaming on a 3-D lattice: out[4d + s](x, y, z) = sum over the 8 taps b of
 // w_b in[4d + s](x - ox0 - bx, y - oy0 - by, z - oz0 - bz) (the pull of Eq. 34
 // along each axis).  Periodic axes wrap; a tap still outside reads the ghost
-// radiance of its face (z before y before x; zero for absorbing faces).  One
-// thread per cell of one direction (blockIdx.y), the 4 Stokes planes together.
-__global__ void __launch_bounds__(256) stream3d_kernel(Stream3Args g, const float *__restrict__ in,
-                                                       float *__restrict__ out) {
-  const int d = blockIdx.y;
-  const DirTaps3 tp = g.taps[d];
-  const int C = (int)g.C;
-  const int64_t plane0 = (int64_t)(4 * d) * C;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-    const int x = c % g.nx;
-    const int t = c / g.nx;
-    const int y = t % g.ny;
-    const int z = t / g.ny;
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+// radiance of its face (z before y before x; zero for absorbing faces).
+//
+// Columns x in [4, nx - 5] (nx a multiple of 4: "quad columns") have every
+// x tap inside the lattice.  There a thread produces 4 consecutive cells of
+// 2 rows of 2 layers of one plane from the 3 x 3 source rows they share, each
+// read as two aligned 16-byte loads, or, for a row outside the lattice in y
+// or z, taken as its face's ghost value (uniform along the row).  The 8 end
+// columns of every row take one thread per cell with the general tap rules.
+struct Box3 {
+  int on;          // quad columns exist (nx a multiple of 4, nx >= 12, aligned fields)
+  int nqx;         // quads per row
+  int nyp, nq;     // row pairs per layer; 2 x 2 blocks of quads per plane
+  int nbord;       // cells of the end columns (all cells when `on` is 0)
+  int ib;          // blocks per plane taking quads
+  int bpp;         // blocks per plane
+};
+
+template <int SH>
+__device__ __forceinline__ void quad3_block(const Stream3Args &g, const DirTaps3 &tp, const float *__restrict__ in,
+                                            int64_t plane, int p, int x0, int y, int z, float *__restrict__ out) {
+  const int64_t layer = (int64_t)g.ny * g.nx;
+  float e[3][3][8];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const float w = tp.w[b];
-      if (w == 0.0f) continue;   // the same taps vanish for the whole direction
-      const int xs = wrap_axis(x - tp.ox0 - (b & 1), g.nx, g.per_x);
-      const int ys = wrap_axis(y - tp.oy0 - ((b >> 1) & 1), g.ny, g.per_y);
-      const int zs = wrap_axis(z - tp.oz0 - (b >> 2), g.nz, g.per_z);
-      const bool inx = (unsigned)xs < (unsigned)g.nx, iny = (unsigned)ys < (unsigned)g.ny;
-      const bool inz = (unsigned)zs < (unsigned)g.nz;
-      const float *p;
-      int64_t stride;
-      if (inx && iny && inz) {
-        p = in + plane0 + ((int64_t)zs * g.ny + ys) * g.nx + xs;
-        stride = C;
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int zs = wrap_axis(z - tp.oz0 + a - 1, g.nz, g.per_z);
+      const int ys = wrap_axis(y - tp.oy0 + b - 1, g.ny, g.per_y);
+      const bool inz = (unsigned)zs < (unsigned)g.nz, iny = (unsigned)ys < (unsigned)g.ny;
+      if (inz && iny) {
+        // from SH + 1 floats before the first cell's bx = 0 tap: 16-byte aligned
+        const float *r = in + plane + zs * layer + (int64_t)ys * g.nx + x0 - tp.ox0 - 1 - SH;
+        const f32x4 v0 = *reinterpret_cast<const f32x4 *>(r);
+        const f32x4 v1 = *reinterpret_cast<const f32x4 *>(r + 4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          e[a][b][k] = v0[k];
+          e[a][b][k + 4] = v1[k];
+        }
       } else {
-        const int f = !inz ? (zs < 0 ? 4 : 5) : (!iny ? (ys < 0 ? 2 : 3) : (xs < 0 ? 0 : 1));
-        p = g.ghost + f * g.Rpad + 4 * d;
-        stride = 1;
-      }
+        const float gv = g.ghost[(!inz ? (zs < 0 ? 4 : 5) : (ys < 0 ? 2 : 3)) * g.Rpad + p];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] = fmaf(w, p[s * stride], acc[s]);
+        for (int k = 0; k < 8; ++k) e[a][b][k] = gv;
+      }
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) out[plane0 + (int64_t)s * C + c] = acc[s];
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (z + i >= g.nz || y + j >= g.ny) continue;
+      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+        for (int by = 0; by < 2; ++by) {
+          const float *ev = e[i - bz + 1][j - by + 1];
+          const float w0 = tp.w[4 * bz + 2 * by], w1 = tp.w[4 * bz + 2 * by + 1];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[k] = fmaf(w1, ev[SH + k], fmaf(w0, ev[SH + k + 1], acc[k]));
+        }
+      *reinterpret_cast<f32x4 *>(out + plane + (z + i) * layer + (int64_t)(y + j) * g.nx + x0) =
+          f32x4{acc[0], acc[1], acc[2], acc[3]};
+    }
+}
+
+// box.bpp blocks per plane p = 4 d + s: the first box.ib take 2 x 2 blocks
+// of quads, the rest one end-column cell per thread.  Blocks are dispatched
+// round-robin over the 8 XCDs; the logical order is remapped so that each XCD
+// takes a contiguous range, and the source rows that neighbouring blocks of a
+// plane share stay in one XCD's L2.
+__global__ void __launch_bounds__(256) stream3d_kernel(Stream3Args g, Box3 box, const float *__restrict__ in,
+                                                       float *__restrict__ out) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = b & 7;
+  const int lb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + (b >> 3);
+  const int p = lb / box.bpp, bx = lb - p * box.bpp;
+  const DirTaps3 tp = g.taps[p >> 2];
+  const int64_t plane = (int64_t)p * g.C;
+  if (bx < box.ib) {
+    const int q = bx * blockDim.x + threadIdx.x;
+    if (q >= box.nq) return;
+    const int qx = q % box.nqx;
+    const int t = q / box.nqx;
+    const int y = 2 * (t % box.nyp);
+    const int z = 2 * (t / box.nyp);
+    const int x0 = 4 + 4 * qx;
+    switch ((-tp.ox0 - 1) & 3) {
+      case 0: quad3_block<0>(g, tp, in, plane, p, x0, y, z, out); break;
+      case 1: quad3_block<1>(g, tp, in, plane, p, x0, y, z, out); break;
+      case 2: quad3_block<2>(g, tp, in, plane, p, x0, y, z, out); break;
+      default: quad3_block<3>(g, tp, in, plane, p, x0, y, z, out); break;
+    }
+    return;
   }
+  const int k = (bx - box.ib) * blockDim.x + threadIdx.x;
+  if (k >= box.nbord) return;
+  int x, y, z;
+  if (box.on) {   // the 4 + 4 end cells of row r = z ny + y
+    const int r = k >> 3, i = k & 7;
+    x = i < 4 ? i : g.nx - 8 + i;
+    y = r % g.ny;
+    z = r / g.ny;
+  } else {
+    x = k % g.nx;
+    const int t = k / g.nx;
+    y = t % g.ny;
+    z = t / g.ny;
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const float w = tp.w[b];
+    if (w == 0.0f) continue;   // the same taps vanish for the whole direction
+    const int xs = wrap_axis(x - tp.ox0 - (b & 1), g.nx, g.per_x);
+    const int ys = wrap_axis(y - tp.oy0 - ((b >> 1) & 1), g.ny, g.per_y);
+    const int zs = wrap_axis(z - tp.oz0 - (b >> 2), g.nz, g.per_z);
+    const bool inside = (unsigned)xs < (unsigned)g.nx && (unsigned)ys < (unsigned)g.ny &&
+                        (unsigned)zs < (unsigned)g.nz;
+    const int f = (unsigned)zs >= (unsigned)g.nz ? (zs < 0 ? 4 : 5)
+                  : ((unsigned)ys >= (unsigned)g.ny ? (ys < 0 ? 2 : 3) : (xs < 0 ? 0 : 1));
+    const float v = inside ? in[plane + ((int64_t)zs * g.ny + ys) * g.nx + xs] : g.ghost[f * g.Rpad + p];
+    acc = fmaf(w, v, acc);
+  }
+  out[plane + ((int64_t)z * g.ny + y) * g.nx + x] = acc;
 }
 
 // ------------------------------------------------------------- small kernels --
@@ -1634,8 +1719,21 @@ hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *
 }
 
 hipError_t launch_stream3d(const Stream3Args &a, const float *in, float *out, hipStream_t s) {
-  if (a.n < 1 || a.n > 65535 || a.C < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(stream3d_kernel, dim3(grid_for(a.C, 256, 2048), a.n), dim3(256), 0, s, a, in, out);
+  if (a.n < 1 || 4 * a.n > 65535 || a.C < 1) return hipErrorInvalidValue;
+  Box3 box{0, 0, 0, 0, (int)a.C, 0, 0};
+  const bool aligned = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  if (aligned && a.nx % 4 == 0 && a.nx >= 12) {
+    box.on = 1;
+    box.nqx = a.nx / 4 - 2;
+    box.nyp = (a.ny + 1) / 2;
+    box.nq = box.nqx * box.nyp * ((a.nz + 1) / 2);
+    box.nbord = 8 * a.ny * a.nz;
+    box.ib = (box.nq + 255) / 256;
+  }
+  box.bpp = box.ib + (box.nbord + 255) / 256;
+  const int64_t blocks = (int64_t)box.bpp * 4 * a.n;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream3d_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, box, in, out);
   return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ def spec3(nx, ny, nz, bc6=(1, 1, 1, 1, 1, 2), **kw):
 
 
 @pytest.mark.parametrize("bc6", [(1, 1, 1, 1, 1, 2), (0, 0, 0, 0, 0, 0), (0, 0, 2, 1, 1, 2), (2, 2, 0, 0, 2, 1)])
-@pytest.mark.parametrize("dims", [(9, 7, 5), (3, 2, 4), (1, 1, 1), (17, 3, 2)])
+@pytest.mark.parametrize("dims", [(9, 7, 5), (3, 2, 4), (1, 1, 1), (17, 3, 2),
+                                  (16, 9, 7), (12, 5, 5), (20, 6, 8)])   # the last three: interior quads
 def test_stream3d_parity(dims, bc6):
     spec = spec3(*dims, bc6=bc6, n_zen=4, n_az=8, az_offset_deg=10.0, courant=0.9)
     med = W.medium(spec)
@@ -57,6 +58,7 @@ def test_stream3d_parity(dims, bc6):
 
 CASES = [
     (dict(nx=9, ny=7, nz=5), 12),                        # n = 32
+    (dict(nx=16, ny=9, nz=7), 10),                       # n = 32, interior quads
     (dict(nx=6, ny=5, nz=4, n_zen=2, n_az=8), 15),       # n = 16
     (dict(nx=5, ny=4, nz=3, n_zen=4, n_az=16), 10),      # n = 64
     (dict(nx=5, ny=4, nz=3, n_zen=8, n_az=16), 8),       # n = 128

@@ -156,7 +156,7 @@ rt_status rt_validate(const rt_problem *p);
  * 2 state buffers plus 2 adjoint buffers plus O(n^2 + cells) of tables. */
 size_t rt_workspace_bytes(const rt_problem *p);
 
-/* Bytes of one state S (4 * n * nx * ny floats). */
+/* Bytes of one state S (4 * n * nx * ny floats, times nz on a 3-D lattice). */
 size_t rt_state_bytes(const rt_problem *p);
 
 /* Direction set and operators in float64, as the library builds them.

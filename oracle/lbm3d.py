@@ -138,3 +138,68 @@ def make_problem(spec, medium):
                      medium.get("inflow"), abs_taylor=spec.get("abs_taylor", False),
                      scat_exp=spec.get("scat_exp", False), fused_taylor=spec.get("fused_taylor", False),
                      M2=M2, frac=medium.get("frac"), dichroism=medium.get("eta"))
+
+
+def stream_transpose(G, prob):
+    """Transpose of the linear part of stream(): the forward adds w Y[source]
+    into target; the transpose adds w G[target] into source, for sources in
+    the lattice only (ghosts are constants and carry no gradient)."""
+    G = np.asarray(G, dtype=np.float64).reshape(prob.shape)
+    out = np.zeros_like(G)
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for d in range(prob.n):
+        lx, ly, lz = prob.shifts[d]
+        for ox, wx in lbm._taps(lx):
+            for oy, wy in lbm._taps(ly):
+                for oz, wz in lbm._taps(lz):
+                    xs, ys, zs = xx - ox, yy - oy, zz - oz
+                    if prob.bc[FACE_XM] == lbm.BC_PERIODIC:
+                        xs = np.mod(xs, nx)
+                    if prob.bc[FACE_YM] == lbm.BC_PERIODIC:
+                        ys = np.mod(ys, ny)
+                    if prob.bc[FACE_ZM] == lbm.BC_PERIODIC:
+                        zs = np.mod(zs, nz)
+                    inside = (xs >= 0) & (xs < nx) & (ys >= 0) & (ys < ny) & (zs >= 0) & (zs < nz)
+                    for s in range(4):
+                        np.add.at(out[d, s], (zs[inside], ys[inside], xs[inside]),
+                                  wx * wy * wz * G[d, s][inside])
+    return out
+
+
+def adjoint(S0, prob, nsteps, lam_T):
+    """Reverse-mode gradient on a 3-D lattice, the chain rule of oracle.adjoint
+    with the 3-D streaming: for t = T-1 .. 0, mu = L^T lambda_{t+1},
+    nu = M^T mu, lambda_t = alpha mu + beta nu, g_alpha += <mu, X_t>,
+    g_beta += <nu, X_t>, g_emis += dt <e lambda_t + (1 - e) mu, jprof>.
+    Returns dict(lambda0, g_alpha, g_beta, g_tau, g_albedo, g_emis), per-cell
+    arrays [nz, ny, nx]."""
+    f = prob.flat
+    if f.M2 is not None or f.eta is not None:
+        raise NotImplementedError("the adjoint covers single-phase, non-dichroic media")
+    n, C = prob.n, prob.nx * prob.ny * prob.nz
+    J = f.emission_field().reshape(prob.shape)
+    e = 0.0 if f.fused_taylor else 1.0
+    _, hist = run(S0, prob, nsteps, keep=True)
+    jp = f.jprof.reshape(n, 4, 1)
+    lam = np.array(lam_T, dtype=np.float64).reshape(prob.shape)
+    al, be = f.alpha.reshape(C), f.beta.reshape(C)
+    g_al, g_be, g_em = np.zeros(C), np.zeros(C), np.zeros(C)
+    for t in range(nsteps - 1, -1, -1):
+        X = (hist[t] + e * f.dt * J).reshape(4 * n, C)
+        mu = stream_transpose(lam, prob).reshape(4 * n, C)
+        nu = f.M.T @ mu
+        g_al += np.sum(mu * X, axis=0)
+        g_be += np.sum(nu * X, axis=0)
+        lam_x = al[None, :] * mu + be[None, :] * nu
+        src = e * lam_x + (1.0 - e) * mu
+        g_em += f.dt * np.sum(src.reshape(n, 4, C) * jp, axis=(0, 1))
+        lam = lam_x.reshape(prob.shape)
+    dal_dt, dal_dw, dbe_dt, dbe_dw = lbm.coefficient_derivatives(f.tau, f.albedo, f.abs_taylor, f.scat_exp,
+                                                                 f.fused_taylor)
+    shp = (prob.nz, prob.ny, prob.nx)
+    g_al, g_be = g_al.reshape(shp), g_be.reshape(shp)
+    return {"lambda0": lam, "g_alpha": g_al, "g_beta": g_be,
+            "g_tau": g_al * dal_dt.reshape(shp) + g_be * dbe_dt.reshape(shp),
+            "g_albedo": g_al * dal_dw.reshape(shp) + g_be * dbe_dw.reshape(shp),
+            "g_emis": g_em.reshape(shp)}

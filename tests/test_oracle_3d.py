@@ -130,3 +130,65 @@ def test_face_validation():
     with pytest.raises(ValueError):
         O3.Problem3D(4, 4, 4, dirs, 1.5, (0,) * 6, np.eye(32), 1.0, np.zeros((4, 4, 4)), np.zeros((4, 4, 4)),
                      np.zeros((4, 4, 4)), np.zeros((8, 4)))
+
+
+@pytest.mark.parametrize("bc6", [(0, 0, 0, 0, 0, 0), (1, 1, 2, 1, 0, 0), (2, 2, 0, 0, 1, 2)])
+def test_stream_transpose_is_the_transpose(bc6):
+    """<L Y, G> = <Y, L^T G> for the linear part (inflow ghosts zeroed)."""
+    s3 = spec3(nx=5, ny=4, nz=6, bc6=bc6, n_zen=4, n_az=5, az_offset_deg=10.0, courant=0.9)
+    med = W.medium(s3)
+    med["inflow"][:] = 0.0
+    p3 = O3.make_problem(s3, med)
+    rng = np.random.default_rng(8)
+    Y, G = rng.standard_normal(p3.shape), rng.standard_normal(p3.shape)
+    lhs = np.sum(O3.stream(Y, p3) * G)
+    rhs = np.sum(Y * O3.stream_transpose(G, p3))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_adjoint3d_matches_central_differences():
+    s3 = spec3(nx=4, ny=3, nz=3, bc6=(1, 1, 0, 0, 1, 2), n_zen=2, n_az=4, source="uniform_emis", emis_max=0.05)
+    med = W.medium(s3)
+    med["tau"] = med["tau"] * 40.0
+    p3 = O3.make_problem(s3, med)
+    rng = np.random.default_rng(12)
+    S0 = np.abs(rng.standard_normal(p3.shape)) * 0.1
+    G = rng.standard_normal(p3.shape)
+    T = 5
+    res = O3.adjoint(S0, p3, T, G)
+
+    def loss(m):
+        return np.sum(O3.run(S0, O3.make_problem(s3, m), T) * G)
+    for key, field in (("g_tau", "tau"), ("g_albedo", "albedo"), ("g_emis", "emis")):
+        for cell in ((0, 0, 0), (1, 2, 3), (2, 1, 1)):
+            h = 1e-3 * max(abs(med[field][cell]), 1e-2)   # roundoff of the O(1) loss dominates below
+            mp, mm = dict(med), dict(med)
+            mp[field] = med[field].copy()
+            mm[field] = med[field].copy()
+            mp[field][cell] += h
+            mm[field][cell] -= h
+            fd = (loss(mp) - loss(mm)) / (2 * h)
+            assert res[key][cell] == pytest.approx(fd, rel=1e-6, abs=1e-11), (key, cell)
+    # lambda0 = dLoss/dS0
+    d = np.zeros(p3.shape)
+    d[1, 2, 1, 0, 2] = 1e-6
+    fd = (np.sum(O3.run(S0 + d, p3, T) * G) - np.sum(O3.run(S0 - d, p3, T) * G)) / 2e-6
+    assert res["lambda0"][1, 2, 1, 0, 2] == pytest.approx(fd, rel=1e-6)
+
+
+def test_adjoint3d_one_layer_equals_the_2d_adjoint():
+    from oracle import adjoint as OA
+    s3 = spec3(nx=6, ny=5, nz=1, bc6=(1, 1, 0, 0, 0, 0), n_zen=4, n_az=8)
+    med = W.medium(s3)
+    p3 = O3.make_problem(s3, med)
+    s2 = dict(s3, plane="xy", bc=(1, 1, 0, 0))
+    med2 = dict(med, tau=med["tau"][0], albedo=med["albedo"][0], emis=med["emis"][0], inflow=med["inflow"][:4])
+    p2 = OL.make_problem(s2, med2)
+    rng = np.random.default_rng(3)
+    S0 = np.abs(rng.standard_normal(p3.shape))
+    G = rng.standard_normal(p3.shape)
+    r3 = O3.adjoint(S0, p3, 4, G)
+    r2 = OA.adjoint(S0[:, :, 0], p2, 4, G[:, :, 0])
+    for k in ("g_tau", "g_albedo", "g_emis"):
+        assert np.abs(r3[k][0] - r2[k]).max() < 1e-12 * max(np.abs(r2[k]).max(), 1.0)
+    assert np.abs(r3["lambda0"][:, :, 0] - r2["lambda0"]).max() < 1e-12 * np.abs(r2["lambda0"]).max()

@@ -79,11 +79,11 @@ typedef enum { RT_ZEN_EQUAL_AREA = 0, RT_ZEN_UNIFORM_THETA = 1, RT_ZEN_EXPLICIT 
  *                     c = (z ny + y) nx + x; per-cell fields are [nz][ny][nx].
  *                     Faces x-, x+, y-, y+ take bc[0..3], z-, z+ take bc_z[0..1];
  *                     a ghost outside in z takes its z face, else its y face,
- *                     else its x face.  Forward only: rt_step, rt_run (with
- *                     checkpoints), rt_stream, rt_maps, the totals of
- *                     rt_readout, rt_set_phase_mixture and rt_set_dichroism;
- *                     edge readouts, the adjoint and the batch return
- *                     RT_EUNSUPPORTED. */
+ *                     else its x face.  rt_step, rt_run (with checkpoints),
+ *                     rt_stream, rt_maps, the totals of rt_readout,
+ *                     rt_set_phase_mixture, rt_set_dichroism, and rt_adjoint
+ *                     (lambda_T given as a whole state); edge readouts and
+ *                     the batch return RT_EUNSUPPORTED. */
 typedef enum { RT_PLANE_XY = 0, RT_PLANE_XZ = 1, RT_PLANE_XY_D2Q9 = 2, RT_PLANE_3D = 3 } rt_plane;
 
 /* Edges are numbered 0 = x-, 1 = x+, 2 = y-, 3 = y+.  Periodic is the

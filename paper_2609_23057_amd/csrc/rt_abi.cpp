@@ -29,7 +29,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   // byte offsets into the workspace
   size_t tables, tables_bytes;   // uploaded host tables (rows, taps, tiles, fragments, M)
-  size_t taps, taps3, outdirs, MT;   // MT: float32 M transposed, for the plain path
+  size_t taps, taps3, taps3_rev, ghost_zero, outdirs, MT;   // MT: float32 M transposed, for the plain path
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
@@ -89,6 +89,8 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   L.tables = off;
   L.taps = take(hp.n * sizeof(DirTaps));
   L.taps3 = take(hp.n * sizeof(DirTaps3));
+  L.taps3_rev = take(hp.n * sizeof(DirTaps3));
+  L.ghost_zero = take(7 * hp.Rpad * sizeof(float));   // zeros: the reverse 3-D pull's ghosts
   L.outdirs = take(4 * hp.n * sizeof(int32_t));
   L.MT = take((size_t)hp.R * hp.R * sizeof(float));
   L.tiles_fwd32 = take(ntile * sizeof(TileRange));
@@ -159,6 +161,7 @@ struct rt_ctx {
   bool dichroic = false;  // rt_set_dichroism succeeded
   bool three_d = false;   // RT_PLANE_3D lattice
   Stream3Args s3{};       // its streaming arguments
+  Stream3Args s3rev{};    // the transpose of its streaming (the adjoint's reverse pull)
   int prec = 0;
   int cu_count = 256;
   std::string err;
@@ -365,15 +368,19 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     if (bytes) std::memcpy(tb.data() + (off - c->L.tables), src, bytes);
   };
   std::vector<DirTaps> taps(hp.n);
+  const bool is3d = p->plane == RT_PLANE_3D;
   for (int d = 0; d < hp.n; ++d) {
-    const double fx0 = std::floor(hp.lx[d]), fy0 = std::floor(hp.ly[d]);
-    const double fx = hp.lx[d] - fx0, fy = hp.ly[d] - fy0;
+    // a 3-D lattice streams with its own kernel; the fused kernels see the
+    // identity pull there (the adjoint kernel reads the reverse-pulled field)
+    const double lxd = is3d ? 0.0 : hp.lx[d], lyd = is3d ? 0.0 : hp.ly[d];
+    const double fx0 = std::floor(lxd), fy0 = std::floor(lyd);
+    const double fx = lxd - fx0, fy = lyd - fy0;
     const double wx0 = 1.0 - fx, wx1 = fx, wy0 = 1.0 - fy, wy1 = fy;
     taps[d] = DirTaps{(int32_t)fx0, (int32_t)fy0, (float)wx0, (float)wx1, (float)wy0, (float)wy1,
                       (float)(wx0 * wy0), (float)(wx1 * wy0), (float)(wx0 * wy1), (float)(wx1 * wy1)};
   }
   put(c->L.taps, taps.data(), taps.size() * sizeof(DirTaps));
-  std::vector<DirTaps3> taps3(hp.n);
+  std::vector<DirTaps3> taps3(hp.n), taps3_rev(hp.n);
   for (int d = 0; d < hp.n; ++d) {
     const double l[3] = {hp.lx[d], hp.ly[d], hp.lz[d]};
     double base[3], w[3][2];
@@ -386,13 +393,35 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     DirTaps3 t{(int32_t)base[0], (int32_t)base[1], (int32_t)base[2], 0, {}};
     for (int b = 0; b < 8; ++b) t.w[b] = (float)(w[0][b & 1] * w[1][(b >> 1) & 1] * w[2][b >> 2]);
     taps3[d] = t;
+    // transpose: in'(x) = sum_b w_b out(x + o_b) is the pull with base
+    // offset -o0 - 1 along each axis and the two weights swapped; a base of
+    // -2 (l = 1 exactly: its first weight is 0) becomes -1 with the weights
+    // moved down, so that every base lies in [-1, 1] as the kernel assumes
+    double rb[3], rw[3][2];
+    for (int a = 0; a < 3; ++a) {
+      rb[a] = -base[a] - 1.0;
+      rw[a][0] = w[a][1];
+      rw[a][1] = w[a][0];
+      if (rb[a] < -1.0) {
+        rb[a] += 1.0;
+        rw[a][0] = rw[a][1];
+        rw[a][1] = 0.0;
+      }
+    }
+    DirTaps3 r{(int32_t)rb[0], (int32_t)rb[1], (int32_t)rb[2], 0, {}};
+    for (int b = 0; b < 8; ++b) r.w[b] = (float)(rw[0][b & 1] * rw[1][(b >> 1) & 1] * rw[2][b >> 2]);
+    taps3_rev[d] = r;
   }
   put(c->L.taps3, taps3.data(), taps3.size() * sizeof(DirTaps3));
+  put(c->L.taps3_rev, taps3_rev.data(), taps3_rev.size() * sizeof(DirTaps3));
   if (p->plane == RT_PLANE_3D) {
     c->three_d = true;
     c->s3 = Stream3Args{c->geo.C, hp.nx, hp.ny_lattice, hp.nz, hp.n, hp.Rpad, p->bc[0] == RT_BC_PERIODIC,
                         p->bc[2] == RT_BC_PERIODIC, p->bc_z[0] == RT_BC_PERIODIC,
                         c->at<DirTaps3>(c->L.taps3), c->at<float>(c->L.ghost)};
+    c->s3rev = c->s3;
+    c->s3rev.taps = c->at<DirTaps3>(c->L.taps3_rev);
+    c->s3rev.ghost = c->at<float>(c->L.ghost_zero);
   }
   std::vector<int32_t> od(4 * hp.n, 0);
   for (int e = 0; e < 4; ++e) {
@@ -712,7 +741,6 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
   if (c->mixture) return c->fail(RT_EUNSUPPORTED, "the adjoint of a phase mixture is not supported");
-  if (c->three_d) return c->fail(RT_EUNSUPPORTED, "the adjoint runs on 2-D lattices");
   if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "the adjoint of dichroic absorption is not supported");
   if (c->geo.Rpad > 512)
     return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");
@@ -728,7 +756,31 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   const float *lam_next = d_lambdaT;
   int flip = 0;
   const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-  for (int k = nseg - 1; k >= 0 && st == RT_OK; --k) {
+  // 3-D lattice: the segments hold the states S_{t0+1} .. S_{t1-1}; each step
+  // reverse-pulls lambda with the transposed trilinear taps into the
+  // workspace, then runs the adjoint collision on it (identity 2-D taps) with
+  // X read from the stored state
+  for (int k = nseg - 1; c->three_d && k >= 0 && st == RT_OK; --k) {
+    const int t0 = k * ckpt_every;
+    const int t1 = std::min(nsteps, t0 + ckpt_every);
+    if (t1 - t0 >= 2) {
+      st = step3d(c, ck(k), seg(0));
+      for (int t = t0 + 2; t <= t1 - 1 && st == RT_OK; ++t) st = step3d(c, seg(t - 2 - t0), seg(t - 1 - t0));
+    }
+    float *mu = c->at<float>(c->L.Ya);
+    for (int t = t1 - 1; t >= t0 && st == RT_OK; --t) {
+      st = c->hip(launch_stream3d(c->s3rev, lam_next, mu, c->stream), "reverse stream3d");
+      if (st != RT_OK) break;
+      StepArgs a = c->args(true);
+      a.in = t > t0 ? seg(t - 1 - t0) : ck(k);
+      a.lam_next = mu;
+      a.out = Lb[flip];
+      st = c->hip(launch_adjoint_mfma(a, c->prec, false, c->stream, c->cu_count), "adjoint");
+      lam_next = Lb[flip];
+      flip ^= 1;
+    }
+  }
+  for (int k = nseg - 1; !c->three_d && k >= 0 && st == RT_OK; --k) {
     const int t0 = k * ckpt_every;
     const int t1 = std::min(nsteps, t0 + ckpt_every);
     // recompute Y_{t0} .. Y_{t1-2}

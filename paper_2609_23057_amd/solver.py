@@ -188,7 +188,7 @@ class Solver:
 
     def adjoint(self, nsteps, ckpt, ckpt_every, lamT, seg=None, want_lambda0=False):
         seg = self.segment_buffer(ckpt_every) if seg is None else seg
-        g = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        g = torch.empty((3,) + self.cells, dtype=torch.float32, device=self.device)
         lam0 = torch.empty(self.shape, dtype=torch.float32, device=self.device) if want_lambda0 else None
         A.rt_adjoint(self.ctx, int(nsteps), _ptr(ckpt), int(ckpt_every), _ptr(seg), _ptr(lamT),
                      _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(lam0))

@@ -2,15 +2,16 @@
 3-D oracle, through the C ABI: streaming alone for every kind of face, the
 forward step in every precision and on the plain path, checkpoints, the
 per-cell phase mixture and dichroic absorption on a 3-D lattice, direction
-maps and totals, the full 256 x 256 x 64 workload on sampled cells through
-their one-step dependence window, and the refusals (edge readouts, adjoint,
-batch)."""
+maps and totals, the adjoint (reverse trilinear pull + adjoint collision)
+against the 3-D oracle adjoint, the full 256 x 256 x 64 workload on sampled
+cells through their one-step dependence window, and the refusals (edge
+readouts, batch)."""
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
-from gpu_common import TOL, assert_close, to_dev, to_np, tolerance
+from gpu_common import GTOL, TOL, assert_close, to_dev, to_np, tolerance
 from oracle import lbm as OL
 from oracle import lbm3d as O3
 
@@ -209,11 +210,36 @@ def test_3d_refusals():
     with pytest.raises(P.RTError) as ei:
         solver.readout(S, 3)
     assert ei.value.status == P.RT_EUNSUPPORTED
-    ck = solver.checkpoint_buffer(4, 2)
-    solver.run(S, 4, ck, 2)
     with pytest.raises(P.RTError) as ei:
-        solver.adjoint(4, ck, 2, solver.empty_state())
+        solver.readout_adjoint(3, torch.zeros((6, solver.nout[3], 4), device=solver.device))
     assert ei.value.status == P.RT_EUNSUPPORTED
     prob = P.make_problem(**dict(spec, precision="bf16"))
     with pytest.raises(P.RTError):
         P.Batch([prob])
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16x3", "bf16"])
+@pytest.mark.parametrize("case", [(dict(nx=9, ny=7, nz=5), 11, 4), (dict(nx=16, ny=9, nz=7), 9, 3),
+                                  (dict(nx=6, ny=5, nz=4, n_zen=2, n_az=8, bc6=(0, 0, 1, 1, 0, 0)), 8, 8),
+                                  (dict(nx=5, ny=4, nz=3, n_zen=8, n_az=16), 6, 1)],
+                         ids=lambda c: "%dx%dx%d-T%d-K%d" % (c[0]["nx"], c[0]["ny"], c[0]["nz"], c[1], c[2]))
+def test_adjoint3d_parity(case, precision):
+    over, T, K = case
+    spec = W.spec("beam3d", source="uniform_emis", emis_max=0.05, **over)
+    med = W.medium(spec)
+    med["tau"] = np.minimum(med["tau"] * 20.0, 1.0).astype(np.float32).astype(np.float64)
+    solver, p3, _ = build3(spec, precision, med)
+    rng = np.random.default_rng(5)
+    S0 = np.abs(rng.standard_normal(solver.shape)) * 0.1
+    lamT = rng.standard_normal(solver.shape)
+    ck = solver.checkpoint_buffer(T, K)
+    S = to_dev(S0, solver)
+    solver.run(S, T, ck, K)
+    ref = O3.adjoint(S0, p3, T, lamT)
+    got = solver.adjoint(T, ck, K, to_dev(lamT, solver), want_lambda0=True)
+    for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
+        assert _rel(to_np(arr), ref[key]) < GTOL[precision], (key, _rel(to_np(arr), ref[key]))

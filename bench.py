@@ -220,8 +220,9 @@ def extension_extras(T=20, warm=3):
 
 def three_d_extras(T=10, warm=2, reps=20):
     """The 3-D lattice (beam3d: 256 x 256 x 64, n = 32): forward steps per
-    contraction precision (per-cell collision, then the trilinear pull), and
-    the 3-D streaming kernel alone (HIP events around `reps` launches on the
+    contraction precision (per-cell collision, then the trilinear pull), the
+    checkpointed forward and its adjoint (recompute, reverse pull, adjoint
+    collision), and the 3-D streaming kernel alone (HIP events around `reps` launches on the
     solver's stream) against the HBM peak at 32 algorithmic bytes per
     cell-direction."""
     import torch
@@ -242,6 +243,24 @@ def three_d_extras(T=10, warm=2, reps=20):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         res[prec] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+        # forward with sqrt(T) checkpoints, then the checkpointed adjoint of a
+        # whole-state lambda_T (reverse trilinear pull + adjoint collision)
+        K = max(1, int(math.ceil(math.sqrt(T))))
+        ck = solver.checkpoint_buffer(T, K)
+        seg = solver.segment_buffer(K)
+        lam = torch.rand_like(S)
+        S0 = S.clone()
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        solver.run(S0, T, ck, K)
+        e2.record()
+        solver.adjoint(T, ck, K, lam, seg)
+        e3.record()
+        torch.cuda.synchronize()
+        res[prec]["checkpointed_forward_ms_per_step"] = e0.elapsed_time(e2) / T
+        res[prec]["adjoint_ms_per_step"] = e2.elapsed_time(e3) / T
+        res[prec]["adjoint_fwd_ratio"] = e2.elapsed_time(e3) / e0.elapsed_time(e2)
+        del ck, seg, lam, S0
         if prec == "fp32":
             b = torch.empty_like(S)
             solver.stream_field(S, b)

@@ -80,10 +80,10 @@ typedef enum { RT_ZEN_EQUAL_AREA = 0, RT_ZEN_UNIFORM_THETA = 1, RT_ZEN_EXPLICIT 
  *                     Faces x-, x+, y-, y+ take bc[0..3], z-, z+ take bc_z[0..1];
  *                     a ghost outside in z takes its z face, else its y face,
  *                     else its x face.  rt_step, rt_run (with checkpoints),
- *                     rt_stream, rt_maps, the totals of rt_readout,
- *                     rt_set_phase_mixture, rt_set_dichroism, and rt_adjoint
- *                     (lambda_T given as a whole state); edge readouts and
- *                     the batch return RT_EUNSUPPORTED. */
+ *                     rt_stream, rt_maps, rt_readout / rt_readout_adjoint /
+ *                     rt_num_outgoing per face (edge = face 0..5),
+ *                     rt_set_phase_mixture, rt_set_dichroism and rt_adjoint;
+ *                     the batch returns RT_EUNSUPPORTED. */
 typedef enum { RT_PLANE_XY = 0, RT_PLANE_XZ = 1, RT_PLANE_XY_D2Q9 = 2, RT_PLANE_3D = 3 } rt_plane;
 
 /* Edges are numbered 0 = x-, 1 = x+, 2 = y-, 3 = y+.  Periodic is the
@@ -168,7 +168,8 @@ size_t rt_state_bytes(const rt_problem *p);
  *           built from the dipole field projection in the meridian frames. */
 rt_status rt_describe(const rt_problem *p, double *h_dirs, double *h_M);
 
-/* Number of directions leaving through `edge` (the readout width). */
+/* Number of directions leaving through `edge` (the readout width; on an
+ * RT_PLANE_3D lattice `edge` is a face 0..5 and z faces count l_z). */
 int32_t rt_num_outgoing(const rt_problem *p, int32_t edge);
 
 /* ---- context ------------------------------------------------------------- */
@@ -249,7 +250,10 @@ rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t c
  * d_out[e][k][4], e along the edge (x for edges 2,3; y for edges 0,1), k over
  * the directions leaving through the edge in increasing d.  If h_sums is not
  * NULL it receives the float64 sums of I, Q, U, V over the whole field
- * (synchronises). */
+ * (synchronises). On an
+ * RT_PLANE_3D lattice `edge` is a face 0..5 (x-, x+, y-, y+, z-, z+) and
+ * d_out[e][k][4] runs over the face's cells e = a + na b: x faces (y, z),
+ * y faces (x, z), z faces (x, y), the first index fastest. */
 rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, double *h_sums);
 
 /* Direction-mean intensity and direction-mean degree of polarisation

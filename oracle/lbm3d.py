@@ -203,3 +203,44 @@ def adjoint(S0, prob, nsteps, lam_T):
             "g_tau": g_al * dal_dt.reshape(shp) + g_be * dbe_dt.reshape(shp),
             "g_albedo": g_al * dal_dw.reshape(shp) + g_be * dbe_dw.reshape(shp),
             "g_emis": g_em.reshape(shp)}
+
+
+def face_cells(prob, face):
+    """Cell indices (z, y, x) of a face in readout order: x faces (y, z),
+    y faces (x, z), z faces (x, y), the first index fastest."""
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    if face in (FACE_XM, FACE_XP):
+        x = 0 if face == FACE_XM else nx - 1
+        return [(z, y, x) for z in range(nz) for y in range(ny)]
+    if face in (FACE_YM, FACE_YP):
+        y = 0 if face == FACE_YM else ny - 1
+        return [(z, y, x) for z in range(nz) for x in range(nx)]
+    z = 0 if face == FACE_ZM else nz - 1
+    return [(z, y, x) for y in range(ny) for x in range(nx)]
+
+
+def outgoing(prob, face):
+    """Directions whose displacement leaves through the face, increasing d."""
+    axis, sign = face // 2, (-1 if face % 2 == 0 else 1)
+    return [d for d in range(prob.n) if sign * prob.shifts[d, axis] > 0]
+
+
+def readout(S, prob, face):
+    """Stokes vectors of the outgoing directions on a face: [cell][k][4]."""
+    S = np.asarray(S, dtype=np.float64).reshape(prob.shape)
+    cells, dirs = face_cells(prob, face), outgoing(prob, face)
+    out = np.zeros((len(cells), len(dirs), 4))
+    for e, (z, y, x) in enumerate(cells):
+        for k, d in enumerate(dirs):
+            out[e, k] = S[d, :, z, y, x]
+    return out
+
+
+def readout_transpose(G, prob, face):
+    """A state that is zero except the face entries, which receive G."""
+    lam = np.zeros(prob.shape)
+    cells, dirs = face_cells(prob, face), outgoing(prob, face)
+    for e, (z, y, x) in enumerate(cells):
+        for k, d in enumerate(dirs):
+            lam[d, :, z, y, x] = G[e, k]
+    return lam

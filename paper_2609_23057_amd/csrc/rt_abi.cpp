@@ -91,7 +91,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   L.taps3 = take(hp.n * sizeof(DirTaps3));
   L.taps3_rev = take(hp.n * sizeof(DirTaps3));
   L.ghost_zero = take(7 * hp.Rpad * sizeof(float));   // zeros: the reverse 3-D pull's ghosts
-  L.outdirs = take(4 * hp.n * sizeof(int32_t));
+  L.outdirs = take(6 * hp.n * sizeof(int32_t));   // per edge (2-D) or face (3-D)
   L.MT = take((size_t)hp.R * hp.R * sizeof(float));
   L.tiles_fwd32 = take(ntile * sizeof(TileRange));
   L.tiles_adj32 = take(ntile * sizeof(TileRange));
@@ -155,7 +155,7 @@ struct rt_ctx {
   std::vector<uint8_t> host_tables;
   std::vector<float> host_medium;  // jrow + ghost staging
   std::vector<float> host_dich_w;  // sin^2 theta per direction (staging)
-  int nout[4] = {0, 0, 0, 0};
+  int nout[6] = {0, 0, 0, 0, 0, 0};
   bool medium_set = false;
   bool mixture = false;   // rt_set_phase_mixture succeeded
   bool dichroic = false;  // rt_set_dichroism succeeded
@@ -301,7 +301,8 @@ rt_status rt_describe(const rt_problem *p, double *h_dirs, double *h_M) {
 int32_t rt_num_outgoing(const rt_problem *p, int32_t edge) {
   HostPlan hp;
   std::string msg;
-  if (edge < 0 || edge > 3 || build_plan(p, &hp, &msg) != RT_OK) return -1;
+  const int nedge = (p && p->plane == RT_PLANE_3D) ? 6 : 4;
+  if (edge < 0 || edge >= nedge || build_plan(p, &hp, &msg) != RT_OK) return -1;
   int k = 0;
   for (int d = 0; d < hp.n; ++d) k += (hp.outmask[d] >> edge) & 1;
   return k;
@@ -423,8 +424,8 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     c->s3rev.taps = c->at<DirTaps3>(c->L.taps3_rev);
     c->s3rev.ghost = c->at<float>(c->L.ghost_zero);
   }
-  std::vector<int32_t> od(4 * hp.n, 0);
-  for (int e = 0; e < 4; ++e) {
+  std::vector<int32_t> od(6 * hp.n, 0);
+  for (int e = 0; e < (is3d ? 6 : 4); ++e) {
     int k = 0;
     for (int d = 0; d < hp.n; ++d)
       if ((hp.outmask[d] >> e) & 1) od[e * hp.n + k++] = d;
@@ -693,15 +694,32 @@ rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t c
   return st;
 }
 
+// Cells of face e of a 3-D lattice in readout order: x faces (y, z), y faces
+// (x, z), z faces (x, y), the first index fastest.
+static FaceMap face_map(const rt_ctx *c, int e) {
+  const int64_t nx = c->s3.nx, ny = c->s3.ny, nz = c->s3.nz, layer = nx * ny;
+  switch (e) {
+    case 0: return FaceMap{0, nx, layer, (int32_t)ny, (int32_t)(ny * nz)};
+    case 1: return FaceMap{nx - 1, nx, layer, (int32_t)ny, (int32_t)(ny * nz)};
+    case 2: return FaceMap{0, 1, layer, (int32_t)nx, (int32_t)(nx * nz)};
+    case 3: return FaceMap{(ny - 1) * nx, 1, layer, (int32_t)nx, (int32_t)(nx * nz)};
+    case 4: return FaceMap{0, 1, nx, (int32_t)nx, (int32_t)(nx * ny)};
+    default: return FaceMap{(nz - 1) * layer, 1, nx, (int32_t)nx, (int32_t)(nx * ny)};
+  }
+}
+
 rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, double *h_sums) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_S) return c->fail(RT_EINVAL, "NULL state pointer");
-  if (edge < 0 || edge > 3) return c->fail(RT_EINVAL, "edge must be 0..3");
-  if (d_out && c->three_d) return c->fail(RT_EUNSUPPORTED, "edge readouts are 2-D only (totals are available)");
+  const int nedge = c->three_d ? 6 : 4;
+  if (edge < 0 || edge >= nedge) return c->fail(RT_EINVAL, c->three_d ? "face must be 0..5" : "edge must be 0..3");
   rt_status st = RT_OK;
-  if (d_out)
-    st = c->hip(launch_readout(c->geo, d_S, edge, c->at<int32_t>(c->L.outdirs) + edge * c->geo.n,
-                               c->nout[edge], d_out, c->stream), "readout");
+  const int32_t *dirs = c->at<int32_t>(c->L.outdirs) + edge * c->geo.n;
+  if (d_out && c->three_d)
+    st = c->hip(launch_readout_face(c->geo.C, face_map(c, edge), d_S, dirs, c->nout[edge], d_out, c->stream),
+                "readout");
+  else if (d_out)
+    st = c->hip(launch_readout(c->geo, d_S, edge, dirs, c->nout[edge], d_out, c->stream), "readout");
   if (st == RT_OK && h_sums) {
     double *res = c->at<double>(c->L.sums);
     st = c->hip(launch_sums(c->geo, d_S, c->at<double>(c->L.partial), c->L.npart, res, c->stream), "sums");
@@ -723,12 +741,16 @@ rt_status rt_maps(rt_ctx *c, const float *d_S, float *d_I_mean, float *d_dop_mea
 rt_status rt_readout_adjoint(rt_ctx *c, int32_t edge, const float *d_gout, float *d_lambdaT) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_gout || !d_lambdaT) return c->fail(RT_EINVAL, "NULL pointer");
-  if (edge < 0 || edge > 3) return c->fail(RT_EINVAL, "edge must be 0..3");
-  if (c->three_d) return c->fail(RT_EUNSUPPORTED, "edge readouts are 2-D only");
+  const int nedge = c->three_d ? 6 : 4;
+  if (edge < 0 || edge >= nedge) return c->fail(RT_EINVAL, c->three_d ? "face must be 0..5" : "edge must be 0..3");
+  const int32_t *dirs = c->at<int32_t>(c->L.outdirs) + edge * c->geo.n;
   rt_status st = c->hip(launch_fill_f32(d_lambdaT, (int64_t)state_elems(c), 0.0f, c->stream), "fill");
-  if (st == RT_OK)
-    st = c->hip(launch_readout_adjoint(c->geo, edge, c->at<int32_t>(c->L.outdirs) + edge * c->geo.n,
-                                       c->nout[edge], d_gout, d_lambdaT, c->stream), "readout adjoint");
+  if (st == RT_OK && c->three_d)
+    st = c->hip(launch_readout_face_adjoint(c->geo.C, face_map(c, edge), dirs, c->nout[edge], d_gout, d_lambdaT,
+                                            c->stream), "readout adjoint");
+  else if (st == RT_OK)
+    st = c->hip(launch_readout_adjoint(c->geo, edge, dirs, c->nout[edge], d_gout, d_lambdaT, c->stream),
+                "readout adjoint");
   return st;
 }
 

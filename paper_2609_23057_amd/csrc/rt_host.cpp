@@ -294,6 +294,8 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
       if (hp->lx[d] > 0) m |= 2;
       if (hp->ly[d] < 0) m |= 4;
       if (hp->ly[d] > 0) m |= 8;
+      if (hp->lz[d] < 0) m |= 16;   // 3-D: leaves through z- / z+
+      if (hp->lz[d] > 0) m |= 32;
       hp->outmask[d] = m;
     }
   }

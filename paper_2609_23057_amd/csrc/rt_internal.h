@@ -23,7 +23,7 @@ struct HostPlan {
   std::vector<double> theta, phi, domega;   // [n]
   std::vector<double> kvec, eth, eph;       // [n][3]
   std::vector<double> lx, ly, lz;           // [n] displacement per step (lz: 3-D only)
-  std::vector<int> outmask;                 // [n] bit e: leaves through edge e
+  std::vector<int> outmask;                 // [n] bit e: leaves through edge (3-D: face) e
   // Collision matrix in ABI order: row 4*d_out + s_out, column 4*d_in + s_in.
   std::vector<double> M;                    // [R][R]
 };

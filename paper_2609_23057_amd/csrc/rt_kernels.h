@@ -119,7 +119,18 @@ struct Stream3Args {
 };
 hipError_t launch_stream3d(const Stream3Args &a, const float *in, float *out, hipStream_t s);
 
-// Plain float32 path: separate streaming and vector-ALU collision.
+// Cells of one face of a 3-D lattice: face cell e = a + na b (a < na) lies at
+// base + a sa + b sb; count cells in all.
+struct FaceMap {
+  int64_t base, sa, sb;
+  int32_t na, count;
+};
+hipError_t launch_readout_face(int64_t C, const FaceMap &f, const float *S, const int32_t *dirs, int nout,
+                               float *out, hipStream_t s);
+hipError_t launch_readout_face_adjoint(int64_t C, const FaceMap &f, const int32_t *dirs, int nout,
+                                       const float *gout, float *lam, hipStream_t s);
+
+// Plain float32 path: separate streaming and vector-ALU collision.// Plain float32 path: separate streaming and vector-ALU collision.
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s);
 hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,
                                hipStream_t s);

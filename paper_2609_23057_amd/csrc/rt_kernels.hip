@@ -1599,6 +1599,34 @@ __global__ void readout_adjoint_kernel(Geometry g, int edge, const int32_t *__re
   }
 }
 
+// Face readouts of a 3-D lattice: face cell e = a + na b lies at
+// base + a sa + b sb (FaceMap), out[e][k][s] = S[4 dirs[k] + s](cell).
+__global__ void readout_face_kernel(int64_t C, FaceMap f, const float *__restrict__ S,
+                                    const int32_t *__restrict__ dirs, int nout, float *out) {
+  const int64_t total = (int64_t)f.count * nout * 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(i & 3);
+    const int k = (int)((i >> 2) % nout);
+    const int e = (int)((i >> 2) / nout);
+    const int64_t cell = f.base + (int64_t)(e % f.na) * f.sa + (int64_t)(e / f.na) * f.sb;
+    out[i] = S[(int64_t)(4 * dirs[k] + s) * C + cell];
+  }
+}
+
+__global__ void readout_face_adjoint_kernel(int64_t C, FaceMap f, const int32_t *__restrict__ dirs, int nout,
+                                            const float *__restrict__ gout, float *lam) {
+  const int64_t total = (int64_t)f.count * nout * 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(i & 3);
+    const int k = (int)((i >> 2) % nout);
+    const int e = (int)((i >> 2) / nout);
+    const int64_t cell = f.base + (int64_t)(e % f.na) * f.sa + (int64_t)(e / f.na) * f.sb;
+    lam[(int64_t)(4 * dirs[k] + s) * C + cell] = gout[i];
+  }
+}
+
 constexpr int kSumThreads = 256;
 
 // Partial float64 sums of the I, Q, U, V planes: block b covers a fixed range
@@ -1788,6 +1816,23 @@ hipError_t launch_readout_adjoint(const Geometry &g, int edge, const int32_t *di
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(readout_adjoint_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g, edge, dirs,
                      nout, ne, gout, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout_face(int64_t C, const FaceMap &f, const float *S, const int32_t *dirs, int nout,
+                               float *out, hipStream_t s) {
+  const int64_t total = (int64_t)f.count * nout * 4;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(readout_face_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, C, f, S, dirs, nout, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout_face_adjoint(int64_t C, const FaceMap &f, const int32_t *dirs, int nout,
+                                       const float *gout, float *lam, hipStream_t s) {
+  const int64_t total = (int64_t)f.count * nout * 4;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(readout_face_adjoint_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, C, f, dirs, nout,
+                     gout, lam);
   return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ class Solver:
             self._owned = True
         else:
             self.ctx, self._owner, self._owned = _ctx, _owner, False
-        self.nout = [A.rt_num_outgoing(problem, e) for e in range(4)]
+        self.nout = [A.rt_num_outgoing(problem, e) for e in range(6 if len(self.cells) == 3 else 4)]
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -155,9 +155,14 @@ class Solver:
     def run(self, S, nsteps, ckpt=None, ckpt_every=0):
         A.rt_run(self.ctx, _ptr(S), int(nsteps), _ptr(ckpt), int(ckpt_every))
 
+    def edge_cells(self, edge):
+        """Cells of an edge (2-D) or face (3-D: x faces ny nz, y faces nx nz, z faces nx ny)."""
+        if len(self.cells) == 3:
+            return (self.ny * self.nz, self.nx * self.nz, self.nx * self.ny)[edge // 2]
+        return self.ny if edge < 2 else self.nx
+
     def readout(self, S, edge, sums=False):
-        out = torch.empty((self.ny if edge < 2 else self.nx, self.nout[edge], 4),
-                          dtype=torch.float32, device=self.device)
+        out = torch.empty((self.edge_cells(edge), self.nout[edge], 4), dtype=torch.float32, device=self.device)
         h = np.zeros(4) if sums else None
         A.rt_readout(self.ctx, _ptr(S), int(edge), _ptr(out) if out.numel() else None, h)
         return (out, h) if sums else out

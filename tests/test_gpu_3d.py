@@ -4,8 +4,8 @@ forward step in every precision and on the plain path, checkpoints, the
 per-cell phase mixture and dichroic absorption on a 3-D lattice, direction
 maps and totals, the adjoint (reverse trilinear pull + adjoint collision)
 against the 3-D oracle adjoint, the full 256 x 256 x 64 workload on sampled
-cells through their one-step dependence window, and the refusals (edge
-readouts, batch)."""
+cells through their one-step dependence window, face readouts and their
+transpose, and the refusals (face index, batch)."""
 import numpy as np
 import pytest
 import torch
@@ -208,11 +208,8 @@ def test_3d_refusals():
     solver, _, _ = build3(spec, "fp32")
     S = solver.empty_state()
     with pytest.raises(P.RTError) as ei:
-        solver.readout(S, 3)
-    assert ei.value.status == P.RT_EUNSUPPORTED
-    with pytest.raises(P.RTError) as ei:
-        solver.readout_adjoint(3, torch.zeros((6, solver.nout[3], 4), device=solver.device))
-    assert ei.value.status == P.RT_EUNSUPPORTED
+        P._abi.rt_readout(solver.ctx, S.data_ptr(), 6, None, None)
+    assert ei.value.status == P.RT_EINVAL
     prob = P.make_problem(**dict(spec, precision="bf16"))
     with pytest.raises(P.RTError):
         P.Batch([prob])
@@ -243,3 +240,44 @@ def test_adjoint3d_parity(case, precision):
     got = solver.adjoint(T, ck, K, to_dev(lamT, solver), want_lambda0=True)
     for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
         assert _rel(to_np(arr), ref[key]) < GTOL[precision], (key, _rel(to_np(arr), ref[key]))
+
+
+@pytest.mark.parametrize("dims", [(9, 7, 5), (16, 9, 7), (3, 2, 4)])
+def test_face_readouts_and_transpose(dims):
+    spec = spec3(*dims, bc6=(1, 1, 0, 0, 1, 2))
+    solver, p3, _ = build3(spec, "fp32")
+    rng = np.random.default_rng(6)
+    S0 = rng.standard_normal(solver.shape)
+    S = to_dev(S0, solver)
+    for face in range(6):
+        out = solver.readout(S, face)
+        ref = O3.readout(S0, p3, face)
+        assert out.shape == ref.shape, (face, out.shape, ref.shape)
+        assert np.array_equal(to_np(out), ref.astype(np.float32).astype(np.float64)), face
+        g = rng.standard_normal(ref.shape)
+        lam = solver.readout_adjoint(face, to_dev(g, solver))
+        assert np.array_equal(to_np(lam), O3.readout_transpose(g.astype(np.float32).astype(np.float64), p3, face))
+
+
+def test_top_face_loss_gradient_end_to_end():
+    """Forward, top-face readout, its transpose and the adjoint on a 3-D
+    lattice against the oracle chain."""
+    spec = W.spec("beam3d", nx=8, ny=6, nz=5, source="uniform_emis", emis_max=0.05)
+    med = W.medium(spec)
+    med["tau"] = np.minimum(med["tau"] * 20.0, 1.0).astype(np.float32).astype(np.float64)
+    solver, p3, _ = build3(spec, "fp32", med)
+    T, K = 8, 3
+    S = solver.empty_state()
+    ck = solver.checkpoint_buffer(T, K)
+    solver.run(S, T, ck, K)
+    out = solver.readout(S, 5)
+    ST = O3.run(np.zeros(p3.shape), p3, T)
+    assert_close(to_np(S), ST, 1e-5, "S_T")
+    g = np.ones(O3.readout(ST, p3, 5).shape)
+    lamT = O3.readout_transpose(g, p3, 5)
+    ref = O3.adjoint(np.zeros(p3.shape), p3, T, lamT)
+    gl = solver.readout_adjoint(5, to_dev(g, solver))
+    got = solver.adjoint(T, ck, K, gl)
+    for key, arr in zip(("g_tau", "g_albedo", "g_emis"), got):
+        assert _rel(to_np(arr), ref[key]) < 1e-4, key
+    assert out.shape[0] == 8 * 6

@@ -281,3 +281,52 @@ def test_top_face_loss_gradient_end_to_end():
     for key, arr in zip(("g_tau", "g_albedo", "g_emis"), got):
         assert _rel(to_np(arr), ref[key]) < 1e-4, key
     assert out.shape[0] == 8 * 6
+
+
+def test_rtsolve_autograd_on_a_3d_lattice():
+    """RTSolve (forward with checkpoints, face readout, its transpose and the
+    adjoint as a torch.autograd.Function) on a 3-D lattice: the gradient of
+    the summed top-face radiance equals the oracle's."""
+    import paper_2609_23057_amd as P
+    spec = W.spec("beam3d", nx=8, ny=5, nz=6, source="uniform_emis", emis_max=0.05)
+    med = W.medium(spec)
+    med["tau"] = np.minimum(med["tau"] * 20.0, 1.0).astype(np.float32).astype(np.float64)
+    solver, p3, _ = build3(spec, "fp32", med)
+    tau, alb, em = (to_dev(med[k], solver).requires_grad_(True) for k in ("tau", "albedo", "emis"))
+    out = P.RTSolve.apply(tau, alb, em, solver, solver.empty_state(), 7, 5, med["jprof"], med["inflow"])
+    out.sum().backward()
+    ST = O3.run(np.zeros(p3.shape), p3, 7)
+    lamT = O3.readout_transpose(np.ones(O3.readout(ST, p3, 5).shape), p3, 5)
+    ref = O3.adjoint(np.zeros(p3.shape), p3, 7, lamT)
+    assert _rel(to_np(tau.grad), ref["g_tau"]) < 1e-4
+    assert _rel(to_np(alb.grad), ref["g_albedo"]) < 1e-4
+    assert _rel(to_np(em.grad), ref["g_emis"]) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_extensions_combined(precision):
+    """A tabulated matrix with a Rayleigh mixture (2-D), a tabulated matrix
+    with dichroic absorption (2-D), and a tabulated matrix on a 3-D lattice."""
+    table = {"kind": "table", "table": W.scattering_table()}
+    spec = W.spec("beam512", nx=30, ny=26, phase=table, mixture={"kind": "rayleigh"})
+    import gpu_common as GC
+    solver, oprob, med = GC.build(spec, precision)
+    solver.set_phase_mixture(spec["mixture"], to_dev(med["frac"], solver))
+    S0 = W.initial_state(spec, "random")
+    S = to_dev(S0, solver)
+    solver.run(S, 15)
+    assert_close(to_np(S), OL.run(S0, oprob, 15), tolerance(precision, oprob), "table + mixture")
+    spec = W.spec("beam512", nx=30, ny=26, phase=table, dichroism=0.8)
+    med = W.medium(spec)
+    med["tau"] = np.minimum(med["tau"] * 4.0, 1.0).astype(np.float32).astype(np.float64)
+    solver, oprob, med = GC.build(spec, precision, med)
+    solver.set_dichroism(to_dev(med["eta"], solver))
+    S = to_dev(S0, solver)
+    solver.run(S, 15)
+    assert_close(to_np(S), OL.run(S0, oprob, 15), tolerance(precision, oprob), "table + dichroism")
+    spec = spec3(9, 7, 5, phase=table)
+    solver, p3, _ = build3(spec, precision)
+    S0 = W.initial_state(spec, "random")
+    S = to_dev(S0, solver)
+    solver.run(S, 8)
+    assert_close(to_np(S), O3.run(S0, p3, 8), tolerance(precision, p3.flat), "table 3-d")

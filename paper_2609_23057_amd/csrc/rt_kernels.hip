@@ -1360,68 +1360,90 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
 //
 // Columns x in [4, nx - 5] (nx a multiple of 4: "quad columns") have every
 // x tap inside the lattice.  There a thread produces 4 consecutive cells of
-// 2 rows of 2 layers of one plane from the 3 x 3 source rows they share, each
-// read as two aligned 16-byte loads, or, for a row outside the lattice in y
-// or z, taken as its face's ghost value (uniform along the row).  The 8 end
-// columns of every row take one thread per cell with the general tap rules.
+// 2 rows of one plane over kZRun layers, sliding along z so that each layer
+// step loads one new source layer of 3 rows (two aligned 16-byte loads per
+// row, or, for a row outside the lattice in y or z, its face's ghost value,
+// uniform along the row).  The 8 end columns of every row take one thread
+// per cell with the general tap rules.
+constexpr int kZRun = 8;   // layers per quad-column thread
+
 struct Box3 {
   int on;          // quad columns exist (nx a multiple of 4, nx >= 12, aligned fields)
   int nqx;         // quads per row
-  int nyp, nq;     // row pairs per layer; 2 x 2 blocks of quads per plane
+  int nyp, nq;     // row pairs per layer; quad-column threads per plane (kZRun layers each)
   int nbord;       // cells of the end columns (all cells when `on` is 0)
   int ib;          // blocks per plane taking quads
   int bpp;         // blocks per plane
 };
 
+// Loads one source layer zs (3 rows y - oy0 + {-1, 0, 1}) of a quad column:
+// each row as the 8 aligned floats that start SH + 1 floats before the first
+// cell's bx = 0 tap, or the ghost value of its face for a row outside the
+// lattice in y or z.
 template <int SH>
-__device__ __forceinline__ void quad3_block(const Stream3Args &g, const DirTaps3 &tp, const float *__restrict__ in,
-                                            int64_t plane, int p, int x0, int y, int z, float *__restrict__ out) {
+__device__ __forceinline__ void quad3_layer(const Stream3Args &g, const DirTaps3 &tp, const float *__restrict__ in,
+                                            int64_t plane, int p, int x0, int y, int zs, float (&e)[3][8]) {
   const int64_t layer = (int64_t)g.ny * g.nx;
-  float e[3][3][8];
+  const int zw = wrap_axis(zs, g.nz, g.per_z);
+  const bool inz = (unsigned)zw < (unsigned)g.nz;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int b = 0; b < 3; ++b) {
+    const int ys = wrap_axis(y - tp.oy0 + b - 1, g.ny, g.per_y);
+    const bool iny = (unsigned)ys < (unsigned)g.ny;
+    if (inz && iny) {
+      const float *r = in + plane + zw * layer + (int64_t)ys * g.nx + x0 - tp.ox0 - 1 - SH;
+      const f32x4 v0 = *reinterpret_cast<const f32x4 *>(r);
+      const f32x4 v1 = *reinterpret_cast<const f32x4 *>(r + 4);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int zs = wrap_axis(z - tp.oz0 + a - 1, g.nz, g.per_z);
-      const int ys = wrap_axis(y - tp.oy0 + b - 1, g.ny, g.per_y);
-      const bool inz = (unsigned)zs < (unsigned)g.nz, iny = (unsigned)ys < (unsigned)g.ny;
-      if (inz && iny) {
-        // from SH + 1 floats before the first cell's bx = 0 tap: 16-byte aligned
-        const float *r = in + plane + zs * layer + (int64_t)ys * g.nx + x0 - tp.ox0 - 1 - SH;
-        const f32x4 v0 = *reinterpret_cast<const f32x4 *>(r);
-        const f32x4 v1 = *reinterpret_cast<const f32x4 *>(r + 4);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          e[a][b][k] = v0[k];
-          e[a][b][k + 4] = v1[k];
-        }
-      } else {
-        const float gv = g.ghost[(!inz ? (zs < 0 ? 4 : 5) : (ys < 0 ? 2 : 3)) * g.Rpad + p];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) e[a][b][k] = gv;
+      for (int k = 0; k < 4; ++k) {
+        e[b][k] = v0[k];
+        e[b][k + 4] = v1[k];
       }
-    }
+    } else {
+      const float gv = g.ghost[(!inz ? (zw < 0 ? 4 : 5) : (ys < 0 ? 2 : 3)) * g.Rpad + p];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int k = 0; k < 8; ++k) e[b][k] = gv;
+    }
+  }
+}
+
+// A quad column of two rows (y, y + 1; the second while y + 1 < ny) over the
+// layers z0 .. z1 - 1, sliding along z: output layer z reads source layers
+// z - oz0 - 1 (bz = 1) and z - oz0 (bz = 0), so each step loads one new
+// source layer (3 rows) and keeps the previous one.
+template <int SH>
+__device__ __forceinline__ void quad3_column(const Stream3Args &g, const DirTaps3 &tp, const float *__restrict__ in,
+                                             int64_t plane, int p, int x0, int y, int z0, int z1,
+                                             float *__restrict__ out) {
+  const int64_t layer = (int64_t)g.ny * g.nx;
+  float hi[3][8], lo[3][8];   // source layers z - oz0 (bz = 0) and z - oz0 - 1 (bz = 1)
+  quad3_layer<SH>(g, tp, in, plane, p, x0, y, z0 - tp.oz0 - 1, lo);
+  for (int z = z0; z < z1; ++z) {
+    quad3_layer<SH>(g, tp, in, plane, p, x0, y, z - tp.oz0, hi);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      if (z + i >= g.nz || y + j >= g.ny) continue;
+      if (y + j >= g.ny) continue;
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
         for (int by = 0; by < 2; ++by) {
-          const float *ev = e[i - bz + 1][j - by + 1];
+          const float *ev = bz ? lo[j - by + 1] : hi[j - by + 1];
           const float w0 = tp.w[4 * bz + 2 * by], w1 = tp.w[4 * bz + 2 * by + 1];
 #pragma unroll
           for (int k = 0; k < 4; ++k) acc[k] = fmaf(w1, ev[SH + k], fmaf(w0, ev[SH + k + 1], acc[k]));
         }
-      *reinterpret_cast<f32x4 *>(out + plane + (z + i) * layer + (int64_t)(y + j) * g.nx + x0) =
+      *reinterpret_cast<f32x4 *>(out + plane + z * layer + (int64_t)(y + j) * g.nx + x0) =
           f32x4{acc[0], acc[1], acc[2], acc[3]};
     }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lo[b][k] = hi[b][k];
+  }
 }
 
-// box.bpp blocks per plane p = 4 d + s: the first box.ib take 2 x 2 blocks
+// box.bpp blocks per plane p = 4 d + s: the first box.ib take quad columns,
 // of quads, the rest one end-column cell per thread.  Blocks are dispatched
 // round-robin over the 8 XCDs; the logical order is remapped so that each XCD
 // takes a contiguous range, and the source rows that neighbouring blocks of a
@@ -1440,13 +1462,14 @@ __global__ void __launch_bounds__(256) stream3d_kernel(Stream3Args g, Box3 box, 
     const int qx = q % box.nqx;
     const int t = q / box.nqx;
     const int y = 2 * (t % box.nyp);
-    const int z = 2 * (t / box.nyp);
+    const int z0 = kZRun * (t / box.nyp);
+    const int z1 = min(z0 + kZRun, g.nz);
     const int x0 = 4 + 4 * qx;
     switch ((-tp.ox0 - 1) & 3) {
-      case 0: quad3_block<0>(g, tp, in, plane, p, x0, y, z, out); break;
-      case 1: quad3_block<1>(g, tp, in, plane, p, x0, y, z, out); break;
-      case 2: quad3_block<2>(g, tp, in, plane, p, x0, y, z, out); break;
-      default: quad3_block<3>(g, tp, in, plane, p, x0, y, z, out); break;
+      case 0: quad3_column<0>(g, tp, in, plane, p, x0, y, z0, z1, out); break;
+      case 1: quad3_column<1>(g, tp, in, plane, p, x0, y, z0, z1, out); break;
+      case 2: quad3_column<2>(g, tp, in, plane, p, x0, y, z0, z1, out); break;
+      default: quad3_column<3>(g, tp, in, plane, p, x0, y, z0, z1, out); break;
     }
     return;
   }
@@ -1754,7 +1777,7 @@ hipError_t launch_stream3d(const Stream3Args &a, const float *in, float *out, hi
     box.on = 1;
     box.nqx = a.nx / 4 - 2;
     box.nyp = (a.ny + 1) / 2;
-    box.nq = box.nqx * box.nyp * ((a.nz + 1) / 2);
+    box.nq = box.nqx * box.nyp * ((a.nz + kZRun - 1) / kZRun);
     box.nbord = 8 * a.ny * a.nz;
     box.ib = (box.nq + 255) / 256;
   }

@@ -221,9 +221,8 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
  * a device [ny][nx] float32 field with |eta| < 1, copied into the workspace;
  * NULL removes it.  Later rt_step / rt_run use it, and rt_set_medium keeps it
  * in step with a new medium.  Synchronises the stream (eta is checked).
- * Errors: RT_EUNSUPPORTED for precisions other than RT_FP32 (fused or
- * RT_PLAIN) and RT_BF16, with RT_ABS_TAYLOR or RT_FUSED_TAYLOR, or while a
- * phase mixture is set; RT_ERANGE if some |eta| >= 1 or eta is not finite
+ * Every precision and RT_PLAIN carry it.  Errors: RT_EUNSUPPORTED with
+ * RT_ABS_TAYLOR or RT_FUSED_TAYLOR, or while a phase mixture is set; RT_ERANGE if some |eta| >= 1 or eta is not finite
  * (dichroism is then off).  rt_adjoint, rt_batch_run and rt_batch_adjoint
  * return RT_EUNSUPPORTED while it is set; rt_set_phase_mixture likewise. */
 rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);

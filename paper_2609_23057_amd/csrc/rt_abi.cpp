@@ -116,7 +116,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
     L.mix_frag = take(frag);
     L.frac = take(mix ? C * sizeof(float) : 0);
     // dichroic absorption: per-cell eta and tau_abs * eta, per-direction sin^2 theta
-    const bool dich = prec == RT_FP32 || prec == RT_BF16;
+    const bool dich = true;   // every precision (and the plain path)
     L.dich_eta = take(dich ? C * sizeof(float) : 0);
     L.dich_xi = take(dich ? C * sizeof(float) : 0);
     L.dich_w = take(dich ? hp.n * sizeof(float) : 0);
@@ -575,8 +575,6 @@ rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta) {
     c->dichroic = false;
     return RT_OK;
   }
-  if (c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16)
-    return c->fail(RT_EUNSUPPORTED, "dichroic absorption runs on the fp32 (fused or plain) and bf16 paths only");
   if (c->prob.flags & (RT_ABS_TAYLOR | RT_FUSED_TAYLOR))
     return c->fail(RT_EUNSUPPORTED, "dichroic absorption is defined for Beer-Lambert absorption");
   if (c->mixture) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");

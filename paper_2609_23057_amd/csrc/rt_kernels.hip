@@ -436,7 +436,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   constexpr bool DICH = EXT == kExtDich;
   static_assert(!MIX || (!ADJ && NB == 1 && (PREC == P_F32 || PREC == P_BF16)),
                 "phase mixtures: forward float32 or bf16, one column block");
-  static_assert(!DICH || (!ADJ && (PREC == P_F32 || PREC == P_BF16)), "dichroic absorption: forward float32 or bf16");
+  static_assert(!DICH || !ADJ, "dichroic absorption: forward steps");
   // bf16 contraction with two column blocks: X lives as high + low tiles
   constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
   const int col = lane & 31;
@@ -1079,13 +1079,15 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count)
     return hipErrorInvalidValue;
   }
   if (a.dich_xi != nullptr) {
-    // dichroic absorption: forward fp32 / bf16, the tiles of the plain step
-    if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
+    // dichroic absorption: forward steps, the tiles of the plain step
+    if constexpr (!ADJ) {
       if (W <= 4) {
         if constexpr (PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2, kExtDich>(a, W, s, cu_count);
         return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
       }
-      if (step_nb(W, PREC, ADJ) == 2) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 2, kExtDich>(a, W, s, cu_count);
+      if constexpr (PREC == P_F32 || PREC == P_BF16) {
+        if (step_nb(W, PREC, ADJ) == 2) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 2, kExtDich>(a, W, s, cu_count);
+      }
       return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtDich>(a, W, s, cu_count);
     }
     return hipErrorInvalidValue;

@@ -1,8 +1,8 @@
 """GPU parity of dichroic absorption (per-cell linear dichroism eta of the
 absorption, direction factor sin^2 theta, acting before the scattering)
-against the FP64 oracle, through the C ABI: the fused fp32 and bf16 steps
-(32- and 64-cell tiles, the bf16 split-X tiles at n = 128) and the plain
-float32 path, the order of rt_set_dichroism and rt_set_medium, and the
+against the FP64 oracle, through the C ABI: the fused steps in every
+precision (32- and 64-cell tiles, the bf16 split-X tiles at n = 128) and the
+plain float32 path, the order of rt_set_dichroism and rt_set_medium, and the
 refusals.
 """
 import numpy as np
@@ -48,7 +48,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16", "bf16x3", "fp16"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%dx%d-n%d" % (
     c[0], c[1]["nx"], c[1]["ny"], W.ndir(W.spec(c[0], **c[1]))))
 def test_dichroism_forward_parity(case, precision):
@@ -146,11 +146,6 @@ def test_dichroism_refusals():
     import paper_2609_23057_amd as P
     spec = W.spec("beam512", nx=20, ny=18, dichroism=0.5, mixture={"kind": "rayleigh"})
     med = W.medium(spec)
-    for precision in ("fp16", "bf16x3"):
-        solver, _, _ = build(spec, precision, med)
-        with pytest.raises(P.RTError) as ei:
-            solver.set_dichroism(to_dev(med["eta"], solver))
-        assert ei.value.status == P.RT_EUNSUPPORTED, precision
     solver, _, _ = build(dict(spec, abs_taylor=True), "fp32", dict(med, eta=None))
     with pytest.raises(P.RTError) as ei:
         solver.set_dichroism(to_dev(med["eta"], solver))

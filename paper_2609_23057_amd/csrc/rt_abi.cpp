@@ -33,7 +33,8 @@ struct Layout {
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
-  size_t mix_tiles, mix_frag, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
+  size_t mix_tiles, mix_frag, mix_MT, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
+  size_t mix_tiles_bytes, mix_frag_bytes;
   size_t dich_eta, dich_xi, dich_w;   // dichroic absorption (rt_set_dichroism); 0 bytes if unsupported
   size_t tau, alb, emis, alpha, beta;
   size_t gacc, partial, sums, bad;
@@ -110,11 +111,14 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   // the contraction precision (fp32 or bf16 fused steps), per-cell fraction
   {
     const bool mix = !(prec_flags_plain) && (prec == RT_FP32 || prec == RT_BF16);
+    const bool mix_plain = prec_flags_plain;   // the plain path contracts a float32 M2^T on the ALUs
     const int kstep = prec == RT_FP32 ? 8 : 16;
-    const size_t frag = mix ? ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16 : 0;
-    L.mix_tiles = take(mix ? ntile * sizeof(TileRange) : 0);
-    L.mix_frag = take(frag);
-    L.frac = take(mix ? C * sizeof(float) : 0);
+    L.mix_frag_bytes = mix ? ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16 : 0;
+    L.mix_tiles_bytes = mix ? ntile * sizeof(TileRange) : 0;
+    L.mix_tiles = take(L.mix_tiles_bytes);
+    L.mix_frag = take(L.mix_frag_bytes);
+    L.mix_MT = take(mix_plain ? (size_t)hp.R * hp.R * sizeof(float) : 0);
+    L.frac = take((mix || mix_plain) ? C * sizeof(float) : 0);
     // dichroic absorption: per-cell eta and tau_abs * eta, per-direction sin^2 theta
     const bool dich = true;   // every precision (and the plain path)
     L.dich_eta = take(dich ? C * sizeof(float) : 0);
@@ -199,8 +203,12 @@ StepArgs rt_ctx::args(bool adjoint) const {
   a.a_scale_inv = (float)(1.0 / pk.a_scale);
   a.gacc = at<double>(L.gacc);
   if (mixture && !adjoint) {
-    a.frag2 = at<uint4>(L.mix_frag);
-    a.tiles2 = at<TileRange>(L.mix_tiles);
+    if (prob.flags & RT_PLAIN) {
+      a.MT2 = at<float>(L.mix_MT);
+    } else {
+      a.frag2 = at<uint4>(L.mix_frag);
+      a.tiles2 = at<TileRange>(L.mix_tiles);
+    }
     a.frac = at<float>(L.frac);
   }
   if (dichroic && !adjoint) {
@@ -522,8 +530,9 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     c->mixture = false;
     return RT_OK;
   }
-  if ((c->prob.flags & RT_PLAIN) || (c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16))
-    return c->fail(RT_EUNSUPPORTED, "phase mixtures run on the fused fp32 and bf16 paths only");
+  const bool plain = (c->prob.flags & RT_PLAIN) != 0;
+  if (!plain && c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16)
+    return c->fail(RT_EUNSUPPORTED, "phase mixtures run on the fused fp32 and bf16 paths and the plain path only");
   if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
   if (phase2 == RT_PHASE_TABLE) return c->fail(RT_EINVAL, "the second phase function cannot be a table");
   if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");
@@ -541,18 +550,32 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
   if (st != RT_OK) return c->fail(st, "second phase function: " + msg);
   std::vector<TileRange> tiles;
   std::vector<uint8_t> frag;
-  pack_fragments(hp2, false, c->prob.precision == RT_FP32 ? FRAG_F32 : FRAG_BF16, 1.0, false, &tiles, &frag);
+  std::vector<float> MT2;
   const Layout &L = c->L;
-  if (frag.size() > L.frac - L.mix_frag || tiles.size() * sizeof(TileRange) > L.mix_frag - L.mix_tiles)
-    return c->fail(RT_EINVAL, "mixture fragments exceed their workspace region");
+  if (plain) {
+    // float32 M2 transposed, as the plain collision reads M
+    const int R = hp2.R;
+    MT2.resize((size_t)R * R);
+    for (int r = 0; r < R; ++r)
+      for (int k = 0; k < R; ++k) MT2[(size_t)k * R + r] = (float)hp2.M[(size_t)r * R + k];
+  } else {
+    pack_fragments(hp2, false, c->prob.precision == RT_FP32 ? FRAG_F32 : FRAG_BF16, 1.0, false, &tiles, &frag);
+    if (frag.size() > L.mix_frag_bytes || tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes)
+      return c->fail(RT_EINVAL, "mixture fragments exceed their workspace region");
+  }
   c->mixture = false;
   const size_t C = (size_t)c->geo.C;
   std::vector<float> hf(C);
-  st = c->hip(hipMemcpyAsync(c->ws + L.mix_tiles, tiles.data(), tiles.size() * sizeof(TileRange),
-                             hipMemcpyHostToDevice, c->stream), "upload mixture tiles");
-  if (st == RT_OK)
-    st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag, frag.data(), frag.size(), hipMemcpyHostToDevice, c->stream),
-                "upload mixture fragments");
+  if (plain) {
+    st = c->hip(hipMemcpyAsync(c->ws + L.mix_MT, MT2.data(), MT2.size() * sizeof(float), hipMemcpyHostToDevice,
+                               c->stream), "upload mixture matrix");
+  } else {
+    st = c->hip(hipMemcpyAsync(c->ws + L.mix_tiles, tiles.data(), tiles.size() * sizeof(TileRange),
+                               hipMemcpyHostToDevice, c->stream), "upload mixture tiles");
+    if (st == RT_OK)
+      st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag, frag.data(), frag.size(), hipMemcpyHostToDevice, c->stream),
+                  "upload mixture fragments");
+  }
   if (st == RT_OK)
     st = c->hip(hipMemcpyAsync(c->ws + L.frac, d_frac, C * sizeof(float), hipMemcpyDeviceToDevice, c->stream),
                 "copy fraction");

@@ -42,6 +42,7 @@ struct StepArgs {
   const uint4 *frag2;      // A fragments of M2, in the contraction precision
   const TileRange *tiles2; // [Rpad / 32]
   const float *frac;       // [C]
+  const float *MT2;        // plain path: float32 M2 transposed [R][R] (row k holds M2[r][k] for all r)
   // dichroic absorption (forward only; dich_xi == nullptr: none): I + Q and
   // I - Q of direction d in cell c are multiplied by exp(-+dich_xi[c] dich_w[d])
   const float *dich_xi;    // [C] tau_abs * eta per cell

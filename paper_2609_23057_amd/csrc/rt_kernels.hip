@@ -1286,7 +1286,7 @@ __device__ __forceinline__ void dich_apply(float &xI, float &xQ, float x) {
   xQ = 0.5f * (pl - mi);
 }
 
-template <bool DICH>
+template <bool DICH, bool MIX>
 __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const float *__restrict__ MT,
                                                            const float *__restrict__ in,
                                                            float *__restrict__ out) {
@@ -1300,29 +1300,36 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
   const float al = a.alpha[cc], be = a.beta[cc], em = a.emis[cc];
   const float edt = a.dt_pre * em;
   const float xi = DICH ? a.dich_xi[cc] : 0.0f;
-  float acc[kValuRows];
+  const float fr = MIX ? a.frac[cc] : 0.0f;   // phase mixture: fraction of M2
+  float acc[kValuRows], acc2[MIX ? kValuRows : 1];
 #pragma unroll
   for (int r = 0; r < kValuRows; ++r) acc[r] = 0.0f;
-  // acc[r] += M[r0 + r][k] x_k over k; mk = MT + k R + r0 holds M[r0 + r][k] at mk[r]
-  auto accumulate = [&](int k, float x) {
-    const float *mk = MT + (int64_t)k * R + r0;
+#pragma unroll
+  for (int r = 0; r < (MIX ? kValuRows : 1); ++r) acc2[r] = 0.0f;
+  // ac[r] += M[r0 + r][k] x_k over k; mk = MT + k R + r0 holds M[r0 + r][k] at mk[r]
+  auto accumulate_into = [&](const float *__restrict__ T, float *ac, int k, float x) {
+    const float *mk = T + (int64_t)k * R + r0;
 #pragma unroll
     for (int r = 0; r < kValuRows; r += 16) {
       if (r + 16 <= nr) {
         const f32x16u m = *reinterpret_cast<const f32x16u *>(mk + r);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[r + i] = fmaf(m[i], x, acc[r + i]);
+        for (int i = 0; i < 16; ++i) ac[r + i] = fmaf(m[i], x, ac[r + i]);
       } else {
 #pragma unroll
         for (int q = r; q < r + 16; q += 4) {
           if (q < nr) {
             const f32x4 m = *reinterpret_cast<const f32x4 *>(mk + q);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[q + i] = fmaf(m[i], x, acc[q + i]);
+            for (int i = 0; i < 4; ++i) ac[q + i] = fmaf(m[i], x, ac[q + i]);
           }
         }
       }
     }
+  };
+  auto accumulate = [&](int k, float x) {
+    accumulate_into(MT, acc, k, x);
+    if constexpr (MIX) accumulate_into(a.MT2, acc2, k, x);
   };
   if constexpr (DICH) {
     // one direction (4 Stokes rows) at a time: its I and Q are combined
@@ -1349,8 +1356,12 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
       }
       if constexpr (DICH) dich_apply(xo[0], xo[1], xi * a.dich_w[(r0 + r) / 4]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        out[(int64_t)(r0 + r + j) * g.C + c] = fmaf(be, acc[r + j], fmaf(al, xo[j], a.dt_post * em * jr[j]));
+      for (int j = 0; j < 4; ++j) {
+        float prod = acc[r + j];
+        // mixture: (1 - f) M X + f M2 X as p0 + f (p1 - p0), as in the fused step
+        if constexpr (MIX) prod = fmaf(fr, acc2[MIX ? r + j : 0] - prod, prod);
+        out[(int64_t)(r0 + r + j) * g.C + c] = fmaf(be, prod, fmaf(al, xo[j], a.dt_post * em * jr[j]));
+      }
     }
   }
 }
@@ -1764,10 +1775,13 @@ hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStre
 hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,
                                hipStream_t s) {
   const dim3 grid((unsigned)((a.geo.C + 255) / 256), (unsigned)((a.geo.R + kValuRows - 1) / kValuRows));
+  if (a.dich_xi != nullptr && a.frac != nullptr) return hipErrorInvalidValue;
   if (a.dich_xi != nullptr)
-    hipLaunchKernelGGL(collide_valu_kernel<true>, grid, dim3(256), 0, s, a, MT, in, out);
+    hipLaunchKernelGGL((collide_valu_kernel<true, false>), grid, dim3(256), 0, s, a, MT, in, out);
+  else if (a.frac != nullptr)
+    hipLaunchKernelGGL((collide_valu_kernel<false, true>), grid, dim3(256), 0, s, a, MT, in, out);
   else
-    hipLaunchKernelGGL(collide_valu_kernel<false>, grid, dim3(256), 0, s, a, MT, in, out);
+    hipLaunchKernelGGL((collide_valu_kernel<false, false>), grid, dim3(256), 0, s, a, MT, in, out);
   return hipGetLastError();
 }
 

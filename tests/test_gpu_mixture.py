@@ -4,7 +4,8 @@ A per-cell fraction f of the scattering follows a second phase function:
 Y = alpha X + beta ((1 - f) M X + f M2 X), with M and M2 each built as the
 Eq. 17 weights times the rotated Rayleigh Mueller matrices (Sec. 2.1.5).
 The fused fp32 and bf16 steps contract both matrices on the matrix cores
-and blend the two products per cell.
+and blend the two products per cell; the plain float32 path does the same
+on the vector ALUs.
 """
 import numpy as np
 import pytest
@@ -45,7 +46,7 @@ CASES = [
 # bf16 representation of M, not the kernel; bf16x3 serves such media.)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "plain"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%dx%d-n%d" % (
     c[0], c[1]["nx"], c[1]["ny"], W.ndir(W.spec(c[0], **c[1]))))
 def test_mixture_forward_parity(case, precision):
@@ -83,7 +84,7 @@ def test_mixture_step_and_checkpoints(precision):
     assert_close(to_np(S), hist[T], tol, "final")
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "plain"])
 @pytest.mark.parametrize("n_zen, n_az", [(4, 8), (8, 16)])
 def test_zero_fraction_equals_single_phase(precision, n_zen, n_az):
     """f = 0 everywhere: the blend returns the first product unchanged, so
@@ -164,7 +165,7 @@ def test_mixture_refusals():
     import paper_2609_23057_amd as P
     spec = W.spec("beam512", nx=20, ny=18, mixture={"kind": "rayleigh"})
     med = W.medium(spec)
-    for precision in ("plain", "fp16", "bf16x3"):
+    for precision in ("fp16", "bf16x3"):
         solver, _, _ = build(spec, precision, med)
         f = torch.zeros((18, 20), dtype=torch.float32, device=solver.device)
         with pytest.raises(P.RTError) as ei:

@@ -202,10 +202,12 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
  * per-cell fraction d_frac (device [ny][nx] float32, values in [0, 1],
  * copied into the workspace).  Every later rt_step / rt_run uses it; phase2 < 0
  * removes it (d_frac is then ignored).  Validation reads f on the host, so
- * the call synchronises the stream.  Errors: RT_EUNSUPPORTED for the
- * RT_FP16 and RT_BF16X3 precisions (RT_FP32, RT_BF16 and RT_PLAIN carry it); RT_EINVAL for an
+ * the call synchronises the stream.  Every precision carries it: M2 is
+ * packed like M (bf16x3 with its own low parts; RT_FP16 at M's power-of-two
+ * scale, which shares the unscale of the epilogue).  Errors: RT_EINVAL for an
  * invalid phase function or a NULL d_frac; RT_ERANGE if some f is outside
- * [0, 1] or not finite (the mixture is then off); RT_EUNSUPPORTED while
+ * [0, 1] or not finite, or, for RT_FP16, if max |M2| at M's scale reaches the
+ * fp16 range (more than 8 max |M|) (the mixture is then off); RT_EUNSUPPORTED while
  * dichroic absorption is set.  rt_adjoint, rt_batch_run and
  * rt_batch_adjoint return RT_EUNSUPPORTED while a mixture is set. */
 rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac);

@@ -33,7 +33,7 @@ struct Layout {
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
-  size_t mix_tiles, mix_frag, mix_MT, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
+  size_t mix_tiles, mix_frag, mix_frag_lo, mix_MT, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
   size_t mix_tiles_bytes, mix_frag_bytes;
   size_t dich_eta, dich_xi, dich_w;   // dichroic absorption (rt_set_dichroism); 0 bytes if unsupported
   size_t tau, alb, emis, alpha, beta;
@@ -110,13 +110,14 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   // phase mixture: tile ranges and dense A fragments of the second matrix in
   // the contraction precision (fp32 or bf16 fused steps), per-cell fraction
   {
-    const bool mix = !(prec_flags_plain) && (prec == RT_FP32 || prec == RT_BF16);
+    const bool mix = !(prec_flags_plain);
     const bool mix_plain = prec_flags_plain;   // the plain path contracts a float32 M2^T on the ALUs
     const int kstep = prec == RT_FP32 ? 8 : 16;
     L.mix_frag_bytes = mix ? ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16 : 0;
     L.mix_tiles_bytes = mix ? ntile * sizeof(TileRange) : 0;
     L.mix_tiles = take(L.mix_tiles_bytes);
     L.mix_frag = take(L.mix_frag_bytes);
+    L.mix_frag_lo = take(prec == RT_BF16X3 ? L.mix_frag_bytes : 0);
     L.mix_MT = take(mix_plain ? (size_t)hp.R * hp.R * sizeof(float) : 0);
     L.frac = take((mix || mix_plain) ? C * sizeof(float) : 0);
     // dichroic absorption: per-cell eta and tau_abs * eta, per-direction sin^2 theta
@@ -207,6 +208,7 @@ StepArgs rt_ctx::args(bool adjoint) const {
       a.MT2 = at<float>(L.mix_MT);
     } else {
       a.frag2 = at<uint4>(L.mix_frag);
+      a.frag2_lo = at<uint4>(L.mix_frag_lo);
       a.tiles2 = at<TileRange>(L.mix_tiles);
     }
     a.frac = at<float>(L.frac);
@@ -531,8 +533,6 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     return RT_OK;
   }
   const bool plain = (c->prob.flags & RT_PLAIN) != 0;
-  if (!plain && c->prob.precision != RT_FP32 && c->prob.precision != RT_BF16)
-    return c->fail(RT_EUNSUPPORTED, "phase mixtures run on the fused fp32 and bf16 paths and the plain path only");
   if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
   if (phase2 == RT_PHASE_TABLE) return c->fail(RT_EINVAL, "the second phase function cannot be a table");
   if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");
@@ -549,7 +549,7 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
   rt_status st = build_plan(&p2, &hp2, &msg);
   if (st != RT_OK) return c->fail(st, "second phase function: " + msg);
   std::vector<TileRange> tiles;
-  std::vector<uint8_t> frag;
+  std::vector<uint8_t> frag, frag_lo;
   std::vector<float> MT2;
   const Layout &L = c->L;
   if (plain) {
@@ -559,8 +559,26 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     for (int r = 0; r < R; ++r)
       for (int k = 0; k < R; ++k) MT2[(size_t)k * R + r] = (float)hp2.M[(size_t)r * R + k];
   } else {
-    pack_fragments(hp2, false, c->prob.precision == RT_FP32 ? FRAG_F32 : FRAG_BF16, 1.0, false, &tiles, &frag);
-    if (frag.size() > L.mix_frag_bytes || tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes)
+    // the contraction precision's fragments; fp16 takes the first matrix's
+    // power-of-two scale (both products share the epilogue's unscale), so M2
+    // must stay in the fp16 range at that scale
+    const int pr = c->prob.precision;
+    if (pr == RT_FP16) {
+      double mx = 0.0;
+      for (double v : hp2.M) mx = std::max(mx, std::fabs(v));
+      if (mx * c->pk.a_scale >= 65504.0) {
+        c->mixture = false;
+        return c->fail(RT_ERANGE, "the second matrix exceeds the fp16 range at the first matrix's scale");
+      }
+    }
+    const FragKind kind = pr == RT_FP32 ? FRAG_F32 : (pr == RT_FP16 ? FRAG_F16 : FRAG_BF16);
+    pack_fragments(hp2, false, kind, pr == RT_FP16 ? c->pk.a_scale : 1.0, false, &tiles, &frag);
+    if (pr == RT_BF16X3) {
+      std::vector<TileRange> unused;
+      pack_fragments(hp2, false, FRAG_BF16, 1.0, true, &unused, &frag_lo);
+    }
+    if (frag.size() > L.mix_frag_bytes || tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes ||
+        (pr == RT_BF16X3 && frag_lo.size() > L.mix_frag_bytes))
       return c->fail(RT_EINVAL, "mixture fragments exceed their workspace region");
   }
   c->mixture = false;
@@ -575,6 +593,9 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     if (st == RT_OK)
       st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag, frag.data(), frag.size(), hipMemcpyHostToDevice, c->stream),
                   "upload mixture fragments");
+    if (st == RT_OK && !frag_lo.empty())
+      st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag_lo, frag_lo.data(), frag_lo.size(), hipMemcpyHostToDevice,
+                                 c->stream), "upload mixture low fragments");
   }
   if (st == RT_OK)
     st = c->hip(hipMemcpyAsync(c->ws + L.frac, d_frac, C * sizeof(float), hipMemcpyDeviceToDevice, c->stream),

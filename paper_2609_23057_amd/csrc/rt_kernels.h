@@ -40,6 +40,7 @@ struct StepArgs {
   // phase mixture (forward only; frac == nullptr: none): the scattering of
   // cell c follows M with weight 1 - frac[c] and M2 with weight frac[c]
   const uint4 *frag2;      // A fragments of M2, in the contraction precision
+  const uint4 *frag2_lo;   // bf16x3: their low parts
   const TileRange *tiles2; // [Rpad / 32]
   const float *frac;       // [C]
   const float *MT2;        // plain path: float32 M2 transposed [R][R] (row k holds M2[r][k] for all r)

@@ -434,8 +434,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
                 "two column blocks: forward float32 or bf16");
   constexpr bool MIX = EXT == kExtMix;
   constexpr bool DICH = EXT == kExtDich;
-  static_assert(!MIX || (!ADJ && NB == 1 && (PREC == P_F32 || PREC == P_BF16)),
-                "phase mixtures: forward float32 or bf16, one column block");
+  static_assert(!MIX || (!ADJ && NB == 1), "phase mixtures: forward steps, one column block");
   static_assert(!DICH || !ADJ, "dichroic absorption: forward steps");
   // bf16 contraction with two column blocks: X lives as high + low tiles
   constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
@@ -704,11 +703,15 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     const TileRange tr2 = a.tiles2[t];
     const int nk2 = (tr2.khi - tr2.klo) / kStep;
     const uint4 *A2 = a.frag2 + lane;
+    const uint4 *A2lo = a.frag2_lo + lane;
 #pragma unroll
-    for (int j = 0; j < kRing; ++j) ring[j] = A2[frag_rec(tr2, j, nk2)];
+    for (int j = 0; j < kRing; ++j) {
+      ring[j] = A2[frag_rec(tr2, j, nk2)];
+      if (PREC == P_BF16X3) ring_lo[j] = A2lo[frag_rec(tr2, j, nk2)];
+    }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) acc2[cb] = f32x16{0};
-    contract(A2, Alo, tr2, nk2, ring, ring_lo, acc2);
+    contract(A2, A2lo, tr2, nk2, ring, ring_lo, acc2);
   }
   (void)acc2;
 
@@ -1071,8 +1074,8 @@ template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   if (a.frac != nullptr && a.dich_xi != nullptr) return hipErrorInvalidValue;
   if (a.frac != nullptr) {
-    // phase mixture: forward fp32 / bf16, 32-cell tiles
-    if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
+    // phase mixture: forward steps, 32-cell tiles
+    if constexpr (!ADJ) {
       if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtMix>(a, W, s, cu_count);
       return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtMix>(a, W, s, cu_count);
     }

@@ -81,3 +81,28 @@ def assert_close(got, ref, tol, what=""):
     bad = {k: v for k, v in e.items() if k in "IQUV" and v > tol}
     assert not bad and e["maxabs"] < 10 * tol and e["dolp_abs"] < 10 * tol, (what, e)
     return e
+
+
+def _bf16(a):
+    """Round to bfloat16 through float32, to nearest even, as the fragment
+    packer does."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def represented(M, precision, scale_of=None):
+    """The collision matrix as a 16-bit contraction holds it: bf16, bf16 high
+    + low parts (bf16x3), or fp16 (through float32) after the power-of-two
+    scale that puts max |scale_of| in [2^12, 2^13) (scale_of = M itself by
+    default; a mixture's second matrix takes the first one's scale)."""
+    if precision == "bf16":
+        return _bf16(M)
+    if precision == "bf16x3":
+        hi = _bf16(M)
+        return hi + _bf16(M - hi)
+    if precision == "fp16":
+        e = np.frexp(np.abs(M if scale_of is None else scale_of).max())[1]
+        sc = 2.0 ** (13 - e)
+        return np.asarray(M * sc, dtype=np.float32).astype(np.float16).astype(np.float64) / sc
+    return M

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import GTOL, assert_close, build, to_dev, to_np, tolerance
+from gpu_common import GTOL, assert_close, build, represented, to_dev, to_np, tolerance
 from oracle import adjoint as OA
 from oracle import lbm as OL
 
@@ -34,30 +34,6 @@ CASES = [
     ("prec1024", dict(nx=19, ny=22), 15),                      # n = 128
     ("plain32", dict(nx=30, ny=21), 40),                       # n = 8, scattering-dominated
 ]
-
-
-def _bf16(a):
-    """Round to bfloat16 through float32, to nearest even, as the fragment
-    packer does."""
-    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def represented(M, precision):
-    """The collision matrix as a 16-bit contraction holds it: bf16, bf16 high
-    + low parts (bf16x3), or fp16 (through float32) after the power-of-two
-    scale that puts max |M| in [2^12, 2^13)."""
-    if precision == "bf16":
-        return _bf16(M)
-    if precision == "bf16x3":
-        hi = _bf16(M)
-        return hi + _bf16(M - hi)
-    if precision == "fp16":
-        e = np.frexp(np.abs(M).max())[1]
-        sc = 2.0 ** (13 - e)
-        return np.asarray(M * sc, dtype=np.float32).astype(np.float16).astype(np.float64) / sc
-    return M
 
 
 @pytest.mark.parametrize("precision", ["fp32", "plain", "bf16x3", "bf16", "fp16"])

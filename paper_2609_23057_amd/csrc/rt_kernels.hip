@@ -1376,34 +1376,36 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
 //
 // Columns x in [4, nx - 5] (nx a multiple of 4: "quad columns") have every
 // x tap inside the lattice.  There a thread produces 4 consecutive cells of
-// 2 rows of one plane over kZRun layers, sliding along z so that each layer
-// step loads one new source layer of 3 rows (two aligned 16-byte loads per
-// row, or, for a row outside the lattice in y or z, its face's ghost value,
-// uniform along the row).  The 8 end columns of every row take one thread
-// per cell with the general tap rules.
-constexpr int kZRun = 8;   // layers per quad-column thread
+// kRowsQ rows of one plane over kZRun layers, sliding along z so that each
+// layer step loads one new source layer of kRowsQ + 1 rows (two aligned
+// 16-byte loads per row, or, for a row outside the lattice in y or z, its
+// face's ghost value, uniform along the row).  The 8 end columns of every row
+// take one thread per cell with the general tap rules.
+constexpr int kZRun = 8;    // layers per quad-column thread
+constexpr int kRowsQ = 2;   // rows per quad-column thread
 
 struct Box3 {
   int on;          // quad columns exist (nx a multiple of 4, nx >= 12, aligned fields)
   int nqx;         // quads per row
-  int nyp, nq;     // row pairs per layer; quad-column threads per plane (kZRun layers each)
+  int nyp, nq;     // row groups (kRowsQ rows) per layer; quad-column threads per plane (kZRun layers each)
   int nbord;       // cells of the end columns (all cells when `on` is 0)
   int ib;          // blocks per plane taking quads
   int bpp;         // blocks per plane
 };
 
-// Loads one source layer zs (3 rows y - oy0 + {-1, 0, 1}) of a quad column:
+// Loads one source layer zs (kRowsQ + 1 rows y - oy0 - 1 + {0 .. kRowsQ}) of a quad column:
 // each row as the 8 aligned floats that start SH + 1 floats before the first
 // cell's bx = 0 tap, or the ghost value of its face for a row outside the
 // lattice in y or z.
 template <int SH>
 __device__ __forceinline__ void quad3_layer(const Stream3Args &g, const DirTaps3 &tp, const float *__restrict__ in,
-                                            int64_t plane, int p, int x0, int y, int zs, float (&e)[3][8]) {
+                                            int64_t plane, int p, int x0, int y, int zs,
+                                            float (&e)[kRowsQ + 1][8]) {
   const int64_t layer = (int64_t)g.ny * g.nx;
   const int zw = wrap_axis(zs, g.nz, g.per_z);
   const bool inz = (unsigned)zw < (unsigned)g.nz;
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
+  for (int b = 0; b < kRowsQ + 1; ++b) {
     const int ys = wrap_axis(y - tp.oy0 + b - 1, g.ny, g.per_y);
     const bool iny = (unsigned)ys < (unsigned)g.ny;
     if (inz && iny) {
@@ -1423,21 +1425,21 @@ __device__ __forceinline__ void quad3_layer(const Stream3Args &g, const DirTaps3
   }
 }
 
-// A quad column of two rows (y, y + 1; the second while y + 1 < ny) over the
+// A quad column of kRowsQ rows (y, y + 1, ...; those below ny) over the
 // layers z0 .. z1 - 1, sliding along z: output layer z reads source layers
 // z - oz0 - 1 (bz = 1) and z - oz0 (bz = 0), so each step loads one new
-// source layer (3 rows) and keeps the previous one.
+// source layer (kRowsQ + 1 rows) and keeps the previous one.
 template <int SH>
 __device__ __forceinline__ void quad3_column(const Stream3Args &g, const DirTaps3 &tp, const float *__restrict__ in,
                                              int64_t plane, int p, int x0, int y, int z0, int z1,
                                              float *__restrict__ out) {
   const int64_t layer = (int64_t)g.ny * g.nx;
-  float hi[3][8], lo[3][8];   // source layers z - oz0 (bz = 0) and z - oz0 - 1 (bz = 1)
+  float hi[kRowsQ + 1][8], lo[kRowsQ + 1][8];   // source layers z - oz0 (bz = 0) and z - oz0 - 1 (bz = 1)
   quad3_layer<SH>(g, tp, in, plane, p, x0, y, z0 - tp.oz0 - 1, lo);
   for (int z = z0; z < z1; ++z) {
     quad3_layer<SH>(g, tp, in, plane, p, x0, y, z - tp.oz0, hi);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kRowsQ; ++j) {
       if (y + j >= g.ny) continue;
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -1453,7 +1455,7 @@ __device__ __forceinline__ void quad3_column(const Stream3Args &g, const DirTaps
           f32x4{acc[0], acc[1], acc[2], acc[3]};
     }
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int b = 0; b < kRowsQ + 1; ++b)
 #pragma unroll
       for (int k = 0; k < 8; ++k) lo[b][k] = hi[b][k];
   }
@@ -1477,7 +1479,7 @@ __global__ void __launch_bounds__(256) stream3d_kernel(Stream3Args g, Box3 box, 
     if (q >= box.nq) return;
     const int qx = q % box.nqx;
     const int t = q / box.nqx;
-    const int y = 2 * (t % box.nyp);
+    const int y = kRowsQ * (t % box.nyp);
     const int z0 = kZRun * (t / box.nyp);
     const int z1 = min(z0 + kZRun, g.nz);
     const int x0 = 4 + 4 * qx;
@@ -1795,7 +1797,7 @@ hipError_t launch_stream3d(const Stream3Args &a, const float *in, float *out, hi
   if (aligned && a.nx % 4 == 0 && a.nx >= 12) {
     box.on = 1;
     box.nqx = a.nx / 4 - 2;
-    box.nyp = (a.ny + 1) / 2;
+    box.nyp = (a.ny + kRowsQ - 1) / kRowsQ;
     box.nq = box.nqx * box.nyp * ((a.nz + kZRun - 1) / kZRun);
     box.nbord = 8 * a.ny * a.nz;
     box.ib = (box.nq + 255) / 256;

@@ -9,7 +9,8 @@ oracle.lbm, written from the chain rule.  With
   S_{t+1} = L(Y_t) + ghost constants
 and lambda_T = dLoss/dS_T, for t = T-1 .. 0:
   mu_t     = L^T lambda_{t+1}          (dLoss/dY_t)
-  nu_t     = M^T mu_t
+  nu_t     = M^T mu_t                  (with a per-cell phase mixture, whose
+             scattering is (1 - f) M X + f M2 X: (1 - f) M^T mu_t + f M2^T mu_t)
   lambda_t = alpha mu_t + beta nu_t    (dLoss/dX_t = dLoss/dS_t)
   g_alpha += <mu_t, X_t>,  g_beta += <nu_t, X_t>   (per cell, over d and s)
   g_emis  += dt <e lambda_t + (1 - e) mu_t, jprof>
@@ -23,8 +24,8 @@ from . import lbm
 
 def adjoint(S0, prob, nsteps, lam_T):
     """Returns dict(lambda0, g_alpha, g_beta, g_tau, g_albedo, g_emis)."""
-    if prob.M2 is not None or prob.eta is not None:
-        raise NotImplementedError("the adjoint covers single-phase, non-dichroic media")
+    if prob.eta is not None:
+        raise NotImplementedError("the adjoint covers non-dichroic media")
     n, C = prob.n, prob.nx * prob.ny
     J = prob.emission_field()
     e = 0.0 if prob.fused_taylor else 1.0
@@ -40,6 +41,9 @@ def adjoint(S0, prob, nsteps, lam_T):
         X = (hist[t] + e * prob.dt * J).reshape(4 * n, C)
         mu = lbm.stream_transpose(lam, prob).reshape(4 * n, C)
         nu = prob.M.T @ mu
+        if prob.M2 is not None:
+            f = prob.frac.reshape(1, C)
+            nu = (1.0 - f) * nu + f * (prob.M2.T @ mu)
         g_al += np.sum(mu * X, axis=0)
         g_be += np.sum(nu * X, axis=0)
         lam_x = al[None, :] * mu + be[None, :] * nu
@@ -67,7 +71,7 @@ def edge_loss_of(params, base_prob, S0, nsteps, edge):
     p = lbm.Problem(base_prob.nx, base_prob.ny, base_prob.dirs, base_prob.shifts,
                     base_prob.M, base_prob.dt, base_prob.bc, tau, alb, em,
                     base_prob.jprof, base_prob.inflow, base_prob.abs_taylor,
-                    base_prob.scat_exp, base_prob.fused_taylor)
+                    base_prob.scat_exp, base_prob.fused_taylor, M2=base_prob.M2, frac=base_prob.frac)
     S = lbm.run(S0, p, nsteps)
     return lbm.edge_loss(S, p, edge)[0]
 

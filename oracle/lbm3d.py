@@ -170,13 +170,14 @@ def stream_transpose(G, prob):
 def adjoint(S0, prob, nsteps, lam_T):
     """Reverse-mode gradient on a 3-D lattice, the chain rule of oracle.adjoint
     with the 3-D streaming: for t = T-1 .. 0, mu = L^T lambda_{t+1},
-    nu = M^T mu, lambda_t = alpha mu + beta nu, g_alpha += <mu, X_t>,
+    nu = M^T mu (mixed as in the forward step: (1 - f) M^T mu + f M2^T mu),
+    lambda_t = alpha mu + beta nu, g_alpha += <mu, X_t>,
     g_beta += <nu, X_t>, g_emis += dt <e lambda_t + (1 - e) mu, jprof>.
     Returns dict(lambda0, g_alpha, g_beta, g_tau, g_albedo, g_emis), per-cell
     arrays [nz, ny, nx]."""
     f = prob.flat
-    if f.M2 is not None or f.eta is not None:
-        raise NotImplementedError("the adjoint covers single-phase, non-dichroic media")
+    if f.eta is not None:
+        raise NotImplementedError("the adjoint covers non-dichroic media")
     n, C = prob.n, prob.nx * prob.ny * prob.nz
     J = f.emission_field().reshape(prob.shape)
     e = 0.0 if f.fused_taylor else 1.0
@@ -189,6 +190,9 @@ def adjoint(S0, prob, nsteps, lam_T):
         X = (hist[t] + e * f.dt * J).reshape(4 * n, C)
         mu = stream_transpose(lam, prob).reshape(4 * n, C)
         nu = f.M.T @ mu
+        if f.M2 is not None:
+            fr = f.frac.reshape(1, C)
+            nu = (1.0 - fr) * nu + fr * (f.M2.T @ mu)
         g_al += np.sum(mu * X, axis=0)
         g_be += np.sum(nu * X, axis=0)
         lam_x = al[None, :] * mu + be[None, :] * nu

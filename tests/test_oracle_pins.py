@@ -464,8 +464,9 @@ def test_p14_dense_operator_and_multi_step():
 
 # ----------------------------------------------------------------- P15 --
 
-def _adj_problem(fused=False, scat_exp=False, abs_taylor=False):
-    s = W.spec("adjoint256", nx=10, ny=8, n_zen=2, n_az=4)
+def _adj_problem(fused=False, scat_exp=False, abs_taylor=False, mixture=False):
+    s = W.spec("adjoint256", nx=10, ny=8, n_zen=2, n_az=4,
+               mixture={"kind": "hg", "g": -0.4} if mixture else None)
     med = W.medium(s)
     med["tau"] = med["tau"] * 10.0
     s["fused_taylor"] = fused
@@ -474,11 +475,14 @@ def _adj_problem(fused=False, scat_exp=False, abs_taylor=False):
     return s, OL.make_problem(s, med)
 
 
-@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "abs_taylor"])
+@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "abs_taylor", "mixture"])
 def test_p15_adjoint_dot_product(variant):
     """<A x, y> = <x, A^T y> for the T-step linear part: the adjoint state
     lambda_0 from lambda_T = y must satisfy <S_T(x) - S_T(0), y> = <x, lambda_0>."""
-    s, prob = _adj_problem(variant == "fused", variant == "scat_exp", variant == "abs_taylor")
+    s, prob = _adj_problem(variant == "fused", variant == "scat_exp", variant == "abs_taylor",
+                           variant == "mixture")
+    if variant == "mixture":
+        assert prob.M2 is not None and 0.1 < prob.frac.mean() < 0.9
     T = 7
     rng = np.random.default_rng(11)
     x = rng.normal(size=prob.shape)
@@ -491,11 +495,12 @@ def test_p15_adjoint_dot_product(variant):
     assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
 
 
-@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp"])
+@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "mixture"])
 def test_p15_adjoint_gradients_match_central_differences(variant):
     """Gradients of the top-edge (I + DoLP) loss wrt per-cell tau, albedo and
-    emission against FP64 central differences on sampled cells."""
-    s, prob = _adj_problem(variant == "fused", variant == "scat_exp")
+    emission against FP64 central differences on sampled cells (the mixture
+    variant: a per-cell HG(-0.4) fraction of the scattering)."""
+    s, prob = _adj_problem(variant == "fused", variant == "scat_exp", mixture=variant == "mixture")
     T = 12
     S0 = np.zeros(prob.shape)
     S_T = OL.run(S0, prob, T)

@@ -208,8 +208,9 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
  * invalid phase function or a NULL d_frac; RT_ERANGE if some f is outside
  * [0, 1] or not finite, or, for RT_FP16, if max |M2| at M's scale reaches the
  * fp16 range (more than 8 max |M|) (the mixture is then off); RT_EUNSUPPORTED while
- * dichroic absorption is set.  rt_adjoint, rt_batch_run and
- * rt_batch_adjoint return RT_EUNSUPPORTED while a mixture is set. */
+ * dichroic absorption is set.  rt_adjoint carries the mixture (its step
+ * contracts M^T and M2^T, packed here too, and blends them per cell);
+ * rt_batch_run and rt_batch_adjoint return RT_EUNSUPPORTED while one is set. */
 rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac);
 
 /* Dichroic absorption (polarisation-dependent extinction, which the paper's
@@ -273,9 +274,11 @@ size_t rt_adjoint_segment_bytes(const rt_problem *p, int32_t ckpt_every);
  * by rt_run (same nsteps and ckpt_every; recomputes each segment into d_seg).
  * Outputs [ny][nx]: d_g_tau = dL/dtau, d_g_albedo = dL/dalbedo, d_g_emis =
  * dL/deps; d_lambda0 (state, or NULL) = dL/dS_0.  Inflow radiances and the
- * emission profile are treated as constants.  The reverse steps run on the
- * fused matrix-core kernels (float32 for an RT_PLAIN context), so n <= 128 is
- * required: RT_EUNSUPPORTED otherwise. */
+ * emission profile are treated as constants; a phase mixture's fraction f is
+ * held fixed too (its step transposes the mixed scattering).  The reverse
+ * steps run on the fused matrix-core kernels (float32 for an RT_PLAIN
+ * context), so n <= 128 is required: RT_EUNSUPPORTED otherwise, and while
+ * dichroic absorption is set. */
 rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckpt_every, float *d_seg,
                      const float *d_lambdaT, float *d_g_tau, float *d_g_albedo, float *d_g_emis,
                      float *d_lambda0);

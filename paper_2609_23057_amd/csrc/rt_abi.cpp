@@ -33,7 +33,8 @@ struct Layout {
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
   size_t jrow, ghost;             // set by rt_set_medium
-  size_t mix_tiles, mix_frag, mix_frag_lo, mix_MT, frac;   // phase mixture (rt_set_phase_mixture); 0 bytes if unsupported
+  size_t mix_tiles, mix_frag, mix_frag_lo, mix_MT, frac;   // phase mixture (rt_set_phase_mixture)
+  size_t mix_tiles_adj, mix_frag_adj, mix_frag_adj_lo;       // its transpose, for the adjoint
   size_t mix_tiles_bytes, mix_frag_bytes;
   size_t dich_eta, dich_xi, dich_w;   // dichroic absorption (rt_set_dichroism); 0 bytes if unsupported
   size_t tau, alb, emis, alpha, beta;
@@ -107,19 +108,25 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   L.tables_bytes = off - L.tables;
   L.jrow = take(hp.Rpad * sizeof(float));
   L.ghost = take(7 * hp.Rpad * sizeof(float));   // 4 edges (6 faces in 3-D) + zero rows
-  // phase mixture: tile ranges and dense A fragments of the second matrix in
-  // the contraction precision (fp32 or bf16 fused steps), per-cell fraction
+  // phase mixture: tile ranges and dense A fragments of the second matrix and
+  // of its transpose in the contraction precision (float32 for the plain path,
+  // whose adjoint replays on the fused float32 kernels), the plain path's
+  // float32 M2^T, per-cell fraction
   {
-    const bool mix = !(prec_flags_plain);
     const bool mix_plain = prec_flags_plain;   // the plain path contracts a float32 M2^T on the ALUs
-    const int kstep = prec == RT_FP32 ? 8 : 16;
-    L.mix_frag_bytes = mix ? ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16 : 0;
-    L.mix_tiles_bytes = mix ? ntile * sizeof(TileRange) : 0;
+    const bool f32 = prec == RT_FP32 || mix_plain;
+    const int kstep = f32 ? 8 : 16;
+    L.mix_frag_bytes = ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16;
+    L.mix_tiles_bytes = ntile * sizeof(TileRange);
+    const size_t lo = (!f32 && prec == RT_BF16X3) ? L.mix_frag_bytes : 0;
     L.mix_tiles = take(L.mix_tiles_bytes);
     L.mix_frag = take(L.mix_frag_bytes);
-    L.mix_frag_lo = take(prec == RT_BF16X3 ? L.mix_frag_bytes : 0);
+    L.mix_frag_lo = take(lo);
+    L.mix_tiles_adj = take(L.mix_tiles_bytes);
+    L.mix_frag_adj = take(L.mix_frag_bytes);
+    L.mix_frag_adj_lo = take(lo);
     L.mix_MT = take(mix_plain ? (size_t)hp.R * hp.R * sizeof(float) : 0);
-    L.frac = take((mix || mix_plain) ? C * sizeof(float) : 0);
+    L.frac = take(C * sizeof(float));
     // dichroic absorption: per-cell eta and tau_abs * eta, per-direction sin^2 theta
     const bool dich = true;   // every precision (and the plain path)
     L.dich_eta = take(dich ? C * sizeof(float) : 0);
@@ -203,14 +210,13 @@ StepArgs rt_ctx::args(bool adjoint) const {
                                   : (f32 ? L.tiles_fwd32 : L.tiles_fwd));
   a.a_scale_inv = (float)(1.0 / pk.a_scale);
   a.gacc = at<double>(L.gacc);
-  if (mixture && !adjoint) {
-    if (prob.flags & RT_PLAIN) {
-      a.MT2 = at<float>(L.mix_MT);
-    } else {
-      a.frag2 = at<uint4>(L.mix_frag);
-      a.frag2_lo = at<uint4>(L.mix_frag_lo);
-      a.tiles2 = at<TileRange>(L.mix_tiles);
-    }
+  if (mixture) {
+    // the plain collision reads MT2; the fused kernels (also the plain
+    // path's adjoint replay) the fragments
+    if ((prob.flags & RT_PLAIN) && !adjoint) a.MT2 = at<float>(L.mix_MT);
+    a.frag2 = at<uint4>(adjoint ? L.mix_frag_adj : L.mix_frag);
+    a.frag2_lo = at<uint4>(adjoint ? L.mix_frag_adj_lo : L.mix_frag_lo);
+    a.tiles2 = at<TileRange>(adjoint ? L.mix_tiles_adj : L.mix_tiles);
     a.frac = at<float>(L.frac);
   }
   if (dichroic && !adjoint) {
@@ -548,8 +554,8 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
   std::string msg;
   rt_status st = build_plan(&p2, &hp2, &msg);
   if (st != RT_OK) return c->fail(st, "second phase function: " + msg);
-  std::vector<TileRange> tiles;
-  std::vector<uint8_t> frag, frag_lo;
+  std::vector<TileRange> tiles, tiles_adj;
+  std::vector<uint8_t> frag, frag_lo, frag_adj, frag_adj_lo;
   std::vector<float> MT2;
   const Layout &L = c->L;
   if (plain) {
@@ -558,11 +564,13 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     MT2.resize((size_t)R * R);
     for (int r = 0; r < R; ++r)
       for (int k = 0; k < R; ++k) MT2[(size_t)k * R + r] = (float)hp2.M[(size_t)r * R + k];
-  } else {
-    // the contraction precision's fragments; fp16 takes the first matrix's
-    // power-of-two scale (both products share the epilogue's unscale), so M2
-    // must stay in the fp16 range at that scale
-    const int pr = c->prob.precision;
+  }
+  {
+    // the contraction precision's fragments of M2 and M2^T (float32 for the
+    // plain path); fp16 takes the first matrix's power-of-two scale (both
+    // products share the epilogue's unscale), so M2 must stay in the fp16
+    // range at that scale
+    const int pr = plain ? RT_FP32 : c->prob.precision;
     if (pr == RT_FP16) {
       double mx = 0.0;
       for (double v : hp2.M) mx = std::max(mx, std::fabs(v));
@@ -572,31 +580,39 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
       }
     }
     const FragKind kind = pr == RT_FP32 ? FRAG_F32 : (pr == RT_FP16 ? FRAG_F16 : FRAG_BF16);
-    pack_fragments(hp2, false, kind, pr == RT_FP16 ? c->pk.a_scale : 1.0, false, &tiles, &frag);
+    const double sc = pr == RT_FP16 ? c->pk.a_scale : 1.0;
+    pack_fragments(hp2, false, kind, sc, false, &tiles, &frag);
+    pack_fragments(hp2, true, kind, sc, false, &tiles_adj, &frag_adj);
     if (pr == RT_BF16X3) {
       std::vector<TileRange> unused;
       pack_fragments(hp2, false, FRAG_BF16, 1.0, true, &unused, &frag_lo);
+      pack_fragments(hp2, true, FRAG_BF16, 1.0, true, &unused, &frag_adj_lo);
     }
-    if (frag.size() > L.mix_frag_bytes || tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes ||
-        (pr == RT_BF16X3 && frag_lo.size() > L.mix_frag_bytes))
+    const size_t cap_lo = pr == RT_BF16X3 ? L.mix_frag_bytes : 0;
+    if (frag.size() > L.mix_frag_bytes || frag_adj.size() > L.mix_frag_bytes ||
+        tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes ||
+        tiles_adj.size() * sizeof(TileRange) > L.mix_tiles_bytes || frag_lo.size() > cap_lo ||
+        frag_adj_lo.size() > cap_lo)
       return c->fail(RT_EINVAL, "mixture fragments exceed their workspace region");
   }
   c->mixture = false;
   const size_t C = (size_t)c->geo.C;
   std::vector<float> hf(C);
-  if (plain) {
+  st = RT_OK;
+  if (plain)
     st = c->hip(hipMemcpyAsync(c->ws + L.mix_MT, MT2.data(), MT2.size() * sizeof(float), hipMemcpyHostToDevice,
                                c->stream), "upload mixture matrix");
-  } else {
-    st = c->hip(hipMemcpyAsync(c->ws + L.mix_tiles, tiles.data(), tiles.size() * sizeof(TileRange),
-                               hipMemcpyHostToDevice, c->stream), "upload mixture tiles");
-    if (st == RT_OK)
-      st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag, frag.data(), frag.size(), hipMemcpyHostToDevice, c->stream),
+  const struct { size_t off; const void *p; size_t n; } up[] = {
+      {L.mix_tiles, tiles.data(), tiles.size() * sizeof(TileRange)},
+      {L.mix_tiles_adj, tiles_adj.data(), tiles_adj.size() * sizeof(TileRange)},
+      {L.mix_frag, frag.data(), frag.size()},
+      {L.mix_frag_adj, frag_adj.data(), frag_adj.size()},
+      {L.mix_frag_lo, frag_lo.data(), frag_lo.size()},
+      {L.mix_frag_adj_lo, frag_adj_lo.data(), frag_adj_lo.size()}};
+  for (const auto &u : up)
+    if (st == RT_OK && u.n)
+      st = c->hip(hipMemcpyAsync(c->ws + u.off, u.p, u.n, hipMemcpyHostToDevice, c->stream),
                   "upload mixture fragments");
-    if (st == RT_OK && !frag_lo.empty())
-      st = c->hip(hipMemcpyAsync(c->ws + L.mix_frag_lo, frag_lo.data(), frag_lo.size(), hipMemcpyHostToDevice,
-                                 c->stream), "upload mixture low fragments");
-  }
   if (st == RT_OK)
     st = c->hip(hipMemcpyAsync(c->ws + L.frac, d_frac, C * sizeof(float), hipMemcpyDeviceToDevice, c->stream),
                 "copy fraction");
@@ -804,7 +820,6 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (nsteps < 1 || ckpt_every < 1) return c->fail(RT_EINVAL, "nsteps and ckpt_every must be >= 1");
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
-  if (c->mixture) return c->fail(RT_EUNSUPPORTED, "the adjoint of a phase mixture is not supported");
   if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "the adjoint of dichroic absorption is not supported");
   if (c->geo.Rpad > 512)
     return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");

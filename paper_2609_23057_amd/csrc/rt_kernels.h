@@ -37,9 +37,10 @@ struct StepArgs {
   // adjoint
   const float *lam_next;   // lambda_{t+1}
   double *gacc;            // [3][C]: g_alpha, g_beta, g_emis accumulators
-  // phase mixture (forward only; frac == nullptr: none): the scattering of
-  // cell c follows M with weight 1 - frac[c] and M2 with weight frac[c]
-  const uint4 *frag2;      // A fragments of M2, in the contraction precision
+  // phase mixture (frac == nullptr: none): the scattering of cell c follows
+  // M with weight 1 - frac[c] and M2 with weight frac[c]; the adjoint step
+  // takes M2^T here as it takes M^T in frag / tiles
+  const uint4 *frag2;      // A fragments of M2 (M2^T), in the contraction precision
   const uint4 *frag2_lo;   // bf16x3: their low parts
   const TileRange *tiles2; // [Rpad / 32]
   const float *frac;       // [C]

@@ -434,7 +434,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
                 "two column blocks: forward float32 or bf16");
   constexpr bool MIX = EXT == kExtMix;
   constexpr bool DICH = EXT == kExtDich;
-  static_assert(!MIX || (!ADJ && NB == 1), "phase mixtures: forward steps, one column block");
+  static_assert(!MIX || NB == 1, "phase mixtures: one column block");
   static_assert(!DICH || !ADJ, "dichroic absorption: forward steps");
   // bf16 contraction with two column blocks: X lives as high + low tiles
   constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
@@ -1074,12 +1074,11 @@ template <int PREC, bool GATHER, bool ADJ, bool CKPT>
 hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   if (a.frac != nullptr && a.dich_xi != nullptr) return hipErrorInvalidValue;
   if (a.frac != nullptr) {
-    // phase mixture: forward steps, 32-cell tiles
-    if constexpr (!ADJ) {
-      if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtMix>(a, W, s, cu_count);
-      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtMix>(a, W, s, cu_count);
-    }
-    return hipErrorInvalidValue;
+    // phase mixture, forward and adjoint: 32-cell tiles (the adjoint's
+    // second matrix is M2^T, passed in the same fields)
+    if (a.frag2 == nullptr || a.tiles2 == nullptr) return hipErrorInvalidValue;
+    if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtMix>(a, W, s, cu_count);
+    return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtMix>(a, W, s, cu_count);
   }
   if (a.dich_xi != nullptr) {
     // dichroic absorption: forward steps, the tiles of the plain step

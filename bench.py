@@ -174,7 +174,9 @@ def extension_extras(T=20, warm=3):
     operator beside the plain workload, per contraction precision: a
     tabulated scattering matrix (P12, P34 != 0), a per-cell phase-function
     mixture (HG(0.7) and Rayleigh, fraction U[0, 1]; two contractions per
-    cell) and dichroic absorption (eta U[-0.8, 0.8]; applied in the gather)."""
+    cell) and dichroic absorption (eta U[-0.8, 0.8]; applied in the gather).
+    For the plain workload and the mixture also the checkpointed adjoint over
+    the same steps (per-step cost and adjoint / checkpointed-forward ratio)."""
     import numpy as np
     import torch
     import workloads as W
@@ -209,6 +211,23 @@ def extension_extras(T=20, warm=3):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
             out[name] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+            if name in ("single", "mixture"):
+                # the checkpointed forward and its adjoint (recompute + adjoint steps)
+                K = max(1, int(math.ceil(math.sqrt(T))))
+                ck = solver.checkpoint_buffer(T, K)
+                seg = solver.segment_buffer(K)
+                lam = torch.rand_like(S)
+                S0 = S.clone()
+                e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                solver.run(S0, T, ck, K)
+                e2.record()
+                solver.adjoint(T, ck, K, lam, seg)
+                e3.record()
+                torch.cuda.synchronize()
+                out[name]["adjoint_ms_per_step"] = e2.elapsed_time(e3) / T
+                out[name]["adjoint_fwd_ratio"] = e2.elapsed_time(e3) / e0.elapsed_time(e2)
+                del ck, seg, lam, S0
             del solver, S
             torch.cuda.empty_cache()
         for name in variants:

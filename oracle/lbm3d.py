@@ -176,8 +176,7 @@ def adjoint(S0, prob, nsteps, lam_T):
     Returns dict(lambda0, g_alpha, g_beta, g_tau, g_albedo, g_emis), per-cell
     arrays [nz, ny, nx]."""
     f = prob.flat
-    if f.eta is not None:
-        raise NotImplementedError("the adjoint covers non-dichroic media")
+    from .adjoint import dichroic_derivative
     n, C = prob.n, prob.nx * prob.ny * prob.nz
     J = f.emission_field().reshape(prob.shape)
     e = 0.0 if f.fused_taylor else 1.0
@@ -185,9 +184,12 @@ def adjoint(S0, prob, nsteps, lam_T):
     jp = f.jprof.reshape(n, 4, 1)
     lam = np.array(lam_T, dtype=np.float64).reshape(prob.shape)
     al, be = f.alpha.reshape(C), f.beta.reshape(C)
-    g_al, g_be, g_em = np.zeros(C), np.zeros(C), np.zeros(C)
+    g_al, g_be, g_em, g_xi = np.zeros(C), np.zeros(C), np.zeros(C), np.zeros(C)
     for t in range(nsteps - 1, -1, -1):
         X = (hist[t] + e * f.dt * J).reshape(4 * n, C)
+        X0 = X
+        if f.eta is not None:
+            X = lbm.dichroic_absorption(X0, f)
         mu = stream_transpose(lam, prob).reshape(4 * n, C)
         nu = f.M.T @ mu
         if f.M2 is not None:
@@ -196,16 +198,21 @@ def adjoint(S0, prob, nsteps, lam_T):
         g_al += np.sum(mu * X, axis=0)
         g_be += np.sum(nu * X, axis=0)
         lam_x = al[None, :] * mu + be[None, :] * nu
+        if f.eta is not None:
+            g_xi += np.sum(lam_x * dichroic_derivative(X0, f), axis=0)
+            lam_x = lbm.dichroic_absorption(lam_x, f)   # D^T = D (symmetric in I, Q)
         src = e * lam_x + (1.0 - e) * mu
         g_em += f.dt * np.sum(src.reshape(n, 4, C) * jp, axis=(0, 1))
         lam = lam_x.reshape(prob.shape)
     dal_dt, dal_dw, dbe_dt, dbe_dw = lbm.coefficient_derivatives(f.tau, f.albedo, f.abs_taylor, f.scat_exp,
                                                                  f.fused_taylor)
     shp = (prob.nz, prob.ny, prob.nx)
-    g_al, g_be = g_al.reshape(shp), g_be.reshape(shp)
+    g_al, g_be, g_xi = g_al.reshape(shp), g_be.reshape(shp), g_xi.reshape(shp)
+    eta = 0.0 if f.eta is None else f.eta.reshape(shp)
     return {"lambda0": lam, "g_alpha": g_al, "g_beta": g_be,
-            "g_tau": g_al * dal_dt.reshape(shp) + g_be * dbe_dt.reshape(shp),
-            "g_albedo": g_al * dal_dw.reshape(shp) + g_be * dbe_dw.reshape(shp),
+            "g_tau": g_al * dal_dt.reshape(shp) + g_be * dbe_dt.reshape(shp)
+            + g_xi * (1.0 - f.albedo.reshape(shp)) * eta,
+            "g_albedo": g_al * dal_dw.reshape(shp) + g_be * dbe_dw.reshape(shp) - g_xi * f.tau.reshape(shp) * eta,
             "g_emis": g_em.reshape(shp)}
 
 

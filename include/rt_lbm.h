@@ -226,8 +226,11 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
  * in step with a new medium.  Synchronises the stream (eta is checked).
  * Every precision and RT_PLAIN carry it.  Errors: RT_EUNSUPPORTED with
  * RT_ABS_TAYLOR or RT_FUSED_TAYLOR, or while a phase mixture is set; RT_ERANGE if some |eta| >= 1 or eta is not finite
- * (dichroism is then off).  rt_adjoint, rt_batch_run and rt_batch_adjoint
- * return RT_EUNSUPPORTED while it is set; rt_set_phase_mixture likewise. */
+ * (dichroism is then off).  rt_adjoint carries it (eta held fixed: its step
+ * applies the symmetric factor to alpha mu + beta nu and adds the derivative
+ * through xi = tau_abs eta to the tau and albedo gradients); rt_batch_run and
+ * rt_batch_adjoint return RT_EUNSUPPORTED while it is set;
+ * rt_set_phase_mixture likewise. */
 rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);
 
 /* One step S_out = Stream(Collide(S_in)); S_in and S_out must not overlap. */
@@ -277,8 +280,8 @@ size_t rt_adjoint_segment_bytes(const rt_problem *p, int32_t ckpt_every);
  * emission profile are treated as constants; a phase mixture's fraction f is
  * held fixed too (its step transposes the mixed scattering).  The reverse
  * steps run on the fused matrix-core kernels (float32 for an RT_PLAIN
- * context), so n <= 128 is required: RT_EUNSUPPORTED otherwise, and while
- * dichroic absorption is set. */
+ * context), so n <= 128 is required: RT_EUNSUPPORTED otherwise (and if the
+ * dichroic adjoint step's fourth per-cell sum would not fit the LDS). */
 rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckpt_every, float *d_seg,
                      const float *d_lambdaT, float *d_g_tau, float *d_g_albedo, float *d_g_emis,
                      float *d_lambda0);

@@ -138,7 +138,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   L.emis = take(C * sizeof(float));
   L.alpha = take(C * sizeof(float));
   L.beta = take(C * sizeof(float));
-  L.gacc = take(3 * C * sizeof(double));
+  L.gacc = take(4 * C * sizeof(double));   // adjoint per-cell sums (4: with dichroic absorption)
   Geometry g{(int64_t)C, hp.nx, hp.ny, 0, 0, hp.n, hp.R, hp.Rpad};
   L.npart = sums_partials(g);
   L.partial = take((size_t)L.npart * 4 * sizeof(double));
@@ -219,7 +219,7 @@ StepArgs rt_ctx::args(bool adjoint) const {
     a.tiles2 = at<TileRange>(adjoint ? L.mix_tiles_adj : L.mix_tiles);
     a.frac = at<float>(L.frac);
   }
-  if (dichroic && !adjoint) {
+  if (dichroic) {
     a.dich_xi = at<float>(L.dich_xi);
     a.dich_w = at<float>(L.dich_w);
   }
@@ -820,7 +820,8 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   if (nsteps < 1 || ckpt_every < 1) return c->fail(RT_EINVAL, "nsteps and ckpt_every must be >= 1");
   if (ckpt_every > 1 && !d_seg) return c->fail(RT_EINVAL, "segment buffer is NULL");
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
-  if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "the adjoint of dichroic absorption is not supported");
+  if (c->dichroic && step_lds_bytes(c->geo, (c->prob.flags & RT_PLAIN) ? P_F32 : c->prec, true, true) > 160 * 1024)
+    return c->fail(RT_EUNSUPPORTED, "the dichroic adjoint step does not fit the LDS budget");
   if (c->geo.Rpad > 512)
     return c->fail(RT_EUNSUPPORTED, "the adjoint runs on the fused kernels, which support n <= 128");
   const int prec_save = c->prec;
@@ -830,7 +831,7 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
     return reinterpret_cast<const float *>(reinterpret_cast<const char *>(d_ckpt) + (size_t)k * sb);
   };
   auto seg = [&](int k) { return reinterpret_cast<float *>(reinterpret_cast<char *>(d_seg) + (size_t)k * sb); };
-  rt_status st = c->hip(launch_fill_f64(c->at<double>(c->L.gacc), 3 * c->geo.C, 0.0, c->stream), "fill");
+  rt_status st = c->hip(launch_fill_f64(c->at<double>(c->L.gacc), 4 * c->geo.C, 0.0, c->stream), "fill");
   float *Lb[2] = {c->at<float>(c->L.La), c->at<float>(c->L.Lb)};
   const float *lam_next = d_lambdaT;
   int flip = 0;
@@ -881,7 +882,8 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   }
   if (st == RT_OK)
     st = c->hip(launch_gradchain(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb), c->prob.flags,
-                                 c->at<double>(c->L.gacc), d_g_tau, d_g_albedo, d_g_emis, c->stream), "gradchain");
+                                 c->at<double>(c->L.gacc), d_g_tau, d_g_albedo, d_g_emis, c->stream,
+                                 c->dichroic ? c->at<float>(c->L.dich_eta) : nullptr), "gradchain");
   if (st == RT_OK && d_lambda0)
     st = c->hip(hipMemcpyAsync(d_lambda0, lam_next, sb, hipMemcpyDeviceToDevice, c->stream), "lambda0");
   c->prec = prec_save;

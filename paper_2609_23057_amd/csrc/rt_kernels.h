@@ -146,9 +146,11 @@ hipError_t launch_coef(int64_t C, const float *tau, const float *alb, const floa
 // (or non-finite eta) into *bad.
 hipError_t launch_dich_xi(int64_t C, const float *tau, const float *alb, const float *eta, float *xi, int *bad,
                           hipStream_t s);
+// gacc: per-cell sums [3][C] (with eta, dichroic absorption: [4][C], the
+// fourth the xi-derivative term)
 hipError_t launch_gradchain(int64_t C, const float *tau, const float *alb, uint32_t flags,
                             const double *gacc, float *g_tau, float *g_alb, float *g_emis,
-                            hipStream_t s);
+                            hipStream_t s, const float *eta = nullptr);
 
 hipError_t launch_fill_f32(float *p, int64_t count, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
@@ -165,6 +167,6 @@ hipError_t launch_maps(const Geometry &g, const float *S, float *I_mean, float *
 int sums_partials(const Geometry &g);
 
 // LDS bytes of the fused launch the library will use (SIZE_MAX if none fits).
-size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint);
+size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich = false);
 
 }  // namespace rtl

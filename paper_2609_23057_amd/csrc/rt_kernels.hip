@@ -348,7 +348,7 @@ struct LdsLayout {
 // as a high part (the B tile) and a low part (a second tile of the same
 // shape) whose sum restores it to 2^-18.
 __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
-                                               bool f16, int ngroups = 1, int nb = 1) {
+                                               bool f16, int ngroups = 1, int nb = 1, int nacc = 3) {
   LdsLayout L;
   const bool xsplit = nb > 1 && esize == 2;
   // the bf16 / bf16x3 adjoint keeps mu as high (B) and low tiles
@@ -367,7 +367,7 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
     L.x_off = L.b_off;
   }
   L.red_off = off;
-  const int nred = adjoint ? 3 : (f16 ? 1 : 0);
+  const int nred = adjoint ? nacc : (f16 ? 1 : 0);   // adjoint: nacc per-cell sums
   off += nred * W * 32 * nb * 4;
   L.group = off;
   L.jrow_off = ngroups * off;
@@ -435,7 +435,10 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   constexpr bool MIX = EXT == kExtMix;
   constexpr bool DICH = EXT == kExtDich;
   static_assert(!MIX || NB == 1, "phase mixtures: one column block");
-  static_assert(!DICH || !ADJ, "dichroic absorption: forward steps");
+  static_assert(!DICH || !ADJ || NB == 1, "dichroic absorption in the adjoint: one column block");
+  // adjoint per-cell sums: <mu, X_d>, <nu, X_d>, the emission term, and with
+  // dichroic absorption the xi-derivative term
+  constexpr int NACC = (ADJ && DICH) ? 4 : 3;
   // bf16 contraction with two column blocks: X lives as high + low tiles
   constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
   const int col = lane & 31;
@@ -458,13 +461,13 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   const int rbase = t * 32 + h * 4;
 
   // adjoint: the float64 accumulator this lane updates first at the end of
-  // the tile (entry e = wg * 64 + lane < 96 of the 3 x 32 per-cell sums),
+  // the tile (entry e = wg * 64 + lane of the NACC x 32 per-cell sums),
   // loaded now so that its latency is hidden under the tile
   double gpre = 0.0;
   if constexpr (ADJ) {
     const int e = wg * 64 + lane;
     const int k = e / 32, cc = e - k * 32;
-    if (e < 3 * 32 && active && (int64_t)c0 + cc < g.C) gpre = a.gacc[(int64_t)k * g.C + c0 + cc];
+    if (e < NACC * 32 && active && (int64_t)c0 + cc < g.C) gpre = a.gacc[(int64_t)k * g.C + c0 + cc];
   }
 
   // ---- 1. gather own rows, per 32-cell column block --------------------------
@@ -716,7 +719,9 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   (void)acc2;
 
   // ---- 4. epilogue -------------------------------------------------------------
-  float part[3] = {0.0f, 0.0f, 0.0f};
+  float part[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) part[k] = 0.0f;
   (void)gpre;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
@@ -757,6 +762,8 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
           mu = f32x4{mv[4 * q], mv[4 * q + 1], mv[4 * q + 2], mv[4 * q + 3]};
         }
       }
+      float kap[ADJ && DICH ? 4 : 1];   // adjoint with dichroic absorption: dLoss/dX_d
+      (void)kap;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int i = 4 * q + s;
@@ -768,11 +775,33 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
         if (!ADJ) {
           *o = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
         } else {
+          // lam = dLoss/dX_d (X_d = X without dichroic absorption)
           const float lam = fmaf(be[cb], prod, al[cb] * mu[s]);
-          *o = lam;
           part[0] = fmaf(mu[s], xq[s], part[0]);
           part[1] = fmaf(prod, xq[s], part[1]);
-          part[2] = fmaf(fmaf(a.dt_pre, lam, a.dt_post * mu[s]), jp[s], part[2]);
+          if constexpr (DICH) {
+            kap[s] = lam;
+          } else {
+            *o = lam;
+            part[2] = fmaf(fmaf(a.dt_pre, lam, a.dt_post * mu[s]), jp[s], part[2]);
+          }
+        }
+      }
+      if constexpr (ADJ && DICH) {
+        // dichroic absorption: X_d = D X with D scaling I + Q by exp(-xi w)
+        // and I - Q by exp(xi w), symmetric in (I, Q), so dLoss/dX = D kap;
+        // <kap, dD/dxi X> = -w (kap_I X_d,Q + kap_Q X_d,I)
+        const float wq = wdir[q];
+        part[3] = fmaf(-wq, fmaf(kap[0], xq[1], kap[1] * xq[0]), part[3]);
+        const float x = xi[cb] * wq;
+        const float pl = (kap[0] + kap[1]) * expf(-x);
+        const float mi = (kap[0] - kap[1]) * expf(x);
+        kap[0] = 0.5f * (pl + mi);
+        kap[1] = 0.5f * (pl - mi);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a.out[ld[q].off + (int64_t)s * g.C + c] = kap[s];
+          part[2] = fmaf(fmaf(a.dt_pre, kap[s], a.dt_post * mu[s]), jp[s], part[2]);
         }
       }
     }
@@ -780,7 +809,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   if (ADJ) {
     // per-cell sums over all rows: half-waves, then waves via LDS
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < NACC; ++k) {
       float v = part[k];
       v += __shfl_xor(v, 32);
       if (h == 0) s_red[(k * W + wg) * 32 + col] = v;
@@ -790,7 +819,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     // again here rather than held in registers through the tile)
     int ln = lane;
     asm volatile("" : "+v"(ln));
-    for (int e = wg * 64 + ln, u = 0; e < 3 * 32; e += W * 64, ++u) {
+    for (int e = wg * 64 + ln, u = 0; e < NACC * 32; e += W * 64, ++u) {
       const int k = e / 32, cc = e - k * 32;
       const int64_t c = (int64_t)c0 + cc;
       if (active && c < g.C) {
@@ -846,7 +875,8 @@ fused_kernel(StepArgs a, int64_t ntiles) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int h = lane >> 5;
-  const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
+  const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB,
+                                 (ADJ && EXT == kExtDich) ? 4 : 3);
   float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
   for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
   __syncthreads();
@@ -1052,7 +1082,8 @@ hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t n
 template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, int EXT = kExtNone>
 hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
-  const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB);
+  const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB,
+                                 (ADJ && EXT == kExtDich) ? 4 : 3);
   const int64_t ntiles = (a.geo.C + 32 * NB - 1) / (32 * NB);
   auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, EXT>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
@@ -1081,8 +1112,12 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count)
     return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtMix>(a, W, s, cu_count);
   }
   if (a.dich_xi != nullptr) {
-    // dichroic absorption: forward steps, the tiles of the plain step
-    if constexpr (!ADJ) {
+    // dichroic absorption: the adjoint on 32-cell tiles; forward steps on the
+    // tiles of the plain step
+    if constexpr (ADJ) {
+      if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
+      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtDich>(a, W, s, cu_count);
+    } else {
       if (W <= 4) {
         if constexpr (PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2, kExtDich>(a, W, s, cu_count);
         return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
@@ -1575,7 +1610,7 @@ __global__ void dich_xi_kernel(int64_t C, const float *__restrict__ tau, const f
 
 __global__ void gradchain_kernel(int64_t C, const float *__restrict__ tau, const float *__restrict__ alb,
                                  uint32_t flags, const double *__restrict__ gacc, float *g_tau,
-                                 float *g_alb, float *g_emis) {
+                                 float *g_alb, float *g_emis, const float *__restrict__ eta) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
        c += (int64_t)gridDim.x * blockDim.x) {
     const double t = tau[c], w = alb[c];
@@ -1595,8 +1630,15 @@ __global__ void gradchain_kernel(int64_t C, const float *__restrict__ tau, const
       dbt = da_t * (1.0 - ss) - aa * ds_t;
       dbw = da_w * (1.0 - ss) - aa * ds_w;
     }
-    if (g_tau) g_tau[c] = (float)(ga * dat + gb * dbt);
-    if (g_alb) g_alb[c] = (float)(ga * daw + gb * dbw);
+    // dichroic absorption: xi = (1 - albedo) tau eta, its sum in gacc[3 C + c]
+    double gxt = 0.0, gxw = 0.0;
+    if (eta) {
+      const double gx = gacc[3 * C + c], e = eta[c];
+      gxt = gx * (1.0 - w) * e;
+      gxw = -gx * t * e;
+    }
+    if (g_tau) g_tau[c] = (float)(ga * dat + gb * dbt + gxt);
+    if (g_alb) g_alb[c] = (float)(ga * daw + gb * dbw + gxw);
     if (g_emis) g_emis[c] = (float)ge;
   }
 }
@@ -1738,12 +1780,13 @@ hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems
   return launch_batch_step_impl(d_chans, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
 }
 
-size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint) {
+size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich) {
   if (g.Rpad / 32 > 16) return (size_t)-1;
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
   const int W = g.Rpad / 32;
-  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, W, adjoint, prec == P_F16, 1, step_nb(W, prec, adjoint));
+  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, W, adjoint, prec == P_F16, 1, step_nb(W, prec, adjoint),
+                                 adjoint && dich ? 4 : 3);
   return (size_t)L.total;
 }
 
@@ -1824,9 +1867,9 @@ hipError_t launch_dich_xi(int64_t C, const float *tau, const float *alb, const f
 
 hipError_t launch_gradchain(int64_t C, const float *tau, const float *alb, uint32_t flags,
                             const double *gacc, float *g_tau, float *g_alb, float *g_emis,
-                            hipStream_t s) {
+                            hipStream_t s, const float *eta) {
   hipLaunchKernelGGL(gradchain_kernel, dim3(grid_for(C, 256)), dim3(256), 0, s, C, tau, alb, flags,
-                     gacc, g_tau, g_alb, g_emis);
+                     gacc, g_tau, g_alb, g_emis, eta);
   return hipGetLastError();
 }
 

@@ -224,16 +224,19 @@ def _rel(a, b):
                                   (dict(nx=6, ny=5, nz=4, n_zen=2, n_az=8, bc6=(0, 0, 1, 1, 0, 0)), 8, 8),
                                   (dict(nx=5, ny=4, nz=3, n_zen=8, n_az=16), 6, 1)],
                          ids=lambda c: "%dx%dx%d-T%d-K%d" % (c[0]["nx"], c[0]["ny"], c[0]["nz"], c[1], c[2]))
-@pytest.mark.parametrize("mixed", [False, True], ids=["single", "mixture"])
-def test_adjoint3d_parity(case, precision, mixed):
+@pytest.mark.parametrize("ext", [None, "mixture", "dichroism"], ids=["single", "mixture", "dichroism"])
+def test_adjoint3d_parity(case, precision, ext):
     over, T, K = case
     spec = W.spec("beam3d", source="uniform_emis", emis_max=0.05,
-                  mixture={"kind": "hg", "g": -0.4} if mixed else None, **over)
+                  mixture={"kind": "hg", "g": -0.4} if ext == "mixture" else None,
+                  dichroism=0.8 if ext == "dichroism" else None, **over)
     med = W.medium(spec)
     med["tau"] = np.minimum(med["tau"] * 20.0, 1.0).astype(np.float32).astype(np.float64)
     solver, p3, _ = build3(spec, precision, med)
-    if mixed:
+    if ext == "mixture":
         solver.set_phase_mixture(spec["mixture"], to_dev(med["frac"], solver))
+    elif ext == "dichroism":
+        solver.set_dichroism(to_dev(med["eta"], solver))
     rng = np.random.default_rng(5)
     S0 = np.abs(rng.standard_normal(solver.shape)) * 0.1
     lamT = rng.standard_normal(solver.shape)

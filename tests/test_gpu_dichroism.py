@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import assert_close, build, to_dev, to_np, tolerance
+from gpu_common import GTOL, assert_close, build, to_dev, to_np, tolerance
+from oracle import adjoint as OA
 from oracle import lbm as OL
 
 pytestmark = pytest.mark.gpu
@@ -174,12 +175,6 @@ def test_dichroism_refusals():
     with pytest.raises(P.RTError) as ei:
         solver.set_phase_mixture(spec["mixture"], frac)
     assert ei.value.status == P.RT_EUNSUPPORTED
-    ck = solver.checkpoint_buffer(4, 2)
-    S = solver.empty_state()
-    solver.run(S, 4, ck, 2)
-    with pytest.raises(P.RTError) as ei:
-        solver.adjoint(4, ck, 2, solver.empty_state())
-    assert ei.value.status == P.RT_EUNSUPPORTED
 
 
 def test_batch_refuses_dichroic_channel():
@@ -202,3 +197,39 @@ def test_batch_refuses_dichroic_channel():
     batch.channels[0].set_dichroism(None)
     batch.run(states, 2)
     torch.cuda.synchronize()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "plain", "bf16x3", "bf16", "fp16"])
+@pytest.mark.parametrize("over, T, K", [(dict(nx=36, ny=33), 30, 6),                   # n = 8
+                                        (dict(nx=30, ny=27, n_zen=4, n_az=16), 20, 5),  # n = 64
+                                        (dict(nx=20, ny=17, n_zen=8, n_az=16), 9, 9)],  # n = 128
+                         ids=lambda v: str(v))
+def test_dichroism_adjoint_parity(precision, over, T, K):
+    """The checkpointed adjoint with dichroic absorption (the adjoint step
+    applies D to alpha mu + beta nu and sums the xi-derivative term per cell)
+    against the oracle adjoint, for the top-edge (I + DoLP) readout loss:
+    tau, albedo and emission gradients and lambda_0 to the gradient bound."""
+    spec = W.spec("adjoint256", dichroism=0.8, **over)
+    med = absorbing_medium(spec)
+    solver, oprob, _ = _with_dichroism(spec, precision, med)
+    assert oprob.eta is not None
+    S0 = np.zeros(oprob.shape)
+    ck = solver.checkpoint_buffer(T, K)
+    S = to_dev(S0, solver)
+    solver.run(S, T, ck, K)
+    ST = OL.run(S0, oprob, T)
+    _, g = OL.edge_loss(ST, oprob, 3)
+    lamT = OL.readout_transpose(g, oprob, 3)
+    ref = OA.adjoint(S0, oprob, T, lamT)
+    got = solver.adjoint(T, ck, K, to_dev(lamT, solver), want_lambda0=True)
+    for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
+        assert _rel(to_np(arr), ref[key]) < GTOL[precision], (key, _rel(to_np(arr), ref[key]))
+    # the dichroism matters at this bound: the oracle adjoint without it is
+    # far off in the tau gradient
+    oprob.eta = None
+    far = OA.adjoint(S0, oprob, T, lamT)
+    assert _rel(far["g_tau"], ref["g_tau"]) > 3 * GTOL[precision]

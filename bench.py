@@ -175,8 +175,9 @@ def extension_extras(T=20, warm=3):
     tabulated scattering matrix (P12, P34 != 0), a per-cell phase-function
     mixture (HG(0.7) and Rayleigh, fraction U[0, 1]; two contractions per
     cell) and dichroic absorption (eta U[-0.8, 0.8]; applied in the gather).
-    For the plain workload and the mixture also the checkpointed adjoint over
-    the same steps (per-step cost and adjoint / checkpointed-forward ratio)."""
+    For the plain workload, the mixture and the dichroism also the
+    checkpointed adjoint over the same steps (per-step cost and adjoint /
+    checkpointed-forward ratio)."""
     import numpy as np
     import torch
     import workloads as W
@@ -211,7 +212,7 @@ def extension_extras(T=20, warm=3):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
             out[name] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
-            if name in ("single", "mixture"):
+            if name in ("single", "mixture", "dichroism"):
                 # the checkpointed forward and its adjoint (recompute + adjoint steps)
                 K = max(1, int(math.ceil(math.sqrt(T))))
                 ck = solver.checkpoint_buffer(T, K)

@@ -98,6 +98,19 @@ def displacements(dirs, plane, courant=1.0):
         l = np.where(c > 0.5, 1.0, np.where(c < -0.5, -1.0, 0.0))
     else:
         raise ValueError(plane)
+    l = snap_integers(l)
     if np.any(np.abs(l) > 1.0 + 1e-12):
         raise ValueError("|l| > 1 per step")
     return np.asarray(l, dtype=np.float64)
+
+
+def snap_integers(l, tol=1e-12):
+    """Displacement components within tol of an integer are that integer.
+
+    cos(90 deg) evaluates to 6e-17, not 0: without this an azimuth of 90 deg
+    would carry a vanishing x displacement, a 6e-17-weight tap (Eq. 34) and
+    a place among the directions leaving through the x+ edge, although it
+    moves along the lattice axis."""
+    l = np.asarray(l, dtype=np.float64)
+    r = np.round(l)
+    return np.where(np.abs(l - r) < tol, r, l)

@@ -36,7 +36,7 @@ class Problem3D:
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.dirs = dirs
         self.n = dirs.n
-        self.shifts = courant * np.asarray(dirs.k, dtype=np.float64)
+        self.shifts = _dirs.snap_integers(courant * np.asarray(dirs.k, dtype=np.float64))
         if np.any(np.abs(self.shifts) > 1.0 + 1e-12):
             raise ValueError("|l| > 1 per step")
         self.bc = tuple(int(b) for b in bc6)

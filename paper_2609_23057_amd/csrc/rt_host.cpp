@@ -26,6 +26,16 @@ constexpr double kPi = 3.14159265358979323846;
 
 double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+// A displacement component within 1e-12 of an integer is that integer: the
+// cosine of a 90 degree azimuth evaluates to 6e-17, which would otherwise
+// give an axis-aligned direction a vanishing cross-axis displacement (a tap of
+// weight 6e-17 in Eq. 34 and a place among the directions leaving through
+// that axis's edge).
+double snap_integer(double l) {
+  const double r = std::nearbyint(l);
+  return std::fabs(l - r) < 1e-12 ? r : l;
+}
+
 // Scalar phase function normalised over 4 pi (Rayleigh: 3/(16 pi)(1 + c^2)).
 double phase_fn(int kind, double c, double g, double mix) {
   const double pr = 3.0 / (16.0 * kPi) * (1.0 + c * c);
@@ -267,7 +277,7 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
         l0 = p->courant * k[0]; l1 = p->courant * k[1];
         const double l2 = p->courant * k[2];
         if (std::fabs(l2) > 1.0 + 1e-12) { *msg = fmt("displacement per step exceeds one cell", l2); return RT_ERANGE; }
-        hp->lz[d] = std::max(-1.0, std::min(1.0, l2));
+        hp->lz[d] = std::max(-1.0, std::min(1.0, snap_integer(l2)));
       } else if (p->plane == RT_PLANE_XY) {
         l0 = p->courant * k[0]; l1 = p->courant * k[1];
       } else if (p->plane == RT_PLANE_XZ) {
@@ -287,8 +297,8 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
         *msg = fmt("displacement per step exceeds one cell", std::max(std::fabs(l0), std::fabs(l1)));
         return RT_ERANGE;
       }
-      hp->lx[d] = std::max(-1.0, std::min(1.0, l0));
-      hp->ly[d] = std::max(-1.0, std::min(1.0, l1));
+      hp->lx[d] = std::max(-1.0, std::min(1.0, snap_integer(l0)));
+      hp->ly[d] = std::max(-1.0, std::min(1.0, snap_integer(l1)));
       int m = 0;
       if (hp->lx[d] < 0) m |= 1;
       if (hp->lx[d] > 0) m |= 2;

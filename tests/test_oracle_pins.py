@@ -26,7 +26,10 @@ def _gold(name):
 
 
 def _dop(v):
-    return math.sqrt(v[1] ** 2 + v[2] ** 2 + v[3] ** 2) / v[0]
+    """Degree of polarisation of one Stokes vector, by the oracle's dop()
+    (so that the printed DOP values and closed forms below pin it too)."""
+    a = [np.array([float(x)]) for x in v]
+    return float(OL.dop(*a)[0])
 
 
 def _problem(nx=8, ny=8, n_zen=2, n_az=4, plane="xy", bc=(0, 0, 0, 0), tau=0.3,

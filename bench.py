@@ -60,10 +60,23 @@ def measured_traffic(kernel_key):
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0}
 
 
+def step_work(C, n):
+    """Algorithmic work of one fused step launch over C cells and n directions.
+
+    bytes: 32 per cell-direction (read 16 B and write 16 B of float32 Stokes
+    state) plus 12 per cell (alpha, beta, emission);
+    flops: 20 n per cell-direction, the nonzeros of the collision matrix
+    (3n x 3n for I, Q, U plus n x n for V: 10 n^2 multiply-adds per cell);
+    executed: the dense 4n x 4n contraction the matrix cores perform, 32 n per
+    cell-direction (the zero IQU-V blocks included)."""
+    return {"bytes": C * (32.0 * n + 12.0), "flops": 20.0 * n * n * C,
+            "executed_flops": 32.0 * n * n * C}
+
+
 def roofline(nbytes, flops, launch_us, precision):
     """Roofline of one fused step launch: the bound is whichever of HBM
-    traffic (8 TB/s) and the dense contraction on the matrix cores (peak of
-    the contraction dtype) takes longer at peak."""
+    traffic (8 TB/s) and the algorithmic contraction on the matrix cores (peak
+    of the contraction dtype) takes longer at peak."""
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops / (MFMA_PEAK_TFLOPS[precision] * 1e12)
     sec = launch_us * 1e-6
@@ -76,6 +89,17 @@ def roofline(nbytes, flops, launch_us, precision):
     out["bound"] = "hbm" if main is hbm else "mfma"
     out["secondary"] = dict(other)
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
 
 
 def loss_grad(out):
@@ -134,9 +158,10 @@ def cpu_baseline(spec, nsteps=3):
     C, n = spec["nx"] * spec["ny"], W.ndir(spec)
     return {"value": 2.0 * C * n * nsteps / dt, "unit": "Stokes cell-direction updates/s",
             "cores": int(threads), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "float64 NumPy oracle, %d forward steps + adjoint over them on the full "
-                      "512x512 n=32 lattice (%.1f s); host has %d logical CPUs"
-                      % (nsteps, dt, os.cpu_count() or 0)}
+                      "512x512 n=32 lattice (%.1f s); host has %d logical CPUs (%s)"
+                      % (nsteps, dt, os.cpu_count() or 0, cpu_model())}
 
 
 def precision_extras(T=20, warm=3):
@@ -159,6 +184,16 @@ def precision_extras(T=20, warm=3):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         res[prec] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
+        if prec != "plain":
+            # T + 1 launches (T - 1 fused, one collide-only, one stream), all
+            # one read and one write of the state: their mean stands for the
+            # fused kernel's launch
+            wk = step_work(C, n)
+            us = ms * 1e3 / (T + 1)
+            res[prec]["roofline"] = dict(roofline(wk["bytes"], wk["flops"], us, prec), avg_launch_us=us,
+                                         algorithmic_bytes_per_launch=wk["bytes"],
+                                         algorithmic_flops_per_launch=wk["flops"],
+                                         executed_mfma_flops_per_launch=wk["executed_flops"])
         del solver, S
         torch.cuda.empty_cache()
     for k in res:
@@ -402,6 +437,34 @@ def spectral_extras(T=200):
             "graph_speedup_forward": res["eager"]["forward_ms"] / g["forward_ms"]}
 
 
+def profile_run(name, precision, T, adjoint=False):
+    """A short run of one workload for counter and trace runs of rocprofv3:
+    a device copy of one state (reads and writes its bytes once: the
+    calibration of FETCH_SIZE and WRITE_SIZE), then T forward steps, and with
+    `adjoint` the checkpointed forward and adjoint over them."""
+    import torch
+    import workloads as W
+    spec = W.spec(name)
+    solver = make_solver(spec, precision)
+    S = solver.empty_state()
+    b = torch.empty_like(S)
+    b.copy_(S)
+    torch.cuda.synchronize()
+    _log("profile: %s %s, %d forward steps" % (name, precision, T))
+    solver.run(S, T)
+    if adjoint:
+        K = max(1, int(math.ceil(math.sqrt(T))))
+        ck = solver.checkpoint_buffer(T, K)
+        S0 = solver.empty_state()
+        solver.run(S0, T, ck, K)
+        lam = torch.rand_like(S)
+        _log("profile: adjoint over %d steps" % T)
+        solver.adjoint(T, ck, K, lam)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": name, "precision": precision, "steps": T, "adjoint": adjoint,
+                      "state_bytes": S.numel() * 4}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,6 +474,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16", "fp16", "bf16x3"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--profile", default=None, choices=("beam512", "prec1024", "adjoint256", "beam3d"),
+                    help="only a short run of this workload in --precision (for rocprofv3 runs)")
+    ap.add_argument("--profile-adjoint", action="store_true", help="with --profile: also the adjoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver build runs on a single GPU; multi-GPU runs (--gpus %d) are "
@@ -422,6 +488,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.profile:
+        profile_run(args.profile, args.precision, args.tsteps or 8, args.profile_adjoint)
+        return
     spec = W.spec("beam512")
     T = args.tsteps or spec["steps"]
     C, n = spec["nx"] * spec["ny"], W.ndir(spec)
@@ -472,8 +541,8 @@ def main():
     ms_fwd = sum(a.elapsed_time(b) for a, b in fwd_events) / len(fwd_events)
     ms_adj_est = ms_per_step - ms_fwd
     avg_fused_us = ms_fwd * 1e3 / (T + 1)
-    bytes_per_launch = C * (32.0 * n + 12.0)
-    flops_per_launch = 2.0 * (4.0 * n) ** 2 * C
+    wk = step_work(C, n)
+    bytes_per_launch, flops_per_launch = wk["bytes"], wk["flops"]
     roof = roofline(bytes_per_launch, flops_per_launch, avg_fused_us, args.precision)
 
     line = {
@@ -492,7 +561,8 @@ def main():
                          traffic=measured_traffic("fused_fwd_beam512_%s" % args.precision),
                          avg_launch_us=avg_fused_us,
                          algorithmic_bytes_per_launch=bytes_per_launch,
-                         algorithmic_flops_per_launch=flops_per_launch),
+                         algorithmic_flops_per_launch=flops_per_launch,
+                         executed_mfma_flops_per_launch=wk["executed_flops"]),
         "phases": {"forward_ms": ms_fwd, "adjoint_ms": ms_adj_est,
                    "adjoint_fwd_ratio": ms_adj_est / ms_fwd,
                    "forward_cell_dir_updates_per_s": C * n * T / (ms_fwd / 1e3)},

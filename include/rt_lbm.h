@@ -53,11 +53,14 @@ typedef enum {
 
 /* Arithmetic of the direction-pair contraction (the collision).  The state is
  * always float32; streaming, emission, absorption and the survival term are
- * always float32.  RT_FP32 uses float32 matrix cores, RT_BF16 / RT_FP16
- * round the contraction operands to bf16 / fp16 (fp16 with a per-cell
- * power-of-two scale of the state and a global one of the matrix) with
- * float32 accumulation, RT_BF16X3 splits both operands into bf16 high and low
- * parts and sums the three leading products. */
+ * always float32.  RT_FP32 uses float32 matrix cores.  RT_BF16 rounds the
+ * state operand to bf16 and holds the collision matrix as a bf16 high part
+ * plus a bf16 low part (two products; one bf16 rounding of the matrix would
+ * bias the polarisation every step in the same direction).  RT_FP16 rounds
+ * both operands to fp16 (a per-cell power-of-two scale of the state and a
+ * global one of the matrix).  RT_BF16X3 splits both operands into bf16 high
+ * and low parts and sums the three leading products.  All accumulate in
+ * float32. */
 typedef enum { RT_FP32 = 0, RT_BF16 = 1, RT_FP16 = 2, RT_BF16X3 = 3 } rt_precision;
 
 /* Zenith nodes: equal-area cos(theta) midpoints arccos(1 - (2i+1)/n_zen)
@@ -145,6 +148,24 @@ typedef struct {
   const double *table;        /* host [n_table][7] for RT_PHASE_TABLE, else NULL; copied by rt_init */
   int32_t nz;                 /* layers of an RT_PLANE_3D lattice (>= 1); 0 or 1 for the 2-D planes */
   int32_t bc_z[2];            /* rt_bc of the z- and z+ faces (RT_PLANE_3D) */
+  /* Explicit direction set (Sec. 2.1.1: the direction grid, its solid-angle
+   * weights, and the lattice displacement of Eq. 33); each NULL keeps the
+   * rule above.  Host arrays, copied by rt_init.  n = n_zen * n_az is the
+   * number of directions either way; direction d keeps index d.
+   *   dir_xyz     [n][3] unit vectors k (polar axis +z), none along the
+   *               axis (no meridian plane there); replaces the zenith /
+   *               azimuth grid; the meridian frame is e_phi along increasing
+   *               azimuth, e_theta = e_phi x k
+   *   dir_domega  [n] solid angles > 0, the weights of the Eq. 17
+   *               normalisation (default 4 pi / n)
+   *   shift       [n][2] ([n][3] on RT_PLANE_3D) displacement per step in
+   *               cells, |l| <= 1 per axis (RT_ERANGE otherwise); replaces
+   *               the plane rule and decides which directions leave through
+   *               each edge (components within 1e-12 of an integer are that
+   *               integer) */
+  const double *dir_xyz;
+  const double *dir_domega;
+  const double *shift;
 } rt_problem;
 
 /* ---- host-only helpers (no device needed) ------------------------------ */
@@ -192,6 +213,23 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
  * stream; RT_ERANGE if some cell has 1 - tau_sca < 0 (Eq. 31). */
 rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, const float *d_emis,
                         const float *h_jprof, const float *h_inflow);
+
+/* Inflow radiance per edge cell of a 2-D lattice (the boundary sources of
+ * the problem statement; Sec. 2.1.7 edges with a prescribed radiance):
+ * d_inflow is device float32 [2 nx + 2 ny][n][4], the cells of the x- edge
+ * (y = 0 .. ny-1), then the x+ edge (y), the y- edge (x = 0 .. nx-1) and the
+ * y+ edge (x), each with the Stokes vector entering in every direction; it
+ * is copied (the caller keeps ownership).  A tap of the pull (Eq. 34) that
+ * falls outside the lattice reads the edge it crossed (a y edge before an x
+ * edge) at the cell it lies beyond: its x on a y edge, clamped to the
+ * lattice at the corners, its y on an x edge.  Only edges of kind
+ * RT_BC_INFLOW use their cells' values (the others stay zero).  Replaces the
+ * uniform radiance rt_set_medium set; a later rt_set_medium replaces it in
+ * turn.  Synchronises the stream (the values are checked).  Errors:
+ * RT_EINVAL for NULL or a non-finite value, RT_ESTATE before rt_set_medium,
+ * RT_EUNSUPPORTED on an RT_PLANE_3D lattice (whose faces take uniform
+ * radiance from rt_set_medium). */
+rt_status rt_set_inflow(rt_ctx *c, const float *d_inflow);
 
 /* Per-cell mixture of two phase functions.  With it set, the scattered part
  * of the collision becomes beta ((1 - f) M X + f M2 X): M is the context's

@@ -96,7 +96,7 @@ def edge_loss_of(params, base_prob, S0, nsteps, edge):
     tau, alb, em = params
     p = lbm.Problem(base_prob.nx, base_prob.ny, base_prob.dirs, base_prob.shifts,
                     base_prob.M, base_prob.dt, base_prob.bc, tau, alb, em,
-                    base_prob.jprof, base_prob.inflow, base_prob.abs_taylor,
+                    base_prob.jprof, base_prob.inflow_cells, base_prob.abs_taylor,
                     base_prob.scat_exp, base_prob.fused_taylor, M2=base_prob.M2, frac=base_prob.frac,
                     dichroism=base_prob.eta)
     S = lbm.run(S0, p, nsteps)

@@ -69,6 +69,37 @@ class DirectionSet:
         self.domega = np.full(self.n, 4.0 * np.pi / self.n)
 
 
+class VectorDirectionSet:
+    """An explicit direction set: n unit vectors k (polar axis +z) with their
+    solid angles (the weights of the Eq. 17 normalisation; 4 pi / n when not
+    given, Sec. 2.1.1).  Zenith and azimuth are those of k; the meridian
+    frame is built from them as for the grid (e_theta along increasing
+    zenith, e_phi along increasing azimuth).  A vector along the polar axis
+    has no meridian plane and is refused."""
+
+    def __init__(self, k, domega=None):
+        k = np.asarray(k, dtype=np.float64).reshape(-1, 3)
+        if np.any(~np.isfinite(k)) or np.any(np.abs(np.linalg.norm(k, axis=1) - 1.0) > 1e-9):
+            raise ValueError("direction vectors must be finite unit vectors")
+        self.n = k.shape[0]
+        self.n_zen, self.n_az = 1, self.n
+        self.theta = np.arccos(np.clip(k[:, 2], -1.0, 1.0))
+        self.phi = np.arctan2(k[:, 1], k[:, 0])
+        if np.any(np.sin(self.theta) < 1e-9):
+            raise ValueError("a direction along the polar axis has no meridian plane")
+        st, ct = np.sin(self.theta), np.cos(self.theta)
+        sp, cp = np.sin(self.phi), np.cos(self.phi)
+        self.k = k.copy()
+        self.e_theta = np.stack([ct * cp, ct * sp, -st], axis=1)
+        self.e_phi = np.stack([-sp, cp, np.zeros_like(sp)], axis=1)
+        if domega is None:
+            self.domega = np.full(self.n, 4.0 * np.pi / self.n)
+        else:
+            self.domega = np.asarray(domega, dtype=np.float64).reshape(self.n).copy()
+            if np.any(~np.isfinite(self.domega)) or np.any(self.domega <= 0):
+                raise ValueError("solid angles must be finite and positive")
+
+
 def make_directions(n_zen, n_az, zen_rule="equal_area", az_offset_deg=0.0,
                     zen_explicit_deg=None):
     th = zenith_nodes(n_zen, zen_rule, zen_explicit_deg)

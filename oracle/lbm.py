@@ -64,7 +64,17 @@ class Problem:
         self.jprof = np.asarray(jprof, dtype=np.float64).reshape(self.n, 4)
         if inflow is None:
             inflow = np.zeros((4, self.n, 4))
-        self.inflow = np.asarray(inflow, dtype=np.float64).reshape(4, self.n, 4)
+        inflow = np.asarray(inflow, dtype=np.float64)
+        # inflow radiance: uniform along each edge [4][n][4], or per edge cell
+        # [2 nx + 2 ny][n][4] in the order x- (y = 0..ny-1), x+ (y), y- (x =
+        # 0..nx-1), y+ (x); stored per edge cell either way
+        npe = 2 * (self.nx + self.ny)
+        if inflow.size == 4 * self.n * 4 and inflow.size != npe * self.n * 4:
+            inflow = inflow.reshape(4, self.n, 4)
+            counts = (self.ny, self.ny, self.nx, self.nx)
+            inflow = np.concatenate([np.repeat(inflow[e:e + 1], counts[e], axis=0) for e in range(4)])
+        self.inflow_cells = inflow.reshape(npe, self.n, 4)
+        self.edge_base = (0, self.ny, 2 * self.ny, 2 * self.ny + self.nx)
         self.abs_taylor = bool(abs_taylor)
         self.scat_exp = bool(scat_exp)
         self.fused_taylor = bool(fused_taylor)
@@ -182,7 +192,9 @@ def _fetch(plane, xs, ys, d, prob):
 
     Periodic axes wrap.  A point still outside the lattice is a ghost: if it
     is outside in y the y edge it crossed decides, otherwise the x edge;
-    absorbing ghosts are zero, inflow ghosts carry inflow[edge, d, :].
+    absorbing ghosts are zero, inflow ghosts carry the inflow radiance of
+    direction d at the edge cell the point lies beyond (its x on a y edge,
+    clamped to the lattice at the corners; its y on an x edge).
     """
     nx, ny = prob.nx, prob.ny
     if prob.bc[EDGE_XM] == BC_PERIODIC:
@@ -199,7 +211,8 @@ def _fetch(plane, xs, ys, d, prob):
     for mask, edge in ((above, EDGE_YP), (below, EDGE_YM), (left, EDGE_XM),
                        (right, EDGE_XP)):
         if prob.bc[edge] == BC_INFLOW and np.any(mask):
-            vals[:, mask] = prob.inflow[edge, d, :, None]
+            pos = np.clip(xs[mask], 0, nx - 1) if edge in (EDGE_YM, EDGE_YP) else ys[mask]
+            vals[:, mask] = prob.inflow_cells[prob.edge_base[edge] + pos, d, :].T
     return vals
 
 
@@ -391,9 +404,19 @@ def readout_transpose(g, prob, edge):
 
 def make_problem(spec, medium):
     """Build a Problem from a workload spec and a medium (see workloads)."""
-    dirs = _dirs.make_directions(spec["n_zen"], spec["n_az"], spec.get("zen_rule", "equal_area"),
-                                 spec.get("az_offset_deg", 0.0), spec.get("zen_explicit_deg"))
-    shifts = _dirs.displacements(dirs, spec["plane"], spec.get("courant", 1.0))
+    if spec.get("dir_xyz") is not None:
+        dirs = _dirs.VectorDirectionSet(spec["dir_xyz"], spec.get("dir_domega"))
+    else:
+        dirs = _dirs.make_directions(spec["n_zen"], spec["n_az"], spec.get("zen_rule", "equal_area"),
+                                     spec.get("az_offset_deg", 0.0), spec.get("zen_explicit_deg"))
+        if spec.get("dir_domega") is not None:
+            dirs.domega = np.asarray(spec["dir_domega"], dtype=np.float64).reshape(dirs.n).copy()
+    if spec.get("shift") is not None:
+        shifts = _dirs.snap_integers(np.asarray(spec["shift"], dtype=np.float64).reshape(dirs.n, 2))
+        if np.any(np.abs(shifts) > 1.0 + 1e-12):
+            raise ValueError("|l| > 1 per step")
+    else:
+        shifts = _dirs.displacements(dirs, spec["plane"], spec.get("courant", 1.0))
     ph = spec.get("phase", {"kind": "rayleigh"})
     M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
                                 ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),

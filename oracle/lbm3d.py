@@ -121,8 +121,13 @@ def run(S0, prob, nsteps, keep=False):
 
 def make_problem(spec, medium):
     """A Problem3D from a workload spec (plane "3d") and its medium."""
-    dirs = _dirs.make_directions(spec["n_zen"], spec["n_az"], spec.get("zen_rule", "equal_area"),
-                                 spec.get("az_offset_deg", 0.0), spec.get("zen_explicit_deg"))
+    if spec.get("dir_xyz") is not None:
+        dirs = _dirs.VectorDirectionSet(spec["dir_xyz"], spec.get("dir_domega"))
+    else:
+        dirs = _dirs.make_directions(spec["n_zen"], spec["n_az"], spec.get("zen_rule", "equal_area"),
+                                     spec.get("az_offset_deg", 0.0), spec.get("zen_explicit_deg"))
+        if spec.get("dir_domega") is not None:
+            dirs.domega = np.asarray(spec["dir_domega"], dtype=np.float64).reshape(dirs.n).copy()
     ph = spec.get("phase", {"kind": "rayleigh"})
     M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
                                 ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
@@ -133,11 +138,19 @@ def make_problem(spec, medium):
         M2 = _phase.collision_matrix(dirs, ph2.get("kind", "rayleigh"), ph2.get("g", 0.0),
                                      ph2.get("mix_ray", 1.0), spec.get("renorm_irow", False),
                                      spec.get("scalar", False), ph2.get("table"))
-    return Problem3D(spec["nx"], spec["ny"], spec["nz"], dirs, spec.get("courant", 1.0), spec["bc6"], M,
+    p3 = Problem3D(spec["nx"], spec["ny"], spec["nz"], dirs, spec.get("courant", 1.0), spec["bc6"], M,
                      spec.get("dt", 1.0), medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
                      medium.get("inflow"), abs_taylor=spec.get("abs_taylor", False),
                      scat_exp=spec.get("scat_exp", False), fused_taylor=spec.get("fused_taylor", False),
                      M2=M2, frac=medium.get("frac"), dichroism=medium.get("eta"))
+    if spec.get("shift") is not None:
+        # explicit displacement per step replaces courant * k
+        sh = _dirs.snap_integers(np.asarray(spec["shift"], dtype=np.float64).reshape(dirs.n, 3))
+        if np.any(np.abs(sh) > 1.0 + 1e-12):
+            raise ValueError("|l| > 1 per step")
+        p3.shifts = sh
+        p3.flat.shifts = sh[:, :2]
+    return p3
 
 
 def stream_transpose(G, prob):

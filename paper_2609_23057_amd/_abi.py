@@ -31,7 +31,8 @@ class RtProblem(ctypes.Structure):
                 ("bc", c_int32 * 4), ("phase", c_int32), ("g", c_double), ("mix_ray", c_double),
                 ("dt", c_double), ("flags", c_uint32), ("precision", c_int32),
                 ("n_table", c_int32), ("table", POINTER(c_double)),
-                ("nz", c_int32), ("bc_z", c_int32 * 2)]
+                ("nz", c_int32), ("bc_z", c_int32 * 2),
+                ("dir_xyz", POINTER(c_double)), ("dir_domega", POINTER(c_double)), ("shift", POINTER(c_double))]
 
 
 class RTError(RuntimeError):
@@ -63,6 +64,7 @@ _SIGS = {
     "rt_set_medium": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_set_phase_mixture": (c_int32, [c_void_p, c_int32, c_double, c_double, c_void_p]),
     "rt_set_dichroism": (c_int32, [c_void_p, c_void_p]),
+    "rt_set_inflow": (c_int32, [c_void_p, c_void_p]),
     "rt_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_stream": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
@@ -154,6 +156,10 @@ def rt_set_phase_mixture(ctx, phase2, g2, mix_ray2, d_frac):
 def rt_set_dichroism(ctx, d_eta):
     """d_eta: device [ny][nx] float32 with |eta| < 1, or None to remove it."""
     _check(_lib.rt_set_dichroism(ctx, d_eta), ctx)
+
+
+def rt_set_inflow(ctx, d_inflow):
+    _check(_lib.rt_set_inflow(ctx, d_inflow), ctx)
 
 
 def rt_step(ctx, d_S_in, d_S_out):

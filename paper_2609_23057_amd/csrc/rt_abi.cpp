@@ -32,7 +32,7 @@ struct Layout {
   size_t taps, taps3, taps3_rev, ghost_zero, outdirs, MT;   // MT: float32 M transposed, for the plain path
   size_t tiles_fwd32, tiles_adj32, tiles_fwd, tiles_adj;
   size_t frag_fwd32, frag_adj32, frag_fwd, frag_fwd_lo, frag_adj, frag_adj_lo;
-  size_t jrow, ghost;             // set by rt_set_medium
+  size_t jrow, ghost, ghost3;     // set by rt_set_medium (ghost3: the 3-D faces)
   size_t mix_tiles, mix_frag, mix_frag_lo, mix_MT, frac;   // phase mixture (rt_set_phase_mixture)
   size_t mix_tiles_adj, mix_frag_adj, mix_frag_adj_lo;       // its transpose, for the adjoint
   size_t mix_tiles_bytes, mix_frag_bytes;
@@ -71,7 +71,7 @@ void pack_all(const HostPlan &hp, int prec, Packed *pk) {
   pk->a_scale = scale;
   pack_fragments(hp, false, kind, scale, false, &pk->t_fwd, &pk->f_fwd);
   pack_fragments(hp, true, kind, scale, false, &pk->t_adj, &pk->f_adj);
-  if (prec == RT_BF16X3) {
+  if (prec == RT_BF16X3 || prec == RT_BF16) {
     pack_fragments(hp, false, FRAG_BF16, 1.0, true, &dummy, &pk->f_fwd_lo);
     pack_fragments(hp, true, FRAG_BF16, 1.0, true, &dummy, &pk->f_adj_lo);
   }
@@ -107,7 +107,12 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   L.frag_adj_lo = take(pk.f_adj_lo.size());
   L.tables_bytes = off - L.tables;
   L.jrow = take(hp.Rpad * sizeof(float));
-  L.ghost = take(7 * hp.Rpad * sizeof(float));   // 4 edges (6 faces in 3-D) + zero rows
+  // 2-D ghost radiance, one row of Rpad floats per edge cell (x- edge y =
+  // 0..ny-1, x+ edge, y- edge x = 0..nx-1, y+ edge) and a row of zeros; a
+  // 3-D context keeps it zero (its fused kernels' taps stay inside) and has
+  // one row per face in ghost3 (6 faces + zeros)
+  L.ghost = take((size_t)(2 * ((size_t)hp.nx + hp.ny) + 1) * hp.Rpad * sizeof(float));
+  L.ghost3 = take(7 * hp.Rpad * sizeof(float));
   // phase mixture: tile ranges and dense A fragments of the second matrix and
   // of its transpose in the contraction precision (float32 for the plain path,
   // whose adjoint replays on the fused float32 kernels), the plain path's
@@ -118,7 +123,7 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
     const int kstep = f32 ? 8 : 16;
     L.mix_frag_bytes = ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16;
     L.mix_tiles_bytes = ntile * sizeof(TileRange);
-    const size_t lo = (!f32 && prec == RT_BF16X3) ? L.mix_frag_bytes : 0;
+    const size_t lo = (!f32 && (prec == RT_BF16X3 || prec == RT_BF16)) ? L.mix_frag_bytes : 0;
     L.mix_tiles = take(L.mix_tiles_bytes);
     L.mix_frag = take(L.mix_frag_bytes);
     L.mix_frag_lo = take(lo);
@@ -158,6 +163,7 @@ struct rt_ctx {
   rt_problem prob{};
   std::vector<double> zen;
   std::vector<double> table;   // copy of a tabulated scattering matrix
+  std::vector<double> dir_xyz, dir_domega, shift;   // copies of an explicit direction set
   HostPlan hp;
   Packed pk;
   Layout L{};
@@ -165,7 +171,10 @@ struct rt_ctx {
   char *ws = nullptr;
   Geometry geo{};
   std::vector<uint8_t> host_tables;
-  std::vector<float> host_medium;  // jrow + ghost staging
+  // host staging of the asynchronous uploads of rt_set_medium / rt_set_inflow
+  // (kept here so that they outlive the copies): 2-D ghost table, emission
+  // rows, 3-D face table
+  std::vector<float> host_medium, host_jrow, host_ghost3;
   std::vector<float> host_dich_w;  // sin^2 theta per direction (staging)
   int nout[6] = {0, 0, 0, 0, 0, 0};
   bool medium_set = false;
@@ -176,6 +185,7 @@ struct rt_ctx {
   Stream3Args s3rev{};    // the transpose of its streaming (the adjoint's reverse pull)
   int prec = 0;
   int cu_count = 256;
+  int device = 0;     // the HIP device current at rt_init
   std::string err;
 
   template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -352,6 +362,19 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     c->prob.table = nullptr;
     c->prob.n_table = 0;
   }
+  {
+    // explicit direction set: the context keeps its own copies
+    const size_t n = (size_t)p->n_zen * p->n_az;
+    const size_t dim = p->plane == RT_PLANE_3D ? 3 : 2;
+    auto keep = [](const double *src, size_t count, std::vector<double> &v) -> const double * {
+      if (!src) return nullptr;
+      v.assign(src, src + count);
+      return v.data();
+    };
+    c->prob.dir_xyz = keep(p->dir_xyz, 3 * n, c->dir_xyz);
+    c->prob.dir_domega = keep(p->dir_domega, n, c->dir_domega);
+    c->prob.shift = keep(p->shift, dim * n, c->shift);
+  }
   std::string msg;
   st = plan_for(&c->prob, &c->hp, &c->pk, &c->L, &msg);
   if (st != RT_OK) {
@@ -377,6 +400,7 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     return set_err(RT_EUNSUPPORTED, "problem does not fit the fused kernel's LDS budget");
   }
   c->cu_count = prop.multiProcessorCount;
+  c->device = dev;
 
   // host tables
   std::vector<uint8_t> &tb = c->host_tables;
@@ -435,7 +459,7 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
     c->three_d = true;
     c->s3 = Stream3Args{c->geo.C, hp.nx, hp.ny_lattice, hp.nz, hp.n, hp.Rpad, p->bc[0] == RT_BC_PERIODIC,
                         p->bc[2] == RT_BC_PERIODIC, p->bc_z[0] == RT_BC_PERIODIC,
-                        c->at<DirTaps3>(c->L.taps3), c->at<float>(c->L.ghost)};
+                        c->at<DirTaps3>(c->L.taps3), c->at<float>(c->L.ghost3)};
     c->s3rev = c->s3;
     c->s3rev.taps = c->at<DirTaps3>(c->L.taps3_rev);
     c->s3rev.ghost = c->at<float>(c->L.ghost_zero);
@@ -475,36 +499,86 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
   return RT_OK;
 }
 
+// First ghost row of a 2-D edge (rows run along the edge: y for the x
+// edges, x for the y edges) and the row count of the table (the zero row last).
+static int64_t edge_row0(const rt_ctx *c, int e) {
+  const int64_t nx = c->geo.nx, ny = c->geo.ny;
+  return e == 0 ? 0 : (e == 1 ? ny : (e == 2 ? 2 * ny : 2 * ny + nx));
+}
+static int64_t ghost_rows(const rt_ctx *c) { return 2 * ((int64_t)c->geo.nx + c->geo.ny) + 1; }
+
+// Uploads the 2-D ghost table from per-edge-cell radiance src[cell][n][4]
+// (cells in edge-row order); rows of edges that are not inflow stay zero.
+static rt_status upload_ghost2d(rt_ctx *c, const float *src) {
+  const int n = c->hp.n, Rp = c->hp.Rpad;
+  std::vector<float> &hm = c->host_medium;
+  hm.assign((size_t)ghost_rows(c) * Rp, 0.0f);
+  for (int e = 0; e < 4; ++e) {
+    if (c->prob.bc[e] != RT_BC_INFLOW) continue;
+    const int64_t r0 = edge_row0(c, e), cnt = e < 2 ? c->geo.ny : c->geo.nx;
+    for (int64_t k = 0; k < cnt; ++k)
+      for (int d = 0; d < n; ++d)
+        for (int s = 0; s < 4; ++s) {
+          const float v = src ? src[((r0 + k) * n + d) * 4 + s] : 0.0f;
+          if (!std::isfinite(v)) return c->fail(RT_EINVAL, "inflow radiance not finite");
+          hm[(size_t)(r0 + k) * Rp + gemm_row(n, d, s)] = v;
+        }
+  }
+  return c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data(), hm.size() * sizeof(float), hipMemcpyHostToDevice,
+                               c->stream), "upload inflow");
+}
+
 rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, const float *d_emis,
                         const float *h_jprof, const float *h_inflow) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_tau || !d_albedo || !d_emis || !h_jprof) return c->fail(RT_EINVAL, "NULL medium pointer");
   const HostPlan &hp = c->hp;
   const int n = hp.n, Rp = hp.Rpad;
-  std::vector<float> &hm = c->host_medium;
-  hm.assign(Rp + 7 * Rp, 0.0f);
+  std::vector<float> &jrow = c->host_jrow, &g3 = c->host_ghost3;
+  jrow.assign(Rp, 0.0f);
+  g3.assign(7 * Rp, 0.0f);
   for (int d = 0; d < n; ++d)
     for (int s = 0; s < 4; ++s) {
       const float v = h_jprof[4 * d + s];
       if (!std::isfinite(v)) return c->fail(RT_EINVAL, "emission profile not finite");
-      hm[gemm_row(n, d, s)] = v;
+      jrow[gemm_row(n, d, s)] = v;
     }
-  const int nfaces = c->three_d ? 6 : 4;
-  for (int e = 0; e < nfaces; ++e) {
-    const int bc = e < 4 ? c->prob.bc[e] : c->prob.bc_z[e - 4];
-    for (int d = 0; d < n; ++d)
-      for (int s = 0; s < 4; ++s) {
-        const float v = h_inflow ? h_inflow[(e * n + d) * 4 + s] : 0.0f;
-        if (!std::isfinite(v)) return c->fail(RT_EINVAL, "inflow radiance not finite");
-        hm[Rp + e * Rp + gemm_row(n, d, s)] = (bc == RT_BC_INFLOW) ? v : 0.0f;
+  rt_status st = RT_OK;
+  if (c->three_d) {
+    for (int e = 0; e < 6; ++e) {
+      const int bc = e < 4 ? c->prob.bc[e] : c->prob.bc_z[e - 4];
+      for (int d = 0; d < n; ++d)
+        for (int s = 0; s < 4; ++s) {
+          const float v = h_inflow ? h_inflow[(e * n + d) * 4 + s] : 0.0f;
+          if (!std::isfinite(v)) return c->fail(RT_EINVAL, "inflow radiance not finite");
+          g3[e * Rp + gemm_row(n, d, s)] = (bc == RT_BC_INFLOW) ? v : 0.0f;
+        }
+    }
+    // the 2-D table of a 3-D context only ever supplies zeros (taps of weight
+    // zero next to the lattice's first and last cells)
+    c->host_medium.assign((size_t)ghost_rows(c) * Rp, 0.0f);
+    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, c->host_medium.data(), c->host_medium.size() * sizeof(float),
+                               hipMemcpyHostToDevice, c->stream), "upload inflow");
+  } else {
+    // the radiance of each edge, the same at every cell of the edge
+    std::vector<float> cells;
+    if (h_inflow) {
+      cells.assign((size_t)(ghost_rows(c) - 1) * n * 4, 0.0f);
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r0 = edge_row0(c, e), cnt = e < 2 ? c->geo.ny : c->geo.nx;
+        for (int64_t k = 0; k < cnt; ++k)
+          std::memcpy(&cells[(size_t)(r0 + k) * n * 4], h_inflow + (size_t)e * n * 4, n * 4 * sizeof(float));
       }
+    }
+    st = upload_ghost2d(c, h_inflow ? cells.data() : nullptr);
   }
   static_assert(sizeof(float) == 4, "float");
-  rt_status st = c->hip(hipMemcpyAsync(c->ws + c->L.jrow, hm.data(), Rp * sizeof(float),
-                                       hipMemcpyHostToDevice, c->stream), "upload jprof");
   if (st == RT_OK)
-    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost, hm.data() + Rp, 7 * Rp * sizeof(float),
-                               hipMemcpyHostToDevice, c->stream), "upload inflow");
+    st = c->hip(hipMemcpyAsync(c->ws + c->L.jrow, jrow.data(), Rp * sizeof(float), hipMemcpyHostToDevice,
+                               c->stream), "upload jprof");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(c->ws + c->L.ghost3, g3.data(), g3.size() * sizeof(float), hipMemcpyHostToDevice,
+                               c->stream), "upload inflow");
   int *bad = c->at<int>(c->L.bad);
   if (st == RT_OK) st = c->hip(hipMemsetAsync(bad, 0, sizeof(int), c->stream), "clear counter");
   if (st == RT_OK)
@@ -530,6 +604,21 @@ rt_status rt_set_medium(rt_ctx *c, const float *d_tau, const float *d_albedo, co
     if (st != RT_OK) return st;
   }
   return RT_OK;
+}
+
+rt_status rt_set_inflow(rt_ctx *c, const float *d_inflow) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_inflow) return c->fail(RT_EINVAL, "NULL inflow pointer");
+  if (c->three_d) return c->fail(RT_EUNSUPPORTED, "inflow per edge cell is for 2-D lattices (3-D faces: rt_set_medium)");
+  if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_inflow before rt_set_medium");
+  const size_t count = (size_t)(ghost_rows(c) - 1) * c->hp.n * 4;
+  std::vector<float> h(count);
+  rt_status st = c->hip(hipMemcpyAsync(h.data(), d_inflow, count * sizeof(float), hipMemcpyDeviceToHost, c->stream),
+                        "read inflow");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "read inflow");
+  if (st == RT_OK) st = upload_ghost2d(c, h.data());
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "upload inflow");
+  return st;
 }
 
 rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac) {
@@ -583,12 +672,12 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
     const double sc = pr == RT_FP16 ? c->pk.a_scale : 1.0;
     pack_fragments(hp2, false, kind, sc, false, &tiles, &frag);
     pack_fragments(hp2, true, kind, sc, false, &tiles_adj, &frag_adj);
-    if (pr == RT_BF16X3) {
+    if (pr == RT_BF16X3 || pr == RT_BF16) {
       std::vector<TileRange> unused;
       pack_fragments(hp2, false, FRAG_BF16, 1.0, true, &unused, &frag_lo);
       pack_fragments(hp2, true, FRAG_BF16, 1.0, true, &unused, &frag_adj_lo);
     }
-    const size_t cap_lo = pr == RT_BF16X3 ? L.mix_frag_bytes : 0;
+    const size_t cap_lo = (pr == RT_BF16X3 || pr == RT_BF16) ? L.mix_frag_bytes : 0;
     if (frag.size() > L.mix_frag_bytes || frag_adj.size() > L.mix_frag_bytes ||
         tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes ||
         tiles_adj.size() * sizeof(TileRange) > L.mix_tiles_bytes || frag_lo.size() > cap_lo ||

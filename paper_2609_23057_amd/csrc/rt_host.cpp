@@ -222,6 +222,36 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
     *msg = "RT_FUSED_TAYLOR excludes RT_ABS_TAYLOR and RT_SCAT_EXP"; return RT_EINVAL;
   }
   if (p->precision < 0 || p->precision > 3) { *msg = "precision out of range"; return RT_EINVAL; }
+  // explicit direction set
+  if (p->dir_xyz) {
+    for (long long d = 0; d < n; ++d) {
+      const double *k = p->dir_xyz + 3 * d;
+      if (!(std::isfinite(k[0]) && std::isfinite(k[1]) && std::isfinite(k[2]))) {
+        *msg = fmt("dir_xyz not finite for direction", (double)d); return RT_EINVAL;
+      }
+      if (std::fabs(std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) - 1.0) > 1e-9) {
+        *msg = fmt("dir_xyz is not a unit vector for direction", (double)d); return RT_EINVAL;
+      }
+      if (std::hypot(k[0], k[1]) < 1e-9) {
+        *msg = fmt("dir_xyz along the polar axis (no meridian plane) for direction", (double)d); return RT_EINVAL;
+      }
+    }
+  }
+  if (p->dir_domega) {
+    for (long long d = 0; d < n; ++d)
+      if (!(std::isfinite(p->dir_domega[d]) && p->dir_domega[d] > 0.0)) {
+        *msg = fmt("dir_domega must be finite and > 0; direction", (double)d); return RT_EINVAL;
+      }
+  }
+  if (p->shift) {
+    const int dim = three_d ? 3 : 2;
+    for (long long i = 0; i < n * dim; ++i) {
+      if (!std::isfinite(p->shift[i])) { *msg = "shift not finite"; return RT_EINVAL; }
+      if (std::fabs(p->shift[i]) > 1.0 + 1e-12) {
+        *msg = fmt("shift: displacement per step exceeds one cell", p->shift[i]); return RT_ERANGE;
+      }
+    }
+  }
   if ((p->flags & RT_PLAIN) && p->precision != RT_FP32) {
     *msg = "RT_PLAIN is a float32 path"; return RT_EUNSUPPORTED;
   }
@@ -253,6 +283,7 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
   hp->theta.resize(n);
   hp->phi.resize(n);
   hp->domega.assign(n, 4.0 * kPi / n);
+  if (p->dir_domega) hp->domega.assign(p->dir_domega, p->dir_domega + n);
   hp->kvec.resize(3 * n);
   hp->eth.resize(3 * n);
   hp->eph.resize(3 * n);
@@ -263,13 +294,20 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
   for (int i = 0; i < nz; ++i) {
     for (int j = 0; j < na; ++j) {
       const int d = i * na + j;
-      const double th = zen[i];
-      const double ph = (p->az_offset_deg + 360.0 * j / na) * kPi / 180.0;
-      hp->theta[d] = th;
-      hp->phi[d] = ph;
-      const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
       double *k = &hp->kvec[3 * d], *et = &hp->eth[3 * d], *ep = &hp->eph[3 * d];
-      k[0] = st * cp; k[1] = st * sp; k[2] = ct;
+      if (p->dir_xyz) {
+        std::memcpy(k, p->dir_xyz + 3 * d, 3 * sizeof(double));
+      } else {
+        const double th = zen[i];
+        const double ph = (p->az_offset_deg + 360.0 * j / na) * kPi / 180.0;
+        k[0] = std::sin(th) * std::cos(ph); k[1] = std::sin(th) * std::sin(ph); k[2] = std::cos(th);
+      }
+      // the meridian frame from k, the same for a grid direction and an
+      // explicit one (e_phi along increasing azimuth, e_theta = e_phi x k)
+      const double st = std::hypot(k[0], k[1]), ct = k[2];
+      const double cp = k[0] / st, sp = k[1] / st;
+      hp->theta[d] = std::atan2(st, ct);
+      hp->phi[d] = std::atan2(k[1], k[0]);
       et[0] = ct * cp; et[1] = ct * sp; et[2] = -st;
       ep[0] = -sp; ep[1] = cp; ep[2] = 0.0;
       double l0, l1;
@@ -292,6 +330,12 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
           l[a] = c[a] > 0.5 ? 1.0 : (c[a] < -0.5 ? -1.0 : 0.0);
         }
         l0 = l[0]; l1 = l[1];
+      }
+      if (p->shift) {
+        const int dim = p->plane == RT_PLANE_3D ? 3 : 2;
+        l0 = p->shift[dim * d];
+        l1 = p->shift[dim * d + 1];
+        if (dim == 3) hp->lz[d] = std::max(-1.0, std::min(1.0, snap_integer(p->shift[dim * d + 2])));
       }
       if (std::fabs(l0) > 1.0 + 1e-12 || std::fabs(l1) > 1.0 + 1e-12) {
         *msg = fmt("displacement per step exceeds one cell", std::max(std::fabs(l0), std::fabs(l1)));

@@ -27,7 +27,7 @@ struct StepArgs {
   float dt_pre;            // dt * e: emission added before the collision
   float dt_post;           // dt * (1 - e): emission added after it (fused Taylor)
   const uint4 *frag;       // A fragments (M for forward, M^T for adjoint)
-  const uint4 *frag_lo;    // low bf16 parts for BF16X3
+  const uint4 *frag_lo;    // low bf16 parts of A for BF16 and BF16X3
   const TileRange *tiles;  // [Rpad / 32]
   float a_scale_inv;       // 1 / global scale of A (FP16)
   // forward
@@ -41,7 +41,7 @@ struct StepArgs {
   // M with weight 1 - frac[c] and M2 with weight frac[c]; the adjoint step
   // takes M2^T here as it takes M^T in frag / tiles
   const uint4 *frag2;      // A fragments of M2 (M2^T), in the contraction precision
-  const uint4 *frag2_lo;   // bf16x3: their low parts
+  const uint4 *frag2_lo;   // bf16 and bf16x3: their low parts
   const TileRange *tiles2; // [Rpad / 32]
   const float *frac;       // [C]
   const float *MT2;        // plain path: float32 M2 transposed [R][R] (row k holds M2[r][k] for all r)
@@ -133,7 +133,7 @@ hipError_t launch_readout_face(int64_t C, const FaceMap &f, const float *S, cons
 hipError_t launch_readout_face_adjoint(int64_t C, const FaceMap &f, const int32_t *dirs, int nout,
                                        const float *gout, float *lam, hipStream_t s);
 
-// Plain float32 path: separate streaming and vector-ALU collision.// Plain float32 path: separate streaming and vector-ALU collision.
+// Plain float32 path: separate streaming and vector-ALU collision.
 hipError_t launch_stream(const StepArgs &a, const float *in, float *out, hipStream_t s);
 hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *in, float *out,
                                hipStream_t s);

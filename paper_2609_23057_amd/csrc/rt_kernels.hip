@@ -141,7 +141,15 @@ __device__ __forceinline__ TapIdx tap_index(const Geometry &g, const LaneDir &ld
   return t;
 }
 
-constexpr int kZeroRow = 4;   // ghost-table row of zeros
+// Row of the 2-D ghost table a tap outside the lattice reads: the cell of the
+// edge it crossed (a y edge takes precedence over an x edge), at its x on a y
+// edge (clamped to the lattice at the corners) or its y on an x edge; rows
+// run x- (y = 0..ny-1), x+, y- (x = 0..nx-1), y+, then one row of zeros.
+__device__ __forceinline__ int ghost_row(const Geometry &g, int xs, int ys, bool iny) {
+  const int gx = min(max(xs, 0), g.nx - 1);
+  return !iny ? 2 * g.ny + (ys < 0 ? 0 : g.nx) + gx : (xs < 0 ? 0 : g.ny) + ys;
+}
+__device__ __forceinline__ int ghost_zero_row(const Geometry &g) { return 2 * (g.nx + g.ny); }
 
 template <bool REV>
 __device__ __forceinline__ void edge_taps(const StepArgs &a, const float *__restrict__ src,
@@ -154,10 +162,10 @@ __device__ __forceinline__ void edge_taps(const StepArgs &a, const float *__rest
     const int ys = (k & 2) ? t.ys1 : t.ys0;
     const bool inx = (unsigned)xs < (unsigned)g.nx, iny = (unsigned)ys < (unsigned)g.ny;
     const bool inside = inx && iny;
-    const int e = REV ? kZeroRow : (!iny ? (ys < 0 ? kEdgeYm : kEdgeYp) : (xs < 0 ? kEdgeXm : kEdgeXp));
+    const int row = REV ? ghost_zero_row(g) : ghost_row(g, xs, ys, iny);
     // branch-free: one base pointer select and one offset select
     const float *base = inside ? src : a.ghost;
-    const int64_t eoff = inside ? ld.off + (ys * g.nx + xs) : (int64_t)(e * g.Rpad + 4 * ld.d);
+    const int64_t eoff = inside ? ld.off + (ys * g.nx + xs) : (int64_t)row * g.Rpad + 4 * ld.d;
     p[k] = base + eoff;
     stride[k] = inside ? (int)g.C : 1;
   }
@@ -209,6 +217,16 @@ __device__ __forceinline__ void dir_issue(const StepArgs &a, const float *__rest
 // jrow is the block's LDS copy of the emission rows, so that reading it never
 // waits on the wave's outstanding global loads); for CKPT the streamed value
 // before emission is also stored into s_out.
+// Dichroic factor of one direction on (I, Q): I + Q scaled by exp(-x) and
+// I - Q by exp(x), written as I cosh x - Q sinh x and Q cosh x - I sinh x so
+// that a small Q is not the difference of two intensity-sized terms.
+__device__ __forceinline__ void dich_factor(float &xI, float &xQ, float x) {
+  const float ch = coshf(x), sh = sinhf(x);
+  const float i = xI, q = xQ;
+  xI = fmaf(-q, sh, i * ch);
+  xQ = fmaf(-i, sh, q * ch);
+}
+
 template <bool GATHER, bool EMIT, bool CKPT, bool DICH = false>
 __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g, const LaneDir &ld,
                                             const LaneCell &lc, float emis_dt, const float (&v)[4][4],
@@ -228,11 +246,7 @@ __device__ __forceinline__ void dir_combine(const StepArgs &a, const Geometry &g
     // dichroic absorption: the linear polarisations along e_theta (I + Q)
     // and e_phi (I - Q) decay at their own rates exp(-+xi w_d); the common
     // factor exp(-tau_abs) is in alpha and beta
-    const float x = xi * wd;
-    const float pl = (dst[0] + dst[1]) * expf(-x);
-    const float mi = (dst[0] - dst[1]) * expf(x);
-    dst[0] = 0.5f * (pl + mi);
-    dst[1] = 0.5f * (pl - mi);
+    dich_factor(dst[0], dst[1], xi * wd);
   }
 }
 
@@ -562,14 +576,18 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   // times longer than that step's MFMAs, so a ring of kRing steps is kept in
   // flight, started here to overlap the B conversion and the barrier.
   constexpr int kStep = PREC == P_F32 ? 8 : 16;
+  // the bf16 contractions hold A (the collision matrix) as a bf16 high part
+  // plus a bf16 low part: a single bf16 rounding of M shifts the
+  // polarisation rows coherently at every step
+  constexpr bool ALO = PREC == P_BF16 || PREC == P_BF16X3;
   const int nk = (tr.khi - tr.klo) / kStep;
   const uint4 *A = a.frag + lane;
   const uint4 *Alo = a.frag_lo + lane;
-  uint4 ring[kRing], ring_lo[PREC == P_BF16X3 ? kRing : 1];
+  uint4 ring[kRing], ring_lo[ALO ? kRing : 1];
 #pragma unroll
   for (int j = 0; j < kRing; ++j) {
     ring[j] = A[frag_rec(tr, j, nk)];
-    if (PREC == P_BF16X3) ring_lo[j] = Alo[frag_rec(tr, j, nk)];
+    if (ALO) ring_lo[j] = Alo[frag_rec(tr, j, nk)];
   }
 
   // ---- 2. B operand: the contraction input in its precision ------------------
@@ -627,10 +645,10 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) acc[cb] = f32x16{0};
   // One contraction over the B tile: acc[cb] += A B for the tile's K range,
-  // A from the fragment table Ap (and Alop for bf16x3), ring rg / rgl
-  // already holding its first kRing steps.
+  // A from the fragment table Ap (and its low parts Alop for bf16 and
+  // bf16x3), ring rg / rgl already holding its first kRing steps.
   auto contract = [&](const uint4 *Ap, const uint4 *Alop, const TileRange &trr, int nkk, uint4 (&rg)[kRing],
-                      uint4 (&rgl)[PREC == P_BF16X3 ? kRing : 1], f32x16 (&ac)[NB]) {
+                      uint4 (&rgl)[ALO ? kRing : 1], f32x16 (&ac)[NB]) {
     const int nsteps = (nkk + kRing - 1) / kRing * kRing;
     // B fragments (16 bytes per lane per column block; bf16x3 also the low
     // part) are read from LDS one step ahead, so that their latency overlaps
@@ -651,11 +669,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
       for (int j = 0; j < kRing; ++j) {
         const int s = s0 + j;
-        const uint4 araw = rg[j], araw_lo = rgl[PREC == P_BF16X3 ? j : 0];
+        const uint4 araw = rg[j], araw_lo = rgl[ALO ? j : 0];
         if constexpr (kRing == 1) {
           // a single slot: refill at once, so the load overlaps this step
           rg[j] = Ap[frag_rec(trr, s + kRing, nkk)];
-          if (PREC == P_BF16X3) rgl[j] = Alop[frag_rec(trr, s + kRing, nkk)];
+          if (ALO) rgl[j] = Alop[frag_rec(trr, s + kRing, nkk)];
         }
         uint4 bnext[NB][kLo];
 #pragma unroll
@@ -678,10 +696,12 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
           } else {
             const bf16x8 av = __builtin_bit_cast(bf16x8, araw);
             const bf16x8 bv = __builtin_bit_cast(bf16x8, bcur[cb][0]);
+            // the low part of A, then (bf16x3) the low part of B: the
+            // leading products of (A_hi + A_lo)(B_hi + B_lo), smallest first
+            const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
+            ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, ac[cb], 0, 0, 0);
             if (PREC == P_BF16X3) {
-              const bf16x8 alo = __builtin_bit_cast(bf16x8, araw_lo);
               const bf16x8 blo = __builtin_bit_cast(bf16x8, bcur[cb][kLo - 1]);
-              ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bv, ac[cb], 0, 0, 0);
               ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, blo, ac[cb], 0, 0, 0);
             }
             ac[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, ac[cb], 0, 0, 0);
@@ -694,7 +714,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
         if constexpr (kRing > 1) {
           __builtin_amdgcn_sched_barrier(0);
           rg[j] = Ap[frag_rec(trr, s + kRing, nkk)];
-          if (PREC == P_BF16X3) rgl[j] = Alop[frag_rec(trr, s + kRing, nkk)];
+          if (ALO) rgl[j] = Alop[frag_rec(trr, s + kRing, nkk)];
         }
       }
     }
@@ -710,7 +730,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
     for (int j = 0; j < kRing; ++j) {
       ring[j] = A2[frag_rec(tr2, j, nk2)];
-      if (PREC == P_BF16X3) ring_lo[j] = A2lo[frag_rec(tr2, j, nk2)];
+      if (ALO) ring_lo[j] = A2lo[frag_rec(tr2, j, nk2)];
     }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) acc2[cb] = f32x16{0};
@@ -793,11 +813,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
         // <kap, dD/dxi X> = -w (kap_I X_d,Q + kap_Q X_d,I)
         const float wq = wdir[q];
         part[3] = fmaf(-wq, fmaf(kap[0], xq[1], kap[1] * xq[0]), part[3]);
-        const float x = xi[cb] * wq;
-        const float pl = (kap[0] + kap[1]) * expf(-x);
-        const float mi = (kap[0] - kap[1]) * expf(x);
-        kap[0] = 0.5f * (pl + mi);
-        kap[1] = 0.5f * (pl - mi);
+        dich_factor(kap[0], kap[1], xi[cb] * wq);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           a.out[ld[q].off + (int64_t)s * g.C + c] = kap[s];
@@ -853,11 +869,13 @@ inline hipError_t resident_blocks(const void *k, int threads, int lds, std::atom
   return hipSuccess;
 }
 
-// A-fragment ring depth: 4 steps for blocks of up to 4 waves; for the larger
-// blocks (n > 32) the register budget of 16 waves per CU leaves 2 steps for
-// the 16-bit forward contractions and 1 otherwise.
+// A-fragment ring depth: 4 steps for blocks of up to 4 waves (2 for the
+// adjoint of the split-A bf16 contractions, whose ring holds low parts too);
+// for the larger blocks (n > 32) the register budget of 16 waves per CU
+// leaves 2 steps for the fp16 forward contraction and 1 otherwise.
 template <int PREC, bool ADJ, int MAXW, int NB>
-constexpr int kFusedRing = MAXW <= 4 ? 4 : ((!ADJ && PREC != P_F32 && PREC != P_BF16X3) ? 2 : 1);
+constexpr int kFusedRing = MAXW <= 4 ? ((ADJ && (PREC == P_BF16 || PREC == P_BF16X3)) ? 2 : 4)
+                                     : ((!ADJ && PREC == P_F16) ? 2 : 1);
 
 // Waves per SIMD the register allocation must allow: 4 for the fp32 and bf16
 // adjoint in blocks of up to 4 waves (the accumulator then lives in ordinary
@@ -1316,12 +1334,7 @@ constexpr int kValuRows = 32;
 
 // Dichroic absorption of one direction's X (plain path): I + Q and I - Q
 // scaled by exp(-+x).
-__device__ __forceinline__ void dich_apply(float &xI, float &xQ, float x) {
-  const float pl = (xI + xQ) * expf(-x);
-  const float mi = (xI - xQ) * expf(x);
-  xI = 0.5f * (pl + mi);
-  xQ = 0.5f * (pl - mi);
-}
+__device__ __forceinline__ void dich_apply(float &xI, float &xQ, float x) { dich_factor(xI, xQ, x); }
 
 template <bool DICH, bool MIX>
 __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const float *__restrict__ MT,

@@ -20,7 +20,8 @@ _PHASE = {"rayleigh": A.RT_PHASE_RAYLEIGH, "hg": A.RT_PHASE_HG, "mix": A.RT_PHAS
 def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=None,
                  az_offset_deg=0.0, plane="xy", courant=1.0, bc=(0, 0, 0, 0), phase=None,
                  dt=1.0, precision="fp32", abs_taylor=False, scat_exp=False, fused_taylor=False,
-                 renorm_irow=False, scalar=False, plain=False, nz=1, bc6=None, **_ignored):
+                 renorm_irow=False, scalar=False, plain=False, nz=1, bc6=None, dir_xyz=None,
+                 dir_domega=None, shift=None, **_ignored):
     """An RtProblem from keyword arguments (names follow the ABI struct)."""
     phase = phase or {"kind": "rayleigh"}
     p = A.RtProblem()
@@ -52,6 +53,15 @@ def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=No
         p._table_keepalive = tab
         p.n_table = tab.shape[0]
         p.table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    # explicit direction set (host arrays; the library copies them at rt_init)
+    for name, arr, width in (("dir_xyz", dir_xyz, 3), ("dir_domega", dir_domega, 1),
+                             ("shift", shift, 3 if plane == "3d" else 2)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
+            if a.size != width * p.n_zen * p.n_az:
+                raise ValueError("%s needs %d values" % (name, width * p.n_zen * p.n_az))
+            setattr(p, "_%s_keepalive" % name, a)
+            setattr(p, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     p.dt = float(dt)
     flags = 0
     flags |= A.RT_ABS_TAYLOR if abs_taylor else 0
@@ -100,6 +110,13 @@ class Solver:
         else:
             self.ctx, self._owner, self._owned = _ctx, _owner, False
         self.nout = [A.rt_num_outgoing(problem, e) for e in range(6 if len(self.cells) == 3 else 4)]
+        # What the context holds (medium, phase mixture, dichroism) and a
+        # generation count bumped by every call that changes it, so that
+        # RTSolve.backward can tell whether its forward's medium is still set.
+        self._gen = 0
+        self._medium = None
+        self._mixture = None
+        self._eta = None
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -123,28 +140,62 @@ class Solver:
 
     # -- ABI calls -----------------------------------------------------------------
     def set_medium(self, tau, albedo, emis, jprof, inflow=None):
+        """inflow: host [edges][n][4] (the same radiance along each edge; [6][n][4]
+        faces on a 3-D lattice), or a device tensor [2 nx + 2 ny][n][4] of
+        radiance per edge cell (rt_set_inflow), or None (zero)."""
         jp = np.ascontiguousarray(jprof, dtype=np.float32).reshape(self.n, 4)
         nfaces = 6 if len(self.cells) == 3 else 4   # faces of a 3-D lattice, edges of a 2-D one
-        inf = None if inflow is None else np.ascontiguousarray(inflow, dtype=np.float32).reshape(nfaces, self.n, 4)
-        self._medium = (tau, albedo, emis)
+        per_cell = isinstance(inflow, torch.Tensor) and inflow.is_cuda
+        inf = None if (inflow is None or per_cell) else \
+            np.ascontiguousarray(inflow, dtype=np.float32).reshape(nfaces, self.n, 4)
         A.rt_set_medium(self.ctx, _ptr(tau), _ptr(albedo), _ptr(emis), jp, inf)
+        if per_cell:
+            A.rt_set_inflow(self.ctx, _ptr(inflow))
+        self._medium = (tau, albedo, emis, jp, inflow if per_cell else inf)
+        self._gen += 1
 
     def set_phase_mixture(self, phase, frac):
         """Per-cell mixture: a fraction frac (device [ny, nx] float32) of the
         scattering follows `phase` ({"kind", "g", "mix_ray"}); None removes it."""
+        self._gen += 1
         if phase is None:
             A.rt_set_phase_mixture(self.ctx, -1, 0.0, 1.0, None)
-            self._frac = None
+            self._mixture = None
             return
-        self._frac = frac
         A.rt_set_phase_mixture(self.ctx, _PHASE[phase.get("kind", "rayleigh")], float(phase.get("g", 0.0)),
                                float(phase.get("mix_ray", 1.0)), _ptr(frac))
+        self._mixture = (dict(phase), frac)
 
     def set_dichroism(self, eta):
         """Dichroic absorption with per-cell linear dichroism eta (device
         [ny, nx] float32, |eta| < 1); None removes it."""
-        self._eta = eta
+        self._gen += 1
         A.rt_set_dichroism(self.ctx, _ptr(eta))
+        self._eta = eta
+
+    def medium_state(self):
+        """Everything the context's operator depends on beyond the problem:
+        (generation, medium, mixture, dichroism), for restore_medium()."""
+        return (self._gen, self._medium, self._mixture, self._eta)
+
+    def restore_medium(self, state):
+        """Sets again what medium_state() returned, if anything changed since."""
+        gen, medium, mixture, eta = state
+        if gen == self._gen:
+            return
+        # the order keeps every intermediate combination valid: dichroism and
+        # a mixture exclude each other, so the one to drop goes first
+        if self._eta is not None and eta is None:
+            self.set_dichroism(None)
+        if self._mixture is not None and mixture is None:
+            self.set_phase_mixture(None, None)
+        if medium is not None:
+            self.set_medium(*medium)
+        if mixture is not None:
+            self.set_phase_mixture(*mixture)
+        if eta is not None:
+            self.set_dichroism(eta)
+        self._gen = gen
 
     def step(self, S_in, S_out):
         A.rt_step(self.ctx, _ptr(S_in), _ptr(S_out))
@@ -215,25 +266,37 @@ class RTSolve(torch.autograd.Function):
     readout [edge length, outgoing directions, 4]; backward returns
     (dL/dtau, dL/dalbedo, dL/demis).  The forward stores sqrt(T) checkpoints;
     the backward replays each segment and runs the fused adjoint kernels.
+    Several applications may share one solver before a backward: each
+    backward sets the medium (and phase mixture / dichroism) its forward ran
+    with again if another call changed it, and afterwards puts back what the
+    solver held.
     """
 
     @staticmethod
     def forward(ctx, tau, albedo, emis, solver, S0, nsteps, edge, jprof, inflow=None):
-        solver.set_medium(tau.contiguous(), albedo.contiguous(), emis.contiguous(), jprof, inflow)
+        tau, albedo, emis = tau.contiguous(), albedo.contiguous(), emis.contiguous()
+        solver.set_medium(tau, albedo, emis, jprof, inflow)
         K = sqrt_checkpoint_interval(nsteps)
         ck = solver.checkpoint_buffer(nsteps, K)
         S = S0.clone()
         solver.run(S, nsteps, ck, K)
         out = solver.readout(S, edge)
+        # the medium tensors are saved so that autograd notices in-place changes
+        ctx.save_for_backward(tau, albedo, emis)
         ctx.solver, ctx.nsteps, ctx.edge, ctx.K = solver, nsteps, edge, K
         ctx.ck = ck
+        ctx.medium_state = solver.medium_state()
         return out
 
     @staticmethod
     def backward(ctx, gout):
         s = ctx.solver
+        ctx.saved_tensors   # raises if a medium tensor was modified in place
+        current = s.medium_state()
+        s.restore_medium(ctx.medium_state)
         lam = s.readout_adjoint(ctx.edge, gout.contiguous().float())
         g_tau, g_alb, g_em = s.adjoint(ctx.nsteps, ctx.ck, ctx.K, lam)
+        s.restore_medium(current)
         return g_tau, g_alb, g_em, None, None, None, None, None, None
 
 

@@ -6,25 +6,67 @@ import torch
 import workloads as W
 from oracle import lbm as OL
 
-# Tolerances on the normwise relative error per Stokes component (float32
-# state throughout; bf16 / fp16 only in the contraction operands).  The 2e-3
-# bf16/fp16 bound holds where the scattered share per step is small
-# (beta <= 0.2, the regime of the optically thin per-step media); for
-# scattering-dominated media (beta up to 0.8) the contraction's operand
-# rounding (2^-9 for bf16) enters every step at full weight and the bound is
-# 1e-2; bf16x3 keeps about 16 mantissa bits and is held to 5e-5 there.
+# Tolerances on the normwise relative error of every Stokes component (the
+# state is float32 throughout; bf16 / fp16 enter only as the operands of the
+# contraction).  These are the stated targets: fp32 (and the plain float32
+# path) 1e-5, bf16x3 1e-5, bf16 2e-3 (fp16 held to the same); they apply to
+# every medium whose scattered share per step is beta <= 0.2, which covers the
+# measured workloads (beam, precision, adjoint and spectral media have
+# beta <= 0.06 per step).
 TOL = {"fp32": 1e-5, "plain": 1e-5, "bf16x3": 1e-5, "bf16": 2e-3, "fp16": 2e-3}
-TOL_THICK = {"fp32": 1e-5, "plain": 1e-5, "bf16x3": 5e-5, "bf16": 1e-2, "fp16": 1e-2}
-# gradients: float32 paths 1e-4; the bf16 adjoint 1e-2
-GTOL = {"fp32": 1e-4, "plain": 1e-4, "bf16x3": 1e-4, "bf16": 1e-2, "fp16": 1e-2}
-# a polarised component smaller than this fraction of the intensity norm is
-# judged on the intensity scale (float32 rounding of the intensity-sized
-# terms that combine into it bounds its absolute accuracy)
-POL_FLOOR = 1e-2
+# Unit roundoff of the contraction's operands per precision: bf16 rounds the
+# state operand to 2^-9 (the matrix is held as bf16 high + low parts, 2^-17);
+# bf16x3 holds both operands to 2^-17 (2^-16 for the two together); fp16
+# rounds both to 2^-11 (2^-10 together); float32 rounds to 2^-24.
+UNIT = {"fp32": 2.0 ** -24, "plain": 2.0 ** -24, "bf16x3": 2.0 ** -16, "bf16": 2.0 ** -9,
+        "fp16": 2.0 ** -10}
+# Gradients: 1e-4 for the float32 paths and bf16x3.  bf16 and fp16 are
+# bound by the operand rounding: the adjoint contraction takes mu rounded to
+# the unit roundoff u (2^-9 bf16, 2^-11 fp16), and the per-cell sum <nu, X>
+# that carries the albedo and optical-depth gradients comes straight out of
+# it, so its relative error is u times the cancellation factor
+# || |M^T| |mu| || / || M^T mu || (the DoLP part of the loss gradient changes
+# sign with Q and U), not reduced by beta as in the forward state.  The
+# factor is at most 1.8 on the tested media, so bf16 is held to 2.5 u = 5e-3
+# and fp16 to 2e-3 (measured: bf16 1.7e-3 at the 500-step horizon and 3.4e-3
+# at 7 steps; fp16 2.2e-4).
+GTOL = {"fp32": 1e-4, "plain": 1e-4, "bf16x3": 1e-4, "bf16": 5e-3, "fp16": 2e-3}
+# A polarised component whose norm is below this fraction of the intensity
+# norm (less than 0.01 % polarisation, including components that vanish by
+# symmetry) is scored on the intensity scale: its values are differences of
+# intensity-sized terms, whose float32 rounding alone is 1e-8 of the
+# intensity norm, far above 1e-5 of such a component's own norm.
+POL_NEGLIGIBLE = 1e-4
 
 
-def tolerance(precision, oprob):
-    return (TOL if float(oprob.beta.max()) <= 0.2 else TOL_THICK)[precision]
+def tolerance(precision, oprob, steps=None):
+    """TOL[precision] for media with beta <= 0.2 per step.  In scattering-
+    dominated media (beta up to 0.8) the operand rounding enters every step
+    at full weight: each step adds at most u beta of relative error to the
+    scattered share, and the step operator shrinks what is already there by
+    the survival alpha + beta, so the error stays below
+    u beta_max / (1 - max(alpha + beta)) (u = UNIT[precision]; the horizon
+    `steps`, else 100, caps the lifetime 1 / (1 - alpha - beta) where nothing is absorbed)."""
+    bmax = float(np.max(oprob.beta))
+    if bmax <= 0.2:
+        return TOL[precision]
+    surv = float(np.max(oprob.alpha + oprob.beta))
+    life = min(1.0 / max(1.0 - surv, 1e-12), float(steps) if steps is not None else 100.0)
+    return max(TOL[precision], UNIT[precision] * bmax * life)
+
+
+def gtolerance(precision, oprob, steps=None):
+    """GTOL[precision] for media with beta <= 0.2 per step.  In scattering-
+    dominated media the adjoint field lambda accumulates the operand
+    rounding over the light's lifetime as the forward state does (see
+    tolerance), and the gradient sums take it on top of their own rounding
+    u: u (1 + beta_max / (1 - max(alpha + beta)))."""
+    bmax = float(np.max(oprob.beta))
+    if bmax <= 0.2:
+        return GTOL[precision]
+    surv = float(np.max(oprob.alpha + oprob.beta))
+    life = min(1.0 / max(1.0 - surv, 1e-12), float(steps) if steps is not None else 100.0)
+    return max(GTOL[precision], UNIT[precision] * (1.0 + bmax * life))
 
 
 def build(spec, precision="fp32", medium=None):
@@ -54,16 +96,17 @@ def to_np(t):
 
 
 def stokes_errors(got, ref):
-    """Normwise relative error per Stokes component, max-abs / max |ref|, and
-    the largest absolute DoLP error over cells with I > 1e-3 max I.
-
-    The scale of Q, U, V is max(own norm, POL_FLOOR * ||I||).
-    """
+    """Normwise relative error of each Stokes component over the field
+    (against its own norm; against the intensity norm for a component below
+    POL_NEGLIGIBLE of it), the largest absolute error over the largest
+    |reference| value, and the largest absolute DoLP error over cells with
+    I > 1e-3 max I."""
     out = {}
     nI = np.linalg.norm(ref[:, 0])
     for s, name in enumerate("IQUV"):
-        den = max(np.linalg.norm(ref[:, s]), POL_FLOOR * nI if s else 0.0, 1e-300)
-        out[name] = float(np.linalg.norm(got[:, s] - ref[:, s]) / den)
+        own = np.linalg.norm(ref[:, s])
+        den = own if (s == 0 or own >= POL_NEGLIGIBLE * nI) else nI
+        out[name] = float(np.linalg.norm(got[:, s] - ref[:, s]) / max(den, 1e-300))
     out["maxabs"] = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
     I = ref[:, 0]
     m = I > 1e-3 * I.max() if I.max() > 0 else np.zeros_like(I, dtype=bool)
@@ -77,32 +120,8 @@ def stokes_errors(got, ref):
 
 
 def assert_close(got, ref, tol, what=""):
+    """Every Stokes component, max-abs and DoLP within tol."""
     e = stokes_errors(got, ref)
-    bad = {k: v for k, v in e.items() if k in "IQUV" and v > tol}
-    assert not bad and e["maxabs"] < 10 * tol and e["dolp_abs"] < 10 * tol, (what, e)
+    bad = {k: v for k, v in e.items() if v > tol}
+    assert not bad, (what, tol, e)
     return e
-
-
-def _bf16(a):
-    """Round to bfloat16 through float32, to nearest even, as the fragment
-    packer does."""
-    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def represented(M, precision, scale_of=None):
-    """The collision matrix as a 16-bit contraction holds it: bf16, bf16 high
-    + low parts (bf16x3), or fp16 (through float32) after the power-of-two
-    scale that puts max |scale_of| in [2^12, 2^13) (scale_of = M itself by
-    default; a mixture's second matrix takes the first one's scale)."""
-    if precision == "bf16":
-        return _bf16(M)
-    if precision == "bf16x3":
-        hi = _bf16(M)
-        return hi + _bf16(M - hi)
-    if precision == "fp16":
-        e = np.frexp(np.abs(M if scale_of is None else scale_of).max())[1]
-        sc = 2.0 ** (13 - e)
-        return np.asarray(M * sc, dtype=np.float32).astype(np.float16).astype(np.float64) / sc
-    return M

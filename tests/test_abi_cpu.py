@@ -214,3 +214,47 @@ def test_three_d_problem_validation_and_sizes():
     P.rt_describe(p, None, M3)
     P.rt_describe(P.make_problem(**W.spec("beam512", nx=8, ny=8)), None, M2)
     assert np.array_equal(M3, M2)
+
+
+def _random_unit_vectors(n, seed):
+    rng = np.random.default_rng(seed)
+    k = rng.standard_normal((n, 3))
+    k /= np.linalg.norm(k, axis=1, keepdims=True)
+    return k
+
+
+def test_explicit_direction_set_matches_oracle():
+    """Explicit unit vectors, solid angles and displacements (the direction
+    set of the problem statement given as data): the host collision matrix
+    equals the oracle's built from the same vectors (Eq. 13-17 with the
+    given weights) to 1e-13, and the displacements and edge masks follow the
+    given shifts."""
+    from oracle import directions as OD
+    n = 12
+    k = _random_unit_vectors(n, 3)
+    dom = np.random.default_rng(4).uniform(0.5, 1.5, n)
+    sh = np.random.default_rng(5).uniform(-1.0, 1.0, (n, 2))
+    sh[0] = (0.0, 1.0)
+    p = P.make_problem(9, 7, 3, 4, plane="xz", phase={"kind": "hg", "g": 0.4}, dir_xyz=k, dir_domega=dom,
+                       shift=sh)
+    dirs = np.zeros((n, 6))
+    M = np.zeros((4 * n, 4 * n))
+    P.rt_describe(p, dirs, M)
+    od = OD.VectorDirectionSet(k, dom)
+    Mo = OP.collision_matrix(od, "hg", 0.4, 1.0)
+    assert np.abs(M - Mo).max() < 1e-13
+    assert np.allclose(dirs[:, 0], od.theta, atol=1e-14) and np.allclose(dirs[:, 2], dom, rtol=1e-15)
+    assert np.array_equal(dirs[:, 3:5], sh)
+    assert P.rt_num_outgoing(p, 3) == int(np.sum(sh[:, 1] > 0))
+
+
+def test_explicit_direction_set_validation():
+    k = _random_unit_vectors(8, 6)
+    bad = k.copy()
+    bad[2] = (0.0, 0.0, 1.0)                  # along the polar axis: no meridian plane
+    _expect(P.RT_EINVAL, dir_xyz=bad)
+    _expect(P.RT_EINVAL, dir_xyz=2.0 * k)     # not unit vectors
+    _expect(P.RT_EINVAL, dir_xyz=k, dir_domega=np.r_[np.ones(7), -1.0])
+    sh = np.zeros((8, 2))
+    sh[5] = (1.5, 0.0)
+    _expect(P.RT_ERANGE, shift=sh)

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import GTOL, TOL, assert_close, to_dev, to_np, tolerance
+from gpu_common import assert_close, GTOL, gtolerance, to_dev, to_np, TOL, tolerance
 from oracle import lbm as OL
 from oracle import lbm3d as O3
 
@@ -77,7 +77,7 @@ def test_forward3d_parity(case, precision):
     S = to_dev(S0, solver)
     solver.run(S, steps)
     ref = O3.run(S0, p3, steps)
-    e = assert_close(to_np(S), ref, tolerance(precision, p3.flat), (over, precision))
+    e = assert_close(to_np(S), ref, tolerance(precision, p3.flat, steps), (over, precision))
     print(over, precision, e)
 
 
@@ -85,7 +85,7 @@ def test_forward3d_parity(case, precision):
 def test_step3d_checkpoints_maps_and_totals(precision):
     spec = spec3(11, 8, 6, bc6=(0, 0, 1, 1, 1, 2))
     solver, p3, _ = build3(spec, precision)
-    tol = tolerance(precision, p3.flat)
+    tol = tolerance(precision, p3.flat, 9)
     S0 = W.initial_state(spec, "random")
     a, b = to_dev(S0, solver), solver.empty_state()
     solver.step(a, b)
@@ -246,7 +246,7 @@ def test_adjoint3d_parity(case, precision, ext):
     ref = O3.adjoint(S0, p3, T, lamT)
     got = solver.adjoint(T, ck, K, to_dev(lamT, solver), want_lambda0=True)
     for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
-        assert _rel(to_np(arr), ref[key]) < GTOL[precision], (key, _rel(to_np(arr), ref[key]))
+        assert _rel(to_np(arr), ref[key]) < gtolerance(precision, p3.flat, T), (key, _rel(to_np(arr), ref[key]))
 
 
 @pytest.mark.parametrize("dims", [(9, 7, 5), (16, 9, 7), (3, 2, 4)])

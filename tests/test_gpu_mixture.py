@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import GTOL, assert_close, build, represented, to_dev, to_np, tolerance
+from gpu_common import assert_close, build, GTOL, gtolerance, to_dev, to_np, tolerance
 from oracle import adjoint as OA
 from oracle import lbm as OL
 
@@ -53,11 +53,9 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%dx%d-n%d" % (
     c[0], c[1]["nx"], c[1]["ny"], W.ndir(W.spec(c[0], **c[1]))))
 def test_mixture_forward_parity(case, precision):
-    """Against the oracle.  In the scattering-dominated n = 8 medium the
-    bf16x3 and fp16 paths are compared with the oracle run on M and M2 as
-    the contraction holds them (the 16-bit representation of the matrices
-    alone moves that run by more than their 1e-5 / 1e-4 bounds after 40
-    steps), which isolates what the kernel adds."""
+    """Against the unmodified oracle in every precision (the n = 8 medium is
+    scattering-dominated: the tolerance there is the accumulation bound of
+    the operand rounding, gpu_common.tolerance)."""
     name, over, steps, init = case
     spec = W.spec(name, **over)
     solver, oprob, _ = _with_mixture(spec, precision)
@@ -65,12 +63,8 @@ def test_mixture_forward_parity(case, precision):
     S0 = W.initial_state(spec, init)
     S = to_dev(S0, solver)
     solver.run(S, steps)
-    if name == "plain32" and precision in ("bf16x3", "fp16"):
-        M = oprob.M
-        oprob.M = represented(M, precision)
-        oprob.M2 = represented(oprob.M2, precision, scale_of=M)
     ref = OL.run(S0, oprob, steps)
-    e = assert_close(to_np(S), ref, tolerance(precision, oprob), (name, precision))
+    e = assert_close(to_np(S), ref, tolerance(precision, oprob, steps), (name, precision))
     print(name, precision, e)
 
 
@@ -115,7 +109,10 @@ def test_zero_fraction_equals_single_phase(precision, n_zen, n_az):
     solver.run(S, 12)
     torch.cuda.synchronize()
     if precision == "bf16" and n_zen * n_az > 64:
-        assert_close(to_np(S), to_np(ref), 1e-5, "f = 0, split X")
+        # X as high + low bf16 parts is exact to 2^-18; the alpha X term passes
+        # that on at every one of the 12 steps (alpha ~ 1), and DoLP takes the
+        # errors of two components
+        assert_close(to_np(S), to_np(ref), 2 * 12 * 2.0 ** -18, "f = 0, split X")
     else:
         assert torch.equal(S, ref)
     one = torch.ones_like(zero)
@@ -277,12 +274,12 @@ def test_mixture_adjoint_parity(precision, over, T, K):
     ref = OA.adjoint(S0, oprob, T, lamT)
     got = solver.adjoint(T, ck, K, to_dev(lamT, solver), want_lambda0=True)
     for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
-        assert _rel(to_np(arr), ref[key]) < GTOL[precision], (key, _rel(to_np(arr), ref[key]))
+        assert _rel(to_np(arr), ref[key]) < gtolerance(precision, oprob, T), (key, _rel(to_np(arr), ref[key]))
     # the second phase function matters at this bound: the single-phase
     # oracle gradient is far off
     oprob.M2 = None
     far = OA.adjoint(S0, oprob, T, lamT)
-    assert _rel(far["g_tau"], ref["g_tau"]) > 10 * GTOL[precision]
+    assert _rel(far["g_tau"], ref["g_tau"]) > 10 * gtolerance(precision, oprob, T)
 
 
 def test_mixture_adjoint_zero_fraction_equals_single_phase():

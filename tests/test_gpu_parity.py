@@ -12,7 +12,7 @@ import workloads as W
 from oracle import adjoint as OA
 from oracle import lbm as OL
 
-from gpu_common import GTOL, assert_close, build, to_dev, to_np, tolerance
+from gpu_common import assert_close, build, GTOL, to_dev, to_np, tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def test_forward_parity(case, precision):
     name, over, steps, init = case
     spec = W.spec(name, **over)
     _, oprob, got, ref = _run_both(spec, precision, steps, init)
-    e = assert_close(got, ref, tolerance(precision, oprob), (name, precision))
+    e = assert_close(got, ref, tolerance(precision, oprob, steps), (name, precision))
     print(name, precision, e)
 
 
@@ -169,7 +169,7 @@ def _rel(a, b):
 @pytest.mark.parametrize("TK", [(30, 6), (31, 6), (7, 1), (9, 9)])
 def test_adjoint_parity(precision, TK):
     T, K = TK
-    tol = GTOL[precision]
+    tol = GTOL[precision]   # the differentiation workload's medium: beta <= 0.1 per step
     spec = W.spec("adjoint256", nx=36, ny=33)
     ref, got = _adjoint_case(spec, precision, T, K)
     for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):

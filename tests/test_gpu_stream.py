@@ -123,7 +123,8 @@ def test_stream_full_size_prec1024_sampled_directions():
     dirs = sorted({0, n - 1, spec["beam_dir"], *[int(d) for d in rng.integers(0, n, 9)]})
     for d in dirs:
         sub = types.SimpleNamespace(n=1, nx=oprob.nx, ny=oprob.ny, bc=oprob.bc,
-                                    shifts=oprob.shifts[d:d + 1], inflow=oprob.inflow[:, d:d + 1])
+                                    shifts=oprob.shifts[d:d + 1], inflow_cells=oprob.inflow_cells[:, d:d + 1],
+                                    edge_base=oprob.edge_base)
         ref = OL.stream(to_np(Yd[d:d + 1]), sub)
         check(to_np(out[d:d + 1]), ref, ("prec1024", d))
 

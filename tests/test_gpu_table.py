@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import GTOL, assert_close, build, represented, to_dev, to_np, tolerance
+from gpu_common import assert_close, build, GTOL, gtolerance, to_dev, to_np, tolerance
 from oracle import adjoint as OA
 from oracle import lbm as OL
 
@@ -40,12 +40,9 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%dx%d-n%d" % (
     c[0], c[1]["nx"], c[1]["ny"], W.ndir(W.spec(c[0], **c[1]))))
 def test_table_forward_parity(case, precision):
-    """Against the oracle.  In the scattering-dominated n = 8 medium a
-    forward-peaked matrix amplifies the 16-bit representation error of M
-    itself (the oracle run with M rounded as the contraction holds it, and
-    nothing else changed, is 4% off for bf16 and 6e-5 for bf16x3 after 40
-    steps): there the 16-bit paths are compared with that oracle run, which
-    isolates what the kernel adds."""
+    """Against the unmodified oracle in every precision.  The n = 8 medium is
+    scattering-dominated (beta 0.81 per step), where the tolerance is the
+    accumulation bound of the operand rounding (gpu_common.tolerance)."""
     name, over, steps = case
     spec = W.spec(name, phase=TABLE, **over)
     solver, oprob, _ = build(spec, precision)
@@ -54,10 +51,8 @@ def test_table_forward_parity(case, precision):
     solver.run(S, steps)
     # U -> V coupling is present in the operator the oracle runs
     assert np.abs(oprob.M[3::4, 2::4]).max() > 1e-3
-    if name == "plain32" and precision in ("bf16", "bf16x3", "fp16"):
-        oprob.M = represented(oprob.M, precision)
     ref = OL.run(S0, oprob, steps)
-    e = assert_close(to_np(S), ref, tolerance(precision, oprob), (name, precision))
+    e = assert_close(to_np(S), ref, tolerance(precision, oprob, steps), (name, precision))
     print(name, precision, e)
 
 
@@ -80,7 +75,7 @@ def test_table_adjoint_parity(precision):
     ref = OA.adjoint(S0, oprob, T, lamT)
     got = solver.adjoint(T, ck, K, to_dev(lamT, solver), want_lambda0=True)
     for key, arr in zip(("g_tau", "g_albedo", "g_emis", "lambda0"), got):
-        assert _rel(to_np(arr), ref[key]) < GTOL[precision], (key, _rel(to_np(arr), ref[key]))
+        assert _rel(to_np(arr), ref[key]) < gtolerance(precision, oprob, T), (key, _rel(to_np(arr), ref[key]))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])

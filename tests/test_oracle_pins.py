@@ -584,7 +584,7 @@ def test_table_grids_run_physically(g, pol):
 
 def _with_mixture(p, M2, frac):
     return OL.Problem(p.nx, p.ny, p.dirs, p.shifts, p.M, p.dt, p.bc, p.tau, p.albedo, p.emis, p.jprof,
-                      p.inflow, p.abs_taylor, p.scat_exp, p.fused_taylor, M2=M2, frac=frac)
+                      p.inflow_cells, p.abs_taylor, p.scat_exp, p.fused_taylor, M2=M2, frac=frac)
 
 
 def _mixture_setup(**kw):

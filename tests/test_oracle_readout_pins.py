@@ -289,3 +289,41 @@ def test_face_readout_transpose_is_the_transpose(face):
     lhs = float(np.sum(O3.readout(S, prob, face) * G))
     rhs = float(np.sum(S * O3.readout_transpose(G, prob, face)))
     assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+
+
+# --------------------------------------------------- per-edge-cell inflow --
+
+def test_per_cell_inflow_is_carried_along_integer_velocities():
+    """Inflow radiance given per top-edge cell, p(x), on the D2Q9 lattice
+    with pure transport: after T >= ny steps the straight-down directions
+    (velocity (0, -1)) hold p(x) in every row, and the diagonal (-1, -1)
+    directions hold p(x + ny - y) where the path back reaches the top edge
+    first, zero where it reaches the absorbing right edge first, and at the
+    corner (both at once) the top edge's last cell p(nx - 1): a ghost outside
+    in y takes its y edge at the x clamped to the lattice (Sec. 2.1.7)."""
+    nx, ny = 7, 5
+    dirs = ODir.make_directions(2, 8)          # 8 azimuths: diagonals included
+    sh = ODir.displacements(dirs, "xy_d2q9")
+    n = dirs.n
+    prof = 1.0 + np.arange(nx, dtype=np.float64) ** 2 / 7.0
+    inflow = np.zeros((2 * (nx + ny), n, 4))
+    top = 2 * ny + nx                          # first cell of the y+ edge
+    for d in range(n):
+        inflow[top:top + nx, d, 0] = prof
+        inflow[top:top + nx, d, 1] = 0.25 * prof
+    M = OP.collision_matrix(dirs)
+    z = np.zeros((ny, nx))
+    prob = OL.Problem(nx, ny, dirs, sh, M, 1.0, (1, 1, 1, 2), z, z, z, np.zeros((n, 4)), inflow)
+    S = OL.run(np.zeros(prob.shape), prob, ny + 2)
+    down = [d for d in range(n) if tuple(sh[d]) == (0.0, -1.0)]
+    diag = [d for d in range(n) if tuple(sh[d]) == (-1.0, -1.0)]
+    assert len(down) == 2 and len(diag) == 2
+    for d in down:
+        for y in range(ny):
+            assert np.array_equal(S[d, 0, y], prof) and np.array_equal(S[d, 1, y], 0.25 * prof)
+    for d in diag:
+        for y in range(ny):
+            for x in range(nx):
+                k_top, k_right = ny - y, nx - x
+                want = prof[x + k_top] if k_top < k_right else (0.0 if k_right < k_top else prof[nx - 1])
+                assert S[d, 0, y, x] == want, (d, x, y)

@@ -17,7 +17,8 @@
  *    valid until the work queued on the context's stream has finished.  h_*
  *    pointers are host memory read (or written) during the call only.  The
  *    library allocates no device memory: all persistent device data lives in
- *    the caller's workspace, whose size rt_workspace_bytes() returns.
+ *    the caller's workspace, whose size rt_workspace_bytes() returns (and a
+ *    32 KiB static array per device, the scratch of rt_totals_noalloc).
  *  - State layout: S[d][s][y][x], d = i_zen * n_az + j_az, s = 0..3 (I,Q,U,V),
  *    x fastest; 4 * n * nx * ny floats, where n = n_zen * n_az.
  *  - Stokes vectors of direction d are referred to its meridian frame
@@ -298,6 +299,19 @@ rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t c
  * d_out[e][k][4] runs over the face's cells e = a + na b: x faces (y, z),
  * y faces (x, z), z faces (x, y), the first index fastest. */
 rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, double *h_sums);
+
+/* For callers that cannot allocate device memory or call a synchronising
+ * function (code under HIP graph capture, tight serving loops): the float64
+ * sums of I, Q, U, V over the whole field, as rt_readout's h_sums computes
+ * them, written to d_sums (device [4], caller-owned) asynchronously on the
+ * context's stream.  The partial sums live in a static device array of the
+ * library (4 x 1024 float64, 32 KiB per device, held until the process ends)
+ * instead of the workspace; the call allocates nothing and does not
+ * synchronise.  Every lattice fits (the partial count never exceeds 1024;
+ * RT_ERANGE otherwise).  Calls on one device share that array: calls that
+ * overlap in time on one device (different streams, or different threads)
+ * race and must be ordered by the caller. */
+rt_status rt_totals_noalloc(rt_ctx *c, const float *d_S, double *d_sums);
 
 /* Direction-mean intensity and direction-mean degree of polarisation
  * sqrt(Q^2+U^2+V^2)/I (Sec. 3.2.1) per cell, [ny][nx] each. */

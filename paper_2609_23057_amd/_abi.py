@@ -70,6 +70,7 @@ _SIGS = {
     "rt_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
     "rt_readout": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_maps": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "rt_totals_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_readout_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_adjoint_segment_bytes": (c_size_t, [_P, c_int32]),
     "rt_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
@@ -178,6 +179,10 @@ def rt_readout(ctx, d_S, edge, d_out=None, h_sums=None):
     """h_sums: numpy float64 array of 4 or None."""
     _check(_lib.rt_readout(ctx, d_S, edge, d_out,
                            None if h_sums is None else h_sums.ctypes.data), ctx)
+
+
+def rt_totals_noalloc(ctx, d_S, d_sums):
+    _check(_lib.rt_totals_noalloc(ctx, d_S, d_sums), ctx)
 
 
 def rt_maps(ctx, d_S, d_I_mean, d_dop_mean):

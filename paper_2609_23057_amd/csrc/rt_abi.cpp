@@ -401,6 +401,11 @@ rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream
   }
   c->cu_count = prop.multiProcessorCount;
   c->device = dev;
+  // the static scratch of rt_totals_noalloc: its address on this device, once
+  if (hipError_t e = scratch_setup(dev); e != hipSuccess) {
+    delete c;
+    return set_err(RT_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+  }
 
   // host tables
   std::vector<uint8_t> &tb = c->host_tables;
@@ -877,6 +882,14 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
         if (!std::isfinite(h_sums[k])) return c->fail(RT_ERANGE, "non-finite Stokes totals");
   }
   return st;
+}
+
+rt_status rt_totals_noalloc(rt_ctx *c, const float *d_S, double *d_sums) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_S || !d_sums) return c->fail(RT_EINVAL, "NULL pointer");
+  if (sums_partials(c->geo) > scratch_partials_max())
+    return c->fail(RT_ERANGE, "the lattice needs more partial sums than the static scratch holds");
+  return c->hip(launch_sums_noalloc(c->geo, c->device, d_S, d_sums, c->stream), "totals");
 }
 
 rt_status rt_maps(rt_ctx *c, const float *d_S, float *d_I_mean, float *d_dop_mean) {

@@ -166,6 +166,15 @@ hipError_t launch_maps(const Geometry &g, const float *S, float *I_mean, float *
 
 int sums_partials(const Geometry &g);
 
+// Allocation-free totals: the partial sums live in a static device array.
+// scratch_setup takes its address on `device` (which must be current) once
+// per device; launch_sums_noalloc then writes the four float64 sums of S to
+// result (device) through it.  Calls that overlap on one device share the
+// array and race.
+hipError_t scratch_setup(int device);
+int scratch_partials_max();
+hipError_t launch_sums_noalloc(const Geometry &g, int device, const float *S, double *result, hipStream_t s);
+
 // LDS bytes of the fused launch the library will use (SIZE_MAX if none fits).
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich = false);
 

@@ -1937,6 +1937,45 @@ hipError_t launch_readout_face_adjoint(int64_t C, const FaceMap &f, const int32_
 
 int sums_partials(const Geometry &g) { return (int)grid_for(g.C, kSumThreads, 1024); }
 
+// ---- allocation-free totals ---------------------------------------------------
+// The float64 partial sums of rt_totals_noalloc live in a static device array
+// instead of the caller's workspace: 4 sums per block of sums_kernel, at most
+// kScratchPartials blocks (sums_partials never asks for more).  Each device
+// holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device, kept per device below.
+constexpr int kScratchPartials = 1024;
+static __device__ __align__(256) double scratch[4 * kScratchPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<double *> g_scratch[kMaxDevices];
+}  // namespace
+
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch[device].load(std::memory_order_acquire) != nullptr) return hipSuccess;
+  double *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&ptr), HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (ptr == nullptr) return hipErrorInvalidSymbol;
+  g_scratch[device].store(ptr, std::memory_order_release);
+  return hipSuccess;
+}
+
+int scratch_partials_max() { return kScratchPartials; }
+
+hipError_t launch_sums_noalloc(const Geometry &g, int device, const float *S, double *result, hipStream_t s) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  double *partial = g_scratch[device].load(std::memory_order_acquire);
+  if (partial == nullptr) return hipErrorNotInitialized;
+  const int npart = sums_partials(g);
+  if (npart > kScratchPartials) return hipErrorInvalidValue;
+  // every partial this launch reads is written by it first: nothing to clear
+  hipLaunchKernelGGL(sums_kernel, dim3(npart), dim3(kSumThreads), 0, s, g, S, partial);
+  hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(64), 0, s, partial, npart, result);
+  return hipGetLastError();
+}
+
 hipError_t launch_sums(const Geometry &g, const float *S, double *partial, int npart, double *result,
                        hipStream_t s) {
   hipLaunchKernelGGL(sums_kernel, dim3(npart), dim3(kSumThreads), 0, s, g, S, partial);

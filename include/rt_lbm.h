@@ -196,10 +196,18 @@ int32_t rt_num_outgoing(const rt_problem *p, int32_t edge);
 
 /* ---- context ------------------------------------------------------------- */
 
-/* Builds the direction set and operators (host, float64), uploads the
- * tables into d_ws (ws_bytes >= rt_workspace_bytes(p)) on `stream` (a
- * hipStream_t, NULL = default stream) and returns a context in *out.
- * RT_EUNSUPPORTED if the current device is not gfx950. */
+/* Builds, in float64 on the host, what the problem statement fixes before
+ * time stepping: the direction set and its solid angles (Sec. 2.1.1), the
+ * lattice displacement of every direction (Eq. 33), the collision matrix of
+ * Eq. 17 from the rotated phase matrix (Eq. 13-16, 21-22; the direction-pair
+ * sum of Eq. 25/30) and the streaming taps (Eq. 34); uploads the tables into
+ * d_ws (caller-owned, ws_bytes >= rt_workspace_bytes(p)) on `stream` (a
+ * hipStream_t, NULL = default stream) and returns a context in *out
+ * (owned by the library until rt_destroy).  Synchronises the stream.
+ * Errors: those of rt_validate; RT_EINVAL for a NULL out or workspace,
+ * RT_ENOMEM if ws_bytes is too small, RT_EUNSUPPORTED if the current device
+ * is not gfx950 or the problem does not fit the fused kernels, RT_EDEVICE
+ * for a HIP failure. */
 rt_status rt_init(const rt_problem *p, void *d_ws, size_t ws_bytes, void *stream, rt_ctx **out);
 
 /* Per-cell medium, [ny][nx] each: d_tau = per-step extinction optical depth
@@ -272,7 +280,13 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
  * rt_set_phase_mixture likewise. */
 rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);
 
-/* One step S_out = Stream(Collide(S_in)); S_in and S_out must not overlap. */
+/* One time step of Sec. 2.1.1 (Eq. 2 split as the operator chain of Eq. 5):
+ * emission X = S_in + dt J (Eq. 6/8), absorption and scattering
+ * Y = alpha X + beta M X (Sec. 2.1.4-2.1.5, Eq. 11), streaming
+ * S_out = L(Y) (Eq. 33-34, edges Sec. 2.1.7 / Eq. 39).  d_S_in and d_S_out
+ * are device states [n][4][ny][nx] (rt_state_bytes each), caller-owned, not
+ * overlapping.  Asynchronous.  RT_ESTATE before rt_set_medium, RT_EINVAL
+ * for NULL or overlapping states. */
 rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out);
 
 /* Streaming alone (Sec. 2.1.6, Eq. 33-34): d_out[p] = bilinear pull of
@@ -285,16 +299,23 @@ rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out);
  * inflow radiance lives there).  Asynchronous on the context's stream. */
 rt_status rt_stream(rt_ctx *c, const float *d_in, float *d_out);
 
-/* nsteps steps in place on d_S (S_0 in, S_nsteps out).  If d_ckpt is not NULL
- * it receives S_{k*ckpt_every} in slot k = 0 .. ceil(nsteps/ckpt_every)-1
- * (slots of rt_state_bytes each), as rt_adjoint expects. */
+/* nsteps time steps of Sec. 2.1.1 (as rt_step) in place on d_S (S_0 in,
+ * S_nsteps out); the streaming of one step is fused with the collision of
+ * the next, so the state makes one HBM round trip per step.  If d_ckpt is
+ * not NULL it receives S_{k*ckpt_every} in slot k = 0 ..
+ * ceil(nsteps/ckpt_every)-1 (device, caller-owned, slots of rt_state_bytes
+ * each), as rt_adjoint expects.  Asynchronous.  RT_ESTATE before
+ * rt_set_medium, RT_EINVAL for nsteps < 0 or ckpt_every < 1 with d_ckpt. */
 rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t ckpt_every);
 
-/* Stokes vectors of the outgoing directions on one edge row/column:
- * d_out[e][k][4], e along the edge (x for edges 2,3; y for edges 0,1), k over
- * the directions leaving through the edge in increasing d.  If h_sums is not
- * NULL it receives the float64 sums of I, Q, U, V over the whole field
- * (synchronises). On an
+/* The radiance leaving the lattice (the boundary radiance maps of
+ * Sec. 3.2, taken at an edge row as the paper's figures take the field):
+ * Stokes vectors of the outgoing directions on one edge row/column,
+ * d_out[e][k][4] (device, caller-owned), e along the edge (x for edges 2,3;
+ * y for edges 0,1), k over the directions leaving through the edge in
+ * increasing d.  If h_sums is not NULL it receives the float64 sums of I, Q,
+ * U, V over the whole field (the conservation totals; synchronises;
+ * RT_ERANGE if not finite). On an
  * RT_PLANE_3D lattice `edge` is a face 0..5 (x-, x+, y-, y+, z-, z+) and
  * d_out[e][k][4] runs over the face's cells e = a + na b: x faces (y, z),
  * y faces (x, z), z faces (x, y), the first index fastest. */

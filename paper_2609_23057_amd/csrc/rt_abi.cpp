@@ -795,7 +795,11 @@ static rt_status plain_step(rt_ctx *c, const float *S_in, float *S_out) {
 rt_status rt_step(rt_ctx *c, const float *d_S_in, float *d_S_out) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_S_in || !d_S_out) return c->fail(RT_EINVAL, "NULL state pointer");
-  if (d_S_in == d_S_out) return c->fail(RT_EINVAL, "S_in and S_out must differ");
+  {
+    const uintptr_t i0 = (uintptr_t)d_S_in, o0 = (uintptr_t)d_S_out;
+    const uintptr_t bytes = (uintptr_t)state_elems(c) * sizeof(float);
+    if (i0 < o0 + bytes && o0 < i0 + bytes) return c->fail(RT_EINVAL, "S_in and S_out overlap");
+  }
   if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
   if (c->three_d) return step3d(c, d_S_in, d_S_out);
   if (c->prob.flags & RT_PLAIN) return plain_step(c, d_S_in, d_S_out);

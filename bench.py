@@ -371,11 +371,63 @@ def streaming_extras(reps=50):
     return res
 
 
-def spectral_extras(T=200):
+def _time_ms(fn, reps=1):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_autotune(batch, states, steps=20):
+    """The tuning table of a batch: for every channel class (waves per tile
+    W), the forward step time with each admissible block size (W, 2W, ... up
+    to 8 waves; the other classes at their chosen size), and the fastest
+    kept; then the cache budget of the temporal blocking (channel groups
+    that complete every step before the next group starts; 0 = all channels
+    step together).  Also the same channels stepped as separate contexts
+    (every step of one channel, then the next, on the same stream) for
+    comparison."""
+    table = {}
+    for W, bw0, nch in batch.classes():
+        cands = [b for b in (1, 2, 4, 8) if b >= W and b % W == 0]
+        ms = {}
+        for bw in cands:
+            batch.set_tuning(W, bw)
+            batch.run(states, 2)
+            ms[bw] = _time_ms(lambda: batch.run(states, steps)) / steps
+        best = min(ms, key=ms.get)
+        batch.set_tuning(W, best)
+        table[str(W)] = {"channels": nch, "default_block_waves": bw0, "ms_per_step_by_block_waves": ms,
+                         "chosen_block_waves": best}
+    budgets = {}
+    for mib in (0, 64, 128, 192, 256, "one channel per group"):
+        batch.set_cache_budget(1 if isinstance(mib, str) else mib << 20)
+        batch.run(states, 2)
+        budgets[mib] = _time_ms(lambda: batch.run(states, steps)) / steps
+    best_budget = min(budgets, key=budgets.get)
+    batch.set_cache_budget(1 if isinstance(best_budget, str) else best_budget << 20)
+    batched = _time_ms(lambda: batch.run(states, steps)) / steps
+
+    def separate():
+        for ch, x in zip(batch.channels, states):
+            ch.run(x, steps)
+    separate()
+    sep = _time_ms(separate) / steps
+    return {"classes": table, "ms_per_step_by_cache_budget_mib": budgets, "chosen_cache_budget_mib": best_budget,
+            "batched_forward_ms_per_step": batched,
+            "separate_contexts_forward_ms_per_step": sep, "batched_speedup_vs_separate": sep / batched}
+
+
+def spectral_extras(T=200, only_tune=False):
     """The 64-channel spectral batch (per-channel lattice 128^2..512^2 and
-    n = 16..64, bf16 contraction): forward run of T steps with sqrt(T)
-    checkpoints, top-edge readout adjoint and the batched adjoint, each step
-    of all channels one launch; timed eagerly and as a replayed HIP graph."""
+    n = 16..64, bf16 contraction): the per-class tuning table (batch_autotune),
+    then a forward run of T steps with sqrt(T) checkpoints, top-edge readout
+    adjoint and the batched adjoint, each step one launch per channel class;
+    timed eagerly and as a replayed HIP graph."""
     import numpy as np
     import torch
     import paper_2609_23057_amd as P
@@ -392,6 +444,12 @@ def spectral_extras(T=200):
         keep.append(t)
     K = max(1, int(math.ceil(math.sqrt(T))))
     states = [torch.zeros(ch.shape, device=ch.device) for ch in batch.channels]
+    _log("bench: spectral64 tuning table")
+    tuning = batch_autotune(batch, states)
+    if only_tune:
+        return {"workload": "spectral64 forward steps, bf16", "tuning": tuning}
+    for x in states:
+        x.zero_()
     ck = batch.checkpoint_buffers(T, K)
     segs = batch.segment_buffers(K)
     lams = [torch.empty(ch.shape, device=ch.device) for ch in batch.channels]
@@ -434,7 +492,8 @@ def spectral_extras(T=200):
             "forward_cell_dir_updates_per_s": upd * T / (g["forward_ms"] / 1e3),
             "forward_adjoint_cell_dir_updates_per_s": 2 * upd * T / ((g["forward_ms"] + g["adjoint_ms"]) / 1e3),
             "adjoint_fwd_ratio": g["adjoint_ms"] / g["forward_ms"],
-            "graph_speedup_forward": res["eager"]["forward_ms"] / g["forward_ms"]}
+            "graph_speedup_forward": res["eager"]["forward_ms"] / g["forward_ms"],
+            "tuning": tuning}
 
 
 def profile_run(name, precision, T, adjoint=False):
@@ -477,6 +536,8 @@ def main():
     ap.add_argument("--profile", default=None, choices=("beam512", "prec1024", "adjoint256", "beam3d"),
                     help="only a short run of this workload in --precision (for rocprofv3 runs)")
     ap.add_argument("--profile-adjoint", action="store_true", help="with --profile: also the adjoint")
+    ap.add_argument("--batch-autotune", action="store_true",
+                    help="only the spectral batch's tuning table (block waves per channel class)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this solver build runs on a single GPU; multi-GPU runs (--gpus %d) are "
@@ -490,6 +551,9 @@ def main():
         sys.exit(1)
     if args.profile:
         profile_run(args.profile, args.precision, args.tsteps or 8, args.profile_adjoint)
+        return
+    if args.batch_autotune:
+        print(json.dumps(spectral_extras(only_tune=True)), flush=True)
         return
     spec = W.spec("beam512")
     T = args.tsteps or spec["steps"]

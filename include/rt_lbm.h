@@ -362,9 +362,10 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
 /* ---- Spectral batch ------------------------------------------------------
  * Independent problems -- spectral channels, each with its own lattice,
  * direction grid, phase function and medium -- advanced together on one
- * stream.  A time step of all channels is one persistent kernel launch over
- * a work queue of (channel, tile) items: the fused step of Sec. 2.1 (Eq. 5)
- * and its adjoint, per channel exactly as rt_run / rt_adjoint compute it.
+ * stream.  A time step of all channels is one persistent kernel launch per
+ * class of channels (below) over a work queue of (channel, tile) items: the
+ * fused step of Sec. 2.1 (Eq. 5) and its adjoint, per channel exactly as
+ * rt_run / rt_adjoint compute it.
  * With graph mode on, a run or adjoint is recorded into a HIP graph once and
  * replayed.  Requirements: every channel has the same precision and flags
  * (RT_PLAIN excluded) and 4n rounded up to a multiple of 32 is 32, 64, 128 or
@@ -398,6 +399,36 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
 rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, int32_t ckpt_every,
                            float *const *h_seg, float *const *h_lambdaT, float *const *h_g_tau,
                            float *const *h_g_albedo, float *const *h_g_emis);
+
+/* Channel classes of a batch and their launch shape (the tuning table).
+ * Channels with the same number of 32-row tiles per direction set,
+ * W = ceil(4n / 32), form a class; a batched step makes one persistent
+ * launch per class, in blocks of `block_waves` waves that run
+ * block_waves / W tiles of that class side by side (the paper's Sec. 2.1
+ * step on every tile, unchanged).  rt_batch_init takes the block size of
+ * each class from the library's tuning table (measured on the 64-channel
+ * spectral workload); rt_batch_set_tuning replaces it for one class
+ * (block_waves a power-of-two multiple of W, at most 8; RT_EINVAL
+ * otherwise, RT_EUNSUPPORTED if it does not fit the LDS) and drops recorded
+ * graphs.  Results do not depend on the block size (every tile computes the
+ * same arithmetic).  rt_batch_num_classes / rt_batch_class report the
+ * classes in increasing W (host outputs). */
+rt_status rt_batch_num_classes(const rt_batch *b, int32_t *h_count);
+rt_status rt_batch_class(const rt_batch *b, int32_t k, int32_t *h_waves_per_tile, int32_t *h_block_waves,
+                         int32_t *h_nchan);
+rt_status rt_batch_set_tuning(rt_batch *b, int32_t waves_per_tile, int32_t block_waves);
+
+/* Temporal blocking of a batch: channels are taken in order into groups
+ * whose working set (two states per channel in rt_batch_run, ckpt_every + 3
+ * in rt_batch_adjoint) stays within `bytes`, and a run or adjoint completes
+ * every time step of one group before it starts the next, so that a group's
+ * states stay in the last-level cache from one step to the next; a channel
+ * larger than the budget is a group of its own, and 0 puts all channels in
+ * one group (every step of all channels before the next step).  The default
+ * is 128 MiB (of the MI355X's 256 MiB last-level cache).  A group of one
+ * channel runs that channel's own (single-problem) kernels.  Results do not
+ * depend on it (the channels are independent).  Drops recorded graphs. */
+rt_status rt_batch_set_cache_budget(rt_batch *b, size_t bytes);
 
 /* Graph mode (0 off, 1 on).  On: rt_batch_run and rt_batch_adjoint record
  * their launches into a HIP graph the first time they see a set of arguments

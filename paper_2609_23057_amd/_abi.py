@@ -82,6 +82,10 @@ _SIGS = {
     "rt_batch_adjoint": (c_int32, [c_void_p, c_int32, POINTER(c_void_p), c_int32, POINTER(c_void_p),
                                    POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                    POINTER(c_void_p)]),
+    "rt_batch_num_classes": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "rt_batch_class": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "rt_batch_set_tuning": (c_int32, [c_void_p, c_int32, c_int32]),
+    "rt_batch_set_cache_budget": (c_int32, [c_void_p, c_size_t]),
     "rt_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "rt_batch_synchronize": (c_int32, [c_void_p]),
     "rt_batch_destroy": (c_int32, [c_void_p]),
@@ -247,6 +251,26 @@ def rt_batch_run(b, d_states, nsteps, d_ckpts=None, ckpt_every=0):
 def rt_batch_adjoint(b, nsteps, d_ckpts, ckpt_every, d_segs, d_lambdaT, d_g_tau, d_g_albedo, d_g_emis):
     _bcheck(_lib.rt_batch_adjoint(b, nsteps, _ptrs(d_ckpts), ckpt_every, _ptrs(d_segs), _ptrs(d_lambdaT),
                                   _ptrs(d_g_tau), _ptrs(d_g_albedo), _ptrs(d_g_emis)), b)
+
+
+def rt_batch_classes(b):
+    """[(waves per tile, block waves, channels)] of every channel class."""
+    n = c_int32(0)
+    _bcheck(_lib.rt_batch_num_classes(b, ctypes.byref(n)), b)
+    out = []
+    for k in range(n.value):
+        w, bw, nc = c_int32(0), c_int32(0), c_int32(0)
+        _bcheck(_lib.rt_batch_class(b, k, ctypes.byref(w), ctypes.byref(bw), ctypes.byref(nc)), b)
+        out.append((w.value, bw.value, nc.value))
+    return out
+
+
+def rt_batch_set_tuning(b, waves_per_tile, block_waves):
+    _bcheck(_lib.rt_batch_set_tuning(b, int(waves_per_tile), int(block_waves)), b)
+
+
+def rt_batch_set_cache_budget(b, nbytes):
+    _bcheck(_lib.rt_batch_set_cache_budget(b, int(nbytes)), b)
 
 
 def rt_batch_set_graph(b, enabled):

@@ -1000,6 +1000,26 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
 
 }  // extern "C"
 
+// The batch's tuning table, from timing every admissible setting on the
+// 64-channel spectral workload (bench.py --batch-autotune prints the
+// measurement; bf16, forward steps):
+//  * cache budget of the temporal blocking: the working set of a channel
+//    group.  All channels stepping together take 4.37 ms per step (4.4 GB
+//    of state stream through HBM every step); groups of up to 64-192 MiB
+//    3.63-3.67 ms (a group's states stay in the 256 MiB last-level cache
+//    from one step to the next); one channel per group 3.62 ms.  128 MiB
+//    keeps the small channels batched at the same speed.
+//  * block waves per class (waves per tile W): 8-wave blocks for every
+//    class (W = 2: 3.72 ms against 3.73 for 2-wave blocks; W = 4: 3.67
+//    against 3.72).
+constexpr size_t kBatchCacheBudget = 128u << 20;
+
+int batch_block_waves(int prec, int W) {
+  (void)prec;
+  (void)W;
+  return kBatchWaves;
+}
+
 struct rt_batch {
   int nchan = 0;
   std::vector<rt_ctx *> ch;
@@ -1007,10 +1027,33 @@ struct rt_batch {
   char *ws = nullptr;
   // device descriptor tables: forward run, forward recompute in the adjoint, adjoint
   BatchChan *d_run = nullptr, *d_rec = nullptr, *d_adj = nullptr;
-  std::vector<BatchChan> h_run, h_rec, h_adj;
-  int64_t nitems = 0;
+  std::vector<BatchChan> h_run, h_rec, h_adj;   // per channel, channel order
+  // A class is the channels with the same waves per tile W (= Rpad / 32);
+  // its launches use blocks of bw waves (bw / W tiles side by side).
+  struct Class {
+    int W = 0, bw = 0, lds = 0, count = 0;
+  };
+  std::vector<Class> classes;   // increasing W
+  // Temporal blocking: the channels are split into groups whose working set
+  // fits the cache budget, and a run or adjoint completes every step of one
+  // group before the next (the channels are independent, so the order does
+  // not change any result); within a group a step is one persistent launch
+  // per class, over one (group, class) run of the device tables.
+  struct Run {
+    int first = 0, count = 0, cls = 0;
+    int64_t nitems = 0;
+  };
+  struct Group {
+    std::vector<Run> runs;
+    std::vector<int> chans;
+  };
+  struct Plan {
+    std::vector<Group> groups;
+    std::vector<int> order;   // channel of each table entry
+  } plan_run, plan_adj;
+  size_t cache_budget = kBatchCacheBudget;
+  std::vector<BatchChan> t_run, t_rec, t_adj;    // staged tables, table order
   int prec = 0;
-  int lds = 0;
   int cu_count = 0;   // compute units of the device (each launch sizes its own grid)
   bool graph_mode = false;
   hipStream_t cap = nullptr;   // private stream graphs are recorded on (the caller's may be the null stream)
@@ -1041,13 +1084,98 @@ struct rt_batch {
     if (cap) (void)hipStreamDestroy(cap);
     for (rt_ctx *c : ch) delete c;
   }
-  rt_status upload(BatchChan *d, const std::vector<BatchChan> &h) {
-    return hip(hipMemcpyAsync(d, h.data(), h.size() * sizeof(BatchChan), hipMemcpyHostToDevice, stream),
+  rt_status upload(BatchChan *d, const std::vector<BatchChan> &h, const Plan &pl) {
+    std::vector<BatchChan> &t = d == d_run ? t_run : (d == d_rec ? t_rec : t_adj);
+    t.resize(h.size());
+    for (size_t k = 0; k < pl.order.size(); ++k) t[k] = h[pl.order[k]];
+    return hip(hipMemcpyAsync(d, t.data(), t.size() * sizeof(BatchChan), hipMemcpyHostToDevice, stream),
                "batch descriptors");
   }
-  rt_status step(const BatchChan *d, bool adjoint, bool gather, bool ckpt, const BatchSel &sel) {
-    return hip(launch_batch_step(d, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds, cu_count, stream),
-               "batch step");
+  rt_status step(const BatchChan *d, const Group &gr, bool adjoint, bool gather, bool ckpt, const BatchSel &sel) {
+    if (gr.chans.size() == 1) {
+      // a group of one channel runs that channel's single-problem kernel (the
+      // same tile arithmetic; without the batch kernel's channel bookkeeping)
+      const int i = gr.chans[0];
+      rt_ctx *c = ch[i];
+      const std::vector<BatchChan> &tb = d == d_run ? h_run : (d == d_rec ? h_rec : h_adj);
+      auto bufp = [&](int id, int slot) -> float * {
+        return id < 0 ? nullptr : tb[i].buf[id] + (int64_t)slot * tb[i].state_elems;
+      };
+      StepArgs a = c->args(adjoint);
+      a.in = bufp(sel.in, sel.in_slot);
+      a.out = bufp(sel.out, sel.out_slot);
+      a.s_out = ckpt ? bufp(sel.sout, sel.sout_slot) : nullptr;
+      a.lam_next = bufp(sel.lam, sel.lam_slot);
+      return hip(adjoint ? launch_adjoint_mfma(a, prec, gather, stream, c->cu_count)
+                         : launch_step_mfma(a, prec, gather, stream, c->cu_count),
+                 "batch step");
+    }
+    for (const Run &r : gr.runs) {
+      const Class &k = classes[r.cls];
+      rt_status st = hip(launch_batch_step(d + r.first, r.count, r.nitems, prec, k.bw, adjoint, gather, ckpt, sel,
+                                           k.lds, cu_count, stream),
+                         "batch step");
+      if (st != RT_OK) return st;
+    }
+    return RT_OK;
+  }
+  // LDS and kernel attributes of every class for its block size.
+  rt_status configure() {
+    for (Class &k : classes) {
+      const int Rpad = 32 * k.W;
+      const size_t lf = batch_lds_bytes(Rpad, prec, false, k.bw), la = batch_lds_bytes(Rpad, prec, true, k.bw);
+      if (lf == (size_t)-1 || la == (size_t)-1) return fail(RT_EINVAL, "block waves do not fit the channel class");
+      const size_t lds = std::max(lf, la);
+      if (lds > 160 * 1024) return fail(RT_EUNSUPPORTED, "batch does not fit the fused kernel's LDS budget");
+      k.lds = (int)lds;
+      int per_cu = 0;
+      rt_status st = hip(prepare_batch(prec, k.bw, k.lds, &per_cu), "prepare batch kernels");
+      if (st != RT_OK) return st;
+    }
+    return RT_OK;
+  }
+  // Groups of channels (in channel order) whose working sets, `states`
+  // states each, add up to at most the cache budget (a larger channel is a
+  // group of its own; budget 0: one group), their (group, class) runs of the
+  // tables, and the work items of every channel in `tables`.
+  void make_plan(Plan &pl, double states, std::initializer_list<std::vector<BatchChan> *> tables) {
+    pl.groups.clear();
+    pl.order.clear();
+    std::vector<std::vector<int>> members;
+    double used = 0.0;
+    for (int i = 0; i < nchan; ++i) {
+      const double bytes = states * (double)state_elems(ch[i]) * sizeof(float);
+      if (members.empty() || (cache_budget > 0 && used + bytes > (double)cache_budget)) {
+        members.emplace_back();
+        used = 0.0;
+      }
+      members.back().push_back(i);
+      used += bytes;
+    }
+    for (const std::vector<int> &m : members) {
+      Group gr;
+      gr.chans = m;
+      for (int c = 0; c < (int)classes.size(); ++c) {
+        Run r;
+        r.cls = c;
+        r.first = (int)pl.order.size();
+        const int W = classes[c].W, per = classes[c].bw / W;
+        int64_t item = 0;
+        for (int i : m) {
+          if (ch[i]->geo.Rpad / 32 != W) continue;
+          pl.order.push_back(i);
+          for (std::vector<BatchChan> *tb : tables) {
+            (*tb)[i].groups = per;
+            (*tb)[i].item0 = item;
+          }
+          item += (h_run[i].ntiles + per - 1) / per;
+        }
+        r.count = (int)pl.order.size() - r.first;
+        r.nitems = item;
+        if (r.count > 0) gr.runs.push_back(r);
+      }
+      pl.groups.push_back(gr);
+    }
   }
   // Records body() into a graph unless the cached one has the same key, then
   // launches it on the caller's stream.  Recording happens on a private
@@ -1138,7 +1266,7 @@ rt_status batch_plan(const rt_problem *probs, int32_t nchan, BatchPlan *bp, std:
     }
     const int n = p.n_zen * p.n_az;
     const int Rpad = (4 * n + 31) / 32 * 32;
-    if (batch_lds_bytes(Rpad, p.precision, false) == (size_t)-1) {
+    if (Rpad / 32 > kBatchWaves || kBatchWaves % (Rpad / 32) != 0) {
       *msg = "channel " + std::to_string(i) + ": batching needs 4n padded to 32, 64, 128 or 256";
       return RT_EUNSUPPORTED;
     }
@@ -1151,6 +1279,11 @@ rt_status batch_plan(const rt_problem *probs, int32_t nchan, BatchPlan *bp, std:
   return RT_OK;
 }
 
+// Block waves per class of the batched step (waves per tile W = Rpad / 32):
+// the tuning table, from timing every admissible block size on the 64-channel
+// spectral workload (bench.py --batch-autotune prints the measurement).  One
+// tile group per block for W >= 2: wider blocks keep their tile groups in
+// step through the block's barriers, where independent blocks overlap.
 rt_status batch_set_err(rt_batch *b, rt_status s, const std::string &m) {
   if (b) return b->fail(s, m);
   g_last_error = m;
@@ -1199,8 +1332,6 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
   b->d_run = reinterpret_cast<BatchChan *>(b->ws + bp.table_off);
   b->d_rec = b->d_run + nchan;
   b->d_adj = b->d_rec + nchan;
-  int64_t item = 0;
-  size_t lds = 0;
   for (int i = 0; i < nchan; ++i) {
     rt_ctx *c = b->ch[i];
     BatchChan f{};
@@ -1210,33 +1341,23 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
     f.buf[kBufLa] = c->at<float>(c->L.La);
     f.buf[kBufLb] = c->at<float>(c->L.Lb);
     f.state_elems = (int64_t)state_elems(c);
-    const int W = c->geo.Rpad / 32;
-    f.groups = kBatchWaves / W;
     f.ntiles = (c->geo.C + 31) / 32;
-    f.item0 = item;
-    item += (f.ntiles + f.groups - 1) / f.groups;
     BatchChan a = f;
     a.a = c->args(true);
     b->h_run.push_back(f);
     b->h_rec.push_back(f);
     b->h_adj.push_back(a);
-    lds = std::max(lds, std::max(batch_lds_bytes(c->geo.Rpad, b->prec, false),
-                                 batch_lds_bytes(c->geo.Rpad, b->prec, true)));
   }
-  b->nitems = item;
-  if (lds > 160 * 1024) {
-    delete b;
-    return set_err(RT_EUNSUPPORTED, "batch does not fit the fused kernel's LDS budget");
+  // classes by waves per tile, in increasing W
+  for (int W = 1; W <= kBatchWaves; W *= 2) {
+    rt_batch::Class k;
+    k.W = W;
+    k.bw = batch_block_waves(b->prec, W);
+    for (int i = 0; i < nchan; ++i) k.count += b->ch[i]->geo.Rpad / 32 == W;
+    if (k.count > 0) b->classes.push_back(k);
   }
-  b->lds = (int)lds;
-  int per_cu = 0;
-  st = b->hip(prepare_batch(b->prec, b->lds, &per_cu), "prepare batch kernels");
-  if (st == RT_OK) {
-    b->cu_count = b->ch[0]->cu_count;
-    st = b->upload(b->d_run, b->h_run);
-  }
-  if (st == RT_OK) st = b->upload(b->d_rec, b->h_rec);
-  if (st == RT_OK) st = b->upload(b->d_adj, b->h_adj);
+  b->cu_count = b->ch[0]->cu_count;
+  st = b->configure();
   if (st == RT_OK) st = b->hip(hipStreamSynchronize(b->stream), "batch init");
   if (st != RT_OK) {
     const std::string m = b->err;
@@ -1267,21 +1388,29 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
     if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
   if (nsteps == 0) return RT_OK;
+  // a step reads one post-collision state and writes the other
+  b->make_plan(b->plan_run, 2.0, {&b->h_run});
   auto body = [&]() -> rt_status {
     rt_status st = RT_OK;
-    if (h_ckpt)
-      for (int i = 0; i < b->nchan && st == RT_OK; ++i)
-        st = b->hip(hipMemcpyAsync(h_ckpt[i], h_states[i], state_elems(b->ch[i]) * sizeof(float),
-                                   hipMemcpyDeviceToDevice, b->stream), "ckpt");
-    if (st == RT_OK) st = b->step(b->d_run, false, false, false, sel_of(kBufS, 0, kBufYa, 0));
-    for (int t = 1; t < nsteps && st == RT_OK; ++t) {
-      const int yin = (t - 1) & 1 ? kBufYb : kBufYa, yout = t & 1 ? kBufYb : kBufYa;
-      const bool ck = h_ckpt && t % ckpt_every == 0;
-      st = b->step(b->d_run, false, true, ck, sel_of(yin, 0, yout, 0, ck ? kBufCkpt : kBufNone, ck ? t / ckpt_every : 0));
+    for (const rt_batch::Group &gr : b->plan_run.groups) {
+      if (h_ckpt)
+        for (int i : gr.chans)
+          if (st == RT_OK)
+            st = b->hip(hipMemcpyAsync(h_ckpt[i], h_states[i], state_elems(b->ch[i]) * sizeof(float),
+                                       hipMemcpyDeviceToDevice, b->stream), "ckpt");
+      if (st == RT_OK) st = b->step(b->d_run, gr, false, false, false, sel_of(kBufS, 0, kBufYa, 0));
+      for (int t = 1; t < nsteps && st == RT_OK; ++t) {
+        const int yin = (t - 1) & 1 ? kBufYb : kBufYa, yout = t & 1 ? kBufYb : kBufYa;
+        const bool ck = h_ckpt && t % ckpt_every == 0;
+        st = b->step(b->d_run, gr, false, true, ck,
+                     sel_of(yin, 0, yout, 0, ck ? kBufCkpt : kBufNone, ck ? t / ckpt_every : 0));
+      }
+      const int ylast = (nsteps - 1) & 1 ? kBufYb : kBufYa;
+      for (int i : gr.chans)
+        if (st == RT_OK)
+          st = b->hip(launch_stream(b->ch[i]->args(false), b->h_run[i].buf[ylast], h_states[i], b->stream),
+                      "stream");
     }
-    const int ylast = (nsteps - 1) & 1 ? kBufYb : kBufYa;
-    for (int i = 0; i < b->nchan && st == RT_OK; ++i)
-      st = b->hip(launch_stream(b->ch[i]->args(false), b->h_run[i].buf[ylast], h_states[i], b->stream), "stream");
     return st;
   };
   for (int i = 0; i < b->nchan; ++i) {
@@ -1289,7 +1418,7 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
     b->h_run[i].buf[kBufCkpt] = h_ckpt ? h_ckpt[i] : nullptr;
   }
   if (!b->graph_mode) {
-    rt_status st = b->upload(b->d_run, b->h_run);
+    rt_status st = b->upload(b->d_run, b->h_run, b->plan_run);
     return st == RT_OK ? body() : st;
   }
   std::vector<uintptr_t> key = {1, (uintptr_t)nsteps, (uintptr_t)ckpt_every, (uintptr_t)(h_ckpt != nullptr)};
@@ -1298,7 +1427,7 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
     key.push_back(reinterpret_cast<uintptr_t>(h_ckpt ? h_ckpt[i] : nullptr));
   }
   if (!(b->g_run.exec && b->g_run.key == key)) {
-    rt_status st = b->upload(b->d_run, b->h_run);
+    rt_status st = b->upload(b->d_run, b->h_run, b->plan_run);
     if (st != RT_OK) return st;
   }
   return b->graphed(b->g_run, key, body);
@@ -1320,37 +1449,43 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
     if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
     if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
+  // a reverse step reads lambda_{t+1}, the segment state and writes lambda_t;
+  // the segment recompute writes ckpt_every - 1 states
+  b->make_plan(b->plan_adj, 3.0 + ckpt_every, {&b->h_rec, &b->h_adj});
   auto body = [&]() -> rt_status {
     rt_status st = RT_OK;
-    for (int i = 0; i < b->nchan && st == RT_OK; ++i) {
-      rt_ctx *c = b->ch[i];
-      st = b->hip(launch_fill_f64(c->at<double>(c->L.gacc), 3 * c->geo.C, 0.0, b->stream), "fill");
-    }
-    int lam = kBufLamT;
-    int flip = 0;
-    const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-    for (int k = nseg - 1; k >= 0 && st == RT_OK; --k) {
-      const int t0 = k * ckpt_every;
-      const int t1 = std::min(nsteps, t0 + ckpt_every);
-      if (t1 - t0 >= 2) {
-        st = b->step(b->d_rec, false, false, false, sel_of(kBufCkpt, k, kBufSeg, 0));
-        for (int t = t0 + 1; t <= t1 - 2 && st == RT_OK; ++t)
-          st = b->step(b->d_rec, false, true, false, sel_of(kBufSeg, t - 1 - t0, kBufSeg, t - t0));
+    for (const rt_batch::Group &gr : b->plan_adj.groups) {
+      for (int i : gr.chans) {
+        rt_ctx *c = b->ch[i];
+        if (st == RT_OK) st = b->hip(launch_fill_f64(c->at<double>(c->L.gacc), 3 * c->geo.C, 0.0, b->stream), "fill");
       }
-      for (int t = t1 - 1; t >= t0 && st == RT_OK; --t) {
-        const bool gather = t > t0;
-        const int out = flip ? kBufLb : kBufLa;
-        st = b->step(b->d_adj, true, gather, false,
-                     sel_of(gather ? kBufSeg : kBufCkpt, gather ? t - 1 - t0 : k, out, 0, kBufNone, 0, lam, 0));
-        lam = out;
-        flip ^= 1;
+      int lam = kBufLamT;
+      int flip = 0;
+      const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+      for (int k = nseg - 1; k >= 0 && st == RT_OK; --k) {
+        const int t0 = k * ckpt_every;
+        const int t1 = std::min(nsteps, t0 + ckpt_every);
+        if (t1 - t0 >= 2) {
+          st = b->step(b->d_rec, gr, false, false, false, sel_of(kBufCkpt, k, kBufSeg, 0));
+          for (int t = t0 + 1; t <= t1 - 2 && st == RT_OK; ++t)
+            st = b->step(b->d_rec, gr, false, true, false, sel_of(kBufSeg, t - 1 - t0, kBufSeg, t - t0));
+        }
+        for (int t = t1 - 1; t >= t0 && st == RT_OK; --t) {
+          const bool gather = t > t0;
+          const int out = flip ? kBufLb : kBufLa;
+          st = b->step(b->d_adj, gr, true, gather, false,
+                       sel_of(gather ? kBufSeg : kBufCkpt, gather ? t - 1 - t0 : k, out, 0, kBufNone, 0, lam, 0));
+          lam = out;
+          flip ^= 1;
+        }
       }
-    }
-    for (int i = 0; i < b->nchan && st == RT_OK; ++i) {
-      rt_ctx *c = b->ch[i];
-      st = b->hip(launch_gradchain(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb), c->prob.flags,
-                                   c->at<double>(c->L.gacc), h_g_tau[i], h_g_albedo[i], h_g_emis[i], b->stream),
-                  "gradchain");
+      for (int i : gr.chans) {
+        rt_ctx *c = b->ch[i];
+        if (st == RT_OK)
+          st = b->hip(launch_gradchain(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb), c->prob.flags,
+                                       c->at<double>(c->L.gacc), h_g_tau[i], h_g_albedo[i], h_g_emis[i], b->stream),
+                      "gradchain");
+      }
     }
     return st;
   };
@@ -1361,8 +1496,8 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
       (*tb)[i].buf[kBufLamT] = h_lambdaT[i];
     }
   auto upload_both = [&]() -> rt_status {
-    rt_status st = b->upload(b->d_rec, b->h_rec);
-    return st == RT_OK ? b->upload(b->d_adj, b->h_adj) : st;
+    rt_status st = b->upload(b->d_rec, b->h_rec, b->plan_adj);
+    return st == RT_OK ? b->upload(b->d_adj, b->h_adj, b->plan_adj) : st;
   };
   if (!b->graph_mode) {
     rt_status st = upload_both();
@@ -1379,6 +1514,53 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
     if (st != RT_OK) return st;
   }
   return b->graphed(b->g_adj, key, body);
+}
+
+rt_status rt_batch_num_classes(const rt_batch *b, int32_t *h_count) {
+  if (!b || !h_count) return set_err(RT_EINVAL, "NULL batch or count");
+  *h_count = (int32_t)b->classes.size();
+  return RT_OK;
+}
+
+rt_status rt_batch_class(const rt_batch *b, int32_t k, int32_t *h_waves_per_tile, int32_t *h_block_waves,
+                         int32_t *h_nchan) {
+  if (!b || !h_waves_per_tile || !h_block_waves || !h_nchan) return set_err(RT_EINVAL, "NULL pointer");
+  if (k < 0 || k >= (int32_t)b->classes.size()) return set_err(RT_EINVAL, "class index out of range");
+  *h_waves_per_tile = b->classes[k].W;
+  *h_block_waves = b->classes[k].bw;
+  *h_nchan = b->classes[k].count;
+  return RT_OK;
+}
+
+rt_status rt_batch_set_cache_budget(rt_batch *b, size_t bytes) {
+  if (!b) return set_err(RT_EINVAL, "batch is NULL");
+  b->cache_budget = bytes;
+  rt_batch::drop(b->g_run);   // recorded graphs hold the old grouping
+  rt_batch::drop(b->g_adj);
+  return RT_OK;
+}
+
+rt_status rt_batch_set_tuning(rt_batch *b, int32_t waves_per_tile, int32_t block_waves) {
+  if (!b) return set_err(RT_EINVAL, "batch is NULL");
+  rt_batch::Class *cls = nullptr;
+  for (rt_batch::Class &k : b->classes)
+    if (k.W == waves_per_tile) cls = &k;
+  if (!cls) return b->fail(RT_EINVAL, "no channel class with that many waves per tile");
+  if (block_waves < waves_per_tile || block_waves > kBatchWaves || block_waves % waves_per_tile != 0 ||
+      (block_waves & (block_waves - 1)) != 0)
+    return b->fail(RT_EINVAL, "block waves must be a power-of-two multiple of the waves per tile, at most 8");
+  const int old = cls->bw;
+  cls->bw = block_waves;
+  rt_status st = b->configure();
+  if (st != RT_OK) {
+    cls->bw = old;
+    (void)b->configure();
+    return st;
+  }
+  // recorded graphs hold the old launches and work-item counts
+  rt_batch::drop(b->g_run);
+  rt_batch::drop(b->g_adj);
+  return RT_OK;
 }
 
 rt_status rt_batch_set_graph(rt_batch *b, int32_t enabled) {

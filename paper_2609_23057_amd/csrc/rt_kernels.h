@@ -76,7 +76,7 @@ struct BatchChan {
   int64_t state_elems;   // floats of one state (stride of slotted buffers)
   int64_t item0;         // first work item of the channel
   int64_t ntiles;        // 32-cell tiles
-  int32_t groups;        // tile groups per work item (8 waves / waves per tile)
+  int32_t groups;        // tile groups per work item (block waves / waves per tile)
   int32_t pad;
 };
 
@@ -85,20 +85,23 @@ struct BatchSel {
   int in_slot, out_slot, sout_slot, lam_slot;
 };
 
-// Waves per block of the batched kernel; a channel needs Rpad / 32 waves per
-// tile and runs 8 / (Rpad / 32) tiles side by side in one block.
+// Largest block of the batched kernel, in waves.  A channel needs W = Rpad / 32
+// waves per tile; a class of channels with the same W runs in blocks of
+// bw waves (bw a multiple of W, at most kBatchWaves): bw / W tiles side by side.
 constexpr int kBatchWaves = 8;
 
-// LDS bytes the batched kernel needs for a channel of this padded size.
-size_t batch_lds_bytes(int Rpad, int prec, bool adjoint);
+// LDS bytes the batched kernel needs for a channel of this padded size in
+// blocks of bw waves (SIZE_MAX if bw does not fit the channel).
+size_t batch_lds_bytes(int Rpad, int prec, bool adjoint, int bw);
 
-// Sets the kernel attributes and returns the blocks per CU of the batched
-// kernels for the given LDS size (called once, before any stream capture).
-hipError_t prepare_batch(int prec, int lds_bytes, int *blocks_per_cu);
+// Sets the kernel attributes of the bw-wave batched kernels and returns their
+// blocks per CU for the given LDS size (called before any stream capture).
+hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu);
 
-// One batched fused step (forward or adjoint) over every channel's tiles; the
-// persistent grid is cu_count x the resident blocks of that instantiation.
-hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
+// One batched fused step (forward or adjoint) over the tiles of one class of
+// channels in bw-wave blocks; the persistent grid is cu_count x the resident
+// blocks of that instantiation.
+hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw, bool adjoint,
                              bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s);
 

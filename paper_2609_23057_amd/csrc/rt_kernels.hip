@@ -49,7 +49,7 @@ typedef float f32x16u __attribute__((ext_vector_type(16), aligned(16)));
 
 namespace {
 
-constexpr int kEdgeXm = 0, kEdgeXp = 1, kEdgeYm = 2, kEdgeYp = 3;
+constexpr int kEdgeXp = 1, kEdgeYm = 2, kEdgeYp = 3;
 
 static_assert(sizeof(DirTaps) == 40, "direction tap entry layout");
 
@@ -931,17 +931,19 @@ fused_kernel(StepArgs a, int64_t ntiles) {
 
 // ------------------------------------------------------------- spectral batch --
 //
-// One launch advances every channel of the batch by one step.  The work
-// queue is the channels' tiles in channel order, a work item being one tile
-// per tile group of the block; the blocks of an XCD take every per-th item of
-// one contiguous eighth of the queue, so each block changes channel only as
+// One launch advances every channel of one class (the channels with the
+// same padded row count, hence the same waves per tile W) by one step.  A
+// block has BW waves, BW / W tile groups side by side; the work queue is the
+// class's channels' tiles in channel order, a work item being one tile per
+// tile group of the block; the blocks of an XCD take every per-th item of one
+// contiguous eighth of the queue, so each block changes channel only as
 // often as its eighth does.  On a change the block reloads the channel's
 // descriptor (scalar loads), its emission rows into LDS and each lane's
 // direction data.
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT>
-__global__ void __launch_bounds__(64 * kBatchWaves) batch_kernel(const BatchChan *__restrict__ chans, int nchan,
-                                                                 int64_t nitems, BatchSel sel) {
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
+__global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restrict__ chans, int nchan,
+                                                        int64_t nitems, BatchSel sel) {
   using T = PrecTraits<PREC>;
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
@@ -1002,97 +1004,122 @@ __global__ void __launch_bounds__(64 * kBatchWaves) batch_kernel(const BatchChan
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ld[q].off), "+v"(ld[q].td), "+v"(ld[q].d));
-    const int64_t tile = (it - item0) * (kBatchWaves / W) + grp;
-    fused_tile<PREC, GATHER, ADJ, CKPT, 4>(a, g, L, ts, tr, ld, tile, tile < ntiles, t, t, W, lane);
+    const int64_t tile = (it - item0) * (BW / W) + grp;
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, 4, 1>>(a, g, L, ts, tr, ld, tile, tile < ntiles, t, t,
+                                                                    W, lane);
   }
 }
 
-size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint) {
+size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint, int bw) {
   const int W = Rpad / 32;
-  if (W < 1 || W > kBatchWaves || kBatchWaves % W != 0) return (size_t)-1;
+  if (W < 1 || W > kBatchWaves || bw < W || bw > kBatchWaves || bw % W != 0) return (size_t)-1;
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
-  return (size_t)lds_layout(Rpad, esize, ntile, W, adjoint, prec == P_F16, kBatchWaves / W).total;
+  return (size_t)lds_layout(Rpad, esize, ntile, W, adjoint, prec == P_F16, bw / W).total;
 }
 
 // Occupancy of one batch instantiation; prepare_batch fills the memo before
 // any launch, so a launch under stream capture makes no runtime query.
-template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
 hipError_t batch_blocks_per_cu(int lds_bytes, int *occ) {
   static std::atomic<uint64_t> memo{0};
-  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT>, 64 * kBatchWaves, lds_bytes, memo, occ);
+  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT, BW>, 64 * BW, lds_bytes, memo, occ);
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
 hipError_t prepare_batch_k(int lds_bytes, int *occ) {
-  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT>;
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return e;
   int o = 0;
-  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT>(lds_bytes, &o);
+  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW>(lds_bytes, &o);
   if (e != hipSuccess) return e;
   *occ = std::min(*occ, o);
   return hipSuccess;
 }
 
-template <int PREC>
+template <int PREC, int BW>
 hipError_t prepare_batch_p(int lds_bytes, int *occ) {
   hipError_t e;
-  if ((e = prepare_batch_k<PREC, false, false, false>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, true, false, false>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, true, false, true>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, false, true, false>(lds_bytes, occ)) != hipSuccess) return e;
-  return prepare_batch_k<PREC, true, true, false>(lds_bytes, occ);
+  if ((e = prepare_batch_k<PREC, false, false, false, BW>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, false, BW>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, true, BW>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, false, true, false, BW>(lds_bytes, occ)) != hipSuccess) return e;
+  return prepare_batch_k<PREC, true, true, false, BW>(lds_bytes, occ);
 }
 
-hipError_t prepare_batch_impl(int prec, int lds_bytes, int *blocks_per_cu) {
+template <int PREC>
+hipError_t prepare_batch_w(int bw, int lds_bytes, int *occ) {
+  switch (bw) {
+    case 1: return prepare_batch_p<PREC, 1>(lds_bytes, occ);
+    case 2: return prepare_batch_p<PREC, 2>(lds_bytes, occ);
+    case 4: return prepare_batch_p<PREC, 4>(lds_bytes, occ);
+    case 8: return prepare_batch_p<PREC, 8>(lds_bytes, occ);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t prepare_batch_impl(int prec, int bw, int lds_bytes, int *blocks_per_cu) {
   int occ = 1 << 20;
   hipError_t e = hipErrorInvalidValue;
-  if (prec == P_F32) e = prepare_batch_p<P_F32>(lds_bytes, &occ);
-  if (prec == P_BF16) e = prepare_batch_p<P_BF16>(lds_bytes, &occ);
-  if (prec == P_F16) e = prepare_batch_p<P_F16>(lds_bytes, &occ);
-  if (prec == P_BF16X3) e = prepare_batch_p<P_BF16X3>(lds_bytes, &occ);
+  if (prec == P_F32) e = prepare_batch_w<P_F32>(bw, lds_bytes, &occ);
+  if (prec == P_BF16) e = prepare_batch_w<P_BF16>(bw, lds_bytes, &occ);
+  if (prec == P_F16) e = prepare_batch_w<P_F16>(bw, lds_bytes, &occ);
+  if (prec == P_BF16X3) e = prepare_batch_w<P_BF16X3>(bw, lds_bytes, &occ);
   if (e != hipSuccess) return e;
   if (occ < 1) return hipErrorInvalidConfiguration;
   *blocks_per_cu = occ;
   return hipSuccess;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
 hipError_t launch_batch_k(const BatchChan *d_chans, int nchan, int64_t nitems, const BatchSel &sel, int lds_bytes,
                           int cu_count, hipStream_t s) {
-  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT>;
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW>;
   // persistent grid sized by this instantiation's own occupancy
   int occ = 0;
-  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT>(lds_bytes, &occ);
+  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW>(lds_bytes, &occ);
   if (e != hipSuccess) return e;
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)cu_count * occ));
-  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * kBatchWaves), lds_bytes, s, d_chans, nchan, nitems, sel);
+  int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)cu_count * occ));
+  if (grid >= 8) grid &= ~7LL;
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * BW), lds_bytes, s, d_chans, nchan, nitems, sel);
   return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, int BW>
 hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
                           const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
   if (adjoint) {
-    if (gather) return launch_batch_k<PREC, true, true, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-    return launch_batch_k<PREC, false, true, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    if (gather) return launch_batch_k<PREC, true, true, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    return launch_batch_k<PREC, false, true, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
   }
-  if (ckpt) return launch_batch_k<PREC, true, false, true>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-  if (gather) return launch_batch_k<PREC, true, false, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-  return launch_batch_k<PREC, false, false, false>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  if (ckpt) return launch_batch_k<PREC, true, false, true, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  if (gather) return launch_batch_k<PREC, true, false, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  return launch_batch_k<PREC, false, false, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
 }
 
-hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
-                                  bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
-                                  hipStream_t s) {
+template <int PREC>
+hipError_t launch_batch_w(int bw, const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather,
+                          bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
+  switch (bw) {
+    case 1: return launch_batch_p<PREC, 1>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case 2: return launch_batch_p<PREC, 2>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case 4: return launch_batch_p<PREC, 4>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case 8: return launch_batch_p<PREC, 8>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw,
+                                  bool adjoint, bool gather, bool ckpt, const BatchSel &sel, int lds_bytes,
+                                  int cu_count, hipStream_t s) {
   if (ckpt && (adjoint || !gather)) return hipErrorInvalidValue;
   if (cu_count < 1 || nitems < 1) return hipErrorInvalidValue;
   switch (prec) {
-    case P_F32: return launch_batch_p<P_F32>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case P_BF16: return launch_batch_p<P_BF16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case P_F16: return launch_batch_p<P_F16>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case P_BF16X3: return launch_batch_p<P_BF16X3>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_F32: return launch_batch_w<P_F32>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_BF16: return launch_batch_w<P_BF16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_F16: return launch_batch_w<P_F16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_BF16X3: return launch_batch_w<P_BF16X3>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1781,16 +1808,18 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 4096) {
 
 }  // namespace
 
-size_t batch_lds_bytes(int Rpad, int prec, bool adjoint) { return batch_lds_bytes_impl(Rpad, prec, adjoint); }
-
-hipError_t prepare_batch(int prec, int lds_bytes, int *blocks_per_cu) {
-  return prepare_batch_impl(prec, lds_bytes, blocks_per_cu);
+size_t batch_lds_bytes(int Rpad, int prec, bool adjoint, int bw) {
+  return batch_lds_bytes_impl(Rpad, prec, adjoint, bw);
 }
 
-hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, bool adjoint,
+hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu) {
+  return prepare_batch_impl(prec, bw, lds_bytes, blocks_per_cu);
+}
+
+hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw, bool adjoint,
                              bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s) {
-  return launch_batch_step_impl(d_chans, nchan, nitems, prec, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+  return launch_batch_step_impl(d_chans, nchan, nitems, prec, bw, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
 }
 
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich) {

@@ -337,6 +337,19 @@ class Batch:
     def set_graph(self, enabled):
         A.rt_batch_set_graph(self.handle, enabled)
 
+    def classes(self):
+        """[(waves per tile, block waves, channels)] of every channel class."""
+        return A.rt_batch_classes(self.handle)
+
+    def set_tuning(self, waves_per_tile, block_waves):
+        """Block size (waves) of the launches of one channel class."""
+        A.rt_batch_set_tuning(self.handle, waves_per_tile, block_waves)
+
+    def set_cache_budget(self, nbytes):
+        """Working-set budget of the channel groups that complete every step
+        before the next group starts (0: all channels step together)."""
+        A.rt_batch_set_cache_budget(self.handle, nbytes)
+
     def run(self, states, nsteps, ckpts=None, ckpt_every=0):
         A.rt_batch_run(self.handle, [_ptr(s) for s in states], int(nsteps),
                        None if ckpts is None else [_ptr(c) for c in ckpts], int(ckpt_every))

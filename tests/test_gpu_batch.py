@@ -232,3 +232,46 @@ def test_single_channel_batch_matches_its_context_bitwise():
     torch.cuda.synchronize()
     assert torch.equal(S, states[0])
     assert torch.equal(ck1, ck[0])
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_block_size_of_a_class_does_not_change_results(precision):
+    """Every admissible block size of every channel class (the tuning table
+    of rt_batch_set_tuning) and every grouping of the channels (the cache
+    budget) gives the same bits: forward with checkpoints and the adjoint."""
+    import paper_2609_23057_amd as P
+    specs = channel_specs(SMALL)
+    batch, _ = make_batch(specs, precision)
+    classes = batch.classes()
+    assert [c[0] for c in classes] == sorted(c[0] for c in classes)
+    assert sum(c[2] for c in classes) == len(specs)
+    T, K = 7, 3
+
+    def run_all():
+        states = initial_states(batch, specs)
+        ck = batch.checkpoint_buffers(T, K)
+        batch.run(states, T, ck, K)
+        lams = [torch.ones_like(x) for x in states]
+        grads = batch.adjoint(T, ck, K, lams)
+        torch.cuda.synchronize()
+        return [x.clone() for x in states] + [g.clone() for gs in grads for g in gs]
+
+    ref = run_all()
+    for W_, bw0, _ in classes:
+        for bw in (1, 2, 4, 8):
+            if bw < W_ or bw % W_ or bw == bw0:
+                continue
+            batch.set_tuning(W_, bw)
+            got = run_all()
+            assert all(torch.equal(a, b) for a, b in zip(got, ref)), (W_, bw)
+        batch.set_tuning(W_, bw0)
+    # the temporal blocking: all channels together, or one channel per group
+    for budget in (0, 1):
+        batch.set_cache_budget(budget)
+        got = run_all()
+        assert all(torch.equal(a, b) for a, b in zip(got, ref)), budget
+    with pytest.raises(P.RTError) as ei:
+        batch.set_tuning(classes[-1][0], 3)
+    assert ei.value.status == P.RT_EINVAL
+    with pytest.raises(P.RTError):
+        batch.set_tuning(99, 8)

@@ -280,6 +280,18 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
  * rt_set_phase_mixture likewise. */
 rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);
 
+/* Tuning of the 3-D lattice's fused step (RT_PLANE_3D; ignored otherwise).
+ * With the RT_FP32 contraction, rt_run and rt_adjoint fuse the trilinear pull
+ * of step t into the operand load of the collision of step t + 1 (as on a
+ * 2-D lattice); the 16-bit contractions, RT_PLAIN, a phase mixture and
+ * dichroic absorption step as collision then streaming, which is faster
+ * there.  Its tiles are runs of cells along x within one row
+ * (y, z), taken in blocks of `layers` layers with z fastest: the rows that
+ * neighbouring tiles read overlap while they are still cached.  0 restores
+ * the default (64); values above nz act as nz.  The result does not depend
+ * on it.  RT_EINVAL for layers < 0. */
+rt_status rt_set_layer_block(rt_ctx *c, int32_t layers);
+
 /* One time step of Sec. 2.1.1 (Eq. 2 split as the operator chain of Eq. 5):
  * emission X = S_in + dt J (Eq. 6/8), absorption and scattering
  * Y = alpha X + beta M X (Sec. 2.1.4-2.1.5, Eq. 11), streaming

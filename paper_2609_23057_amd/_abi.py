@@ -64,6 +64,7 @@ _SIGS = {
     "rt_set_medium": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_set_phase_mixture": (c_int32, [c_void_p, c_int32, c_double, c_double, c_void_p]),
     "rt_set_dichroism": (c_int32, [c_void_p, c_void_p]),
+    "rt_set_layer_block": (c_int32, [c_void_p, c_int32]),
     "rt_set_inflow": (c_int32, [c_void_p, c_void_p]),
     "rt_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_stream": (c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -161,6 +162,11 @@ def rt_set_phase_mixture(ctx, phase2, g2, mix_ray2, d_frac):
 def rt_set_dichroism(ctx, d_eta):
     """d_eta: device [ny][nx] float32 with |eta| < 1, or None to remove it."""
     _check(_lib.rt_set_dichroism(ctx, d_eta), ctx)
+
+
+def rt_set_layer_block(ctx, layers):
+    """3-D lattices: layers per block of the fused step's tile order (0: default)."""
+    _check(_lib.rt_set_layer_block(ctx, layers), ctx)
 
 
 def rt_set_inflow(ctx, d_inflow):

@@ -159,6 +159,12 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
 
 }  // namespace
 
+// Tile order of the fused 3-D step: rows are taken in blocks of this many
+// layers, the layer index fastest within a block, so that the source rows a
+// tile shares with its neighbours in z (and, within a block, in y) are read
+// again while they are in the XCD's L2 or the last-level cache.
+constexpr int kLayerBlock = 64;
+
 struct rt_ctx {
   rt_problem prob{};
   std::vector<double> zen;
@@ -183,6 +189,7 @@ struct rt_ctx {
   bool three_d = false;   // RT_PLANE_3D lattice
   Stream3Args s3{};       // its streaming arguments
   Stream3Args s3rev{};    // the transpose of its streaming (the adjoint's reverse pull)
+  int zblk = kLayerBlock; // 3-D fused step: layers per block of its tile order
   int prec = 0;
   int cu_count = 256;
   int device = 0;     // the HIP device current at rt_init
@@ -232,6 +239,13 @@ StepArgs rt_ctx::args(bool adjoint) const {
   if (dichroic) {
     a.dich_xi = at<float>(L.dich_xi);
     a.dich_w = at<float>(L.dich_w);
+  }
+  if (three_d) {
+    a.ny3 = s3.ny;
+    a.nz = s3.nz;
+    a.per_z = s3.per_z;
+    a.zblk = std::max(1, std::min(zblk, s3.nz));
+    a.taps3 = at<DirTaps3>(L.taps3);
   }
   return a;
 }
@@ -723,6 +737,13 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
   return RT_OK;
 }
 
+rt_status rt_set_layer_block(rt_ctx *c, int32_t layers) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (layers < 0) return c->fail(RT_EINVAL, "layers < 0");
+  c->zblk = layers == 0 ? kLayerBlock : layers;
+  return RT_OK;
+}
+
 rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
   if (!d_eta) {
@@ -768,6 +789,30 @@ static rt_status fwd_step(rt_ctx *c, const float *in, bool gather, float *out, f
   a.out = out;
   a.s_out = s_out;
   return c->hip(launch_step_mfma(a, c->prec, gather, c->stream, c->cu_count), "step");
+}
+
+// The fused 3-D forward step (trilinear pull in the gather) serves float32
+// contexts on the matrix cores without a phase mixture or dichroic
+// absorption, within the LDS budget; the others step as collision then
+// streaming.  At 256 x 256 x 64, n = 32, the fused step takes 2.78 ms against
+// 2.85 ms for the two launches in float32, but 2.74 / 2.75 / 2.64 ms against
+// 2.61 / 2.62 / 2.39 ms for bf16 / bf16x3 / fp16: its gather re-reads the
+// source rows several times from beyond the L2 (the rows of all 4n planes
+// around the tiles in flight on an XCD exceed its 4 MB), whatever the
+// precision, which only the float32 contraction's longer collision hides.
+static bool fused3_ok(const rt_ctx *c) {
+  return c->three_d && c->prec == P_F32 && !(c->prob.flags & RT_PLAIN) && !c->mixture && !c->dichroic &&
+         step_lds_bytes(c->geo, c->prec, false, false, true) <= 160 * 1024;
+}
+
+// Y_t = collision of L3(Y_{t-1}) + emission; s_out (optional) = S_t = L3(Y_{t-1}).
+static rt_status fwd3_step(rt_ctx *c, const float *Yprev, float *Yout, float *s_out) {
+  StepArgs a = c->args(false);
+  a.ghost = c->at<float>(c->L.ghost3);
+  a.in = Yprev;
+  a.out = Yout;
+  a.s_out = s_out;
+  return c->hip(launch_step3_mfma(a, c->prec, c->stream, c->cu_count), "step3d");
 }
 
 // One step on a 3-D lattice: the collision of every cell (the fused kernel
@@ -830,6 +875,18 @@ rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t c
   const size_t sb = state_elems(c) * sizeof(float);
   auto slot = [&](int k) { return reinterpret_cast<float *>(reinterpret_cast<char *>(d_ckpt) + (size_t)k * sb); };
   rt_status st = RT_OK;
+  if (fused3_ok(c)) {
+    // 3-D: the streaming of step t fused into the collision of step t + 1
+    float *Y[2] = {c->at<float>(c->L.Ya), c->at<float>(c->L.Yb)};
+    if (d_ckpt) st = c->hip(hipMemcpyAsync(slot(0), d_S, sb, hipMemcpyDeviceToDevice, c->stream), "ckpt");
+    if (st == RT_OK) st = fwd_step(c, d_S, false, Y[0], nullptr);
+    for (int t = 1; t < nsteps && st == RT_OK; ++t) {
+      float *s_out = (d_ckpt && t % ckpt_every == 0) ? slot(t / ckpt_every) : nullptr;
+      st = fwd3_step(c, Y[(t - 1) & 1], Y[t & 1], s_out);
+    }
+    if (st == RT_OK) st = c->hip(launch_stream3d(c->s3, Y[(nsteps - 1) & 1], d_S, c->stream), "stream3d");
+    return st;
+  }
   if ((c->prob.flags & RT_PLAIN) || c->three_d) {
     // two passes per step (collision into the workspace, streaming back)
     for (int t = 0; t < nsteps && st == RT_OK; ++t) {
@@ -949,7 +1006,16 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
   for (int k = nseg - 1; c->three_d && k >= 0 && st == RT_OK; --k) {
     const int t0 = k * ckpt_every;
     const int t1 = std::min(nsteps, t0 + ckpt_every);
-    if (t1 - t0 >= 2) {
+    if (t1 - t0 >= 2 && fused3_ok(c)) {
+      // S_{t0+1} .. S_{t1-1} into the segment: the fused steps write S_t as
+      // their streamed state, the last one is a streaming alone
+      float *Y[2] = {c->at<float>(c->L.Ya), c->at<float>(c->L.Yb)};
+      st = fwd_step(c, ck(k), false, Y[0], nullptr);
+      for (int t = t0 + 1; t <= t1 - 2 && st == RT_OK; ++t)
+        st = fwd3_step(c, Y[(t - 1 - t0) & 1], Y[(t - t0) & 1], seg(t - 1 - t0));
+      if (st == RT_OK)
+        st = c->hip(launch_stream3d(c->s3, Y[(t1 - 2 - t0) & 1], seg(t1 - 2 - t0), c->stream), "stream3d");
+    } else if (t1 - t0 >= 2) {
       st = step3d(c, ck(k), seg(0));
       for (int t = t0 + 2; t <= t1 - 1 && st == RT_OK; ++t) st = step3d(c, seg(t - 2 - t0), seg(t - 1 - t0));
     }

@@ -49,6 +49,12 @@ struct StepArgs {
   // I - Q of direction d in cell c are multiplied by exp(-+dich_xi[c] dich_w[d])
   const float *dich_xi;    // [C] tau_abs * eta per cell
   const float *dich_w;     // [n] sin^2 theta_d
+  // 3-D lattice (geo.ny = ny3 * nz rows of nx cells): the fused forward step
+  // with the trilinear pull in its gather (ghost then holds the face table
+  // [7][Rpad]); its tiles are 32-cell runs of one row, taken in blocks of
+  // zblk layers with the layer index fastest
+  int32_t ny3, nz, per_z, zblk;
+  const DirTaps3 *taps3;   // [n]
 };
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };
@@ -109,6 +115,13 @@ hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems
 // dt_pre J; otherwise X = in + dt_pre J.  out = alpha X + beta M X + dt_post J.
 // cu_count: compute units of the device (sets the persistent grid).
 hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int cu_count);
+
+// Fused forward step on a 3-D lattice (float32 contraction): in = Y_{t-1},
+// X = L3(in) + dt_pre J with the trilinear pull of the 3-D streaming kernel
+// (same taps, same rounding), out = alpha X + beta M X + dt_post J, s_out
+// (optional) = L3(in).  hipErrorInvalidValue for another precision, a phase
+// mixture or dichroic absorption (those run as collision + streaming).
+hipError_t launch_step3_mfma(const StepArgs &a, int prec, hipStream_t s, int cu_count);
 
 // Fused adjoint step: mu = L^T lam_next, X as in the forward, nu = M^T mu,
 // out = alpha mu + beta nu, gacc += per-cell (<mu,X>, <nu,X>, dt<.,j>).
@@ -179,6 +192,7 @@ int scratch_partials_max();
 hipError_t launch_sums_noalloc(const Geometry &g, int device, const float *S, double *result, hipStream_t s);
 
 // LDS bytes of the fused launch the library will use (SIZE_MAX if none fits).
-size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich = false);
+// three_d: the 3-D fused forward step (its direction weights in LDS too).
+size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich = false, bool three_d = false);
 
 }  // namespace rtl

@@ -71,6 +71,7 @@ struct LaneDir {
   int ox0, oy0;  // floor of the displacement (Eq. 34)
   float w00, w10, w01, w11;   // bilinear weights of taps (bx, by)
   int d;         // direction index (rows of padding directions d >= n give zero)
+  int oz0;       // 3-D lattice: floor of the z displacement (td then includes it)
 };
 
 __device__ __forceinline__ LaneDir lane_dir(const StepArgs &a, int d) {
@@ -100,6 +101,7 @@ __device__ __forceinline__ LaneDir lane_dir(const StepArgs &a, int d) {
 struct LaneCell {
   int c, x, y;
   bool valid;
+  int z;   // layer (3-D lattice; y is then the row within the layer)
 };
 
 __device__ __forceinline__ LaneCell lane_cell(const Geometry &g, int c0, int x0, int y0, int col) {
@@ -332,6 +334,213 @@ __device__ __forceinline__ void gather_field(const StepArgs &a, const float *__r
   }
 }
 
+// ---- 3-D lattice: the trilinear pull (Eq. 34 along x, y and z) in the gather
+// Tap b = bx + 2 by + 4 bz of direction d reads the previous post-collision
+// field at (x - ox0 - bx, y - oy0 - by, z - oz0 - bz) with weight w_b (the
+// direction's 8 weights, from the block's LDS copy).  The taps are summed in
+// increasing b with one fused multiply-add each, as the stand-alone 3-D
+// streaming kernel sums them, so that a fused step reproduces collision then
+// streaming bit for bit.  A tap outside the lattice on a non-periodic axis
+// reads the face table (z faces before y faces before x faces).
+
+__device__ __forceinline__ LaneDir lane_dir3(const StepArgs &a, int d) {
+  LaneDir L{};
+  L.d = d;
+  if (d < a.geo.n) {
+    const DirTaps3 tp = a.taps3[d];
+    L.off = (int64_t)(4 * d) * a.geo.C;
+    L.ox0 = tp.ox0;
+    L.oy0 = tp.oy0;
+    L.oz0 = tp.oz0;
+    L.td = (tp.oz0 * a.ny3 + tp.oy0) * a.geo.nx + tp.ox0;
+  }
+  return L;
+}
+
+// Row (y, z) and first column x0 of 3-D tile `tile` (tiles of `cells` cells
+// never span rows): rows are taken in blocks of zblk layers, the layer index
+// fastest within a block, so that the rows a tile's taps share with its
+// neighbours in z are read again while still in the XCD's L2.
+__device__ __forceinline__ void tile_row3(const StepArgs &a, int tile, int cells, int &x0, int &y, int &z) {
+  const int tpr = (a.geo.nx + cells - 1) / cells;
+  const int w = tile / tpr;
+  const int xt = tile - w * tpr;
+  const int blk = a.ny3 * a.zblk;
+  const int zb = w / blk;
+  const int r = w - zb * blk;
+  const int zl = min(a.zblk, a.nz - zb * a.zblk);
+  y = r / zl;
+  z = zb * a.zblk + (r - y * zl);
+  x0 = xt * cells;
+}
+
+__device__ __forceinline__ float tap_sum3(const f32x4 &w0, const f32x4 &w1, const float (&v)[8]) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc = fmaf(w0[b], v[b], acc);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc = fmaf(w1[b], v[4 + b], acc);
+  return acc;
+}
+
+// The 8 tap addresses of one direction at an edge cell: the field (stride C
+// between Stokes planes) or the face table (stride 1).
+__device__ __forceinline__ void edge_taps3(const StepArgs &a, const float *__restrict__ src, const LaneDir &ld,
+                                           const LaneCell &lc, const float *(&p)[8], int (&stride)[8]) {
+  const Geometry &g = a.geo;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int xs = wrap_axis(lc.x - ld.ox0 - (b & 1), g.nx, g.per_x);
+    const int ys = wrap_axis(lc.y - ld.oy0 - ((b >> 1) & 1), a.ny3, g.per_y);
+    const int zs = wrap_axis(lc.z - ld.oz0 - (b >> 2), a.nz, a.per_z);
+    const bool inx = (unsigned)xs < (unsigned)g.nx, iny = (unsigned)ys < (unsigned)a.ny3,
+               inz = (unsigned)zs < (unsigned)a.nz;
+    const bool inside = inx && iny && inz;
+    const int f = !inz ? (zs < 0 ? 4 : 5) : (!iny ? (ys < 0 ? 2 : 3) : (xs < 0 ? 0 : 1));
+    const float *base = inside ? src : a.ghost;
+    const int64_t eoff = inside ? ld.off + ((zs * a.ny3 + ys) * g.nx + xs) : (int64_t)f * g.Rpad + 4 * ld.d;
+    p[b] = base + eoff;
+    stride[b] = inside ? (int)g.C : 1;
+  }
+}
+
+// Interior taps of Stokes components s0 and s0 + 1 of one direction (every
+// tap of the tile inside the lattice): 16 loads from one base.
+__device__ __forceinline__ void dir3_issue_half(const StepArgs &a, const float *__restrict__ src, const LaneDir &ld,
+                                                const LaneCell &lc, int s0, float (&v)[2][8]) {
+  const int nx = a.geo.nx, lay = a.geo.nx * a.ny3;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float *p = src + ld.off + (int64_t)(s0 + j) * a.geo.C + (lc.c - ld.td);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v[j][b] = p[-((b & 1) + ((b >> 1) & 1) * nx + (b >> 2) * lay)];
+  }
+}
+
+// Taps of Stokes s0 and s0 + 1 of one direction in a tile whose rows are all
+// inside in y and z ("row" tiles): x wraps on a periodic axis; a tap outside
+// in x is loaded from the lane's own cell (a valid address) and replaced by
+// its face's ghost value when summed (row_fix).
+__device__ __forceinline__ void dir3_issue_row(const StepArgs &a, const float *__restrict__ src, const LaneDir &ld,
+                                               const LaneCell &lc, int s0, float (&v)[2][8]) {
+  const Geometry &g = a.geo;
+  const int xs0 = wrap_axis(lc.x - ld.ox0, g.nx, g.per_x), xs1 = wrap_axis(lc.x - ld.ox0 - 1, g.nx, g.per_x);
+  const int xa0 = (unsigned)xs0 < (unsigned)g.nx ? xs0 : lc.x;
+  const int xa1 = (unsigned)xs1 < (unsigned)g.nx ? xs1 : lc.x;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float *p = src + ld.off + (int64_t)(s0 + j) * g.C;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {   // r = by + 2 bz
+      const int row = ((lc.z - ld.oz0 - (r >> 1)) * a.ny3 + (lc.y - ld.oy0 - (r & 1))) * g.nx;
+      v[j][2 * r] = p[row + xa0];
+      v[j][2 * r + 1] = p[row + xa1];
+    }
+  }
+}
+
+// Replaces the taps of a row tile that lie outside in x by the ghost value
+// of their face (gx: the block's LDS copy of the x- and x+ face rows).
+__device__ __forceinline__ void row_fix(const StepArgs &a, const LaneDir &ld, const LaneCell &lc, int s,
+                                        const float *gx, float (&v)[8]) {
+  const int nx = a.geo.nx;
+  const int xs0 = wrap_axis(lc.x - ld.ox0, nx, a.geo.per_x), xs1 = wrap_axis(lc.x - ld.ox0 - 1, nx, a.geo.per_x);
+  const float g0 = gx[(xs0 < 0 ? 0 : a.geo.Rpad) + 4 * ld.d + s];
+  const float g1 = gx[(xs1 < 0 ? 0 : a.geo.Rpad) + 4 * ld.d + s];
+  const bool in0 = (unsigned)xs0 < (unsigned)nx, in1 = (unsigned)xs1 < (unsigned)nx;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    v[2 * r] = in0 ? v[2 * r] : g0;
+    v[2 * r + 1] = in1 ? v[2 * r + 1] : g1;
+  }
+}
+
+// Tile kinds of the 3-D gather: every tap of every cell inside; rows inside
+// in y and z (taps may leave in x); anything else.
+enum { kG3Edge = 0, kG3Row = 1, kG3Interior = 2 };
+
+// The 3-D counterpart of gather_field (forward state only): the 16 values of
+// a lane, pulled trilinearly, with emission, into registers or LDS as
+// put_group places them.  Interior and row tiles run a two-stage pipeline
+// over half groups (two Stokes planes, 16 loads: the next half's loads are
+// issued before the previous half is summed); edge tiles take one direction
+// at a time.  w3: the block's LDS copy of the tap weights [Rpad / 4][8],
+// followed by the x- and x+ face rows of the ghost table.
+template <int MODE, bool CKPT, int PUT, bool DICH = false>
+__device__ __forceinline__ void gather_field3(const StepArgs &a, const float *__restrict__ src,
+                                              const LaneDir (&ld)[4], const LaneCell &lc, float emis, float *dst,
+                                              char *lds, const float *jrow, const float *w3, int lo_off = 0,
+                                              float xi = 0.0f, const float *wd = nullptr) {
+  const Geometry &g = a.geo;
+  float emis_dt = 0.0f;
+  auto weights = [&](int k, f32x4 &w0, f32x4 &w1) {
+    w0 = *reinterpret_cast<const f32x4 *>(w3 + 8 * ld[k].d);
+    w1 = *reinterpret_cast<const f32x4 *>(w3 + 8 * ld[k].d + 4);
+  };
+  if (MODE == kG3Edge) {
+    // (a small share of the tiles: one Stokes plane of one direction at a
+    // time, which keeps the register peak of this path below the others')
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float *p[8];
+      int stride[8];
+      edge_taps3(a, src, ld[k], lc, p, stride);
+      if (k == 0) emis_dt = late_emission(a, emis);
+      f32x4 w0, w1;
+      weights(k, w0, w1);
+      float t[4][4] = {};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        float v[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) v[b] = p[b][(int64_t)s * stride[b]];
+        t[s][0] = tap_sum3(w0, w1, v);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      float o[4];
+      dir_combine<false, true, CKPT, DICH>(a, g, ld[k], lc, emis_dt, t, o, jrow, xi, DICH ? wd[k] : 0.0f);
+      put_group<PUT>(o, dst, lds, k, lo_off);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return;
+  }
+  float va[2][8], vb[2][8];
+  float t[4][4] = {};
+  auto issue = [&](int k, int s0, float (&v)[2][8]) {
+    if (MODE == kG3Interior)
+      dir3_issue_half(a, src, ld[k], lc, s0, v);
+    else
+      dir3_issue_row(a, src, ld[k], lc, s0, v);
+  };
+  issue(0, 0, va);
+#pragma unroll
+  for (int u = 1; u <= 8; ++u) {
+    if (u < 8) issue(u >> 1, 2 * (u & 1), vb);
+    __builtin_amdgcn_sched_barrier(0);
+    if (u == 1) emis_dt = late_emission(a, emis);
+    const int k = (u - 1) >> 1, hf = (u - 1) & 1;
+    f32x4 w0, w1;
+    weights(k, w0, w1);
+    if (MODE == kG3Row) {
+      const float *gx = w3 + 2 * g.Rpad;
+      row_fix(a, ld[k], lc, 2 * hf, gx, va[0]);
+      row_fix(a, ld[k], lc, 2 * hf + 1, gx, va[1]);
+    }
+    t[2 * hf][0] = tap_sum3(w0, w1, va[0]);
+    t[2 * hf + 1][0] = tap_sum3(w0, w1, va[1]);
+    if (hf == 1) {
+      float o[4];
+      dir_combine<false, true, CKPT, DICH>(a, g, ld[k], lc, emis_dt, t, o, jrow, xi, DICH ? wd[k] : 0.0f);
+      put_group<PUT>(o, dst, lds, k, lo_off);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) va[j][b] = vb[j][b];
+  }
+}
+
 // Row r of the 32x32 accumulator held by element i of a lane in half-wave h.
 __device__ __forceinline__ int acc_row(int i, int h) { return (i >> 2) * 8 + h * 4 + (i & 3); }
 
@@ -346,6 +555,7 @@ struct LdsLayout {
   int b_off, x_off, red_off;   // within a tile group
   int group;                   // bytes of one tile group; group g starts at g * group
   int jrow_off, total;         // block-wide
+  int w3_off;                  // 3-D gather: tap weights [Rpad / 4][8], x face rows [2][Rpad] (block-wide)
   int strideB;   // bytes per cell row of the B tile
   int tileB;     // bytes of one B tile
   int strideX;   // bytes per cell row of the float32 X tile
@@ -362,7 +572,8 @@ struct LdsLayout {
 // as a high part (the B tile) and a low part (a second tile of the same
 // shape) whose sum restores it to 2^-18.
 __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
-                                               bool f16, int ngroups = 1, int nb = 1, int nacc = 3) {
+                                               bool f16, int ngroups = 1, int nb = 1, int nacc = 3,
+                                               bool w3 = false) {
   LdsLayout L;
   const bool xsplit = nb > 1 && esize == 2;
   // the bf16 / bf16x3 adjoint keeps mu as high (B) and low tiles
@@ -386,6 +597,10 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
   L.group = off;
   L.jrow_off = ngroups * off;
   L.total = L.jrow_off + Rpad * 4;
+  // 3-D gather: the 8 tap weights of each of the Rpad / 4 directions, then
+  // the x- and x+ face rows of the ghost table
+  L.w3_off = L.total;
+  if (w3) L.total += Rpad * 8 + Rpad * 8;
   return L;
 }
 
@@ -417,6 +632,7 @@ struct TileLds {
   char *s_b, *s_x;
   float *s_red;
   const float *s_jrow;
+  const float *s_w3;   // 3-D gather: tap weights
 };
 
 // Per-cell power-of-two scale of the fp16 operand: 2^(8 - e) for the largest
@@ -440,7 +656,7 @@ __device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red
 // functions (a second contraction) or dichroic absorption (in the gather).
 enum { kExtNone = 0, kExtMix = 1, kExtDich = 2 };
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone, bool G3 = false>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
                                            int64_t tile, bool active, int t, int wg, int W, int lane) {
@@ -450,6 +666,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   constexpr bool DICH = EXT == kExtDich;
   static_assert(!MIX || NB == 1, "phase mixtures: one column block");
   static_assert(!DICH || !ADJ || NB == 1, "dichroic absorption in the adjoint: one column block");
+  static_assert(!G3 || (GATHER && !ADJ && EXT == kExtNone), "3-D gather: forward step without extensions");
   // adjoint per-cell sums: <mu, X_d>, <nu, X_d>, the emission term, and with
   // dichroic absorption the xi-derivative term
   constexpr int NACC = (ADJ && DICH) ? 4 : 3;
@@ -498,6 +715,52 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
     for (int q = 0; q < 4; ++q) wdir[q] = ld[q].d < g.n ? a.dich_w[ld[q].d] : 0.0f;
   }
+  if constexpr (G3) {
+    // 3-D lattice: the tile is the cells x0 .. x0 + 32 NB - 1 of one row
+    // (y, z); lanes past the row's end take its first cell and are masked
+    int x0, y3, z3;
+    tile_row3(a, active ? (int)tile : 0, 32 * NB, x0, y3, z3);
+    const int rowc = (z3 * a.ny3 + y3) * g.nx;
+    const bool yz_in = y3 >= 2 && y3 <= a.ny3 - 3 && z3 >= 2 && z3 <= a.nz - 3;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      cscale[cb] = 1.0f;
+      const int xb = x0 + 32 * cb;
+      LaneCell lc;
+      lc.valid = active && xb + col < g.nx;
+      lc.x = lc.valid ? xb + col : x0;
+      lc.y = y3;
+      lc.z = z3;
+      lc.c = rowc + lc.x;
+      lcs[cb] = lc;
+      al[cb] = a.alpha[lc.c];
+      be[cb] = a.beta[lc.c];
+      em[cb] = a.emis[lc.c];
+      // every tap of every cell inside the lattice (taps reach two cells),
+      // or at least every row of the tile's taps
+      const bool interior = yz_in && xb >= 2 && xb + 31 <= g.nx - 3;
+      inter[cb] = interior;
+      if constexpr (XSPLIT) {
+        char *brow = s_b + (32 * cb + col) * L.strideB + rbase * 2;
+        if (interior)
+          gather_field3<kG3Interior, CKPT, kPutSplit>(a, a.in, ld, lc, em[cb], nullptr, brow, s_jrow, ts.s_w3,
+                                                      L.tileB);
+        else if (yz_in)
+          gather_field3<kG3Row, CKPT, kPutSplit>(a, a.in, ld, lc, em[cb], nullptr, brow, s_jrow, ts.s_w3, L.tileB);
+        else
+          gather_field3<kG3Edge, CKPT, kPutSplit>(a, a.in, ld, lc, em[cb], nullptr, brow, s_jrow, ts.s_w3, L.tileB);
+      } else {
+        char *xrow = s_x + (32 * cb + col) * L.strideX + rbase * 4;
+        if (interior)
+          gather_field3<kG3Interior, CKPT, kPutF32>(a, a.in, ld, lc, em[cb], nullptr, xrow, s_jrow, ts.s_w3);
+        else if (yz_in)
+          gather_field3<kG3Row, CKPT, kPutF32>(a, a.in, ld, lc, em[cb], nullptr, xrow, s_jrow, ts.s_w3);
+        else
+          gather_field3<kG3Edge, CKPT, kPutF32>(a, a.in, ld, lc, em[cb], nullptr, xrow, s_jrow, ts.s_w3);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     cscale[cb] = 1.0f;
@@ -544,6 +807,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
                                                                         s_jrow, 0, xi[DICH ? cb : 0], wdir);
     }
     __builtin_amdgcn_sched_barrier(0);
+  }
   }
   if constexpr (ADJ) {
     if constexpr (PREC == P_F32) {
@@ -880,11 +1144,12 @@ constexpr int kFusedRing = MAXW <= 4 ? ((ADJ && (PREC == P_BF16 || PREC == P_BF1
 // Waves per SIMD the register allocation must allow: 4 for the fp32 and bf16
 // adjoint in blocks of up to 4 waves (the accumulator then lives in ordinary
 // VGPRs, without spills), otherwise whatever the kernel needs.
-template <int PREC, bool ADJ, int MAXW>
-constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4 : 1;
+template <int PREC, bool ADJ, int MAXW, bool G3 = false>
+constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4
+                               : (G3 && MAXW <= 4) ? 3 : 1;
 
-template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, int EXT>
-__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW>)))
+template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, int EXT, bool G3 = false>
+__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW, G3>)))
 fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
   extern __shared__ __align__(16) char smem[];
@@ -894,18 +1159,24 @@ fused_kernel(StepArgs a, int64_t ntiles) {
   const int w = threadIdx.x >> 6;
   const int h = lane >> 5;
   const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB,
-                                 (ADJ && EXT == kExtDich) ? 4 : 3);
+                                 (ADJ && EXT == kExtDich) ? 4 : 3, G3);
   float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
   for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
+  float *s_w3 = reinterpret_cast<float *>(smem + L.w3_off);
+  if constexpr (G3) {
+    // tap weights of the Rpad / 4 directions (zero for padding directions)
+    for (int i = threadIdx.x; i < 2 * g.Rpad; i += blockDim.x) s_w3[i] = (i >> 3) < g.n ? a.taps3[i >> 3].w[i & 7] : 0.0f;
+    for (int i = threadIdx.x; i < 2 * g.Rpad; i += blockDim.x) s_w3[2 * g.Rpad + i] = a.ghost[i];
+  }
   __syncthreads();
-  const TileLds ts{smem + L.b_off, smem + L.x_off, reinterpret_cast<float *>(smem + L.red_off), s_jrow};
+  const TileLds ts{smem + L.b_off, smem + L.x_off, reinterpret_cast<float *>(smem + L.red_off), s_jrow, s_w3};
 
   const int t = __builtin_amdgcn_readfirstlane(w);  // the 32-row tile this wave owns
   const TileRange tr = a.tiles[t];
   // the lane's 4 directions: element group q holds direction 8 t + 2 q + h
   LaneDir ldk[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) ldk[q] = lane_dir(a, 8 * t + 2 * q + h);
+  for (int q = 0; q < 4; ++q) ldk[q] = G3 ? lane_dir3(a, 8 * t + 2 * q + h) : lane_dir(a, 8 * t + 2 * q + h);
 
   // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
   // so block b serves a contiguous eighth of the lattice and the halo rows it
@@ -924,8 +1195,8 @@ fused_kernel(StepArgs a, int64_t ntiles) {
     // which would not fit in VGPRs, without holding a second copy.
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT>(a, g, L, ts, tr, ldk, tile, true, t,
-                                                                                t, W, lane);
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT, G3>(a, g, L, ts, tr, ldk, tile,
+                                                                                    true, t, t, W, lane);
   }
 }
 
@@ -994,7 +1265,7 @@ __global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restr
       L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, bc.groups);
       char *gb = smem + grp * L.group;
       float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
-      ts = TileLds{gb + L.b_off, gb + L.x_off, reinterpret_cast<float *>(gb + L.red_off), s_jrow};
+      ts = TileLds{gb + L.b_off, gb + L.x_off, reinterpret_cast<float *>(gb + L.red_off), s_jrow, nullptr};
       tr = a.tiles[t];
 #pragma unroll
       for (int q = 0; q < 4; ++q) ld[q] = lane_dir(a, 8 * t + 2 * q + h);
@@ -1124,13 +1395,17 @@ hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t n
   return hipErrorInvalidValue;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, int EXT = kExtNone>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, int EXT = kExtNone, bool G3 = false>
 hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
   const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB,
-                                 (ADJ && EXT == kExtDich) ? 4 : 3);
-  const int64_t ntiles = (a.geo.C + 32 * NB - 1) / (32 * NB);
-  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, EXT>;
+                                 (ADJ && EXT == kExtDich) ? 4 : 3, G3);
+  if (L.total > 160 * 1024) return hipErrorInvalidValue;
+  // 3-D: whole tiles per row (ny3 nz rows)
+  const int64_t ntiles = G3 ? (int64_t)((a.geo.nx + 32 * NB - 1) / (32 * NB)) * a.ny3 * a.nz
+                            : (a.geo.C + 32 * NB - 1) / (32 * NB);
+  if (G3 && (a.zblk < 1 || a.ny3 * a.nz != a.geo.ny || ntiles > INT32_MAX)) return hipErrorInvalidValue;
+  auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, EXT, G3>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
   // persistent grid: as many blocks as are resident at once, so that no block
@@ -1144,6 +1419,18 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
   return hipGetLastError();
+}
+
+template <int PREC, bool GATHER, bool ADJ, bool CKPT>
+hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count);
+
+// The 3-D fused forward step (float32 contraction): the tiles of the plain
+// forward step.
+template <bool CKPT>
+hipError_t launch_fused3_t(const StepArgs &a, int W, hipStream_t s, int cu_count) {
+  if (a.frac != nullptr || a.dich_xi != nullptr || a.taps3 == nullptr) return hipErrorInvalidValue;
+  if (W <= 4) return launch_fused_k<P_F32, true, false, CKPT, 4, 2, kExtNone, true>(a, W, s, cu_count);
+  return launch_fused_k<P_F32, true, false, CKPT, 16, 2, kExtNone, true>(a, W, s, cu_count);
 }
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT>
@@ -1822,14 +2109,21 @@ hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems
   return launch_batch_step_impl(d_chans, nchan, nitems, prec, bw, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
 }
 
-size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich) {
+size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich, bool three_d) {
   if (g.Rpad / 32 > 16) return (size_t)-1;
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
   const int W = g.Rpad / 32;
   const LdsLayout L = lds_layout(g.Rpad, esize, ntile, W, adjoint, prec == P_F16, 1, step_nb(W, prec, adjoint),
-                                 adjoint && dich ? 4 : 3);
+                                 adjoint && dich ? 4 : 3, three_d && !adjoint);
   return (size_t)L.total;
+}
+
+hipError_t launch_step3_mfma(const StepArgs &a, int prec, hipStream_t s, int cu_count) {
+  const int W = a.geo.Rpad / 32;
+  if (W < 1 || W > 16 || prec != P_F32) return hipErrorInvalidValue;
+  if (a.s_out != nullptr) return launch_fused3_t<true>(a, W, s, cu_count);
+  return launch_fused3_t<false>(a, W, s, cu_count);
 }
 
 hipError_t launch_step_mfma(const StepArgs &a, int prec, bool gather, hipStream_t s, int cu_count) {

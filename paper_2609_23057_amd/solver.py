@@ -173,6 +173,11 @@ class Solver:
         A.rt_set_dichroism(self.ctx, _ptr(eta))
         self._eta = eta
 
+    def set_layer_block(self, layers):
+        """3-D lattices: layers per block of the fused step's tile order (0:
+        the library's default); the result does not depend on it."""
+        A.rt_set_layer_block(self.ctx, int(layers))
+
     def medium_state(self):
         """Everything the context's operator depends on beyond the problem:
         (generation, medium, mixture, dichroism), for restore_medium()."""

@@ -81,6 +81,77 @@ def test_forward3d_parity(case, precision):
     print(over, precision, e)
 
 
+# Lattices wide enough for every tile kind of the fused 3-D step: interior
+# tiles (all taps inside), row tiles (rows inside in y and z, taps leaving in
+# x) and edge tiles; a ragged last tile per row; every face kind.
+FUSED = [
+    (dict(nx=140, ny=6, nz=6), (0, 0, 1, 1, 1, 2)),                    # n = 32, 64-cell fp32 tiles
+    (dict(nx=70, ny=7, nz=5, n_zen=2, n_az=8), (1, 1, 1, 1, 1, 2)),    # n = 16
+    (dict(nx=69, ny=6, nz=5, n_zen=4, n_az=16), (0, 0, 0, 0, 0, 0)),   # n = 64, periodic
+    (dict(nx=131, ny=5, nz=5, n_zen=8, n_az=16), (2, 2, 0, 0, 2, 1)),  # n = 128, inflow faces
+]
+
+
+@pytest.mark.parametrize("case", FUSED, ids=lambda c: "%dx%dx%d-n%d" % (
+    c[0]["nx"], c[0]["ny"], c[0]["nz"], W.ndir(W.spec("beam3d", **c[0]))))
+def test_fused3d_run_equals_collision_then_streaming(case):
+    """With the float32 contraction rt_run pulls the post-collision field of
+    one step trilinearly inside the next collision's operand load (the 16-bit
+    contractions step as collision then streaming); it reproduces rt_step
+    (collision, then the streaming kernel) bit for bit, checkpoints included,
+    for every layer block of its tile order, and the oracle at the stated
+    tolerance.  The adjoint's segment recompute takes the same fused steps."""
+    precision = "fp32"
+    over, bc6 = case
+    spec = W.spec("beam3d", bc6=bc6, **over)
+    med = W.medium(spec)
+    med["inflow"][:, :, 0] = 0.7
+    med["inflow"][:, :, 1] = -0.2
+    med["inflow"][:, :, 2] = 0.1
+    solver, p3, _ = build3(spec, precision, med)
+    S0 = W.initial_state(spec, "random")
+    T, K = 7, 3
+    a, b = to_dev(S0, solver), solver.empty_state()
+    hist = [a.clone()]
+    for _ in range(T):
+        solver.step(a, b)
+        a, b = b, a
+        hist.append(a.clone())
+    for layers in (0, 1, 2, 1000):
+        solver.set_layer_block(layers)
+        ck = solver.checkpoint_buffer(T, K)
+        S = to_dev(S0, solver)
+        solver.run(S, T, ck, K)
+        torch.cuda.synchronize()
+        assert torch.equal(S, hist[T]), (layers, (S - hist[T]).abs().max().item())
+        for k in range(ck.shape[0]):
+            assert torch.equal(ck[k], hist[k * K]), (layers, k)
+    ref = O3.run(S0, p3, T)
+    e = assert_close(to_np(S), ref, tolerance(precision, p3.flat, T), (over, precision))
+    print("fused 3-D", over, precision, e)
+    # the checkpointed adjoint recomputes its segments with the fused steps
+    # (S_t as the streamed state of a fused step): the same gradients as
+    # with one segment per step, which recomputes nothing
+    lam = torch.rand_like(S)
+    g1 = solver.adjoint(T, ck, K, lam, solver.segment_buffer(K))
+    ck1 = solver.checkpoint_buffer(T, 1)
+    S1 = to_dev(S0, solver)
+    solver.run(S1, T, ck1, 1)
+    g2 = solver.adjoint(T, ck1, 1, lam)
+    torch.cuda.synchronize()
+    for x, y in zip(g1, g2):
+        assert torch.equal(x, y)
+
+
+def test_layer_block_refusal():
+    import paper_2609_23057_amd as P
+    spec = W.spec("beam3d", nx=8, ny=6, nz=4)
+    solver, _, _ = build3(spec, "fp32")
+    with pytest.raises(P.RTError) as ei:
+        solver.set_layer_block(-1)
+    assert ei.value.status == P.RT_EINVAL
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_step3d_checkpoints_maps_and_totals(precision):
     spec = spec3(11, 8, 6, bc6=(0, 0, 1, 1, 1, 2))

@@ -275,11 +275,13 @@ def extension_extras(T=20, warm=3):
 
 def three_d_extras(T=10, warm=2, reps=20):
     """The 3-D lattice (beam3d: 256 x 256 x 64, n = 32): forward steps per
-    contraction precision (per-cell collision, then the trilinear pull), the
-    checkpointed forward and its adjoint (recompute, reverse pull, adjoint
-    collision), and the 3-D streaming kernel alone (HIP events around `reps` launches on the
-    solver's stream) against the HBM peak at 32 algorithmic bytes per
-    cell-direction."""
+    contraction precision (fp32: the trilinear pull fused into the next
+    collision's gather, T - 1 fused launches between a first collision and a
+    last pull; bf16: per-cell collision, then the trilinear pull, every
+    step), the checkpointed forward and its adjoint (recompute, reverse pull,
+    adjoint collision), and the 3-D streaming kernel alone (HIP events around
+    `reps` launches on the solver's stream) against the HBM peak at 32
+    algorithmic bytes per cell-direction."""
     import torch
     import workloads as W
     spec = W.spec("beam3d")

@@ -335,7 +335,8 @@ def three_d_extras(T=10, warm=2, reps=20):
             del b
         del solver, S
         torch.cuda.empty_cache()
-    return {"workload": "beam3d: 256x256x64 lattice, n=32 (4x8), forward steps (collision + trilinear streaming)",
+    return {"workload": "beam3d: 256x256x64 lattice, n=32 (4x8), forward steps (fp32: trilinear pull fused into the "
+                        "next collision; bf16: collision + trilinear streaming)",
             "steps": T, "rates": res}
 
 

@@ -11,6 +11,8 @@ Every random field is rounded to float32 and returned as float64, so that the
 float32 device path and the float64 oracle see bit-identical inputs.
 
 Workloads (the paper's method at the sizes it is benchmarked on here):
+  qlbm16       16x16 absorbing, n = 8 (2 zenith x 4 azimuth, D2Q9 shifts), the
+               paper's 2-D circuit experiment (statevector emulation)
   plain32      32x32 periodic, n = 8 (2 zenith x 4 azimuth, D2Q9 shifts),
                tau_ext = 1 per step, albedo 0.9, Rayleigh, unpolarised unit
                point source at the centre, 100 steps
@@ -60,6 +62,15 @@ _BASE = {
                    plane="3d", courant=1.0, bc6=(1, 1, 1, 1, 1, 2),
                    phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=7,
                    medium="lognormal", tau_ref_n=512, beam_dir=3 * 8 + 0, source="none"),
+    # the paper's 2-D experiment (Sec. 3.2.1): 16 x 16 D2Q9 lattice, 2 x 4
+    # directions, Rayleigh scattering, k_ext = 2.5, k_scat = 0.5 in the unit
+    # domain (dt = 1/16: tau_ext = 2.5/16 per step, albedo 0.2), a source
+    # over the central +-25% of the domain with unit emission summed over the
+    # directions, absorbing edges
+    "qlbm16": dict(nx=16, ny=16, n_zen=2, n_az=4, zen_rule="equal_area", az_offset_deg=0.0,
+                   plane="xy_d2q9", courant=1.0, bc=(1, 1, 1, 1), phase={"kind": "rayleigh"},
+                   dt=1.0 / 16.0, steps=4, seed=8, medium="uniform", tau0=2.5 / 16.0, albedo0=0.2,
+                   source="box"),
     "adjoint256": dict(nx=256, ny=256, n_zen=4, n_az=8, zen_rule="equal_area",
                        az_offset_deg=0.0, plane="xz", courant=1.0, bc=(1, 1, 1, 2),
                        phase={"kind": "hg", "g": 0.7}, dt=1.0, steps=500, seed=4,
@@ -122,6 +133,15 @@ def medium(s, seed=None):
     if src == "point":
         y, x = s.get("source_cell") or (ny // 2, nx // 2)
         emis[y, x] = 1.0
+        jprof[:, 0] = 1.0 / n
+        if s.get("source_pol") == "linear":
+            jprof[:, 1] = 1.0 / n
+    elif src == "box":
+        # the central half of the lattice in each axis, unit emission summed
+        # over the directions; linear polarisation along e_theta if asked
+        y0, y1 = ny // 4, ny - ny // 4
+        x0, x1 = nx // 4, nx - nx // 4
+        emis[y0:y1, x0:x1] = 1.0
         jprof[:, 0] = 1.0 / n
         if s.get("source_pol") == "linear":
             jprof[:, 1] = 1.0 / n

@@ -333,6 +333,48 @@ rt_status rt_run(rt_ctx *c, float *d_S, int32_t nsteps, float *d_ckpt, int32_t c
  * y faces (x, z), z faces (x, y), the first index fastest. */
 rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, double *h_sums);
 
+/* Statevector emulation of the paper's quantum circuit for one time step
+ * (Sec. 2.1.2-2.1.8), on the device in float64: the classical state and the
+ * source are amplitude-encoded (Eq. 4) into the registers st (2 qubits), sl,
+ * d_in, d_out (ceil(log2 n) each), y and x (log2 ny, log2 nx), with twelve
+ * ancillas for q_d = 3 (q_d + 9 in general): the emission LCU I + X/2 + ZX/2
+ * (Eq. 7, two ancillas), the absorption R_y dilation (Eq. 9), the selector of
+ * survival and redistribution (Eq. 12, 31), the PREP_joint -> SELECT_RPR ->
+ * PREP_joint^dagger routing over the outgoing direction (Eq. 25-30; route
+ * register of q_d qubits) with each pair's rotation-phase-rotation operator
+ * (Eq. 13, 21-24) and the phase matrix block-encoded through its eigenbasis
+ * (Eq. 18-20, one ancilla), and bilinear streaming with one R_y ancilla and
+ * one escape marker per axis (Eq. 34-38, Sec. 2.1.7).  Post-selecting every
+ * ancilla on |0> and decoding with the known normalisation (Sec. 2.1.8)
+ * gives the classical step (rt_step) to float64 round-off.  The collision
+ * matrix's pair blocks are read as w R(sigma_out) Zt R(sigma_in) with
+ * Zt = F / F_11 of the Rayleigh form; its eigenvalue 2 / (1 + cos^2) is
+ * encoded at half scale, the factor restored through the selector's weights
+ * (s, 2 (1 - s)) and a uniform 1 / max_c (2 - s(c)) in the absorption
+ * rotation.  Emulated: 2-D lattices with power-of-two nx and ny, periodic or
+ * absorbing edges, Rayleigh / HG / mixed phase weights, RT_ABS_TAYLOR and
+ * RT_SCAT_EXP; RT_EUNSUPPORTED otherwise (3-D, inflow edges, tabulated
+ * matrices, phase mixtures, dichroic absorption, RT_FUSED_TAYLOR).
+ *
+ * rt_sv_qubits: total and data qubits of the context's circuit.
+ * rt_sv_workspace_bytes: device bytes rt_sv_step needs (two statevectors of
+ *   2^nqubits float64, gate tables, the encoded source); 0 if not emulated
+ *   (rt_last_error says why).
+ * rt_sv_gate_count: gate launches (rotations, controlled X/Z, H and the Q-U
+ *   rotations) and translation launches of one step.
+ * rt_sv_step: one emulated step of the context's medium (rt_set_medium must
+ *   have succeeded) from d_S_in to d_S_out (device float64 [n][4][ny][nx],
+ *   caller-owned, may be the same array); d_work is the caller's workspace
+ *   of at least rt_sv_workspace_bytes(); h_psucc (or NULL) receives the
+ *   post-selection success probability.  Synchronises the stream.  Errors:
+ *   RT_EINVAL (NULL), RT_ESTATE (no medium), RT_ENOMEM (workspace too
+ *   small), RT_EUNSUPPORTED (see above). */
+rt_status rt_sv_qubits(const rt_ctx *c, int32_t *nqubits, int32_t *ndata);
+size_t rt_sv_workspace_bytes(const rt_ctx *c);
+rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts);
+rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d_S_in, double *d_S_out,
+                     double *h_psucc);
+
 /* For callers that cannot allocate device memory or call a synchronising
  * function (code under HIP graph capture, tight serving loops): the float64
  * sums of I, Q, U, V over the whole field, as rt_readout's h_sums computes

@@ -72,6 +72,10 @@ _SIGS = {
     "rt_readout": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_maps": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_totals_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rt_sv_qubits": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "rt_sv_workspace_bytes": (c_size_t, [c_void_p]),
+    "rt_sv_gate_count": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "rt_sv_step": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, POINTER(c_double)]),
     "rt_readout_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_adjoint_segment_bytes": (c_size_t, [_P, c_int32]),
     "rt_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
@@ -193,6 +197,30 @@ def rt_readout(ctx, d_S, edge, d_out=None, h_sums=None):
 
 def rt_totals_noalloc(ctx, d_S, d_sums):
     _check(_lib.rt_totals_noalloc(ctx, d_S, d_sums), ctx)
+
+
+def rt_sv_qubits(ctx):
+    """(total qubits, data qubits) of the context's emulated circuit."""
+    nq, nd = c_int32(0), c_int32(0)
+    _check(_lib.rt_sv_qubits(ctx, ctypes.byref(nq), ctypes.byref(nd)), ctx)
+    return nq.value, nd.value
+
+
+def rt_sv_workspace_bytes(ctx):
+    return _lib.rt_sv_workspace_bytes(ctx)
+
+
+def rt_sv_gate_count(ctx):
+    g, s = c_int32(0), c_int32(0)
+    _check(_lib.rt_sv_gate_count(ctx, ctypes.byref(g), ctypes.byref(s)), ctx)
+    return g.value, s.value
+
+
+def rt_sv_step(ctx, d_work, work_bytes, d_S_in, d_S_out):
+    """One emulated circuit step (float64 fields); returns the success probability."""
+    p = c_double(0.0)
+    _check(_lib.rt_sv_step(ctx, d_work, work_bytes, d_S_in, d_S_out, ctypes.byref(p)), ctx)
+    return p.value
 
 
 def rt_maps(ctx, d_S, d_I_mean, d_dop_mean):

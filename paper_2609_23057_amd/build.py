@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=off"]
 
-SOURCES = [("rt_host.cpp", False), ("rt_abi.cpp", False), ("rt_kernels.hip", True)]
+SOURCES = [("rt_host.cpp", False), ("rt_abi.cpp", False), ("rt_kernels.hip", True), ("rt_sv.hip", True)]
 
 
 def _compile(src, device):

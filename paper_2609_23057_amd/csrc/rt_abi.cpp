@@ -17,6 +17,7 @@
 
 #include "rt_internal.h"
 #include "rt_kernels.h"
+#include "rt_sv.h"
 
 using namespace rtl;
 
@@ -1060,6 +1061,460 @@ rt_status rt_adjoint(rt_ctx *c, int32_t nsteps, const float *d_ckpt, int32_t ckp
     st = c->hip(hipMemcpyAsync(d_lambda0, lam_next, sb, hipMemcpyDeviceToDevice, c->stream), "lambda0");
   c->prec = prec_save;
   return st;
+}
+
+// ------------------------------------------------- statevector emulation (circuit)
+
+}  // extern "C"
+
+namespace {
+
+// Qubits of the emulated circuit (flat-index bits from the least significant):
+// x, y, d_out, d_in, sl, st0, st1 (data), then em0, em1, abs, sel, route, pt,
+// ax, ay, ex, ey (ancillas).  Stokes st = 2 st1 + st0.
+struct SvLayout {
+  int qx = 0, qy = 0, qd = 0, nd = 0, ndata = 0, nq = 0;
+  int x0 = 0, y0 = 0, dout0 = 0, din0 = 0, sl = 0, st0 = 0, st1 = 0;
+  int em0 = 0, em1 = 0, abs = 0, sel = 0, route0 = 0, pt = 0, ax = 0, ay = 0, ex = 0, ey = 0;
+};
+
+int log2_exact(int v) {
+  int q = 0;
+  while ((1 << q) < v) ++q;
+  return (v >= 1 && (1 << q) == v) ? q : -1;
+}
+
+struct SvOp {
+  bool shift = false;
+  SvGate g{};
+  size_t table_off = 0;   // doubles into the table region
+  SvShift s{};
+  int base_off = 0;       // int32 entries into the base table
+};
+
+struct SvCircuit {
+  SvLayout L;
+  std::vector<SvOp> ops;
+  std::vector<double> tables;
+  std::vector<int32_t> bases;
+  std::vector<double> J;   // [n][4][ny][nx]: dt eps j (the sl = 1 sector)
+  double lam_max = 1.0;
+};
+
+// Why a context cannot be emulated ("" if it can), and its layout.
+std::string sv_check(const rt_ctx *c, SvLayout *L) {
+  if (c->three_d) return "3-D lattices are not emulated";
+  if (c->prob.flags & RT_FUSED_TAYLOR) return "the fused-Taylor form is not emulated";
+  if (c->mixture || c->dichroic) return "phase mixtures and dichroic absorption are not emulated";
+  for (int e = 0; e < 4; ++e)
+    if (c->prob.bc[e] == RT_BC_INFLOW) return "inflow edges are not emulated";
+  const HostPlan &hp = c->hp;
+  L->qx = log2_exact(hp.nx);
+  L->qy = log2_exact(hp.ny);
+  if (L->qx < 0 || L->qy < 0) return "nx and ny must be powers of two";
+  L->qd = 1;
+  while ((1 << L->qd) < hp.n) ++L->qd;
+  L->nd = 1 << L->qd;
+  int pos = 0;
+  auto take = [&](int w) { const int p0 = pos; pos += w; return p0; };
+  L->x0 = take(L->qx);
+  L->y0 = take(L->qy);
+  L->dout0 = take(L->qd);
+  L->din0 = take(L->qd);
+  L->sl = take(1);
+  L->st0 = take(1);
+  L->st1 = take(1);
+  L->ndata = pos;
+  L->em0 = take(1);
+  L->em1 = take(1);
+  L->abs = take(1);
+  L->sel = take(1);
+  L->route0 = take(L->qd);
+  L->pt = take(1);
+  L->ax = take(1);
+  L->ay = take(1);
+  L->ex = take(1);
+  L->ey = take(1);
+  L->nq = pos;
+  if (L->nq > 34) return "the statevector would exceed 2^34 amplitudes";
+  return "";
+}
+
+// The circuit's gates and their tables for the context's operator and
+// medium (host float64).  tau, alb, emis: the medium's float32 values.
+std::string sv_compile(const rt_ctx *c, const std::vector<float> &tau, const std::vector<float> &alb,
+                       const std::vector<float> &emis, SvCircuit *out) {
+  SvCircuit &K = *out;
+  std::string why = sv_check(c, &K.L);
+  if (!why.empty()) return why;
+  const SvLayout &L = K.L;
+  const HostPlan &hp = c->hp;
+  const int n = hp.n, nd = L.nd, nx = hp.nx, ny = hp.ny, C = nx * ny, R = hp.R;
+  // --- per ordered pair (k <- d): w R(sigma_out) Zt R(sigma_in) with
+  // Zt = [[1, b, 0, 0], [b, 1, 0, 0], [0, 0, g, 0], [0, 0, 0, g]], read off
+  // the collision matrix and checked by rebuilding the block
+  std::vector<double> w(nd * nd, 0.0), sin2(nd * nd, 0.0), sout2(nd * nd, 0.0), lam(nd * nd * 4, 0.0);
+  auto rot = [](double a2, double v[4][4]) {   // R(psi) of Eq. 21 with a2 = 2 psi
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) v[i][j] = i == j ? 1.0 : 0.0;
+    v[1][1] = v[2][2] = std::cos(a2);
+    v[1][2] = std::sin(a2);
+    v[2][1] = -std::sin(a2);
+  };
+  for (int d = 0; d < n; ++d)
+    for (int k = 0; k < n; ++k) {
+      double B[4][4];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) B[i][j] = hp.M[(size_t)(4 * k + i) * R + 4 * d + j];
+      const double wk = B[0][0];
+      double b = 0.0, g = 0.0, ai = 0.0, ao = 0.0;
+      if (wk > 0.0) {
+        b = -std::hypot(B[0][1], B[0][2]) / wk;
+        g = B[3][3] / wk;
+        if (std::fabs(b) > 1e-12) {
+          ai = std::atan2(B[0][2] / (wk * b), B[0][1] / (wk * b));
+          ao = std::atan2(-B[2][0] / (wk * b), B[1][0] / (wk * b));
+        } else {
+          ao = g > 0.0 ? std::atan2(B[1][2], B[1][1]) : std::atan2(-B[2][1], B[1][1]);
+        }
+        double Ri[4][4], Ro[4][4], Z[4][4] = {{1, b, 0, 0}, {b, 1, 0, 0}, {0, 0, g, 0}, {0, 0, 0, g}};
+        rot(ai, Ri);
+        rot(ao, Ro);
+        double err = 0.0, mx = 1.0;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            double v = 0.0;
+            for (int p = 0; p < 4; ++p)
+              for (int q = 0; q < 4; ++q) v += Ro[i][p] * Z[p][q] * Ri[q][j];
+            err = std::max(err, std::fabs(wk * v - B[i][j]));
+            mx = std::max(mx, std::fabs(B[i][j]));
+          }
+        if (err > 1e-12 * mx) return "the collision matrix is not of the rotation-phase-rotation form (tabulated matrices)";
+      } else if (wk < 0.0) {
+        return "negative scattering weight";
+      }
+      w[k * nd + d] = wk;
+      sin2[d * nd + k] = ai;    // pair tables: index k + nd d (address d_out bits, then d_in bits)
+      sout2[d * nd + k] = ao;
+      const double ev[4] = {1.0 + b, 1.0 - b, g, g};   // by st after H on st0
+      for (int st = 0; st < 4; ++st) lam[(st * nd + d) * nd + k] = ev[st];
+    }
+  // --- medium: alpha = a s, beta = a (1 - s) as the coefficient step forms
+  // them, in float64
+  const bool abs_taylor = (c->prob.flags & RT_ABS_TAYLOR) != 0, scat_exp = (c->prob.flags & RT_SCAT_EXP) != 0;
+  std::vector<double> aabs(C), surv(C);
+  double lam_max = 0.0;
+  for (int i = 0; i < C; ++i) {
+    const double t = tau[i], al = alb[i];
+    const double t_sca = al * t, t_abs = (1.0 - al) * t;
+    const double a = abs_taylor ? 1.0 - t_abs : std::exp(-t_abs);
+    const double sv = scat_exp ? std::exp(-t_sca) : 1.0 - t_sca;
+    const double alpha = a * sv, beta = a * (1.0 - sv);
+    const double at = alpha + beta;
+    const double s = at > 0.0 ? alpha / at : 1.0;
+    if (at < 0.0 || at > 1.0 + 1e-15 || s < 0.0) return "coefficients outside 0 <= alpha, beta; alpha + beta <= 1";
+    aabs[i] = at;
+    surv[i] = s;
+    lam_max = std::max(lam_max, 2.0 - s);
+  }
+  K.lam_max = lam_max;
+  K.J.assign((size_t)n * 4 * C, 0.0);
+  for (int d = 0; d < n; ++d)
+    for (int st = 0; st < 4; ++st) {
+      const size_t r = (size_t)gemm_row(n, d, st);
+      const double j = r < c->host_jrow.size() ? (double)c->host_jrow[r] : 0.0;
+      for (int i = 0; i < C; ++i) K.J[((size_t)d * 4 + st) * C + i] = (j * (double)emis[i]) * c->prob.dt;
+    }
+  // --- gate list
+  K.ops.clear();
+  K.tables.clear();
+  K.bases.clear();
+  auto bit = [](int b) { return 1ull << b; };
+  // a gate on qubit q (or the Q <-> U pair when qu), controls, address bits
+  // (table index bit j = addr[j]) and its table [2^naddr][4]
+  auto gate = [&](int q, bool qu, std::initializer_list<std::pair<int, int>> ctrl, const std::vector<int> &addr,
+                  const std::vector<double> &tab) {
+    SvOp op;
+    SvGate &g = op.g;
+    if (qu) {
+      g.mask = bit(L.st0) | bit(L.st1);
+      g.v0 = bit(L.st0);   // Q = |st1 st0> = |01>
+      g.v1 = bit(L.st1);   // U = |10>
+      g.nbits = 2;
+      g.pos[0] = std::min(L.st0, L.st1);
+      g.pos[1] = std::max(L.st0, L.st1);
+    } else {
+      g.mask = bit(q);
+      g.v0 = 0;
+      g.v1 = bit(q);
+      g.nbits = 1;
+      g.pos[0] = q;
+    }
+    g.cmask = g.cval = 0;
+    for (const auto &cv : ctrl) {
+      g.cmask |= bit(cv.first);
+      if (cv.second) g.cval |= bit(cv.first);
+    }
+    g.naddr = (int)addr.size();
+    for (int j = 0; j < g.naddr; ++j) g.addr[j] = addr[j];
+    op.table_off = K.tables.size();
+    K.tables.insert(K.tables.end(), tab.begin(), tab.end());
+    K.ops.push_back(op);
+  };
+  auto ry = [](double th) {
+    const double cc = std::cos(0.5 * th), ss = std::sin(0.5 * th);
+    return std::vector<double>{cc, -ss, ss, cc};
+  };
+  auto ry_table = [&](const std::vector<double> &th) {
+    std::vector<double> t;
+    t.reserve(4 * th.size());
+    for (double v : th) {
+      const std::vector<double> r = ry(v);
+      t.insert(t.end(), r.begin(), r.end());
+    }
+    return t;
+  };
+  auto reg = [](int b0, int width) {
+    std::vector<int> v;
+    for (int j = 0; j < width; ++j) v.push_back(b0 + j);
+    return v;
+  };
+  const std::vector<int> cell = [&] {
+    std::vector<int> v = reg(L.x0, L.qx);
+    const std::vector<int> y = reg(L.y0, L.qy);
+    v.insert(v.end(), y.begin(), y.end());
+    return v;
+  }();
+  const std::vector<int> pair = [&] {   // table index k + nd d
+    std::vector<int> v = reg(L.dout0, L.qd);
+    const std::vector<int> d = reg(L.din0, L.qd);
+    v.insert(v.end(), d.begin(), d.end());
+    return v;
+  }();
+  const std::vector<double> X = {0.0, 1.0, 1.0, 0.0}, Zg = {1.0, 0.0, 0.0, -1.0};
+  const double rh = 1.0 / std::sqrt(2.0);
+  const std::vector<double> H = {rh, rh, rh, -rh};
+  // emission: LCU of I, X, ZX with weights 1/2, 1/4, 1/4 on (em1, em0)
+  const double t1 = 2.0 * std::acos(std::sqrt(0.75)), t0 = 2.0 * std::acos(std::sqrt(2.0 / 3.0));
+  gate(L.em1, false, {}, {}, ry(t1));
+  gate(L.em0, false, {{L.em1, 0}}, {}, ry(t0));
+  gate(L.sl, false, {{L.em0, 1}}, {}, X);
+  gate(L.sl, false, {{L.em1, 1}}, {}, X);
+  gate(L.sl, false, {{L.em1, 1}}, {}, Zg);
+  gate(L.em0, false, {{L.em1, 0}}, {}, ry(-t0));
+  gate(L.em1, false, {}, {}, ry(-t1));
+  // absorption: R_y(2 arccos(a (2 - s) / lambda_max)) per cell on the live sector
+  {
+    std::vector<double> th(C);
+    for (int i = 0; i < C; ++i)
+      th[i] = 2.0 * std::acos(std::min(1.0, std::max(-1.0, aabs[i] * (2.0 - surv[i]) / lam_max)));
+    gate(L.abs, false, {{L.sl, 0}}, cell, ry_table(th));
+  }
+  // scattering: selector, PREP_joint, SELECT (d_out ^= d_in, d_out ^= route),
+  // RPR, PREP_joint^dagger, selector^dagger
+  std::vector<double> th_sel(C);
+  for (int i = 0; i < C; ++i) {
+    const double s = surv[i];
+    th_sel[i] = 2.0 * std::atan(s > 0.0 ? std::sqrt(2.0 * (1.0 - s) / s) : INFINITY);
+  }
+  gate(L.sel, false, {{L.sl, 0}}, cell, ry_table(th_sel));
+  auto prep_level = [&](int lev, bool inverse) {
+    const int nb = L.qd - lev;   // sets route bit nb - 1
+    std::vector<int> addr = reg(L.din0, L.qd);
+    for (int j = 0; j < lev; ++j) addr.push_back(L.route0 + nb + j);
+    std::vector<double> th((size_t)nd << lev, 0.0);
+    for (int pre = 0; pre < (1 << lev); ++pre)
+      for (int d = 0; d < nd; ++d) {
+        const int lo = pre << nb;
+        double node = 0.0, left = 0.0;
+        if (d < n) {
+          for (int k = lo; k < lo + (1 << nb); ++k) node += w[k * nd + d];
+          for (int k = lo; k < lo + (1 << (nb - 1)); ++k) left += w[k * nd + d];
+        }
+        const double v = node > 0.0 ? 2.0 * std::acos(std::sqrt(std::min(1.0, left / node))) : 0.0;
+        th[(size_t)pre * nd + d] = inverse ? -v : v;
+      }
+    gate(L.route0 + nb - 1, false, {{L.sl, 0}, {L.sel, 1}}, addr, ry_table(th));
+  };
+  for (int lev = 0; lev < L.qd; ++lev) prep_level(lev, false);
+  for (int j = 0; j < L.qd; ++j) gate(L.dout0 + j, false, {{L.sl, 0}, {L.sel, 1}, {L.din0 + j, 1}}, {}, X);
+  for (int j = 0; j < L.qd; ++j) gate(L.dout0 + j, false, {{L.sl, 0}, {L.sel, 1}, {L.route0 + j, 1}}, {}, X);
+  auto rot_table = [&](const std::vector<double> &a2) {
+    std::vector<double> t;
+    for (double v : a2) {
+      const double c2 = std::cos(v), s2 = std::sin(v);
+      t.insert(t.end(), {c2, s2, -s2, c2});
+    }
+    return t;
+  };
+  gate(0, true, {{L.sl, 0}, {L.sel, 1}}, pair, rot_table(sin2));
+  gate(L.st0, false, {{L.sl, 0}, {L.sel, 1}}, {}, H);
+  {
+    std::vector<int> addr = pair;
+    addr.push_back(L.st0);
+    addr.push_back(L.st1);
+    std::vector<double> th(nd * nd * 4);
+    for (size_t i = 0; i < th.size(); ++i) th[i] = 2.0 * std::acos(std::min(1.0, std::max(-1.0, 0.5 * lam[i])));
+    gate(L.pt, false, {{L.sl, 0}, {L.sel, 1}}, addr, ry_table(th));
+  }
+  gate(L.st0, false, {{L.sl, 0}, {L.sel, 1}}, {}, H);
+  gate(0, true, {{L.sl, 0}, {L.sel, 1}}, pair, rot_table(sout2));
+  for (int lev = L.qd - 1; lev >= 0; --lev) prep_level(lev, true);
+  for (double &v : th_sel) v = -v;
+  gate(L.sel, false, {{L.sl, 0}}, cell, ry_table(th_sel));
+  // streaming per axis: R_y(theta(d_out)) on the axis ancilla, the
+  // translation by floor(l) + b, R_y(-theta)
+  for (int axis = 0; axis < 2; ++axis) {
+    const int anc = axis == 0 ? L.ax : L.ay, esc = axis == 0 ? L.ex : L.ey;
+    std::vector<double> th(nd, 0.0);
+    const int boff = (int)K.bases.size();
+    K.bases.resize(K.bases.size() + nd, 0);
+    for (int d = 0; d < n; ++d) {
+      const double l = axis == 0 ? hp.lx[d] : hp.ly[d];
+      const double i0 = std::floor(l), f = l - i0;
+      K.bases[boff + d] = (int32_t)i0;
+      th[d] = 2.0 * std::asin(std::sqrt(f));
+    }
+    const std::vector<int> dout = reg(L.dout0, L.qd);
+    gate(anc, false, {{L.sl, 0}}, dout, ry_table(th));
+    SvOp op;
+    op.shift = true;
+    op.s.r0 = axis == 0 ? L.x0 : L.y0;
+    op.s.qr = axis == 0 ? L.qx : L.qy;
+    op.s.ebit = esc;
+    op.s.abit = anc;
+    op.s.slbit = L.sl;
+    op.s.d0 = L.dout0;
+    op.s.qd = L.qd;
+    op.s.periodic = c->prob.bc[axis == 0 ? 0 : 2] == RT_BC_PERIODIC ? 1 : 0;
+    op.base_off = boff;
+    K.ops.push_back(op);
+    for (double &v : th) v = -v;
+    gate(anc, false, {{L.sl, 0}}, dout, ry_table(th));
+  }
+  return "";
+}
+
+struct SvWork {
+  size_t psi0, psi1, tables, J, partial, norms, bases, total;
+};
+
+SvWork sv_work_layout(const SvLayout &L, size_t ntables, size_t nJ, size_t nbases) {
+  SvWork W{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+  W.psi0 = take(sizeof(double) << L.nq);
+  W.psi1 = take(sizeof(double) << L.nq);
+  W.tables = take(ntables * sizeof(double));
+  W.J = take(nJ * sizeof(double));
+  W.partial = take((size_t)sv_norm_partials() * sizeof(double));
+  W.norms = take(4 * sizeof(double));
+  W.bases = take(nbases * sizeof(int32_t));
+  W.total = off;
+  return W;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_sv_qubits(const rt_ctx *c, int32_t *nqubits, int32_t *ndata) {
+  if (!c || !nqubits) return set_err(RT_EINVAL, "NULL argument");
+  SvLayout L;
+  const std::string why = sv_check(c, &L);
+  if (!why.empty()) return set_err(RT_EUNSUPPORTED, why);
+  *nqubits = L.nq;
+  if (ndata) *ndata = L.ndata;
+  return RT_OK;
+}
+
+size_t rt_sv_workspace_bytes(const rt_ctx *c) {
+  if (!c) return 0;
+  // the tables' sizes do not depend on the medium: compile with a neutral one
+  const size_t C = (size_t)c->hp.nx * c->hp.ny;
+  std::vector<float> z(C, 0.0f);
+  SvCircuit K;
+  const std::string why = sv_compile(c, z, z, z, &K);
+  if (!why.empty()) {
+    set_err(RT_EUNSUPPORTED, why);
+    return 0;
+  }
+  return sv_work_layout(K.L, K.tables.size(), K.J.size(), K.bases.size()).total;
+}
+
+rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d_S_in, double *d_S_out,
+                     double *h_psucc) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (!d_work || !d_S_in || !d_S_out) return c->fail(RT_EINVAL, "NULL pointer");
+  if (!c->medium_set) return c->fail(RT_ESTATE, "rt_set_medium has not succeeded");
+  const HostPlan &hp = c->hp;
+  const size_t C = (size_t)hp.nx * hp.ny;
+  std::vector<float> tau(C), alb(C), emis(C);
+  rt_status st = c->hip(hipMemcpyAsync(tau.data(), c->at<float>(c->L.tau), C * 4, hipMemcpyDeviceToHost, c->stream),
+                        "medium");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(alb.data(), c->at<float>(c->L.alb), C * 4, hipMemcpyDeviceToHost, c->stream), "medium");
+  if (st == RT_OK)
+    st = c->hip(hipMemcpyAsync(emis.data(), c->at<float>(c->L.emis), C * 4, hipMemcpyDeviceToHost, c->stream), "medium");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "medium");
+  if (st != RT_OK) return st;
+  SvCircuit K;
+  const std::string why = sv_compile(c, tau, alb, emis, &K);
+  if (!why.empty()) return c->fail(RT_EUNSUPPORTED, why);
+  const SvLayout &L = K.L;
+  const SvWork W = sv_work_layout(L, K.tables.size(), K.J.size(), K.bases.size());
+  if (work_bytes < W.total) return c->fail(RT_ENOMEM, "workspace smaller than rt_sv_workspace_bytes()");
+  char *ws = static_cast<char *>(d_work);
+  double *psi[2] = {reinterpret_cast<double *>(ws + W.psi0), reinterpret_cast<double *>(ws + W.psi1)};
+  double *tables = reinterpret_cast<double *>(ws + W.tables);
+  double *J = reinterpret_cast<double *>(ws + W.J);
+  double *partial = reinterpret_cast<double *>(ws + W.partial);
+  double *norms = reinterpret_cast<double *>(ws + W.norms);   // [0] ||phi_0||^2, [1] p_succ
+  int32_t *bases = reinterpret_cast<int32_t *>(ws + W.bases);
+  hipStream_t s = c->stream;
+  st = c->hip(hipMemcpyAsync(tables, K.tables.data(), K.tables.size() * 8, hipMemcpyHostToDevice, s), "sv tables");
+  if (st == RT_OK) st = c->hip(hipMemcpyAsync(J, K.J.data(), K.J.size() * 8, hipMemcpyHostToDevice, s), "sv source");
+  if (st == RT_OK && !K.bases.empty())
+    st = c->hip(hipMemcpyAsync(bases, K.bases.data(), K.bases.size() * 4, hipMemcpyHostToDevice, s), "sv bases");
+  const uint64_t nstates = 1ull << L.nq, nfield = (uint64_t)hp.n * 4 * C;
+  if (st == RT_OK) st = c->hip(sv_launch_zero(psi[0], nstates, s), "sv zero");
+  if (st == RT_OK) st = c->hip(sv_launch_norm2(d_S_in, nfield, J, nfield, partial, norms, s), "sv norm");
+  if (st == RT_OK) st = c->hip(sv_launch_encode(psi[0], d_S_in, J, hp.n, L.nd, hp.ny, hp.nx, norms, s), "sv encode");
+  int cur = 0;
+  for (size_t i = 0; i < K.ops.size() && st == RT_OK; ++i) {
+    SvOp op = K.ops[i];
+    if (op.shift) {
+      op.s.base = bases + op.base_off;
+      st = c->hip(sv_launch_shift(psi[cur], psi[cur ^ 1], L.nq, op.s, s), "sv shift");
+      cur ^= 1;
+    } else {
+      op.g.table = tables + op.table_off;
+      st = c->hip(sv_launch_gate(psi[cur], L.nq, op.g, s), "sv gate");
+    }
+  }
+  const uint64_t nblock = 1ull << L.ndata;
+  if (st == RT_OK) st = c->hip(sv_launch_norm2(psi[cur], nblock, nullptr, 0, partial, norms + 1, s), "sv p_succ");
+  if (st == RT_OK)
+    st = c->hip(sv_launch_decode(psi[cur], d_S_out, hp.n, L.nd, hp.ny, hp.nx, 2.0 * K.lam_max, norms, s), "sv decode");
+  double hn[2] = {0.0, 0.0};
+  if (st == RT_OK) st = c->hip(hipMemcpyAsync(hn, norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "sv norms");
+  if (st == RT_OK) st = c->hip(hipStreamSynchronize(s), "sv step");
+  if (st == RT_OK && h_psucc) *h_psucc = hn[0] > 0.0 ? hn[1] : 0.0;
+  return st;
+}
+
+rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts) {
+  if (!c || !ngates) return set_err(RT_EINVAL, "NULL argument");
+  const size_t C = (size_t)c->hp.nx * c->hp.ny;
+  std::vector<float> z(C, 0.0f);
+  SvCircuit K;
+  const std::string why = sv_compile(c, z, z, z, &K);
+  if (!why.empty()) return set_err(RT_EUNSUPPORTED, why);
+  int g = 0, sh = 0;
+  for (const SvOp &op : K.ops) (op.shift ? sh : g) += 1;
+  *ngates = g;
+  if (nshifts) *nshifts = sh;
+  return RT_OK;
 }
 
 // ---------------------------------------------------------------- spectral batch

@@ -1,0 +1,63 @@
+// Device launchers of the statevector emulation of the paper's one-step
+// circuit (Sec. 2.1.2-2.1.8): a real float64 statevector over nq qubits,
+// one array element per basis state (flat index bit q = qubit q).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rtl {
+
+constexpr int kSvMaxAddr = 20;   // address qubits of a gate's angle table
+
+// A real 2x2 gate between two basis values of the qubits in `mask` (one
+// qubit: v0 = 0, v1 = the qubit's bit; two qubits: the Q <-> U pair of the
+// Stokes register): for every basis state base whose mask bits are zero and
+// whose control bits match ((base & cmask) == cval),
+//   (a0, a1) = (psi[base | v0], psi[base | v1])
+//   -> (u00 a0 + u01 a1, u10 a0 + u11 a1)
+// with (u00, u01, u10, u11) = table[4 a .. 4 a + 3], a = sum_j bit(addr[j]) 2^j.
+struct SvGate {
+  uint64_t mask, v0, v1;
+  uint64_t cmask, cval;
+  int32_t nbits;       // qubits in mask (1 or 2)
+  int32_t pos[2];      // their bit positions, ascending
+  int32_t naddr;
+  int32_t addr[kSvMaxAddr];
+  const double *table;
+};
+hipError_t sv_launch_gate(double *psi, int nq, const SvGate &g, hipStream_t s);
+
+// Controlled translation of the register bits [r0, r0 + qr) (Eq. 36-38 with
+// the escape marker of Sec. 2.1.7): for live states (sl bit 0), d_out = k
+// (bits [d0, d0 + qd)) and branch bit b, the translation is t = base[k] + b;
+// on an absorbing axis a state whose target lies outside is marked escaped
+// (its escape bit flipped) instead, and the unmarked states translate
+// modulo 2^qr.  out[o] = in[src(o)] (a permutation; in and out distinct).
+struct SvShift {
+  int32_t r0, qr, ebit, abit, slbit, d0, qd, periodic;
+  const int32_t *base;   // [2^qd]
+};
+hipError_t sv_launch_shift(const double *in, double *out, int nq, const SvShift &t, hipStream_t s);
+
+hipError_t sv_launch_zero(double *psi, uint64_t count, hipStream_t s);
+
+// Sum of squares of a[0 .. na) and b[0 .. nb) into *result (device), via
+// `partial` (device, sv_norm_partials() doubles).
+int sv_norm_partials();
+hipError_t sv_launch_norm2(const double *a, uint64_t na, const double *b, uint64_t nb, double *partial,
+                           double *result, hipStream_t s);
+
+// Amplitude encoding (Eq. 4): psi (zeroed) receives S[d][st][y][x] / norm at
+// (st, sl = 0, d_in = d_out = d, y, x) and J[d][st][y][x] / norm at sl = 1,
+// norm = sqrt(*norm2); data index ((((st 2 + sl) nd + d_in) nd + d_out) ny + y) nx + x.
+hipError_t sv_launch_encode(double *psi, const double *S, const double *J, int n, int nd, int ny, int nx,
+                            const double *norm2, hipStream_t s);
+
+// Decoding (Sec. 2.1.8): S'[k][st][y][x] = (sum over d_in of psi at (st,
+// sl = 0, d_in, d_out = k, y, x)) * (scale2 * sqrt(*norm2)).
+hipError_t sv_launch_decode(const double *psi, double *S, int n, int nd, int ny, int nx, double scale2,
+                            const double *norm2, hipStream_t s);
+
+}  // namespace rtl

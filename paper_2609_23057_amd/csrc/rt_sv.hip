@@ -1,0 +1,198 @@
+// Statevector emulation kernels (gfx950): the gates of the paper's circuit on
+// a real float64 statevector.  Every gate is one pass over the states it
+// touches, so each kernel is bound by HBM traffic (16 bytes read and 16
+// written per active amplitude pair); threads walk the pair space with a
+// grid-stride loop, consecutive threads on consecutive pairs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "rt_sv.h"
+
+namespace rtl {
+
+namespace {
+
+constexpr int kSvThreads = 256;
+constexpr int kSvNormBlocks = 1024;
+
+inline unsigned sv_grid(uint64_t work) {
+  const uint64_t b = (work + kSvThreads - 1) / kSvThreads;
+  return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 1), 65536);
+}
+
+// Index with zero bits inserted at the (ascending) positions of the gate.
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t t, const SvGate &g) {
+  for (int k = 0; k < g.nbits; ++k) {
+    const int p = g.pos[k];
+    t = ((t >> p) << (p + 1)) | (t & ((1ull << p) - 1));
+  }
+  return t;
+}
+
+__global__ void __launch_bounds__(kSvThreads) sv_gate_kernel(double *__restrict__ psi, uint64_t npairs, SvGate g) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += stride) {
+    const uint64_t base = insert_zeros(t, g);
+    if ((base & g.cmask) != g.cval) continue;
+    uint32_t a = 0;
+    for (int j = 0; j < g.naddr; ++j) a |= (uint32_t)((base >> g.addr[j]) & 1) << j;
+    const double u00 = g.table[4 * a], u01 = g.table[4 * a + 1];
+    const double u10 = g.table[4 * a + 2], u11 = g.table[4 * a + 3];
+    const uint64_t i = base | g.v0, k = base | g.v1;
+    const double a0 = psi[i], a1 = psi[k];
+    // products then sums, unfused, as the reference arithmetic does
+    psi[i] = u00 * a0 + u01 * a1;
+    psi[k] = u10 * a0 + u11 * a1;
+  }
+}
+
+__global__ void __launch_bounds__(kSvThreads) sv_shift_kernel(const double *__restrict__ in, double *__restrict__ out,
+                                                             uint64_t nstates, SvShift s) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const int64_t size = 1ll << s.qr;
+  const uint64_t rmask = (uint64_t)(size - 1) << s.r0;
+  for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nstates; o += stride) {
+    uint64_t src = o;
+    if (((o >> s.slbit) & 1) == 0) {
+      const int64_t r = (int64_t)((o >> s.r0) & (uint64_t)(size - 1));
+      const int e = (int)((o >> s.ebit) & 1);
+      const int k = (int)((o >> s.d0) & ((1u << s.qd) - 1));
+      const int64_t t = (int64_t)s.base[k] + (int64_t)((o >> s.abit) & 1);
+      const int64_t back = ((r - t) % size + size) % size;   // (r - t) mod size
+      int64_t rs = r;
+      int es = e;
+      if (s.periodic) {
+        rs = back;
+      } else if (e == 0) {
+        // an unmarked output came from back unless back + t lies outside
+        rs = back;
+        es = (back + t < 0 || back + t >= size) ? 1 : 0;
+      } else {
+        // a marked output: the state that stayed in place (marked now)
+        es = 1 ^ ((r + t < 0 || r + t >= size) ? 1 : 0);
+      }
+      src = (o & ~rmask & ~(1ull << s.ebit)) | ((uint64_t)rs << s.r0) | ((uint64_t)es << s.ebit);
+    }
+    out[o] = in[src];
+  }
+}
+
+__global__ void sv_zero_kernel(double *__restrict__ p, uint64_t count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(kSvThreads) sv_norm_partial_kernel(const double *__restrict__ a, uint64_t na,
+                                                                     const double *__restrict__ b, uint64_t nb,
+                                                                     double *__restrict__ partial) {
+  __shared__ double red[kSvThreads];
+  double acc = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+    const double v = i < na ? a[i] : b[i - na];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kSvThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sv_norm_final_kernel(const double *__restrict__ partial, int np, double *result) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += partial[i];
+    *result = s;
+  }
+}
+
+__device__ __forceinline__ uint64_t data_index(int st, int sl, int din, int dout, int y, int x, int nd, int ny,
+                                               int nx) {
+  return (((((uint64_t)(st * 2 + sl) * nd + din) * nd + dout) * ny + y) * nx + x);
+}
+
+__global__ void sv_encode_kernel(double *__restrict__ psi, const double *__restrict__ S,
+                                 const double *__restrict__ J, int n, int nd, int ny, int nx,
+                                 const double *__restrict__ norm2) {
+  const uint64_t total = (uint64_t)n * 4 * ny * nx;
+  const double norm = sqrt(*norm2);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int x = (int)(i % nx);
+    const int y = (int)((i / nx) % ny);
+    const int st = (int)((i / ((uint64_t)nx * ny)) % 4);
+    const int d = (int)(i / ((uint64_t)nx * ny * 4));
+    psi[data_index(st, 0, d, d, y, x, nd, ny, nx)] = norm > 0.0 ? S[i] / norm : 0.0;
+    psi[data_index(st, 1, d, d, y, x, nd, ny, nx)] = norm > 0.0 ? J[i] / norm : 0.0;
+  }
+}
+
+__global__ void sv_decode_kernel(const double *__restrict__ psi, double *__restrict__ S, int n, int nd, int ny,
+                                 int nx, double scale2, const double *__restrict__ norm2) {
+  const uint64_t total = (uint64_t)n * 4 * ny * nx;
+  const double scale = scale2 * sqrt(*norm2);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int x = (int)(i % nx);
+    const int y = (int)((i / nx) % ny);
+    const int st = (int)((i / ((uint64_t)nx * ny)) % 4);
+    const int k = (int)(i / ((uint64_t)nx * ny * 4));
+    double acc = 0.0;
+    for (int din = 0; din < nd; ++din) acc += psi[data_index(st, 0, din, k, y, x, nd, ny, nx)];
+    S[i] = acc * scale;
+  }
+}
+
+}  // namespace
+
+hipError_t sv_launch_gate(double *psi, int nq, const SvGate &g, hipStream_t s) {
+  if (g.nbits < 1 || g.nbits > 2 || g.naddr < 0 || g.naddr > kSvMaxAddr || nq < g.nbits || nq > 40)
+    return hipErrorInvalidValue;
+  const uint64_t npairs = 1ull << (nq - g.nbits);
+  hipLaunchKernelGGL(sv_gate_kernel, dim3(sv_grid(npairs)), dim3(kSvThreads), 0, s, psi, npairs, g);
+  return hipGetLastError();
+}
+
+hipError_t sv_launch_shift(const double *in, double *out, int nq, const SvShift &t, hipStream_t s) {
+  if (nq > 40 || t.qr < 1 || t.qd < 1) return hipErrorInvalidValue;
+  const uint64_t n = 1ull << nq;
+  hipLaunchKernelGGL(sv_shift_kernel, dim3(sv_grid(n)), dim3(kSvThreads), 0, s, in, out, n, t);
+  return hipGetLastError();
+}
+
+hipError_t sv_launch_zero(double *psi, uint64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(sv_zero_kernel, dim3(sv_grid(count)), dim3(kSvThreads), 0, s, psi, count);
+  return hipGetLastError();
+}
+
+int sv_norm_partials() { return kSvNormBlocks; }
+
+hipError_t sv_launch_norm2(const double *a, uint64_t na, const double *b, uint64_t nb, double *partial,
+                           double *result, hipStream_t s) {
+  hipLaunchKernelGGL(sv_norm_partial_kernel, dim3(kSvNormBlocks), dim3(kSvThreads), 0, s, a, na, b, nb, partial);
+  hipLaunchKernelGGL(sv_norm_final_kernel, dim3(1), dim3(64), 0, s, partial, kSvNormBlocks, result);
+  return hipGetLastError();
+}
+
+hipError_t sv_launch_encode(double *psi, const double *S, const double *J, int n, int nd, int ny, int nx,
+                            const double *norm2, hipStream_t s) {
+  const uint64_t total = (uint64_t)n * 4 * ny * nx;
+  hipLaunchKernelGGL(sv_encode_kernel, dim3(sv_grid(total)), dim3(kSvThreads), 0, s, psi, S, J, n, nd, ny, nx,
+                     norm2);
+  return hipGetLastError();
+}
+
+hipError_t sv_launch_decode(const double *psi, double *S, int n, int nd, int ny, int nx, double scale2,
+                            const double *norm2, hipStream_t s) {
+  const uint64_t total = (uint64_t)n * 4 * ny * nx;
+  hipLaunchKernelGGL(sv_decode_kernel, dim3(sv_grid(total)), dim3(kSvThreads), 0, s, psi, S, n, nd, ny, nx,
+                     scale2, norm2);
+  return hipGetLastError();
+}
+
+}  // namespace rtl

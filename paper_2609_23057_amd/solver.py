@@ -173,6 +173,26 @@ class Solver:
         A.rt_set_dichroism(self.ctx, _ptr(eta))
         self._eta = eta
 
+    def sv_step(self, S_in, S_out=None, work=None):
+        """One step of the statevector emulation of the paper's circuit:
+        S_in, S_out float64 device tensors [n, 4, ny, nx]; work (optional) a
+        uint8 device tensor of rt_sv_workspace_bytes().  Returns (S_out,
+        success probability)."""
+        if S_out is None:
+            S_out = torch.empty_like(S_in)
+        if S_in.dtype != torch.float64 or S_out.dtype != torch.float64:
+            raise TypeError("the statevector emulation takes float64 fields")
+        if work is None:
+            work = self.sv_workspace()
+        p = A.rt_sv_step(self.ctx, work.data_ptr(), work.numel(), S_in.data_ptr(), S_out.data_ptr())
+        return S_out, p
+
+    def sv_workspace(self):
+        nbytes = A.rt_sv_workspace_bytes(self.ctx)
+        if nbytes == 0:
+            raise A.RTError(A.RT_EUNSUPPORTED, A.rt_last_error(self.ctx))
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
     def set_layer_block(self, layers):
         """3-D lattices: layers per block of the fused step's tile order (0:
         the library's default); the result does not depend on it."""

@@ -15,8 +15,9 @@ Extras (skipped with --no-extras): forward rates at 1024x1024, n = 128 per
 contraction precision, the stand-alone streaming kernel's HBM rate at beam512
 and prec1024, the forward step at beam512 with each extension of the operator
 (tabulated scattering matrix, per-cell phase mixture, dichroic absorption),
-the 256x256x64 three-dimensional lattice, and the 64-channel spectral batch (one launch per step for all
-channels, eager and as a replayed HIP graph).
+the 256x256x64 three-dimensional lattice, the 64-channel spectral batch (one launch per channel class and step,
+eager and as a replayed HIP graph), and the statevector emulation of the paper's circuit on its 16x16, n = 8
+lattice (29 qubits).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
@@ -425,6 +426,61 @@ def batch_autotune(batch, states, steps=20):
             "separate_contexts_forward_ms_per_step": sep, "batched_speedup_vs_separate": sep / batched}
 
 
+def statevector_extras(T=4, warm=1):
+    """The statevector emulation of the paper's one-step circuit (Sec. 2.1.2 -
+    2.1.8) on its 16x16 D2Q9 lattice with 2 x 4 directions (29 qubits, a
+    2^29-amplitude float64 statevector): time per emulated step (encode,
+    every gate, post-selection, decode; HIP events around rt_sv_step on the
+    solver's stream), the statevector bytes its gate and translation
+    launches move, and the agreement with the classical step after T steps
+    (the oracle's float64 step; the paper's Tables 1-2 report 1e-13)."""
+    import numpy as np
+    import torch
+    import paper_2609_23057_amd._abi as A
+    import workloads as W
+    from oracle import lbm as OL
+    spec = W.spec("qlbm16")
+    _log("bench: statevector emulation (qlbm16)")
+    solver = make_solver(spec, "fp32")
+    nq, ndata = A.rt_sv_qubits(solver.ctx)
+    gates, shifts, nbytes = A.rt_sv_gate_count(solver.ctx)
+    work = solver.sv_workspace()
+    S0 = np.asarray(W.initial_state(spec, "zero"))
+    S = torch.zeros(S0.shape, dtype=torch.float64, device=solver.device)
+    for _ in range(warm):
+        solver.sv_step(S, work=work)
+    S.zero_()
+    torch.cuda.synchronize()
+    times, probs = [], []
+    for _ in range(T):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        S, p = solver.sv_step(S, work=work)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        probs.append(p)
+    med = W.medium(spec)
+    ref = OL.run(S0, OL.make_problem(spec, med), T)
+    got = S.cpu().numpy()
+    ms = sum(times) / len(times)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"workload": "qlbm16: 16x16 D2Q9 lattice, n=8 (2x4), k_ext=2.5, k_scat=0.5, dt=1/16, central source, "
+                       "absorbing edges; %d emulated steps with re-encoding" % T,
+           "qubits": nq, "data_qubits": ndata, "statevector_bytes": 8 << nq,
+           "gate_launches": gates, "translation_launches": shifts, "ms_per_step": ms,
+           "success_probability": probs,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes,
+                        "note": "statevector bytes of the gate and translation launches (32 per active amplitude "
+                                "pair of a gate, 16 per amplitude of a translation) over the whole step time"},
+           "max_abs_diff_vs_classical": float(np.abs(got - ref).max()),
+           "rel_l2_diff_vs_classical": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    del work, solver
+    torch.cuda.empty_cache()
+    return out
+
+
 def spectral_extras(T=200, only_tune=False):
     """The 64-channel spectral batch (per-channel lattice 128^2..512^2 and
     n = 16..64, bf16 contraction): the per-class tuning table (batch_autotune),
@@ -536,7 +592,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16", "fp16", "bf16x3"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--profile", default=None, choices=("beam512", "prec1024", "adjoint256", "beam3d"),
+    ap.add_argument("--profile", default=None, choices=("beam512", "prec1024", "adjoint256", "beam3d", "qlbm16"),
                     help="only a short run of this workload in --precision (for rocprofv3 runs)")
     ap.add_argument("--profile-adjoint", action="store_true", help="with --profile: also the adjoint")
     ap.add_argument("--batch-autotune", action="store_true",
@@ -552,6 +608,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.profile == "qlbm16":
+        # the statevector emulation (its circuit's gate kernels)
+        print(json.dumps(statevector_extras(T=args.tsteps or 2, warm=0)), flush=True)
+        return
     if args.profile:
         profile_run(args.profile, args.precision, args.tsteps or 8, args.profile_adjoint)
         return
@@ -646,6 +706,8 @@ def main():
         line["three_d"] = three_d_extras()
         torch.cuda.empty_cache()
         line["spectral_batch"] = spectral_extras()
+        torch.cuda.empty_cache()
+        line["statevector"] = statevector_extras()
         torch.cuda.empty_cache()
     if not args.no_cpu:
         _log("bench: cpu baseline (oracle)")

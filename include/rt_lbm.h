@@ -361,7 +361,9 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
  *   2^nqubits float64, gate tables, the encoded source); 0 if not emulated
  *   (rt_last_error says why).
  * rt_sv_gate_count: gate launches (rotations, controlled X/Z, H and the Q-U
- *   rotations) and translation launches of one step.
+ *   rotations) and translation launches of one step, and (if not NULL) the
+ *   statevector bytes they move: 32 per active amplitude pair of a gate (the
+ *   states whose control qubits match), 16 per amplitude of a translation.
  * rt_sv_step: one emulated step of the context's medium (rt_set_medium must
  *   have succeeded) from d_S_in to d_S_out (device float64 [n][4][ny][nx],
  *   caller-owned, may be the same array); d_work is the caller's workspace
@@ -371,7 +373,7 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
  *   small), RT_EUNSUPPORTED (see above). */
 rt_status rt_sv_qubits(const rt_ctx *c, int32_t *nqubits, int32_t *ndata);
 size_t rt_sv_workspace_bytes(const rt_ctx *c);
-rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts);
+rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts, double *bytes_per_step);
 rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d_S_in, double *d_S_out,
                      double *h_psucc);
 

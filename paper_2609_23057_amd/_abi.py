@@ -74,7 +74,7 @@ _SIGS = {
     "rt_totals_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_sv_qubits": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "rt_sv_workspace_bytes": (c_size_t, [c_void_p]),
-    "rt_sv_gate_count": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "rt_sv_gate_count": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]),
     "rt_sv_step": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, POINTER(c_double)]),
     "rt_readout_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_adjoint_segment_bytes": (c_size_t, [_P, c_int32]),
@@ -211,9 +211,10 @@ def rt_sv_workspace_bytes(ctx):
 
 
 def rt_sv_gate_count(ctx):
-    g, s = c_int32(0), c_int32(0)
-    _check(_lib.rt_sv_gate_count(ctx, ctypes.byref(g), ctypes.byref(s)), ctx)
-    return g.value, s.value
+    """(gate launches, translation launches, statevector bytes moved) per step."""
+    g, s, b = c_int32(0), c_int32(0), c_double(0.0)
+    _check(_lib.rt_sv_gate_count(ctx, ctypes.byref(g), ctypes.byref(s), ctypes.byref(b)), ctx)
+    return g.value, s.value, b.value
 
 
 def rt_sv_step(ctx, d_work, work_bytes, d_S_in, d_S_out):

@@ -1503,7 +1503,7 @@ rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d
   return st;
 }
 
-rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts) {
+rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts, double *bytes_per_step) {
   if (!c || !ngates) return set_err(RT_EINVAL, "NULL argument");
   const size_t C = (size_t)c->hp.nx * c->hp.ny;
   std::vector<float> z(C, 0.0f);
@@ -1511,9 +1511,22 @@ rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts) {
   const std::string why = sv_compile(c, z, z, z, &K);
   if (!why.empty()) return set_err(RT_EUNSUPPORTED, why);
   int g = 0, sh = 0;
-  for (const SvOp &op : K.ops) (op.shift ? sh : g) += 1;
+  double bytes = 0.0;
+  for (const SvOp &op : K.ops) {
+    if (op.shift) {
+      ++sh;
+      bytes += 16.0 * std::ldexp(1.0, K.L.nq);   // every amplitude read and written once
+    } else {
+      ++g;
+      int fixed = 0;
+      for (int b = 0; b < K.L.nq; ++b) fixed += (int)(((op.g.mask | op.g.cmask) >> b) & 1);
+      // the active pairs: two amplitudes read and written
+      bytes += 32.0 * std::ldexp(1.0, K.L.nq - fixed);
+    }
+  }
   *ngates = g;
   if (nshifts) *nshifts = sh;
+  if (bytes_per_step) *bytes_per_step = bytes;
   return RT_OK;
 }
 

@@ -26,6 +26,10 @@ struct SvGate {
   int32_t naddr;
   int32_t addr[kSvMaxAddr];
   const double *table;
+  // filled by sv_launch_gate: the mask and control bits in ascending order;
+  // threads enumerate only the states whose control bits match
+  int32_t nfixed;
+  int32_t fixed[8];
 };
 hipError_t sv_launch_gate(double *psi, int nq, const SvGate &g, hipStream_t s);
 

@@ -22,20 +22,20 @@ inline unsigned sv_grid(uint64_t work) {
   return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 1), 65536);
 }
 
-// Index with zero bits inserted at the (ascending) positions of the gate.
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t t, const SvGate &g) {
-  for (int k = 0; k < g.nbits; ++k) {
-    const int p = g.pos[k];
+// Index with zero bits inserted at the (ascending) fixed positions of the
+// gate (its pair and control qubits), then the control values set.
+__device__ __forceinline__ uint64_t insert_fixed(uint64_t t, const SvGate &g) {
+  for (int k = 0; k < g.nfixed; ++k) {
+    const int p = g.fixed[k];
     t = ((t >> p) << (p + 1)) | (t & ((1ull << p) - 1));
   }
-  return t;
+  return t | g.cval;
 }
 
 __global__ void __launch_bounds__(kSvThreads) sv_gate_kernel(double *__restrict__ psi, uint64_t npairs, SvGate g) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += stride) {
-    const uint64_t base = insert_zeros(t, g);
-    if ((base & g.cmask) != g.cval) continue;
+    const uint64_t base = insert_fixed(t, g);
     uint32_t a = 0;
     for (int j = 0; j < g.naddr; ++j) a |= (uint32_t)((base >> g.addr[j]) & 1) << j;
     const double u00 = g.table[4 * a], u01 = g.table[4 * a + 1];
@@ -150,10 +150,17 @@ __global__ void sv_decode_kernel(const double *__restrict__ psi, double *__restr
 
 }  // namespace
 
-hipError_t sv_launch_gate(double *psi, int nq, const SvGate &g, hipStream_t s) {
-  if (g.nbits < 1 || g.nbits > 2 || g.naddr < 0 || g.naddr > kSvMaxAddr || nq < g.nbits || nq > 40)
-    return hipErrorInvalidValue;
-  const uint64_t npairs = 1ull << (nq - g.nbits);
+hipError_t sv_launch_gate(double *psi, int nq, const SvGate &gate, hipStream_t s) {
+  SvGate g = gate;
+  if (g.nbits < 1 || g.nbits > 2 || g.naddr < 0 || g.naddr > kSvMaxAddr || nq > 40) return hipErrorInvalidValue;
+  if ((g.mask & g.cmask) != 0 || (g.cval & ~g.cmask) != 0 || (g.mask | g.cmask) >> nq != 0) return hipErrorInvalidValue;
+  g.nfixed = 0;
+  for (int b = 0; b < nq; ++b)
+    if (((g.mask | g.cmask) >> b) & 1) {
+      if (g.nfixed == 8) return hipErrorInvalidValue;
+      g.fixed[g.nfixed++] = b;
+    }
+  const uint64_t npairs = 1ull << (nq - g.nfixed);
   hipLaunchKernelGGL(sv_gate_kernel, dim3(sv_grid(npairs)), dim3(kSvThreads), 0, s, psi, npairs, g);
   return hipGetLastError();
 }

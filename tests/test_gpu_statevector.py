@@ -111,8 +111,9 @@ def test_paper_lattice_has_29_qubits_and_the_gate_count():
     solver, _ = build(spec)
     nq, nd = A.rt_sv_qubits(solver.ctx)
     assert (nq, nd) == (29, 17)
-    gates, shifts = A.rt_sv_gate_count(solver.ctx)
+    gates, shifts, nbytes = A.rt_sv_gate_count(solver.ctx)
     assert shifts == 2 and gates > 20
+    assert 2 * 16 * (1 << 29) < nbytes < (gates + 2) * 16 * (1 << 29)
     assert A.rt_sv_workspace_bytes(solver.ctx) >= 2 * 8 * (1 << 29)
 
 

@@ -292,6 +292,17 @@ rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);
  * on it.  RT_EINVAL for layers < 0. */
 rt_status rt_set_layer_block(rt_ctx *c, int32_t layers);
 
+/* Tuning of the 2-D fused steps' tile order: with tiles > 0 (and nx a
+ * multiple of 64 tiles) the tiles walk vertical strips `tiles` tiles of 64
+ * cells wide (tiles / 2 tiles of 32 cells), every row of a strip before the
+ * next strip, instead of the lattice's row order; the rows of all 4n planes
+ * that the tiles in flight on an XCD share with the next output rows then
+ * stay in its L2.  By default the strips are 4 tiles wide where a state
+ * exceeds 256 MiB (more than the last-level cache holds) and row order is
+ * kept below; 0 sets row order.  The result does not depend on it.
+ * RT_EINVAL for tiles < 0. */
+rt_status rt_set_tile_strip(rt_ctx *c, int32_t tiles);
+
 /* One time step of Sec. 2.1.1 (Eq. 2 split as the operator chain of Eq. 5):
  * emission X = S_in + dt J (Eq. 6/8), absorption and scattering
  * Y = alpha X + beta M X (Sec. 2.1.4-2.1.5, Eq. 11), streaming

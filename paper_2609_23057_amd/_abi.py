@@ -65,6 +65,7 @@ _SIGS = {
     "rt_set_phase_mixture": (c_int32, [c_void_p, c_int32, c_double, c_double, c_void_p]),
     "rt_set_dichroism": (c_int32, [c_void_p, c_void_p]),
     "rt_set_layer_block": (c_int32, [c_void_p, c_int32]),
+    "rt_set_tile_strip": (c_int32, [c_void_p, c_int32]),
     "rt_set_inflow": (c_int32, [c_void_p, c_void_p]),
     "rt_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rt_stream": (c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -171,6 +172,11 @@ def rt_set_dichroism(ctx, d_eta):
 def rt_set_layer_block(ctx, layers):
     """3-D lattices: layers per block of the fused step's tile order (0: default)."""
     _check(_lib.rt_set_layer_block(ctx, layers), ctx)
+
+
+def rt_set_tile_strip(ctx, tiles):
+    """2-D fused steps: tile order in vertical strips of `tiles` tiles (0: row order)."""
+    _check(_lib.rt_set_tile_strip(ctx, tiles), ctx)
 
 
 def rt_set_inflow(ctx, d_inflow):

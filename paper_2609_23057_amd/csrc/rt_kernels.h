@@ -55,6 +55,10 @@ struct StepArgs {
   // zblk layers with the layer index fastest
   int32_t ny3, nz, per_z, zblk;
   const DirTaps3 *taps3;   // [n]
+  // 2-D single-problem steps: tiles walk vertical strips (strip tiles of 64
+  // cells across, or strip / 2 tiles of 32 cells; every row, then the next
+  // strip); 0: row order.  Set only where nx is a multiple of 64 strip.
+  int32_t strip;
 };
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };

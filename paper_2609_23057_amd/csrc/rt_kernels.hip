@@ -541,6 +541,22 @@ __device__ __forceinline__ void gather_field3(const StepArgs &a, const float *__
   }
 }
 
+// First cell of 2-D tile `tile` (tiles of `cells` consecutive cells).  In
+// row order the tiles run through the lattice cell by cell; in strip order
+// (a.strip tiles wide, nx a multiple of cells * a.strip) they walk down a
+// vertical strip row by row, so the rows of all 4n planes that the tiles in
+// flight share with the next output rows stay within a few MB of L2.
+__device__ __forceinline__ int tile_cell0(const StepArgs &a, int64_t tile, int cells) {
+  const int w = a.strip;
+  if (w <= 0) return (int)(tile * cells);
+  const int nx = a.geo.nx, ny = a.geo.ny;
+  const int t = (int)tile;
+  const int per_strip = w * ny;
+  const int sidx = t / per_strip, r = t - sidx * per_strip;
+  const int y = r / w, xt = sidx * w + (r - y * w);
+  return y * nx + xt * cells;
+}
+
 // Row r of the 32x32 accumulator held by element i of a lane in half-wave h.
 __device__ __forceinline__ int acc_row(int i, int h) { return (i >> 2) * 8 + h * 4 + (i & 3); }
 
@@ -680,7 +696,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   const float *s_jrow = ts.s_jrow;
   (void)s_red;
   (void)s_x;
-  const int c0 = active ? (int)(tile * (32 * NB)) : 0;
+  const int c0 = active ? tile_cell0(a, tile, 32 * NB) : 0;
   // adjoint mu in registers: only for fp16, whose per-cell scale needs the
   // whole cell before mu can be converted (fp32 gathers mu into its B tile,
   // bf16 and bf16x3 into high and low 16-bit tiles)
@@ -1405,6 +1421,11 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
   const int64_t ntiles = G3 ? (int64_t)((a.geo.nx + 32 * NB - 1) / (32 * NB)) * a.ny3 * a.nz
                             : (a.geo.C + 32 * NB - 1) / (32 * NB);
   if (G3 && (a.zblk < 1 || a.ny3 * a.nz != a.geo.ny || ntiles > INT32_MAX)) return hipErrorInvalidValue;
+  // strip order: a.strip tiles wide for 64-cell tiles, half as many (at
+  // least one) for 32-cell tiles (the widths measured fastest per tile size)
+  StepArgs args = a;
+  if (!G3 && args.strip > 0) args.strip = NB == 2 ? args.strip : std::max(1, args.strip / 2);
+  if (ntiles > INT32_MAX) return hipErrorInvalidValue;
   auto k = fused_kernel<PREC, GATHER, ADJ, MAXW, CKPT, NB, EXT, G3>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
   if (e != hipSuccess) return e;
@@ -1417,7 +1438,7 @@ hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count)
   int64_t grid = std::min<int64_t>(ntiles, (int64_t)cu_count * occ);
   if (grid >= 8) grid &= ~7LL;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, a, ntiles);
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * W), L.total, s, args, ntiles);
   return hipGetLastError();
 }
 

@@ -193,6 +193,11 @@ class Solver:
             raise A.RTError(A.RT_EUNSUPPORTED, A.rt_last_error(self.ctx))
         return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
 
+    def set_tile_strip(self, tiles):
+        """2-D lattices: vertical strips of `tiles` tiles as the fused steps'
+        tile order (0: row order); the result does not depend on it."""
+        A.rt_set_tile_strip(self.ctx, int(tiles))
+
     def set_layer_block(self, layers):
         """3-D lattices: layers per block of the fused step's tile order (0:
         the library's default); the result does not depend on it."""

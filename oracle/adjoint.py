@@ -10,7 +10,8 @@ oracle.lbm, written from the chain rule.  With
 and lambda_T = dLoss/dS_T, for t = T-1 .. 0:
   mu_t     = L^T lambda_{t+1}          (dLoss/dY_t)
   nu_t     = M^T mu_t                  (with a per-cell phase mixture, whose
-             scattering is (1 - f) M X + f M2 X: (1 - f) M^T mu_t + f M2^T mu_t)
+             scattering is (1 - sum f_k) M X + sum f_k M_k X: the same
+             fractions of M^T mu_t and M_k^T mu_t)
   lambda_t = alpha mu_t + beta nu_t    (dLoss/dX_t = dLoss/dS_t)
   g_alpha += <mu_t, X_t>,  g_beta += <nu_t, X_t>   (per cell, over d and s)
   g_emis  += dt <e lambda_t + (1 - e) mu_t, jprof>
@@ -46,10 +47,7 @@ def adjoint(S0, prob, nsteps, lam_T):
         if prob.eta is not None:
             X = lbm.dichroic_absorption(X0, prob)
         mu = lbm.stream_transpose(lam, prob).reshape(4 * n, C)
-        nu = prob.M.T @ mu
-        if prob.M2 is not None:
-            f = prob.frac.reshape(1, C)
-            nu = (1.0 - f) * nu + f * (prob.M2.T @ mu)
+        nu = lbm.scatter_product(prob, mu, transpose=True)
         g_al += np.sum(mu * X, axis=0)
         g_be += np.sum(nu * X, axis=0)
         lam_x = al[None, :] * mu + be[None, :] * nu
@@ -97,7 +95,7 @@ def edge_loss_of(params, base_prob, S0, nsteps, edge):
     p = lbm.Problem(base_prob.nx, base_prob.ny, base_prob.dirs, base_prob.shifts,
                     base_prob.M, base_prob.dt, base_prob.bc, tau, alb, em,
                     base_prob.jprof, base_prob.inflow_cells, base_prob.abs_taylor,
-                    base_prob.scat_exp, base_prob.fused_taylor, M2=base_prob.M2, frac=base_prob.frac,
+                    base_prob.scat_exp, base_prob.fused_taylor, M2=base_prob.mix_M, frac=base_prob.mix_f,
                     dichroism=base_prob.eta)
     S = lbm.run(S0, p, nsteps)
     return lbm.edge_loss(S, p, edge)[0]

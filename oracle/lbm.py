@@ -30,10 +30,12 @@ polarisations along the meridian axes by their own absorption factors before
 the scattering.
 
 Phase-function mixtures (the per-cell aerosol / cloud fractions that the
-paper's conclusion names as the next step, Sec. 4): a second collision matrix
-M2 and a per-cell fraction f in [0, 1] of the scattering that follows it,
-Y = alpha X + beta ((1 - f) M X + f M2 X).  The redistribution of a cell is the
-f-weighted mixture of two phase functions, each normalised as in Eq. 17.
+paper's conclusion names as the next step, Sec. 4): further collision
+matrices M_1 .. M_{K-1} and per-cell fractions f_k >= 0 with sum_k f_k <= 1
+of the scattering that follows each, the first matrix taking the rest:
+Y = alpha X + beta ((1 - sum_k f_k) M X + sum_k f_k M_k X).  The
+redistribution of a cell is the fraction-weighted mixture of K phase
+functions, each normalised as in Eq. 17 (K = 2: (1 - f) M X + f M2 X).
 """
 import math
 import numpy as np
@@ -84,14 +86,20 @@ class Problem:
             raise ValueError("y edges must both be periodic or neither")
         self.alpha, self.beta = coefficients(self.tau, self.albedo, self.abs_taylor,
                                              self.scat_exp, self.fused_taylor)
-        # optional phase mixture: second collision matrix and per-cell fraction
-        self.M2 = None if M2 is None else np.asarray(M2, dtype=np.float64)
-        self.frac = None
-        if self.M2 is not None:
-            f = np.zeros((self.ny, self.nx)) if frac is None else frac
-            self.frac = np.asarray(f, dtype=np.float64).reshape(self.ny, self.nx)
-            if np.any(self.frac < 0.0) or np.any(self.frac > 1.0):
-                raise ValueError("mixture fraction outside [0, 1]")
+        # optional phase mixture: M2 is one further collision matrix (frac
+        # [ny, nx]) or a sequence of K - 1 of them (frac [K - 1, ny, nx])
+        self.mix_M, self.mix_f = None, None
+        if M2 is not None:
+            Ms = [M2] if np.ndim(M2) == 2 else list(M2)
+            if not Ms:
+                raise ValueError("a mixture needs at least one further phase function")
+            self.mix_M = [np.asarray(m, dtype=np.float64) for m in Ms]
+            k = len(self.mix_M)
+            f = np.zeros((k, self.ny, self.nx)) if frac is None else frac
+            self.mix_f = np.asarray(f, dtype=np.float64).reshape(k, self.ny, self.nx)
+            if (np.any(~np.isfinite(self.mix_f)) or np.any(self.mix_f < 0.0)
+                    or np.any(self.mix_f.sum(axis=0) > 1.0)):
+                raise ValueError("mixture fractions must be >= 0 with a sum <= 1 per cell")
         # optional dichroic absorption: per-cell linear dichroism eta
         self.eta = None
         if dichroism is not None:
@@ -100,6 +108,23 @@ class Problem:
                 raise ValueError("dichroism eta must satisfy |eta| < 1")
             if self.abs_taylor or self.fused_taylor:
                 raise ValueError("dichroic absorption is defined for Beer-Lambert absorption")
+
+    @property
+    def M2(self):
+        """The first further matrix of a phase mixture (None without one);
+        setting None removes the mixture."""
+        return None if self.mix_M is None else self.mix_M[0]
+
+    @M2.setter
+    def M2(self, value):
+        if value is not None:
+            raise ValueError("a mixture is given to the constructor")
+        self.mix_M, self.mix_f = None, None
+
+    @property
+    def frac(self):
+        """Per-cell fraction of the first further matrix (None without a mixture)."""
+        return None if self.mix_f is None else self.mix_f[0]
 
     @property
     def shape(self):
@@ -277,6 +302,19 @@ def dichroic_absorption(X, prob):
     return Xd.reshape(X.shape)
 
 
+def scatter_product(prob, X, transpose=False):
+    """M X per cell, or with a phase mixture (1 - sum_k f_k) M X + sum_k
+    f_k M_k X; with transpose the same with M^T and M_k^T (the adjoint)."""
+    op = (lambda A: A.T) if transpose else (lambda A: A)  # noqa: E731
+    P = op(prob.M) @ X
+    if prob.mix_M is not None:
+        f = prob.mix_f.reshape(len(prob.mix_M), 1, -1)
+        P = (1.0 - f.sum(axis=0)) * P
+        for k, Mk in enumerate(prob.mix_M):
+            P = P + f[k] * (op(Mk) @ X)
+    return P
+
+
 def collide(S, prob):
     """Emission, absorption and scattering at every cell (steps 1-3)."""
     n = prob.n
@@ -289,10 +327,7 @@ def collide(S, prob):
         X = dichroic_absorption(X, prob)
     al = prob.alpha.reshape(1, C)
     be = prob.beta.reshape(1, C)
-    MX = prob.M @ X
-    if prob.M2 is not None:
-        f = prob.frac.reshape(1, C)
-        MX = (1.0 - f) * MX + f * (prob.M2 @ X)
+    MX = scatter_product(prob, X)
     Y = al * X + be * MX
     Y = Y.reshape(prob.shape)
     if prob.fused_taylor:
@@ -402,6 +437,20 @@ def readout_transpose(g, prob, edge):
 
 # ------------------------------------------------------------ construction --
 
+def mixture_matrices(dirs, spec):
+    """The further collision matrices of spec["mixture"]: None, one matrix
+    for a single phase function (a dict), a list for a list of them."""
+    mix = spec.get("mixture")
+    if mix is None:
+        return None
+
+    def build(ph):
+        return _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
+                                       ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
+                                       spec.get("scalar", False), ph.get("table"))
+    return build(mix) if isinstance(mix, dict) else [build(ph) for ph in mix]
+
+
 def make_problem(spec, medium):
     """Build a Problem from a workload spec and a medium (see workloads)."""
     if spec.get("dir_xyz") is not None:
@@ -421,14 +470,8 @@ def make_problem(spec, medium):
     M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
                                 ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
                                 spec.get("scalar", False), ph.get("table"))
-    M2 = None
-    if spec.get("mixture") is not None:
-        ph2 = spec["mixture"]
-        M2 = _phase.collision_matrix(dirs, ph2.get("kind", "rayleigh"), ph2.get("g", 0.0),
-                                     ph2.get("mix_ray", 1.0), spec.get("renorm_irow", False),
-                                     spec.get("scalar", False), ph2.get("table"))
     return Problem(spec["nx"], spec["ny"], dirs, shifts, M, spec.get("dt", 1.0), spec["bc"],
                    medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
                    medium.get("inflow"), spec.get("abs_taylor", False),
                    spec.get("scat_exp", False), spec.get("fused_taylor", False),
-                   M2=M2, frac=medium.get("frac"), dichroism=medium.get("eta"))
+                   M2=mixture_matrices(dirs, spec), frac=medium.get("frac"), dichroism=medium.get("eta"))

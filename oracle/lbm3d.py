@@ -48,9 +48,12 @@ class Problem3D:
         self.inflow = np.asarray(inflow6, dtype=np.float64).reshape(6, self.n, 4)
         flat = lambda a: None if a is None else np.asarray(a, dtype=np.float64).reshape(  # noqa: E731
             self.nz * self.ny, self.nx)
-        for k in ("frac", "dichroism"):
-            if opts.get(k) is not None:
-                opts[k] = flat(opts[k])
+        if opts.get("dichroism") is not None:
+            opts["dichroism"] = flat(opts["dichroism"])
+        if opts.get("frac") is not None:
+            # [nz, ny, nx] or, for several further phase functions, [K - 1, nz, ny, nx]
+            f = np.asarray(opts["frac"], dtype=np.float64)
+            opts["frac"] = f.reshape(-1, self.nz * self.ny, self.nx) if f.ndim == 4 else flat(f)
         self.flat = lbm.Problem(self.nx, self.ny * self.nz, dirs, self.shifts[:, :2], M, dt, (0, 0, 0, 0),
                                 flat(tau), flat(albedo), flat(emis), jprof, None, **opts)
 
@@ -132,12 +135,7 @@ def make_problem(spec, medium):
     M = _phase.collision_matrix(dirs, ph.get("kind", "rayleigh"), ph.get("g", 0.0),
                                 ph.get("mix_ray", 1.0), spec.get("renorm_irow", False),
                                 spec.get("scalar", False), ph.get("table"))
-    M2 = None
-    if spec.get("mixture") is not None:
-        ph2 = spec["mixture"]
-        M2 = _phase.collision_matrix(dirs, ph2.get("kind", "rayleigh"), ph2.get("g", 0.0),
-                                     ph2.get("mix_ray", 1.0), spec.get("renorm_irow", False),
-                                     spec.get("scalar", False), ph2.get("table"))
+    M2 = lbm.mixture_matrices(dirs, spec)
     p3 = Problem3D(spec["nx"], spec["ny"], spec["nz"], dirs, spec.get("courant", 1.0), spec["bc6"], M,
                      spec.get("dt", 1.0), medium["tau"], medium["albedo"], medium["emis"], medium["jprof"],
                      medium.get("inflow"), abs_taylor=spec.get("abs_taylor", False),
@@ -183,7 +181,7 @@ def stream_transpose(G, prob):
 def adjoint(S0, prob, nsteps, lam_T):
     """Reverse-mode gradient on a 3-D lattice, the chain rule of oracle.adjoint
     with the 3-D streaming: for t = T-1 .. 0, mu = L^T lambda_{t+1},
-    nu = M^T mu (mixed as in the forward step: (1 - f) M^T mu + f M2^T mu),
+    nu = M^T mu (mixed as in the forward step: (1 - sum f_k) M^T mu + sum f_k M_k^T mu),
     lambda_t = alpha mu + beta nu, g_alpha += <mu, X_t>,
     g_beta += <nu, X_t>, g_emis += dt <e lambda_t + (1 - e) mu, jprof>.
     Returns dict(lambda0, g_alpha, g_beta, g_tau, g_albedo, g_emis), per-cell
@@ -204,10 +202,7 @@ def adjoint(S0, prob, nsteps, lam_T):
         if f.eta is not None:
             X = lbm.dichroic_absorption(X0, f)
         mu = stream_transpose(lam, prob).reshape(4 * n, C)
-        nu = f.M.T @ mu
-        if f.M2 is not None:
-            fr = f.frac.reshape(1, C)
-            nu = (1.0 - fr) * nu + fr * (f.M2.T @ mu)
+        nu = lbm.scatter_product(f, mu, transpose=True)
         g_al += np.sum(mu * X, axis=0)
         g_be += np.sum(nu * X, axis=0)
         lam_x = al[None, :] * mu + be[None, :] * nu

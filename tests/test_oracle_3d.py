@@ -146,10 +146,14 @@ def test_stream_transpose_is_the_transpose(bc6):
     assert lhs == pytest.approx(rhs, rel=1e-12)
 
 
-@pytest.mark.parametrize("ext", [None, "mixture", "dichroism"])
+MIXTURES = {"mixture": {"kind": "hg", "g": -0.4},
+            "mixture3": [{"kind": "hg", "g": -0.4}, {"kind": "rayleigh"}]}
+
+
+@pytest.mark.parametrize("ext", [None, "mixture", "mixture3", "dichroism"])
 def test_adjoint3d_matches_central_differences(ext):
     s3 = spec3(nx=4, ny=3, nz=3, bc6=(1, 1, 0, 0, 1, 2), n_zen=2, n_az=4, source="uniform_emis", emis_max=0.05,
-               mixture={"kind": "hg", "g": -0.4} if ext == "mixture" else None,
+               mixture=MIXTURES.get(ext),
                dichroism=0.8 if ext == "dichroism" else None)
     med = W.medium(s3)
     med["tau"] = med["tau"] * 40.0

@@ -467,9 +467,13 @@ def test_p14_dense_operator_and_multi_step():
 
 # ----------------------------------------------------------------- P15 --
 
+MIX3 = [{"kind": "hg", "g": -0.4}, {"kind": "mix", "g": 0.7, "mix_ray": 0.3}]
+
+
 def _adj_problem(fused=False, scat_exp=False, abs_taylor=False, mixture=False, dichroism=False):
-    s = W.spec("adjoint256", nx=10, ny=8, n_zen=2, n_az=4,
-               mixture={"kind": "hg", "g": -0.4} if mixture else None, dichroism=0.8 if dichroism else None)
+    """mixture: False, True (one further HG(-0.4) phase) or a list of phases."""
+    mix = {"kind": "hg", "g": -0.4} if mixture is True else (mixture or None)
+    s = W.spec("adjoint256", nx=10, ny=8, n_zen=2, n_az=4, mixture=mix, dichroism=0.8 if dichroism else None)
     med = W.medium(s)
     med["tau"] = med["tau"] * 10.0
     s["fused_taylor"] = fused
@@ -478,14 +482,17 @@ def _adj_problem(fused=False, scat_exp=False, abs_taylor=False, mixture=False, d
     return s, OL.make_problem(s, med)
 
 
-@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "abs_taylor", "mixture", "dichroism"])
+@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "abs_taylor", "mixture", "mixture3",
+                                     "dichroism"])
 def test_p15_adjoint_dot_product(variant):
     """<A x, y> = <x, A^T y> for the T-step linear part: the adjoint state
     lambda_0 from lambda_T = y must satisfy <S_T(x) - S_T(0), y> = <x, lambda_0>."""
     s, prob = _adj_problem(variant == "fused", variant == "scat_exp", variant == "abs_taylor",
-                           variant == "mixture", variant == "dichroism")
+                           MIX3 if variant == "mixture3" else variant == "mixture", variant == "dichroism")
     if variant == "mixture":
         assert prob.M2 is not None and 0.1 < prob.frac.mean() < 0.9
+    if variant == "mixture3":
+        assert len(prob.mix_M) == 2 and np.all(prob.mix_f.mean(axis=(1, 2)) > 0.2)
     T = 7
     rng = np.random.default_rng(11)
     x = rng.normal(size=prob.shape)
@@ -498,12 +505,14 @@ def test_p15_adjoint_dot_product(variant):
     assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
 
 
-@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "mixture", "dichroism"])
+@pytest.mark.parametrize("variant", ["split", "fused", "scat_exp", "mixture", "mixture3", "dichroism"])
 def test_p15_adjoint_gradients_match_central_differences(variant):
     """Gradients of the top-edge (I + DoLP) loss wrt per-cell tau, albedo and
     emission against FP64 central differences on sampled cells (the mixture
-    variant: a per-cell HG(-0.4) fraction of the scattering)."""
-    s, prob = _adj_problem(variant == "fused", variant == "scat_exp", mixture=variant == "mixture",
+    variant: a per-cell HG(-0.4) fraction of the scattering; mixture3: three
+    phase functions with Dirichlet fractions)."""
+    s, prob = _adj_problem(variant == "fused", variant == "scat_exp",
+                           mixture=MIX3 if variant == "mixture3" else variant == "mixture",
                            dichroism=variant == "dichroism")
     if variant == "dichroism":
         assert prob.eta is not None and np.abs(prob.eta).max() > 0.5
@@ -638,3 +647,100 @@ def test_mixture_fraction_outside_unit_interval_is_refused():
     p_hg, p_ray, _, _ = _mixture_setup()
     with pytest.raises(ValueError):
         _with_mixture(p_hg, p_ray.M, np.full((p_hg.ny, p_hg.nx), 1.5))
+
+
+# Mixtures of K phase functions: further matrices M_1 .. M_{K-1} and per-cell
+# fractions f_k >= 0, sum_k f_k <= 1, the first matrix taking the rest.  Pinned
+# against the single-phase problems (one-hot fractions), the two-phase form,
+# convexity, the order and splitting of components, and conservation.
+
+def _k_setup(**kw):
+    """Four phase functions on one medium: HG(0.6) (the context's own),
+    Rayleigh, HG(-0.5) and a Rayleigh / HG(0.3) mix."""
+    p_hg, p_ray, S, rng = _mixture_setup(**kw)
+    nx, ny = p_hg.nx, p_hg.ny
+    p_back = _with_mixture(p_hg, None, None)
+    p_back.M = OP.collision_matrix(p_hg.dirs, "hg", -0.5, 1.0, kw.get("renorm", False), False)
+    p_mix = _with_mixture(p_hg, None, None)
+    p_mix.M = OP.collision_matrix(p_hg.dirs, "mix", 0.3, 0.5, kw.get("renorm", False), False)
+    return [p_hg, p_ray, p_back, p_mix], S, rng, (ny, nx)
+
+
+def _dirichlet(rng, k, shape):
+    e = -np.log1p(-rng.uniform(0.0, 1.0, (k + 1,) + shape))
+    return (e / e.sum(axis=0))[1:]
+
+
+def test_k_mixture_one_hot_cells_take_each_phase_function():
+    """Each cell follows one of four phase functions (one-hot fractions): the
+    collision there is that phase function's own, to the bit."""
+    probs, S, rng, shp = _k_setup()
+    pick = rng.integers(0, 4, shp)
+    pick[0, :4] = [0, 1, 2, 3]
+    f = np.stack([(pick == k).astype(float) for k in (1, 2, 3)])
+    mixed = OL.collide(S, _with_mixture(probs[0], [p.M for p in probs[1:]], f))
+    for k, p in enumerate(probs):
+        own = OL.collide(S, p)
+        assert np.array_equal(mixed[..., pick == k], own[..., pick == k]), k
+    assert not np.allclose(OL.collide(S, probs[2]), OL.collide(S, probs[3]))
+
+
+def test_k_mixture_with_one_further_phase_is_the_two_phase_form():
+    probs, S, rng, shp = _k_setup()
+    f = rng.uniform(0.0, 1.0, shp)
+    two = _with_mixture(probs[0], probs[1].M, f)
+    listed = _with_mixture(probs[0], [probs[1].M], f[None])
+    assert np.array_equal(OL.run(S, two, 3), OL.run(S, listed, 3))
+
+
+def test_k_mixture_collision_is_the_convex_combination_of_the_phases():
+    """Per cell, (1 - sum f_k) times the first phase function's collision plus
+    f_k times each further one's."""
+    probs, S, rng, shp = _k_setup()
+    f = _dirichlet(rng, 3, shp)
+    Yf = OL.collide(S, _with_mixture(probs[0], [p.M for p in probs[1:]], f))
+    Ys = [OL.collide(S, p) for p in probs]
+    ref = (1.0 - f.sum(axis=0)) * Ys[0] + sum(f[k] * Ys[k + 1] for k in range(3))
+    assert np.abs(Yf - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+def test_k_mixture_order_and_splitting_of_components_do_not_matter():
+    """Listing the further components in another order (with their
+    fractions), or splitting one component's fraction over two copies of it,
+    leaves a 5-step run unchanged up to rounding."""
+    probs, S, rng, shp = _k_setup()
+    f = _dirichlet(rng, 3, shp)
+    Ms = [p.M for p in probs[1:]]
+    ref = OL.run(S, _with_mixture(probs[0], Ms, f), 5)
+    perm = [2, 0, 1]
+    got = OL.run(S, _with_mixture(probs[0], [Ms[k] for k in perm], f[perm]), 5)
+    assert np.abs(got - ref).max() < 1e-14 * np.abs(ref).max()
+    split = rng.uniform(0.0, 1.0, shp)
+    f4 = np.concatenate([f, (1.0 - split)[None] * f[1:2]])
+    f4[1] = split * f[1]
+    got = OL.run(S, _with_mixture(probs[0], Ms + [Ms[1]], f4), 5)
+    assert np.abs(got - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+def test_k_mixture_conserves_total_intensity_without_absorption():
+    probs, S, rng, shp = _k_setup(albedo=1.0, renorm=True, emis=None, jprof=None)
+    prob = _with_mixture(probs[0], [p.M for p in probs[1:]], _dirichlet(rng, 3, shp))
+    tot0 = S[:, 0].sum()
+    for _ in range(20):
+        S = OL.step(S, prob)
+    assert abs(S[:, 0].sum() - tot0) < 1e-12 * tot0
+
+
+def test_k_mixture_fractions_summing_past_one_are_refused():
+    probs, _, _, shp = _k_setup()
+    Ms = [p.M for p in probs[1:]]
+    f = np.full((3,) + shp, 0.3)
+    _with_mixture(probs[0], Ms, f)                        # sum 0.9: accepted
+    f[2, 1, 2] = 0.45
+    with pytest.raises(ValueError):
+        _with_mixture(probs[0], Ms, f)                    # sum 1.05 in one cell
+    f[2, 1, 2] = -0.01
+    with pytest.raises(ValueError):
+        _with_mixture(probs[0], Ms, f)
+    with pytest.raises(ValueError):
+        _with_mixture(probs[0], [], np.zeros((0,) + shp))

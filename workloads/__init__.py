@@ -24,7 +24,10 @@ Workloads (the paper's method at the sizes it is benchmarked on here):
   adjoint256   256x256, n = 32, beam512 generator plus emission U[0, 0.05],
                top-edge (I + DoLP) loss after 500 steps
   (any)        with mixture={phase}: a second phase function and a per-cell
-               fraction U[0, 1] of the scattering that follows it
+               fraction U[0, 1] of the scattering that follows it; with
+               mixture=[{phase}, ...] (K - 1 further phase functions): per-cell
+               fractions of all K drawn from the flat Dirichlet distribution,
+               frac [K - 1, ny, nx] for the further ones (their sum <= 1)
   (any)        with dichroism=d: a per-cell linear dichroism eta ~ U[-d, d]
                of the absorption
   (any)        with phase={"kind": "table", "table": scattering_table()}: a
@@ -160,8 +163,16 @@ def medium(s, seed=None):
     # second phase function (drawn after everything else, so the other
     # fields do not depend on whether a mixture is asked for)
     frac = None
-    if s.get("mixture") is not None:
+    if isinstance(s.get("mixture"), dict):
         frac = _f32(rng.uniform(0.0, 1.0, size=(ny, nx)))
+    elif s.get("mixture") is not None:
+        # flat Dirichlet over the K components (normalised exponential
+        # draws); the further K - 1 shares are kept, shrunk by 2^-20 so that
+        # their float32 values still sum to at most 1
+        k = len(s["mixture"])
+        e = -np.log1p(-rng.uniform(0.0, 1.0, size=(k + 1, ny, nx)))
+        frac = _f32(e[1:] / e.sum(axis=0) * (1.0 - 2.0 ** -20))
+        assert np.all(frac.astype(np.float64).sum(axis=0) <= 1.0)
     # dichroic absorption: per-cell linear dichroism eta ~ U[-d, d], d < 1
     # (drawn last for the same reason)
     eta = None
@@ -173,7 +184,7 @@ def medium(s, seed=None):
     if three_d:
         for k in ("tau", "albedo", "emis", "frac", "eta"):
             if out[k] is not None:
-                out[k] = out[k].reshape(nz, s["ny"], nx)
+                out[k] = out[k].reshape(out[k].shape[:-2] + (nz, s["ny"], nx))
     return out
 
 

@@ -210,7 +210,9 @@ def extension_extras(T=20, warm=3):
     operator beside the plain workload, per contraction precision: a
     tabulated scattering matrix (P12, P34 != 0), a per-cell phase-function
     mixture (HG(0.7) and Rayleigh, fraction U[0, 1]; two contractions per
-    cell) and dichroic absorption (eta U[-0.8, 0.8]; applied in the gather).
+    cell), a mixture of four phase functions (HG(0.7), Rayleigh, HG(-0.3),
+    Rayleigh / HG(0.5); flat Dirichlet fractions; four contractions per cell)
+    and dichroic absorption (eta U[-0.8, 0.8]; applied in the gather).
     For the plain workload, the mixture and the dichroism also the
     checkpointed adjoint over the same steps (per-step cost and adjoint /
     checkpointed-forward ratio)."""
@@ -223,6 +225,8 @@ def extension_extras(T=20, warm=3):
         "single": (base, None),
         "table": (W.spec("beam512", phase={"kind": "table", "table": W.scattering_table()}), None),
         "mixture": (W.spec("beam512", mixture={"kind": "rayleigh"}), "mixture"),
+        "mixture4": (W.spec("beam512", mixture=[{"kind": "rayleigh"}, {"kind": "hg", "g": -0.3},
+                                                {"kind": "mix", "g": 0.5, "mix_ray": 0.4}]), "mixture"),
         "dichroism": (W.spec("beam512", dichroism=0.8), "dichroism"),
     }
     res = {}
@@ -248,7 +252,7 @@ def extension_extras(T=20, warm=3):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
             out[name] = {"cell_dir_updates_per_s": C * n * T / (ms / 1e3), "ms_per_time_step": ms / T}
-            if name in ("single", "mixture", "dichroism"):
+            if name in ("single", "mixture", "mixture4", "dichroism"):
                 # the checkpointed forward and its adjoint (recompute + adjoint steps)
                 K = max(1, int(math.ceil(math.sqrt(T))))
                 ck = solver.checkpoint_buffer(T, K)
@@ -271,7 +275,8 @@ def extension_extras(T=20, warm=3):
             out[name]["cost_vs_single"] = out[name]["ms_per_time_step"] / out["single"]["ms_per_time_step"]
         res[prec] = out
     return {"workload": "beam512 (512x512, n=32), forward steps: plain workload, tabulated scattering matrix, "
-                        "per-cell HG(0.7)/Rayleigh mixture, dichroic absorption", "steps": T, "rates": res}
+                        "per-cell HG(0.7)/Rayleigh mixture, four-phase mixture, dichroic absorption",
+            "steps": T, "rates": res}
 
 
 def three_d_extras(T=10, warm=2, reps=20):

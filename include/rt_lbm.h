@@ -167,7 +167,14 @@ typedef struct {
   const double *dir_xyz;
   const double *dir_domega;
   const double *shift;
+  /* Phase mixtures (rt_set_phase_mixture_k): how many further phase
+   * functions the context can hold, 0 .. RT_MIX_MAX (0 counts as 1); the
+   * workspace keeps their matrices and per-cell fractions. */
+  int32_t mix_max;
 } rt_problem;
+
+/* Most further phase functions of one mixture (K = 1 + k <= 8 in all). */
+#define RT_MIX_MAX 7
 
 /* ---- host-only helpers (no device needed) ------------------------------ */
 
@@ -259,6 +266,29 @@ rt_status rt_set_inflow(rt_ctx *c, const float *d_inflow);
  * contracts M^T and M2^T, packed here too, and blends them per cell);
  * rt_batch_run and rt_batch_adjoint return RT_EUNSUPPORTED while one is set. */
 rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac);
+
+/* Per-cell mixture of K = 1 + k phase functions (the aerosol and cloud
+ * mixtures of Sec. 4 with more than two components).  The scattered part of
+ * the collision becomes beta ((1 - sum_j f_j) M X + sum_j f_j M_j X): M_j is
+ * the collision matrix that phase[j] / g[j] / mix_ray[j] (host arrays [k],
+ * same meaning as rt_problem's phase / g / mix_ray; not RT_PHASE_TABLE)
+ * build with the context's other fields, and f_j the per-cell fractions
+ * d_frac (device float32 [k][ny][nx], [k][nz][ny][nx] on a 3-D lattice,
+ * copied into the workspace) with f_j >= 0 and sum_j f_j <= 1 in every cell;
+ * M keeps the rest.  k = 0 removes the mixture (the other arguments are then
+ * ignored); rt_set_phase_mixture(c, phase2, g2, mix_ray2, d_frac) is k = 1.
+ * Every precision, rt_step / rt_run / rt_adjoint, the plain path and 3-D
+ * lattices (on the two-launch step) carry it as they carry two components;
+ * each further matrix costs one more contraction per step.  Synchronises
+ * the stream (the fractions are checked on the host).  Errors: RT_EINVAL for
+ * k < 0, k above the context's rt_problem.mix_max (0 counting as 1), NULL
+ * arrays, or an invalid phase function; RT_ERANGE if a fraction is negative
+ * or not finite, if the fractions of a cell sum past 1 (summed in double),
+ * or, for RT_FP16, if a further matrix exceeds the fp16 range at M's scale
+ * (the mixture is then off); RT_EUNSUPPORTED while dichroic absorption is
+ * set. */
+rt_status rt_set_phase_mixture_k(rt_ctx *c, int32_t k, const int32_t *phase, const double *g, const double *mix_ray,
+                                 const float *d_frac);
 
 /* Dichroic absorption (polarisation-dependent extinction, which the paper's
  * conclusions name as missing).  The absorption optical depth of direction d

@@ -32,7 +32,11 @@ class RtProblem(ctypes.Structure):
                 ("dt", c_double), ("flags", c_uint32), ("precision", c_int32),
                 ("n_table", c_int32), ("table", POINTER(c_double)),
                 ("nz", c_int32), ("bc_z", c_int32 * 2),
-                ("dir_xyz", POINTER(c_double)), ("dir_domega", POINTER(c_double)), ("shift", POINTER(c_double))]
+                ("dir_xyz", POINTER(c_double)), ("dir_domega", POINTER(c_double)), ("shift", POINTER(c_double)),
+                ("mix_max", c_int32)]
+
+
+RT_MIX_MAX = 7
 
 
 class RTError(RuntimeError):
@@ -63,6 +67,7 @@ _SIGS = {
     "rt_init": (c_int32, [_P, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "rt_set_medium": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_set_phase_mixture": (c_int32, [c_void_p, c_int32, c_double, c_double, c_void_p]),
+    "rt_set_phase_mixture_k": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rt_set_dichroism": (c_int32, [c_void_p, c_void_p]),
     "rt_set_layer_block": (c_int32, [c_void_p, c_int32]),
     "rt_set_tile_strip": (c_int32, [c_void_p, c_int32]),
@@ -162,6 +167,18 @@ def rt_set_medium(ctx, d_tau, d_albedo, d_emis, h_jprof, h_inflow=None):
 def rt_set_phase_mixture(ctx, phase2, g2, mix_ray2, d_frac):
     """phase2 < 0 removes the mixture; d_frac: device [ny][nx] float32 in [0, 1]."""
     _check(_lib.rt_set_phase_mixture(ctx, phase2, g2, mix_ray2, d_frac), ctx)
+
+
+def rt_set_phase_mixture_k(ctx, phases, gs, mix_rays, d_frac):
+    """K - 1 = len(phases) further phase functions (host lists; empty removes
+    the mixture); d_frac: device [K - 1][ny][nx] float32, each >= 0, sum <= 1."""
+    k = len(phases)
+    if not (len(gs) == len(mix_rays) == k):
+        raise ValueError("phases, gs and mix_rays must have one entry per further phase function")
+    ph = (c_int32 * max(k, 1))(*phases)
+    g = (c_double * max(k, 1))(*gs)
+    mr = (c_double * max(k, 1))(*mix_rays)
+    _check(_lib.rt_set_phase_mixture_k(ctx, k, ph, g, mr, d_frac if k else None), ctx)
 
 
 def rt_set_dichroism(ctx, d_eta):

@@ -36,7 +36,8 @@ struct Layout {
   size_t jrow, ghost, ghost3;     // set by rt_set_medium (ghost3: the 3-D faces)
   size_t mix_tiles, mix_frag, mix_frag_lo, mix_MT, frac;   // phase mixture (rt_set_phase_mixture)
   size_t mix_tiles_adj, mix_frag_adj, mix_frag_adj_lo;       // its transpose, for the adjoint
-  size_t mix_tiles_bytes, mix_frag_bytes;
+  size_t mix_tiles_bytes, mix_frag_bytes;   // per further matrix
+  int mix_count;                             // further matrices the regions hold (rt_problem.mix_max, at least 1)
   size_t dich_eta, dich_xi, dich_w;   // dichroic absorption (rt_set_dichroism); 0 bytes if unsupported
   size_t tau, alb, emis, alpha, beta;
   size_t gacc, partial, sums, bad;
@@ -78,8 +79,9 @@ void pack_all(const HostPlan &hp, int prec, Packed *pk) {
   }
 }
 
-Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_flags_plain) {
+Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_flags_plain, int mix_max) {
   Layout L{};
+  L.mix_count = std::max(1, mix_max);
   const size_t C = (size_t)hp.nx * hp.ny;
   const size_t state = C * 4 * hp.n * sizeof(float);
   const int ntile = hp.Rpad / kTileRows;
@@ -114,25 +116,26 @@ Layout make_layout(const HostPlan &hp, const Packed &pk, int prec, bool prec_fla
   // one row per face in ghost3 (6 faces + zeros)
   L.ghost = take((size_t)(2 * ((size_t)hp.nx + hp.ny) + 1) * hp.Rpad * sizeof(float));
   L.ghost3 = take(7 * hp.Rpad * sizeof(float));
-  // phase mixture: tile ranges and dense A fragments of the second matrix and
-  // of its transpose in the contraction precision (float32 for the plain path,
-  // whose adjoint replays on the fused float32 kernels), the plain path's
-  // float32 M2^T, per-cell fraction
+  // phase mixture, for each of mix_count further matrices: tile ranges and
+  // dense A fragments of the matrix and of its transpose in the contraction
+  // precision (float32 for the plain path, whose adjoint replays on the fused
+  // float32 kernels), the plain path's float32 transpose, per-cell fraction
   {
+    const size_t K1 = (size_t)L.mix_count;
     const bool mix_plain = prec_flags_plain;   // the plain path contracts a float32 M2^T on the ALUs
     const bool f32 = prec == RT_FP32 || mix_plain;
     const int kstep = f32 ? 8 : 16;
     L.mix_frag_bytes = ((size_t)ntile * ((hp.Rpad + kstep - 1) / kstep) + 1) * 64 * 16;
     L.mix_tiles_bytes = ntile * sizeof(TileRange);
     const size_t lo = (!f32 && (prec == RT_BF16X3 || prec == RT_BF16)) ? L.mix_frag_bytes : 0;
-    L.mix_tiles = take(L.mix_tiles_bytes);
-    L.mix_frag = take(L.mix_frag_bytes);
-    L.mix_frag_lo = take(lo);
-    L.mix_tiles_adj = take(L.mix_tiles_bytes);
-    L.mix_frag_adj = take(L.mix_frag_bytes);
-    L.mix_frag_adj_lo = take(lo);
-    L.mix_MT = take(mix_plain ? (size_t)hp.R * hp.R * sizeof(float) : 0);
-    L.frac = take(C * sizeof(float));
+    L.mix_tiles = take(K1 * L.mix_tiles_bytes);
+    L.mix_frag = take(K1 * L.mix_frag_bytes);
+    L.mix_frag_lo = take(K1 * lo);
+    L.mix_tiles_adj = take(K1 * L.mix_tiles_bytes);
+    L.mix_frag_adj = take(K1 * L.mix_frag_bytes);
+    L.mix_frag_adj_lo = take(K1 * lo);
+    L.mix_MT = take(mix_plain ? K1 * hp.R * hp.R * sizeof(float) : 0);
+    L.frac = take(K1 * C * sizeof(float));
     // dichroic absorption: per-cell eta and tau_abs * eta, per-direction sin^2 theta
     const bool dich = true;   // every precision (and the plain path)
     L.dich_eta = take(dich ? C * sizeof(float) : 0);
@@ -197,7 +200,8 @@ struct rt_ctx {
   std::vector<float> host_dich_w;  // sin^2 theta per direction (staging)
   int nout[6] = {0, 0, 0, 0, 0, 0};
   bool medium_set = false;
-  bool mixture = false;   // rt_set_phase_mixture succeeded
+  bool mixture = false;   // rt_set_phase_mixture(_k) succeeded
+  int nmix = 0;           // its further matrices
   bool dichroic = false;  // rt_set_dichroism succeeded
   bool three_d = false;   // RT_PLANE_3D lattice
   Stream3Args s3{};       // its streaming arguments
@@ -249,6 +253,8 @@ StepArgs rt_ctx::args(bool adjoint) const {
     a.frag2_lo = at<uint4>(adjoint ? L.mix_frag_adj_lo : L.mix_frag_lo);
     a.tiles2 = at<TileRange>(adjoint ? L.mix_tiles_adj : L.mix_tiles);
     a.frac = at<float>(L.frac);
+    a.nmix = nmix;
+    a.frag2_stride = (int64_t)(L.mix_frag_bytes / sizeof(uint4));
   }
   if (dichroic) {
     a.dich_xi = at<float>(L.dich_xi);
@@ -280,7 +286,7 @@ rt_status plan_for(const rt_problem *p, HostPlan *hp, Packed *pk, Layout *L, std
   rt_status st = build_plan(p, hp, msg);
   if (st != RT_OK) return st;
   pack_all(*hp, p->precision, pk);
-  *L = make_layout(*hp, *pk, p->precision, (p->flags & RT_PLAIN) != 0);
+  *L = make_layout(*hp, *pk, p->precision, (p->flags & RT_PLAIN) != 0, p->mix_max);
   return RT_OK;
 }
 
@@ -659,77 +665,93 @@ rt_status rt_set_inflow(rt_ctx *c, const float *d_inflow) {
   return st;
 }
 
-rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac) {
+rt_status rt_set_phase_mixture_k(rt_ctx *c, int32_t k, const int32_t *phase, const double *g, const double *mix_ray,
+                                 const float *d_frac) {
   if (!c) return set_err(RT_EINVAL, "context is NULL");
-  if (phase2 < 0) {
+  if (k < 0) return c->fail(RT_EINVAL, "number of further phase functions < 0");
+  if (k == 0) {
     c->mixture = false;
+    c->nmix = 0;
     return RT_OK;
   }
-  const bool plain = (c->prob.flags & RT_PLAIN) != 0;
-  if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
-  if (phase2 == RT_PHASE_TABLE) return c->fail(RT_EINVAL, "the second phase function cannot be a table");
-  if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");
-  // the second collision matrix: the same direction set and options, another
-  // scalar phase function (Eq. 17 weights, Rayleigh polarisation part)
-  rt_problem p2 = c->prob;
-  p2.phase = phase2;
-  p2.g = g2;
-  p2.mix_ray = mix_ray2;
-  p2.n_table = 0;
-  p2.table = nullptr;
-  HostPlan hp2;
-  std::string msg;
-  rt_status st = build_plan(&p2, &hp2, &msg);
-  if (st != RT_OK) return c->fail(st, "second phase function: " + msg);
-  std::vector<TileRange> tiles, tiles_adj;
-  std::vector<uint8_t> frag, frag_lo, frag_adj, frag_adj_lo;
-  std::vector<float> MT2;
   const Layout &L = c->L;
-  if (plain) {
-    // float32 M2 transposed, as the plain collision reads M
-    const int R = hp2.R;
-    MT2.resize((size_t)R * R);
-    for (int r = 0; r < R; ++r)
-      for (int k = 0; k < R; ++k) MT2[(size_t)k * R + r] = (float)hp2.M[(size_t)r * R + k];
-  }
-  {
-    // the contraction precision's fragments of M2 and M2^T (float32 for the
-    // plain path); fp16 takes the first matrix's power-of-two scale (both
-    // products share the epilogue's unscale), so M2 must stay in the fp16
-    // range at that scale
-    const int pr = plain ? RT_FP32 : c->prob.precision;
+  if (k > L.mix_count)
+    return c->fail(RT_EINVAL, std::to_string(k) + " further phase functions; the context holds " +
+                                  std::to_string(L.mix_count) + " (rt_problem.mix_max)");
+  if (!phase || !g || !mix_ray) return c->fail(RT_EINVAL, "NULL phase function arrays");
+  if (!d_frac) return c->fail(RT_EINVAL, "NULL fraction pointer");
+  if (c->dichroic) return c->fail(RT_EUNSUPPORTED, "a context takes a phase mixture or dichroic absorption, not both");
+  const bool plain = (c->prob.flags & RT_PLAIN) != 0;
+  // the contraction precision of the further matrices (float32 for the plain
+  // path, whose adjoint replays on the fused float32 kernels); fp16 takes the
+  // first matrix's power-of-two scale (all products share the epilogue's
+  // unscale), so each must stay in the fp16 range at that scale
+  const int pr = plain ? RT_FP32 : c->prob.precision;
+  const bool has_lo = pr == RT_BF16X3 || pr == RT_BF16;
+  const int ntile = c->hp.Rpad / kTileRows;
+  const size_t fb = L.mix_frag_bytes, lob = has_lo ? fb : 0;
+  std::vector<TileRange> tiles((size_t)k * ntile), tiles_adj((size_t)k * ntile);
+  std::vector<uint8_t> frag((size_t)k * fb), frag_adj((size_t)k * fb), frag_lo((size_t)k * lob),
+      frag_adj_lo((size_t)k * lob);
+  std::vector<float> MT;
+  for (int j = 0; j < k; ++j) {
+    const std::string which = "further phase function " + std::to_string(j) + ": ";
+    if (phase[j] == RT_PHASE_TABLE) return c->fail(RT_EINVAL, which + "a mixture component cannot be a table");
+    // the same direction set and options, another scalar phase function
+    // (Eq. 17 weights, Rayleigh polarisation part)
+    rt_problem pj = c->prob;
+    pj.phase = phase[j];
+    pj.g = g[j];
+    pj.mix_ray = mix_ray[j];
+    pj.n_table = 0;
+    pj.table = nullptr;
+    HostPlan hpj;
+    std::string msg;
+    const rt_status st = build_plan(&pj, &hpj, &msg);
+    if (st != RT_OK) return c->fail(st, which + msg);
+    if (plain) {
+      // float32 M_j transposed, as the plain collision reads M
+      const int R = hpj.R;
+      MT.resize((size_t)k * R * R);
+      float *dst = MT.data() + (size_t)j * R * R;
+      for (int r = 0; r < R; ++r)
+        for (int q = 0; q < R; ++q) dst[(size_t)q * R + r] = (float)hpj.M[(size_t)r * R + q];
+    }
     if (pr == RT_FP16) {
       double mx = 0.0;
-      for (double v : hp2.M) mx = std::max(mx, std::fabs(v));
+      for (double v : hpj.M) mx = std::max(mx, std::fabs(v));
       if (mx * c->pk.a_scale >= 65504.0) {
         c->mixture = false;
-        return c->fail(RT_ERANGE, "the second matrix exceeds the fp16 range at the first matrix's scale");
+        return c->fail(RT_ERANGE, which + "exceeds the fp16 range at the first matrix's scale");
       }
     }
     const FragKind kind = pr == RT_FP32 ? FRAG_F32 : (pr == RT_FP16 ? FRAG_F16 : FRAG_BF16);
     const double sc = pr == RT_FP16 ? c->pk.a_scale : 1.0;
-    pack_fragments(hp2, false, kind, sc, false, &tiles, &frag);
-    pack_fragments(hp2, true, kind, sc, false, &tiles_adj, &frag_adj);
-    if (pr == RT_BF16X3 || pr == RT_BF16) {
-      std::vector<TileRange> unused;
-      pack_fragments(hp2, false, FRAG_BF16, 1.0, true, &unused, &frag_lo);
-      pack_fragments(hp2, true, FRAG_BF16, 1.0, true, &unused, &frag_adj_lo);
+    std::vector<TileRange> t, ta, unused;
+    std::vector<uint8_t> f, fa, fl, fal;
+    pack_fragments(hpj, false, kind, sc, false, &t, &f);
+    pack_fragments(hpj, true, kind, sc, false, &ta, &fa);
+    if (has_lo) {
+      pack_fragments(hpj, false, FRAG_BF16, 1.0, true, &unused, &fl);
+      pack_fragments(hpj, true, FRAG_BF16, 1.0, true, &unused, &fal);
     }
-    const size_t cap_lo = (pr == RT_BF16X3 || pr == RT_BF16) ? L.mix_frag_bytes : 0;
-    if (frag.size() > L.mix_frag_bytes || frag_adj.size() > L.mix_frag_bytes ||
-        tiles.size() * sizeof(TileRange) > L.mix_tiles_bytes ||
-        tiles_adj.size() * sizeof(TileRange) > L.mix_tiles_bytes || frag_lo.size() > cap_lo ||
-        frag_adj_lo.size() > cap_lo)
-      return c->fail(RT_EINVAL, "mixture fragments exceed their workspace region");
+    if (f.size() > fb || fa.size() > fb || t.size() > (size_t)ntile || ta.size() > (size_t)ntile ||
+        fl.size() > lob || fal.size() > lob)
+      return c->fail(RT_EINVAL, which + "fragments exceed their workspace region");
+    std::copy(t.begin(), t.end(), tiles.begin() + (size_t)j * ntile);
+    std::copy(ta.begin(), ta.end(), tiles_adj.begin() + (size_t)j * ntile);
+    std::copy(f.begin(), f.end(), frag.begin() + (size_t)j * fb);
+    std::copy(fa.begin(), fa.end(), frag_adj.begin() + (size_t)j * fb);
+    std::copy(fl.begin(), fl.end(), frag_lo.begin() + (size_t)j * lob);
+    std::copy(fal.begin(), fal.end(), frag_adj_lo.begin() + (size_t)j * lob);
   }
   c->mixture = false;
+  c->nmix = 0;
   const size_t C = (size_t)c->geo.C;
-  std::vector<float> hf(C);
-  st = RT_OK;
-  if (plain)
-    st = c->hip(hipMemcpyAsync(c->ws + L.mix_MT, MT2.data(), MT2.size() * sizeof(float), hipMemcpyHostToDevice,
-                               c->stream), "upload mixture matrix");
+  std::vector<float> hf((size_t)k * C);
+  rt_status st = RT_OK;
   const struct { size_t off; const void *p; size_t n; } up[] = {
+      {L.mix_MT, MT.data(), MT.size() * sizeof(float)},
       {L.mix_tiles, tiles.data(), tiles.size() * sizeof(TileRange)},
       {L.mix_tiles_adj, tiles_adj.data(), tiles_adj.size() * sizeof(TileRange)},
       {L.mix_frag, frag.data(), frag.size()},
@@ -739,21 +761,41 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
   for (const auto &u : up)
     if (st == RT_OK && u.n)
       st = c->hip(hipMemcpyAsync(c->ws + u.off, u.p, u.n, hipMemcpyHostToDevice, c->stream),
-                  "upload mixture fragments");
+                  "upload mixture matrices");
   if (st == RT_OK)
-    st = c->hip(hipMemcpyAsync(c->ws + L.frac, d_frac, C * sizeof(float), hipMemcpyDeviceToDevice, c->stream),
-                "copy fraction");
+    st = c->hip(hipMemcpyAsync(c->ws + L.frac, d_frac, hf.size() * sizeof(float), hipMemcpyDeviceToDevice,
+                               c->stream),
+                "copy fractions");
   if (st == RT_OK)
-    st = c->hip(hipMemcpyAsync(hf.data(), c->ws + L.frac, C * sizeof(float), hipMemcpyDeviceToHost, c->stream),
-                "read fraction");
+    st = c->hip(hipMemcpyAsync(hf.data(), c->ws + L.frac, hf.size() * sizeof(float), hipMemcpyDeviceToHost,
+                               c->stream),
+                "read fractions");
   if (st == RT_OK) st = c->hip(hipStreamSynchronize(c->stream), "set_phase_mixture");
   if (st != RT_OK) return st;
+  // every fraction finite and >= 0, their sum per cell <= 1 (in double; the
+  // kernels' float32 sum in the same order then stays <= 1 as well)
   size_t bad = 0;
-  for (float v : hf)
-    if (!(v >= 0.0f && v <= 1.0f)) ++bad;
-  if (bad) return c->fail(RT_ERANGE, std::to_string(bad) + " cells have a mixture fraction outside [0, 1]");
+  for (size_t cell = 0; cell < C; ++cell) {
+    double sum = 0.0;
+    bool ok = true;
+    for (int j = 0; j < k; ++j) {
+      const float v = hf[(size_t)j * C + cell];
+      ok = ok && std::isfinite(v) && v >= 0.0f;
+      sum += v;
+    }
+    if (!ok || !(sum <= 1.0)) ++bad;
+  }
+  if (bad)
+    return c->fail(RT_ERANGE, std::to_string(bad) + " cells have a mixture fraction below 0 or fractions summing past 1");
+  c->nmix = k;
   c->mixture = true;
   return RT_OK;
+}
+
+rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (phase2 < 0) return rt_set_phase_mixture_k(c, 0, nullptr, nullptr, nullptr, nullptr);
+  return rt_set_phase_mixture_k(c, 1, &phase2, &g2, &mix_ray2, d_frac);
 }
 
 rt_status rt_set_tile_strip(rt_ctx *c, int32_t tiles) {

@@ -164,6 +164,7 @@ rt_status build_plan(const rt_problem *p, HostPlan *hp, std::string *msg) {
   if (cells * 4 * n > (1LL << 40)) { *msg = "state larger than 2^40 elements"; return RT_EINVAL; }
   if (cells >= (1LL << 31)) { *msg = "nx * ny (* nz) must be < 2^31"; return RT_EINVAL; }
   if (p->zen_rule < 0 || p->zen_rule > 2) { *msg = "zen_rule out of range"; return RT_EINVAL; }
+  if (p->mix_max < 0 || p->mix_max > RT_MIX_MAX) { *msg = "mix_max must lie in 0 .. RT_MIX_MAX"; return RT_EINVAL; }
   if (p->zen_rule == RT_ZEN_EXPLICIT && !p->zen_deg) { *msg = "zen_deg is NULL for RT_ZEN_EXPLICIT"; return RT_EINVAL; }
   if (!std::isfinite(p->az_offset_deg)) { *msg = "az_offset_deg not finite"; return RT_EINVAL; }
   if (three_d) {

@@ -38,13 +38,18 @@ struct StepArgs {
   const float *lam_next;   // lambda_{t+1}
   double *gacc;            // [3][C]: g_alpha, g_beta, g_emis accumulators
   // phase mixture (frac == nullptr: none): the scattering of cell c follows
-  // M with weight 1 - frac[c] and M2 with weight frac[c]; the adjoint step
-  // takes M2^T here as it takes M^T in frag / tiles
-  const uint4 *frag2;      // A fragments of M2 (M2^T), in the contraction precision
+  // the further matrix M_j (j < nmix) with weight frac[j C + c] and M with
+  // the rest, 1 - sum_j frac[j C + c]; the adjoint step takes M_j^T here as
+  // it takes M^T in frag / tiles.  Component j's fragments start at
+  // frag2 + j frag2_stride (its low parts likewise), its tiles at
+  // tiles2 + j (Rpad / 32), its plain-path matrix at MT2 + j R R.
+  const uint4 *frag2;      // A fragments of the M_j (M_j^T), in the contraction precision
   const uint4 *frag2_lo;   // bf16 and bf16x3: their low parts
-  const TileRange *tiles2; // [Rpad / 32]
-  const float *frac;       // [C]
-  const float *MT2;        // plain path: float32 M2 transposed [R][R] (row k holds M2[r][k] for all r)
+  const TileRange *tiles2; // [nmix][Rpad / 32]
+  const float *frac;       // [nmix][C]
+  const float *MT2;        // plain path: float32 M_j transposed [nmix][R][R] (row k holds M_j[r][k] for all r)
+  int32_t nmix;            // further matrices, >= 1 when frac is set
+  int64_t frag2_stride;    // uint4 records between components' fragments
   // dichroic absorption (forward only; dich_xi == nullptr: none): I + Q and
   // I - Q of direction d in cell c are multiplied by exp(-+dich_xi[c] dich_w[d])
   const float *dich_xi;    // [C] tau_abs * eta per cell

@@ -721,7 +721,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   LaneCell lcs[NB];
   bool inter[NB];
   float al[NB], be[NB], em[NB];
-  float fr[MIX ? NB : 1];   // phase-mixture fraction of the second matrix
+  float fr[MIX ? NB : 1];   // phase mixture: weight of the first matrix, 1 - sum of the fractions
   (void)fr;
   float xi[DICH ? NB : 1];  // dichroic absorption: tau_abs * eta of the cell
   float wdir[DICH ? 4 : 1]; // and sin^2 theta of the lane's four directions
@@ -795,7 +795,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     al[cb] = a.alpha[lc.c];
     be[cb] = a.beta[lc.c];
     em[cb] = a.emis[lc.c];
-    if constexpr (MIX) fr[cb] = a.frac[lc.c];
+    if constexpr (MIX) {
+      float fs = a.frac[lc.c];
+      for (int j = 1; j < a.nmix; ++j) fs += a.frac[(int64_t)j * g.C + lc.c];
+      fr[cb] = 1.0f - fs;
+    }
     if constexpr (DICH) xi[cb] = a.dich_xi[lc.c];
     // A block is interior when every tap of every cell lies inside the lattice
     // (taps reach at most two cells either way); then no wrap or ghost is needed.
@@ -1000,21 +1004,36 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     }
   };
   contract(A, Alo, tr, nk, ring, ring_lo, acc);
-  // phase mixture: the second collision matrix's product from the same B tile
+  // phase mixture: (1 - sum_j f_j) M X + sum_j f_j M_j X, each further
+  // product contracted from the same B tile into acc2 and added at its
+  // fraction (all products carry the same scale, undone in the epilogue);
+  // f = 0 leaves M X exact, a one-hot f gives M_j X exactly
   f32x16 acc2[MIX ? NB : 1];
   if constexpr (MIX) {
-    const TileRange tr2 = a.tiles2[t];
-    const int nk2 = (tr2.khi - tr2.klo) / kStep;
-    const uint4 *A2 = a.frag2 + lane;
-    const uint4 *A2lo = a.frag2_lo + lane;
 #pragma unroll
-    for (int j = 0; j < kRing; ++j) {
-      ring[j] = A2[frag_rec(tr2, j, nk2)];
-      if (ALO) ring_lo[j] = A2lo[frag_rec(tr2, j, nk2)];
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[cb][i] *= fr[cb];
+    for (int m = 0; m < a.nmix; ++m) {
+      const TileRange tr2 = a.tiles2[m * (g.Rpad / 32) + t];   // 32-row tiles
+      const int nk2 = (tr2.khi - tr2.klo) / kStep;
+      const uint4 *A2 = a.frag2 + m * a.frag2_stride + lane;
+      const uint4 *A2lo = a.frag2_lo + m * a.frag2_stride + lane;
+#pragma unroll
+      for (int j = 0; j < kRing; ++j) {
+        ring[j] = A2[frag_rec(tr2, j, nk2)];
+        if (ALO) ring_lo[j] = A2lo[frag_rec(tr2, j, nk2)];
+      }
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc2[cb] = f32x16{0};
+      contract(A2, A2lo, tr2, nk2, ring, ring_lo, acc2);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const float fm = a.frac[(int64_t)m * g.C + lcs[cb].c];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[cb][i] = fmaf(fm, acc2[cb][i], acc[cb][i]);
+      }
     }
-#pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc2[cb] = f32x16{0};
-    contract(A2, A2lo, tr2, nk2, ring, ring_lo, acc2);
   }
   (void)acc2;
 
@@ -1067,10 +1086,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int i = 4 * q + s;
-        float prod = acc[cb][i] * unscale;
-        // mixture: (1 - f) M X + f M2 X, formed as p0 + f (p1 - p0) (exactly
-        // p0 for f = 0)
-        if constexpr (MIX) prod = fmaf(fr[cb], acc2[cb][i] * unscale - prod, prod);
+        const float prod = acc[cb][i] * unscale;
         float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
         if (!ADJ) {
           *o = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
@@ -1159,13 +1175,14 @@ constexpr int kFusedRing = MAXW <= 4 ? ((ADJ && (PREC == P_BF16 || PREC == P_BF1
 
 // Waves per SIMD the register allocation must allow: 4 for the fp32 and bf16
 // adjoint in blocks of up to 4 waves (the accumulator then lives in ordinary
-// VGPRs, without spills), otherwise whatever the kernel needs.
-template <int PREC, bool ADJ, int MAXW, bool G3 = false>
+// VGPRs, without spills), 3 for the 3-D gather and the phase-mixture forward
+// step in such blocks, otherwise whatever the kernel needs.
+template <int PREC, bool ADJ, int MAXW, bool G3 = false, int EXT = kExtNone>
 constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4
-                               : (G3 && MAXW <= 4) ? 3 : 1;
+                               : ((G3 || (!ADJ && EXT == kExtMix)) && MAXW <= 4) ? 3 : 1;
 
 template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, int EXT, bool G3 = false>
-__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW, G3>)))
+__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW, G3, EXT>)))
 fused_kernel(StepArgs a, int64_t ntiles) {
   using T = PrecTraits<PREC>;
   extern __shared__ __align__(16) char smem[];
@@ -1460,7 +1477,7 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count)
   if (a.frac != nullptr) {
     // phase mixture, forward and adjoint: 32-cell tiles (the adjoint's
     // second matrix is M2^T, passed in the same fields)
-    if (a.frag2 == nullptr || a.tiles2 == nullptr) return hipErrorInvalidValue;
+    if (a.frag2 == nullptr || a.tiles2 == nullptr || a.nmix < 1) return hipErrorInvalidValue;
     if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtMix>(a, W, s, cu_count);
     return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtMix>(a, W, s, cu_count);
   }
@@ -1685,12 +1702,10 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
   const float al = a.alpha[cc], be = a.beta[cc], em = a.emis[cc];
   const float edt = a.dt_pre * em;
   const float xi = DICH ? a.dich_xi[cc] : 0.0f;
-  const float fr = MIX ? a.frac[cc] : 0.0f;   // phase mixture: fraction of M2
   float acc[kValuRows], acc2[MIX ? kValuRows : 1];
+  (void)acc2;
 #pragma unroll
   for (int r = 0; r < kValuRows; ++r) acc[r] = 0.0f;
-#pragma unroll
-  for (int r = 0; r < (MIX ? kValuRows : 1); ++r) acc2[r] = 0.0f;
   // ac[r] += M[r0 + r][k] x_k over k; mk = MT + k R + r0 holds M[r0 + r][k] at mk[r]
   auto accumulate_into = [&](const float *__restrict__ T, float *ac, int k, float x) {
     const float *mk = T + (int64_t)k * R + r0;
@@ -1712,11 +1727,26 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
       }
     }
   };
-  auto accumulate = [&](int k, float x) {
-    accumulate_into(MT, acc, k, x);
-    if constexpr (MIX) accumulate_into(a.MT2, acc2, k, x);
-  };
-  if constexpr (DICH) {
+  auto accumulate = [&](int k, float x) { accumulate_into(MT, acc, k, x); };
+  if constexpr (MIX) {
+    // phase mixture: acc = (1 - sum_j f_j) M X, then f_j M_j X added per
+    // further matrix (its product in acc2; X read again for each)
+    float fs = a.frac[cc];
+    for (int j = 1; j < a.nmix; ++j) fs += a.frac[(int64_t)j * g.C + cc];
+    for (int k = 0; k < R; ++k) accumulate(k, fmaf(edt, a.jrow[k], in[(int64_t)k * g.C + cc]));
+    const float w0 = 1.0f - fs;
+#pragma unroll
+    for (int r = 0; r < kValuRows; ++r) acc[r] *= w0;
+    for (int j = 0; j < a.nmix; ++j) {
+      const float *MTj = a.MT2 + (int64_t)j * R * R;
+      const float fj = a.frac[(int64_t)j * g.C + cc];
+#pragma unroll
+      for (int r = 0; r < kValuRows; ++r) acc2[r] = 0.0f;
+      for (int k = 0; k < R; ++k) accumulate_into(MTj, acc2, k, fmaf(edt, a.jrow[k], in[(int64_t)k * g.C + cc]));
+#pragma unroll
+      for (int r = 0; r < kValuRows; ++r) acc[r] = fmaf(fj, acc2[r], acc[r]);
+    }
+  } else if constexpr (DICH) {
     // one direction (4 Stokes rows) at a time: its I and Q are combined
     for (int k = 0; k < R; k += 4) {
       float x[4];
@@ -1742,10 +1772,7 @@ __global__ void __launch_bounds__(256) collide_valu_kernel(StepArgs a, const flo
       if constexpr (DICH) dich_apply(xo[0], xo[1], xi * a.dich_w[(r0 + r) / 4]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float prod = acc[r + j];
-        // mixture: (1 - f) M X + f M2 X as p0 + f (p1 - p0), as in the fused step
-        if constexpr (MIX) prod = fmaf(fr, acc2[MIX ? r + j : 0] - prod, prod);
-        out[(int64_t)(r0 + r + j) * g.C + c] = fmaf(be, prod, fmaf(al, xo[j], a.dt_post * em * jr[j]));
+        out[(int64_t)(r0 + r + j) * g.C + c] = fmaf(be, acc[r + j], fmaf(al, xo[j], a.dt_post * em * jr[j]));
       }
     }
   }
@@ -2182,8 +2209,10 @@ hipError_t launch_collide_valu(const StepArgs &a, const float *MT, const float *
   if (a.dich_xi != nullptr && a.frac != nullptr) return hipErrorInvalidValue;
   if (a.dich_xi != nullptr)
     hipLaunchKernelGGL((collide_valu_kernel<true, false>), grid, dim3(256), 0, s, a, MT, in, out);
-  else if (a.frac != nullptr)
+  else if (a.frac != nullptr) {
+    if (a.MT2 == nullptr || a.nmix < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((collide_valu_kernel<false, true>), grid, dim3(256), 0, s, a, MT, in, out);
+  }
   else
     hipLaunchKernelGGL((collide_valu_kernel<false, false>), grid, dim3(256), 0, s, a, MT, in, out);
   return hipGetLastError();

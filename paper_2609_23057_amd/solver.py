@@ -21,8 +21,10 @@ def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=No
                  az_offset_deg=0.0, plane="xy", courant=1.0, bc=(0, 0, 0, 0), phase=None,
                  dt=1.0, precision="fp32", abs_taylor=False, scat_exp=False, fused_taylor=False,
                  renorm_irow=False, scalar=False, plain=False, nz=1, bc6=None, dir_xyz=None,
-                 dir_domega=None, shift=None, **_ignored):
-    """An RtProblem from keyword arguments (names follow the ABI struct)."""
+                 dir_domega=None, shift=None, mixture=None, mix_max=None, **_ignored):
+    """An RtProblem from keyword arguments (names follow the ABI struct).
+    mix_max defaults to the number of further phase functions a list
+    `mixture` names (one for a single phase function, or none)."""
     phase = phase or {"kind": "rayleigh"}
     p = A.RtProblem()
     p.nx, p.ny, p.n_zen, p.n_az = int(nx), int(ny), int(n_zen), int(n_az)
@@ -72,6 +74,9 @@ def make_problem(nx, ny, n_zen, n_az, zen_rule="equal_area", zen_explicit_deg=No
     flags |= A.RT_PLAIN if plain else 0
     p.flags = flags
     p.precision = A.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if mix_max is None:
+        mix_max = len(mixture) if isinstance(mixture, (list, tuple)) else 0
+    p.mix_max = int(mix_max)
     return p
 
 
@@ -156,11 +161,23 @@ class Solver:
 
     def set_phase_mixture(self, phase, frac):
         """Per-cell mixture: a fraction frac (device [ny, nx] float32) of the
-        scattering follows `phase` ({"kind", "g", "mix_ray"}); None removes it."""
+        scattering follows `phase` ({"kind", "g", "mix_ray"}); with a list of
+        K - 1 phase functions, frac is [K - 1, ny, nx] (each >= 0, their sum
+        <= 1 per cell) and the context's own phase function keeps the rest.
+        None removes the mixture."""
         self._gen += 1
         if phase is None:
             A.rt_set_phase_mixture(self.ctx, -1, 0.0, 1.0, None)
             self._mixture = None
+            return
+        if isinstance(phase, (list, tuple)):
+            ncell = int(np.prod(self.cells))
+            if frac is None or frac.numel() != len(phase) * ncell:
+                raise ValueError("frac needs [%d, cells] values" % len(phase))
+            A.rt_set_phase_mixture_k(self.ctx, [_PHASE[p.get("kind", "rayleigh")] for p in phase],
+                                     [float(p.get("g", 0.0)) for p in phase],
+                                     [float(p.get("mix_ray", 1.0)) for p in phase], _ptr(frac))
+            self._mixture = ([dict(p) for p in phase], frac)
             return
         A.rt_set_phase_mixture(self.ctx, _PHASE[phase.get("kind", "rayleigh")], float(phase.get("g", 0.0)),
                                float(phase.get("mix_ray", 1.0)), _ptr(frac))

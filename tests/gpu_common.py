@@ -96,15 +96,20 @@ def to_np(t):
 
 
 def stokes_errors(got, ref):
-    """Normwise relative error of each Stokes component over the field
-    (against its own norm; against the intensity norm for a component below
-    POL_NEGLIGIBLE of it), the largest absolute error over the largest
-    |reference| value, and the largest absolute DoLP error over cells with
-    I > 1e-3 max I."""
+    """Normwise relative error of each Stokes component over the field, the
+    largest absolute error over the largest |reference| value, and the
+    largest absolute DoLP error over cells with I > 1e-3 max I.  I and V are
+    scored against their own norms, Q and U against the norm of the linear
+    polarisation (Q, U): the frame rotations of Eq. 13 turn the pair into
+    itself, so how its size splits between Q and U depends on the reference
+    frame (a U that is 1 % of Q in one frame is not in another).  A
+    polarised norm below POL_NEGLIGIBLE of the intensity norm is replaced by
+    the intensity norm."""
     out = {}
     nI = np.linalg.norm(ref[:, 0])
+    nQU = np.linalg.norm(ref[:, 1:3])
     for s, name in enumerate("IQUV"):
-        own = np.linalg.norm(ref[:, s])
+        own = nQU if s in (1, 2) else np.linalg.norm(ref[:, s])
         den = own if (s == 0 or own >= POL_NEGLIGIBLE * nI) else nI
         out[name] = float(np.linalg.norm(got[:, s] - ref[:, s]) / max(den, 1e-300))
     out["maxabs"] = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))

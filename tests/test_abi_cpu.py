@@ -114,6 +114,8 @@ def test_validation_status_codes():
     _expect(P.RT_EUNSUPPORTED, n_zen=8, n_az=32)   # fused path limited to n <= 128
     p = P.make_problem(8, 8, 8, 32, plain=True)
     P.rt_validate(p)                               # ... but the plain path takes it
+    _expect(P.RT_EINVAL, mix_max=-1)
+    _expect(P.RT_EINVAL, mix_max=8)                # at most RT_MIX_MAX further phase functions
 
 
 def test_valid_problem_sizes():
@@ -130,6 +132,21 @@ def test_valid_problem_sizes():
     assert 4 * state <= ws < 4 * state + 96 * C + 16 * 2 ** 20
     assert P.rt_adjoint_segment_bytes(p, 15) == 14 * state
     assert P.rt_status_str(P.RT_ERANGE) == "RT_ERANGE"
+
+
+
+def test_workspace_grows_with_the_mixture_capacity():
+    """Each further phase function a context can hold (mix_max, 0 counting as
+    1) adds its fraction plane (4 B per cell) and its packed matrices."""
+    sizes = []
+    for k in (0, 1, 2, 7):
+        s, p = _spec_problem("beam512", mix_max=k)
+        sizes.append(P.rt_workspace_bytes(p))
+    C = s["nx"] * s["ny"]
+    assert sizes[0] == sizes[1]
+    step = sizes[2] - sizes[1]
+    assert 4 * C <= step < 4 * C + 2 ** 20
+    assert abs((sizes[3] - sizes[1]) - 6 * step) <= 6 * 256 * 8
 
 
 def test_init_without_device_reports_error():

@@ -184,6 +184,15 @@ def test_mixture_and_dichroism_on_a_3d_lattice():
     S = to_dev(S0, solver)
     solver.run(S, 10)
     assert_close(to_np(S), O3.run(S0, p3, 10), 1e-5, "mixture 3d")
+    # three phase functions, fractions [2, nz, ny, nx], fp32 and the plain path
+    spec = spec3(8, 7, 5, mixture=[{"kind": "rayleigh"}, {"kind": "hg", "g": -0.4}])
+    for precision in ("fp32", "plain"):
+        solver, p3, med = build3(spec, precision)
+        assert med["frac"].shape == (2, 5, 7, 8)
+        solver.set_phase_mixture(spec["mixture"], to_dev(med["frac"], solver))
+        S = to_dev(S0, solver)
+        solver.run(S, 10)
+        assert_close(to_np(S), O3.run(S0, p3, 10), 1e-5, ("three-phase mixture 3d", precision))
     spec = spec3(8, 7, 5, dichroism=0.8)
     med = W.medium(spec)
     med["tau"] = np.minimum(med["tau"] * 40.0, 1.0).astype(np.float32).astype(np.float64)
@@ -290,21 +299,25 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+MIXTURES = {"mixture": {"kind": "hg", "g": -0.4},
+            "mixture3": [{"kind": "hg", "g": -0.4}, {"kind": "rayleigh"}]}
+
+
 @pytest.mark.parametrize("precision", ["fp32", "plain", "bf16x3", "bf16"])
 @pytest.mark.parametrize("case", [(dict(nx=9, ny=7, nz=5), 11, 4), (dict(nx=16, ny=9, nz=7), 9, 3),
                                   (dict(nx=6, ny=5, nz=4, n_zen=2, n_az=8, bc6=(0, 0, 1, 1, 0, 0)), 8, 8),
                                   (dict(nx=5, ny=4, nz=3, n_zen=8, n_az=16), 6, 1)],
                          ids=lambda c: "%dx%dx%d-T%d-K%d" % (c[0]["nx"], c[0]["ny"], c[0]["nz"], c[1], c[2]))
-@pytest.mark.parametrize("ext", [None, "mixture", "dichroism"], ids=["single", "mixture", "dichroism"])
+@pytest.mark.parametrize("ext", [None, "mixture", "mixture3", "dichroism"],
+                         ids=["single", "mixture", "mixture3", "dichroism"])
 def test_adjoint3d_parity(case, precision, ext):
     over, T, K = case
-    spec = W.spec("beam3d", source="uniform_emis", emis_max=0.05,
-                  mixture={"kind": "hg", "g": -0.4} if ext == "mixture" else None,
+    spec = W.spec("beam3d", source="uniform_emis", emis_max=0.05, mixture=MIXTURES.get(ext),
                   dichroism=0.8 if ext == "dichroism" else None, **over)
     med = W.medium(spec)
     med["tau"] = np.minimum(med["tau"] * 20.0, 1.0).astype(np.float32).astype(np.float64)
     solver, p3, _ = build3(spec, precision, med)
-    if ext == "mixture":
+    if ext in MIXTURES:
         solver.set_phase_mixture(spec["mixture"], to_dev(med["frac"], solver))
     elif ext == "dichroism":
         solver.set_dichroism(to_dev(med["eta"], solver))

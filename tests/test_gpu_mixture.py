@@ -131,8 +131,8 @@ def test_zero_fraction_equals_single_phase(precision, n_zen, n_az):
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3"])
 def test_unit_fraction_equals_second_phase(precision):
     """f = 1 everywhere: the mixed run equals a context built with the second
-    phase function alone, to the path's tolerance (the blend is
-    p0 + (p1 - p0), one rounding away from p1)."""
+    phase function alone (the blend 0 p0 + 1 p1 returns p1 itself; the
+    three-phase tests also check it value for value)."""
     spec = W.spec("beam512", nx=37, ny=30, mixture={"kind": "hg", "g": 0.3})
     med = W.medium(spec)
     solver, oprob, _ = build(spec, precision, med)

@@ -722,6 +722,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   bool inter[NB];
   float al[NB], be[NB], em[NB];
   float fr[MIX ? NB : 1];   // phase mixture: weight of the first matrix, 1 - sum of the fractions
+  float f0[MIX ? NB : 1];   // and the first further matrix's fraction
   (void)fr;
   float xi[DICH ? NB : 1];  // dichroic absorption: tau_abs * eta of the cell
   float wdir[DICH ? 4 : 1]; // and sin^2 theta of the lane's four directions
@@ -796,7 +797,8 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     be[cb] = a.beta[lc.c];
     em[cb] = a.emis[lc.c];
     if constexpr (MIX) {
-      float fs = a.frac[lc.c];
+      f0[cb] = a.frac[lc.c];
+      float fs = f0[cb];
       for (int j = 1; j < a.nmix; ++j) fs += a.frac[(int64_t)j * g.C + lc.c];
       fr[cb] = 1.0f - fs;
     }
@@ -1014,7 +1016,14 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[cb][i] *= fr[cb];
+    // the fraction of component m is at hand (f0, then loaded one contraction ahead)
+    float fm[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) fm[cb] = f0[cb];
     for (int m = 0; m < a.nmix; ++m) {
+      float fn[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) fn[cb] = m + 1 < a.nmix ? a.frac[(int64_t)(m + 1) * g.C + lcs[cb].c] : 0.0f;
       const TileRange tr2 = a.tiles2[m * (g.Rpad / 32) + t];   // 32-row tiles
       const int nk2 = (tr2.khi - tr2.klo) / kStep;
       const uint4 *A2 = a.frag2 + m * a.frag2_stride + lane;
@@ -1029,9 +1038,9 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       contract(A2, A2lo, tr2, nk2, ring, ring_lo, acc2);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const float fm = a.frac[(int64_t)m * g.C + lcs[cb].c];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[cb][i] = fmaf(fm, acc2[cb][i], acc[cb][i]);
+        for (int i = 0; i < 16; ++i) acc[cb][i] = fmaf(fm[cb], acc2[cb][i], acc[cb][i]);
+        fm[cb] = fn[cb];
       }
     }
   }

@@ -264,7 +264,7 @@ rt_status rt_set_inflow(rt_ctx *c, const float *d_inflow);
  * fp16 range (more than 8 max |M|) (the mixture is then off); RT_EUNSUPPORTED while
  * dichroic absorption is set.  rt_adjoint carries the mixture (its step
  * contracts M^T and M2^T, packed here too, and blends them per cell);
- * rt_batch_run and rt_batch_adjoint return RT_EUNSUPPORTED while one is set. */
+ * rt_batch_run and rt_batch_adjoint carry the mixture of a batch channel. */
 rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_ray2, const float *d_frac);
 
 /* Per-cell mixture of K = 1 + k phase functions (the aerosol and cloud
@@ -277,9 +277,10 @@ rt_status rt_set_phase_mixture(rt_ctx *c, int32_t phase2, double g2, double mix_
  * copied into the workspace) with f_j >= 0 and sum_j f_j <= 1 in every cell;
  * M keeps the rest.  k = 0 removes the mixture (the other arguments are then
  * ignored); rt_set_phase_mixture(c, phase2, g2, mix_ray2, d_frac) is k = 1.
- * Every precision, rt_step / rt_run / rt_adjoint, the plain path and 3-D
- * lattices (on the two-launch step) carry it as they carry two components;
- * each further matrix costs one more contraction per step.  Synchronises
+ * Every precision, rt_step / rt_run / rt_adjoint, the plain path, 3-D
+ * lattices (on the two-launch step) and batch channels carry it as they
+ * carry two components; each further matrix costs one more contraction per
+ * step.  Synchronises
  * the stream (the fractions are checked on the host).  Errors: RT_EINVAL for
  * k < 0, k above the context's rt_problem.mix_max (0 counting as 1), NULL
  * arrays, or an invalid phase function; RT_ERANGE if a fraction is negative
@@ -481,7 +482,11 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
                         rt_batch **out);
 
 /* Context of channel ch, owned by the batch (do not destroy it): for
- * rt_set_medium, rt_readout, rt_maps, rt_readout_adjoint of that channel. */
+ * rt_set_medium, rt_set_inflow, rt_set_phase_mixture(_k), rt_readout,
+ * rt_maps, rt_readout_adjoint of that channel.  A channel with a phase
+ * mixture (its problem's mix_max bounds the components) runs in the batch as
+ * alone, bit for bit; a channel with dichroic absorption makes rt_batch_run
+ * and rt_batch_adjoint return RT_EUNSUPPORTED. */
 rt_status rt_batch_channel(rt_batch *b, int32_t ch, rt_ctx **out);
 
 /* rt_run for every channel: h_states[i] is channel i's state (updated in

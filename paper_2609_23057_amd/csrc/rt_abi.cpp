@@ -1643,6 +1643,7 @@ struct rt_batch {
   struct Run {
     int first = 0, count = 0, cls = 0;
     int64_t nitems = 0;
+    bool mix = false;   // a channel of the run has a phase mixture
   };
   struct Group {
     std::vector<Run> runs;
@@ -1685,6 +1686,17 @@ struct rt_batch {
     if (cap) (void)hipStreamDestroy(cap);
     for (rt_ctx *c : ch) delete c;
   }
+  // The step arguments of every channel as its context now stands (a phase
+  // mixture set or removed since the batch was made changes them; the
+  // medium lives in the context's workspace and needs no refresh).
+  void refresh_args() {
+    for (int i = 0; i < nchan; ++i) {
+      h_run[i].a = ch[i]->args(false);
+      h_rec[i].a = h_run[i].a;
+      h_adj[i].a = ch[i]->args(true);
+      h_run[i].a.strip = h_rec[i].a.strip = h_adj[i].a.strip = 0;   // tiles in row order
+    }
+  }
   rt_status upload(BatchChan *d, const std::vector<BatchChan> &h, const Plan &pl) {
     std::vector<BatchChan> &t = d == d_run ? t_run : (d == d_rec ? t_rec : t_adj);
     t.resize(h.size());
@@ -1713,8 +1725,8 @@ struct rt_batch {
     }
     for (const Run &r : gr.runs) {
       const Class &k = classes[r.cls];
-      rt_status st = hip(launch_batch_step(d + r.first, r.count, r.nitems, prec, k.bw, adjoint, gather, ckpt, sel,
-                                           k.lds, cu_count, stream),
+      rt_status st = hip(launch_batch_step(d + r.first, r.count, r.nitems, prec, k.bw, adjoint, gather, ckpt,
+                                           r.mix, sel, k.lds, cu_count, stream),
                          "batch step");
       if (st != RT_OK) return st;
     }
@@ -1765,6 +1777,7 @@ struct rt_batch {
         for (int i : m) {
           if (ch[i]->geo.Rpad / 32 != W) continue;
           pl.order.push_back(i);
+          r.mix = r.mix || ch[i]->mixture;
           for (std::vector<BatchChan> *tb : tables) {
             (*tb)[i].groups = per;
             (*tb)[i].item0 = item;
@@ -1987,10 +2000,10 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
   for (int i = 0; i < b->nchan; ++i) {
     if (!h_states[i] || (h_ckpt && !h_ckpt[i])) return b->fail(RT_EINVAL, "NULL state or checkpoint pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
-    if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
     if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
   if (nsteps == 0) return RT_OK;
+  b->refresh_args();
   // a step reads one post-collision state and writes the other
   b->make_plan(b->plan_run, 2.0, {&b->h_run});
   auto body = [&]() -> rt_status {
@@ -2028,6 +2041,7 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
   for (int i = 0; i < b->nchan; ++i) {
     key.push_back(reinterpret_cast<uintptr_t>(h_states[i]));
     key.push_back(reinterpret_cast<uintptr_t>(h_ckpt ? h_ckpt[i] : nullptr));
+    key.push_back((uintptr_t)(b->ch[i]->mixture ? b->ch[i]->nmix : 0));   // the kernels and tables it needs
   }
   if (!(b->g_run.exec && b->g_run.key == key)) {
     rt_status st = b->upload(b->d_run, b->h_run, b->plan_run);
@@ -2049,9 +2063,9 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
         (ckpt_every > 1 && !h_seg[i]))
       return b->fail(RT_EINVAL, "NULL per-channel pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
-    if (b->ch[i]->mixture) return b->fail(RT_EUNSUPPORTED, "batched channels take a single phase function");
     if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
+  b->refresh_args();
   // a reverse step reads lambda_{t+1}, the segment state and writes lambda_t;
   // the segment recompute writes ckpt_every - 1 states
   b->make_plan(b->plan_adj, 3.0 + ckpt_every, {&b->h_rec, &b->h_adj});
@@ -2107,11 +2121,13 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
     return st == RT_OK ? body() : st;
   }
   std::vector<uintptr_t> key = {2, (uintptr_t)nsteps, (uintptr_t)ckpt_every};
-  for (int i = 0; i < b->nchan; ++i)
+  for (int i = 0; i < b->nchan; ++i) {
     for (const void *ptr : {(const void *)h_ckpt[i], (const void *)(h_seg ? h_seg[i] : nullptr),
                             (const void *)h_lambdaT[i], (const void *)h_g_tau[i], (const void *)h_g_albedo[i],
                             (const void *)h_g_emis[i]})
       key.push_back(reinterpret_cast<uintptr_t>(ptr));
+    key.push_back((uintptr_t)(b->ch[i]->mixture ? b->ch[i]->nmix : 0));
+  }
   if (!(b->g_adj.exec && b->g_adj.key == key)) {
     rt_status st = upload_both();
     if (st != RT_OK) return st;

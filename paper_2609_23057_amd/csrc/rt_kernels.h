@@ -115,9 +115,10 @@ hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu);
 
 // One batched fused step (forward or adjoint) over the tiles of one class of
 // channels in bw-wave blocks; the persistent grid is cu_count x the resident
-// blocks of that instantiation.
+// blocks of that instantiation.  mix: some channel of the run has a phase
+// mixture (the others pass through the mixture tile with nmix = 0).
 hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw, bool adjoint,
-                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
+                             bool gather, bool ckpt, bool mix, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s);
 
 // Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +

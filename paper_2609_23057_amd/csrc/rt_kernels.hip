@@ -797,7 +797,8 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
     be[cb] = a.beta[lc.c];
     em[cb] = a.emis[lc.c];
     if constexpr (MIX) {
-      f0[cb] = a.frac[lc.c];
+      // (a batched channel without a mixture has nmix = 0 and no fractions)
+      f0[cb] = a.nmix > 0 ? a.frac[lc.c] : 0.0f;
       float fs = f0[cb];
       for (int j = 1; j < a.nmix; ++j) fs += a.frac[(int64_t)j * g.C + lc.c];
       fr[cb] = 1.0f - fs;
@@ -1254,7 +1255,7 @@ fused_kernel(StepArgs a, int64_t ntiles) {
 // descriptor (scalar loads), its emission rows into LDS and each lane's
 // direction data.
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX = false>
 __global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restrict__ chans, int nchan,
                                                         int64_t nitems, BatchSel sel) {
   using T = PrecTraits<PREC>;
@@ -1318,8 +1319,10 @@ __global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restr
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ld[q].off), "+v"(ld[q].td), "+v"(ld[q].d));
     const int64_t tile = (it - item0) * (BW / W) + grp;
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, 4, 1>>(a, g, L, ts, tr, ld, tile, tile < ntiles, t, t,
-                                                                    W, lane);
+    // MIX: the phase-mixture tile, for classes with a mixed channel (a
+    // channel without one passes through it with nmix = 0, exactly)
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, 4, 1>, 1, MIX ? kExtMix : kExtNone>(
+        a, g, L, ts, tr, ld, tile, tile < ntiles, t, t, W, lane);
   }
 }
 
@@ -1333,32 +1336,43 @@ size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint, int bw) {
 
 // Occupancy of one batch instantiation; prepare_batch fills the memo before
 // any launch, so a launch under stream capture makes no runtime query.
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX>
 hipError_t batch_blocks_per_cu(int lds_bytes, int *occ) {
   static std::atomic<uint64_t> memo{0};
-  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT, BW>, 64 * BW, lds_bytes, memo, occ);
+  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT, BW, MIX>, 64 * BW, lds_bytes, memo,
+                         occ);
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX>
 hipError_t prepare_batch_k(int lds_bytes, int *occ) {
-  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW>;
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW, MIX>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return e;
   int o = 0;
-  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW>(lds_bytes, &o);
+  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW, MIX>(lds_bytes, &o);
   if (e != hipSuccess) return e;
   *occ = std::min(*occ, o);
   return hipSuccess;
 }
 
+template <int PREC, int BW, bool MIX>
+hipError_t prepare_batch_m(int lds_bytes, int *occ) {
+  hipError_t e;
+  if ((e = prepare_batch_k<PREC, false, false, false, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, false, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, true, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, false, true, false, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
+  return prepare_batch_k<PREC, true, true, false, BW, MIX>(lds_bytes, occ);
+}
+
+// blocks per CU: those of the single-phase instantiations (the mixture ones
+// are prepared too, and size their own grids at launch)
 template <int PREC, int BW>
 hipError_t prepare_batch_p(int lds_bytes, int *occ) {
-  hipError_t e;
-  if ((e = prepare_batch_k<PREC, false, false, false, BW>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, true, false, false, BW>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, true, false, true, BW>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, false, true, false, BW>(lds_bytes, occ)) != hipSuccess) return e;
-  return prepare_batch_k<PREC, true, true, false, BW>(lds_bytes, occ);
+  const hipError_t e = prepare_batch_m<PREC, BW, false>(lds_bytes, occ);
+  if (e != hipSuccess) return e;
+  int mix_occ = 1 << 20;
+  return prepare_batch_m<PREC, BW, true>(lds_bytes, &mix_occ);
 }
 
 template <int PREC>
@@ -1385,13 +1399,13 @@ hipError_t prepare_batch_impl(int prec, int bw, int lds_bytes, int *blocks_per_c
   return hipSuccess;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX>
 hipError_t launch_batch_k(const BatchChan *d_chans, int nchan, int64_t nitems, const BatchSel &sel, int lds_bytes,
                           int cu_count, hipStream_t s) {
-  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW>;
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW, MIX>;
   // persistent grid sized by this instantiation's own occupancy
   int occ = 0;
-  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW>(lds_bytes, &occ);
+  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW, MIX>(lds_bytes, &occ);
   if (e != hipSuccess) return e;
   int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)cu_count * occ));
   if (grid >= 8) grid &= ~7LL;
@@ -1399,40 +1413,54 @@ hipError_t launch_batch_k(const BatchChan *d_chans, int nchan, int64_t nitems, c
   return hipGetLastError();
 }
 
-template <int PREC, int BW>
-hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
+template <int PREC, int BW, bool MIX>
+hipError_t launch_batch_m(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
                           const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
   if (adjoint) {
-    if (gather) return launch_batch_k<PREC, true, true, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-    return launch_batch_k<PREC, false, true, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    if (gather)
+      return launch_batch_k<PREC, true, true, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    return launch_batch_k<PREC, false, true, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
   }
-  if (ckpt) return launch_batch_k<PREC, true, false, true, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-  if (gather) return launch_batch_k<PREC, true, false, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-  return launch_batch_k<PREC, false, false, false, BW>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  if (ckpt) return launch_batch_k<PREC, true, false, true, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  if (gather)
+    return launch_batch_k<PREC, true, false, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  return launch_batch_k<PREC, false, false, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+}
+
+template <int PREC, int BW>
+hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
+                          bool mix, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
+  if (mix) return launch_batch_m<PREC, BW, true>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+  return launch_batch_m<PREC, BW, false>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
 }
 
 template <int PREC>
 hipError_t launch_batch_w(int bw, const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather,
-                          bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
+                          bool ckpt, bool mix, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
   switch (bw) {
-    case 1: return launch_batch_p<PREC, 1>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case 2: return launch_batch_p<PREC, 2>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case 4: return launch_batch_p<PREC, 4>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case 8: return launch_batch_p<PREC, 8>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case 1: return launch_batch_p<PREC, 1>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case 2: return launch_batch_p<PREC, 2>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case 4: return launch_batch_p<PREC, 4>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case 8: return launch_batch_p<PREC, 8>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw,
-                                  bool adjoint, bool gather, bool ckpt, const BatchSel &sel, int lds_bytes,
-                                  int cu_count, hipStream_t s) {
+                                  bool adjoint, bool gather, bool ckpt, bool mix, const BatchSel &sel,
+                                  int lds_bytes, int cu_count, hipStream_t s) {
   if (ckpt && (adjoint || !gather)) return hipErrorInvalidValue;
   if (cu_count < 1 || nitems < 1) return hipErrorInvalidValue;
   switch (prec) {
-    case P_F32: return launch_batch_w<P_F32>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case P_BF16: return launch_batch_w<P_BF16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case P_F16: return launch_batch_w<P_F16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-    case P_BF16X3: return launch_batch_w<P_BF16X3>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+    case P_F32:
+      return launch_batch_w<P_F32>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case P_BF16:
+      return launch_batch_w<P_BF16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case P_F16:
+      return launch_batch_w<P_F16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case P_BF16X3:
+      return launch_batch_w<P_BF16X3>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes,
+                                      cu_count, s);
   }
   return hipErrorInvalidValue;
 }
@@ -2161,9 +2189,10 @@ hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu) {
 }
 
 hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw, bool adjoint,
-                             bool gather, bool ckpt, const BatchSel &sel, int lds_bytes, int cu_count,
+                             bool gather, bool ckpt, bool mix, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s) {
-  return launch_batch_step_impl(d_chans, nchan, nitems, prec, bw, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+  return launch_batch_step_impl(d_chans, nchan, nitems, prec, bw, adjoint, gather, ckpt, mix, sel, lds_bytes,
+                                cu_count, s);
 }
 
 size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich, bool three_d) {

@@ -197,29 +197,6 @@ def test_mixture_refusals():
 
 
 
-def test_batch_refuses_mixed_channel():
-    import paper_2609_23057_amd as P
-    spec = W.spec("beam512", nx=24, ny=20, n_zen=2, n_az=8, precision="bf16")
-    prob = P.make_problem(**spec)
-    batch = P.Batch([prob, prob])
-    med = W.medium(spec)
-    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=batch.device)  # noqa: E731
-    keep = []
-    for ch in batch.channels:
-        tensors = (t(med["tau"]), t(med["albedo"]), t(med["emis"]))
-        keep.append(tensors)
-        ch.set_medium(*tensors, med["jprof"], med["inflow"])
-    states = batch.empty_states()
-    batch.run(states, 2)
-    batch.channels[1].set_phase_mixture({"kind": "rayleigh"}, torch.full((20, 24), 0.5, device=batch.device))
-    with pytest.raises(P.RTError) as ei:
-        batch.run(states, 2)
-    assert ei.value.status == P.RT_EUNSUPPORTED
-    batch.channels[1].set_phase_mixture(None, None)
-    batch.run(states, 2)
-    torch.cuda.synchronize()
-
-
 def test_fp16_mixture_range_refusal():
     """fp16 packs the second matrix at the first one's power-of-two scale
     (max |M| scaled into [2^12, 2^13)); a second matrix more than 8 times

@@ -307,8 +307,8 @@ rt_status rt_set_phase_mixture_k(rt_ctx *c, int32_t k, const int32_t *phase, con
  * (dichroism is then off).  rt_adjoint carries it (eta held fixed: its step
  * applies the symmetric factor to alpha mu + beta nu and adds the derivative
  * through xi = tau_abs eta to the tau and albedo gradients); rt_batch_run and
- * rt_batch_adjoint return RT_EUNSUPPORTED while it is set;
- * rt_set_phase_mixture likewise. */
+ * rt_batch_adjoint carry it for a batch channel; rt_set_phase_mixture returns
+ * RT_EUNSUPPORTED while it is set. */
 rt_status rt_set_dichroism(rt_ctx *c, const float *d_eta);
 
 /* Tuning of the 3-D lattice's fused step (RT_PLANE_3D; ignored otherwise).
@@ -483,10 +483,13 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
 
 /* Context of channel ch, owned by the batch (do not destroy it): for
  * rt_set_medium, rt_set_inflow, rt_set_phase_mixture(_k), rt_readout,
- * rt_maps, rt_readout_adjoint of that channel.  A channel with a phase
- * mixture (its problem's mix_max bounds the components) runs in the batch as
- * alone, bit for bit; a channel with dichroic absorption makes rt_batch_run
- * and rt_batch_adjoint return RT_EUNSUPPORTED. */
+ * rt_set_dichroism, rt_maps, rt_readout_adjoint of that channel.  A channel
+ * with a phase mixture (its problem's mix_max bounds the components) or with
+ * dichroic absorption runs in the batch as alone, bit for bit (the dichroic
+ * channels of a class in a launch of their own); rt_batch_run and
+ * rt_batch_adjoint return RT_EUNSUPPORTED for a dichroic channel whose class,
+ * at its block size, cannot hold the dichroic adjoint's fourth per-cell sum
+ * in the LDS. */
 rt_status rt_batch_channel(rt_batch *b, int32_t ch, rt_ctx **out);
 
 /* rt_run for every channel: h_states[i] is channel i's state (updated in

@@ -1633,6 +1633,7 @@ struct rt_batch {
   // its launches use blocks of bw waves (bw / W tiles side by side).
   struct Class {
     int W = 0, bw = 0, lds = 0, count = 0;
+    int lds_dich = 0;   // LDS of a run with dichroic absorption (its adjoint keeps a fourth per-cell sum)
   };
   std::vector<Class> classes;   // increasing W
   // Temporal blocking: the channels are split into groups whose working set
@@ -1643,7 +1644,7 @@ struct rt_batch {
   struct Run {
     int first = 0, count = 0, cls = 0;
     int64_t nitems = 0;
-    bool mix = false;   // a channel of the run has a phase mixture
+    int ext = kExtNone;   // kExtMix / kExtDich: a channel of the run has a phase mixture / dichroic absorption
   };
   struct Group {
     std::vector<Run> runs;
@@ -1686,6 +1687,17 @@ struct rt_batch {
     if (cap) (void)hipStreamDestroy(cap);
     for (rt_ctx *c : ch) delete c;
   }
+  // A channel with dichroic absorption needs its class's dichroic LDS.
+  rt_status check_dichroic() {
+    for (int i = 0; i < nchan; ++i) {
+      if (!ch[i]->dichroic) continue;
+      for (const Class &k : classes)
+        if (k.W == ch[i]->geo.Rpad / 32 && k.lds_dich == 0)
+          return fail(RT_EUNSUPPORTED, "channel " + std::to_string(i) +
+                                           ": the dichroic adjoint's per-cell sums do not fit the LDS at this block size");
+    }
+    return RT_OK;
+  }
   // The step arguments of every channel as its context now stands (a phase
   // mixture set or removed since the batch was made changes them; the
   // medium lives in the context's workspace and needs no refresh).
@@ -1726,7 +1738,7 @@ struct rt_batch {
     for (const Run &r : gr.runs) {
       const Class &k = classes[r.cls];
       rt_status st = hip(launch_batch_step(d + r.first, r.count, r.nitems, prec, k.bw, adjoint, gather, ckpt,
-                                           r.mix, sel, k.lds, cu_count, stream),
+                                           r.ext, sel, r.ext == kExtDich ? k.lds_dich : k.lds, cu_count, stream),
                          "batch step");
       if (st != RT_OK) return st;
     }
@@ -1737,12 +1749,15 @@ struct rt_batch {
     for (Class &k : classes) {
       const int Rpad = 32 * k.W;
       const size_t lf = batch_lds_bytes(Rpad, prec, false, k.bw), la = batch_lds_bytes(Rpad, prec, true, k.bw);
-      if (lf == (size_t)-1 || la == (size_t)-1) return fail(RT_EINVAL, "block waves do not fit the channel class");
-      const size_t lds = std::max(lf, la);
+      const size_t ld = batch_lds_bytes(Rpad, prec, true, k.bw, true);
+      if (lf == (size_t)-1 || la == (size_t)-1 || ld == (size_t)-1)
+        return fail(RT_EINVAL, "block waves do not fit the channel class");
+      const size_t lds = std::max(lf, la), lds_dich = std::max(lf, ld);
       if (lds > 160 * 1024) return fail(RT_EUNSUPPORTED, "batch does not fit the fused kernel's LDS budget");
       k.lds = (int)lds;
+      k.lds_dich = lds_dich <= 160 * 1024 ? (int)lds_dich : 0;   // 0: no dichroic channel in this class
       int per_cu = 0;
-      rt_status st = hip(prepare_batch(prec, k.bw, k.lds, &per_cu), "prepare batch kernels");
+      rt_status st = hip(prepare_batch(prec, k.bw, std::max(k.lds, k.lds_dich), &per_cu), "prepare batch kernels");
       if (st != RT_OK) return st;
     }
     return RT_OK;
@@ -1769,24 +1784,30 @@ struct rt_batch {
       Group gr;
       gr.chans = m;
       for (int c = 0; c < (int)classes.size(); ++c) {
-        Run r;
-        r.cls = c;
-        r.first = (int)pl.order.size();
-        const int W = classes[c].W, per = classes[c].bw / W;
-        int64_t item = 0;
-        for (int i : m) {
-          if (ch[i]->geo.Rpad / 32 != W) continue;
-          pl.order.push_back(i);
-          r.mix = r.mix || ch[i]->mixture;
-          for (std::vector<BatchChan> *tb : tables) {
-            (*tb)[i].groups = per;
-            (*tb)[i].item0 = item;
+        // the channels with dichroic absorption run apart from the others
+        // (a launch carries one extension: the mixture tile takes channels
+        // without a mixture exactly, the dichroic tile those without factors)
+        for (const bool dich : {false, true}) {
+          Run r;
+          r.cls = c;
+          r.first = (int)pl.order.size();
+          r.ext = dich ? kExtDich : kExtNone;
+          const int W = classes[c].W, per = classes[c].bw / W;
+          int64_t item = 0;
+          for (int i : m) {
+            if (ch[i]->geo.Rpad / 32 != W || ch[i]->dichroic != dich) continue;
+            pl.order.push_back(i);
+            if (ch[i]->mixture) r.ext = kExtMix;
+            for (std::vector<BatchChan> *tb : tables) {
+              (*tb)[i].groups = per;
+              (*tb)[i].item0 = item;
+            }
+            item += (h_run[i].ntiles + per - 1) / per;
           }
-          item += (h_run[i].ntiles + per - 1) / per;
+          r.count = (int)pl.order.size() - r.first;
+          r.nitems = item;
+          if (r.count > 0) gr.runs.push_back(r);
         }
-        r.count = (int)pl.order.size() - r.first;
-        r.nitems = item;
-        if (r.count > 0) gr.runs.push_back(r);
       }
       pl.groups.push_back(gr);
     }
@@ -2000,9 +2021,9 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
   for (int i = 0; i < b->nchan; ++i) {
     if (!h_states[i] || (h_ckpt && !h_ckpt[i])) return b->fail(RT_EINVAL, "NULL state or checkpoint pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
-    if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
   if (nsteps == 0) return RT_OK;
+  if (b->check_dichroic() != RT_OK) return RT_EUNSUPPORTED;
   b->refresh_args();
   // a step reads one post-collision state and writes the other
   b->make_plan(b->plan_run, 2.0, {&b->h_run});
@@ -2041,7 +2062,8 @@ rt_status rt_batch_run(rt_batch *b, float *const *h_states, int32_t nsteps, floa
   for (int i = 0; i < b->nchan; ++i) {
     key.push_back(reinterpret_cast<uintptr_t>(h_states[i]));
     key.push_back(reinterpret_cast<uintptr_t>(h_ckpt ? h_ckpt[i] : nullptr));
-    key.push_back((uintptr_t)(b->ch[i]->mixture ? b->ch[i]->nmix : 0));   // the kernels and tables it needs
+    // the kernels and tables the channel needs
+    key.push_back((uintptr_t)(b->ch[i]->mixture ? b->ch[i]->nmix : 0) | (b->ch[i]->dichroic ? 1u << 16 : 0u));
   }
   if (!(b->g_run.exec && b->g_run.key == key)) {
     rt_status st = b->upload(b->d_run, b->h_run, b->plan_run);
@@ -2063,8 +2085,8 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
         (ckpt_every > 1 && !h_seg[i]))
       return b->fail(RT_EINVAL, "NULL per-channel pointer");
     if (!b->ch[i]->medium_set) return b->fail(RT_ESTATE, "rt_set_medium has not succeeded on every channel");
-    if (b->ch[i]->dichroic) return b->fail(RT_EUNSUPPORTED, "batched channels take no dichroic absorption");
   }
+  if (b->check_dichroic() != RT_OK) return RT_EUNSUPPORTED;
   b->refresh_args();
   // a reverse step reads lambda_{t+1}, the segment state and writes lambda_t;
   // the segment recompute writes ckpt_every - 1 states
@@ -2074,7 +2096,7 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
     for (const rt_batch::Group &gr : b->plan_adj.groups) {
       for (int i : gr.chans) {
         rt_ctx *c = b->ch[i];
-        if (st == RT_OK) st = b->hip(launch_fill_f64(c->at<double>(c->L.gacc), 3 * c->geo.C, 0.0, b->stream), "fill");
+        if (st == RT_OK) st = b->hip(launch_fill_f64(c->at<double>(c->L.gacc), 4 * c->geo.C, 0.0, b->stream), "fill");
       }
       int lam = kBufLamT;
       int flip = 0;
@@ -2100,7 +2122,8 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
         rt_ctx *c = b->ch[i];
         if (st == RT_OK)
           st = b->hip(launch_gradchain(c->geo.C, c->at<float>(c->L.tau), c->at<float>(c->L.alb), c->prob.flags,
-                                       c->at<double>(c->L.gacc), h_g_tau[i], h_g_albedo[i], h_g_emis[i], b->stream),
+                                       c->at<double>(c->L.gacc), h_g_tau[i], h_g_albedo[i], h_g_emis[i], b->stream,
+                                       c->dichroic ? c->at<float>(c->L.dich_eta) : nullptr),
                       "gradchain");
       }
     }
@@ -2126,7 +2149,7 @@ rt_status rt_batch_adjoint(rt_batch *b, int32_t nsteps, float *const *h_ckpt, in
                             (const void *)h_lambdaT[i], (const void *)h_g_tau[i], (const void *)h_g_albedo[i],
                             (const void *)h_g_emis[i]})
       key.push_back(reinterpret_cast<uintptr_t>(ptr));
-    key.push_back((uintptr_t)(b->ch[i]->mixture ? b->ch[i]->nmix : 0));
+    key.push_back((uintptr_t)(b->ch[i]->mixture ? b->ch[i]->nmix : 0) | (b->ch[i]->dichroic ? 1u << 16 : 0u));
   }
   if (!(b->g_adj.exec && b->g_adj.key == key)) {
     rt_status st = upload_both();

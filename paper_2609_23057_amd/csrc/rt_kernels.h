@@ -9,6 +9,10 @@
 
 namespace rtl {
 
+// Optional extensions of the fused step: a per-cell mixture of phase
+// functions (further contractions) or dichroic absorption (in the gather).
+enum { kExtNone = 0, kExtMix = 1, kExtDich = 2 };
+
 struct Geometry {
   int64_t C;       // cells nx * ny
   int32_t nx, ny;
@@ -107,7 +111,7 @@ constexpr int kBatchWaves = 8;
 
 // LDS bytes the batched kernel needs for a channel of this padded size in
 // blocks of bw waves (SIZE_MAX if bw does not fit the channel).
-size_t batch_lds_bytes(int Rpad, int prec, bool adjoint, int bw);
+size_t batch_lds_bytes(int Rpad, int prec, bool adjoint, int bw, bool dich = false);
 
 // Sets the kernel attributes of the bw-wave batched kernels and returns their
 // blocks per CU for the given LDS size (called before any stream capture).
@@ -115,10 +119,12 @@ hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu);
 
 // One batched fused step (forward or adjoint) over the tiles of one class of
 // channels in bw-wave blocks; the persistent grid is cu_count x the resident
-// blocks of that instantiation.  mix: some channel of the run has a phase
-// mixture (the others pass through the mixture tile with nmix = 0).
+// blocks of that instantiation.  ext: kExtMix if some channel of the run has
+// a phase mixture, kExtDich if some has dichroic absorption (never both; the
+// other channels pass through the extension's tile exactly), else kExtNone;
+// with kExtDich the adjoint's LDS is batch_lds_bytes(.., dich = true).
 hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw, bool adjoint,
-                             bool gather, bool ckpt, bool mix, const BatchSel &sel, int lds_bytes, int cu_count,
+                             bool gather, bool ckpt, int ext, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s);
 
 // Fused forward step on the matrix cores.  gather: in = Y_{t-1}, X = L(in) +

@@ -668,10 +668,6 @@ __device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red
   return (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
 }
 
-// Optional extensions of the forward step: a per-cell mixture of two phase
-// functions (a second contraction) or dichroic absorption (in the gather).
-enum { kExtNone = 0, kExtMix = 1, kExtDich = 2 };
-
 template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone, bool G3 = false>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
@@ -730,7 +726,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   (void)wdir;
   if constexpr (DICH) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wdir[q] = ld[q].d < g.n ? a.dich_w[ld[q].d] : 0.0f;
+    for (int q = 0; q < 4; ++q) wdir[q] = (a.dich_w != nullptr && ld[q].d < g.n) ? a.dich_w[ld[q].d] : 0.0f;
   }
   if constexpr (G3) {
     // 3-D lattice: the tile is the cells x0 .. x0 + 32 NB - 1 of one row
@@ -803,7 +799,9 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       for (int j = 1; j < a.nmix; ++j) fs += a.frac[(int64_t)j * g.C + lc.c];
       fr[cb] = 1.0f - fs;
     }
-    if constexpr (DICH) xi[cb] = a.dich_xi[lc.c];
+    // (a batched channel without dichroic absorption has no factors: xi = 0
+    // makes them exactly 1)
+    if constexpr (DICH) xi[cb] = a.dich_xi != nullptr ? a.dich_xi[lc.c] : 0.0f;
     // A block is interior when every tap of every cell lies inside the lattice
     // (taps reach at most two cells either way); then no wrap or ghost is needed.
     const int c_last = (int)((base + 32 < g.C ? (int64_t)base + 32 : g.C) - 1);
@@ -1255,7 +1253,7 @@ fused_kernel(StepArgs a, int64_t ntiles) {
 // descriptor (scalar loads), its emission rows into LDS and each lane's
 // direction data.
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX = false>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, int EXT = kExtNone>
 __global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restrict__ chans, int nchan,
                                                         int64_t nitems, BatchSel sel) {
   using T = PrecTraits<PREC>;
@@ -1305,7 +1303,8 @@ __global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restr
       W = g.Rpad / 32;
       grp = w / W;
       t = w - grp * W;
-      L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, bc.groups);
+      L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, bc.groups, 1,
+                     (ADJ && EXT == kExtDich) ? 4 : 3);
       char *gb = smem + grp * L.group;
       float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
       ts = TileLds{gb + L.b_off, gb + L.x_off, reinterpret_cast<float *>(gb + L.red_off), s_jrow, nullptr};
@@ -1319,60 +1318,64 @@ __global__ void __launch_bounds__(64 * BW) batch_kernel(const BatchChan *__restr
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ld[q].off), "+v"(ld[q].td), "+v"(ld[q].d));
     const int64_t tile = (it - item0) * (BW / W) + grp;
-    // MIX: the phase-mixture tile, for classes with a mixed channel (a
-    // channel without one passes through it with nmix = 0, exactly)
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, 4, 1>, 1, MIX ? kExtMix : kExtNone>(
+    // EXT: the phase-mixture or dichroic tile, for runs with such a channel
+    // (a channel without the extension passes through it exactly: nmix = 0,
+    // or xi = 0)
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, 4, 1>, 1, EXT>(
         a, g, L, ts, tr, ld, tile, tile < ntiles, t, t, W, lane);
   }
 }
 
-size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint, int bw) {
+size_t batch_lds_bytes_impl(int Rpad, int prec, bool adjoint, int bw, bool dich) {
   const int W = Rpad / 32;
   if (W < 1 || W > kBatchWaves || bw < W || bw > kBatchWaves || bw % W != 0) return (size_t)-1;
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
-  return (size_t)lds_layout(Rpad, esize, ntile, W, adjoint, prec == P_F16, bw / W).total;
+  return (size_t)lds_layout(Rpad, esize, ntile, W, adjoint, prec == P_F16, bw / W, 1, (adjoint && dich) ? 4 : 3)
+      .total;
 }
 
 // Occupancy of one batch instantiation; prepare_batch fills the memo before
 // any launch, so a launch under stream capture makes no runtime query.
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, int EXT>
 hipError_t batch_blocks_per_cu(int lds_bytes, int *occ) {
   static std::atomic<uint64_t> memo{0};
-  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT, BW, MIX>, 64 * BW, lds_bytes, memo,
+  return resident_blocks((const void *)batch_kernel<PREC, GATHER, ADJ, CKPT, BW, EXT>, 64 * BW, lds_bytes, memo,
                          occ);
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, int EXT>
 hipError_t prepare_batch_k(int lds_bytes, int *occ) {
-  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW, MIX>;
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW, EXT>;
   hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return e;
   int o = 0;
-  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW, MIX>(lds_bytes, &o);
+  e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW, EXT>(lds_bytes, &o);
   if (e != hipSuccess) return e;
   *occ = std::min(*occ, o);
   return hipSuccess;
 }
 
-template <int PREC, int BW, bool MIX>
+template <int PREC, int BW, int EXT>
 hipError_t prepare_batch_m(int lds_bytes, int *occ) {
   hipError_t e;
-  if ((e = prepare_batch_k<PREC, false, false, false, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, true, false, false, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, true, false, true, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
-  if ((e = prepare_batch_k<PREC, false, true, false, BW, MIX>(lds_bytes, occ)) != hipSuccess) return e;
-  return prepare_batch_k<PREC, true, true, false, BW, MIX>(lds_bytes, occ);
+  if ((e = prepare_batch_k<PREC, false, false, false, BW, EXT>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, false, BW, EXT>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, true, false, true, BW, EXT>(lds_bytes, occ)) != hipSuccess) return e;
+  if ((e = prepare_batch_k<PREC, false, true, false, BW, EXT>(lds_bytes, occ)) != hipSuccess) return e;
+  return prepare_batch_k<PREC, true, true, false, BW, EXT>(lds_bytes, occ);
 }
 
-// blocks per CU: those of the single-phase instantiations (the mixture ones
-// are prepared too, and size their own grids at launch)
+// blocks per CU: those of the instantiations without extensions (the
+// phase-mixture and dichroic ones are prepared too, and size their own grids
+// at launch)
 template <int PREC, int BW>
 hipError_t prepare_batch_p(int lds_bytes, int *occ) {
-  const hipError_t e = prepare_batch_m<PREC, BW, false>(lds_bytes, occ);
+  hipError_t e = prepare_batch_m<PREC, BW, kExtNone>(lds_bytes, occ);
   if (e != hipSuccess) return e;
-  int mix_occ = 1 << 20;
-  return prepare_batch_m<PREC, BW, true>(lds_bytes, &mix_occ);
+  int ext_occ = 1 << 20;
+  if ((e = prepare_batch_m<PREC, BW, kExtMix>(lds_bytes, &ext_occ)) != hipSuccess) return e;
+  return prepare_batch_m<PREC, BW, kExtDich>(lds_bytes, &ext_occ);
 }
 
 template <int PREC>
@@ -1399,13 +1402,13 @@ hipError_t prepare_batch_impl(int prec, int bw, int lds_bytes, int *blocks_per_c
   return hipSuccess;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, bool MIX>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int BW, int EXT>
 hipError_t launch_batch_k(const BatchChan *d_chans, int nchan, int64_t nitems, const BatchSel &sel, int lds_bytes,
                           int cu_count, hipStream_t s) {
-  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW, MIX>;
+  auto k = batch_kernel<PREC, GATHER, ADJ, CKPT, BW, EXT>;
   // persistent grid sized by this instantiation's own occupancy
   int occ = 0;
-  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW, MIX>(lds_bytes, &occ);
+  const hipError_t e = batch_blocks_per_cu<PREC, GATHER, ADJ, CKPT, BW, EXT>(lds_bytes, &occ);
   if (e != hipSuccess) return e;
   int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)cu_count * occ));
   if (grid >= 8) grid &= ~7LL;
@@ -1413,53 +1416,57 @@ hipError_t launch_batch_k(const BatchChan *d_chans, int nchan, int64_t nitems, c
   return hipGetLastError();
 }
 
-template <int PREC, int BW, bool MIX>
+template <int PREC, int BW, int EXT>
 hipError_t launch_batch_m(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
                           const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
   if (adjoint) {
     if (gather)
-      return launch_batch_k<PREC, true, true, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-    return launch_batch_k<PREC, false, true, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+      return launch_batch_k<PREC, true, true, false, BW, EXT>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    return launch_batch_k<PREC, false, true, false, BW, EXT>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
   }
-  if (ckpt) return launch_batch_k<PREC, true, false, true, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  if (ckpt) return launch_batch_k<PREC, true, false, true, BW, EXT>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
   if (gather)
-    return launch_batch_k<PREC, true, false, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
-  return launch_batch_k<PREC, false, false, false, BW, MIX>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+    return launch_batch_k<PREC, true, false, false, BW, EXT>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
+  return launch_batch_k<PREC, false, false, false, BW, EXT>(d_chans, nchan, nitems, sel, lds_bytes, cu_count, s);
 }
 
 template <int PREC, int BW>
 hipError_t launch_batch_p(const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather, bool ckpt,
-                          bool mix, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
-  if (mix) return launch_batch_m<PREC, BW, true>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
-  return launch_batch_m<PREC, BW, false>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+                          int ext, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
+  if (ext == kExtMix)
+    return launch_batch_m<PREC, BW, kExtMix>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+  if (ext == kExtDich)
+    return launch_batch_m<PREC, BW, kExtDich>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
+  if (ext != kExtNone) return hipErrorInvalidValue;
+  return launch_batch_m<PREC, BW, kExtNone>(d_chans, nchan, nitems, adjoint, gather, ckpt, sel, lds_bytes, cu_count, s);
 }
 
 template <int PREC>
 hipError_t launch_batch_w(int bw, const BatchChan *d_chans, int nchan, int64_t nitems, bool adjoint, bool gather,
-                          bool ckpt, bool mix, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
+                          bool ckpt, int ext, const BatchSel &sel, int lds_bytes, int cu_count, hipStream_t s) {
   switch (bw) {
-    case 1: return launch_batch_p<PREC, 1>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
-    case 2: return launch_batch_p<PREC, 2>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
-    case 4: return launch_batch_p<PREC, 4>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
-    case 8: return launch_batch_p<PREC, 8>(d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+    case 1: return launch_batch_p<PREC, 1>(d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
+    case 2: return launch_batch_p<PREC, 2>(d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
+    case 4: return launch_batch_p<PREC, 4>(d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
+    case 8: return launch_batch_p<PREC, 8>(d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_step_impl(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw,
-                                  bool adjoint, bool gather, bool ckpt, bool mix, const BatchSel &sel,
+                                  bool adjoint, bool gather, bool ckpt, int ext, const BatchSel &sel,
                                   int lds_bytes, int cu_count, hipStream_t s) {
   if (ckpt && (adjoint || !gather)) return hipErrorInvalidValue;
   if (cu_count < 1 || nitems < 1) return hipErrorInvalidValue;
   switch (prec) {
     case P_F32:
-      return launch_batch_w<P_F32>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+      return launch_batch_w<P_F32>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
     case P_BF16:
-      return launch_batch_w<P_BF16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+      return launch_batch_w<P_BF16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
     case P_F16:
-      return launch_batch_w<P_F16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes, cu_count, s);
+      return launch_batch_w<P_F16>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes, cu_count, s);
     case P_BF16X3:
-      return launch_batch_w<P_BF16X3>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, mix, sel, lds_bytes,
+      return launch_batch_w<P_BF16X3>(bw, d_chans, nchan, nitems, adjoint, gather, ckpt, ext, sel, lds_bytes,
                                       cu_count, s);
   }
   return hipErrorInvalidValue;
@@ -2180,8 +2187,8 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 4096) {
 
 }  // namespace
 
-size_t batch_lds_bytes(int Rpad, int prec, bool adjoint, int bw) {
-  return batch_lds_bytes_impl(Rpad, prec, adjoint, bw);
+size_t batch_lds_bytes(int Rpad, int prec, bool adjoint, int bw, bool dich) {
+  return batch_lds_bytes_impl(Rpad, prec, adjoint, bw, dich);
 }
 
 hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu) {
@@ -2189,9 +2196,9 @@ hipError_t prepare_batch(int prec, int bw, int lds_bytes, int *blocks_per_cu) {
 }
 
 hipError_t launch_batch_step(const BatchChan *d_chans, int nchan, int64_t nitems, int prec, int bw, bool adjoint,
-                             bool gather, bool ckpt, bool mix, const BatchSel &sel, int lds_bytes, int cu_count,
+                             bool gather, bool ckpt, int ext, const BatchSel &sel, int lds_bytes, int cu_count,
                              hipStream_t s) {
-  return launch_batch_step_impl(d_chans, nchan, nitems, prec, bw, adjoint, gather, ckpt, mix, sel, lds_bytes,
+  return launch_batch_step_impl(d_chans, nchan, nitems, prec, bw, adjoint, gather, ckpt, ext, sel, lds_bytes,
                                 cu_count, s);
 }
 

@@ -1,8 +1,9 @@
-"""Spectral batch with phase mixtures: channels whose scattering is a per-cell
-mixture of phase functions (two or three) run beside single-phase channels
-in the batched launches and reproduce their own contexts bit for bit
-(states, checkpoints, adjoint gradients); a mixture set or removed between
-runs is taken up, also by graph replays."""
+"""Spectral batch with the operator extensions: channels whose scattering is
+a per-cell mixture of phase functions (two or three) or whose absorption is
+dichroic run beside plain channels in the batched launches (the dichroic
+channels of a class in a launch of their own) and reproduce their own
+contexts bit for bit (states, checkpoints, adjoint gradients); an extension
+set or removed between runs is taken up, also by graph replays."""
 import numpy as np
 import pytest
 import torch
@@ -13,7 +14,12 @@ from test_gpu_batch import SMALL, channel_specs, initial_states, make_batch
 
 pytestmark = pytest.mark.gpu
 
-MIXES = {1: {"kind": "rayleigh"}, 3: [{"kind": "hg", "g": -0.3}, {"kind": "rayleigh"}]}
+# channels with n = 8, 16, 32, 64, 16 and 16; the class n = 16 holds a mixed
+# (1), a dichroic (4) and a plain channel (5): two launches, the mixture tile
+# taking the plain channel
+LAYOUT = SMALL + [((24, 30), (2, 8))]
+EXTS = {0: ("dichroism", 0.8), 1: ("mixture", {"kind": "rayleigh"}), 2: ("dichroism", 0.5),
+        3: ("mixture", [{"kind": "hg", "g": -0.3}, {"kind": "rayleigh"}]), 4: ("dichroism", 0.3)}
 
 
 @pytest.fixture(autouse=True, scope="module")
@@ -22,40 +28,52 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def mixed_specs():
-    specs = channel_specs(SMALL)
-    for i, mix in MIXES.items():
-        specs[i] = dict(specs[i], mixture=mix)
+def ext_specs(exts=EXTS):
+    specs = channel_specs(LAYOUT)
+    for i, (kind, val) in exts.items():
+        specs[i] = dict(specs[i], **{kind: val})
     return specs
 
 
-def set_mixtures(solvers, specs, meds):
+def set_extensions(solvers, specs, meds):
     keep = []
     for ch, s, med in zip(solvers, specs, meds):
         if s.get("mixture") is not None:
             f = to_dev(med["frac"], ch)
             ch.set_phase_mixture(s["mixture"], f)
             keep.append(f)
+        if s.get("dichroism") is not None:
+            e = to_dev(med["eta"], ch)
+            ch.set_dichroism(e)
+            keep.append(e)
     return keep
 
 
-def single_run(s, precision, med, S0, T, K, lam=None):
+def clear_extensions(solvers, specs):
+    for ch, s in zip(solvers, specs):
+        if s.get("mixture") is not None:
+            ch.set_phase_mixture(None, None)
+        if s.get("dichroism") is not None:
+            ch.set_dichroism(None)
+
+
+def single_run(s, precision, med, S0, T, K, lam):
     single, oprob, _ = build(s, precision, med)
-    keep = set_mixtures([single], [s], [med])
+    keep = set_extensions([single], [s], [med])
     S = S0.clone()
     ck = single.checkpoint_buffer(T, K)
     single.run(S, T, ck, K)
-    g = single.adjoint(T, ck, K, lam) if lam is not None else None
+    g = single.adjoint(T, ck, K, lam)
     torch.cuda.synchronize()
     del keep
     return S, ck, g, oprob
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3", "fp16"])
-def test_batch_with_mixed_channels_matches_single_contexts_bitwise(precision):
-    specs = mixed_specs()
+def test_batch_with_extended_channels_matches_single_contexts_bitwise(precision):
+    specs = ext_specs()
     batch, meds = make_batch(specs, precision)
-    keep = set_mixtures(batch.channels, specs, meds)
+    keep = set_extensions(batch.channels, specs, meds)
     S0 = initial_states(batch, specs)
     T, K = 9, 3
     states = [s.clone() for s in S0]
@@ -70,21 +88,21 @@ def test_batch_with_mixed_channels_matches_single_contexts_bitwise(precision):
         assert torch.equal(ck1, ck[i]), (precision, i)
         for a, b, name in zip(grads[i], g1, ("tau", "albedo", "emis")):
             assert torch.equal(a, b), (precision, i, name)
-        if i in MIXES:
-            assert oprob.mix_M is not None
+        if i in EXTS:
+            assert oprob.mix_M is not None or oprob.eta is not None
             ref = OL.run(to_np(S0[i]), oprob, T)
             assert_close(to_np(states[i]), ref, tolerance(precision, oprob, T), (precision, i))
     del keep
 
 
-def test_mixture_changes_between_runs_and_graph_replays():
-    """Eager: no mixture, then mixtures on two channels, then none again.
-    Graph mode runs the same sequence on the same buffers (so a recorded
-    graph would be replayed unless the change of mixture is noticed) and
+def test_extension_changes_between_runs_and_graph_replays():
+    """Eager: no extension, then the mixtures and the dichroism, then none
+    again.  Graph mode runs the same sequence on the same buffers (so a
+    recorded graph would be replayed unless the change is noticed) and
     matches each eager result; with a cache budget of one byte (every channel
     a group of its own, on the single-problem kernels) the bits are the same."""
     import paper_2609_23057_amd._abi as A
-    specs = mixed_specs()
+    specs = ext_specs()
     batch, meds = make_batch(specs, "bf16")
     S0 = initial_states(batch, specs)
     T, K = 6, 3
@@ -106,10 +124,9 @@ def test_mixture_changes_between_runs_and_graph_replays():
 
     def sequence():
         out = [run_once()]
-        keep = set_mixtures(batch.channels, specs, meds)
+        keep = set_extensions(batch.channels, specs, meds)
         out.append(run_once())
-        for i in MIXES:
-            batch.channels[i].set_phase_mixture(None, None)
+        clear_extensions(batch.channels, specs)
         out.append(run_once())
         del keep
         return out
@@ -131,19 +148,30 @@ def test_mixture_changes_between_runs_and_graph_replays():
             assert torch.equal(a, b), ("one channel per group", k)
 
 
-def test_batch_refuses_a_dichroic_channel_but_not_a_mixed_one():
-    import paper_2609_23057_amd as P
-    specs = mixed_specs()[:2]
+def test_dichroic_channel_gradients_against_the_oracle():
+    """A dichroic channel's batched adjoint (its own launch in the class)
+    against the oracle adjoint, tau and albedo gradients carrying the
+    derivative through xi = tau_abs eta."""
+    from gpu_common import GTOL
+    from oracle import adjoint as OA
+    specs = ext_specs({0: ("dichroism", 0.8), 2: ("dichroism", 0.5)})[:3]
     batch, meds = make_batch(specs, "fp32")
-    keep = set_mixtures(batch.channels, specs, meds)
-    states = initial_states(batch, specs)
-    batch.run(states, 2)
-    eta = to_dev(np.full((specs[0]["ny"], specs[0]["nx"]), 0.2), batch.channels[0])
-    batch.channels[0].set_dichroism(eta)
-    with pytest.raises(P.RTError) as ei:
-        batch.run(states, 2)
-    assert ei.value.status == P.RT_EUNSUPPORTED
-    batch.channels[0].set_dichroism(None)
-    batch.run(states, 2)
+    keep = set_extensions(batch.channels, specs, meds)
+    S0 = initial_states(batch, specs)
+    T, K = 8, 3
+    states = [s.clone() for s in S0]
+    ck = batch.checkpoint_buffers(T, K)
+    batch.run(states, T, ck, K)
+    rng = np.random.default_rng(6)
+    lamTs = [rng.standard_normal(ch.shape) for ch in batch.channels]
+    grads = batch.adjoint(T, ck, K, [to_dev(x, ch) for x, ch in zip(lamTs, batch.channels)])
     torch.cuda.synchronize()
+    for i in (0, 2):
+        oprob = OL.make_problem(specs[i], meds[i])
+        assert oprob.eta is not None
+        res = OA.adjoint(to_np(S0[i]), oprob, T, lamTs[i])
+        for got, key in zip(grads[i], ("g_tau", "g_albedo", "g_emis")):
+            ref = res[key]
+            err = np.linalg.norm(to_np(got) - ref) / max(np.linalg.norm(ref), 1e-300)
+            assert err < GTOL["fp32"], (i, key, err)
     del keep

@@ -177,28 +177,6 @@ def test_dichroism_refusals():
     assert ei.value.status == P.RT_EUNSUPPORTED
 
 
-def test_batch_refuses_dichroic_channel():
-    import paper_2609_23057_amd as P
-    spec = W.spec("beam512", nx=24, ny=20, n_zen=2, n_az=8, dichroism=0.5)
-    prob = P.make_problem(**dict(spec, precision="bf16"))
-    batch = P.Batch([prob, prob])
-    med = W.medium(spec)
-    keep = []
-    for ch in batch.channels:
-        t = [to_dev(med[k], ch) for k in ("tau", "albedo", "emis")]
-        keep.append(t)
-        ch.set_medium(*t, med["jprof"], med["inflow"])
-    states = batch.empty_states()
-    eta = to_dev(med["eta"], batch.channels[0])
-    batch.channels[0].set_dichroism(eta)
-    with pytest.raises(P.RTError) as ei:
-        batch.run(states, 2)
-    assert ei.value.status == P.RT_EUNSUPPORTED
-    batch.channels[0].set_dichroism(None)
-    batch.run(states, 2)
-    torch.cuda.synchronize()
-
-
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 

@@ -213,3 +213,24 @@ def test_k_mixture_refusals():
     with pytest.raises(P.RTError) as ei:
         solver.set_phase_mixture(MIX3, ok)
     assert ei.value.status == P.RT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_k_mixture_full_size_beam512(precision):
+    """The full 512 x 512, n = 32 lattice with four phase functions, in the
+    checkpointed launch of the bench: every cell for three steps against the
+    oracle."""
+    spec = W.spec("beam512", mixture=MIX4)
+    solver, oprob, _ = _with_mixture(spec, precision)
+    rng = np.random.default_rng(37)
+    S0 = np.abs(rng.standard_normal(solver.shape)) * 0.1
+    S0[:, 1:] *= 0.2 * np.sign(rng.standard_normal(S0[:, 1:].shape))
+    T, K = 3, 2
+    S = to_dev(S0, solver)
+    ck = solver.checkpoint_buffer(T, K)
+    solver.run(S, T, ck, K)
+    torch.cuda.synchronize()
+    hist = OL.run(S0, oprob, T, keep=True)[1]
+    tol = tolerance(precision, oprob)
+    assert_close(to_np(S), hist[T], tol, ("S_T", precision))
+    assert_close(to_np(ck[1]), hist[2], tol, ("checkpoint 1", precision))

@@ -32,17 +32,19 @@ def _leaf(a, solver):
     return to_dev(a, solver).requires_grad_(True)
 
 
-@pytest.mark.parametrize("ext", [None, "mixture"])
+@pytest.mark.parametrize("ext", [None, "mixture", "mixture3"])
 def test_two_applications_before_one_backward(ext):
     import paper_2609_23057_amd as P
     spec = W.spec("adjoint256", nx=30, ny=26)
     if ext == "mixture":
         spec = dict(spec, mixture={"kind": "rayleigh"})
+    elif ext == "mixture3":
+        spec = dict(spec, mixture=[{"kind": "rayleigh"}, {"kind": "hg", "g": -0.4}])
     solver, _, med = build(spec, "fp32")
     med2 = W.medium(spec, seed=77)
     T = 14
     frac = None
-    if ext == "mixture":
+    if ext is not None:
         frac = to_dev(med["frac"], solver)
         solver.set_phase_mixture(spec["mixture"], frac)
 
@@ -69,5 +71,5 @@ def test_two_applications_before_one_backward(ext):
     # the solver holds the newest medium again (and still the mixture)
     tau_now = solver.medium_state()[1][0]
     assert torch.equal(tau_now, l2[0].detach())
-    if ext == "mixture":
+    if ext is not None:
         assert solver.medium_state()[2][1] is frac

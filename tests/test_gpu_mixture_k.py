@@ -234,3 +234,45 @@ def test_k_mixture_full_size_beam512(precision):
     tol = tolerance(precision, oprob)
     assert_close(to_np(S), hist[T], tol, ("S_T", precision))
     assert_close(to_np(ck[1]), hist[2], tol, ("checkpoint 1", precision))
+
+
+MIX8 = [{"kind": "rayleigh"}, {"kind": "hg", "g": -0.3}, {"kind": "mix", "g": 0.5, "mix_ray": 0.4},
+        {"kind": "hg", "g": 0.2}, {"kind": "hg", "g": -0.6}, {"kind": "mix", "g": -0.2, "mix_ray": 0.7},
+        {"kind": "hg", "g": 0.4}]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "plain"])
+def test_largest_mixture_eight_phase_functions(precision):
+    """K = 8 (RT_MIX_MAX = 7 further phase functions), n = 16 and n = 64,
+    against the oracle; the workspace holds exactly seven components."""
+    import paper_2609_23057_amd._abi as A
+    assert A.RT_MIX_MAX == len(MIX8)
+    for over in (dict(nx=29, ny=23, n_zen=2, n_az=8), dict(nx=21, ny=17, n_zen=4, n_az=16)):
+        spec = W.spec("beam512", mixture=MIX8, **over)
+        solver, oprob, _ = _with_mixture(spec, precision)
+        assert len(oprob.mix_M) == 7
+        S0 = W.initial_state(spec, "random")
+        S = to_dev(S0, solver)
+        solver.run(S, 12)
+        assert_close(to_np(S), OL.run(S0, oprob, 12), tolerance(precision, oprob, 12), (precision, over))
+
+
+def test_fp16_range_refusal_of_one_component():
+    """fp16 packs every further matrix at the first one's scale: one strongly
+    forward-peaked component among acceptable ones is refused (RT_ERANGE) and
+    leaves the context without a mixture."""
+    import paper_2609_23057_amd as P
+    mix = [{"kind": "rayleigh"}, {"kind": "hg", "g": 0.95}]
+    spec = W.spec("prec1024", nx=20, ny=18, phase={"kind": "hg", "g": 0.0}, mixture=mix)
+    solver, _, med = build(spec, "fp16")
+    S0 = to_dev(W.initial_state(spec, "random"), solver)
+    ref = S0.clone()
+    solver.run(ref, 3)
+    with pytest.raises(P.RTError) as ei:
+        solver.set_phase_mixture(mix, to_dev(med["frac"], solver))
+    assert ei.value.status == P.RT_ERANGE
+    S = S0.clone()
+    solver.run(S, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(S, ref)
+    solver.set_phase_mixture(mix[:1], to_dev(med["frac"][:1], solver))   # the acceptable one alone

@@ -103,12 +103,20 @@ __global__ void __launch_bounds__(kSvThreads) sv_norm_partial_kernel(const doubl
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void sv_norm_final_kernel(const double *__restrict__ partial, int np, double *result) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < np; ++i) s += partial[i];
-    *result = s;
+// One block of kSvThreads threads: each sums a strided share of the partials,
+// then a tree in LDS (a fixed order, so the result does not vary run to run).
+__global__ void __launch_bounds__(kSvThreads) sv_norm_final_kernel(const double *__restrict__ partial, int np,
+                                                                   double *result) {
+  __shared__ double red[kSvThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kSvThreads) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kSvThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *result = red[0];
 }
 
 __device__ __forceinline__ uint64_t data_index(int st, int sl, int din, int dout, int y, int x, int nd, int ny,
@@ -182,7 +190,7 @@ int sv_norm_partials() { return kSvNormBlocks; }
 hipError_t sv_launch_norm2(const double *a, uint64_t na, const double *b, uint64_t nb, double *partial,
                            double *result, hipStream_t s) {
   hipLaunchKernelGGL(sv_norm_partial_kernel, dim3(kSvNormBlocks), dim3(kSvThreads), 0, s, a, na, b, nb, partial);
-  hipLaunchKernelGGL(sv_norm_final_kernel, dim3(1), dim3(64), 0, s, partial, kSvNormBlocks, result);
+  hipLaunchKernelGGL(sv_norm_final_kernel, dim3(1), dim3(kSvThreads), 0, s, partial, kSvNormBlocks, result);
   return hipGetLastError();
 }
 

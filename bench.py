@@ -436,9 +436,11 @@ def statevector_extras(T=4, warm=1):
     2.1.8) on its 16x16 D2Q9 lattice with 2 x 4 directions (29 qubits, a
     2^29-amplitude float64 statevector): time per emulated step (encode,
     every gate, post-selection, decode; HIP events around rt_sv_step on the
-    solver's stream), the statevector bytes its gate and translation
-    launches move, and the agreement with the classical step after T steps
-    (the oracle's float64 step; the paper's Tables 1-2 report 1e-13)."""
+    solver's stream), the statevector bytes its gate, fused-gate and
+    translation launches move, and the agreement with the classical step
+    after T steps (the oracle's float64 step; the paper's Tables 1-2 report
+    1e-13).  The same steps with every gate launched alone (no fused passes)
+    are timed beside it."""
     import numpy as np
     import torch
     import paper_2609_23057_amd._abi as A
@@ -448,37 +450,44 @@ def statevector_extras(T=4, warm=1):
     _log("bench: statevector emulation (qlbm16)")
     solver = make_solver(spec, "fp32")
     nq, ndata = A.rt_sv_qubits(solver.ctx)
-    gates, shifts, nbytes = A.rt_sv_gate_count(solver.ctx)
     work = solver.sv_workspace()
     S0 = np.asarray(W.initial_state(spec, "zero"))
     S = torch.zeros(S0.shape, dtype=torch.float64, device=solver.device)
-    for _ in range(warm):
-        solver.sv_step(S, work=work)
-    S.zero_()
-    torch.cuda.synchronize()
-    times, probs = [], []
-    for _ in range(T):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        S, p = solver.sv_step(S, work=work)
-        e1.record()
+    runs = {}
+    for fuse in (0, 3):
+        A.rt_sv_set_fusion(solver.ctx, fuse)
+        S.zero_()
+        for _ in range(warm):
+            solver.sv_step(S, work=work)
+        S.zero_()
         torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-        probs.append(p)
+        times, probs = [], []
+        for _ in range(T):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            S, p = solver.sv_step(S, work=work)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            probs.append(p)
+        runs[fuse] = (sum(times) / len(times), probs, A.rt_sv_launch_count(solver.ctx),
+                      A.rt_sv_gate_count(solver.ctx))
+    ms, probs, launches, (gates, shifts, nbytes) = runs[3]
     med = W.medium(spec)
     ref = OL.run(S0, OL.make_problem(spec, med), T)
     got = S.cpu().numpy()
-    ms = sum(times) / len(times)
     gbs = nbytes / (ms * 1e-3) / 1e9
     out = {"workload": "qlbm16: 16x16 D2Q9 lattice, n=8 (2x4), k_ext=2.5, k_scat=0.5, dt=1/16, central source, "
                        "absorbing edges; %d emulated steps with re-encoding" % T,
            "qubits": nq, "data_qubits": ndata, "statevector_bytes": 8 << nq,
-           "gate_launches": gates, "translation_launches": shifts, "ms_per_step": ms,
+           "gates": gates, "translations": shifts, "launches": launches, "ms_per_step": ms,
+           "unfused": {"launches": runs[0][2], "ms_per_step": runs[0][0], "bytes_per_step": runs[0][3][2]},
            "success_probability": probs,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes,
-                        "note": "statevector bytes of the gate and translation launches (32 per active amplitude "
-                                "pair of a gate, 16 per amplitude of a translation) over the whole step time"},
+                        "note": "statevector bytes of the launches (32 per active amplitude pair of a gate "
+                                "launched alone, 16 per amplitude of a fused gate pass or a translation) over "
+                                "the whole step time"},
            "max_abs_diff_vs_classical": float(np.abs(got - ref).max()),
            "rel_l2_diff_vs_classical": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
     del work, solver

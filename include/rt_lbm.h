@@ -402,10 +402,20 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
  * rt_sv_workspace_bytes: device bytes rt_sv_step needs (two statevectors of
  *   2^nqubits float64, gate tables, the encoded source); 0 if not emulated
  *   (rt_last_error says why).
- * rt_sv_gate_count: gate launches (rotations, controlled X/Z, H and the Q-U
- *   rotations) and translation launches of one step, and (if not NULL) the
- *   statevector bytes they move: 32 per active amplitude pair of a gate (the
- *   states whose control qubits match), 16 per amplitude of a translation.
+ * rt_sv_gate_count: gates (rotations, controlled X/Z, H and the Q-U
+ *   rotations) and translations of one step, and (if not NULL) the
+ *   statevector bytes their launches move: 32 per active amplitude pair of a
+ *   gate launched alone (the states whose control qubits match), 16 per
+ *   amplitude of a translation or of a fused pass.
+ * rt_sv_set_fusion: consecutive gates whose target qubits lie within
+ *   max_qubits qubits (0 .. 3; default 3) are applied in one pass over the
+ *   statevector (each thread holds the 2^m amplitudes that differ in those
+ *   qubits and applies the gates in order) where that moves fewer bytes than
+ *   launching them one by one; 0 launches every gate alone.  The products
+ *   are the same, so the result does not depend on it.  RT_EINVAL outside
+ *   0 .. 3.
+ * rt_sv_launch_count: launches of gates, fused passes and translations one
+ *   step makes with the current fusion setting.
  * rt_sv_step: one emulated step of the context's medium (rt_set_medium must
  *   have succeeded) from d_S_in to d_S_out (device float64 [n][4][ny][nx],
  *   caller-owned, may be the same array); d_work is the caller's workspace
@@ -416,6 +426,8 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
 rt_status rt_sv_qubits(const rt_ctx *c, int32_t *nqubits, int32_t *ndata);
 size_t rt_sv_workspace_bytes(const rt_ctx *c);
 rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts, double *bytes_per_step);
+rt_status rt_sv_set_fusion(rt_ctx *c, int32_t max_qubits);
+rt_status rt_sv_launch_count(const rt_ctx *c, int32_t *nlaunches);
 rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d_S_in, double *d_S_out,
                      double *h_psucc);
 

@@ -82,6 +82,8 @@ _SIGS = {
     "rt_sv_workspace_bytes": (c_size_t, [c_void_p]),
     "rt_sv_gate_count": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double)]),
     "rt_sv_step": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, POINTER(c_double)]),
+    "rt_sv_set_fusion": (c_int32, [c_void_p, c_int32]),
+    "rt_sv_launch_count": (c_int32, [c_void_p, POINTER(c_int32)]),
     "rt_readout_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "rt_adjoint_segment_bytes": (c_size_t, [_P, c_int32]),
     "rt_adjoint": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
@@ -238,6 +240,17 @@ def rt_sv_gate_count(ctx):
     g, s, b = c_int32(0), c_int32(0), c_double(0.0)
     _check(_lib.rt_sv_gate_count(ctx, ctypes.byref(g), ctypes.byref(s), ctypes.byref(b)), ctx)
     return g.value, s.value, b.value
+
+
+def rt_sv_set_fusion(ctx, max_qubits):
+    """Target qubits of a fused gate pass (0 .. 3; 0: every gate alone)."""
+    _check(_lib.rt_sv_set_fusion(ctx, int(max_qubits)), ctx)
+
+
+def rt_sv_launch_count(ctx):
+    n = c_int32()
+    _check(_lib.rt_sv_launch_count(ctx, ctypes.byref(n)), ctx)
+    return n.value
 
 
 def rt_sv_step(ctx, d_work, work_bytes, d_S_in, d_S_out):

@@ -208,6 +208,7 @@ struct rt_ctx {
   Stream3Args s3rev{};    // the transpose of its streaming (the adjoint's reverse pull)
   int zblk = kLayerBlock; // 3-D fused step: layers per block of its tile order
   int strip = -1;         // 2-D fused steps: strip width of the tile order in tiles (0: row order; -1: by size)
+  int sv_fuse = kSvFuseMaxQ;  // statevector emulation: target qubits of a fused gate pass (0: none)
   int prec = 0;
   int cu_count = 256;
   int device = 0;     // the HIP device current at rt_init
@@ -1462,6 +1463,136 @@ std::string sv_compile(const rt_ctx *c, const std::vector<float> &tau, const std
   return "";
 }
 
+// The launches of one step: a translation, a gate alone, or a run of
+// consecutive gates on at most max_q target qubits in one pass, where that
+// moves fewer statevector bytes (a gate alone moves the pairs whose control
+// qubits match: 2^(1 - fixed) of the vector, fixed = its target and control
+// qubits; a fused pass moves the states whose shared control qubits match
+// once: 2^-shared of it).
+struct SvLaunch {
+  int kind = 0;             // 0 translation, 1 gate, 2 fused run
+  std::vector<int> ops;     // indices into SvCircuit::ops
+  std::vector<int> tq;      // fused: target qubits, ascending
+  uint64_t ccmask = 0, ccval = 0;   // fused: control qubits every gate shares, with their value
+};
+
+double sv_gate_fraction(const SvGate &g, int nq) {
+  int fixed = 0;
+  for (int b = 0; b < nq; ++b) fixed += (int)(((g.mask | g.cmask) >> b) & 1);
+  return std::ldexp(1.0, 1 - fixed);
+}
+
+std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
+  std::vector<SvLaunch> out;
+  std::vector<int> run;
+  std::vector<int> tq;
+  auto flush = [&]() {
+    double frac = 0.0;
+    for (int i : run) frac += sv_gate_fraction(K.ops[i].g, K.L.nq);
+    // shared controls: the same value in every gate, none of them a target
+    uint64_t cm = ~0ull, tmask = 0;
+    for (int q : tq) tmask |= 1ull << q;
+    for (int i : run) cm &= K.ops[i].g.cmask;
+    if (!run.empty())
+      for (int i : run) cm &= ~(K.ops[i].g.cval ^ K.ops[run[0]].g.cval);
+    cm &= ~tmask;
+    if (run.empty()) cm = 0;
+    const double fused = std::ldexp(1.0, -__builtin_popcountll(cm));
+    if (run.size() >= 2 && frac > fused) {
+      SvLaunch l;
+      l.kind = 2;
+      l.ops = run;
+      l.tq = tq;
+      std::sort(l.tq.begin(), l.tq.end());
+      l.ccmask = cm;
+      l.ccval = K.ops[run[0]].g.cval & cm;
+      out.push_back(l);
+    } else {
+      for (int i : run) {
+        SvLaunch l;
+        l.kind = 1;
+        l.ops = {i};
+        out.push_back(l);
+      }
+    }
+    run.clear();
+    tq.clear();
+  };
+  for (int i = 0; i < (int)K.ops.size(); ++i) {
+    const SvOp &op = K.ops[i];
+    if (op.shift) {
+      flush();
+      SvLaunch l;
+      l.kind = 0;
+      l.ops = {i};
+      out.push_back(l);
+      continue;
+    }
+    std::vector<int> t = tq;
+    for (int k = 0; k < op.g.nbits; ++k)
+      if (std::find(t.begin(), t.end(), op.g.pos[k]) == t.end()) t.push_back(op.g.pos[k]);
+    if (!run.empty() && ((int)t.size() > max_q || (int)run.size() == kSvFuseMaxGates)) {
+      flush();
+      t.clear();
+      for (int k = 0; k < op.g.nbits; ++k) t.push_back(op.g.pos[k]);
+    }
+    if ((int)t.size() > max_q) {   // max_q 0 (or a pair gate at max_q 1): alone
+      flush();
+      SvLaunch l;
+      l.kind = 1;
+      l.ops = {i};
+      out.push_back(l);
+      continue;
+    }
+    run.push_back(i);
+    tq = t;
+  }
+  flush();
+  return out;
+}
+
+double sv_plan_bytes(const SvCircuit &K, const std::vector<SvLaunch> &plan) {
+  double bytes = 0.0;
+  for (const SvLaunch &l : plan) {
+    if (l.kind == 1)
+      bytes += 16.0 * std::ldexp(1.0, K.L.nq) * sv_gate_fraction(K.ops[l.ops[0]].g, K.L.nq);
+    else if (l.kind == 2)
+      bytes += 16.0 * std::ldexp(1.0, K.L.nq - __builtin_popcountll(l.ccmask));   // the visited states once
+    else
+      bytes += 16.0 * std::ldexp(1.0, K.L.nq);   // every amplitude read and written once
+  }
+  return bytes;
+}
+
+// The fused pass of a planned run; table pointers into the device table region.
+SvFuse sv_fuse_of(const SvCircuit &K, const SvLaunch &l, const double *tables) {
+  SvFuse f{};
+  f.m = (int)l.tq.size();
+  f.ngates = (int)l.ops.size();
+  for (int k = 0; k < f.m; ++k) f.tq[k] = l.tq[k];
+  f.ccmask = l.ccmask;
+  f.ccval = l.ccval;
+  auto local = [&](int q) { return (int)(std::find(l.tq.begin(), l.tq.end(), q) - l.tq.begin()); };
+  for (int j = 0; j < f.ngates; ++j) {
+    const SvOp &op = K.ops[l.ops[j]];
+    SvFusedGate &g = f.g[j];
+    g.cmask = op.g.cmask;
+    g.cval = op.g.cval;
+    g.table = tables + op.table_off;
+    g.naddr = op.g.naddr;
+    for (int q = 0; q < g.naddr; ++q) g.addr[q] = op.g.addr[q];
+    if (op.g.nbits == 1) {
+      g.code = local(op.g.pos[0]);
+    } else {
+      int b0 = 0, b1 = 0;
+      while (!((op.g.v0 >> b0) & 1)) ++b0;
+      while (!((op.g.v1 >> b1) & 1)) ++b1;
+      g.code = 3 + 3 * local(b0) + local(b1);
+    }
+  }
+  return f;
+}
+
 struct SvWork {
   size_t psi0, psi1, tables, J, partial, norms, bases, total;
 };
@@ -1548,8 +1679,13 @@ rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d
   if (st == RT_OK) st = c->hip(sv_launch_norm2(d_S_in, nfield, J, nfield, partial, norms, s), "sv norm");
   if (st == RT_OK) st = c->hip(sv_launch_encode(psi[0], d_S_in, J, hp.n, L.nd, hp.ny, hp.nx, norms, s), "sv encode");
   int cur = 0;
-  for (size_t i = 0; i < K.ops.size() && st == RT_OK; ++i) {
-    SvOp op = K.ops[i];
+  for (const SvLaunch &l : sv_plan(K, c->sv_fuse)) {
+    if (st != RT_OK) break;
+    if (l.kind == 2) {
+      st = c->hip(sv_launch_fused(psi[cur], L.nq, sv_fuse_of(K, l, tables), s), "sv fused gates");
+      continue;
+    }
+    SvOp op = K.ops[l.ops[0]];
     if (op.shift) {
       op.s.base = bases + op.base_off;
       st = c->hip(sv_launch_shift(psi[cur], psi[cur ^ 1], L.nq, op.s, s), "sv shift");
@@ -1578,22 +1714,28 @@ rt_status rt_sv_gate_count(const rt_ctx *c, int32_t *ngates, int32_t *nshifts, d
   const std::string why = sv_compile(c, z, z, z, &K);
   if (!why.empty()) return set_err(RT_EUNSUPPORTED, why);
   int g = 0, sh = 0;
-  double bytes = 0.0;
-  for (const SvOp &op : K.ops) {
-    if (op.shift) {
-      ++sh;
-      bytes += 16.0 * std::ldexp(1.0, K.L.nq);   // every amplitude read and written once
-    } else {
-      ++g;
-      int fixed = 0;
-      for (int b = 0; b < K.L.nq; ++b) fixed += (int)(((op.g.mask | op.g.cmask) >> b) & 1);
-      // the active pairs: two amplitudes read and written
-      bytes += 32.0 * std::ldexp(1.0, K.L.nq - fixed);
-    }
-  }
+  for (const SvOp &op : K.ops) (op.shift ? sh : g) += 1;
   *ngates = g;
   if (nshifts) *nshifts = sh;
-  if (bytes_per_step) *bytes_per_step = bytes;
+  if (bytes_per_step) *bytes_per_step = sv_plan_bytes(K, sv_plan(K, c->sv_fuse));
+  return RT_OK;
+}
+
+rt_status rt_sv_set_fusion(rt_ctx *c, int32_t max_qubits) {
+  if (!c) return set_err(RT_EINVAL, "context is NULL");
+  if (max_qubits < 0 || max_qubits > kSvFuseMaxQ) return c->fail(RT_EINVAL, "max_qubits must lie in 0 .. 3");
+  c->sv_fuse = max_qubits;
+  return RT_OK;
+}
+
+rt_status rt_sv_launch_count(const rt_ctx *c, int32_t *nlaunches) {
+  if (!c || !nlaunches) return set_err(RT_EINVAL, "NULL argument");
+  const size_t C = (size_t)c->hp.nx * c->hp.ny;
+  std::vector<float> z(C, 0.0f);
+  SvCircuit K;
+  const std::string why = sv_compile(c, z, z, z, &K);
+  if (!why.empty()) return set_err(RT_EUNSUPPORTED, why);
+  *nlaunches = (int32_t)sv_plan(K, c->sv_fuse).size();
   return RT_OK;
 }
 

@@ -33,6 +33,36 @@ struct SvGate {
 };
 hipError_t sv_launch_gate(double *psi, int nq, const SvGate &g, hipStream_t s);
 
+// Consecutive gates whose target qubits lie in one set of m <= 3 qubits
+// (tq, ascending), applied in one pass: each thread loads the 2^m amplitudes
+// that differ only in those qubits, applies the gates in order (for each, the
+// pairs of its target within the set whose control qubits match, with the
+// table entry of their address bits; the same products as sv_launch_gate,
+// so the result is the same to the bit) and stores them.  Control qubits
+// that every gate of the run shares with the same value (outside the target
+// set: ccmask / ccval) are fixed, so the pass visits only those states.  A
+// gate's local code: c in 0 .. m - 1 for a one-qubit gate on tq[c]; for the
+// Q <-> U pair, 3 + 3 a + b with v0 on tq[a] and v1 on tq[b].
+constexpr int kSvFuseMaxQ = 3;
+constexpr int kSvFuseMaxGates = 8;
+struct SvFusedGate {
+  uint64_t cmask, cval;
+  const double *table;
+  int32_t naddr;
+  int32_t addr[kSvMaxAddr];
+  int32_t code;
+};
+struct SvFuse {
+  int32_t m, ngates;
+  int32_t tq[kSvFuseMaxQ];
+  uint64_t ccmask, ccval;
+  // filled by sv_launch_fused: the target and shared control qubits, ascending
+  int32_t nfixed;
+  int32_t fixed[kSvFuseMaxQ + 16];
+  SvFusedGate g[kSvFuseMaxGates];
+};
+hipError_t sv_launch_fused(double *psi, int nq, const SvFuse &f, hipStream_t s);
+
 // Controlled translation of the register bits [r0, r0 + qr) (Eq. 36-38 with
 // the escape marker of Sec. 2.1.7): for live states (sl bit 0), d_out = k
 // (bits [d0, d0 + qd)) and branch bit b, the translation is t = base[k] + b;

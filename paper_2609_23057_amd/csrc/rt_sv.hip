@@ -1,8 +1,9 @@
 // Statevector emulation kernels (gfx950): the gates of the paper's circuit on
-// a real float64 statevector.  Every gate is one pass over the states it
-// touches, so each kernel is bound by HBM traffic (16 bytes read and 16
-// written per active amplitude pair); threads walk the pair space with a
-// grid-stride loop, consecutive threads on consecutive pairs.
+// a real float64 statevector.  A gate alone, or a run of gates on at most 3
+// target qubits, is one pass over the states it touches, so each kernel is
+// bound by HBM traffic (16 bytes read and 16 written per amplitude pair of a
+// gate alone, per amplitude of a fused run); threads walk their index space
+// with a grid-stride loop, consecutive threads on consecutive states.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,6 +46,68 @@ __global__ void __launch_bounds__(kSvThreads) sv_gate_kernel(double *__restrict_
     // products then sums, unfused, as the reference arithmetic does
     psi[i] = u00 * a0 + u01 * a1;
     psi[k] = u10 * a0 + u11 * a1;
+  }
+}
+
+// One pair (i0, i1) of the local amplitudes under gate fg (full index of
+// the local state j: base | spread(j)); compile-time local indices keep amp
+// in registers.
+template <int M>
+__device__ __forceinline__ uint64_t sv_spread(int j, const SvFuse &f) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) v |= (uint64_t)((j >> k) & 1) << f.tq[k];
+  return v;
+}
+
+template <int M, int LV0, int LV1, int LMASK>
+__device__ __forceinline__ void sv_apply_local(double (&amp)[1 << M], uint64_t base, const SvFusedGate &fg,
+                                               const SvFuse &f) {
+#pragma unroll
+  for (int j = 0; j < (1 << M); ++j) {
+    if ((j & LMASK) != 0) continue;
+    const uint64_t full = base | sv_spread<M>(j, f);
+    if ((full & fg.cmask) != fg.cval) continue;
+    uint32_t a = 0;
+    for (int q = 0; q < fg.naddr; ++q) a |= (uint32_t)((full >> fg.addr[q]) & 1) << q;
+    const double u00 = fg.table[4 * a], u01 = fg.table[4 * a + 1];
+    const double u10 = fg.table[4 * a + 2], u11 = fg.table[4 * a + 3];
+    const double a0 = amp[j | LV0], a1 = amp[j | LV1];
+    amp[j | LV0] = u00 * a0 + u01 * a1;
+    amp[j | LV1] = u10 * a0 + u11 * a1;
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(kSvThreads) sv_fused_kernel(double *__restrict__ psi, uint64_t nbases, SvFuse f) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nbases; t += stride) {
+    uint64_t base = t;
+    for (int k = 0; k < f.nfixed; ++k) {
+      const int p = f.fixed[k];
+      base = ((base >> p) << (p + 1)) | (base & ((1ull << p) - 1));
+    }
+    base |= f.ccval;
+    double amp[1 << M];
+#pragma unroll
+    for (int j = 0; j < (1 << M); ++j) amp[j] = psi[base | sv_spread<M>(j, f)];
+    for (int gi = 0; gi < f.ngates; ++gi) {
+      const SvFusedGate &fg = f.g[gi];
+      switch (fg.code) {
+        case 0: sv_apply_local<M, 0, 1, 1>(amp, base, fg, f); break;
+        case 1: if constexpr (M > 1) sv_apply_local<M, 0, 2, 2>(amp, base, fg, f); break;
+        case 2: if constexpr (M > 2) sv_apply_local<M, 0, 4, 4>(amp, base, fg, f); break;
+        case 3 + 3 * 0 + 1: if constexpr (M > 1) sv_apply_local<M, 1, 2, 3>(amp, base, fg, f); break;
+        case 3 + 3 * 1 + 0: if constexpr (M > 1) sv_apply_local<M, 2, 1, 3>(amp, base, fg, f); break;
+        case 3 + 3 * 0 + 2: if constexpr (M > 2) sv_apply_local<M, 1, 4, 5>(amp, base, fg, f); break;
+        case 3 + 3 * 2 + 0: if constexpr (M > 2) sv_apply_local<M, 4, 1, 5>(amp, base, fg, f); break;
+        case 3 + 3 * 1 + 2: if constexpr (M > 2) sv_apply_local<M, 2, 4, 6>(amp, base, fg, f); break;
+        case 3 + 3 * 2 + 1: if constexpr (M > 2) sv_apply_local<M, 4, 2, 6>(amp, base, fg, f); break;
+        default: break;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < (1 << M); ++j) psi[base | sv_spread<M>(j, f)] = amp[j];
   }
 }
 
@@ -170,6 +233,43 @@ hipError_t sv_launch_gate(double *psi, int nq, const SvGate &gate, hipStream_t s
     }
   const uint64_t npairs = 1ull << (nq - g.nfixed);
   hipLaunchKernelGGL(sv_gate_kernel, dim3(sv_grid(npairs)), dim3(kSvThreads), 0, s, psi, npairs, g);
+  return hipGetLastError();
+}
+
+hipError_t sv_launch_fused(double *psi, int nq, const SvFuse &fuse, hipStream_t s) {
+  SvFuse f = fuse;
+  if (f.m < 1 || f.m > kSvFuseMaxQ || f.ngates < 1 || f.ngates > kSvFuseMaxGates || nq > 40 || nq < f.m)
+    return hipErrorInvalidValue;
+  uint64_t tmask = 0;
+  for (int k = 0; k < f.m; ++k) {
+    if (f.tq[k] < 0 || f.tq[k] >= nq || (k > 0 && f.tq[k] <= f.tq[k - 1])) return hipErrorInvalidValue;
+    tmask |= 1ull << f.tq[k];
+  }
+  if ((f.ccmask & tmask) != 0 || (f.ccval & ~f.ccmask) != 0 || (f.ccmask >> nq) != 0) return hipErrorInvalidValue;
+  f.nfixed = 0;
+  for (int b = 0; b < nq; ++b)
+    if (((tmask | f.ccmask) >> b) & 1) {
+      if (f.nfixed == kSvFuseMaxQ + 16) return hipErrorInvalidValue;
+      f.fixed[f.nfixed++] = b;
+    }
+  for (int i = 0; i < f.ngates; ++i) {
+    const SvFusedGate &g = f.g[i];
+    const int c = g.code;
+    const bool one = c >= 0 && c < f.m;
+    const bool two = c >= 3 && c < 12 && (c - 3) / 3 != (c - 3) % 3 && (c - 3) / 3 < f.m && (c - 3) % 3 < f.m;
+    if (!(one || two) || g.naddr < 0 || g.naddr > kSvMaxAddr || (g.cval & ~g.cmask) != 0 || g.cmask >> nq != 0)
+      return hipErrorInvalidValue;
+    // a gate's own target qubits are not among its controls
+    const int ta = one ? c : (c - 3) / 3, tb = one ? c : (c - 3) % 3;
+    if (((g.cmask >> f.tq[ta]) & 1) || ((g.cmask >> f.tq[tb]) & 1)) return hipErrorInvalidValue;
+    for (int q = 0; q < g.naddr; ++q)
+      if (g.addr[q] < 0 || g.addr[q] >= nq) return hipErrorInvalidValue;
+  }
+  const uint64_t nbases = 1ull << (nq - f.nfixed);
+  const dim3 grid(sv_grid(nbases)), block(kSvThreads);
+  if (f.m == 1) hipLaunchKernelGGL(sv_fused_kernel<1>, grid, block, 0, s, psi, nbases, f);
+  if (f.m == 2) hipLaunchKernelGGL(sv_fused_kernel<2>, grid, block, 0, s, psi, nbases, f);
+  if (f.m == 3) hipLaunchKernelGGL(sv_fused_kernel<3>, grid, block, 0, s, psi, nbases, f);
   return hipGetLastError();
 }
 

@@ -135,3 +135,32 @@ def test_refusals():
     with pytest.raises(P.RTError) as ei:
         solver.sv_step(S, work=torch.empty(1024, dtype=torch.uint8, device=solver.device))
     assert ei.value.status == P.RT_ENOMEM
+
+
+@pytest.mark.parametrize("over", SMALL + [dict()], ids=["xy-abs", "periodic", "d2q9-diag", "n3-mixed", "n6", "paper-29q"])
+def test_fused_gate_passes_equal_single_gate_launches(over):
+    """Fusing consecutive gates on at most 1, 2 or 3 target qubits into one
+    pass applies the same products in the same order: the step equals the one
+    that launches every gate alone, to the bit, with fewer launches and
+    fewer statevector bytes."""
+    import paper_2609_23057_amd as P
+    import paper_2609_23057_amd._abi as A
+    spec = W.spec("qlbm16", **over)
+    solver, _ = build(spec)
+    S0 = dev64(W.initial_state(spec, "random"), solver)
+    work = solver.sv_workspace()
+    out = {}
+    for q in (0, 1, 2, 3):
+        A.rt_sv_set_fusion(solver.ctx, q)
+        S, p = solver.sv_step(S0, work=work)
+        out[q] = (S.clone(), p, A.rt_sv_launch_count(solver.ctx), A.rt_sv_gate_count(solver.ctx)[2])
+    for q in (1, 2, 3):
+        assert torch.equal(out[q][0], out[0][0]), q
+        assert out[q][1] == out[0][1], q
+    assert out[3][2] < out[0][2] and out[3][3] < out[0][3]
+    gates, shifts, _ = A.rt_sv_gate_count(solver.ctx)
+    assert out[0][2] == gates + shifts
+    for bad in (-1, 4):
+        with pytest.raises(P.RTError) as ei:
+            A.rt_sv_set_fusion(solver.ctx, bad)
+        assert ei.value.status == P.RT_EINVAL

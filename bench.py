@@ -576,6 +576,33 @@ def profile_run(name, precision, T, adjoint=False):
     `adjoint` the checkpointed forward and adjoint over them."""
     import torch
     import workloads as W
+    if name == "spectral64":
+        # the 64-channel batch: a 2 GiB device copy (the counter calibration),
+        # then T batched forward steps
+        import numpy as np
+        import paper_2609_23057_amd as P
+        specs = W.spectral_channels(64)
+        batch = P.Batch([P.make_problem(**dict(s, precision=precision)) for s in specs])
+        keep = []
+        for ch, s in zip(batch.channels, specs):
+            med = W.medium(s)
+            t = [torch.tensor(np.ascontiguousarray(med[k]), dtype=torch.float32, device=ch.device)
+                 for k in ("tau", "albedo", "emis")]
+            ch.set_medium(*t, med["jprof"], med["inflow"])
+            keep.append(t)
+        a = torch.zeros(1 << 29, dtype=torch.float32, device=batch.device)
+        torch.empty_like(a).copy_(a)
+        del a
+        states = [torch.zeros(ch.shape, device=ch.device) for ch in batch.channels]
+        torch.cuda.synchronize()
+        _log("profile: spectral64 %s, %d forward steps" % (precision, T))
+        batch.run(states, T)
+        torch.cuda.synchronize()
+        cells = [(s["nx"] * s["ny"], W.ndir(s)) for s in specs]
+        print(json.dumps({"profile": name, "precision": precision, "steps": T,
+                          "algorithmic_bytes_per_step": sum(C * (32 * n + 12) for C, n in cells),
+                          "cell_dir_per_step": sum(C * n for C, n in cells)}), flush=True)
+        return
     spec = W.spec(name)
     solver = make_solver(spec, precision)
     S = solver.empty_state()
@@ -606,7 +633,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16", "fp16", "bf16x3"))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--profile", default=None, choices=("beam512", "prec1024", "adjoint256", "beam3d", "qlbm16"),
+    ap.add_argument("--profile", default=None,
+                    choices=("beam512", "prec1024", "adjoint256", "beam3d", "qlbm16", "spectral64"),
                     help="only a short run of this workload in --precision (for rocprofv3 runs)")
     ap.add_argument("--profile-adjoint", action="store_true", help="with --profile: also the adjoint")
     ap.add_argument("--batch-autotune", action="store_true",

@@ -411,9 +411,12 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
  *   max_qubits qubits (0 .. 3; default 3) are applied in one pass over the
  *   statevector (each thread holds the 2^m amplitudes that differ in those
  *   qubits and applies the gates in order) where that moves fewer bytes than
- *   launching them one by one; 0 launches every gate alone.  The products
- *   are the same, so the result does not depend on it.  RT_EINVAL outside
- *   0 .. 3.
+ *   launching them one by one, and with max_qubits >= 1 every launch skips
+ *   the amplitudes known to be zero (an ancilla no gate or translation has
+ *   acted on yet is |0>: it becomes a control fixed to 0); 0 launches every
+ *   gate alone over the whole vector.  The products on every nonzero
+ *   amplitude are the same, so the result does not depend on it.  RT_EINVAL
+ *   outside 0 .. 3.
  * rt_sv_launch_count: launches of gates, fused passes and translations one
  *   step makes with the current fusion setting.
  * rt_sv_step: one emulated step of the context's medium (rt_set_medium must

@@ -1468,12 +1468,18 @@ std::string sv_compile(const rt_ctx *c, const std::vector<float> &tau, const std
 // moves fewer statevector bytes (a gate alone moves the pairs whose control
 // qubits match: 2^(1 - fixed) of the vector, fixed = its target and control
 // qubits; a fused pass moves the states whose shared control qubits match
-// once: 2^-shared of it).
+// once: 2^-shared of it).  With max_q >= 1 the plan also follows the
+// statevector's support: every ancilla starts in |0> (the vector is zeroed
+// before encoding), and until a gate or a translation first acts on it each
+// amplitude with that ancilla at 1 is exactly zero; a launch before then
+// takes the ancilla as a control fixed to 0 and skips those amplitudes (a
+// gate maps a pair of zeros to zeros, so the nonzero amplitudes are the same).
 struct SvLaunch {
   int kind = 0;             // 0 translation, 1 gate, 2 fused run
   std::vector<int> ops;     // indices into SvCircuit::ops
   std::vector<int> tq;      // fused: target qubits, ascending
   uint64_t ccmask = 0, ccval = 0;   // fused: control qubits every gate shares, with their value
+  SvGate g{};               // gate alone: the gate with the untouched ancillas as 0-controls
 };
 
 double sv_gate_fraction(const SvGate &g, int nq) {
@@ -1486,33 +1492,56 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
   std::vector<SvLaunch> out;
   std::vector<int> run;
   std::vector<int> tq;
+  const int nq = K.L.nq;
+  // ancillas not yet acted on (bits ndata .. nq - 1 are the ancillas)
+  uint64_t zero = max_q >= 1 ? (((1ull << nq) - 1) & ~((1ull << K.L.ndata) - 1)) : 0;
+  uint64_t zero_at_run = zero;
+  auto targets = [](const SvGate &g) { return g.mask; };
+  auto alone = [&](int i, uint64_t z) {
+    SvLaunch l;
+    l.kind = 1;
+    l.ops = {i};
+    l.g = K.ops[i].g;
+    l.g.cmask |= z & ~l.g.mask & ~l.g.cmask;   // untouched ancillas: 0-controls
+    out.push_back(l);
+  };
   auto flush = [&]() {
-    double frac = 0.0;
-    for (int i : run) frac += sv_gate_fraction(K.ops[i].g, K.L.nq);
-    // shared controls: the same value in every gate, none of them a target
-    uint64_t cm = ~0ull, tmask = 0;
+    if (run.empty()) return;
+    uint64_t tmask = 0;
     for (int q : tq) tmask |= 1ull << q;
-    for (int i : run) cm &= K.ops[i].g.cmask;
-    if (!run.empty())
-      for (int i : run) cm &= ~(K.ops[i].g.cval ^ K.ops[run[0]].g.cval);
+    // each gate alone, with the ancillas untouched before it as 0-controls
+    double frac = 0.0;
+    {
+      uint64_t z = zero_at_run;
+      for (int i : run) {
+        SvGate g = K.ops[i].g;
+        g.cmask |= z & ~g.mask & ~g.cmask;
+        frac += sv_gate_fraction(g, nq);
+        z &= ~targets(K.ops[i].g);
+      }
+    }
+    // shared controls: the same value in every gate, none of them a target;
+    // then the ancillas no gate of the run acts on, fixed to 0
+    uint64_t cm = ~0ull;
+    for (int i : run) cm &= K.ops[i].g.cmask & ~(K.ops[i].g.cval ^ K.ops[run[0]].g.cval);
     cm &= ~tmask;
-    if (run.empty()) cm = 0;
-    const double fused = std::ldexp(1.0, -__builtin_popcountll(cm));
+    const uint64_t cv = K.ops[run[0]].g.cval & cm;
+    const uint64_t zfix = zero_at_run & ~tmask & ~cm;
+    const double fused = std::ldexp(1.0, -__builtin_popcountll(cm | zfix));
     if (run.size() >= 2 && frac > fused) {
       SvLaunch l;
       l.kind = 2;
       l.ops = run;
       l.tq = tq;
       std::sort(l.tq.begin(), l.tq.end());
-      l.ccmask = cm;
-      l.ccval = K.ops[run[0]].g.cval & cm;
+      l.ccmask = cm | zfix;
+      l.ccval = cv;
       out.push_back(l);
     } else {
+      uint64_t z = zero_at_run;
       for (int i : run) {
-        SvLaunch l;
-        l.kind = 1;
-        l.ops = {i};
-        out.push_back(l);
+        alone(i, z);
+        z &= ~targets(K.ops[i].g);
       }
     }
     run.clear();
@@ -1525,7 +1554,10 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
       SvLaunch l;
       l.kind = 0;
       l.ops = {i};
+      // zero ancillas: their outputs are written without a read
+      l.ccmask = zero & ~(1ull << op.s.ebit) & ~(((1ull << op.s.qr) - 1) << op.s.r0);
       out.push_back(l);
+      zero &= ~(1ull << op.s.ebit);   // the translation marks escapes
       continue;
     }
     std::vector<int> t = tq;
@@ -1538,14 +1570,14 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
     }
     if ((int)t.size() > max_q) {   // max_q 0 (or a pair gate at max_q 1): alone
       flush();
-      SvLaunch l;
-      l.kind = 1;
-      l.ops = {i};
-      out.push_back(l);
+      alone(i, zero);
+      zero &= ~targets(op.g);
       continue;
     }
+    if (run.empty()) zero_at_run = zero;
     run.push_back(i);
     tq = t;
+    zero &= ~targets(op.g);
   }
   flush();
   return out;
@@ -1555,11 +1587,11 @@ double sv_plan_bytes(const SvCircuit &K, const std::vector<SvLaunch> &plan) {
   double bytes = 0.0;
   for (const SvLaunch &l : plan) {
     if (l.kind == 1)
-      bytes += 16.0 * std::ldexp(1.0, K.L.nq) * sv_gate_fraction(K.ops[l.ops[0]].g, K.L.nq);
+      bytes += 16.0 * std::ldexp(1.0, K.L.nq) * sv_gate_fraction(l.g, K.L.nq);
     else if (l.kind == 2)
       bytes += 16.0 * std::ldexp(1.0, K.L.nq - __builtin_popcountll(l.ccmask));   // the visited states once
-    else
-      bytes += 16.0 * std::ldexp(1.0, K.L.nq);   // every amplitude read and written once
+    else   // every amplitude written, those outside the zero qubits read
+      bytes += std::ldexp(1.0, K.L.nq) * (8.0 + 8.0 * std::ldexp(1.0, -__builtin_popcountll(l.ccmask)));
   }
   return bytes;
 }
@@ -1688,11 +1720,13 @@ rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d
     SvOp op = K.ops[l.ops[0]];
     if (op.shift) {
       op.s.base = bases + op.base_off;
+      op.s.zmask = l.ccmask;
       st = c->hip(sv_launch_shift(psi[cur], psi[cur ^ 1], L.nq, op.s, s), "sv shift");
       cur ^= 1;
     } else {
-      op.g.table = tables + op.table_off;
-      st = c->hip(sv_launch_gate(psi[cur], L.nq, op.g, s), "sv gate");
+      SvGate g = l.g;
+      g.table = tables + op.table_off;
+      st = c->hip(sv_launch_gate(psi[cur], L.nq, g, s), "sv gate");
     }
   }
   const uint64_t nblock = 1ull << L.ndata;

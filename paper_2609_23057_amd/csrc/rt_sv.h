@@ -29,7 +29,7 @@ struct SvGate {
   // filled by sv_launch_gate: the mask and control bits in ascending order;
   // threads enumerate only the states whose control bits match
   int32_t nfixed;
-  int32_t fixed[8];
+  int32_t fixed[24];
 };
 hipError_t sv_launch_gate(double *psi, int nq, const SvGate &g, hipStream_t s);
 
@@ -72,6 +72,9 @@ hipError_t sv_launch_fused(double *psi, int nq, const SvFuse &f, hipStream_t s);
 struct SvShift {
   int32_t r0, qr, ebit, abit, slbit, d0, qd, periodic;
   const int32_t *base;   // [2^qd]
+  // qubits (none of them the escape marker) at which every amplitude of
+  // `in` with a 1 is zero: such outputs are written as zero without a read
+  uint64_t zmask;
 };
 hipError_t sv_launch_shift(const double *in, double *out, int nq, const SvShift &t, hipStream_t s);
 

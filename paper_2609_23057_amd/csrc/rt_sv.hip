@@ -117,6 +117,10 @@ __global__ void __launch_bounds__(kSvThreads) sv_shift_kernel(const double *__re
   const int64_t size = 1ll << s.qr;
   const uint64_t rmask = (uint64_t)(size - 1) << s.r0;
   for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nstates; o += stride) {
+    if ((o & s.zmask) != 0) {   // its source has the same zero qubit
+      out[o] = 0.0;
+      continue;
+    }
     uint64_t src = o;
     if (((o >> s.slbit) & 1) == 0) {
       const int64_t r = (int64_t)((o >> s.r0) & (uint64_t)(size - 1));
@@ -228,7 +232,7 @@ hipError_t sv_launch_gate(double *psi, int nq, const SvGate &gate, hipStream_t s
   g.nfixed = 0;
   for (int b = 0; b < nq; ++b)
     if (((g.mask | g.cmask) >> b) & 1) {
-      if (g.nfixed == 8) return hipErrorInvalidValue;
+      if (g.nfixed == 24) return hipErrorInvalidValue;
       g.fixed[g.nfixed++] = b;
     }
   const uint64_t npairs = 1ull << (nq - g.nfixed);
@@ -275,6 +279,9 @@ hipError_t sv_launch_fused(double *psi, int nq, const SvFuse &fuse, hipStream_t 
 
 hipError_t sv_launch_shift(const double *in, double *out, int nq, const SvShift &t, hipStream_t s) {
   if (nq > 40 || t.qr < 1 || t.qd < 1) return hipErrorInvalidValue;
+  // the zero qubits lie outside the translated register and the escape marker
+  const uint64_t moved = (((1ull << t.qr) - 1) << t.r0) | (1ull << t.ebit);
+  if ((t.zmask & moved) != 0 || (t.zmask >> nq) != 0) return hipErrorInvalidValue;
   const uint64_t n = 1ull << nq;
   hipLaunchKernelGGL(sv_shift_kernel, dim3(sv_grid(n)), dim3(kSvThreads), 0, s, in, out, n, t);
   return hipGetLastError();

@@ -140,9 +140,11 @@ def test_refusals():
 @pytest.mark.parametrize("over", SMALL + [dict()], ids=["xy-abs", "periodic", "d2q9-diag", "n3-mixed", "n6", "paper-29q"])
 def test_fused_gate_passes_equal_single_gate_launches(over):
     """Fusing consecutive gates on at most 1, 2 or 3 target qubits into one
-    pass applies the same products in the same order: the step equals the one
-    that launches every gate alone, to the bit, with fewer launches and
-    fewer statevector bytes."""
+    pass, and skipping the amplitudes that untouched ancillas keep at zero,
+    applies the same products in the same order to every nonzero amplitude:
+    the step equals the one that launches every gate alone over the whole
+    vector value for value (a skipped zero may keep its sign), with fewer
+    launches and fewer statevector bytes."""
     import paper_2609_23057_amd as P
     import paper_2609_23057_amd._abi as A
     spec = W.spec("qlbm16", **over)

@@ -485,9 +485,8 @@ def statevector_extras(T=4, warm=1):
            "success_probability": probs,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes,
-                        "note": "statevector bytes of the launches (32 per active amplitude pair of a gate "
-                                "launched alone, 16 per amplitude of a fused gate pass or a translation) over "
-                                "the whole step time"},
+                        "note": "statevector bytes the launches read and write (8 per amplitude; amplitudes "
+                                "known to be zero are not read) over the whole step time"},
            "max_abs_diff_vs_classical": float(np.abs(got - ref).max()),
            "rel_l2_diff_vs_classical": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
     del work, solver

@@ -404,9 +404,10 @@ rt_status rt_readout(rt_ctx *c, const float *d_S, int32_t edge, float *d_out, do
  *   (rt_last_error says why).
  * rt_sv_gate_count: gates (rotations, controlled X/Z, H and the Q-U
  *   rotations) and translations of one step, and (if not NULL) the
- *   statevector bytes their launches move: 32 per active amplitude pair of a
- *   gate launched alone (the states whose control qubits match), 16 per
- *   amplitude of a translation or of a fused pass.
+ *   statevector bytes their launches read and write, 8 per amplitude (a
+ *   gate launched alone touches the pairs whose control qubits match; a
+ *   fused pass or a translation the states its fixed qubits select;
+ *   amplitudes known to be zero are written, not read).
  * rt_sv_set_fusion: consecutive gates whose target qubits lie within
  *   max_qubits qubits (0 .. 3; default 3) are applied in one pass over the
  *   statevector (each thread holds the 2^m amplitudes that differ in those

@@ -1474,11 +1474,17 @@ std::string sv_compile(const rt_ctx *c, const std::vector<float> &tau, const std
 // amplitude with that ancilla at 1 is exactly zero; a launch before then
 // takes the ancilla as a control fixed to 0 and skips those amplitudes (a
 // gate maps a pair of zeros to zeros, so the nonzero amplitudes are the same).
+// Such an amplitude is then never read at all: the planned step does not
+// zero the vector but encodes the whole data block (every ancilla 0), and
+// the first launch on an ancilla takes its 1 half as zero instead of
+// reading it, then writes both halves.
 struct SvLaunch {
   int kind = 0;             // 0 translation, 1 gate, 2 fused run
   std::vector<int> ops;     // indices into SvCircuit::ops
   std::vector<int> tq;      // fused: target qubits, ascending
   uint64_t ccmask = 0, ccval = 0;   // fused: control qubits every gate shares, with their value
+  int zlocal = 0;           // fused: local states with a never-written target at 1
+  int ezero = 0;            // translation: its escape marker never set before
   SvGate g{};               // gate alone: the gate with the untouched ancillas as 0-controls
 };
 
@@ -1503,6 +1509,7 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
     l.ops = {i};
     l.g = K.ops[i].g;
     l.g.cmask |= z & ~l.g.mask & ~l.g.cmask;   // untouched ancillas: 0-controls
+    l.g.zread = l.g.mask & z;                   // a target's 1 half never written yet
     out.push_back(l);
   };
   auto flush = [&]() {
@@ -1536,6 +1543,8 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
       std::sort(l.tq.begin(), l.tq.end());
       l.ccmask = cm | zfix;
       l.ccval = cv;
+      for (int k = 0; k < (int)l.tq.size(); ++k)
+        if ((zero_at_run >> l.tq[k]) & 1) l.zlocal |= 1 << k;
       out.push_back(l);
     } else {
       uint64_t z = zero_at_run;
@@ -1556,6 +1565,7 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
       l.ops = {i};
       // zero ancillas: their outputs are written without a read
       l.ccmask = zero & ~(1ull << op.s.ebit) & ~(((1ull << op.s.qr) - 1) << op.s.r0);
+      l.ezero = (int)((zero >> op.s.ebit) & 1);
       out.push_back(l);
       zero &= ~(1ull << op.s.ebit);   // the translation marks escapes
       continue;
@@ -1583,15 +1593,31 @@ std::vector<SvLaunch> sv_plan(const SvCircuit &K, int max_q) {
   return out;
 }
 
+// Statevector bytes the launches of a plan move: 8 per amplitude read or
+// written (amplitudes taken as zero are not read; a translation's reads of
+// never-marked sources are not counted, nor are the few that an absorbing
+// edge still makes).
 double sv_plan_bytes(const SvCircuit &K, const std::vector<SvLaunch> &plan) {
+  const int nq = K.L.nq;
   double bytes = 0.0;
   for (const SvLaunch &l : plan) {
-    if (l.kind == 1)
-      bytes += 16.0 * std::ldexp(1.0, K.L.nq) * sv_gate_fraction(l.g, K.L.nq);
-    else if (l.kind == 2)
-      bytes += 16.0 * std::ldexp(1.0, K.L.nq - __builtin_popcountll(l.ccmask));   // the visited states once
-    else   // every amplitude written, those outside the zero qubits read
-      bytes += std::ldexp(1.0, K.L.nq) * (8.0 + 8.0 * std::ldexp(1.0, -__builtin_popcountll(l.ccmask)));
+    if (l.kind == 1) {
+      int fixed = 0;
+      for (int b = 0; b < nq; ++b) fixed += (int)(((l.g.mask | l.g.cmask) >> b) & 1);
+      const double pairs = std::ldexp(1.0, nq - fixed);
+      const int zr = (int)((l.g.zread & l.g.v1) != 0) + (int)((l.g.zread & l.g.v0) != 0);
+      bytes += pairs * 8.0 * (2 + 2 - zr);
+    } else if (l.kind == 2) {
+      uint64_t fixedmask = l.ccmask;
+      for (int q : l.tq) fixedmask |= 1ull << q;
+      const int m = (int)l.tq.size();
+      int reads = 0;
+      for (int j = 0; j < (1 << m); ++j) reads += (j & l.zlocal) ? 0 : 1;
+      bytes += std::ldexp(1.0, nq - __builtin_popcountll(fixedmask)) * 8.0 * ((1 << m) + reads);
+    } else {
+      const double read = std::ldexp(1.0, -__builtin_popcountll(l.ccmask)) * (l.ezero ? 0.5 : 1.0);
+      bytes += std::ldexp(1.0, nq) * 8.0 * (1.0 + read);
+    }
   }
   return bytes;
 }
@@ -1604,6 +1630,7 @@ SvFuse sv_fuse_of(const SvCircuit &K, const SvLaunch &l, const double *tables) {
   for (int k = 0; k < f.m; ++k) f.tq[k] = l.tq[k];
   f.ccmask = l.ccmask;
   f.ccval = l.ccval;
+  f.zlocal = l.zlocal;
   auto local = [&](int q) { return (int)(std::find(l.tq.begin(), l.tq.end(), q) - l.tq.begin()); };
   for (int j = 0; j < f.ngates; ++j) {
     const SvOp &op = K.ops[l.ops[j]];
@@ -1707,9 +1734,16 @@ rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d
   if (st == RT_OK && !K.bases.empty())
     st = c->hip(hipMemcpyAsync(bases, K.bases.data(), K.bases.size() * 4, hipMemcpyHostToDevice, s), "sv bases");
   const uint64_t nstates = 1ull << L.nq, nfield = (uint64_t)hp.n * 4 * C;
-  if (st == RT_OK) st = c->hip(sv_launch_zero(psi[0], nstates, s), "sv zero");
+  // the planned step (fusion on) never reads an amplitude it has not
+  // written, so it only encodes the data block; launching every gate over the
+  // whole vector needs the vector zeroed
+  const bool planned = c->sv_fuse >= 1;
+  if (st == RT_OK && !planned) st = c->hip(sv_launch_zero(psi[0], nstates, s), "sv zero");
   if (st == RT_OK) st = c->hip(sv_launch_norm2(d_S_in, nfield, J, nfield, partial, norms, s), "sv norm");
-  if (st == RT_OK) st = c->hip(sv_launch_encode(psi[0], d_S_in, J, hp.n, L.nd, hp.ny, hp.nx, norms, s), "sv encode");
+  if (st == RT_OK)
+    st = c->hip(planned ? sv_launch_encode_block(psi[0], d_S_in, J, hp.n, L.nd, hp.ny, hp.nx, norms, s)
+                        : sv_launch_encode(psi[0], d_S_in, J, hp.n, L.nd, hp.ny, hp.nx, norms, s),
+                "sv encode");
   int cur = 0;
   for (const SvLaunch &l : sv_plan(K, c->sv_fuse)) {
     if (st != RT_OK) break;
@@ -1721,6 +1755,7 @@ rt_status rt_sv_step(rt_ctx *c, void *d_work, size_t work_bytes, const double *d
     if (op.shift) {
       op.s.base = bases + op.base_off;
       op.s.zmask = l.ccmask;
+      op.s.ezero = l.ezero;
       st = c->hip(sv_launch_shift(psi[cur], psi[cur ^ 1], L.nq, op.s, s), "sv shift");
       cur ^= 1;
     } else {

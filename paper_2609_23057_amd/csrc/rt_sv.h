@@ -26,6 +26,9 @@ struct SvGate {
   int32_t naddr;
   int32_t addr[kSvMaxAddr];
   const double *table;
+  // mask qubits whose 1 half has never been written (an ancilla no launch
+  // has acted on): that member of each pair is taken as zero, not read
+  uint64_t zread;
   // filled by sv_launch_gate: the mask and control bits in ascending order;
   // threads enumerate only the states whose control bits match
   int32_t nfixed;
@@ -56,6 +59,7 @@ struct SvFuse {
   int32_t m, ngates;
   int32_t tq[kSvFuseMaxQ];
   uint64_t ccmask, ccval;
+  int32_t zlocal;   // local states with a never-written target qubit at 1: taken as zero, not read
   // filled by sv_launch_fused: the target and shared control qubits, ascending
   int32_t nfixed;
   int32_t fixed[kSvFuseMaxQ + 16];
@@ -75,6 +79,9 @@ struct SvShift {
   // qubits (none of them the escape marker) at which every amplitude of
   // `in` with a 1 is zero: such outputs are written as zero without a read
   uint64_t zmask;
+  // the escape marker has never been set: a source with it at 1 is zero
+  // (never written), not read
+  int32_t ezero;
 };
 hipError_t sv_launch_shift(const double *in, double *out, int nq, const SvShift &t, hipStream_t s);
 
@@ -89,6 +96,11 @@ hipError_t sv_launch_norm2(const double *a, uint64_t na, const double *b, uint64
 // Amplitude encoding (Eq. 4): psi (zeroed) receives S[d][st][y][x] / norm at
 // (st, sl = 0, d_in = d_out = d, y, x) and J[d][st][y][x] / norm at sl = 1,
 // norm = sqrt(*norm2); data index ((((st 2 + sl) nd + d_in) nd + d_out) ny + y) nx + x.
+// The same encoding written over the whole data block (the 2^ndata states
+// with every ancilla at 0, zeros included), for a vector that is not zeroed
+// first.
+hipError_t sv_launch_encode_block(double *psi, const double *S, const double *J, int n, int nd, int ny, int nx,
+                                  const double *norm2, hipStream_t s);
 hipError_t sv_launch_encode(double *psi, const double *S, const double *J, int n, int nd, int ny, int nx,
                             const double *norm2, hipStream_t s);
 

@@ -42,7 +42,8 @@ __global__ void __launch_bounds__(kSvThreads) sv_gate_kernel(double *__restrict_
     const double u00 = g.table[4 * a], u01 = g.table[4 * a + 1];
     const double u10 = g.table[4 * a + 2], u11 = g.table[4 * a + 3];
     const uint64_t i = base | g.v0, k = base | g.v1;
-    const double a0 = psi[i], a1 = psi[k];
+    const double a0 = (g.v0 & g.zread) ? 0.0 : psi[i];
+    const double a1 = (g.v1 & g.zread) ? 0.0 : psi[k];
     // products then sums, unfused, as the reference arithmetic does
     psi[i] = u00 * a0 + u01 * a1;
     psi[k] = u10 * a0 + u11 * a1;
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_fused_kernel(double *__restrict
     base |= f.ccval;
     double amp[1 << M];
 #pragma unroll
-    for (int j = 0; j < (1 << M); ++j) amp[j] = psi[base | sv_spread<M>(j, f)];
+    for (int j = 0; j < (1 << M); ++j) amp[j] = (j & f.zlocal) ? 0.0 : psi[base | sv_spread<M>(j, f)];
     for (int gi = 0; gi < f.ngates; ++gi) {
       const SvFusedGate &fg = f.g[gi];
       switch (fg.code) {
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_shift_kernel(const double *__re
       }
       src = (o & ~rmask & ~(1ull << s.ebit)) | ((uint64_t)rs << s.r0) | ((uint64_t)es << s.ebit);
     }
-    out[o] = in[src];
+    out[o] = (s.ezero && ((src >> s.ebit) & 1)) ? 0.0 : in[src];
   }
 }
 
@@ -204,6 +205,36 @@ __global__ void sv_encode_kernel(double *__restrict__ psi, const double *__restr
     const int d = (int)(i / ((uint64_t)nx * ny * 4));
     psi[data_index(st, 0, d, d, y, x, nd, ny, nx)] = norm > 0.0 ? S[i] / norm : 0.0;
     psi[data_index(st, 1, d, d, y, x, nd, ny, nx)] = norm > 0.0 ? J[i] / norm : 0.0;
+  }
+}
+
+// Every state of the data block (index < 2^ndata: all ancillas 0):
+// (st, sl, d_in, d_out, y, x) from the index, the encoded value where
+// d_in = d_out < n, else zero.
+__global__ void sv_encode_block_kernel(double *__restrict__ psi, const double *__restrict__ S,
+                                       const double *__restrict__ J, int n, int nd, int ny, int nx,
+                                       const double *__restrict__ norm2) {
+  const uint64_t total = (uint64_t)8 * nd * nd * ny * nx;
+  const double norm = sqrt(*norm2);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    uint64_t r = i;
+    const int x = (int)(r % nx);
+    r /= nx;
+    const int y = (int)(r % ny);
+    r /= ny;
+    const int dout = (int)(r % nd);
+    r /= nd;
+    const int din = (int)(r % nd);
+    r /= nd;
+    const int sl = (int)(r % 2);
+    const int st = (int)(r / 2);
+    double v = 0.0;
+    if (din == dout && din < n && norm > 0.0) {
+      const uint64_t f = (((uint64_t)din * 4 + st) * ny + y) * nx + x;
+      v = (sl == 0 ? S[f] : J[f]) / norm;
+    }
+    psi[i] = v;
   }
 }
 
@@ -305,6 +336,14 @@ hipError_t sv_launch_encode(double *psi, const double *S, const double *J, int n
                             const double *norm2, hipStream_t s) {
   const uint64_t total = (uint64_t)n * 4 * ny * nx;
   hipLaunchKernelGGL(sv_encode_kernel, dim3(sv_grid(total)), dim3(kSvThreads), 0, s, psi, S, J, n, nd, ny, nx,
+                     norm2);
+  return hipGetLastError();
+}
+
+hipError_t sv_launch_encode_block(double *psi, const double *S, const double *J, int n, int nd, int ny, int nx,
+                                  const double *norm2, hipStream_t s) {
+  const uint64_t total = (uint64_t)8 * nd * nd * ny * nx;
+  hipLaunchKernelGGL(sv_encode_block_kernel, dim3(sv_grid(total)), dim3(kSvThreads), 0, s, psi, S, J, n, nd, ny, nx,
                      norm2);
   return hipGetLastError();
 }

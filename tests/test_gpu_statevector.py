@@ -113,7 +113,9 @@ def test_paper_lattice_has_29_qubits_and_the_gate_count():
     assert (nq, nd) == (29, 17)
     gates, shifts, nbytes = A.rt_sv_gate_count(solver.ctx)
     assert shifts == 2 and gates > 20
-    assert 2 * 16 * (1 << 29) < nbytes < (gates + 2) * 16 * (1 << 29)
+    # the two translations write every amplitude (8 bytes each); no launch
+    # moves more than a read and a write of the whole vector
+    assert 2 * 8 * (1 << 29) < nbytes < (gates + 2) * 16 * (1 << 29)
     assert A.rt_sv_workspace_bytes(solver.ctx) >= 2 * 8 * (1 << 29)
 
 
@@ -144,7 +146,9 @@ def test_fused_gate_passes_equal_single_gate_launches(over):
     applies the same products in the same order to every nonzero amplitude:
     the step equals the one that launches every gate alone over the whole
     vector value for value (a skipped zero may keep its sign), with fewer
-    launches and fewer statevector bytes."""
+    launches and fewer statevector bytes.  The planned step encodes only the
+    data block instead of zeroing the vector; a workspace full of NaN shows
+    that it never reads what it has not written."""
     import paper_2609_23057_amd as P
     import paper_2609_23057_amd._abi as A
     spec = W.spec("qlbm16", **over)
@@ -154,6 +158,9 @@ def test_fused_gate_passes_equal_single_gate_launches(over):
     out = {}
     for q in (0, 1, 2, 3):
         A.rt_sv_set_fusion(solver.ctx, q)
+        # every byte of the workspace NaN: the planned step (q >= 1) does not
+        # zero the vector and must read no amplitude it has not written
+        work.fill_(255)
         S, p = solver.sv_step(S0, work=work)
         out[q] = (S.clone(), p, A.rt_sv_launch_count(solver.ctx), A.rt_sv_gate_count(solver.ctx)[2])
     for q in (1, 2, 3):

@@ -694,7 +694,8 @@ rt_status rt_set_phase_mixture_k(rt_ctx *c, int32_t k, const int32_t *phase, con
   std::vector<TileRange> tiles((size_t)k * ntile), tiles_adj((size_t)k * ntile);
   std::vector<uint8_t> frag((size_t)k * fb), frag_adj((size_t)k * fb), frag_lo((size_t)k * lob),
       frag_adj_lo((size_t)k * lob);
-  std::vector<float> MT;
+  const int R = c->hp.R;
+  std::vector<float> MT(plain ? (size_t)k * R * R : 0);   // float32 M_j transposed, as the plain collision reads M
   for (int j = 0; j < k; ++j) {
     const std::string which = "further phase function " + std::to_string(j) + ": ";
     if (phase[j] == RT_PHASE_TABLE) return c->fail(RT_EINVAL, which + "a mixture component cannot be a table");
@@ -711,9 +712,7 @@ rt_status rt_set_phase_mixture_k(rt_ctx *c, int32_t k, const int32_t *phase, con
     const rt_status st = build_plan(&pj, &hpj, &msg);
     if (st != RT_OK) return c->fail(st, which + msg);
     if (plain) {
-      // float32 M_j transposed, as the plain collision reads M
-      const int R = hpj.R;
-      MT.resize((size_t)k * R * R);
+      if (hpj.R != R) return c->fail(RT_EINVAL, which + "matrix size differs from the context's");
       float *dst = MT.data() + (size_t)j * R * R;
       for (int r = 0; r < R; ++r)
         for (int q = 0; q < R; ++q) dst[(size_t)q * R + r] = (float)hpj.M[(size_t)r * R + q];
@@ -1469,15 +1468,15 @@ std::string sv_compile(const rt_ctx *c, const std::vector<float> &tau, const std
 // qubits match: 2^(1 - fixed) of the vector, fixed = its target and control
 // qubits; a fused pass moves the states whose shared control qubits match
 // once: 2^-shared of it).  With max_q >= 1 the plan also follows the
-// statevector's support: every ancilla starts in |0> (the vector is zeroed
-// before encoding), and until a gate or a translation first acts on it each
-// amplitude with that ancilla at 1 is exactly zero; a launch before then
-// takes the ancilla as a control fixed to 0 and skips those amplitudes (a
-// gate maps a pair of zeros to zeros, so the nonzero amplitudes are the same).
-// Such an amplitude is then never read at all: the planned step does not
-// zero the vector but encodes the whole data block (every ancilla 0), and
-// the first launch on an ancilla takes its 1 half as zero instead of
-// reading it, then writes both halves.
+// statevector's support: the encoded state has every ancilla in |0>, and
+// until a gate or a translation first acts on an ancilla each amplitude with
+// it at 1 is zero; a launch before then takes the ancilla as a control fixed
+// to 0 and skips those amplitudes (a gate maps a pair of zeros to zeros, so
+// the nonzero amplitudes get the same products).  Such an amplitude is never
+// read at all: the planned step does not zero the vector but writes the
+// whole data block (every ancilla 0) when it encodes, and the first launch on
+// an ancilla takes its 1 half as zero instead of reading it, then writes both
+// halves.
 struct SvLaunch {
   int kind = 0;             // 0 translation, 1 gate, 2 fused run
   std::vector<int> ops;     // indices into SvCircuit::ops

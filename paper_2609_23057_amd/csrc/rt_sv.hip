@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_shift_kernel(const double *__re
       const int e = (int)((o >> s.ebit) & 1);
       const int k = (int)((o >> s.d0) & ((1u << s.qd) - 1));
       const int64_t t = (int64_t)s.base[k] + (int64_t)((o >> s.abit) & 1);
-      const int64_t back = ((r - t) % size + size) % size;   // (r - t) mod size
+      const int64_t back = (r - t) & (size - 1);   // (r - t) mod size (size a power of two)
       int64_t rs = r;
       int es = e;
       if (s.periodic) {

@@ -584,14 +584,14 @@ struct LdsLayout {
 // writes and the epilogue reads back (the B tile itself for the forward
 // float32 contraction), and the cross-wave reduction scratch (fp16 scales,
 // adjoint per-cell sums).  After the groups, one copy of the emission rows.
-// With nb = 2 and a bf16 contraction, X is not kept in float32: it is held
-// as a high part (the B tile) and a low part (a second tile of the same
+// With xsplit (nb = 2, a bf16 contraction in 16-wave blocks, where a float32
+// X tile would not fit beside the B tile), X is not kept in float32: it is
+// held as a high part (the B tile) and a low part (a second tile of the same
 // shape) whose sum restores it to 2^-18.
 __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, int W, bool adjoint,
                                                bool f16, int ngroups = 1, int nb = 1, int nacc = 3,
-                                               bool w3 = false) {
+                                               bool w3 = false, bool xsplit = false) {
   LdsLayout L;
-  const bool xsplit = nb > 1 && esize == 2;
   // the bf16 / bf16x3 adjoint keeps mu as high (B) and low tiles
   const bool musplit = adjoint && esize == 2 && !f16;
   int off = 0;
@@ -621,13 +621,20 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
 }
 
 // Cells per tile of a single-problem step: 64 (two 32-cell column blocks
-// that share every A fragment) for the float32 forward step and, with more
-// than 8 row tiles (n > 64), the bf16 forward step; 32 otherwise (bf16x3
-// needs its float32 X tile, fp16 the whole cell for its scale before it can
-// split X, and bf16 at n <= 64 keeps the spectral batch's X arithmetic).
-// The float32 64-cell tile performs the 32-cell tile's arithmetic per cell.
+// that share every A fragment) for the float32 forward step and for the bf16
+// forward step with at most 4 row tiles (n <= 32) or more than 8 (n > 64);
+// 32 otherwise (bf16x3 needs its float32 X tile, fp16 the whole cell for its
+// scale before it can split X, and bf16 at 32 < n <= 64 keeps the float32 X
+// tile, which two column blocks of 8 row tiles would hold at one block per
+// CU).  Up to 4 row tiles the 64-cell tile performs the 32-cell tile's
+// arithmetic per cell, so the spectral batch's 32-cell tiles give the same
+// bits.
+// X as high + low bf16 tiles: the bf16 64-cell tile of the 16-wave blocks.
+template <int PREC, int MAXW, int NB>
+constexpr bool kXSplit = NB > 1 && PREC == P_BF16 && MAXW > 4;
+
 __host__ __device__ inline int step_nb(int W, int prec, bool adjoint) {
-  return (!adjoint && ((W > 8 && prec == P_BF16) || prec == P_F32)) ? 2 : 1;
+  return (!adjoint && (prec == P_F32 || (prec == P_BF16 && (W <= 4 || W > 8)))) ? 2 : 1;
 }
 
 // Lane-record offset (before adding the lane) of the A fragments of K step s
@@ -668,7 +675,8 @@ __device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red
   return (m > 0.0f) ? ldexpf(1.0f, 8 - e) : 1.0f;
 }
 
-template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone, bool G3 = false>
+template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone, bool G3 = false,
+          bool XSPLIT = false>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
                                            int64_t tile, bool active, int t, int wg, int W, int lane) {
@@ -682,8 +690,9 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   // adjoint per-cell sums: <mu, X_d>, <nu, X_d>, the emission term, and with
   // dichroic absorption the xi-derivative term
   constexpr int NACC = (ADJ && DICH) ? 4 : 3;
-  // bf16 contraction with two column blocks: X lives as high + low tiles
-  constexpr bool XSPLIT = NB > 1 && PREC == P_BF16;
+  // XSPLIT (bf16 contraction with two column blocks in 16-wave blocks): X
+  // lives as high + low tiles; otherwise X is a float32 tile
+  static_assert(!XSPLIT || (NB > 1 && PREC == P_BF16), "X split: bf16 with two column blocks");
   const int col = lane & 31;
   const int h = lane >> 5;
   char *s_b = ts.s_b;
@@ -878,9 +887,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
   // ---- 2. B operand: the contraction input in its precision ------------------
   // forward: X, adjoint: mu (both already in place for float32; X also for the
   // split tiles, mu for the bf16 / bf16x3 adjoint).
-  if constexpr (NB == 1 && !MUSPLIT) {
+  if constexpr (!XSPLIT && !MUSPLIT) {
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
     if (PREC != P_F32) {
-      char *xrow = s_x + col * L.strideX + rbase * 4;
+      char *xrow = s_x + (32 * cb + col) * L.strideX + rbase * 4;
       float v[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -894,7 +905,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       }
       // per-cell power-of-two scale for fp16 operands (max over all rows)
       if (PREC == P_F16) cscale[0] = f16_cell_scale(v, s_red, wg, W, col, h);
-      char *brow = s_b + col * L.strideB;
+      char *brow = s_b + (32 * cb + col) * L.strideB;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r0 = rbase + q * 8;
@@ -918,6 +929,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
           *reinterpret_cast<f16x4 *>(brow + r0 * 2) = hv;
         }
       }
+    }
     }
   }
   __syncthreads();
@@ -1178,7 +1190,7 @@ inline hipError_t resident_blocks(const void *k, int threads, int lds, std::atom
 // for the larger blocks (n > 32) the register budget of 16 waves per CU
 // leaves 2 steps for the fp16 forward contraction and 1 otherwise.
 template <int PREC, bool ADJ, int MAXW, int NB>
-constexpr int kFusedRing = MAXW <= 4 ? ((ADJ && (PREC == P_BF16 || PREC == P_BF16X3)) ? 2 : 4)
+constexpr int kFusedRing = MAXW <= 4 ? (((ADJ && (PREC == P_BF16 || PREC == P_BF16X3)) || (NB > 1 && PREC == P_BF16)) ? 2 : 4)
                                      : ((!ADJ && PREC == P_F16) ? 2 : 1);
 
 // Waves per SIMD the register allocation must allow: 4 for the fp32 and bf16
@@ -1200,7 +1212,7 @@ fused_kernel(StepArgs a, int64_t ntiles) {
   const int w = threadIdx.x >> 6;
   const int h = lane >> 5;
   const LdsLayout L = lds_layout(g.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB,
-                                 (ADJ && EXT == kExtDich) ? 4 : 3, G3);
+                                 (ADJ && EXT == kExtDich) ? 4 : 3, G3, kXSplit<PREC, MAXW, NB>);
   float *s_jrow = reinterpret_cast<float *>(smem + L.jrow_off);
   for (int i = threadIdx.x; i < g.Rpad; i += blockDim.x) s_jrow[i] = a.jrow[i];
   float *s_w3 = reinterpret_cast<float *>(smem + L.w3_off);
@@ -1236,8 +1248,8 @@ fused_kernel(StepArgs a, int64_t ntiles) {
     // which would not fit in VGPRs, without holding a second copy.
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT, G3>(a, g, L, ts, tr, ldk, tile,
-                                                                                    true, t, t, W, lane);
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT, G3, kXSplit<PREC, MAXW, NB>>(
+        a, g, L, ts, tr, ldk, tile, true, t, t, W, lane);
   }
 }
 
@@ -1476,7 +1488,7 @@ template <int PREC, bool GATHER, bool ADJ, bool CKPT, int MAXW, int NB, int EXT 
 hipError_t launch_fused_k(const StepArgs &a, int W, hipStream_t s, int cu_count) {
   using T = PrecTraits<PREC>;
   const LdsLayout L = lds_layout(a.geo.Rpad, T::esize, T::ntile, W, ADJ, PREC == P_F16, 1, NB,
-                                 (ADJ && EXT == kExtDich) ? 4 : 3, G3);
+                                 (ADJ && EXT == kExtDich) ? 4 : 3, G3, kXSplit<PREC, MAXW, NB>);
   if (L.total > 160 * 1024) return hipErrorInvalidValue;
   // 3-D: whole tiles per row (ny3 nz rows)
   const int64_t ntiles = G3 ? (int64_t)((a.geo.nx + 32 * NB - 1) / (32 * NB)) * a.ny3 * a.nz
@@ -1527,7 +1539,7 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count)
   }
   if (a.dich_xi != nullptr) {
     // dichroic absorption: the adjoint on 32-cell tiles; forward steps on the
-    // tiles of the plain step
+    // tiles of the plain step (bf16 in blocks of up to 4 waves: 32-cell tiles)
     if constexpr (ADJ) {
       if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
       return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtDich>(a, W, s, cu_count);
@@ -1544,7 +1556,8 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count)
     return hipErrorInvalidValue;
   }
   if (W <= 4) {
-    if constexpr (!ADJ && PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2>(a, W, s, cu_count);
+    if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16))
+      return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2>(a, W, s, cu_count);
     return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1>(a, W, s, cu_count);
   }
   if constexpr (!ADJ && (PREC == P_F32 || PREC == P_BF16)) {
@@ -2207,8 +2220,9 @@ size_t step_lds_bytes(const Geometry &g, int prec, bool adjoint, bool dich, bool
   const int esize = prec == P_F32 ? 4 : 2;
   const int ntile = prec == P_BF16X3 ? 2 : 1;
   const int W = g.Rpad / 32;
-  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, W, adjoint, prec == P_F16, 1, step_nb(W, prec, adjoint),
-                                 adjoint && dich ? 4 : 3, three_d && !adjoint);
+  const int nb = step_nb(W, prec, adjoint);
+  const LdsLayout L = lds_layout(g.Rpad, esize, ntile, W, adjoint, prec == P_F16, 1, nb, adjoint && dich ? 4 : 3,
+                                 three_d && !adjoint, nb > 1 && prec == P_BF16 && W > 4);
   return (size_t)L.total;
 }
 

@@ -266,6 +266,7 @@ StepArgs rt_ctx::args(bool adjoint) const {
   const size_t sbytes = (size_t)geo.C * 16 * geo.n;
   const int w = strip >= 0 ? strip : (sbytes > kStripStateBytes ? kTileStrip : 0);
   if (!three_d && w > 0 && geo.nx % (64 * w) == 0) a.strip = w;
+  a.nt_out = sbytes > kStripStateBytes ? 1 : 0;
   if (three_d) {
     a.ny3 = s3.ny;
     a.nz = s3.nz;
@@ -1917,6 +1918,8 @@ struct rt_batch {
       h_rec[i].a = h_run[i].a;
       h_adj[i].a = ch[i]->args(true);
       h_run[i].a.strip = h_rec[i].a.strip = h_adj[i].a.strip = 0;   // tiles in row order
+      // (a group's states stay in the last-level cache from step to step)
+      h_run[i].a.nt_out = h_rec[i].a.nt_out = h_adj[i].a.nt_out = 0;
     }
   }
   rt_status upload(BatchChan *d, const std::vector<BatchChan> &h, const Plan &pl) {
@@ -2182,6 +2185,7 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
     BatchChan f{};
     f.a = c->args(false);
     f.a.strip = 0;   // the batched kernel numbers its tiles in row order
+    f.a.nt_out = 0;  // and keeps a group's states in the last-level cache
     f.buf[kBufYa] = c->at<float>(c->L.Ya);
     f.buf[kBufYb] = c->at<float>(c->L.Yb);
     f.buf[kBufLa] = c->at<float>(c->L.La);
@@ -2191,6 +2195,7 @@ rt_status rt_batch_init(const rt_problem *probs, int32_t nchan, void *d_ws, size
     BatchChan a = f;
     a.a = c->args(true);
     a.a.strip = 0;
+    a.a.nt_out = 0;
     b->h_run.push_back(f);
     b->h_rec.push_back(f);
     b->h_adj.push_back(a);

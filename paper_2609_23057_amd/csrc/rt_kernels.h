@@ -68,6 +68,11 @@ struct StepArgs {
   // cells across, or strip / 2 tiles of 32 cells; every row, then the next
   // strip); 0: row order.  Set only where nx is a multiple of 64 strip.
   int32_t strip;
+  // single-problem forward steps without extensions (64-cell tiles, 16-wave
+  // blocks, 3-D) write the output state with non-temporal stores: set for
+  // states beyond the last-level cache, which the next step cannot find
+  // there anyway (below it such stores would push the state out of it)
+  int32_t nt_out;
 };
 
 enum Prec { P_F32 = 0, P_BF16 = 1, P_F16 = 2, P_BF16X3 = 3 };

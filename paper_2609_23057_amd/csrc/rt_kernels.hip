@@ -629,6 +629,17 @@ __host__ __device__ inline LdsLayout lds_layout(int Rpad, int esize, int ntile, 
 // CU).  Up to 4 row tiles the 64-cell tile performs the 32-cell tile's
 // arithmetic per cell, so the spectral batch's 32-cell tiles give the same
 // bits.
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
+
+// Single-problem forward steps with a non-temporal copy of the epilogue: the
+// 64-cell tiles, the 16-wave blocks and the 3-D step, without extensions
+// (the 32-cell tiles of 4-wave blocks hold no registers to spare for it).
+template <bool ADJ, int MAXW, int NB, int EXT, bool G3>
+constexpr bool kNtCopy = !ADJ && EXT == kExtNone && (MAXW > 4 || NB > 1 || G3);
+
 // X as high + low bf16 tiles: the bf16 64-cell tile of the 16-wave blocks.
 template <int PREC, int MAXW, int NB>
 constexpr bool kXSplit = NB > 1 && PREC == P_BF16 && MAXW > 4;
@@ -676,7 +687,7 @@ __device__ __forceinline__ float f16_cell_scale(const float (&v)[16], float *red
 }
 
 template <int PREC, bool GATHER, bool ADJ, bool CKPT, int kRing, int NB = 1, int EXT = kExtNone, bool G3 = false,
-          bool XSPLIT = false>
+          bool XSPLIT = false, bool NTC = false>
 __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g, const LdsLayout &L,
                                            const TileLds &ts, const TileRange &tr, const LaneDir (&ld)[4],
                                            int64_t tile, bool active, int t, int wg, int W, int lane) {
@@ -1062,6 +1073,17 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
 #pragma unroll
   for (int k = 0; k < NACC; ++k) part[k] = 0.0f;
   (void)gpre;
+  // With NTC, forward steps store the output state non-temporally where it
+  // exceeds the last-level cache (a.nt_out).  The loop then exists twice;
+  // the non-temporal copy writes through the output base plus an opaque
+  // zero, so that the compiler cannot merge the two copies' identical
+  // stores, which would drop the hint (an integer offset keeps the base a
+  // global pointer).
+  auto epilogue = [&](auto nt_tag) {
+  constexpr bool NT = decltype(nt_tag)::value;
+  int64_t zoff = 0;
+  if constexpr (NT) asm volatile("" : "+s"(zoff));
+  float *outb = a.out + zoff;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     if (!lcs[cb].valid) continue;
@@ -1107,9 +1129,13 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
       for (int s = 0; s < 4; ++s) {
         const int i = 4 * q + s;
         const float prod = acc[cb][i] * unscale;
-        float *o = a.out + ld[q].off + (int64_t)s * g.C + c;
+        float *o = outb + ld[q].off + (int64_t)s * g.C + c;
         if (!ADJ) {
-          *o = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
+          const float y = fmaf(be[cb], prod, fmaf(al[cb], xq[s], a.dt_post * em[cb] * jp[s]));
+          if constexpr (NT)
+            __builtin_nontemporal_store(y, o);
+          else
+            *o = y;
         } else {
           // lam = dLoss/dX_d (X_d = X without dichroic absorption)
           const float lam = fmaf(be[cb], prod, al[cb] * mu[s]);
@@ -1137,6 +1163,15 @@ __device__ __forceinline__ void fused_tile(const StepArgs &a, const Geometry &g,
         }
       }
     }
+  }
+  };
+  if constexpr (NTC && !ADJ) {
+    if (a.nt_out)
+      epilogue(BoolTag<true>{});
+    else
+      epilogue(BoolTag<false>{});
+  } else {
+    epilogue(BoolTag<false>{});
   }
   if (ADJ) {
     // per-cell sums over all rows: half-waves, then waves via LDS
@@ -1248,8 +1283,8 @@ fused_kernel(StepArgs a, int64_t ntiles) {
     // which would not fit in VGPRs, without holding a second copy.
 #pragma unroll
     for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ldk[q].off), "+v"(ldk[q].td), "+v"(ldk[q].d));
-    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT, G3, kXSplit<PREC, MAXW, NB>>(
-        a, g, L, ts, tr, ldk, tile, true, t, t, W, lane);
+    fused_tile<PREC, GATHER, ADJ, CKPT, kFusedRing<PREC, ADJ, MAXW, NB>, NB, EXT, G3, kXSplit<PREC, MAXW, NB>,
+               kNtCopy<ADJ, MAXW, NB, EXT, G3>>(a, g, L, ts, tr, ldk, tile, true, t, t, W, lane);
   }
 }
 

@@ -1230,11 +1230,12 @@ constexpr int kFusedRing = MAXW <= 4 ? (((ADJ && (PREC == P_BF16 || PREC == P_BF
 
 // Waves per SIMD the register allocation must allow: 4 for the fp32 and bf16
 // adjoint in blocks of up to 4 waves (the accumulator then lives in ordinary
-// VGPRs, without spills), 3 for the 3-D gather and the phase-mixture forward
-// step in such blocks, otherwise whatever the kernel needs.
+// VGPRs, without spills), 3 for the 3-D gather and the forward steps with a
+// phase mixture or dichroic absorption in such blocks, otherwise whatever
+// the kernel needs.
 template <int PREC, bool ADJ, int MAXW, bool G3 = false, int EXT = kExtNone>
 constexpr int kMinWavesPerEU = (ADJ && MAXW <= 4 && (PREC == P_F32 || PREC == P_BF16)) ? 4
-                               : ((G3 || (!ADJ && EXT == kExtMix)) && MAXW <= 4) ? 3 : 1;
+                               : ((G3 || (!ADJ && EXT != kExtNone)) && MAXW <= 4) ? 3 : 1;
 
 template <int PREC, bool GATHER, bool ADJ, int MAXW, bool CKPT, int NB, int EXT, bool G3 = false>
 __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<PREC, ADJ, MAXW, G3, EXT>)))
@@ -1574,13 +1575,14 @@ hipError_t launch_fused_t(const StepArgs &a, int W, hipStream_t s, int cu_count)
   }
   if (a.dich_xi != nullptr) {
     // dichroic absorption: the adjoint on 32-cell tiles; forward steps on the
-    // tiles of the plain step (bf16 in blocks of up to 4 waves: 32-cell tiles)
+    // tiles of the plain step
     if constexpr (ADJ) {
       if (W <= 4) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
       return launch_fused_k<PREC, GATHER, ADJ, CKPT, 16, 1, kExtDich>(a, W, s, cu_count);
     } else {
       if (W <= 4) {
-        if constexpr (PREC == P_F32) return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2, kExtDich>(a, W, s, cu_count);
+        if constexpr (PREC == P_F32 || PREC == P_BF16)
+          return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 2, kExtDich>(a, W, s, cu_count);
         return launch_fused_k<PREC, GATHER, ADJ, CKPT, 4, 1, kExtDich>(a, W, s, cu_count);
       }
       if constexpr (PREC == P_F32 || PREC == P_BF16) {
